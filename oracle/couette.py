@@ -33,8 +33,8 @@ def build(force: bool = False) -> str:
     """Compile the oracle shared object next to its source."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                               "-shared", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-Wall",
+                               "-Werror=sequence-point", "-Werror=unused-value", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -51,6 +51,7 @@ def lib():
             _lib.oracle_weno5.argtypes = [ctypes.c_double] * 5
             _lib.oracle_weno5.restype = ctypes.c_double
             _lib.oracle_weno5_omega.argtypes = [ctypes.c_double] * 3 + [dp]
+            _lib.oracle_weno5_sigma.argtypes = [ctypes.c_double] * 5 + [dp]
         return _lib
 
 
@@ -77,6 +78,13 @@ def weno5_omega(s1, s2, s3) -> np.ndarray:
     w = np.zeros(3)
     lib().oracle_weno5_omega(s1, s2, s3, _ptr(w))
     return w
+
+
+def weno5_sigma(a, b, c, d, e) -> np.ndarray:
+    """Smoothness indicators of Eq. weno_sigma for upwind-ordered cells (a, b, c, d, e)."""
+    s = np.zeros(3)
+    lib().oracle_weno5_sigma(a, b, c, d, e, _ptr(s))
+    return s
 
 
 def couette_faces(R_in: float, R_out: float, N_R: int, A: float = 0.0, delta: float = 0.5) -> np.ndarray:

@@ -172,16 +172,24 @@ void oracle_weno5_omega(double s1, double s2, double s3, double* w) {
     w[0] = w1 / sum; w[1] = w2 / sum; w[2] = w3 / sum;
 }
 
+/* Smoothness indicators of Eq. weno_sigma for the upwind-ordered cells (a, b, c, d, e). */
+void oracle_weno5_sigma(double a, double b, double c, double d, double e, double* s) {
+    const double x1 = a - 2.0 * b + c, y1 = a - 4.0 * b + 3.0 * c;
+    const double x2 = b - 2.0 * c + d, y2 = b - d;
+    const double x3 = c - 2.0 * d + e, y3 = 3.0 * c - 4.0 * d + e;
+    s[0] = 13.0 / 12.0 * (x1 * x1) + 0.25 * (y1 * y1);
+    s[1] = 13.0 / 12.0 * (x2 * x2) + 0.25 * (y2 * y2);
+    s[2] = 13.0 / 12.0 * (x3 * x3) + 0.25 * (y3 * y3);
+}
+
 double oracle_weno5(double a, double b, double c, double d, double e) {
     double f1 = a / 3.0 - 7.0 / 6.0 * b + 11.0 / 6.0 * c;
     double f2 = -b / 6.0 + 5.0 / 6.0 * c + d / 3.0;
     double f3 = c / 3.0 + 5.0 / 6.0 * d - e / 6.0;
-    double t;
-    double s1 = 13.0 / 12.0 * (t = a - 2.0 * b + c, t * t) + 0.25 * (t = a - 4.0 * b + 3.0 * c, t * t);
-    double s2 = 13.0 / 12.0 * (t = b - 2.0 * c + d, t * t) + 0.25 * (t = b - d, t * t);
-    double s3 = 13.0 / 12.0 * (t = c - 2.0 * d + e, t * t) + 0.25 * (t = 3.0 * c - 4.0 * d + e, t * t);
+    double s[3];
+    oracle_weno5_sigma(a, b, c, d, e, s);
     double w[3];
-    oracle_weno5_omega(s1, s2, s3, w);
+    oracle_weno5_omega(s[0], s[1], s[2], w);
     return w[0] * f1 + w[1] * f2 + w[2] * f3;
 }
 

@@ -6,7 +6,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
-from oracle.couette import weno5, weno5_omega
+from oracle.couette import weno5, weno5_omega, weno5_sigma
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "weno_table.txt")
 
@@ -86,3 +86,32 @@ def test_fifth_order_on_smooth_data():
     e = [_deriv_error(N) for N in (20, 40, 80)]
     orders = [math.log2(e[i] / e[i + 1]) for i in range(2)]
     assert min(orders) > 4.5, (e, orders)
+
+
+def _reconstruction(vals, centres):
+    """Quadratic p(x) = al + be x + ga x^2 whose averages over the unit cells centred at
+    `centres` equal `vals` (cell-average reconstruction; target cell [-1/2, 1/2])."""
+    M = np.array([[1.0, m, m * m + 1.0 / 12] for m in centres])
+    return np.linalg.solve(M, np.asarray(vals, dtype=float))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_smoothness_indicators_and_flux_from_definition(seed):
+    """Jiang-Shu definition of the smoothness indicators, independent of the printed
+    closed form: sigma_q = int_{-1/2}^{1/2} (p_q')^2 + (p_q'')^2 dx for the quadratic p_q
+    reconstructing stencil q, i.e. be^2 + (13/3) ga^2; candidate flux p_q(1/2).  The
+    oracle's Eq. weno_sigma values and its flux (weights pinned by Table weno) must
+    agree with this route."""
+    rng = np.random.default_rng(seed)
+    data = rng.uniform(-1, 2, 5) * (10.0 ** rng.integers(-12, 1))
+    stencils = [((-2, -1, 0), data[0:3]), ((-1, 0, 1), data[1:4]), ((0, 1, 2), data[2:5])]
+    sig, cand = [], []
+    for centres, vals in stencils:
+        al, be, ga = _reconstruction(vals, centres)
+        sig.append(be * be + 13.0 / 3.0 * ga * ga)
+        cand.append(al + be / 2 + ga / 4)
+    got = weno5_sigma(*data)
+    scale = max(sig)
+    assert np.allclose(got, sig, rtol=1e-12, atol=1e-13 * scale)
+    want = float(np.dot(weno5_omega(*sig), cand))
+    assert weno5(*data) == pytest.approx(want, rel=1e-12, abs=1e-14 * np.abs(data).max())
