@@ -1,0 +1,143 @@
+"""Throughput benchmark of the vielbein-LB hot path on one MI355X.
+
+Workload (seeded, synthetic): the batched circular-Couette sweep -- 256 instances with
+Kn = 10^U(-2,1), wall speed U(0.05, 0.5), radius ratio U(0.3, 0.8), 64..512 cells, and
+HH(N;Q_R) x H(N;Q_phi) velocity sets whose orders grow with Kn (32..640 velocities),
+all advanced together by the library's FP64 RK3 stage kernels.  One "step" is one full
+third-order Runge-Kutta step of every instance.
+
+Prints one JSON line: site-velocity updates per second (sum over instances of
+cells x velocities x steps / wall time), the roofline of the dominant stage-kernel
+instantiation (HIP events around each of its launches over the timed region; bytes =
+algorithmic HBM traffic, one read of the stage input, one read of F_n in stages 2 and
+3, one write, per population) and the CPU oracle's rate on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _cpu_worker(args):
+    """Oracle (plain C FP64, one thread) on one instance for a few steps; returns
+    (site-velocity updates, seconds)."""
+    idx, nsteps = args
+    from oracle.couette import CouetteOracle
+    from paper_1708_05944_amd import workloads
+    d = workloads.couette_sweep()[idx]
+    o = CouetteOracle(R_in=d.R_in, R_out=d.R_out, N_R=d.N_R, ax1=d.ax1, ax2=d.ax2, Kn=d.Kn,
+                      tau_model=d.tau_model, u_in=d.u_in, T_in=d.T_in, u_out=d.u_out, T_out=d.T_out)
+    F = o.equilibrium(1.0, 0.0, 0.0, 1.0)
+    dt = o.cfl_dt(d.cfl)
+    o.step(F, dt, 1)                       # warm (tables, page faults)
+    t0 = time.perf_counter()
+    o.step(F, dt, nsteps)
+    el = time.perf_counter() - t0
+    return o.NR * o.NV * nsteps, el
+
+
+def cpu_baseline(n_inst: int, nsteps: int):
+    """The oracle on the first n_inst instances of the sweep, nsteps RK3 steps each, one
+    process per host core (instances are independent)."""
+    import multiprocessing as mp
+    from oracle import couette as oc
+    oc.build()
+    cores = min(os.cpu_count() or 1, 16)
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_cpu_worker, [(i, nsteps) for i in range(n_inst)])
+    wall = time.perf_counter() - t0
+    upd = sum(r[0] for r in res)
+    busy = sum(r[1] for r in res)
+    return dict(value=upd / busy * min(cores, n_inst), unit="site-velocity updates/s", cores=cores, kind="oracle",
+                sample=f"first {n_inst} of the 256 sweep instances, {nsteps} RK3 steps each from rest, "
+                       f"{cores} worker processes x 1 thread; value = updates / per-process busy time x workers "
+                       f"(wall {wall:.1f} s incl. table set-up)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-instances", type=int, default=64)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(instances shard across GPUs without communication; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1708_05944_amd import Batch, workloads
+
+    descs = workloads.couette_sweep()
+    updates_per_step = workloads.site_velocities(descs)
+    batch = Batch(descs)
+    batch.step(args.warmup)
+    torch.cuda.synchronize()
+    batch.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    groups = batch.timing_query()
+    batch.timing_enable(False)
+    r = batch.residual()
+    # untimed pass without events to check the event brackets do not distort the rate
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    batch.step(args.steps)
+    torch.cuda.synchronize()
+    el_plain = time.perf_counter() - t1
+    value = updates_per_step * args.steps / el
+    dom = max(groups, key=lambda g: g["total_ms"])
+    achieved = dom["alg_bytes"] / (dom["total_ms"] * 1e-3) / 1e9
+    kern_ms = sum(g["total_ms"] for g in groups)
+    out = {
+        "metric": "site-velocity updates/s (batched Couette sweep, FP64)",
+        "value": value,
+        "unit": "site-velocity updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batched circular-Couette sweep: 256 seeded instances (PCG64 seed 20261203), "
+                               "64-512 cells, HH(N;4..16) x H(N;4..20) velocity sets (32-640 velocities), "
+                               "Kn 0.01-10, FP64",
+                   "instances": len(descs), "site_velocities_per_step": updates_per_step},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"couette_stage_f64<{dom['vpt']}>", "launches": dom["launches"],
+                     "avg_launch_ms": dom["total_ms"] / dom["launches"],
+                     "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"]},
+        "all_stage_kernels": {"achieved_GBps": sum(g["alg_bytes"] for g in groups) / (kern_ms * 1e-3) / 1e9,
+                              "kernel_ms_per_step": kern_ms / args.steps},
+        "ms_per_step_no_events": el_plain / args.steps * 1e3,
+        "max_residual": float(r.max()),
+    }
+    batch.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_instances, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * vlb.h -- C ABI of the MI355X vielbein lattice-Boltzmann library (libvlb.so).
+ *
+ * The library advances the finite-difference lattice Boltzmann model of
+ * Busuioc & Ambrus, arXiv:1708.05944: the Boltzmann-BGK equation in the conservative
+ * vielbein ("chi") form (Sec. II.B, Eq. boltz_noncons; Sec. III, Eq. numsch_eq),
+ * written for circular Couette flow (Sec. V.A, Eq. boltz_couette_kom and, on
+ * stretched grids, Eq. boltz_couette_str_kom), on the reduced distributions f' and
+ * f'' (Sec. IV.A, Eq. fred) over mixed half-/full-range Gauss-Hermite velocity sets
+ * HH(N;Q) x H(N;Q) (Sec. IV.B, Eq. model).  One time step is the third-order TVD
+ * Runge-Kutta scheme (Sec. III.A, Eq. rk3); each stage evaluates moments, the
+ * polynomial equilibrium (Sec. IV.D), diffuse-reflection walls (Sec. III.F),
+ * epsilon-free WENO-5 fluxes (Sec. III.C) and the projected inertial force
+ * (Sec. IV.C) on the GPU.
+ *
+ * Conventions
+ *   - Units: m = k_B = T_w(reference) = 1; momenta in units of sqrt(m k_B T_0).
+ *   - A "batch" holds B independent Couette instances of possibly different grid
+ *     sizes and velocity sets; a single solver is a batch of one.
+ *   - State layout (host and device): instances one after the other; instance b is
+ *     a block [2][N_R][NV] of doubles: f' then f'', cell s = 0..N_R-1 (cell s+1 of
+ *     the paper, cell-centred, Sec. V.C.1), velocity k = i*Q2 + j with i the node of
+ *     axis 1 (radial momentum p^R) and j the node of axis 2 (azimuthal p^phi).  Node
+ *     order per axis: full range -> ascending roots of He_Q; half range -> the Q
+ *     positive roots ascending, then their mirror images (Sec. IV.B).  Stored values
+ *     are the weighted populations f_ij = w_i w_j f(p_i, p_j)/(omega(p_i) omega(p_j)).
+ *   - Errors: every call returns a vlb_status; no C++ exception crosses the ABI.
+ *     vlb_last_error() gives a thread-local message for the last failure.
+ *   - Ownership: the caller owns every host array it passes; the library never keeps
+ *     a host pointer past the call.  Device memory is allocated by the library on
+ *     creation, or supplied by the caller with vlb_batch_bind_workspace (e.g. a
+ *     torch tensor), in which case the caller keeps it alive until destroy.
+ *   - Streams: work is enqueued on the hipStream_t given at creation (NULL = the
+ *     default stream).  Calls that return host data synchronise that stream.
+ *   - Handles are not thread-safe; use one handle per thread.
+ */
+#ifndef VLB_H
+#define VLB_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VLB_OK = 0,
+    VLB_EINVAL = -1,       /* invalid argument (sizes, orders, pointers, unknown enum) */
+    VLB_ENOMEM = -2,       /* host or device allocation failed / workspace too small */
+    VLB_EDEVICE = -3,      /* a HIP runtime call or kernel launch failed */
+    VLB_ESTATE = -4,       /* call not valid in the handle's current state */
+    VLB_ENOTCONV = -5,     /* run_to_steady stopped at max_steps above tolerance */
+    VLB_ENONFINITE = -6,   /* NaN or Inf found in the state or residual */
+    VLB_EUNSTABLE = -7     /* requested dt violates the stability limits */
+} vlb_status;
+
+/* One momentum axis: kind 0 = full-range Gauss-Hermite H(N;Q), kind 1 = half-range
+ * HH(N;Q) (2Q nodes); N is the expansion order of the equilibrium, 0 <= N < Q
+ * (Sec. IV.D, Eq. norder_limit), N <= 4; 1 <= Q <= 64. */
+typedef struct {
+    int kind;
+    int Q;
+    int N;
+} vlb_axis;
+
+/* Relaxation-time models tau(n, T) of the BGK term (Eq. BGK). */
+enum {
+    VLB_TAU_AOKI = 0,      /* tau = Kn sqrt(pi/8) / n   (Sec. V.F, Eq. tau_aoki) */
+    VLB_TAU_HYDRO = 1,     /* tau = Kn / (n T)          (Sec. V.D, Eq. hydro_tau) */
+    VLB_TAU_KN = 2         /* tau = Kn / n              (Sec. V.G benchmark runs) */
+};
+
+enum { VLB_FP64 = 0 };
+
+/* One circular-Couette instance (Sec. V).  Grid: N_R >= 3 cells between R_in < R_out;
+ * A = 0 gives an equidistant grid, 0 < A < 1 the tanh stretching of Sec. III.B
+ * (Eqs. eta_def, eta_inout) with centre parameter delta in [0, 1].  ax1 is the radial
+ * axis, ax2 the azimuthal one; ax1.kind = 1 (half range) is the choice that resolves
+ * the wall discontinuity (Sec. IV.B).  dt = 0 picks dt = cfl * min_s dchi_s /
+ * (R_{s+1/2} max|p^R|).  Walls: tangential speeds u_in / u_out and temperatures
+ * T_in / T_out of the inner and outer cylinder (Sec. III.F, Eq. diffuse_f). */
+typedef struct {
+    double R_in, R_out;
+    int N_R;
+    double A, delta;
+    vlb_axis ax1, ax2;
+    double Kn;
+    int tau_model;
+    double dt, cfl;
+    double u_in, T_in, u_out, T_out;
+} vlb_couette_desc;
+
+typedef struct vlb_batch vlb_batch;
+
+/* Creates B >= 1 instances; builds velocity sets and grids on the host, uploads
+ * tables, allocates device memory unless defer_alloc != 0 (then bind a workspace
+ * before any other call), and sets every instance to the rest state n = 1, u = 0,
+ * T = T_in (Sec. V, initial state).  precision must be VLB_FP64.  hip_stream is a
+ * hipStream_t (may be NULL).  Errors: VLB_EINVAL for invalid descriptors (N_R < 3,
+ * R_out <= R_in, invalid axes, Kn <= 0, dt < 0), VLB_EUNSTABLE if an explicit dt
+ * exceeds the CFL limit of the instance, VLB_ENOMEM, VLB_EDEVICE. */
+vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_desc* descs, int precision,
+                                    void* hip_stream, int defer_alloc);
+void vlb_batch_destroy(vlb_batch* b);
+
+/* Bytes of device memory the batch needs, and binding of a caller-owned buffer of at
+ * least that size (256-byte aligned).  Binding replaces library-owned memory and
+ * resets the state to rest. */
+vlb_status vlb_batch_workspace_bytes(const vlb_batch* b, size_t* bytes);
+vlb_status vlb_batch_bind_workspace(vlb_batch* b, void* dev_ptr, size_t bytes);
+
+/* Per-instance sizes: cells, velocities (NV = nodes1 * nodes2), axis node counts,
+ * the time step in use, and the element offset of the instance in the state. */
+vlb_status vlb_batch_info(const vlb_batch* b, int inst, int* N_R, int* NV, int* nodes1, int* nodes2, double* dt,
+                          size_t* state_offset);
+/* Total number of doubles of the state (sum over instances of 2 N_R NV). */
+vlb_status vlb_batch_state_size(const vlb_batch* b, size_t* n_doubles);
+
+/* Velocity set of one instance: nodes and weights of axis 1 / 2 (host arrays of
+ * length nodes1 / nodes2). */
+vlb_status vlb_batch_velocities(const vlb_batch* b, int inst, double* p1, double* w1, double* p2, double* w2);
+
+/* Replace the wall parameters of one instance (side 0 = inner, 1 = outer). */
+vlb_status vlb_set_wall(vlb_batch* b, int inst, int side, double u_tangential, double T_w);
+
+/* Initialise instance inst (or all instances when inst = -1, arrays concatenated over
+ * instances) to the local equilibrium f' = f'_eq(n, u, T), f'' = T f'_eq per cell
+ * (Sec. IV.D).  Host arrays of N_R (or total cells) entries. */
+vlb_status vlb_init_equilibrium(vlb_batch* b, int inst, const double* n, const double* u1, const double* u2,
+                                const double* T);
+
+/* Copy the whole state to / from a host array of vlb_batch_state_size doubles.
+ * set_state rejects non-finite values with VLB_ENONFINITE. */
+vlb_status vlb_set_state(vlb_batch* b, const double* host, size_t n);
+vlb_status vlb_get_state(vlb_batch* b, double* host, size_t n);
+
+/* Advance every instance by nsteps >= 0 RK3 steps, each with its own dt.  The last
+ * step records the steady-state residual r of each instance (see vlb_residual).
+ * Enqueued on the stream; returns without synchronising. */
+vlb_status vlb_step(vlb_batch* b, long nsteps);
+
+/* One application of the operator L[F] of Eq. L_def (advection + force + BGK with the
+ * diffuse walls) to the current state; result written to the host array L (same
+ * layout and size as the state).  The state is not modified.  Synchronises. */
+vlb_status vlb_apply_L(vlb_batch* b, double* L, size_t n);
+
+/* Macroscopic fields of one instance (host arrays of N_R; any may be NULL):
+ * n, u^R, u^phi, T, T^{R phi}, q^R, q^phi (Sec. IV.A, Eq. macro_red).  Synchronises. */
+vlb_status vlb_moments(vlb_batch* b, int inst, double* n, double* u1, double* u2, double* T, double* T12,
+                       double* q1, double* q2);
+
+/* Steady-state residual of the last recorded step of each instance (host array of B):
+ * r = ||F^{n+1} - F^n||_W / (dt ||F^n||_W), ||F||_W^2 = sum_s dchi_s sum_k
+ * (f'^2 + f''^2)/(w_i w_j).  VLB_ESTATE if no step was taken since the last state
+ * change; VLB_ENONFINITE if any r is not finite.  Synchronises. */
+vlb_status vlb_residual(vlb_batch* b, double* r);
+
+/* Particle number per unit height and radian, N_tot = sum_s dchi_s n_s
+ * (Sec. II.B, Eq. Ntot_def), per instance (host array of B).  Synchronises. */
+vlb_status vlb_total_mass(vlb_batch* b, double* Ntot);
+
+/* Step every instance until its residual is below tol, checking every check_every
+ * steps, at most max_steps steps.  Converged instances keep stepping while others
+ * run.  steps / r (host arrays of B, may be NULL) receive the step count at which
+ * each instance first reached tol (or -1) and its last residual.  Returns
+ * VLB_ENOTCONV if some instance did not converge. */
+vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check_every, long* steps, double* r);
+
+/* Host-side velocity-set tables of one axis, for checking against independent
+ * implementations: nodes p, weights w (nodes entries), d/dp kernel K and d(p .)/dp
+ * kernel Kt (nodes x nodes, row-major; Sec. IV.C).  nodes = Q (kind 0) or 2Q. */
+vlb_status vlb_axis_tables(vlb_axis ax, double* p, double* w, double* K, double* Kt);
+
+/* Kernel timing for roofline reports.  When enabled, every launch of the stage kernel
+ * is bracketed by HIP events recorded on the batch's stream; launches are grouped by
+ * kernel instantiation (velocities per lane, VPT).  vlb_timing_query synchronises the
+ * stream and returns, for up to max_groups groups: the VPT of the instantiation, the
+ * number of launches recorded, their summed duration in ms, and the algorithmic HBM
+ * bytes they moved (each launch: per population of the instances it covers, one read
+ * of the stage input, one read of F_n in stages 2 and 3, one write).  Querying clears
+ * the record.  ngroups receives the number of groups with launches. */
+vlb_status vlb_timing_enable(vlb_batch* b, int enable);
+vlb_status vlb_timing_query(vlb_batch* b, int max_groups, int* ngroups, int* vpt, long* launches, double* total_ms,
+                            double* alg_bytes);
+
+const char* vlb_status_string(vlb_status s);
+const char* vlb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VLB_H */

@@ -1,0 +1,709 @@
+// Host side of libvlb.so: the C ABI of include/vlb.h.  Builds velocity sets and
+// Couette grids, lays out the device workspace, enqueues the stage kernels and the
+// deterministic reductions, and moves data across the host/device boundary.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/vlb.h"
+#include "vlb_internal.h"
+
+namespace vlb {
+hipError_t launch_stage(int vpt, int nblocks, size_t lds_bytes, hipStream_t st, const StageArgs& A);
+hipError_t launch_moments(int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
+                          const double* tab, const double* F, double* msum);
+hipError_t launch_reduce(int ninst, hipStream_t st, const InstDesc* insts, const double* tab, const double* rpart,
+                         const double* msum, double* resid, double* mass, int want_resid);
+hipError_t launch_diag(int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
+                       const double* tab, const double* F, double* diag);
+}  // namespace vlb
+
+using namespace vlb;
+
+namespace {
+
+thread_local std::string g_err;
+
+vlb_status fail(vlb_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(VLB_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+struct LaunchGroup {
+    int vpt, first_block, nblocks;
+    int kmax, nvmax;
+    double pops;   // populations (2 N_R NV summed over the group's instances)
+};
+
+struct TimedLaunch {
+    int group;
+    hipEvent_t start, stop;
+    double bytes;
+};
+
+struct InstHost {
+    vlb_couette_desc d;
+    AxisTables a1, a2;
+    std::vector<double> Rf, dchi, Gam;
+    int NV;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct vlb_batch {
+    int B = 0;
+    hipStream_t stream = nullptr;
+    std::vector<InstHost> inst;
+    std::vector<InstDesc> desc;
+    std::vector<WorkItem> work;
+    std::vector<LaunchGroup> groups;
+    std::vector<double> tab;
+    size_t state_n = 0, ncells = 0;
+    // workspace layout (byte offsets)
+    size_t off_F[3], off_M[3], off_rpart, off_resid, off_mass, off_tab, off_desc, off_work, off_diag, total_bytes;
+    char* ws = nullptr;
+    bool owns = false;
+    bool have_resid = false;
+    bool timing = false;
+    std::vector<TimedLaunch> timed;
+    std::vector<hipEvent_t> event_pool;
+
+    double* F(int i) { return (double*)(ws + off_F[i]); }
+    double* M(int i) { return (double*)(ws + off_M[i]); }
+    double* rpart() { return (double*)(ws + off_rpart); }
+    double* resid() { return (double*)(ws + off_resid); }
+    double* massv() { return (double*)(ws + off_mass); }
+    double* dtab() { return (double*)(ws + off_tab); }
+    InstDesc* ddesc() { return (InstDesc*)(ws + off_desc); }
+    WorkItem* dwork() { return (WorkItem*)(ws + off_work); }
+    double* diag() { return (double*)(ws + off_diag); }
+};
+
+namespace {
+
+bool axis_ok(const vlb_axis& a) {
+    return (a.kind == 0 || a.kind == 1) && a.Q >= 1 && a.Q <= kMaxQ && a.N >= 0 && a.N < a.Q && a.N <= kMaxN;
+}
+
+// Face radii R_{s-1/2}, s = 1..N_R+1 (Sec. V.C.1; stretching Sec. III.B, Eqs. eta_def, eta_inout).
+std::vector<double> faces(const vlb_couette_desc& d) {
+    std::vector<double> R(d.N_R + 1);
+    if (d.A == 0.0) {
+        for (int s = 0; s <= d.N_R; ++s) R[s] = d.R_in + (d.R_out - d.R_in) * s / d.N_R;
+    } else {
+        const double A0 = std::max(d.delta, 1.0 - d.delta);
+        const double el = -std::atanh(d.A * d.delta / A0), er = std::atanh(d.A * (1.0 - d.delta) / A0);
+        for (int s = 0; s <= d.N_R; ++s) {
+            const double eta = el + (er - el) * s / d.N_R;
+            R[s] = d.R_in + (d.R_out - d.R_in) * (d.delta + A0 / d.A * std::tanh(eta));
+        }
+        R[0] = d.R_in;
+        R[d.N_R] = d.R_out;
+    }
+    return R;
+}
+
+double tau_rest(const vlb_couette_desc& d) {
+    if (d.tau_model == VLB_TAU_AOKI) return d.Kn * std::sqrt(M_PI / 8.0);
+    return d.Kn;
+}
+
+// Emitted-wall table f'_eq(1, (0, u), T) per velocity and the denominator of Eq. nw.
+void wall_table(const InstHost& h, double u, double T, int side, std::vector<double>& tbl, double& den) {
+    std::vector<double> g1(h.a1.nodes), g2(h.a2.nodes);
+    axis_equilibrium_host(h.a1, 0.0, T, g1.data());
+    axis_equilibrium_host(h.a2, u, T, g2.data());
+    tbl.assign(h.NV, 0.0);
+    den = 0.0;
+    for (int i = 0; i < h.a1.nodes; ++i)
+        for (int j = 0; j < h.a2.nodes; ++j) {
+            const double p = h.a1.p[i];
+            const bool emitted = side == 0 ? p > 0.0 : p < 0.0;
+            if (!emitted) continue;
+            const double v = g1[i] * g2[j];
+            tbl[i * h.a2.nodes + j] = v;
+            den += p * v;
+        }
+}
+
+vlb_status upload_tables(vlb_batch* b) {
+    HIP_TRY(hipMemcpyAsync(b->dtab(), b->tab.data(), b->tab.size() * sizeof(double), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->ddesc(), b->desc.data(), b->desc.size() * sizeof(InstDesc), hipMemcpyHostToDevice,
+                           b->stream));
+    return VLB_OK;
+}
+
+vlb_status refresh_moments(vlb_batch* b) {
+    const int nblocks = (int)(b->work.size() / kWavesPerBlock);
+    HIP_TRY(launch_moments(nblocks, b->stream, b->ddesc(), b->dwork(), b->dtab(), b->F(0), b->M(0)));
+    b->have_resid = false;
+    return VLB_OK;
+}
+
+vlb_status set_state_device(vlb_batch* b, const double* host) {
+    HIP_TRY(hipMemcpyAsync(b->F(0), host, b->state_n * sizeof(double), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return refresh_moments(b);
+}
+
+// Host-side local-equilibrium state for one instance (used for initial states).
+void equilibrium_state(const InstHost& h, const double* n, const double* u1, const double* u2, const double* T,
+                       double* out) {
+    const int NR = h.d.N_R, NV = h.NV, n1 = h.a1.nodes, n2 = h.a2.nodes;
+    std::vector<double> g1(n1), g2(n2);
+    for (int s = 0; s < NR; ++s) {
+        axis_equilibrium_host(h.a1, u1[s], T[s], g1.data());
+        axis_equilibrium_host(h.a2, u2[s], T[s], g2.data());
+        for (int i = 0; i < n1; ++i)
+            for (int j = 0; j < n2; ++j) {
+                const double v = n[s] * g1[i] * g2[j];
+                out[(size_t)s * NV + i * n2 + j] = v;
+                out[(size_t)NR * NV + (size_t)s * NV + i * n2 + j] = T[s] * v;
+            }
+    }
+}
+
+vlb_status layout_and_alloc(vlb_batch* b, bool alloc) {
+    size_t off = 0;
+    for (int i = 0; i < 3; ++i) { b->off_F[i] = off; off = align256(off + b->state_n * sizeof(double)); }
+    for (int i = 0; i < 3; ++i) { b->off_M[i] = off; off = align256(off + b->ncells * 5 * sizeof(double)); }
+    b->off_rpart = off; off = align256(off + b->ncells * 4 * sizeof(double));
+    b->off_diag = off; off = align256(off + b->ncells * 7 * sizeof(double));
+    b->off_resid = off; off = align256(off + b->B * sizeof(double));
+    b->off_mass = off; off = align256(off + b->B * sizeof(double));
+    b->off_tab = off; off = align256(off + b->tab.size() * sizeof(double));
+    b->off_desc = off; off = align256(off + b->desc.size() * sizeof(InstDesc));
+    b->off_work = off; off = align256(off + b->work.size() * sizeof(WorkItem));
+    b->total_bytes = off;
+    if (!alloc) return VLB_OK;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, b->total_bytes);
+    if (e != hipSuccess) return fail(VLB_ENOMEM, "hipMalloc(%zu) failed: %s", b->total_bytes, hipGetErrorString(e));
+    b->ws = (char*)p;
+    b->owns = true;
+    return VLB_OK;
+}
+
+vlb_status finish_setup(vlb_batch* b) {
+    vlb_status st = upload_tables(b);
+    if (st != VLB_OK) return st;
+    HIP_TRY(hipMemcpyAsync(b->dwork(), b->work.data(), b->work.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
+                           b->stream));
+    // rest state n = 1, u = 0, T = T_in
+    std::vector<double> host(b->state_n);
+    for (int i = 0; i < b->B; ++i) {
+        const InstHost& h = b->inst[i];
+        std::vector<double> n(h.d.N_R, 1.0), z(h.d.N_R, 0.0), T(h.d.N_R, h.d.T_in);
+        equilibrium_state(h, n.data(), z.data(), z.data(), T.data(), host.data() + b->desc[i].offF);
+    }
+    return set_state_device(b, host.data());
+}
+
+bool check_instance(vlb_batch* b, int inst) { return b && inst >= 0 && inst < b->B; }
+
+vlb_status run_stage(vlb_batch* b, int stage, bool last, bool l_only) {
+    StageArgs A;
+    A.inst = b->ddesc();
+    A.work = b->dwork();
+    A.tab = b->dtab();
+    A.rpart = nullptr;
+    A.l_only = l_only ? 1 : 0;
+    if (l_only) {
+        A.Fin = b->F(0); A.Fn = b->F(0); A.Fout = b->F(1);
+        A.msum_in = b->M(0); A.msum_out = b->M(1);
+        A.ca = 0.0; A.cb = 0.0; A.cc = 1.0;
+    } else if (stage == 0) {
+        A.Fin = b->F(0); A.Fn = b->F(0); A.Fout = b->F(1);
+        A.msum_in = b->M(0); A.msum_out = b->M(1);
+        A.ca = 0.0; A.cb = 1.0; A.cc = 1.0;
+    } else if (stage == 1) {
+        A.Fin = b->F(1); A.Fn = b->F(0); A.Fout = b->F(2);
+        A.msum_in = b->M(1); A.msum_out = b->M(2);
+        A.ca = 0.75; A.cb = 0.25; A.cc = 0.25;
+    } else {
+        A.Fin = b->F(2); A.Fn = b->F(0); A.Fout = b->F(0);
+        A.msum_in = b->M(2); A.msum_out = b->M(0);
+        A.ca = 1.0 / 3.0; A.cb = 2.0 / 3.0; A.cc = 2.0 / 3.0;
+        if (last) A.rpart = b->rpart();
+    }
+    const double values = (l_only || stage == 0) ? 2.0 : 3.0;   // algorithmic HBM values per population
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        const LaunchGroup& g = b->groups[gi];
+        StageArgs G = A;
+        G.work = b->dwork() + (size_t)g.first_block * kWavesPerBlock;
+        G.kmax = g.kmax;
+        G.nvmax = g.nvmax;
+        const size_t lds = (size_t)(g.kmax + kWavesPerBlock * (g.nvmax + kWave + kTileCells * kEqStride)) * sizeof(double);
+        TimedLaunch t{};
+        if (b->timing) {
+            for (hipEvent_t* e : {&t.start, &t.stop}) {
+                if (b->event_pool.empty()) {
+                    HIP_TRY(hipEventCreate(e));
+                } else {
+                    *e = b->event_pool.back();
+                    b->event_pool.pop_back();
+                }
+            }
+            HIP_TRY(hipEventRecord(t.start, b->stream));
+        }
+        HIP_TRY(launch_stage(g.vpt, g.nblocks, lds, b->stream, G));
+        if (b->timing) {
+            HIP_TRY(hipEventRecord(t.stop, b->stream));
+            t.group = (int)gi;
+            t.bytes = values * g.pops * sizeof(double);
+            b->timed.push_back(t);
+        }
+    }
+    return VLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vlb_status_string(vlb_status s) {
+    switch (s) {
+        case VLB_OK: return "ok";
+        case VLB_EINVAL: return "invalid argument";
+        case VLB_ENOMEM: return "out of memory";
+        case VLB_EDEVICE: return "device error";
+        case VLB_ESTATE: return "invalid state";
+        case VLB_ENOTCONV: return "not converged";
+        case VLB_ENONFINITE: return "non-finite value";
+        case VLB_EUNSTABLE: return "unstable time step";
+    }
+    return "unknown status";
+}
+
+const char* vlb_last_error(void) { return g_err.c_str(); }
+
+vlb_status vlb_axis_tables(vlb_axis ax, double* p, double* w, double* K, double* Kt) {
+    if (!axis_ok(ax)) return fail(VLB_EINVAL, "invalid axis (kind=%d Q=%d N=%d)", ax.kind, ax.Q, ax.N);
+    AxisTables t;
+    if (!build_axis(ax.kind, ax.Q, ax.N, t)) return fail(VLB_EINVAL, "axis construction failed");
+    if (p) std::memcpy(p, t.p.data(), t.p.size() * sizeof(double));
+    if (w) std::memcpy(w, t.w.data(), t.w.size() * sizeof(double));
+    if (K) std::memcpy(K, t.K.data(), t.K.size() * sizeof(double));
+    if (Kt) std::memcpy(Kt, t.Kt.data(), t.Kt.size() * sizeof(double));
+    return VLB_OK;
+}
+
+vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_desc* descs, int precision,
+                                    void* hip_stream, int defer_alloc) {
+    if (!out || B < 1 || !descs) return fail(VLB_EINVAL, "need out, B >= 1 and descriptors");
+    *out = nullptr;
+    if (precision != VLB_FP64) return fail(VLB_EINVAL, "unsupported precision %d", precision);
+    vlb_batch* b = new (std::nothrow) vlb_batch;
+    if (!b) return fail(VLB_ENOMEM, "host allocation failed");
+    b->B = B;
+    b->stream = (hipStream_t)hip_stream;
+    b->inst.resize(B);
+    b->desc.resize(B);
+    std::map<std::tuple<int, int, int>, AxisTables> cache;
+    size_t offF = 0, offC = 0;
+    for (int i = 0; i < B; ++i) {
+        const vlb_couette_desc& d = descs[i];
+        if (!(d.N_R >= 3 && d.R_in > 0 && d.R_out > d.R_in && d.Kn > 0 && d.dt >= 0 && d.A >= 0 && d.A < 1 &&
+              d.delta >= 0 && d.delta <= 1 && d.T_in > 0 && d.T_out > 0 && d.tau_model >= 0 && d.tau_model <= 2 &&
+              axis_ok(d.ax1) && axis_ok(d.ax2) && (d.dt > 0 || d.cfl > 0))) {
+            delete b;
+            return fail(VLB_EINVAL, "invalid descriptor for instance %d", i);
+        }
+        InstHost& h = b->inst[i];
+        h.d = d;
+        for (int ax = 0; ax < 2; ++ax) {
+            const vlb_axis& a = ax == 0 ? d.ax1 : d.ax2;
+            auto key = std::make_tuple(a.kind, a.Q, a.N);
+            auto it = cache.find(key);
+            if (it == cache.end()) {
+                AxisTables t;
+                if (!build_axis(a.kind, a.Q, a.N, t)) { delete b; return fail(VLB_EINVAL, "axis build failed"); }
+                it = cache.emplace(key, std::move(t)).first;
+            }
+            (ax == 0 ? h.a1 : h.a2) = it->second;
+        }
+        h.NV = h.a1.nodes * h.a2.nodes;
+        if (h.NV > kWave * kMaxVPT || h.a1.nodes + h.a2.nodes > kWave) {
+            delete b;
+            return fail(VLB_EINVAL, "instance %d: %d velocities / %d+%d nodes exceed the kernel limits", i, h.NV,
+                        h.a1.nodes, h.a2.nodes);
+        }
+        h.Rf = faces(d);
+        h.dchi.resize(d.N_R);
+        h.Gam.resize(d.N_R);
+        for (int s = 0; s < d.N_R; ++s) {
+            h.dchi[s] = 0.5 * (h.Rf[s + 1] * h.Rf[s + 1] - h.Rf[s] * h.Rf[s]);   // chi = R^2/2
+            h.Gam[s] = 2.0 / (h.Rf[s + 1] + h.Rf[s]);                              // 1/R of the force, cell value
+        }
+        double pmax = 0;
+        for (double v : h.a1.p) pmax = std::max(pmax, std::fabs(v));
+        double dt_cfl1 = 1e300;
+        for (int s = 0; s < d.N_R; ++s) dt_cfl1 = std::min(dt_cfl1, h.dchi[s] / (h.Rf[s + 1] * pmax));
+        double dt = d.dt;
+        if (dt == 0.0) {
+            dt = std::min(d.cfl * dt_cfl1, 2.0 * tau_rest(d));
+        } else if (dt > dt_cfl1 || dt > 2.5 * tau_rest(d)) {
+            delete b;
+            return fail(VLB_EUNSTABLE, "instance %d: dt=%g exceeds the CFL limit %g or 2.5 tau=%g", i, dt, dt_cfl1,
+                        2.5 * tau_rest(d));
+        }
+
+        InstDesc& D = b->desc[i];
+        std::memset(&D, 0, sizeof D);
+        D.NR = d.N_R;
+        D.Q1 = h.a1.nodes;
+        D.Q2 = h.a2.nodes;
+        D.NV = h.NV;
+        D.kind1 = h.a1.kind; D.kind2 = h.a2.kind;
+        D.N1 = h.a1.N; D.N2 = h.a2.N;
+        D.Qh1 = h.a1.Q; D.Qh2 = h.a2.Q;
+        D.tau_model = d.tau_model;
+        D.vpt = (h.NV + kWave - 1) / kWave;
+        D.Kn = d.Kn;
+        D.dt = dt;
+        D.T_in = d.T_in;
+        D.T_out = d.T_out;
+        D.offF = (long long)offF;
+        D.offC = (long long)offC;
+        D.offT = (long long)b->tab.size();
+        auto put = [&](const std::vector<double>& v) {
+            int o = (int)(b->tab.size() - D.offT);
+            b->tab.insert(b->tab.end(), v.begin(), v.end());
+            return o;
+        };
+        D.tp1 = put(h.a1.p); D.tp2 = put(h.a2.p);
+        D.tK1 = put(h.a1.K); D.tKt2 = put(h.a2.Kt);
+        D.tB1 = put(h.a1.B); D.tB2 = put(h.a2.B);
+        D.tC1 = put(h.a1.C); D.tC2 = put(h.a2.C);
+        D.tisf1 = put(h.a1.invsqrtfact); D.tisf2 = put(h.a2.invsqrtfact);
+        std::vector<double> tin, tout;
+        wall_table(h, d.u_in, d.T_in, 0, tin, D.den_in);
+        wall_table(h, d.u_out, d.T_out, 1, tout, D.den_out);
+        D.tfin = put(tin);
+        D.tfout = put(tout);
+        std::vector<double> invW(h.NV);
+        for (int a = 0; a < h.a1.nodes; ++a)
+            for (int c = 0; c < h.a2.nodes; ++c) invW[a * h.a2.nodes + c] = 1.0 / (h.a1.w[a] * h.a2.w[c]);
+        D.tinvW = put(invW);
+        D.tRf = put(h.Rf);
+        D.tdchi = put(h.dchi);
+        D.tGam = put(h.Gam);
+        offF += (size_t)2 * d.N_R * h.NV;
+        offC += d.N_R;
+    }
+    b->state_n = offF;
+    b->ncells = offC;
+
+    // work list: per instance and distribution, runs of <= kTileCells cells, grouped in
+    // blocks of 4 wavefronts of the same (instance, distribution); blocks sorted by VPT.
+    std::map<int, std::vector<WorkItem>> byvpt;
+    std::map<int, std::pair<int, int>> limits;   // vpt -> (kmax, nvmax)
+    std::map<int, double> pops;
+    for (int i = 0; i < B; ++i) {
+        const InstDesc& D = b->desc[i];
+        const int ntiles = (D.NR + kTileCells - 1) / kTileCells;
+        const int per = (D.NR + ntiles - 1) / ntiles;
+        std::vector<WorkItem>& L = byvpt[D.vpt];
+        for (int dist = 0; dist < 2; ++dist) {
+            int made = 0;
+            for (int s = 0; s < D.NR; s += per) {
+                L.push_back({i, dist, s, std::min(per, D.NR - s)});
+                ++made;
+            }
+            while (made % kWavesPerBlock) { L.push_back({i, dist, 0, 0}); ++made; }
+        }
+        auto& lim = limits[D.vpt];
+        lim.first = std::max(lim.first, D.Q1 * D.Q1 + D.Q2 * D.Q2);
+        lim.second = std::max(lim.second, D.NV);
+        pops[D.vpt] += 2.0 * D.NR * D.NV;
+    }
+    int block = 0;
+    for (auto& kv : byvpt) {
+        LaunchGroup g;
+        g.vpt = kv.first;
+        g.first_block = block;
+        g.nblocks = (int)(kv.second.size() / kWavesPerBlock);
+        g.kmax = (limits[kv.first].first + 1) & ~1;
+        g.nvmax = (limits[kv.first].second + 1) & ~1;
+        g.pops = pops[kv.first];
+        const size_t lds = (size_t)(g.kmax + kWavesPerBlock * (g.nvmax + kWave + kTileCells * kEqStride)) * sizeof(double);
+        if (lds > 160 * 1024) {
+            delete b;
+            return fail(VLB_EINVAL, "velocity sets too large for LDS (%zu bytes)", lds);
+        }
+        b->groups.push_back(g);
+        b->work.insert(b->work.end(), kv.second.begin(), kv.second.end());
+        block += g.nblocks;
+    }
+
+    vlb_status st = layout_and_alloc(b, defer_alloc == 0);
+    if (st != VLB_OK) { delete b; return st; }
+    if (!defer_alloc) {
+        st = finish_setup(b);
+        if (st != VLB_OK) { vlb_batch_destroy(b); return st; }
+    }
+    *out = b;
+    return VLB_OK;
+}
+
+void vlb_batch_destroy(vlb_batch* b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    for (TimedLaunch& t : b->timed) { (void)hipEventDestroy(t.start); (void)hipEventDestroy(t.stop); }
+    for (hipEvent_t e : b->event_pool) (void)hipEventDestroy(e);
+    if (b->owns && b->ws) {
+        (void)hipStreamSynchronize(b->stream);
+        (void)hipFree(b->ws);
+    }
+    delete b;
+}
+
+vlb_status vlb_batch_workspace_bytes(const vlb_batch* b, size_t* bytes) {
+    if (!b || !bytes) return fail(VLB_EINVAL, "null argument");
+    *bytes = b->total_bytes;
+    return VLB_OK;
+}
+
+vlb_status vlb_batch_bind_workspace(vlb_batch* b, void* dev_ptr, size_t bytes) {
+    if (!b || !dev_ptr) return fail(VLB_EINVAL, "null argument");
+    if (((size_t)dev_ptr & 255) != 0) return fail(VLB_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < b->total_bytes) return fail(VLB_ENOMEM, "workspace of %zu bytes < required %zu", bytes, b->total_bytes);
+    if (b->owns && b->ws) {
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        HIP_TRY(hipFree(b->ws));
+    }
+    b->ws = (char*)dev_ptr;
+    b->owns = false;
+    return finish_setup(b);
+}
+
+vlb_status vlb_batch_info(const vlb_batch* b, int inst, int* N_R, int* NV, int* nodes1, int* nodes2, double* dt,
+                          size_t* state_offset) {
+    if (!b || inst < 0 || inst >= b->B) return fail(VLB_EINVAL, "bad instance");
+    const InstDesc& D = b->desc[inst];
+    if (N_R) *N_R = D.NR;
+    if (NV) *NV = D.NV;
+    if (nodes1) *nodes1 = D.Q1;
+    if (nodes2) *nodes2 = D.Q2;
+    if (dt) *dt = D.dt;
+    if (state_offset) *state_offset = (size_t)D.offF;
+    return VLB_OK;
+}
+
+vlb_status vlb_batch_state_size(const vlb_batch* b, size_t* n) {
+    if (!b || !n) return fail(VLB_EINVAL, "null argument");
+    *n = b->state_n;
+    return VLB_OK;
+}
+
+vlb_status vlb_batch_velocities(const vlb_batch* b, int inst, double* p1, double* w1, double* p2, double* w2) {
+    if (!b || inst < 0 || inst >= b->B) return fail(VLB_EINVAL, "bad instance");
+    const InstHost& h = b->inst[inst];
+    if (p1) std::memcpy(p1, h.a1.p.data(), h.a1.p.size() * sizeof(double));
+    if (w1) std::memcpy(w1, h.a1.w.data(), h.a1.w.size() * sizeof(double));
+    if (p2) std::memcpy(p2, h.a2.p.data(), h.a2.p.size() * sizeof(double));
+    if (w2) std::memcpy(w2, h.a2.w.data(), h.a2.w.size() * sizeof(double));
+    return VLB_OK;
+}
+
+vlb_status vlb_set_wall(vlb_batch* b, int inst, int side, double u, double T) {
+    if (!check_instance(b, inst) || (side != 0 && side != 1) || !(T > 0) || !std::isfinite(u))
+        return fail(VLB_EINVAL, "bad wall arguments");
+    if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
+    InstHost& h = b->inst[inst];
+    InstDesc& D = b->desc[inst];
+    std::vector<double> tbl;
+    double den = 0;
+    wall_table(h, u, T, side, tbl, den);
+    const int off = side == 0 ? D.tfin : D.tfout;
+    std::copy(tbl.begin(), tbl.end(), b->tab.begin() + D.offT + off);
+    if (side == 0) { h.d.u_in = u; h.d.T_in = T; D.den_in = den; D.T_in = T; }
+    else { h.d.u_out = u; h.d.T_out = T; D.den_out = den; D.T_out = T; }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return upload_tables(b);
+}
+
+vlb_status vlb_init_equilibrium(vlb_batch* b, int inst, const double* n, const double* u1, const double* u2,
+                                const double* T) {
+    if (!b || !n || !u1 || !u2 || !T || inst < -1 || inst >= b->B) return fail(VLB_EINVAL, "bad arguments");
+    if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
+    std::vector<double> host(b->state_n);
+    HIP_TRY(hipMemcpyAsync(host.data(), b->F(0), b->state_n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    size_t cell = 0;
+    for (int i = 0; i < b->B; ++i) {
+        const int NR = b->desc[i].NR;
+        if (inst == -1 || inst == i) {
+            const size_t o = inst == -1 ? cell : 0;
+            for (int s = 0; s < NR; ++s)
+                if (!(n[o + s] > 0) || !(T[o + s] > 0) || !std::isfinite(u1[o + s]) || !std::isfinite(u2[o + s]))
+                    return fail(VLB_EINVAL, "invalid equilibrium fields at instance %d cell %d", i, s);
+            equilibrium_state(b->inst[i], n + o, u1 + o, u2 + o, T + o, host.data() + b->desc[i].offF);
+        }
+        cell += NR;
+    }
+    return set_state_device(b, host.data());
+}
+
+vlb_status vlb_set_state(vlb_batch* b, const double* host, size_t n) {
+    if (!b || !host || n != b->state_n) return fail(VLB_EINVAL, "state size mismatch (%zu vs %zu)", n, b ? b->state_n : 0);
+    if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
+    for (size_t x = 0; x < n; ++x)
+        if (!std::isfinite(host[x])) return fail(VLB_ENONFINITE, "non-finite value at element %zu", x);
+    return set_state_device(b, host);
+}
+
+vlb_status vlb_get_state(vlb_batch* b, double* host, size_t n) {
+    if (!b || !host || n != b->state_n) return fail(VLB_EINVAL, "state size mismatch");
+    if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
+    HIP_TRY(hipMemcpyAsync(host, b->F(0), n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return VLB_OK;
+}
+
+vlb_status vlb_step(vlb_batch* b, long nsteps) {
+    if (!b || nsteps < 0) return fail(VLB_EINVAL, "bad arguments");
+    if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
+    for (long it = 0; it < nsteps; ++it) {
+        const bool last = it + 1 == nsteps;
+        for (int st = 0; st < 3; ++st) {
+            vlb_status s = run_stage(b, st, last, false);
+            if (s != VLB_OK) return s;
+        }
+        if (last) {
+            HIP_TRY(launch_reduce(b->B, b->stream, b->ddesc(), b->dtab(), b->rpart(), b->M(0), b->resid(), b->massv(), 1));
+            b->have_resid = true;
+        }
+    }
+    return VLB_OK;
+}
+
+vlb_status vlb_apply_L(vlb_batch* b, double* L, size_t n) {
+    if (!b || !L || n != b->state_n) return fail(VLB_EINVAL, "size mismatch");
+    if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
+    vlb_status s = run_stage(b, 0, false, true);
+    if (s != VLB_OK) return s;
+    HIP_TRY(hipMemcpyAsync(L, b->F(1), n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return VLB_OK;
+}
+
+vlb_status vlb_moments(vlb_batch* b, int inst, double* n, double* u1, double* u2, double* T, double* T12,
+                       double* q1, double* q2) {
+    if (!check_instance(b, inst)) return fail(VLB_EINVAL, "bad instance");
+    if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
+    const int nblocks = (int)(b->work.size() / kWavesPerBlock);
+    HIP_TRY(launch_diag(nblocks, b->stream, b->ddesc(), b->dwork(), b->dtab(), b->F(0), b->diag()));
+    const InstDesc& D = b->desc[inst];
+    std::vector<double> h((size_t)D.NR * 7);
+    HIP_TRY(hipMemcpyAsync(h.data(), b->diag() + (size_t)D.offC * 7, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    double* outs[7] = {n, u1, u2, T, T12, q1, q2};
+    for (int q = 0; q < 7; ++q)
+        if (outs[q])
+            for (int s = 0; s < D.NR; ++s) outs[q][s] = h[(size_t)s * 7 + q];
+    return VLB_OK;
+}
+
+vlb_status vlb_residual(vlb_batch* b, double* r) {
+    if (!b || !r) return fail(VLB_EINVAL, "null argument");
+    if (!b->have_resid) return fail(VLB_ESTATE, "no step recorded since the last state change");
+    HIP_TRY(hipMemcpyAsync(r, b->resid(), b->B * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (int i = 0; i < b->B; ++i)
+        if (!std::isfinite(r[i])) return fail(VLB_ENONFINITE, "non-finite residual in instance %d", i);
+    return VLB_OK;
+}
+
+vlb_status vlb_total_mass(vlb_batch* b, double* Ntot) {
+    if (!b || !Ntot) return fail(VLB_EINVAL, "null argument");
+    if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
+    HIP_TRY(launch_reduce(b->B, b->stream, b->ddesc(), b->dtab(), b->rpart(), b->M(0), b->resid(), b->massv(), 0));
+    HIP_TRY(hipMemcpyAsync(Ntot, b->massv(), b->B * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return VLB_OK;
+}
+
+vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check_every, long* steps, double* r) {
+    if (!b || !(tol > 0) || max_steps < 1 || check_every < 1) return fail(VLB_EINVAL, "bad arguments");
+    std::vector<long> conv(b->B, -1);
+    std::vector<double> res(b->B, INFINITY);
+    long done = 0;
+    int remaining = b->B;
+    while (done < max_steps && remaining > 0) {
+        const long n = std::min<long>(check_every, max_steps - done);
+        vlb_status s = vlb_step(b, n);
+        if (s != VLB_OK) return s;
+        done += n;
+        s = vlb_residual(b, res.data());
+        if (s != VLB_OK) return s;
+        for (int i = 0; i < b->B; ++i)
+            if (conv[i] < 0 && res[i] < tol) { conv[i] = done; --remaining; }
+    }
+    if (steps) std::copy(conv.begin(), conv.end(), steps);
+    if (r) std::copy(res.begin(), res.end(), r);
+    return remaining ? fail(VLB_ENOTCONV, "%d instance(s) above tol after %ld steps", remaining, done) : VLB_OK;
+}
+
+vlb_status vlb_timing_enable(vlb_batch* b, int enable) {
+    if (!b) return fail(VLB_EINVAL, "null batch");
+    b->timing = enable != 0;
+    return VLB_OK;
+}
+
+vlb_status vlb_timing_query(vlb_batch* b, int max_groups, int* ngroups, int* vpt, long* launches, double* total_ms,
+                            double* alg_bytes) {
+    if (!b || max_groups < 0 || !ngroups) return fail(VLB_EINVAL, "bad arguments");
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    const int G = (int)b->groups.size();
+    std::vector<long> n(G, 0);
+    std::vector<double> ms(G, 0.0), by(G, 0.0);
+    for (TimedLaunch& t : b->timed) {
+        float e = 0.f;
+        HIP_TRY(hipEventElapsedTime(&e, t.start, t.stop));
+        n[t.group] += 1;
+        ms[t.group] += e;
+        by[t.group] += t.bytes;
+        b->event_pool.push_back(t.start);
+        b->event_pool.push_back(t.stop);
+    }
+    b->timed.clear();
+    int out = 0;
+    for (int g = 0; g < G; ++g) {
+        if (n[g] == 0) continue;
+        if (out < max_groups) {
+            if (vpt) vpt[out] = b->groups[g].vpt;
+            if (launches) launches[out] = n[g];
+            if (total_ms) total_ms[out] = ms[g];
+            if (alg_bytes) alg_bytes[out] = by[g];
+        }
+        ++out;
+    }
+    *ngroups = out;
+    return VLB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,481 @@
+// FP64 HIP kernels of the circular-Couette vielbein LB hot path (gfx950).
+//
+// One launch = one stage of the third-order TVD Runge-Kutta scheme (Sec. III.A,
+// Eq. rk3) for every instance of a batch.  A wavefront owns a run of consecutive
+// cells of one distribution (f' or f'') of one instance and all of that cell run's
+// velocities: lane l holds velocities k = l + 64 v, v < VPT.  It sweeps the cells in
+// order with a six-cell register window per velocity, so every population of the
+// stage input is read from HBM once (plus a three-cell halo on each side of the run)
+// and every output population is written once.  Per cell it
+//   * takes n, u, T of the stage input from the moment sums its producer left
+//     (Sec. IV.A, Eq. macro_red) and builds the polynomial equilibrium
+//     f'_eq = n g1 g2, f''_eq = T f'_eq (Sec. IV.D, Eqs. feq_red, eq_gak_H, eq_gak_hh);
+//   * computes the epsilon-free WENO-5 face flux (Sec. III.C, Eqs. weno5_flux,
+//     weno5_omega, weno_sigma, Table weno), upwinded by the sign of p^R, and the chi-form
+//     flux difference (Sec. V.C.1, Eqs. flux_kom_R / flux_kom_eta);
+//   * applies the projected momentum derivatives of the inertial force
+//     (Sec. V.A, Eq. boltz_couette_kom; kernels of Sec. IV.C) from an LDS copy of the
+//     cell's populations;
+//   * relaxes with BGK (Eq. BGK), combines the RK stage, stores, and reduces the
+//     moment sums of its output for the next stage (wavefront shuffles, fixed order).
+// Diffuse walls (Sec. III.F, Eqs. weno_flux_eq, weno_populate, extrapol, nw): the
+// wavefronts whose window reaches a wall recompute n_w from the wall-bound WENO flux
+// (a half-range sum reduced across the wavefront) and fill the ghost cells.
+#include <hip/hip_runtime.h>
+
+#include "vlb_internal.h"
+
+namespace vlb {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
+    return v;
+}
+
+// Flux at the face between c and d, upwinded from c (a, b, c, d, e in upwind order).
+__device__ __forceinline__ double weno5(double a, double b, double c, double d, double e) {
+    const double f1 = a * (1.0 / 3.0) - b * (7.0 / 6.0) + c * (11.0 / 6.0);
+    const double f2 = -b * (1.0 / 6.0) + c * (5.0 / 6.0) + d * (1.0 / 3.0);
+    const double f3 = c * (1.0 / 3.0) + d * (5.0 / 6.0) - e * (1.0 / 6.0);
+    double t1 = a - 2.0 * b + c, t2 = a - 4.0 * b + 3.0 * c;
+    const double s1 = (13.0 / 12.0) * (t1 * t1) + 0.25 * (t2 * t2);
+    t1 = b - 2.0 * c + d;
+    t2 = b - d;
+    const double s2 = (13.0 / 12.0) * (t1 * t1) + 0.25 * (t2 * t2);
+    t1 = c - 2.0 * d + e;
+    t2 = 3.0 * c - 4.0 * d + e;
+    const double s3 = (13.0 / 12.0) * (t1 * t1) + 0.25 * (t2 * t2);
+    double w1, w2, w3;
+    if (s1 == 0.0 || s2 == 0.0 || s3 == 0.0) {   // limits of Table weno
+        w1 = s1 == 0.0 ? 0.1 : 0.0;
+        w2 = s2 == 0.0 ? 0.6 : 0.0;
+        w3 = s3 == 0.0 ? 0.3 : 0.0;
+    } else {
+        w1 = 0.1 / (s1 * s1);
+        w2 = 0.6 / (s2 * s2);
+        w3 = 0.3 / (s3 * s3);
+    }
+    const double sum = w1 + w2 + w3;
+    return (w1 / sum) * f1 + (w2 / sum) * f2 + (w3 / sum) * f3;
+}
+
+// Expansion coefficients of one axis' equilibrium factor at (u, T) (Sec. IV.D):
+// full range: coefficient of phi_l = He_l/sqrt(l!) is E[He_l(X)]/sqrt(l!), X ~ N(u, T),
+//   with a_l = E[He_l]/l! from l a_l = u a_{l-1} + (T-1) a_{l-2};
+// half range: coefficient of phi_l is sum_s C[l][s] M_s with the half-line moments
+//   M_s = int_0^inf x^s N(x; +-u, T) dx:  M_0 = (1+erf(zeta))/2, M_1 = u M_0 + T g(0),
+//   M_s = u M_{s-1} + (s-1) T M_{s-2}.  Writes plus- and minus-side coefficients.
+__device__ void axis_coef(int kind, int N, double u, double T, const double* C, const double* isf,
+                          double* cp, double* cm) {
+    if (kind == 0) {
+        double a0 = 1.0, a1 = u;
+        cp[0] = cm[0] = a0 / isf[0];
+        if (N >= 1) cp[1] = cm[1] = a1 / isf[1];
+        for (int l = 2; l <= N; ++l) {
+            const double a2 = (u * a1 + (T - 1.0) * a0) / l;
+            cp[l] = cm[l] = a2 / isf[l];
+            a0 = a1;
+            a1 = a2;
+        }
+        return;
+    }
+    for (int sg = 0; sg < 2; ++sg) {
+        const double uu = sg == 0 ? u : -u;
+        double M[kMaxN + 1];
+        const double g0 = exp(-uu * uu / (2.0 * T)) / sqrt(2.0 * M_PI * T);
+        M[0] = 0.5 * (1.0 + erf(uu / sqrt(2.0 * T)));
+        if (N >= 1) M[1] = uu * M[0] + T * g0;
+        for (int s = 2; s <= N; ++s) M[s] = uu * M[s - 1] + (s - 1) * T * M[s - 2];
+        double* co = sg == 0 ? cp : cm;
+        for (int l = 0; l <= N; ++l) {
+            double acc = 0.0;
+            for (int s = 0; s <= l; ++s) acc += C[l * (N + 1) + s] * M[s];
+            co[l] = acc;
+        }
+    }
+}
+
+__device__ __forceinline__ double tau_of(int model, double Kn, double n, double T) {
+    if (model == 0) return Kn * 0.62665706865775012 / n;   // Kn sqrt(pi/8)/n, Eq. tau_aoki
+    if (model == 1) return Kn / (n * T);                   // Eq. hydro_tau
+    return Kn / n;
+}
+
+template <int VPT>
+__global__ __launch_bounds__(256) void couette_stage_f64(StageArgs A) {
+    extern __shared__ double smem[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const WorkItem* wp = A.work + (size_t)blockIdx.x * kWavesPerBlock + wave;
+    const int inst = __builtin_amdgcn_readfirstlane(wp->inst);
+    const int dist = __builtin_amdgcn_readfirstlane(wp->dist);
+    const int s0 = __builtin_amdgcn_readfirstlane(wp->s0);
+    const int ncell = __builtin_amdgcn_readfirstlane(wp->ncell);
+    const InstDesc& I = A.inst[inst];
+    const double* tab = A.tab + I.offT;
+    const int NR = I.NR, Q1 = I.Q1, Q2 = I.Q2, NV = I.NV;
+
+    // kernels of the block's instance into LDS (all waves of a block share it)
+    double* Ks = smem;
+    const int n1 = Q1 * Q1, n2 = Q2 * Q2;
+    for (int x = threadIdx.x; x < n1 + n2; x += blockDim.x) Ks[x] = x < n1 ? tab[I.tK1 + x] : tab[I.tKt2 + x - n1];
+    __syncthreads();
+    if (ncell <= 0) return;
+
+    double* row = smem + A.kmax + (size_t)wave * (A.nvmax + kWave + kTileCells * kEqStride);
+    double* gbuf = row + A.nvmax;
+    double* eqc = gbuf + kWave;
+
+    const size_t dsz = (size_t)NR * NV;
+    const double* Fd = A.Fin + I.offF + (size_t)dist * dsz;    // this distribution
+    const double* Fp = A.Fin + I.offF;                         // f' (wall density)
+    const double* Fnd = A.Fn + I.offF + (size_t)dist * dsz;
+    double* Fo = A.Fout + I.offF + (size_t)dist * dsz;
+
+    // ---- per-lane velocities
+    int vi[VPT], vj[VPT];
+    double p1[VPT], p2[VPT];
+    bool ok[VPT];
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) {
+        const int k = lane + kWave * v;
+        ok[v] = k < NV;
+        const int kk = ok[v] ? k : 0;
+        vi[v] = kk / Q2;
+        vj[v] = kk - vi[v] * Q2;
+        p1[v] = tab[I.tp1 + vi[v]];
+        p2[v] = tab[I.tp2 + vj[v]];
+    }
+
+    // ---- equilibrium coefficients of the run's cells (lane c -> cell s0 + c)
+    const int N1 = I.N1, N2 = I.N2;
+    if (lane < ncell) {
+        const double* ms = A.msum_in + (size_t)(I.offC + s0 + lane) * 5;
+        const double n = ms[0], u1 = ms[1] / n, u2 = ms[2] / n;
+        const double T = (ms[3] + ms[4] - n * (u1 * u1 + u2 * u2)) / (3.0 * n);
+        double* e = eqc + lane * kEqStride;
+        e[0] = n;
+        e[1] = T;
+        e[2] = 1.0 / tau_of(I.tau_model, I.Kn, n, T);
+        axis_coef(I.kind1, N1, u1, T, tab + I.tC1, tab + I.tisf1, e + 3, e + 3 + (N1 + 1));
+        axis_coef(I.kind2, N2, u2, T, tab + I.tC2, tab + I.tisf2, e + 3 + 2 * (N1 + 1), e + 3 + 2 * (N1 + 1) + (N2 + 1));
+    }
+    // lane role for the per-cell factor table: g1 (lane < Q1) or g2 (Q1 <= lane < Q1+Q2)
+    double brow[kMaxN + 1];
+    int coff = -1, nb = 0;
+    if (lane < Q1) {
+        nb = N1 + 1;
+        for (int l = 0; l < nb; ++l) brow[l] = tab[I.tB1 + lane * nb + l];
+        coff = 3 + ((I.kind1 == 1 && lane >= I.Qh1) ? nb : 0);
+    } else if (lane < Q1 + Q2) {
+        const int j = lane - Q1;
+        nb = N2 + 1;
+        for (int l = 0; l < nb; ++l) brow[l] = tab[I.tB2 + j * nb + l];
+        coff = 3 + 2 * (N1 + 1) + ((I.kind2 == 1 && j >= I.Qh2) ? nb : 0);
+    }
+    __syncwarp();
+
+    // ---- diffuse walls: n_w from the zero-mass-flux balance (Eq. nw)
+    const bool near_in = s0 < 3, near_out = s0 + ncell > NR - 3;
+    double nw_in = 0.0, nw_out = 0.0;
+    if (near_in) {
+        double acc = 0.0;
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) {
+            const int k = lane + kWave * v;
+            if (ok[v] && p1[v] < 0.0) {
+                const double F1 = Fp[k], F2 = Fp[NV + k], F3 = Fp[2 * NV + k];
+                const double g0 = 3.0 * F1 - 3.0 * F2 + F3, gm1 = 6.0 * F1 - 8.0 * F2 + 3.0 * F3;
+                acc += p1[v] * weno5(F3, F2, F1, g0, gm1);
+            }
+        }
+        nw_in = -wave_sum(acc) / I.den_in;
+    }
+    if (near_out) {
+        double acc = 0.0;
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) {
+            const int k = lane + kWave * v;
+            if (ok[v] && p1[v] > 0.0) {
+                const double G1 = Fp[(size_t)(NR - 1) * NV + k], G2 = Fp[(size_t)(NR - 2) * NV + k],
+                             G3 = Fp[(size_t)(NR - 3) * NV + k];
+                const double g0 = 3.0 * G1 - 3.0 * G2 + G3, gp1 = 6.0 * G1 - 8.0 * G2 + 3.0 * G3;
+                acc += p1[v] * weno5(G3, G2, G1, g0, gp1);
+            }
+        }
+        nw_out = -wave_sum(acc) / I.den_out;
+    }
+    const double wi_scale = dist ? I.T_in * nw_in : nw_in;
+    const double wo_scale = dist ? I.T_out * nw_out : nw_out;
+    const double* fin = tab + I.tfin;
+    const double* fout = tab + I.tfout;
+
+    // value of cell c (0-based; ghosts outside [0, NR)) for lane velocity v
+    auto cell = [&](int c, int v) -> double {
+        const int k = lane + kWave * v;
+        if (!ok[v]) return 0.0;
+        if (c >= 0 && c < NR) return Fd[(size_t)c * NV + k];
+        if (c < 0) {
+            if (p1[v] > 0.0) return wi_scale * fin[k];                 // Eq. weno_populate
+            const double F1 = Fd[k], F2 = Fd[NV + k], F3 = Fd[2 * NV + k];
+            if (c == -1) return 3.0 * F1 - 3.0 * F2 + F3;               // Eq. extrapol
+            if (c == -2) return 6.0 * F1 - 8.0 * F2 + 3.0 * F3;
+            return 0.0;
+        }
+        if (p1[v] < 0.0) return wo_scale * fout[k];
+        const double G1 = Fd[(size_t)(NR - 1) * NV + k], G2 = Fd[(size_t)(NR - 2) * NV + k],
+                     G3 = Fd[(size_t)(NR - 3) * NV + k];
+        if (c == NR) return 3.0 * G1 - 3.0 * G2 + G3;
+        if (c == NR + 1) return 6.0 * G1 - 8.0 * G2 + 3.0 * G3;
+        return 0.0;
+    };
+
+    // ---- window over cells s-3 .. s+2 and the flux at the first face
+    double win[VPT][6], fl[VPT];
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) win[v][q] = cell(s0 - 3 + q, v);
+        fl[v] = p1[v] > 0.0 ? weno5(win[v][0], win[v][1], win[v][2], win[v][3], win[v][4])
+                            : weno5(win[v][5], win[v][4], win[v][3], win[v][2], win[v][1]);
+    }
+
+    const double dt = A.l_only ? 1.0 : I.dt;
+    const double cdt = A.cc * dt;
+    const double* invW = tab + I.tinvW;
+    const double* Kt = Ks + n1;
+
+    for (int c = 0; c < ncell; ++c) {
+        const int s = s0 + c;
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) win[v][q] = win[v][q + 1];
+            win[v][5] = cell(s + 3, v);
+            if (ok[v]) row[lane + kWave * v] = win[v][2];
+        }
+        const double* e = eqc + c * kEqStride;
+        if (coff >= 0) {
+            double g = 0.0;
+            for (int l = 0; l < nb; ++l) g += brow[l] * e[coff + l];
+            gbuf[lane] = g;
+        }
+        __syncwarp();
+        const double Rl = tab[I.tRf + s], Rr = tab[I.tRf + s + 1];
+        const double dchi = tab[I.tdchi + s], gam = tab[I.tGam + s];
+        const double n = e[0], T = e[1], itau = e[2];
+        double m0 = 0, m1 = 0, m2 = 0, m3 = 0, rd = 0, rn = 0;
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) {
+            const int k = lane + kWave * v;
+            const double fr = p1[v] > 0.0 ? weno5(win[v][0], win[v][1], win[v][2], win[v][3], win[v][4])
+                                          : weno5(win[v][5], win[v][4], win[v][3], win[v][2], win[v][1]);
+            if (ok[v]) {
+                const int i = vi[v], j = vj[v];
+                const double adv = p1[v] * (Rr * fr - Rl * fl[v]) / dchi;
+                double kf = 0.0, ktf = 0.0;
+                for (int ip = 0; ip < Q1; ++ip) kf += Ks[i * Q1 + ip] * row[ip * Q2 + j];
+                for (int jp = 0; jp < Q2; ++jp) ktf += Kt[j * Q2 + jp] * row[i * Q2 + jp];
+                const double force = gam * (p2[v] * p2[v] * kf - p1[v] * ktf);
+                double fe = n * gbuf[i] * gbuf[Q1 + j];
+                if (dist) fe = T * fe;
+                const double Fc = win[v][2];
+                const double L = -adv - force - (Fc - fe) * itau;
+                double out;
+                if (A.l_only) {
+                    out = L;
+                } else {
+                    const double fn = A.ca != 0.0 ? Fnd[(size_t)s * NV + k] : 0.0;
+                    out = A.ca * fn + A.cb * Fc + cdt * L;
+                    if (A.rpart) {
+                        const double d = out - fn;
+                        rd += d * d * invW[k];
+                        rn += fn * fn * invW[k];
+                    }
+                }
+                Fo[(size_t)s * NV + k] = out;
+                m0 += out;
+                if (dist == 0) {
+                    m1 += p1[v] * out;
+                    m2 += p2[v] * out;
+                    m3 += (p1[v] * p1[v] + p2[v] * p2[v]) * out;
+                }
+            }
+            fl[v] = fr;
+        }
+        m0 = wave_sum(m0);
+        double* mo = A.msum_out + (size_t)(I.offC + s) * 5;
+        if (dist == 0) {
+            m1 = wave_sum(m1);
+            m2 = wave_sum(m2);
+            m3 = wave_sum(m3);
+            if (lane == 0) { mo[0] = m0; mo[1] = m1; mo[2] = m2; mo[3] = m3; }
+        } else if (lane == 0) {
+            mo[4] = m0;
+        }
+        if (A.rpart) {
+            rd = wave_sum(rd);
+            rn = wave_sum(rn);
+            if (lane == 0) {
+                double* rp = A.rpart + ((size_t)(I.offC + s) * 2 + dist) * 2;
+                rp[0] = dchi * rd;
+                rp[1] = dchi * rn;
+            }
+        }
+        __syncwarp();
+    }
+}
+
+// Moment sums [n, sum p1 f', sum p2 f', sum |p|^2 f', sum f''] of a state, per cell.
+__global__ __launch_bounds__(256) void couette_moments_f64(const InstDesc* insts, const WorkItem* work,
+                                                           const double* tab_all, const double* F,
+                                                           double* msum) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const WorkItem* wp = work + (size_t)blockIdx.x * kWavesPerBlock + wave;
+    const int inst = __builtin_amdgcn_readfirstlane(wp->inst);
+    const int dist = __builtin_amdgcn_readfirstlane(wp->dist);
+    const int s0 = __builtin_amdgcn_readfirstlane(wp->s0);
+    const int ncell = __builtin_amdgcn_readfirstlane(wp->ncell);
+    if (ncell <= 0 || dist != 0) return;
+    const InstDesc& I = insts[inst];
+    const double* tab = tab_all + I.offT;
+    const int NV = I.NV, Q2 = I.Q2;
+    const size_t dsz = (size_t)I.NR * NV;
+    for (int c = 0; c < ncell; ++c) {
+        const int s = s0 + c;
+        const double* fp = F + I.offF + (size_t)s * NV;
+        double m0 = 0, m1 = 0, m2 = 0, m3 = 0, m4 = 0;
+        for (int k = lane; k < NV; k += kWave) {
+            const int i = k / Q2, j = k - (k / Q2) * Q2;
+            const double a = tab[I.tp1 + i], b = tab[I.tp2 + j];
+            const double f = fp[k];
+            m0 += f;
+            m1 += a * f;
+            m2 += b * f;
+            m3 += (a * a + b * b) * f;
+            m4 += fp[dsz + k];
+        }
+        m0 = wave_sum(m0); m1 = wave_sum(m1); m2 = wave_sum(m2); m3 = wave_sum(m3); m4 = wave_sum(m4);
+        if (lane == 0) {
+            double* mo = msum + (size_t)(I.offC + s) * 5;
+            mo[0] = m0; mo[1] = m1; mo[2] = m2; mo[3] = m3; mo[4] = m4;
+        }
+    }
+}
+
+// Macroscopic fields n, u^R, u^phi, T, T^{R phi}, q^R, q^phi per cell (Eq. macro_red),
+// two passes over the cell's velocities (central moments about the cell velocity).
+__global__ __launch_bounds__(256) void couette_diag_f64(const InstDesc* insts, const WorkItem* work,
+                                                        const double* tab_all, const double* F, double* diag) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const WorkItem* wp = work + (size_t)blockIdx.x * kWavesPerBlock + wave;
+    const int inst = __builtin_amdgcn_readfirstlane(wp->inst);
+    const int dist = __builtin_amdgcn_readfirstlane(wp->dist);
+    const int s0 = __builtin_amdgcn_readfirstlane(wp->s0);
+    const int ncell = __builtin_amdgcn_readfirstlane(wp->ncell);
+    if (ncell <= 0 || dist != 0) return;
+    const InstDesc& I = insts[inst];
+    const double* tab = tab_all + I.offT;
+    const int NV = I.NV, Q2 = I.Q2;
+    const size_t dsz = (size_t)I.NR * NV;
+    for (int c = 0; c < ncell; ++c) {
+        const int s = s0 + c;
+        const double* fp = F + I.offF + (size_t)s * NV;
+        double m0 = 0, m1 = 0, m2 = 0;
+        for (int k = lane; k < NV; k += kWave) {
+            const int i = k / Q2, j = k - (k / Q2) * Q2;
+            const double f = fp[k];
+            m0 += f;
+            m1 += tab[I.tp1 + i] * f;
+            m2 += tab[I.tp2 + j] * f;
+        }
+        const double n = wave_sum(m0), u1 = wave_sum(m1) / n, u2 = wave_sum(m2) / n;
+        double e = 0, t12 = 0, q1 = 0, q2 = 0;
+        for (int k = lane; k < NV; k += kWave) {
+            const int i = k / Q2, j = k - (k / Q2) * Q2;
+            const double x1 = tab[I.tp1 + i] - u1, x2 = tab[I.tp2 + j] - u2;
+            const double f = fp[k], g = fp[dsz + k];
+            const double xi2 = x1 * x1 + x2 * x2;
+            e += xi2 * f + g;
+            t12 += x1 * x2 * f;
+            const double heat = 0.5 * (xi2 * f + g);
+            q1 += heat * x1;
+            q2 += heat * x2;
+        }
+        e = wave_sum(e); t12 = wave_sum(t12); q1 = wave_sum(q1); q2 = wave_sum(q2);
+        if (lane == 0) {
+            double* o = diag + (size_t)(I.offC + s) * 7;
+            o[0] = n; o[1] = u1; o[2] = u2; o[3] = e / (3.0 * n); o[4] = t12; o[5] = q1; o[6] = q2;
+        }
+    }
+}
+
+// Per-instance steady-state residual and particle number, in a fixed summation order:
+// r = sqrt(sum dchi (F_new - F_old)^2 / W) / (dt sqrt(sum dchi F_old^2 / W)),
+// N_tot = sum_s dchi_s n_s.  One block per instance.
+__global__ __launch_bounds__(256) void couette_reduce_f64(const InstDesc* insts, const double* tab_all,
+                                                          const double* rpart, const double* msum,
+                                                          double* resid, double* mass, int want_resid) {
+    __shared__ double sh[3][256];
+    const InstDesc& I = insts[blockIdx.x];
+    const double* tab = tab_all + I.offT;
+    double a = 0, b = 0, m = 0;
+    for (int s = threadIdx.x; s < I.NR; s += blockDim.x) {
+        const size_t c = (size_t)(I.offC + s);
+        if (want_resid) {
+            a += rpart[c * 4 + 0] + rpart[c * 4 + 2];
+            b += rpart[c * 4 + 1] + rpart[c * 4 + 3];
+        }
+        m += tab[I.tdchi + s] * msum[c * 5];
+    }
+    sh[0][threadIdx.x] = a;
+    sh[1][threadIdx.x] = b;
+    sh[2][threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (want_resid) resid[blockIdx.x] = sqrt(sh[0][0] / sh[1][0]) / I.dt;
+        mass[blockIdx.x] = sh[2][0];
+    }
+}
+
+// ------------------------------------------------------------------ host launchers
+hipError_t launch_stage(int vpt, int nblocks, size_t lds_bytes, hipStream_t st, const StageArgs& A) {
+    dim3 grid(nblocks), block(kWave * kWavesPerBlock);
+    switch (vpt) {
+#define VLB_CASE(V) \
+    case V: hipLaunchKernelGGL(couette_stage_f64<V>, grid, block, lds_bytes, st, A); break;
+        VLB_CASE(1) VLB_CASE(2) VLB_CASE(3) VLB_CASE(4) VLB_CASE(5)
+        VLB_CASE(6) VLB_CASE(7) VLB_CASE(8) VLB_CASE(9) VLB_CASE(10)
+#undef VLB_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
+                          const double* tab, const double* F, double* msum) {
+    hipLaunchKernelGGL(couette_moments_f64, dim3(nblocks), dim3(kWave * kWavesPerBlock), 0, st, insts, work, tab,
+                       F, msum);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
+                       const double* tab, const double* F, double* diag) {
+    hipLaunchKernelGGL(couette_diag_f64, dim3(nblocks), dim3(kWave * kWavesPerBlock), 0, st, insts, work, tab, F,
+                       diag);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(int ninst, hipStream_t st, const InstDesc* insts, const double* tab, const double* rpart,
+                         const double* msum, double* resid, double* mass, int want_resid) {
+    hipLaunchKernelGGL(couette_reduce_f64, dim3(ninst), dim3(256), 0, st, insts, tab, rpart, msum, resid, mass,
+                       want_resid);
+    return hipGetLastError();
+}
+
+}  // namespace vlb

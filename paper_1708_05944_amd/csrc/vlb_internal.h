@@ -1,0 +1,66 @@
+// Internal declarations of the vielbein-LB library (not part of the C ABI).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace vlb {
+
+constexpr int kMaxQ = 64;      // quadrature order per axis (nodes <= 128)
+constexpr int kMaxN = 4;       // equilibrium expansion order (Eq. norder_limit: N < Q)
+constexpr int kWave = 64;      // CDNA wavefront width
+constexpr int kWavesPerBlock = 4;
+constexpr int kMaxVPT = 10;    // velocities per lane -> at most 640 velocities per cell
+constexpr int kTileCells = 16; // cells swept by one wavefront
+constexpr int kEqStride = 24;  // doubles of equilibrium coefficients kept per cell
+
+// Host-side tables of one momentum axis (velocity_set.cpp).
+struct AxisTables {
+    int kind = 0, Q = 0, N = 0, nodes = 0;
+    std::vector<double> p, w;      // nodes, weights (axis ordering of Sec. IV.B)
+    std::vector<double> K, Kt;     // [nodes][nodes] d/dp and d(p .)/dp kernels
+    std::vector<double> B;         // [nodes][N+1] w_k phi_l(|p_k|)
+    std::vector<double> C;         // [N+1][N+1] monomial coefficients of phi_l (half range)
+    std::vector<double> invsqrtfact;  // 1/sqrt(l!) (full range)
+};
+
+bool build_axis(int kind, int Q, int N, AxisTables& t);
+void axis_equilibrium_host(const AxisTables& t, double u, double T, double* g);
+
+// Per-instance descriptor in device memory.  Offsets: F in elements of the state
+// buffers (instance block = [2][NR][NV]), cells in the per-cell arrays, tables in doubles.
+struct InstDesc {
+    int NR, Q1, Q2, NV;
+    int kind1, kind2, N1, N2;
+    int Qh1, Qh2, tau_model, vpt;
+    double Kn, dt, T_in, T_out, den_in, den_out;
+    long long offF, offC, offT;
+    // table offsets relative to offT
+    int tp1, tp2, tK1, tKt2, tB1, tB2, tC1, tC2, tisf1, tisf2;
+    int tfin, tfout, tinvW, tRf, tdchi, tGam;
+};
+
+// One wavefront's work: cells [s0, s0 + ncell) of one distribution of one instance.
+struct WorkItem {
+    int inst, dist, s0, ncell;
+};
+
+// Arguments of one RK stage launch: out = ca*Fn + cb*Fin + cc*dt*L[Fin].
+struct StageArgs {
+    const InstDesc* inst;
+    const WorkItem* work;
+    const double* tab;
+    const double* Fin;
+    const double* Fn;
+    double* Fout;
+    const double* msum_in;   // [cells][5] moment sums of Fin
+    double* msum_out;        // [cells][5] moment sums of Fout
+    double* rpart;           // [cells][2][2] residual partial sums (nullable)
+    double ca, cb, cc;
+    int l_only;              // 1: Fout = L[Fin] (dt taken as 1)
+    int kmax;                // doubles reserved for kernels in LDS
+    int nvmax;               // largest NV among the launch's instances
+};
+
+}  // namespace vlb

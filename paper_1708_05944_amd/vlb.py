@@ -1,0 +1,272 @@
+"""ctypes binding of libvlb.so (C ABI in include/vlb.h).  Argument marshalling only.
+
+PyTorch supplies the device memory (one uint8 workspace tensor bound to each batch)
+and the HIP stream (torch's current stream); every numerical step runs in the
+library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+VLB_FP64 = 0
+VLB_TAU_AOKI, VLB_TAU_HYDRO, VLB_TAU_KN = 0, 1, 2
+
+_lib = None
+
+
+def library_path() -> str:
+    return os.path.join(HERE, "libvlb.so")
+
+
+class VlbError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: status {status} ({message})")
+        self.status = status
+
+
+class _Axis(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("Q", ctypes.c_int), ("N", ctypes.c_int)]
+
+
+class _CouetteDesc(ctypes.Structure):
+    _fields_ = [("R_in", ctypes.c_double), ("R_out", ctypes.c_double), ("N_R", ctypes.c_int),
+                ("A", ctypes.c_double), ("delta", ctypes.c_double), ("ax1", _Axis), ("ax2", _Axis),
+                ("Kn", ctypes.c_double), ("tau_model", ctypes.c_int), ("dt", ctypes.c_double),
+                ("cfl", ctypes.c_double), ("u_in", ctypes.c_double), ("T_in", ctypes.c_double),
+                ("u_out", ctypes.c_double), ("T_out", ctypes.c_double)]
+
+
+@dataclass
+class CouetteDesc:
+    """One circular-Couette instance; ax1 / ax2 = (kind, Q, N) with kind 0 = full range
+    H(N;Q), 1 = half range HH(N;Q)."""
+    R_in: float = 1.0
+    R_out: float = 2.0
+    N_R: int = 64
+    ax1: tuple = (1, 4, 2)
+    ax2: tuple = (0, 4, 2)
+    Kn: float = 0.1
+    tau_model: int = VLB_TAU_AOKI
+    dt: float = 0.0
+    cfl: float = 0.5
+    u_in: float = 0.1
+    T_in: float = 1.0
+    u_out: float = 0.0
+    T_out: float = 1.0
+    A: float = 0.0
+    delta: float = 0.5
+
+    def _c(self) -> _CouetteDesc:
+        return _CouetteDesc(self.R_in, self.R_out, self.N_R, self.A, self.delta, _Axis(*self.ax1),
+                            _Axis(*self.ax2), self.Kn, self.tau_model, self.dt, self.cfl, self.u_in,
+                            self.T_in, self.u_out, self.T_out)
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_SIGS = {
+    "vlb_batch_create_couette": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(_CouetteDesc),
+                                 ctypes.c_int, ctypes.c_void_p, ctypes.c_int],
+    "vlb_batch_destroy": [ctypes.c_void_p],
+    "vlb_batch_workspace_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "vlb_batch_bind_workspace": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t],
+    "vlb_batch_info": [ctypes.c_void_p, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 4
+    + [_dp, ctypes.POINTER(ctypes.c_size_t)],
+    "vlb_batch_state_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "vlb_batch_velocities": [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp, _dp],
+    "vlb_set_wall": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double],
+    "vlb_init_equilibrium": [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp, _dp],
+    "vlb_set_state": [ctypes.c_void_p, _dp, ctypes.c_size_t],
+    "vlb_get_state": [ctypes.c_void_p, _dp, ctypes.c_size_t],
+    "vlb_step": [ctypes.c_void_p, ctypes.c_long],
+    "vlb_apply_L": [ctypes.c_void_p, _dp, ctypes.c_size_t],
+    "vlb_moments": [ctypes.c_void_p, ctypes.c_int] + [_dp] * 7,
+    "vlb_residual": [ctypes.c_void_p, _dp],
+    "vlb_total_mass": [ctypes.c_void_p, _dp],
+    "vlb_run_to_steady": [ctypes.c_void_p, ctypes.c_double, ctypes.c_long, ctypes.c_int,
+                          ctypes.POINTER(ctypes.c_long), _dp],
+    "vlb_axis_tables": [_Axis, _dp, _dp, _dp, _dp],
+    "vlb_timing_enable": [ctypes.c_void_p, ctypes.c_int],
+    "vlb_timing_query": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                         ctypes.POINTER(ctypes.c_long), _dp, _dp],
+    "vlb_status_string": [ctypes.c_int],
+    "vlb_last_error": [],
+}
+
+
+def load_library():
+    """Load libvlb.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1708_05944_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, args in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.vlb_status_string.restype = ctypes.c_char_p
+    lib.vlb_last_error.restype = ctypes.c_char_p
+    lib.vlb_batch_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        lib = load_library()
+        raise VlbError(status, where, lib.vlb_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def axis_tables(kind: int, Q: int, N: int = 0):
+    """Host tables of one axis as built by the library: (p, w, K, Kt)."""
+    lib = load_library()
+    n = Q if kind == 0 else 2 * Q
+    p, w = np.zeros(n), np.zeros(n)
+    K, Kt = np.zeros((n, n)), np.zeros((n, n))
+    _check(lib.vlb_axis_tables(_Axis(kind, Q, N), _ptr(p), _ptr(w), _ptr(K), _ptr(Kt)), "vlb_axis_tables")
+    return p, w, K, Kt
+
+
+class Batch:
+    """B Couette instances advanced together on one GPU."""
+
+    def __init__(self, descs, precision: int = VLB_FP64, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the vielbein LB library runs on the GPU only")
+        self._torch = torch
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        lib = load_library()
+        self.descs = list(descs)
+        arr = (_CouetteDesc * len(self.descs))(*[d._c() for d in self.descs])
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(lib.vlb_batch_create_couette(ctypes.byref(h), len(self.descs), arr, precision,
+                                            ctypes.c_void_p(self.stream.cuda_stream), 1), "vlb_batch_create_couette")
+        self._h = h
+        nbytes = ctypes.c_size_t()
+        _check(lib.vlb_batch_workspace_bytes(h, ctypes.byref(nbytes)), "vlb_batch_workspace_bytes")
+        self._ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        aligned = (base + 255) & ~255
+        _check(lib.vlb_batch_bind_workspace(h, ctypes.c_void_p(aligned), nbytes.value), "vlb_batch_bind_workspace")
+        self.B = len(self.descs)
+        n = ctypes.c_size_t()
+        _check(lib.vlb_batch_state_size(h, ctypes.byref(n)), "vlb_batch_state_size")
+        self.state_size = n.value
+        self.info = [self._info(b) for b in range(self.B)]
+
+    def _info(self, b):
+        lib = load_library()
+        NR, NV, n1, n2 = (ctypes.c_int() for _ in range(4))
+        dt = ctypes.c_double()
+        off = ctypes.c_size_t()
+        _check(lib.vlb_batch_info(self._h, b, ctypes.byref(NR), ctypes.byref(NV), ctypes.byref(n1), ctypes.byref(n2),
+                                  ctypes.byref(dt), ctypes.byref(off)), "vlb_batch_info")
+        return dict(N_R=NR.value, NV=NV.value, nodes1=n1.value, nodes2=n2.value, dt=dt.value, offset=off.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().vlb_batch_destroy(self._h)
+            self._h = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ state
+    def instance_view(self, state: np.ndarray, b: int) -> np.ndarray:
+        i = self.info[b]
+        n = 2 * i["N_R"] * i["NV"]
+        return state[i["offset"]:i["offset"] + n].reshape(2, i["N_R"], i["NV"])
+
+    def get_state(self) -> np.ndarray:
+        out = np.empty(self.state_size)
+        _check(load_library().vlb_get_state(self._h, _ptr(out), out.size), "vlb_get_state")
+        return out
+
+    def set_state(self, state: np.ndarray):
+        s = np.ascontiguousarray(state, dtype=np.float64).ravel()
+        _check(load_library().vlb_set_state(self._h, _ptr(s), s.size), "vlb_set_state")
+
+    def set_instance_state(self, b: int, F: np.ndarray):
+        st = self.get_state()
+        self.instance_view(st, b)[...] = F
+        self.set_state(st)
+
+    def init_equilibrium(self, b: int, n, u1, u2, T):
+        cells = self.info[b]["N_R"] if b >= 0 else sum(i["N_R"] for i in self.info)
+        arrs = [np.ascontiguousarray(np.broadcast_to(np.asarray(x, dtype=np.float64), (cells,))) for x in (n, u1, u2, T)]
+        _check(load_library().vlb_init_equilibrium(self._h, b, *[_ptr(a) for a in arrs]), "vlb_init_equilibrium")
+
+    def set_wall(self, b: int, side: int, u: float, T: float):
+        _check(load_library().vlb_set_wall(self._h, b, side, u, T), "vlb_set_wall")
+
+    # ------------------------------------------------------------------ stepping
+    def step(self, nsteps: int = 1):
+        _check(load_library().vlb_step(self._h, nsteps), "vlb_step")
+
+    def apply_L(self) -> np.ndarray:
+        out = np.empty(self.state_size)
+        _check(load_library().vlb_apply_L(self._h, _ptr(out), out.size), "vlb_apply_L")
+        return out
+
+    def run_to_steady(self, tol: float, max_steps: int, check_every: int = 100):
+        steps = (ctypes.c_long * self.B)()
+        r = np.empty(self.B)
+        st = load_library().vlb_run_to_steady(self._h, tol, max_steps, check_every, steps, _ptr(r))
+        if st not in (0, -5):
+            _check(st, "vlb_run_to_steady")
+        return np.array(list(steps)), r, st == 0
+
+    # ------------------------------------------------------------------ diagnostics
+    def moments(self, b: int) -> dict:
+        NR = self.info[b]["N_R"]
+        outs = [np.empty(NR) for _ in range(7)]
+        _check(load_library().vlb_moments(self._h, b, *[_ptr(o) for o in outs]), "vlb_moments")
+        return dict(zip(("n", "u1", "u2", "T", "T12", "q1", "q2"), outs))
+
+    def residual(self) -> np.ndarray:
+        r = np.empty(self.B)
+        _check(load_library().vlb_residual(self._h, _ptr(r)), "vlb_residual")
+        return r
+
+    def total_mass(self) -> np.ndarray:
+        m = np.empty(self.B)
+        _check(load_library().vlb_total_mass(self._h, _ptr(m)), "vlb_total_mass")
+        return m
+
+    def timing_enable(self, on: bool = True):
+        _check(load_library().vlb_timing_enable(self._h, 1 if on else 0), "vlb_timing_enable")
+
+    def timing_query(self):
+        """List of dicts per stage-kernel instantiation: vpt, launches, total_ms, alg_bytes."""
+        G = 64
+        ng = ctypes.c_int()
+        vpt = (ctypes.c_int * G)()
+        launches = (ctypes.c_long * G)()
+        ms, by = np.zeros(G), np.zeros(G)
+        _check(load_library().vlb_timing_query(self._h, G, ctypes.byref(ng), vpt, launches, _ptr(ms), _ptr(by)),
+               "vlb_timing_query")
+        return [dict(vpt=vpt[i], launches=launches[i], total_ms=ms[i], alg_bytes=by[i]) for i in range(ng.value)]
+
+    def velocities(self, b: int):
+        i = self.info[b]
+        p1, w1, p2, w2 = np.empty(i["nodes1"]), np.empty(i["nodes1"]), np.empty(i["nodes2"]), np.empty(i["nodes2"])
+        _check(load_library().vlb_batch_velocities(self._h, b, _ptr(p1), _ptr(w1), _ptr(p2), _ptr(w2)),
+               "vlb_batch_velocities")
+        return p1, w1, p2, w2

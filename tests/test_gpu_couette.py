@@ -1,0 +1,165 @@
+"""GPU parity of the FP64 Couette hot path against the CPU oracle, through the C ABI.
+
+Bar: max-norm difference per distribution, relative to the oracle's max-norm, at most
+1e-12 (the FP64 agreement the scheme admits: both sides round differently, e.g. fused
+multiply-adds on the GPU, but follow the same arithmetic).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.couette import TAU_AOKI, TAU_HYDRO, CouetteOracle
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _pair(**kw):
+    from paper_1708_05944_amd import Batch, CouetteDesc
+    ora = CouetteOracle(**kw)
+    dt = kw.pop("dt", None) or ora.cfl_dt(0.5)
+    desc = CouetteDesc(**{k: v for k, v in kw.items()}, dt=dt)
+    return ora, desc, dt
+
+
+def _perturbed(o, seed):
+    rng = np.random.default_rng(seed)
+    R = o.Rc
+    F = o.equilibrium(1 + 0.1 * np.sin(3 * R), 0.05 * np.cos(2 * R), 0.2 * np.sin(R), 1 + 0.1 * np.cos(R))
+    return F * rng.uniform(0.8, 1.2, F.shape)
+
+
+def _relerr(a, b):
+    a = np.asarray(a).reshape(2, -1)
+    b = np.asarray(b).reshape(2, -1)
+    return max(np.abs(a[d] - b[d]).max() / np.abs(b[d]).max() for d in range(2))
+
+
+L_CASES = [
+    dict(N_R=64, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.1, u_in=0.1),                       # single-instance workload
+    dict(N_R=37, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.1, u_in=0.3, A=0.95),               # ragged tiles, stretched
+    dict(N_R=3, ax1=(1, 4, 3), ax2=(0, 5, 4), Kn=1.0, u_in=0.2, u_out=-0.1, T_out=1.1),  # minimum grid
+    dict(N_R=40, ax1=(0, 5, 4), ax2=(0, 5, 4), Kn=1e-3, tau_model=TAU_HYDRO, u_in=0.5),  # p^R = 0 node
+    dict(N_R=70, ax1=(1, 8, 4), ax2=(1, 4, 3), Kn=2.0, u_in=0.4, A=0.5, delta=0.3),     # HH x HH
+    dict(N_R=50, ax1=(1, 16, 4), ax2=(0, 20, 4), Kn=10.0, u_in=0.5, R_out=3.0),          # 640 velocities (VPT 10)
+    dict(N_R=33, ax1=(1, 10, 4), ax2=(0, 9, 4), Kn=0.3, u_in=0.25),                     # 180 velocities (VPT 3)
+]
+
+
+@pytest.mark.parametrize("case", L_CASES)
+def test_operator_matches_oracle(case):
+    """One application of L[F] (walls, WENO, force, BGK) on a perturbed state."""
+    from paper_1708_05944_amd import Batch
+    _say(f"case {case}")
+    ora, desc, dt = _pair(**dict(case))
+    b = Batch([desc])
+    F = _perturbed(ora, 3)
+    b.set_state(F.ravel())
+    L = b.instance_view(b.apply_L(), 0)
+    Lw, _ = ora.L(F)
+    assert _relerr(L, Lw) <= TOL
+    b.close()
+
+
+def test_rk3_steps_match_oracle():
+    """1000 RK3 steps of the single-instance workload from rest."""
+    from paper_1708_05944_amd import Batch
+    ora, desc, dt = _pair(N_R=64, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.1, u_in=0.1)
+    b = Batch([desc])
+    F0 = b.instance_view(b.get_state(), 0).copy()
+    assert _relerr(F0, ora.equilibrium(1, 0, 0, 1)) <= 1e-14
+    b.step(1000)
+    got = b.instance_view(b.get_state(), 0)
+    want = ora.step(F0, dt, 1000)
+    assert _relerr(got, want) <= TOL
+    # residual of the last step and the moments agree too
+    Fm = ora.step(F0, dt, 999)
+    r_want = ora.residual(want, Fm, dt)
+    assert abs(b.residual()[0] / r_want - 1) <= 1e-9
+    m = b.moments(0)
+    mw = ora.moments(want)
+    for key in ("n", "u1", "u2", "T", "T12", "q1", "q2"):
+        scale = max(np.abs(mw[key]).max(), 1e-300)
+        assert np.abs(m[key] - mw[key]).max() <= 1e-11 * max(scale, 1e-6), key
+    b.close()
+
+
+def test_uneven_batch_matches_oracle():
+    """Instances of different grids and velocity sets advanced in the same launches."""
+    from paper_1708_05944_amd import Batch
+    cases = [L_CASES[0], L_CASES[1], L_CASES[4], L_CASES[5], L_CASES[6],
+             dict(N_R=129, ax1=(1, 6, 4), ax2=(0, 7, 4), Kn=0.05, u_in=0.2, R_out=1.5)]
+    pairs = [_pair(**dict(c)) for c in cases]
+    b = Batch([p[1] for p in pairs])
+    st = b.get_state()
+    inits = []
+    for i, (ora, _, _) in enumerate(pairs):
+        F = _perturbed(ora, 10 + i)
+        b.instance_view(st, i)[...] = F
+        inits.append(F)
+    b.set_state(st)
+    b.step(30)
+    got = b.get_state()
+    for i, (ora, _, dt) in enumerate(pairs):
+        _say(f"instance {i}: {cases[i]}")
+        want = ora.step(inits[i], dt, 30)
+        assert _relerr(b.instance_view(got, i), want) <= TOL, i
+    b.close()
+
+
+def test_particle_number_conserved_on_gpu():
+    from paper_1708_05944_amd import Batch
+    ora, desc, dt = _pair(N_R=64, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.1, u_in=0.1)
+    b = Batch([desc])
+    m0 = b.total_mass()[0]
+    assert abs(m0 / ora.mass(ora.equilibrium(1, 0, 0, 1)) - 1) <= 1e-14
+    b.step(10000)
+    assert abs(b.total_mass()[0] / m0 - 1) <= 1e4 * 2.2e-16
+    b.close()
+
+
+def test_steady_state_matches_oracle():
+    """Single-instance workload to r < 1e-10: the GPU takes exactly the oracle's step
+    count and lands on the same state; its own residual is below 1e-10 there."""
+    from paper_1708_05944_amd import Batch
+    ora, desc, dt = _pair(N_R=64, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.1, u_in=0.1)
+    F = ora.equilibrium(1, 0, 0, 1)
+    steps = 0
+    while True:
+        F = ora.step(F, dt, 499)
+        Fn = ora.step(F, dt, 1)
+        steps += 500
+        r = ora.residual(Fn, F, dt)
+        F = Fn
+        if r < 1e-10 or steps > 60000:
+            break
+    assert r < 1e-10
+    b = Batch([desc])
+    b.step(steps)
+    assert b.residual()[0] < 1e-10
+    assert _relerr(b.instance_view(b.get_state(), 0), F) <= TOL
+    b.close()
+
+
+def test_run_to_steady_and_errors():
+    from paper_1708_05944_amd import Batch, VlbError
+    ora, desc, dt = _pair(N_R=32, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.1, u_in=0.1)
+    b = Batch([desc])
+    with pytest.raises(VlbError) as e:
+        b.residual()
+    assert e.value.status == -4
+    bad = b.get_state()
+    bad[5] = math.nan
+    with pytest.raises(VlbError) as e:
+        b.set_state(bad)
+    assert e.value.status == -6
+    steps, r, ok = b.run_to_steady(1e-10, 40000, 500)
+    assert ok and r[0] < 1e-10 and steps[0] > 0
+    b.close()

@@ -1,0 +1,46 @@
+"""Host-side checks of libvlb.so that need no GPU: the library loads, exports every
+entry point declared in include/vlb.h, rejects bad arguments, and its velocity-set
+tables (built in long double by its own route) agree with the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import quadrature as q
+from paper_1708_05944_amd import axis_tables, load_library
+from paper_1708_05944_amd.vlb import VlbError
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "vlb.h")
+
+
+def test_library_exports_every_declared_symbol():
+    names = set(re.findall(r"\b(vlb_[a-z0-9_]+)\s*\(", open(HEADER).read()))
+    assert len(names) >= 19
+    lib = ctypes.CDLL(load_library()._name)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("kind,Q", [(0, 3), (0, 4), (0, 5), (0, 16), (0, 20), (1, 2), (1, 4), (1, 8), (1, 12), (1, 16), (1, 24)])
+def test_axis_tables_match_oracle(kind, Q):
+    p, w, K, Kt = axis_tables(kind, Q, 0)
+    ax = q.axis(kind, Q, 0)
+    assert np.abs(p - ax.p).max() <= 1e-14 * np.abs(ax.p).max()
+    assert np.abs(w / ax.w - 1).max() <= 1e-13
+    assert np.abs(K - ax.K).max() <= 1e-14 * np.abs(ax.K).max()
+    assert np.abs(Kt - ax.Kt).max() <= 1e-14 * max(1e-300, np.abs(ax.Kt).max())
+
+
+@pytest.mark.parametrize("axis", [(2, 4, 2), (0, 0, 0), (1, 4, 4), (0, 65, 2), (1, 8, 5)])
+def test_axis_tables_reject_invalid(axis):
+    with pytest.raises(VlbError) as e:
+        axis_tables(*axis)
+    assert e.value.status == -1
+
+
+def test_status_strings():
+    lib = load_library()
+    assert lib.vlb_status_string(0) == b"ok"
+    assert lib.vlb_status_string(-6) == b"non-finite value"
