@@ -70,7 +70,12 @@ enum {
     VLB_TAU_KN = 2         /* tau = Kn / n              (Sec. V.G benchmark runs) */
 };
 
-enum { VLB_FP64 = 0 };
+/* Precision of a batch.  VLB_FP64: every stage in FP64.  VLB_MIXED: the batch also
+ * holds an FP32 copy of the state, stored as the populations divided by their
+ * quadrature weight w_i w_j (O(1) values); its stage kernels stream and compute in FP32
+ * while moment sums, the wall mass balance (Eq. nw) and the residual accumulate in
+ * FP64.  Results handed to the caller (state, moments, L) are always FP64. */
+enum { VLB_FP64 = 0, VLB_MIXED = 1 };
 
 /* One circular-Couette instance (Sec. V).  Grid: N_R >= 3 cells between R_in < R_out;
  * A = 0 gives an equidistant grid, 0 < A < 1 the tanh stretching of Sec. III.B
@@ -95,7 +100,7 @@ typedef struct vlb_batch vlb_batch;
 /* Creates B >= 1 instances; builds velocity sets and grids on the host, uploads
  * tables, allocates device memory unless defer_alloc != 0 (then bind a workspace
  * before any other call), and sets every instance to the rest state n = 1, u = 0,
- * T = T_in (Sec. V, initial state).  precision must be VLB_FP64.  hip_stream is a
+ * T = T_in (Sec. V, initial state).  precision is VLB_FP64 or VLB_MIXED.  hip_stream is a
  * hipStream_t (may be NULL).  Errors: VLB_EINVAL for invalid descriptors (N_R < 3,
  * R_out <= R_in, invalid axes, Kn <= 0, dt < 0), VLB_EUNSTABLE if an explicit dt
  * exceeds the CFL limit of the instance, VLB_ENOMEM, VLB_EDEVICE. */
@@ -134,14 +139,18 @@ vlb_status vlb_init_equilibrium(vlb_batch* b, int inst, const double* n, const d
 vlb_status vlb_set_state(vlb_batch* b, const double* host, size_t n);
 vlb_status vlb_get_state(vlb_batch* b, double* host, size_t n);
 
-/* Advance every instance by nsteps >= 0 RK3 steps, each with its own dt.  The last
- * step records the steady-state residual r of each instance (see vlb_residual).
- * Enqueued on the stream; returns without synchronising. */
+/* Advance every instance by nsteps >= 0 RK3 steps, each with its own dt, in the batch's
+ * streaming precision (FP32 for VLB_MIXED batches, converting the state on first use).
+ * The last step records the steady-state residual r of each instance (see
+ * vlb_residual).  Enqueued on the stream; returns without synchronising.
+ * vlb_step_fp64 always steps in FP64 (converting a MIXED batch's state back first). */
 vlb_status vlb_step(vlb_batch* b, long nsteps);
+vlb_status vlb_step_fp64(vlb_batch* b, long nsteps);
 
 /* One application of the operator L[F] of Eq. L_def (advection + force + BGK with the
- * diffuse walls) to the current state; result written to the host array L (same
- * layout and size as the state).  The state is not modified.  Synchronises. */
+ * diffuse walls) to the current state, in the precision the state currently lives in;
+ * result written to the host array L (unscaled, same layout and size as the state).
+ * The state is not modified.  Synchronises. */
 vlb_status vlb_apply_L(vlb_batch* b, double* L, size_t n);
 
 /* Macroscopic fields of one instance (host arrays of N_R; any may be NULL):
@@ -163,8 +172,12 @@ vlb_status vlb_total_mass(vlb_batch* b, double* Ntot);
  * steps, at most max_steps steps.  Converged instances keep stepping while others
  * run.  steps / r (host arrays of B, may be NULL) receive the step count at which
  * each instance first reached tol (or -1) and its last residual.  Returns
- * VLB_ENOTCONV if some instance did not converge. */
+ * VLB_ENOTCONV if some instance did not converge.  For VLB_MIXED batches the run
+ * starts with FP32 steps until the largest residual is below max(tol, 1e-5) or stops
+ * falling (the FP32 rounding floor is about 6e-8/dt), then continues in FP64, so the
+ * final state is an FP64 fixed point; vlb_mixed_fp32_steps reports the FP32 steps. */
 vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check_every, long* steps, double* r);
+vlb_status vlb_mixed_fp32_steps(const vlb_batch* b, long* n);
 
 /* Host-side velocity-set tables of one axis, for checking against independent
  * implementations: nodes p, weights w (nodes entries), d/dp kernel K and d(p .)/dp
@@ -174,7 +187,8 @@ vlb_status vlb_axis_tables(vlb_axis ax, double* p, double* w, double* K, double*
 /* Kernel timing for roofline reports.  When enabled, every launch of the stage kernel
  * is bracketed by HIP events recorded on the batch's stream; launches are grouped by
  * kernel instantiation (velocities per lane, VPT).  vlb_timing_query synchronises the
- * stream and returns, for up to max_groups groups: the VPT of the instantiation, the
+ * stream and returns, for up to max_groups groups: the VPT of the instantiation (negated
+ * for the FP32 instantiation), the
  * number of launches recorded, their summed duration in ms, and the algorithmic HBM
  * bytes they moved (each launch: per population of the instances it covers, one read
  * of the stage input, one read of F_n in stages 2 and 3, one write).  Querying clears

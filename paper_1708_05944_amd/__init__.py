@@ -4,8 +4,8 @@ The numerical work runs in ``libvlb.so`` (hand-written HIP for gfx950 behind the
 of ``include/vlb.h``); this package only marshals arguments to it.  There is no CPU
 fallback: if the library is missing or no GPU is visible, calls fail loudly.
 """
-from .vlb import (VLB_FP64, VLB_TAU_AOKI, VLB_TAU_HYDRO, VLB_TAU_KN, Batch, CouetteDesc, VlbError,  # noqa: F401
+from .vlb import (VLB_FP64, VLB_MIXED, VLB_TAU_AOKI, VLB_TAU_HYDRO, VLB_TAU_KN, Batch, CouetteDesc, VlbError,  # noqa: F401
                   axis_tables, library_path, load_library)
 
 __all__ = ["Batch", "CouetteDesc", "VlbError", "axis_tables", "load_library", "library_path",
-           "VLB_FP64", "VLB_TAU_AOKI", "VLB_TAU_HYDRO", "VLB_TAU_KN"]
+           "VLB_FP64", "VLB_MIXED", "VLB_TAU_AOKI", "VLB_TAU_HYDRO", "VLB_TAU_KN"]

@@ -18,9 +18,12 @@
 #include "vlb_internal.h"
 
 namespace vlb {
-hipError_t launch_stage(int vpt, int nblocks, size_t lds_bytes, hipStream_t st, const StageArgs& A);
-hipError_t launch_moments(int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
-                          const double* tab, const double* F, double* msum);
+hipError_t launch_stage(int fp32, int vpt, int nblocks, hipStream_t st, const StageArgs& A);
+size_t stage_lds(int kmax, int nvmax, int elem);
+hipError_t launch_moments(int fp32, int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
+                          const double* tab, const void* F, double* msum);
+hipError_t launch_convert(int to32, int nblocks, hipStream_t st, const InstDesc* insts32, const WorkItem* work,
+                          const double* tab, double* F64, float* F32);
 hipError_t launch_reduce(int ninst, hipStream_t st, const InstDesc* insts, const double* tab, const double* rpart,
                          const double* msum, double* resid, double* mass, int want_resid);
 hipError_t launch_diag(int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
@@ -57,6 +60,7 @@ struct LaunchGroup {
 
 struct TimedLaunch {
     int group;
+    bool fp32;
     hipEvent_t start, stop;
     double bytes;
 };
@@ -82,7 +86,12 @@ struct vlb_batch {
     std::vector<double> tab;
     size_t state_n = 0, ncells = 0;
     // workspace layout (byte offsets)
-    size_t off_F[3], off_M[3], off_rpart, off_resid, off_mass, off_tab, off_desc, off_work, off_diag, total_bytes;
+    size_t off_F[3], off_F32[3], off_M[3], off_rpart, off_resid, off_mass, off_tab, off_desc, off_desc32, off_work,
+        off_diag, total_bytes;
+    int precision = VLB_FP64;
+    bool cur32 = false;                 // the current state lives in the FP32 buffers
+    long fp32_steps = 0;                // steps of the FP32 phase of the last run_to_steady
+    std::vector<InstDesc> desc32;       // FP32 descriptors (rescaled tables)
     char* ws = nullptr;
     bool owns = false;
     bool have_resid = false;
@@ -91,6 +100,8 @@ struct vlb_batch {
     std::vector<hipEvent_t> event_pool;
 
     double* F(int i) { return (double*)(ws + off_F[i]); }
+    float* F32(int i) { return (float*)(ws + off_F32[i]); }
+    InstDesc* ddesc32() { return (InstDesc*)(ws + off_desc32); }
     double* M(int i) { return (double*)(ws + off_M[i]); }
     double* rpart() { return (double*)(ws + off_rpart); }
     double* resid() { return (double*)(ws + off_resid); }
@@ -152,19 +163,37 @@ vlb_status upload_tables(vlb_batch* b) {
     HIP_TRY(hipMemcpyAsync(b->dtab(), b->tab.data(), b->tab.size() * sizeof(double), hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipMemcpyAsync(b->ddesc(), b->desc.data(), b->desc.size() * sizeof(InstDesc), hipMemcpyHostToDevice,
                            b->stream));
+    if (b->precision == VLB_MIXED)
+        HIP_TRY(hipMemcpyAsync(b->ddesc32(), b->desc32.data(), b->desc32.size() * sizeof(InstDesc),
+                               hipMemcpyHostToDevice, b->stream));
     return VLB_OK;
 }
 
 vlb_status refresh_moments(vlb_batch* b) {
     const int nblocks = (int)(b->work.size() / kWavesPerBlock);
-    HIP_TRY(launch_moments(nblocks, b->stream, b->ddesc(), b->dwork(), b->dtab(), b->F(0), b->M(0)));
-    b->have_resid = false;
+    if (b->cur32)
+        HIP_TRY(launch_moments(1, nblocks, b->stream, b->ddesc32(), b->dwork(), b->dtab(), b->F32(0), b->M(0)));
+    else
+        HIP_TRY(launch_moments(0, nblocks, b->stream, b->ddesc(), b->dwork(), b->dtab(), b->F(0), b->M(0)));
     return VLB_OK;
+}
+
+// Move the current state between the FP64 buffer and the scaled FP32 buffer.
+vlb_status ensure_precision(vlb_batch* b, bool want32) {
+    if (b->cur32 == want32) return VLB_OK;
+    if (want32 && b->precision != VLB_MIXED) return fail(VLB_ESTATE, "batch has no FP32 buffers");
+    const int nblocks = (int)(b->work.size() / kWavesPerBlock);
+    HIP_TRY(launch_convert(want32 ? 1 : 0, nblocks, b->stream, b->ddesc32(), b->dwork(), b->dtab(), b->F(0),
+                           b->F32(0)));
+    b->cur32 = want32;
+    return refresh_moments(b);
 }
 
 vlb_status set_state_device(vlb_batch* b, const double* host) {
     HIP_TRY(hipMemcpyAsync(b->F(0), host, b->state_n * sizeof(double), hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
+    b->cur32 = false;
+    b->have_resid = false;
     return refresh_moments(b);
 }
 
@@ -188,6 +217,10 @@ void equilibrium_state(const InstHost& h, const double* n, const double* u1, con
 vlb_status layout_and_alloc(vlb_batch* b, bool alloc) {
     size_t off = 0;
     for (int i = 0; i < 3; ++i) { b->off_F[i] = off; off = align256(off + b->state_n * sizeof(double)); }
+    for (int i = 0; i < 3; ++i) {
+        b->off_F32[i] = off;
+        if (b->precision == VLB_MIXED) off = align256(off + b->state_n * sizeof(float));
+    }
     for (int i = 0; i < 3; ++i) { b->off_M[i] = off; off = align256(off + b->ncells * 5 * sizeof(double)); }
     b->off_rpart = off; off = align256(off + b->ncells * 4 * sizeof(double));
     b->off_diag = off; off = align256(off + b->ncells * 7 * sizeof(double));
@@ -195,6 +228,7 @@ vlb_status layout_and_alloc(vlb_batch* b, bool alloc) {
     b->off_mass = off; off = align256(off + b->B * sizeof(double));
     b->off_tab = off; off = align256(off + b->tab.size() * sizeof(double));
     b->off_desc = off; off = align256(off + b->desc.size() * sizeof(InstDesc));
+    b->off_desc32 = off; off = align256(off + b->desc32.size() * sizeof(InstDesc));
     b->off_work = off; off = align256(off + b->work.size() * sizeof(WorkItem));
     b->total_bytes = off;
     if (!alloc) return VLB_OK;
@@ -223,39 +257,43 @@ vlb_status finish_setup(vlb_batch* b) {
 
 bool check_instance(vlb_batch* b, int inst) { return b && inst >= 0 && inst < b->B; }
 
+// One RK stage (or one operator application) on the current precision's buffers.
 vlb_status run_stage(vlb_batch* b, int stage, bool last, bool l_only) {
+    const bool f32 = b->cur32;
+    auto Fb = [&](int i) -> void* { return f32 ? (void*)b->F32(i) : (void*)b->F(i); };
     StageArgs A;
-    A.inst = b->ddesc();
+    A.inst = f32 ? b->ddesc32() : b->ddesc();
     A.work = b->dwork();
     A.tab = b->dtab();
     A.rpart = nullptr;
+    A.C = nullptr;
     A.l_only = l_only ? 1 : 0;
     if (l_only) {
-        A.Fin = b->F(0); A.Fn = b->F(0); A.Fout = b->F(1);
+        A.Fin = Fb(0); A.Fn = Fb(0); A.Fout = Fb(1);
         A.msum_in = b->M(0); A.msum_out = b->M(1);
         A.ca = 0.0; A.cb = 0.0; A.cc = 1.0;
     } else if (stage == 0) {
-        A.Fin = b->F(0); A.Fn = b->F(0); A.Fout = b->F(1);
+        A.Fin = Fb(0); A.Fn = Fb(0); A.Fout = Fb(1);
         A.msum_in = b->M(0); A.msum_out = b->M(1);
         A.ca = 0.0; A.cb = 1.0; A.cc = 1.0;
     } else if (stage == 1) {
-        A.Fin = b->F(1); A.Fn = b->F(0); A.Fout = b->F(2);
+        A.Fin = Fb(1); A.Fn = Fb(0); A.Fout = Fb(2);
         A.msum_in = b->M(1); A.msum_out = b->M(2);
         A.ca = 0.75; A.cb = 0.25; A.cc = 0.25;
     } else {
-        A.Fin = b->F(2); A.Fn = b->F(0); A.Fout = b->F(0);
+        A.Fin = Fb(2); A.Fn = Fb(0); A.Fout = Fb(0);
         A.msum_in = b->M(2); A.msum_out = b->M(0);
         A.ca = 1.0 / 3.0; A.cb = 2.0 / 3.0; A.cc = 2.0 / 3.0;
         if (last) A.rpart = b->rpart();
     }
     const double values = (l_only || stage == 0) ? 2.0 : 3.0;   // algorithmic HBM values per population
+    const double elem = f32 ? sizeof(float) : sizeof(double);
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
         const LaunchGroup& g = b->groups[gi];
         StageArgs G = A;
         G.work = b->dwork() + (size_t)g.first_block * kWavesPerBlock;
         G.kmax = g.kmax;
         G.nvmax = g.nvmax;
-        const size_t lds = (size_t)(g.kmax + kWavesPerBlock * (g.nvmax + kWave + kTileCells * kEqStride)) * sizeof(double);
         TimedLaunch t{};
         if (b->timing) {
             for (hipEvent_t* e : {&t.start, &t.stop}) {
@@ -268,14 +306,39 @@ vlb_status run_stage(vlb_batch* b, int stage, bool last, bool l_only) {
             }
             HIP_TRY(hipEventRecord(t.start, b->stream));
         }
-        HIP_TRY(launch_stage(g.vpt, g.nblocks, lds, b->stream, G));
+        HIP_TRY(launch_stage(f32 ? 1 : 0, g.vpt, g.nblocks, b->stream, G));
         if (b->timing) {
             HIP_TRY(hipEventRecord(t.stop, b->stream));
             t.group = (int)gi;
-            t.bytes = values * g.pops * sizeof(double);
+            t.fp32 = f32;
+            t.bytes = values * g.pops * elem;
             b->timed.push_back(t);
         }
     }
+    return VLB_OK;
+}
+
+vlb_status step_current(vlb_batch* b, long nsteps) {
+    for (long it = 0; it < nsteps; ++it) {
+        const bool last = it + 1 == nsteps;
+        for (int st = 0; st < 3; ++st) {
+            vlb_status s = run_stage(b, st, last, false);
+            if (s != VLB_OK) return s;
+        }
+        if (last) {
+            HIP_TRY(launch_reduce(b->B, b->stream, b->cur32 ? b->ddesc32() : b->ddesc(), b->dtab(), b->rpart(), b->M(0),
+                                  b->resid(), b->massv(), 1));
+            b->have_resid = true;
+        }
+    }
+    return VLB_OK;
+}
+
+vlb_status read_residual(vlb_batch* b, double* r) {
+    HIP_TRY(hipMemcpyAsync(r, b->resid(), b->B * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (int i = 0; i < b->B; ++i)
+        if (!std::isfinite(r[i])) return fail(VLB_ENONFINITE, "non-finite residual in instance %d", i);
     return VLB_OK;
 }
 
@@ -314,13 +377,15 @@ vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_de
                                     void* hip_stream, int defer_alloc) {
     if (!out || B < 1 || !descs) return fail(VLB_EINVAL, "need out, B >= 1 and descriptors");
     *out = nullptr;
-    if (precision != VLB_FP64) return fail(VLB_EINVAL, "unsupported precision %d", precision);
+    if (precision != VLB_FP64 && precision != VLB_MIXED) return fail(VLB_EINVAL, "unsupported precision %d", precision);
     vlb_batch* b = new (std::nothrow) vlb_batch;
     if (!b) return fail(VLB_ENOMEM, "host allocation failed");
     b->B = B;
+    b->precision = precision;
     b->stream = (hipStream_t)hip_stream;
     b->inst.resize(B);
     b->desc.resize(B);
+    if (precision == VLB_MIXED) b->desc32.resize(B);
     std::map<std::tuple<int, int, int>, AxisTables> cache;
     size_t offF = 0, offC = 0;
     for (int i = 0; i < B; ++i) {
@@ -403,13 +468,43 @@ vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_de
         wall_table(h, d.u_out, d.T_out, 1, tout, D.den_out);
         D.tfin = put(tin);
         D.tfout = put(tout);
-        std::vector<double> invW(h.NV);
+        std::vector<double> W(h.NV), invW(h.NV), ones(h.NV, 1.0);
         for (int a = 0; a < h.a1.nodes; ++a)
-            for (int c = 0; c < h.a2.nodes; ++c) invW[a * h.a2.nodes + c] = 1.0 / (h.a1.w[a] * h.a2.w[c]);
-        D.tinvW = put(invW);
+            for (int c = 0; c < h.a2.nodes; ++c) {
+                W[a * h.a2.nodes + c] = h.a1.w[a] * h.a2.w[c];
+                invW[a * h.a2.nodes + c] = 1.0 / W[a * h.a2.nodes + c];
+            }
+        D.tWm = put(ones);       // stored populations are the weighted f_ij themselves
+        D.tresW = put(invW);     // ||F||_W^2 = sum F^2 / W
         D.tRf = put(h.Rf);
         D.tdchi = put(h.dchi);
         D.tGam = put(h.Gam);
+        if (precision == VLB_MIXED) {
+            // FP32 path: populations scaled by 1/W (f/omega at the nodes, O(1) values); the
+            // kernels become diag(1/w) K diag(w), the equilibrium bases lose their w factor
+            // and the wall tables are divided by W.  Moments and n_w sums weight by W; the
+            // residual weight becomes W.
+            InstDesc& E = b->desc32[i];
+            E = D;
+            const int n1 = h.a1.nodes, n2 = h.a2.nodes;
+            std::vector<double> K1s(h.a1.K), Kt2s(h.a2.Kt), B1s(h.a1.B), B2s(h.a2.B);
+            for (int a = 0; a < n1; ++a)
+                for (int c = 0; c < n1; ++c) K1s[a * n1 + c] *= h.a1.w[c] / h.a1.w[a];
+            for (int a = 0; a < n2; ++a)
+                for (int c = 0; c < n2; ++c) Kt2s[a * n2 + c] *= h.a2.w[c] / h.a2.w[a];
+            for (int a = 0; a < n1; ++a)
+                for (int l = 0; l <= h.a1.N; ++l) B1s[a * (h.a1.N + 1) + l] /= h.a1.w[a];
+            for (int a = 0; a < n2; ++a)
+                for (int l = 0; l <= h.a2.N; ++l) B2s[a * (h.a2.N + 1) + l] /= h.a2.w[a];
+            std::vector<double> tins(tin), touts(tout);
+            for (int k = 0; k < h.NV; ++k) { tins[k] *= invW[k]; touts[k] *= invW[k]; }
+            E.tK1 = put(K1s); E.tKt2 = put(Kt2s);
+            E.tB1 = put(B1s); E.tB2 = put(B2s);
+            E.tfin = put(tins); E.tfout = put(touts);
+            E.tWm = put(W);
+            E.tresW = E.tWm;
+        }
+        if (precision == VLB_MIXED) b->desc32[i].offT = D.offT;
         offF += (size_t)2 * d.N_R * h.NV;
         offC += d.N_R;
     }
@@ -448,7 +543,7 @@ vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_de
         g.kmax = (limits[kv.first].first + 1) & ~1;
         g.nvmax = (limits[kv.first].second + 1) & ~1;
         g.pops = pops[kv.first];
-        const size_t lds = (size_t)(g.kmax + kWavesPerBlock * (g.nvmax + kWave + kTileCells * kEqStride)) * sizeof(double);
+        const size_t lds = stage_lds(g.kmax, g.nvmax, sizeof(double));
         if (lds > 160 * 1024) {
             delete b;
             return fail(VLB_EINVAL, "velocity sets too large for LDS (%zu bytes)", lds);
@@ -539,8 +634,17 @@ vlb_status vlb_set_wall(vlb_batch* b, int inst, int side, double u, double T) {
     wall_table(h, u, T, side, tbl, den);
     const int off = side == 0 ? D.tfin : D.tfout;
     std::copy(tbl.begin(), tbl.end(), b->tab.begin() + D.offT + off);
+    if (b->precision == VLB_MIXED) {
+        const InstDesc& E = b->desc32[inst];
+        const int off32 = side == 0 ? E.tfin : E.tfout;
+        for (int k = 0; k < h.NV; ++k) b->tab[E.offT + off32 + k] = tbl[k] * b->tab[D.offT + D.tresW + k];
+    }
     if (side == 0) { h.d.u_in = u; h.d.T_in = T; D.den_in = den; D.T_in = T; }
     else { h.d.u_out = u; h.d.T_out = T; D.den_out = den; D.T_out = T; }
+    if (b->precision == VLB_MIXED) {
+        InstDesc& E = b->desc32[inst];
+        E.den_in = D.den_in; E.den_out = D.den_out; E.T_in = D.T_in; E.T_out = D.T_out;
+    }
     HIP_TRY(hipStreamSynchronize(b->stream));
     return upload_tables(b);
 }
@@ -549,6 +653,8 @@ vlb_status vlb_init_equilibrium(vlb_batch* b, int inst, const double* n, const d
                                 const double* T) {
     if (!b || !n || !u1 || !u2 || !T || inst < -1 || inst >= b->B) return fail(VLB_EINVAL, "bad arguments");
     if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
+    vlb_status es = ensure_precision(b, false);
+    if (es != VLB_OK) return es;
     std::vector<double> host(b->state_n);
     HIP_TRY(hipMemcpyAsync(host.data(), b->F(0), b->state_n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
@@ -578,6 +684,8 @@ vlb_status vlb_set_state(vlb_batch* b, const double* host, size_t n) {
 vlb_status vlb_get_state(vlb_batch* b, double* host, size_t n) {
     if (!b || !host || n != b->state_n) return fail(VLB_EINVAL, "state size mismatch");
     if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
+    vlb_status es = ensure_precision(b, false);
+    if (es != VLB_OK) return es;
     HIP_TRY(hipMemcpyAsync(host, b->F(0), n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     return VLB_OK;
@@ -586,18 +694,17 @@ vlb_status vlb_get_state(vlb_batch* b, double* host, size_t n) {
 vlb_status vlb_step(vlb_batch* b, long nsteps) {
     if (!b || nsteps < 0) return fail(VLB_EINVAL, "bad arguments");
     if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
-    for (long it = 0; it < nsteps; ++it) {
-        const bool last = it + 1 == nsteps;
-        for (int st = 0; st < 3; ++st) {
-            vlb_status s = run_stage(b, st, last, false);
-            if (s != VLB_OK) return s;
-        }
-        if (last) {
-            HIP_TRY(launch_reduce(b->B, b->stream, b->ddesc(), b->dtab(), b->rpart(), b->M(0), b->resid(), b->massv(), 1));
-            b->have_resid = true;
-        }
-    }
-    return VLB_OK;
+    vlb_status s = ensure_precision(b, b->precision == VLB_MIXED);
+    if (s != VLB_OK) return s;
+    return step_current(b, nsteps);
+}
+
+vlb_status vlb_step_fp64(vlb_batch* b, long nsteps) {
+    if (!b || nsteps < 0) return fail(VLB_EINVAL, "bad arguments");
+    if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
+    vlb_status s = ensure_precision(b, false);
+    if (s != VLB_OK) return s;
+    return step_current(b, nsteps);
 }
 
 vlb_status vlb_apply_L(vlb_batch* b, double* L, size_t n) {
@@ -605,6 +712,11 @@ vlb_status vlb_apply_L(vlb_batch* b, double* L, size_t n) {
     if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
     vlb_status s = run_stage(b, 0, false, true);
     if (s != VLB_OK) return s;
+    if (b->cur32) {
+        // unscale the FP32 result into the FP64 scratch buffer (F * W on the device)
+        const int nblocks = (int)(b->work.size() / kWavesPerBlock);
+        HIP_TRY(launch_convert(0, nblocks, b->stream, b->ddesc32(), b->dwork(), b->dtab(), b->F(1), b->F32(1)));
+    }
     HIP_TRY(hipMemcpyAsync(L, b->F(1), n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     return VLB_OK;
@@ -614,6 +726,8 @@ vlb_status vlb_moments(vlb_batch* b, int inst, double* n, double* u1, double* u2
                        double* q1, double* q2) {
     if (!check_instance(b, inst)) return fail(VLB_EINVAL, "bad instance");
     if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
+    vlb_status es = ensure_precision(b, false);
+    if (es != VLB_OK) return es;
     const int nblocks = (int)(b->work.size() / kWavesPerBlock);
     HIP_TRY(launch_diag(nblocks, b->stream, b->ddesc(), b->dwork(), b->dtab(), b->F(0), b->diag()));
     const InstDesc& D = b->desc[inst];
@@ -631,11 +745,7 @@ vlb_status vlb_moments(vlb_batch* b, int inst, double* n, double* u1, double* u2
 vlb_status vlb_residual(vlb_batch* b, double* r) {
     if (!b || !r) return fail(VLB_EINVAL, "null argument");
     if (!b->have_resid) return fail(VLB_ESTATE, "no step recorded since the last state change");
-    HIP_TRY(hipMemcpyAsync(r, b->resid(), b->B * sizeof(double), hipMemcpyDeviceToHost, b->stream));
-    HIP_TRY(hipStreamSynchronize(b->stream));
-    for (int i = 0; i < b->B; ++i)
-        if (!std::isfinite(r[i])) return fail(VLB_ENONFINITE, "non-finite residual in instance %d", i);
-    return VLB_OK;
+    return read_residual(b, r);
 }
 
 vlb_status vlb_total_mass(vlb_batch* b, double* Ntot) {
@@ -649,16 +759,41 @@ vlb_status vlb_total_mass(vlb_batch* b, double* Ntot) {
 
 vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check_every, long* steps, double* r) {
     if (!b || !(tol > 0) || max_steps < 1 || check_every < 1) return fail(VLB_EINVAL, "bad arguments");
+    if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
     std::vector<long> conv(b->B, -1);
     std::vector<double> res(b->B, INFINITY);
     long done = 0;
+    vlb_status s = VLB_OK;
+    if (b->precision == VLB_MIXED) {
+        // FP32 phase: stream the scaled FP32 state while every instance's residual still
+        // falls; stop at 1e-5 (the FP32 rounding floor is eps32/dt) or when the largest
+        // residual stops improving by 5% over three checks.
+        s = ensure_precision(b, true);
+        if (s != VLB_OK) return s;
+        double best = INFINITY;
+        int stall = 0;
+        while (done < max_steps) {
+            const long n = std::min<long>(check_every, max_steps - done);
+            s = step_current(b, n);
+            if (s != VLB_OK) return s;
+            done += n;
+            s = read_residual(b, res.data());
+            if (s != VLB_OK) return s;
+            const double worst = *std::max_element(res.begin(), res.end());
+            if (worst < std::max(tol, 1e-5)) break;
+            if (worst < 0.95 * best) { best = worst; stall = 0; } else if (++stall >= 3) break;
+        }
+        b->fp32_steps = done;
+    }
+    s = ensure_precision(b, false);
+    if (s != VLB_OK) return s;
     int remaining = b->B;
     while (done < max_steps && remaining > 0) {
         const long n = std::min<long>(check_every, max_steps - done);
-        vlb_status s = vlb_step(b, n);
+        s = step_current(b, n);
         if (s != VLB_OK) return s;
         done += n;
-        s = vlb_residual(b, res.data());
+        s = read_residual(b, res.data());
         if (s != VLB_OK) return s;
         for (int i = 0; i < b->B; ++i)
             if (conv[i] < 0 && res[i] < tol) { conv[i] = done; --remaining; }
@@ -666,6 +801,12 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
     if (steps) std::copy(conv.begin(), conv.end(), steps);
     if (r) std::copy(res.begin(), res.end(), r);
     return remaining ? fail(VLB_ENOTCONV, "%d instance(s) above tol after %ld steps", remaining, done) : VLB_OK;
+}
+
+vlb_status vlb_mixed_fp32_steps(const vlb_batch* b, long* n) {
+    if (!b || !n) return fail(VLB_EINVAL, "null argument");
+    *n = b->fp32_steps;
+    return VLB_OK;
 }
 
 vlb_status vlb_timing_enable(vlb_batch* b, int enable) {
@@ -678,15 +819,16 @@ vlb_status vlb_timing_query(vlb_batch* b, int max_groups, int* ngroups, int* vpt
                             double* alg_bytes) {
     if (!b || max_groups < 0 || !ngroups) return fail(VLB_EINVAL, "bad arguments");
     HIP_TRY(hipStreamSynchronize(b->stream));
-    const int G = (int)b->groups.size();
+    const int G = (int)b->groups.size() * 2;   // (group, precision)
     std::vector<long> n(G, 0);
     std::vector<double> ms(G, 0.0), by(G, 0.0);
     for (TimedLaunch& t : b->timed) {
         float e = 0.f;
         HIP_TRY(hipEventElapsedTime(&e, t.start, t.stop));
-        n[t.group] += 1;
-        ms[t.group] += e;
-        by[t.group] += t.bytes;
+        const int key = t.group * 2 + (t.fp32 ? 1 : 0);
+        n[key] += 1;
+        ms[key] += e;
+        by[key] += t.bytes;
         b->event_pool.push_back(t.start);
         b->event_pool.push_back(t.stop);
     }
@@ -695,7 +837,7 @@ vlb_status vlb_timing_query(vlb_batch* b, int max_groups, int* ngroups, int* vpt
     for (int g = 0; g < G; ++g) {
         if (n[g] == 0) continue;
         if (out < max_groups) {
-            if (vpt) vpt[out] = b->groups[g].vpt;
+            if (vpt) vpt[out] = b->groups[g / 2].vpt * ((g & 1) ? -1 : 1);
             if (launches) launches[out] = n[g];
             if (total_ms) total_ms[out] = ms[g];
             if (alg_bytes) alg_bytes[out] = by[g];

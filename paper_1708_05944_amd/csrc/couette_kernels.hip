@@ -34,30 +34,40 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Flux at the face between c and d, upwinded from c (a, b, c, d, e in upwind order).
-__device__ __forceinline__ double weno5(double a, double b, double c, double d, double e) {
-    const double f1 = a * (1.0 / 3.0) - b * (7.0 / 6.0) + c * (11.0 / 6.0);
-    const double f2 = -b * (1.0 / 6.0) + c * (5.0 / 6.0) + d * (1.0 / 3.0);
-    const double f3 = c * (1.0 / 3.0) + d * (5.0 / 6.0) - e * (1.0 / 6.0);
-    double t1 = a - 2.0 * b + c, t2 = a - 4.0 * b + 3.0 * c;
-    const double s1 = (13.0 / 12.0) * (t1 * t1) + 0.25 * (t2 * t2);
-    t1 = b - 2.0 * c + d;
+template <typename T>
+__device__ __forceinline__ T weno5(T a, T b, T c, T d, T e) {
+    const T f1 = a * T(1.0 / 3.0) - b * T(7.0 / 6.0) + c * T(11.0 / 6.0);
+    const T f2 = -b * T(1.0 / 6.0) + c * T(5.0 / 6.0) + d * T(1.0 / 3.0);
+    const T f3 = c * T(1.0 / 3.0) + d * T(5.0 / 6.0) - e * T(1.0 / 6.0);
+    T t1 = a - T(2) * b + c, t2 = a - T(4) * b + T(3) * c;
+    const T s1 = T(13.0 / 12.0) * (t1 * t1) + T(0.25) * (t2 * t2);
+    t1 = b - T(2) * c + d;
     t2 = b - d;
-    const double s2 = (13.0 / 12.0) * (t1 * t1) + 0.25 * (t2 * t2);
-    t1 = c - 2.0 * d + e;
-    t2 = 3.0 * c - 4.0 * d + e;
-    const double s3 = (13.0 / 12.0) * (t1 * t1) + 0.25 * (t2 * t2);
-    double w1, w2, w3;
-    if (s1 == 0.0 || s2 == 0.0 || s3 == 0.0) {   // limits of Table weno
-        w1 = s1 == 0.0 ? 0.1 : 0.0;
-        w2 = s2 == 0.0 ? 0.6 : 0.0;
-        w3 = s3 == 0.0 ? 0.3 : 0.0;
+    const T s2 = T(13.0 / 12.0) * (t1 * t1) + T(0.25) * (t2 * t2);
+    t1 = c - T(2) * d + e;
+    t2 = T(3) * c - T(4) * d + e;
+    const T s3 = T(13.0 / 12.0) * (t1 * t1) + T(0.25) * (t2 * t2);
+    T w1, w2, w3;
+    if (s1 == T(0) || s2 == T(0) || s3 == T(0)) {   // limits of Table weno
+        w1 = s1 == T(0) ? T(0.1) : T(0);
+        w2 = s2 == T(0) ? T(0.6) : T(0);
+        w3 = s3 == T(0) ? T(0.3) : T(0);
     } else {
-        w1 = 0.1 / (s1 * s1);
-        w2 = 0.6 / (s2 * s2);
-        w3 = 0.3 / (s3 * s3);
+        // w_q proportional to d_q / s_q^2, rewritten as d_q (r_a r_b)^2 with r = s / max(s):
+        // one division instead of three and no overflow.  In FP64 an underflow would need
+        // two indicators below 1e-155 of the largest, which only exact zeros reach; the
+        // FP32 path runs on populations scaled by 1/(w_i w_j), which are O(1), so its
+        // indicators stay far from the FP32 range limits.
+        T m = s1 > s2 ? s1 : s2;
+        m = m > s3 ? m : s3;
+        const T inv = T(1) / m;
+        const T r1 = s1 * inv, r2 = s2 * inv, r3 = s3 * inv;
+        const T q23 = r2 * r3, q13 = r1 * r3, q12 = r1 * r2;
+        w1 = T(0.1) * (q23 * q23);
+        w2 = T(0.6) * (q13 * q13);
+        w3 = T(0.3) * (q12 * q12);
     }
-    const double sum = w1 + w2 + w3;
-    return (w1 / sum) * f1 + (w2 / sum) * f2 + (w3 / sum) * f3;
+    return (w1 * f1 + w2 * f2 + w3 * f3) / (w1 + w2 + w3);
 }
 
 // Expansion coefficients of one axis' equilibrium factor at (u, T) (Sec. IV.D):
@@ -102,9 +112,18 @@ __device__ __forceinline__ double tau_of(int model, double Kn, double n, double 
     return Kn / n;
 }
 
-template <int VPT>
-__global__ __launch_bounds__(256) void couette_stage_f64(StageArgs A) {
-    extern __shared__ double smem[];
+// Bytes of LDS a stage launch needs: kernel tables, then per wavefront the cell row, the
+// per-cell equilibrium factors and the equilibrium coefficients of its cell run.
+__host__ __device__ inline size_t stage_lds_bytes(int kmax, int nvmax, int elem) {
+    const size_t kb = ((size_t)kmax * elem + 7) & ~size_t(7);
+    const size_t wb = (((size_t)(nvmax + kWave) * elem + 7) & ~size_t(7)) + (size_t)kTileCells * kEqStride * 8;
+    return kb + kWavesPerBlock * wb;
+}
+
+template <typename T, int VPT>
+__global__ __launch_bounds__(256) void couette_stage(StageArgs A) {
+    extern __shared__ double smem_d[];
+    char* smem = reinterpret_cast<char*>(smem_d);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const WorkItem* wp = A.work + (size_t)blockIdx.x * kWavesPerBlock + wave;
     const int inst = __builtin_amdgcn_readfirstlane(wp->inst);
@@ -116,25 +135,28 @@ __global__ __launch_bounds__(256) void couette_stage_f64(StageArgs A) {
     const int NR = I.NR, Q1 = I.Q1, Q2 = I.Q2, NV = I.NV;
 
     // kernels of the block's instance into LDS (all waves of a block share it)
-    double* Ks = smem;
+    T* Ks = reinterpret_cast<T*>(smem);
     const int n1 = Q1 * Q1, n2 = Q2 * Q2;
-    for (int x = threadIdx.x; x < n1 + n2; x += blockDim.x) Ks[x] = x < n1 ? tab[I.tK1 + x] : tab[I.tKt2 + x - n1];
+    for (int x = threadIdx.x; x < n1 + n2; x += blockDim.x) Ks[x] = T(x < n1 ? tab[I.tK1 + x] : tab[I.tKt2 + x - n1]);
     __syncthreads();
     if (ncell <= 0) return;
 
-    double* row = smem + A.kmax + (size_t)wave * (A.nvmax + kWave + kTileCells * kEqStride);
-    double* gbuf = row + A.nvmax;
-    double* eqc = gbuf + kWave;
+    const size_t kb = ((size_t)A.kmax * sizeof(T) + 7) & ~size_t(7);
+    const size_t wb = (((size_t)(A.nvmax + kWave) * sizeof(T) + 7) & ~size_t(7)) + (size_t)kTileCells * kEqStride * 8;
+    T* row = reinterpret_cast<T*>(smem + kb + wave * wb);
+    T* gbuf = row + A.nvmax;
+    double* eqc = reinterpret_cast<double*>(smem + kb + wave * wb + wb - (size_t)kTileCells * kEqStride * 8);
 
     const size_t dsz = (size_t)NR * NV;
-    const double* Fd = A.Fin + I.offF + (size_t)dist * dsz;    // this distribution
-    const double* Fp = A.Fin + I.offF;                         // f' (wall density)
-    const double* Fnd = A.Fn + I.offF + (size_t)dist * dsz;
-    double* Fo = A.Fout + I.offF + (size_t)dist * dsz;
+    const T* Fd = static_cast<const T*>(A.Fin) + I.offF + (size_t)dist * dsz;   // this distribution
+    const T* Fp = static_cast<const T*>(A.Fin) + I.offF;                        // f' (wall density)
+    const T* Fnd = static_cast<const T*>(A.Fn) + I.offF + (size_t)dist * dsz;
+    T* Fo = static_cast<T*>(A.Fout) + I.offF + (size_t)dist * dsz;
+    const T* Cd = A.C ? static_cast<const T*>(A.C) + I.offF + (size_t)dist * dsz : nullptr;
 
     // ---- per-lane velocities
     int vi[VPT], vj[VPT];
-    double p1[VPT], p2[VPT];
+    T p1[VPT], p2[VPT];
     bool ok[VPT];
 #pragma unroll
     for (int v = 0; v < VPT; ++v) {
@@ -143,22 +165,22 @@ __global__ __launch_bounds__(256) void couette_stage_f64(StageArgs A) {
         const int kk = ok[v] ? k : 0;
         vi[v] = kk / Q2;
         vj[v] = kk - vi[v] * Q2;
-        p1[v] = tab[I.tp1 + vi[v]];
-        p2[v] = tab[I.tp2 + vj[v]];
+        p1[v] = T(tab[I.tp1 + vi[v]]);
+        p2[v] = T(tab[I.tp2 + vj[v]]);
     }
 
-    // ---- equilibrium coefficients of the run's cells (lane c -> cell s0 + c)
+    // ---- equilibrium coefficients of the run's cells (lane c -> cell s0 + c), FP64
     const int N1 = I.N1, N2 = I.N2;
     if (lane < ncell) {
         const double* ms = A.msum_in + (size_t)(I.offC + s0 + lane) * 5;
         const double n = ms[0], u1 = ms[1] / n, u2 = ms[2] / n;
-        const double T = (ms[3] + ms[4] - n * (u1 * u1 + u2 * u2)) / (3.0 * n);
+        const double T_ = (ms[3] + ms[4] - n * (u1 * u1 + u2 * u2)) / (3.0 * n);
         double* e = eqc + lane * kEqStride;
         e[0] = n;
-        e[1] = T;
-        e[2] = 1.0 / tau_of(I.tau_model, I.Kn, n, T);
-        axis_coef(I.kind1, N1, u1, T, tab + I.tC1, tab + I.tisf1, e + 3, e + 3 + (N1 + 1));
-        axis_coef(I.kind2, N2, u2, T, tab + I.tC2, tab + I.tisf2, e + 3 + 2 * (N1 + 1), e + 3 + 2 * (N1 + 1) + (N2 + 1));
+        e[1] = T_;
+        e[2] = 1.0 / tau_of(I.tau_model, I.Kn, n, T_);
+        axis_coef(I.kind1, N1, u1, T_, tab + I.tC1, tab + I.tisf1, e + 3, e + 3 + (N1 + 1));
+        axis_coef(I.kind2, N2, u2, T_, tab + I.tC2, tab + I.tisf2, e + 3 + 2 * (N1 + 1), e + 3 + 2 * (N1 + 1) + (N2 + 1));
     }
     // lane role for the per-cell factor table: g1 (lane < Q1) or g2 (Q1 <= lane < Q1+Q2)
     double brow[kMaxN + 1];
@@ -175,7 +197,8 @@ __global__ __launch_bounds__(256) void couette_stage_f64(StageArgs A) {
     }
     __syncwarp();
 
-    // ---- diffuse walls: n_w from the zero-mass-flux balance (Eq. nw)
+    // ---- diffuse walls: n_w from the zero-mass-flux balance (Eq. nw), FP64 sums
+    const double* Wm = tab + I.tWm;   // quadrature weight of a stored population (1 when unscaled)
     const bool near_in = s0 < 3, near_out = s0 + ncell > NR - 3;
     double nw_in = 0.0, nw_out = 0.0;
     if (near_in) {
@@ -183,10 +206,10 @@ __global__ __launch_bounds__(256) void couette_stage_f64(StageArgs A) {
 #pragma unroll
         for (int v = 0; v < VPT; ++v) {
             const int k = lane + kWave * v;
-            if (ok[v] && p1[v] < 0.0) {
-                const double F1 = Fp[k], F2 = Fp[NV + k], F3 = Fp[2 * NV + k];
-                const double g0 = 3.0 * F1 - 3.0 * F2 + F3, gm1 = 6.0 * F1 - 8.0 * F2 + 3.0 * F3;
-                acc += p1[v] * weno5(F3, F2, F1, g0, gm1);
+            if (ok[v] && p1[v] < T(0)) {
+                const T F1 = Fp[k], F2 = Fp[NV + k], F3 = Fp[2 * NV + k];
+                const T g0 = T(3) * F1 - T(3) * F2 + F3, gm1 = T(6) * F1 - T(8) * F2 + T(3) * F3;
+                acc += (double)p1[v] * Wm[k] * (double)weno5<T>(F3, F2, F1, g0, gm1);
             }
         }
         nw_in = -wave_sum(acc) / I.den_in;
@@ -196,54 +219,54 @@ __global__ __launch_bounds__(256) void couette_stage_f64(StageArgs A) {
 #pragma unroll
         for (int v = 0; v < VPT; ++v) {
             const int k = lane + kWave * v;
-            if (ok[v] && p1[v] > 0.0) {
-                const double G1 = Fp[(size_t)(NR - 1) * NV + k], G2 = Fp[(size_t)(NR - 2) * NV + k],
-                             G3 = Fp[(size_t)(NR - 3) * NV + k];
-                const double g0 = 3.0 * G1 - 3.0 * G2 + G3, gp1 = 6.0 * G1 - 8.0 * G2 + 3.0 * G3;
-                acc += p1[v] * weno5(G3, G2, G1, g0, gp1);
+            if (ok[v] && p1[v] > T(0)) {
+                const T G1 = Fp[(size_t)(NR - 1) * NV + k], G2 = Fp[(size_t)(NR - 2) * NV + k],
+                        G3 = Fp[(size_t)(NR - 3) * NV + k];
+                const T g0 = T(3) * G1 - T(3) * G2 + G3, gp1 = T(6) * G1 - T(8) * G2 + T(3) * G3;
+                acc += (double)p1[v] * Wm[k] * (double)weno5<T>(G3, G2, G1, g0, gp1);
             }
         }
         nw_out = -wave_sum(acc) / I.den_out;
     }
-    const double wi_scale = dist ? I.T_in * nw_in : nw_in;
-    const double wo_scale = dist ? I.T_out * nw_out : nw_out;
+    const T wi_scale = T(dist ? I.T_in * nw_in : nw_in);
+    const T wo_scale = T(dist ? I.T_out * nw_out : nw_out);
     const double* fin = tab + I.tfin;
     const double* fout = tab + I.tfout;
 
     // value of cell c (0-based; ghosts outside [0, NR)) for lane velocity v
-    auto cell = [&](int c, int v) -> double {
+    auto cell = [&](int c, int v) -> T {
         const int k = lane + kWave * v;
-        if (!ok[v]) return 0.0;
+        if (!ok[v]) return T(0);
         if (c >= 0 && c < NR) return Fd[(size_t)c * NV + k];
         if (c < 0) {
-            if (p1[v] > 0.0) return wi_scale * fin[k];                 // Eq. weno_populate
-            const double F1 = Fd[k], F2 = Fd[NV + k], F3 = Fd[2 * NV + k];
-            if (c == -1) return 3.0 * F1 - 3.0 * F2 + F3;               // Eq. extrapol
-            if (c == -2) return 6.0 * F1 - 8.0 * F2 + 3.0 * F3;
-            return 0.0;
+            if (p1[v] > T(0)) return wi_scale * T(fin[k]);             // Eq. weno_populate
+            const T F1 = Fd[k], F2 = Fd[NV + k], F3 = Fd[2 * NV + k];
+            if (c == -1) return T(3) * F1 - T(3) * F2 + F3;            // Eq. extrapol
+            if (c == -2) return T(6) * F1 - T(8) * F2 + T(3) * F3;
+            return T(0);
         }
-        if (p1[v] < 0.0) return wo_scale * fout[k];
-        const double G1 = Fd[(size_t)(NR - 1) * NV + k], G2 = Fd[(size_t)(NR - 2) * NV + k],
-                     G3 = Fd[(size_t)(NR - 3) * NV + k];
-        if (c == NR) return 3.0 * G1 - 3.0 * G2 + G3;
-        if (c == NR + 1) return 6.0 * G1 - 8.0 * G2 + 3.0 * G3;
-        return 0.0;
+        if (p1[v] < T(0)) return wo_scale * T(fout[k]);
+        const T G1 = Fd[(size_t)(NR - 1) * NV + k], G2 = Fd[(size_t)(NR - 2) * NV + k],
+                G3 = Fd[(size_t)(NR - 3) * NV + k];
+        if (c == NR) return T(3) * G1 - T(3) * G2 + G3;
+        if (c == NR + 1) return T(6) * G1 - T(8) * G2 + T(3) * G3;
+        return T(0);
     };
 
     // ---- window over cells s-3 .. s+2 and the flux at the first face
-    double win[VPT][6], fl[VPT];
+    T win[VPT][6], fl[VPT];
 #pragma unroll
     for (int v = 0; v < VPT; ++v) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) win[v][q] = cell(s0 - 3 + q, v);
-        fl[v] = p1[v] > 0.0 ? weno5(win[v][0], win[v][1], win[v][2], win[v][3], win[v][4])
-                            : weno5(win[v][5], win[v][4], win[v][3], win[v][2], win[v][1]);
+        fl[v] = p1[v] > T(0) ? weno5<T>(win[v][0], win[v][1], win[v][2], win[v][3], win[v][4])
+                             : weno5<T>(win[v][5], win[v][4], win[v][3], win[v][2], win[v][1]);
     }
 
     const double dt = A.l_only ? 1.0 : I.dt;
-    const double cdt = A.cc * dt;
-    const double* invW = tab + I.tinvW;
-    const double* Kt = Ks + n1;
+    const T cdt = T(A.cc * dt), ca = T(A.ca), cb = T(A.cb);
+    const double* resW = tab + I.tresW;
+    const T* Kt = Ks + n1;
 
     for (int c = 0; c < ncell; ++c) {
         const int s = s0 + c;
@@ -258,47 +281,49 @@ __global__ __launch_bounds__(256) void couette_stage_f64(StageArgs A) {
         if (coff >= 0) {
             double g = 0.0;
             for (int l = 0; l < nb; ++l) g += brow[l] * e[coff + l];
-            gbuf[lane] = g;
+            gbuf[lane] = T(g);
         }
         __syncwarp();
-        const double Rl = tab[I.tRf + s], Rr = tab[I.tRf + s + 1];
-        const double dchi = tab[I.tdchi + s], gam = tab[I.tGam + s];
-        const double n = e[0], T = e[1], itau = e[2];
+        const T Rl = T(tab[I.tRf + s]), Rr = T(tab[I.tRf + s + 1]);
+        const T dchi = T(tab[I.tdchi + s]), gam = T(tab[I.tGam + s]);
+        const T n = T(e[0]), Tc = T(e[1]), itau = T(e[2]);
         double m0 = 0, m1 = 0, m2 = 0, m3 = 0, rd = 0, rn = 0;
 #pragma unroll
         for (int v = 0; v < VPT; ++v) {
             const int k = lane + kWave * v;
-            const double fr = p1[v] > 0.0 ? weno5(win[v][0], win[v][1], win[v][2], win[v][3], win[v][4])
-                                          : weno5(win[v][5], win[v][4], win[v][3], win[v][2], win[v][1]);
+            const T fr = p1[v] > T(0) ? weno5<T>(win[v][0], win[v][1], win[v][2], win[v][3], win[v][4])
+                                      : weno5<T>(win[v][5], win[v][4], win[v][3], win[v][2], win[v][1]);
             if (ok[v]) {
                 const int i = vi[v], j = vj[v];
-                const double adv = p1[v] * (Rr * fr - Rl * fl[v]) / dchi;
-                double kf = 0.0, ktf = 0.0;
+                const T adv = p1[v] * (Rr * fr - Rl * fl[v]) / dchi;
+                T kf = T(0), ktf = T(0);
                 for (int ip = 0; ip < Q1; ++ip) kf += Ks[i * Q1 + ip] * row[ip * Q2 + j];
                 for (int jp = 0; jp < Q2; ++jp) ktf += Kt[j * Q2 + jp] * row[i * Q2 + jp];
-                const double force = gam * (p2[v] * p2[v] * kf - p1[v] * ktf);
-                double fe = n * gbuf[i] * gbuf[Q1 + j];
-                if (dist) fe = T * fe;
-                const double Fc = win[v][2];
-                const double L = -adv - force - (Fc - fe) * itau;
-                double out;
+                const T force = gam * (p2[v] * p2[v] * kf - p1[v] * ktf);
+                T fe = n * gbuf[i] * gbuf[Q1 + j];
+                if (dist) fe = Tc * fe;
+                const T Fc = win[v][2];
+                T L = -adv - force - (Fc - fe) * itau;
+                if (Cd) L += Cd[(size_t)s * NV + k];
+                T out;
                 if (A.l_only) {
                     out = L;
                 } else {
-                    const double fn = A.ca != 0.0 ? Fnd[(size_t)s * NV + k] : 0.0;
-                    out = A.ca * fn + A.cb * Fc + cdt * L;
+                    const T fn = ca != T(0) ? Fnd[(size_t)s * NV + k] : T(0);
+                    out = ca * fn + cb * Fc + cdt * L;
                     if (A.rpart) {
-                        const double d = out - fn;
-                        rd += d * d * invW[k];
-                        rn += fn * fn * invW[k];
+                        const double d = (double)out - (double)fn;
+                        rd += d * d * resW[k];
+                        rn += (double)fn * (double)fn * resW[k];
                     }
                 }
                 Fo[(size_t)s * NV + k] = out;
-                m0 += out;
+                const double wo = Wm[k] * (double)out;
+                m0 += wo;
                 if (dist == 0) {
-                    m1 += p1[v] * out;
-                    m2 += p2[v] * out;
-                    m3 += (p1[v] * p1[v] + p2[v] * p2[v]) * out;
+                    m1 += (double)p1[v] * wo;
+                    m2 += (double)p2[v] * wo;
+                    m3 += ((double)p1[v] * (double)p1[v] + (double)p2[v] * (double)p2[v]) * wo;
                 }
             }
             fl[v] = fr;
@@ -318,18 +343,19 @@ __global__ __launch_bounds__(256) void couette_stage_f64(StageArgs A) {
             rn = wave_sum(rn);
             if (lane == 0) {
                 double* rp = A.rpart + ((size_t)(I.offC + s) * 2 + dist) * 2;
-                rp[0] = dchi * rd;
-                rp[1] = dchi * rn;
+                rp[0] = (double)dchi * rd;
+                rp[1] = (double)dchi * rn;
             }
         }
         __syncwarp();
     }
 }
 
-// Moment sums [n, sum p1 f', sum p2 f', sum |p|^2 f', sum f''] of a state, per cell.
-__global__ __launch_bounds__(256) void couette_moments_f64(const InstDesc* insts, const WorkItem* work,
-                                                           const double* tab_all, const double* F,
-                                                           double* msum) {
+// Moment sums [n, sum p1 f', sum p2 f', sum |p|^2 f', sum f''] of a state, per cell
+// (FP64 accumulation; populations weighted by Wm, 1 for unscaled FP64 states).
+template <typename T>
+__global__ __launch_bounds__(256) void couette_moments(const InstDesc* insts, const WorkItem* work,
+                                                       const double* tab_all, const T* F, double* msum) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const WorkItem* wp = work + (size_t)blockIdx.x * kWavesPerBlock + wave;
     const int inst = __builtin_amdgcn_readfirstlane(wp->inst);
@@ -339,26 +365,51 @@ __global__ __launch_bounds__(256) void couette_moments_f64(const InstDesc* insts
     if (ncell <= 0 || dist != 0) return;
     const InstDesc& I = insts[inst];
     const double* tab = tab_all + I.offT;
+    const double* Wm = tab + I.tWm;
     const int NV = I.NV, Q2 = I.Q2;
     const size_t dsz = (size_t)I.NR * NV;
     for (int c = 0; c < ncell; ++c) {
         const int s = s0 + c;
-        const double* fp = F + I.offF + (size_t)s * NV;
+        const T* fp = F + I.offF + (size_t)s * NV;
         double m0 = 0, m1 = 0, m2 = 0, m3 = 0, m4 = 0;
         for (int k = lane; k < NV; k += kWave) {
             const int i = k / Q2, j = k - (k / Q2) * Q2;
             const double a = tab[I.tp1 + i], b = tab[I.tp2 + j];
-            const double f = fp[k];
+            const double f = Wm[k] * (double)fp[k];
             m0 += f;
             m1 += a * f;
             m2 += b * f;
             m3 += (a * a + b * b) * f;
-            m4 += fp[dsz + k];
+            m4 += Wm[k] * (double)fp[dsz + k];
         }
         m0 = wave_sum(m0); m1 = wave_sum(m1); m2 = wave_sum(m2); m3 = wave_sum(m3); m4 = wave_sum(m4);
         if (lane == 0) {
             double* mo = msum + (size_t)(I.offC + s) * 5;
             mo[0] = m0; mo[1] = m1; mo[2] = m2; mo[3] = m3; mo[4] = m4;
+        }
+    }
+}
+
+// Conversions between the FP64 state and the scaled FP32 state F/(w_i w_j) of the
+// reduced-precision path (to32: F32 = F64 / W; from32: F64 = W * F32), element-wise.
+template <bool TO32>
+__global__ __launch_bounds__(256) void couette_convert(const InstDesc* insts32, const WorkItem* work,
+                                                       const double* tab_all, double* F64, float* F32) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const WorkItem* wp = work + (size_t)blockIdx.x * kWavesPerBlock + wave;
+    const int inst = __builtin_amdgcn_readfirstlane(wp->inst);
+    const int dist = __builtin_amdgcn_readfirstlane(wp->dist);
+    const int s0 = __builtin_amdgcn_readfirstlane(wp->s0);
+    const int ncell = __builtin_amdgcn_readfirstlane(wp->ncell);
+    if (ncell <= 0) return;
+    const InstDesc& I = insts32[inst];
+    const double* W = tab_all + I.offT + I.tWm;
+    const size_t base = I.offF + (size_t)dist * I.NR * I.NV;
+    for (int c = 0; c < ncell; ++c) {
+        const size_t row = base + (size_t)(s0 + c) * I.NV;
+        for (int k = lane; k < I.NV; k += kWave) {
+            if (TO32) F32[row + k] = (float)(F64[row + k] / W[k]);
+            else F64[row + k] = W[k] * (double)F32[row + k];
         }
     }
 }
@@ -444,11 +495,13 @@ __global__ __launch_bounds__(256) void couette_reduce_f64(const InstDesc* insts,
 }
 
 // ------------------------------------------------------------------ host launchers
-hipError_t launch_stage(int vpt, int nblocks, size_t lds_bytes, hipStream_t st, const StageArgs& A) {
+template <typename T>
+static hipError_t launch_stage_t(int vpt, int nblocks, hipStream_t st, const StageArgs& A) {
     dim3 grid(nblocks), block(kWave * kWavesPerBlock);
+    const size_t lds = stage_lds_bytes(A.kmax, A.nvmax, sizeof(T));
     switch (vpt) {
 #define VLB_CASE(V) \
-    case V: hipLaunchKernelGGL(couette_stage_f64<V>, grid, block, lds_bytes, st, A); break;
+    case V: hipLaunchKernelGGL((couette_stage<T, V>), grid, block, lds, st, A); break;
         VLB_CASE(1) VLB_CASE(2) VLB_CASE(3) VLB_CASE(4) VLB_CASE(5)
         VLB_CASE(6) VLB_CASE(7) VLB_CASE(8) VLB_CASE(9) VLB_CASE(10)
 #undef VLB_CASE
@@ -457,10 +510,31 @@ hipError_t launch_stage(int vpt, int nblocks, size_t lds_bytes, hipStream_t st, 
     return hipGetLastError();
 }
 
-hipError_t launch_moments(int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
-                          const double* tab, const double* F, double* msum) {
-    hipLaunchKernelGGL(couette_moments_f64, dim3(nblocks), dim3(kWave * kWavesPerBlock), 0, st, insts, work, tab,
-                       F, msum);
+size_t stage_lds(int kmax, int nvmax, int elem) { return stage_lds_bytes(kmax, nvmax, elem); }
+
+hipError_t launch_stage(int fp32, int vpt, int nblocks, hipStream_t st, const StageArgs& A) {
+    return fp32 ? launch_stage_t<float>(vpt, nblocks, st, A) : launch_stage_t<double>(vpt, nblocks, st, A);
+}
+
+hipError_t launch_moments(int fp32, int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
+                          const double* tab, const void* F, double* msum) {
+    if (fp32)
+        hipLaunchKernelGGL(couette_moments<float>, dim3(nblocks), dim3(kWave * kWavesPerBlock), 0, st, insts, work,
+                           tab, static_cast<const float*>(F), msum);
+    else
+        hipLaunchKernelGGL(couette_moments<double>, dim3(nblocks), dim3(kWave * kWavesPerBlock), 0, st, insts, work,
+                           tab, static_cast<const double*>(F), msum);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(int to32, int nblocks, hipStream_t st, const InstDesc* insts32, const WorkItem* work,
+                          const double* tab, double* F64, float* F32) {
+    if (to32)
+        hipLaunchKernelGGL(couette_convert<true>, dim3(nblocks), dim3(kWave * kWavesPerBlock), 0, st, insts32, work,
+                           tab, F64, F32);
+    else
+        hipLaunchKernelGGL(couette_convert<false>, dim3(nblocks), dim3(kWave * kWavesPerBlock), 0, st, insts32, work,
+                           tab, F64, F32);
     return hipGetLastError();
 }
 

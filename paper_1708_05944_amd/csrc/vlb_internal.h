@@ -30,6 +30,8 @@ void axis_equilibrium_host(const AxisTables& t, double u, double T, double* g);
 
 // Per-instance descriptor in device memory.  Offsets: F in elements of the state
 // buffers (instance block = [2][NR][NV]), cells in the per-cell arrays, tables in doubles.
+// The FP32 path works on scaled populations F/(w_i w_j) and has its own descriptor whose
+// table offsets point at rescaled tables (kernels, equilibrium bases, wall tables).
 struct InstDesc {
     int NR, Q1, Q2, NV;
     int kind1, kind2, N1, N2;
@@ -38,7 +40,7 @@ struct InstDesc {
     long long offF, offC, offT;
     // table offsets relative to offT
     int tp1, tp2, tK1, tKt2, tB1, tB2, tC1, tC2, tisf1, tisf2;
-    int tfin, tfout, tinvW, tRf, tdchi, tGam;
+    int tfin, tfout, tWm, tresW, tRf, tdchi, tGam, pad;
 };
 
 // One wavefront's work: cells [s0, s0 + ncell) of one distribution of one instance.
@@ -46,20 +48,22 @@ struct WorkItem {
     int inst, dist, s0, ncell;
 };
 
-// Arguments of one RK stage launch: out = ca*Fn + cb*Fin + cc*dt*L[Fin].
+// Arguments of one RK stage launch: out = ca*Fn + cb*Fin + cc*dt*(L[Fin] + C).
+// F pointers are double* (FP64 path) or float* (FP32 path).
 struct StageArgs {
     const InstDesc* inst;
     const WorkItem* work;
     const double* tab;
-    const double* Fin;
-    const double* Fn;
-    double* Fout;
+    const void* Fin;
+    const void* Fn;
+    void* Fout;
+    const void* C;           // constant forcing added to L (nullable)
     const double* msum_in;   // [cells][5] moment sums of Fin
     double* msum_out;        // [cells][5] moment sums of Fout
     double* rpart;           // [cells][2][2] residual partial sums (nullable)
     double ca, cb, cc;
     int l_only;              // 1: Fout = L[Fin] (dt taken as 1)
-    int kmax;                // doubles reserved for kernels in LDS
+    int kmax;                // kernel-table elements reserved in LDS
     int nvmax;               // largest NV among the launch's instances
 };
 

@@ -13,7 +13,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-VLB_FP64 = 0
+VLB_FP64, VLB_MIXED = 0, 1
 VLB_TAU_AOKI, VLB_TAU_HYDRO, VLB_TAU_KN = 0, 1, 2
 
 _lib = None
@@ -83,6 +83,8 @@ _SIGS = {
     "vlb_set_state": [ctypes.c_void_p, _dp, ctypes.c_size_t],
     "vlb_get_state": [ctypes.c_void_p, _dp, ctypes.c_size_t],
     "vlb_step": [ctypes.c_void_p, ctypes.c_long],
+    "vlb_step_fp64": [ctypes.c_void_p, ctypes.c_long],
+    "vlb_mixed_fp32_steps": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_long)],
     "vlb_apply_L": [ctypes.c_void_p, _dp, ctypes.c_size_t],
     "vlb_moments": [ctypes.c_void_p, ctypes.c_int] + [_dp] * 7,
     "vlb_residual": [ctypes.c_void_p, _dp],
@@ -220,6 +222,14 @@ class Batch:
     def step(self, nsteps: int = 1):
         _check(load_library().vlb_step(self._h, nsteps), "vlb_step")
 
+    def step_fp64(self, nsteps: int = 1):
+        _check(load_library().vlb_step_fp64(self._h, nsteps), "vlb_step_fp64")
+
+    def fp32_steps(self) -> int:
+        n = ctypes.c_long()
+        _check(load_library().vlb_mixed_fp32_steps(self._h, ctypes.byref(n)), "vlb_mixed_fp32_steps")
+        return n.value
+
     def apply_L(self) -> np.ndarray:
         out = np.empty(self.state_size)
         _check(load_library().vlb_apply_L(self._h, _ptr(out), out.size), "vlb_apply_L")
@@ -254,7 +264,8 @@ class Batch:
         _check(load_library().vlb_timing_enable(self._h, 1 if on else 0), "vlb_timing_enable")
 
     def timing_query(self):
-        """List of dicts per stage-kernel instantiation: vpt, launches, total_ms, alg_bytes."""
+        """List of dicts per stage-kernel instantiation: vpt (negative for FP32), launches,
+        total_ms, alg_bytes."""
         G = 64
         ng = ctypes.c_int()
         vpt = (ctypes.c_int * G)()

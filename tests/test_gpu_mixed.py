@@ -1,0 +1,95 @@
+"""Reduced-precision (VLB_MIXED) path: FP32 stage kernels on scaled populations, FP64
+moment / wall / residual accumulation, FP64 polish to the steady state.
+
+Bars: the FP32 operator agrees with the FP64 oracle to FP32 rounding (relative
+max-norm 2e-6, about 30 ulp of float); every steady-state profile (n, u^phi, T,
+T^{R phi}) of the mixed run is within 1e-5 relative of the FP64 run; the mixed run ends
+below the same residual tolerance."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.couette import TAU_HYDRO, CouetteOracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _perturbed(o, seed):
+    rng = np.random.default_rng(seed)
+    R = o.Rc
+    F = o.equilibrium(1 + 0.1 * np.sin(3 * R), 0.05 * np.cos(2 * R), 0.2 * np.sin(R), 1 + 0.1 * np.cos(R))
+    return F * rng.uniform(0.8, 1.2, F.shape)
+
+
+CASES = [
+    dict(N_R=64, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.1, u_in=0.1),
+    dict(N_R=45, ax1=(1, 16, 4), ax2=(0, 20, 4), Kn=10.0, u_in=0.5, R_out=3.0),
+    dict(N_R=40, ax1=(0, 5, 4), ax2=(0, 5, 4), Kn=1e-3, tau_model=TAU_HYDRO, u_in=0.5),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_fp32_operator_matches_oracle_to_fp32_rounding(case):
+    from paper_1708_05944_amd import VLB_MIXED, Batch, CouetteDesc
+    _say(f"case {case}")
+    ora = CouetteOracle(**case)
+    b = Batch([CouetteDesc(**case, dt=ora.cfl_dt(0.5))], precision=VLB_MIXED)
+    F = _perturbed(ora, 5)
+    b.set_state(F.ravel())
+    b.step(0)                      # moves the state into the FP32 buffers
+    L = b.instance_view(b.apply_L(), 0)
+    Lw, _ = ora.L(F)
+    err = max(np.abs(L[d] - Lw[d]).max() / np.abs(Lw[d]).max() for d in range(2))
+    _say(f"fp32 operator rel err {err:.2e}")
+    assert err <= 2e-6
+    b.close()
+
+
+def test_mixed_steady_state_matches_fp64():
+    """Single-instance workload to r < 1e-10 in FP64 and in mixed precision."""
+    from paper_1708_05944_amd import VLB_MIXED, Batch, CouetteDesc, workloads
+    d = workloads.single_couette()
+    runs = {}
+    for name, prec in (("fp64", 0), ("mixed", VLB_MIXED)):
+        b = Batch([d], precision=prec)
+        steps, r, ok = b.run_to_steady(1e-10, 60000, 500)
+        assert ok and r[0] < 1e-10, (name, r)
+        runs[name] = (b.moments(0), steps[0], b.fp32_steps() if prec else 0)
+        b.close()
+    m64, m32 = runs["fp64"][0], runs["mixed"][0]
+    for key in ("n", "u2", "T", "T12"):
+        err = np.abs(m32[key] - m64[key]).max() / np.abs(m64[key]).max()
+        _say(f"{key}: mixed vs fp64 rel err {err:.2e}")
+        assert err <= 1e-5, key
+    _say(f"steps fp64 {runs['fp64'][1]}, mixed {runs['mixed'][1]} ({runs['mixed'][2]} in FP32)")
+
+
+def test_fp32_phase_profile_error_is_stated():
+    """The FP32-only state where the residual stops falling, against the FP64 steady
+    state: the profile error there is what the FP64 polish removes (reported, and
+    bounded by 1e-3 so that the polish starts close)."""
+    from paper_1708_05944_amd import VLB_MIXED, Batch, workloads
+    d = workloads.single_couette()
+    b64 = Batch([d])
+    b64.run_to_steady(1e-10, 60000, 500)
+    m64 = b64.moments(0)
+    b64.close()
+    b = Batch([d], precision=VLB_MIXED)
+    last = None
+    for _ in range(60):
+        b.step(500)
+        r = b.residual()[0]
+        if last is not None and r > 0.95 * last:
+            break
+        last = r
+    m = b.moments(0)
+    errs = {k: float(np.abs(m[k] - m64[k]).max() / np.abs(m64[k]).max()) for k in ("n", "u2", "T", "T12")}
+    _say(f"FP32 floor residual {r:.2e}; profile errors {errs}")
+    assert max(errs.values()) < 1e-3
+    b.close()
