@@ -10,7 +10,7 @@ import sys
 import numpy as np
 import pytest
 
-from oracle.couette import TAU_AOKI, TAU_HYDRO, CouetteOracle
+from oracle.couette import TAU_HYDRO, CouetteOracle
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -22,11 +22,12 @@ def _say(msg):
 
 
 def _pair(**kw):
-    from paper_1708_05944_amd import Batch, CouetteDesc
+    """Oracle and library descriptor of one instance; dt = 0 lets the library pick its
+    stable step (advection CFL 0.5, force and relaxation limits), which the test then
+    hands to the oracle."""
+    from paper_1708_05944_amd import CouetteDesc
     ora = CouetteOracle(**kw)
-    dt = kw.pop("dt", None) or ora.cfl_dt(0.5)
-    desc = CouetteDesc(**{k: v for k, v in kw.items()}, dt=dt)
-    return ora, desc, dt
+    return ora, CouetteDesc(**kw)
 
 
 def _perturbed(o, seed):
@@ -58,7 +59,7 @@ def test_operator_matches_oracle(case):
     """One application of L[F] (walls, WENO, force, BGK) on a perturbed state."""
     from paper_1708_05944_amd import Batch
     _say(f"case {case}")
-    ora, desc, dt = _pair(**dict(case))
+    ora, desc = _pair(**dict(case))
     b = Batch([desc])
     F = _perturbed(ora, 3)
     b.set_state(F.ravel())
@@ -71,8 +72,9 @@ def test_operator_matches_oracle(case):
 def test_rk3_steps_match_oracle():
     """1000 RK3 steps of the single-instance workload from rest."""
     from paper_1708_05944_amd import Batch
-    ora, desc, dt = _pair(N_R=64, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.1, u_in=0.1)
+    ora, desc = _pair(N_R=64, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.1, u_in=0.1)
     b = Batch([desc])
+    dt = b.info[0]["dt"]
     F0 = b.instance_view(b.get_state(), 0).copy()
     assert _relerr(F0, ora.equilibrium(1, 0, 0, 1)) <= 1e-14
     b.step(1000)
@@ -86,8 +88,10 @@ def test_rk3_steps_match_oracle():
     m = b.moments(0)
     mw = ora.moments(want)
     for key in ("n", "u1", "u2", "T", "T12", "q1", "q2"):
-        scale = max(np.abs(mw[key]).max(), 1e-300)
-        assert np.abs(m[key] - mw[key]).max() <= 1e-11 * max(scale, 1e-6), key
+        # u^R, q and T^{R phi} are small differences of O(0.1-1) quadrature sums, so the
+        # bar is relative to max(|value|, 1e-3)
+        scale = max(np.abs(mw[key]).max(), 1e-3)
+        assert np.abs(m[key] - mw[key]).max() <= 1e-11 * scale, key
     b.close()
 
 
@@ -100,23 +104,23 @@ def test_uneven_batch_matches_oracle():
     b = Batch([p[1] for p in pairs])
     st = b.get_state()
     inits = []
-    for i, (ora, _, _) in enumerate(pairs):
+    for i, (ora, _) in enumerate(pairs):
         F = _perturbed(ora, 10 + i)
         b.instance_view(st, i)[...] = F
         inits.append(F)
     b.set_state(st)
     b.step(30)
     got = b.get_state()
-    for i, (ora, _, dt) in enumerate(pairs):
+    for i, (ora, _) in enumerate(pairs):
         _say(f"instance {i}: {cases[i]}")
-        want = ora.step(inits[i], dt, 30)
+        want = ora.step(inits[i], b.info[i]["dt"], 30)
         assert _relerr(b.instance_view(got, i), want) <= TOL, i
     b.close()
 
 
 def test_particle_number_conserved_on_gpu():
     from paper_1708_05944_amd import Batch
-    ora, desc, dt = _pair(N_R=64, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.1, u_in=0.1)
+    ora, desc = _pair(N_R=64, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.1, u_in=0.1)
     b = Batch([desc])
     m0 = b.total_mass()[0]
     assert abs(m0 / ora.mass(ora.equilibrium(1, 0, 0, 1)) - 1) <= 1e-14
@@ -129,7 +133,9 @@ def test_steady_state_matches_oracle():
     """Single-instance workload to r < 1e-10: the GPU takes exactly the oracle's step
     count and lands on the same state; its own residual is below 1e-10 there."""
     from paper_1708_05944_amd import Batch
-    ora, desc, dt = _pair(N_R=64, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.1, u_in=0.1)
+    ora, desc = _pair(N_R=64, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.1, u_in=0.1)
+    b = Batch([desc])
+    dt = b.info[0]["dt"]
     F = ora.equilibrium(1, 0, 0, 1)
     steps = 0
     while True:
@@ -141,7 +147,6 @@ def test_steady_state_matches_oracle():
         if r < 1e-10 or steps > 60000:
             break
     assert r < 1e-10
-    b = Batch([desc])
     b.step(steps)
     assert b.residual()[0] < 1e-10
     assert _relerr(b.instance_view(b.get_state(), 0), F) <= TOL
@@ -150,7 +155,7 @@ def test_steady_state_matches_oracle():
 
 def test_run_to_steady_and_errors():
     from paper_1708_05944_amd import Batch, VlbError
-    ora, desc, dt = _pair(N_R=32, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.1, u_in=0.1)
+    ora, desc = _pair(N_R=32, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.1, u_in=0.1)
     b = Batch([desc])
     with pytest.raises(VlbError) as e:
         b.residual()
@@ -163,3 +168,12 @@ def test_run_to_steady_and_errors():
     steps, r, ok = b.run_to_steady(1e-10, 40000, 500)
     assert ok and r[0] < 1e-10 and steps[0] > 0
     b.close()
+
+
+def test_unstable_dt_is_rejected():
+    """An explicit dt beyond the force-operator limit of the RK3 stability region is
+    refused with VLB_EUNSTABLE (HH(4;16) x H(4;20): rho(force) ~ 1.8e3)."""
+    from paper_1708_05944_amd import Batch, CouetteDesc, VlbError
+    with pytest.raises(VlbError) as e:
+        Batch([CouetteDesc(N_R=50, ax1=(1, 16, 4), ax2=(0, 20, 4), Kn=10.0, u_in=0.5, R_out=3.0, dt=2e-3)])
+    assert e.value.status == -7
