@@ -3,8 +3,9 @@
 Workload (seeded, synthetic): the batched circular-Couette sweep -- 256 instances with
 Kn = 10^U(-2,1), wall speed U(0.05, 0.5), radius ratio U(0.3, 0.8), 64..512 cells, and
 HH(N;Q_R) x H(N;Q_phi) velocity sets whose orders grow with Kn (32..640 velocities),
-all advanced together by the library's FP64 RK3 stage kernels.  One "step" is one full
-third-order Runge-Kutta step of every instance.
+all advanced together by the library's RK3 stage kernels, in mixed precision (FP32
+stage kernels on weight-scaled populations; the headline) and in FP64.  One "step" is
+one full third-order Runge-Kutta step of every instance.
 
 Prints one JSON line: site-velocity updates per second (sum over instances of
 cells x velocities x steps / wall time), the roofline of the dominant stage-kernel
@@ -73,6 +74,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-instances", type=int, default=64)
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="after the run, one plain device copy of this many MiB (reference kernel for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -80,60 +84,83 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1708_05944_amd import Batch, workloads
+    from paper_1708_05944_amd import VLB_MIXED, Batch, workloads
 
     descs = workloads.couette_sweep()
     updates_per_step = workloads.site_velocities(descs)
-    batch = Batch(descs)
-    batch.step(args.warmup)
-    torch.cuda.synchronize()
-    batch.timing_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    batch.step(args.steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    groups = batch.timing_query()
-    batch.timing_enable(False)
-    r = batch.residual()
-    # untimed pass without events to check the event brackets do not distort the rate
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    batch.step(args.steps)
-    torch.cuda.synchronize()
-    el_plain = time.perf_counter() - t1
-    value = updates_per_step * args.steps / el
-    dom = max(groups, key=lambda g: g["total_ms"])
+
+    def measure(precision):
+        batch = Batch(descs, precision=precision)
+        batch.step(args.warmup)
+        torch.cuda.synchronize()
+        batch.timing_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.step(args.steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        groups = batch.timing_query()
+        batch.timing_enable(False)
+        r = batch.residual()
+        batch.close()
+        dom = max(groups, key=lambda g: g["total_ms"])
+        return dict(value=updates_per_step * args.steps / el, ms_per_step=el / args.steps * 1e3, dom=dom,
+                    max_residual=float(r.max()))
+
+    fp64 = measure(0)
+    mixed = measure(VLB_MIXED)
+    dom = mixed["dom"]
     achieved = dom["alg_bytes"] / (dom["total_ms"] * 1e-3) / 1e9
-    kern_ms = sum(g["total_ms"] for g in groups)
+    dom64 = fp64["dom"]
+    achieved64 = dom64["alg_bytes"] / (dom64["total_ms"] * 1e-3) / 1e9
+
+    # time to steady state (r < 1e-10) of the single-instance workload, FP64 vs mixed
+    tts = {}
+    for name, prec in (("fp64", 0), ("mixed", VLB_MIXED)):
+        b = Batch([workloads.single_couette()], precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps, r, ok = b.run_to_steady(1e-10, 100000, 500)
+        torch.cuda.synchronize()
+        tts[name] = dict(seconds=time.perf_counter() - t0, steps=int(steps[0]), converged=bool(ok),
+                         fp32_steps=b.fp32_steps() if prec else 0)
+        b.close()
+
     out = {
-        "metric": "site-velocity updates/s (batched Couette sweep, FP64)",
-        "value": value,
+        "metric": "site-velocity updates/s (batched Couette sweep, mixed precision: FP32 streaming)",
+        "value": mixed["value"],
         "unit": "site-velocity updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": el / args.steps * 1e3,
+        "ms_per_step": mixed["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "batched circular-Couette sweep: 256 seeded instances (PCG64 seed 20261203), "
                                "64-512 cells, HH(N;4..16) x H(N;4..20) velocity sets (32-640 velocities), "
-                               "Kn 0.01-10, FP64",
+                               "Kn 0.01-10; FP32 stage kernels with FP64 moment/wall/residual sums",
                    "instances": len(descs), "site_velocities_per_step": updates_per_step},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"couette_stage_f64<{dom['vpt']}>", "launches": dom["launches"],
+                     "kernel": "couette_stage<float>", "launches": dom["launches"],
                      "avg_launch_ms": dom["total_ms"] / dom["launches"],
                      "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"]},
-        "all_stage_kernels": {"achieved_GBps": sum(g["alg_bytes"] for g in groups) / (kern_ms * 1e-3) / 1e9,
-                              "kernel_ms_per_step": kern_ms / args.steps},
-        "ms_per_step_no_events": el_plain / args.steps * 1e3,
-        "max_residual": float(r.max()),
+        "fp64": {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"], "kernel": "couette_stage<double>",
+                 "achieved_GBps": achieved64, "frac": achieved64 / HBM_PEAK_GBS,
+                 "avg_launch_ms": dom64["total_ms"] / dom64["launches"]},
+        "time_to_steady_state_single": tts,
     }
-    batch.close()
+    if args.copy_ref_mib:
+        n = args.copy_ref_mib << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_ref_bytes"] = n
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_instances, args.cpu_steps)
     print(json.dumps(out), flush=True)

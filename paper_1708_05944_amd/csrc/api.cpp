@@ -18,14 +18,16 @@
 #include "vlb_internal.h"
 
 namespace vlb {
-hipError_t launch_stage(int fp32, int vpt, int nblocks, hipStream_t st, const StageArgs& A);
-size_t stage_lds(int kmax, int nvmax, int elem);
+hipError_t launch_stage(int fp32, int nblocks, hipStream_t st, const StageArgs& A);
+size_t stage_lds(int kmax, int elem);
 hipError_t launch_moments(int fp32, int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
                           const double* tab, const void* F, double* msum);
 hipError_t launch_convert(int to32, int nblocks, hipStream_t st, const InstDesc* insts32, const WorkItem* work,
                           const double* tab, double* F64, float* F32);
 hipError_t launch_reduce(int ninst, hipStream_t st, const InstDesc* insts, const double* tab, const double* rpart,
                          const double* msum, double* resid, double* mass, int want_resid);
+hipError_t launch_rescale(int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
+                          const double* target, const double* current, double* F);
 hipError_t launch_diag(int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
                        const double* tab, const double* F, double* diag);
 }  // namespace vlb
@@ -53,9 +55,9 @@ vlb_status fail(vlb_status s, const char* fmt, ...) {
     } while (0)
 
 struct LaunchGroup {
-    int vpt, first_block, nblocks;
-    int kmax, nvmax;
-    double pops;   // populations (2 N_R NV summed over the group's instances)
+    int nblocks;
+    int kmax;
+    double pops;   // populations (2 N_R NV summed over all instances)
 };
 
 struct TimedLaunch {
@@ -81,13 +83,14 @@ struct vlb_batch {
     hipStream_t stream = nullptr;
     std::vector<InstHost> inst;
     std::vector<InstDesc> desc;
-    std::vector<WorkItem> work;
+    std::vector<WorkItem> work;        // per-wavefront list of the auxiliary kernels
+    std::vector<BlockWork> blocks;     // stage-kernel blocks
     std::vector<LaunchGroup> groups;
     std::vector<double> tab;
     size_t state_n = 0, ncells = 0;
     // workspace layout (byte offsets)
     size_t off_F[3], off_F32[3], off_M[3], off_rpart, off_resid, off_mass, off_tab, off_desc, off_desc32, off_work,
-        off_diag, total_bytes;
+        off_diag, off_mass0, off_blocks, total_bytes;
     int precision = VLB_FP64;
     bool cur32 = false;                 // the current state lives in the FP32 buffers
     long fp32_steps = 0;                // steps of the FP32 phase of the last run_to_steady
@@ -106,9 +109,11 @@ struct vlb_batch {
     double* rpart() { return (double*)(ws + off_rpart); }
     double* resid() { return (double*)(ws + off_resid); }
     double* massv() { return (double*)(ws + off_mass); }
+    double* mass0() { return (double*)(ws + off_mass0); }
     double* dtab() { return (double*)(ws + off_tab); }
     InstDesc* ddesc() { return (InstDesc*)(ws + off_desc); }
     WorkItem* dwork() { return (WorkItem*)(ws + off_work); }
+    BlockWork* dblocks() { return (BlockWork*)(ws + off_blocks); }
     double* diag() { return (double*)(ws + off_diag); }
 };
 
@@ -134,6 +139,47 @@ std::vector<double> faces(const vlb_couette_desc& d) {
         R[d.N_R] = d.R_out;
     }
     return R;
+}
+
+// Largest singular value of the force operator A = K1 (x) diag(p2^2) - diag(p1) (x) Kt2
+// (Sec. V.A, Eq. boltz_couette_kom, with 1/R = 1) in the inner product weighted by the
+// quadrature weights, where A is close to normal and this norm equals its spectral
+// radius; power iteration on S^T S, S = W^{-1/2} A W^{1/2}.
+double force_norm(const AxisTables& a1, const AxisTables& a2) {
+    const int n1 = a1.nodes, n2 = a2.nodes, NV = n1 * n2;
+    std::vector<double> s1(n1), s2(n2);
+    for (int i = 0; i < n1; ++i) s1[i] = std::sqrt(a1.w[i]);
+    for (int j = 0; j < n2; ++j) s2[j] = std::sqrt(a2.w[j]);
+    auto K1 = [&](int i, int ip) { return a1.K[(size_t)i * n1 + ip] * s1[ip] / s1[i]; };
+    auto K2 = [&](int j, int jp) { return a2.Kt[(size_t)j * n2 + jp] * s2[jp] / s2[j]; };
+    std::vector<double> x(NV), y(NV), z(NV);
+    for (int k = 0; k < NV; ++k) x[k] = 1.0 + 0.37 * std::sin(1.3 * k + 0.2);
+    double sig = 0;
+    for (int it = 0; it < 200; ++it) {
+        double nx = 0;
+        for (double v : x) nx += v * v;
+        nx = std::sqrt(nx);
+        for (double& v : x) v /= nx;
+        for (int i = 0; i < n1; ++i)          // y = S x
+            for (int j = 0; j < n2; ++j) {
+                double a = 0, b = 0;
+                for (int ip = 0; ip < n1; ++ip) a += K1(i, ip) * x[ip * n2 + j];
+                for (int jp = 0; jp < n2; ++jp) b += K2(j, jp) * x[i * n2 + jp];
+                y[i * n2 + j] = a2.p[j] * a2.p[j] * a - a1.p[i] * b;
+            }
+        for (int i = 0; i < n1; ++i)          // z = S^T y
+            for (int j = 0; j < n2; ++j) {
+                double a = 0, b = 0;
+                for (int ip = 0; ip < n1; ++ip) a += K1(ip, i) * y[ip * n2 + j] * a2.p[j] * a2.p[j];
+                for (int jp = 0; jp < n2; ++jp) b += K2(jp, j) * y[i * n2 + jp] * a1.p[i];
+                z[i * n2 + j] = a - b;
+            }
+        double nz = 0;
+        for (double v : z) nz += v * v;
+        sig = std::sqrt(std::sqrt(nz));
+        x.swap(z);
+    }
+    return sig;
 }
 
 double tau_rest(const vlb_couette_desc& d) {
@@ -226,10 +272,12 @@ vlb_status layout_and_alloc(vlb_batch* b, bool alloc) {
     b->off_diag = off; off = align256(off + b->ncells * 7 * sizeof(double));
     b->off_resid = off; off = align256(off + b->B * sizeof(double));
     b->off_mass = off; off = align256(off + b->B * sizeof(double));
+    b->off_mass0 = off; off = align256(off + b->B * sizeof(double));
     b->off_tab = off; off = align256(off + b->tab.size() * sizeof(double));
     b->off_desc = off; off = align256(off + b->desc.size() * sizeof(InstDesc));
     b->off_desc32 = off; off = align256(off + b->desc32.size() * sizeof(InstDesc));
     b->off_work = off; off = align256(off + b->work.size() * sizeof(WorkItem));
+    b->off_blocks = off; off = align256(off + b->blocks.size() * sizeof(BlockWork));
     b->total_bytes = off;
     if (!alloc) return VLB_OK;
     void* p = nullptr;
@@ -245,6 +293,8 @@ vlb_status finish_setup(vlb_batch* b) {
     if (st != VLB_OK) return st;
     HIP_TRY(hipMemcpyAsync(b->dwork(), b->work.data(), b->work.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
                            b->stream));
+    HIP_TRY(hipMemcpyAsync(b->dblocks(), b->blocks.data(), b->blocks.size() * sizeof(BlockWork),
+                           hipMemcpyHostToDevice, b->stream));
     // rest state n = 1, u = 0, T = T_in
     std::vector<double> host(b->state_n);
     for (int i = 0; i < b->B; ++i) {
@@ -291,9 +341,8 @@ vlb_status run_stage(vlb_batch* b, int stage, bool last, bool l_only) {
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
         const LaunchGroup& g = b->groups[gi];
         StageArgs G = A;
-        G.work = b->dwork() + (size_t)g.first_block * kWavesPerBlock;
+        G.blocks = b->dblocks();
         G.kmax = g.kmax;
-        G.nvmax = g.nvmax;
         TimedLaunch t{};
         if (b->timing) {
             for (hipEvent_t* e : {&t.start, &t.stop}) {
@@ -306,7 +355,7 @@ vlb_status run_stage(vlb_batch* b, int stage, bool last, bool l_only) {
             }
             HIP_TRY(hipEventRecord(t.start, b->stream));
         }
-        HIP_TRY(launch_stage(f32 ? 1 : 0, g.vpt, g.nblocks, b->stream, G));
+        HIP_TRY(launch_stage(f32 ? 1 : 0, g.nblocks, b->stream, G));
         if (b->timing) {
             HIP_TRY(hipEventRecord(t.stop, b->stream));
             t.group = (int)gi;
@@ -410,7 +459,7 @@ vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_de
             (ax == 0 ? h.a1 : h.a2) = it->second;
         }
         h.NV = h.a1.nodes * h.a2.nodes;
-        if (h.NV > kWave * kMaxVPT || h.a1.nodes + h.a2.nodes > kWave) {
+        if (h.NV > kMaxNV || h.a1.nodes + h.a2.nodes > kWave) {
             delete b;
             return fail(VLB_EINVAL, "instance %d: %d velocities / %d+%d nodes exceed the kernel limits", i, h.NV,
                         h.a1.nodes, h.a2.nodes);
@@ -422,17 +471,24 @@ vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_de
             h.dchi[s] = 0.5 * (h.Rf[s + 1] * h.Rf[s + 1] - h.Rf[s] * h.Rf[s]);   // chi = R^2/2
             h.Gam[s] = 2.0 / (h.Rf[s + 1] + h.Rf[s]);                              // 1/R of the force, cell value
         }
+        // time-step limits: advection CFL (number 1), the force operator on the imaginary
+        // axis of the RK3 stability region (|lambda dt| <= sqrt(3)), and the BGK relaxation
         double pmax = 0;
         for (double v : h.a1.p) pmax = std::max(pmax, std::fabs(v));
-        double dt_cfl1 = 1e300;
-        for (int s = 0; s < d.N_R; ++s) dt_cfl1 = std::min(dt_cfl1, h.dchi[s] / (h.Rf[s + 1] * pmax));
+        double dt_adv = 1e300, gmax = 0;
+        for (int s = 0; s < d.N_R; ++s) {
+            dt_adv = std::min(dt_adv, h.dchi[s] / (h.Rf[s + 1] * pmax));
+            gmax = std::max(gmax, h.Gam[s]);
+        }
+        const double rho_force = gmax * force_norm(h.a1, h.a2);
+        const double dt1 = 1.0 / (1.0 / dt_adv + rho_force / std::sqrt(3.0));
         double dt = d.dt;
         if (dt == 0.0) {
-            dt = std::min(d.cfl * dt_cfl1, 2.0 * tau_rest(d));
-        } else if (dt > dt_cfl1 || dt > 2.5 * tau_rest(d)) {
+            dt = std::min(d.cfl * dt1, 2.0 * tau_rest(d));
+        } else if (dt > dt1 || dt > 2.5 * tau_rest(d)) {
             delete b;
-            return fail(VLB_EUNSTABLE, "instance %d: dt=%g exceeds the CFL limit %g or 2.5 tau=%g", i, dt, dt_cfl1,
-                        2.5 * tau_rest(d));
+            return fail(VLB_EUNSTABLE, "instance %d: dt=%g exceeds the stability limit %g (advection %g, force %g) "
+                        "or 2.5 tau=%g", i, dt, dt1, dt_adv, std::sqrt(3.0) / rho_force, 2.5 * tau_rest(d));
         }
 
         InstDesc& D = b->desc[i];
@@ -511,47 +567,43 @@ vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_de
     b->state_n = offF;
     b->ncells = offC;
 
-    // work list: per instance and distribution, runs of <= kTileCells cells, grouped in
-    // blocks of 4 wavefronts of the same (instance, distribution); blocks sorted by VPT.
-    std::map<int, std::vector<WorkItem>> byvpt;
-    std::map<int, std::pair<int, int>> limits;   // vpt -> (kmax, nvmax)
-    std::map<int, double> pops;
+    // auxiliary-kernel work list: per instance and distribution, runs of <= kTileCells
+    // cells, one per wavefront, padded to blocks of kWavesPerBlock wavefronts
+    LaunchGroup g{0, 0, 0.0};
     for (int i = 0; i < B; ++i) {
         const InstDesc& D = b->desc[i];
-        const int ntiles = (D.NR + kTileCells - 1) / kTileCells;
-        const int per = (D.NR + ntiles - 1) / ntiles;
-        std::vector<WorkItem>& L = byvpt[D.vpt];
+        const int nruns = (D.NR + kTileCells - 1) / kTileCells;
+        const int per = (D.NR + nruns - 1) / nruns;
         for (int dist = 0; dist < 2; ++dist) {
             int made = 0;
             for (int s = 0; s < D.NR; s += per) {
-                L.push_back({i, dist, s, std::min(per, D.NR - s)});
+                b->work.push_back({i, dist, s, std::min(per, D.NR - s)});
                 ++made;
             }
-            while (made % kWavesPerBlock) { L.push_back({i, dist, 0, 0}); ++made; }
+            while (made % kWavesPerBlock) { b->work.push_back({i, dist, 0, 0}); ++made; }
+            // stage-kernel blocks: R runs of `per` cells, one thread per velocity
+            const int nvpad = (D.NV + kWave - 1) / kWave * kWave;
+            const int rmax = std::min(kMaxRuns, kStageThreads / nvpad);
+            for (int r0 = 0; r0 < nruns; r0 += rmax) {
+                const int R = std::min(rmax, nruns - r0);
+                b->blocks.push_back({i, dist, r0 * per, R, per, nvpad, 0, 0});
+            }
         }
-        auto& lim = limits[D.vpt];
-        lim.first = std::max(lim.first, D.Q1 * D.Q1 + D.Q2 * D.Q2);
-        lim.second = std::max(lim.second, D.NV);
-        pops[D.vpt] += 2.0 * D.NR * D.NV;
+        g.kmax = std::max(g.kmax, D.Q1 * D.Q1 + D.Q2 * D.Q2);
+        g.pops += 2.0 * D.NR * D.NV;
     }
-    int block = 0;
-    for (auto& kv : byvpt) {
-        LaunchGroup g;
-        g.vpt = kv.first;
-        g.first_block = block;
-        g.nblocks = (int)(kv.second.size() / kWavesPerBlock);
-        g.kmax = (limits[kv.first].first + 1) & ~1;
-        g.nvmax = (limits[kv.first].second + 1) & ~1;
-        g.pops = pops[kv.first];
-        const size_t lds = stage_lds(g.kmax, g.nvmax, sizeof(double));
-        if (lds > 160 * 1024) {
-            delete b;
-            return fail(VLB_EINVAL, "velocity sets too large for LDS (%zu bytes)", lds);
-        }
-        b->groups.push_back(g);
-        b->work.insert(b->work.end(), kv.second.begin(), kv.second.end());
-        block += g.nblocks;
+    // heaviest blocks first, so the tail of a launch is made of small blocks
+    std::stable_sort(b->blocks.begin(), b->blocks.end(), [&](const BlockWork& x, const BlockWork& y) {
+        const double wx = (double)x.R * x.TC * b->desc[x.inst].NV, wy = (double)y.R * y.TC * b->desc[y.inst].NV;
+        return wx > wy;
+    });
+    g.kmax = (g.kmax + 1) & ~1;
+    g.nblocks = (int)b->blocks.size();
+    if (stage_lds(g.kmax, sizeof(double)) > 160 * 1024) {
+        delete b;
+        return fail(VLB_EINVAL, "velocity sets too large for LDS (%zu bytes)", stage_lds(g.kmax, sizeof(double)));
     }
+    b->groups.push_back(g);
 
     vlb_status st = layout_and_alloc(b, defer_alloc == 0);
     if (st != VLB_OK) { delete b; return st; }
@@ -768,6 +820,11 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
         // FP32 phase: stream the scaled FP32 state while every instance's residual still
         // falls; stop at 1e-5 (the FP32 rounding floor is eps32/dt) or when the largest
         // residual stops improving by 5% over three checks.
+        // the steady state of a closed Couette cell depends on its particle number, which
+        // FP32 rounding lets drift: record it in FP64 first
+        s = ensure_precision(b, false);
+        if (s != VLB_OK) return s;
+        HIP_TRY(launch_reduce(b->B, b->stream, b->ddesc(), b->dtab(), b->rpart(), b->M(0), b->resid(), b->mass0(), 0));
         s = ensure_precision(b, true);
         if (s != VLB_OK) return s;
         double best = INFINITY;
@@ -784,6 +841,14 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
             if (worst < 0.95 * best) { best = worst; stall = 0; } else if (++stall >= 3) break;
         }
         b->fp32_steps = done;
+        s = ensure_precision(b, false);
+        if (s != VLB_OK) return s;
+        // restore the particle number of every instance (scale both distributions)
+        const int nblocks = (int)(b->work.size() / kWavesPerBlock);
+        HIP_TRY(launch_reduce(b->B, b->stream, b->ddesc(), b->dtab(), b->rpart(), b->M(0), b->resid(), b->massv(), 0));
+        HIP_TRY(launch_rescale(nblocks, b->stream, b->ddesc(), b->dwork(), b->mass0(), b->massv(), b->F(0)));
+        s = refresh_moments(b);
+        if (s != VLB_OK) return s;
     }
     s = ensure_precision(b, false);
     if (s != VLB_OK) return s;
@@ -837,7 +902,7 @@ vlb_status vlb_timing_query(vlb_batch* b, int max_groups, int* ngroups, int* vpt
     for (int g = 0; g < G; ++g) {
         if (n[g] == 0) continue;
         if (out < max_groups) {
-            if (vpt) vpt[out] = b->groups[g / 2].vpt * ((g & 1) ? -1 : 1);
+            if (vpt) vpt[out] = (g & 1) ? 32 : 64;
             if (launches) launches[out] = n[g];
             if (total_ms) total_ms[out] = ms[g];
             if (alg_bytes) alg_bytes[out] = by[g];

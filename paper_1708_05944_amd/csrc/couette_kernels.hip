@@ -27,13 +27,46 @@
 
 namespace vlb {
 
+// Lane permutation of a double by a DPP control (applied to both 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)x, l);
+    const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wavefront, returned in every lane, in a fixed order:
+// quad butterflies (xor 1, xor 2) and the half-row and row mirrors by DPP give every
+// lane its 16-lane row total; the four row totals are then added in lane order.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
-    return v;
+    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);   // row_half_mirror
+    v += dpp_mov<0x140>(v);   // row_mirror
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 // Flux at the face between c and d, upwinded from c (a, b, c, d, e in upwind order).
+template <typename T>
+__device__ __forceinline__ T weno5(T a, T b, T c, T d, T e);
+
+// Face flux between window cells 2 and 3 of a six-cell window (cells s-2 .. s+3):
+// upwinded from cell 2 when the advection velocity is positive, from cell 3 otherwise
+// (the mirror image of the printed stencil).  The five stencil values are selected
+// first, so a wavefront holding both signs evaluates WENO once.
+template <typename T>
+__device__ __forceinline__ T weno_face(bool pos, T w0, T w1, T w2, T w3, T w4, T w5) {
+    return weno5<T>(pos ? w0 : w5, pos ? w1 : w4, pos ? w2 : w3, pos ? w3 : w2, pos ? w4 : w1);
+}
+
 template <typename T>
 __device__ __forceinline__ T weno5(T a, T b, T c, T d, T e) {
     const T f1 = a * T(1.0 / 3.0) - b * T(7.0 / 6.0) + c * T(11.0 / 6.0);
@@ -47,26 +80,22 @@ __device__ __forceinline__ T weno5(T a, T b, T c, T d, T e) {
     t1 = c - T(2) * d + e;
     t2 = T(3) * c - T(4) * d + e;
     const T s3 = T(13.0 / 12.0) * (t1 * t1) + T(0.25) * (t2 * t2);
-    T w1, w2, w3;
-    if (s1 == T(0) || s2 == T(0) || s3 == T(0)) {   // limits of Table weno
-        w1 = s1 == T(0) ? T(0.1) : T(0);
-        w2 = s2 == T(0) ? T(0.6) : T(0);
-        w3 = s3 == T(0) ? T(0.3) : T(0);
-    } else {
-        // w_q proportional to d_q / s_q^2, rewritten as d_q (r_a r_b)^2 with r = s / max(s):
-        // one division instead of three and no overflow.  In FP64 an underflow would need
-        // two indicators below 1e-155 of the largest, which only exact zeros reach; the
-        // FP32 path runs on populations scaled by 1/(w_i w_j), which are O(1), so its
-        // indicators stay far from the FP32 range limits.
-        T m = s1 > s2 ? s1 : s2;
-        m = m > s3 ? m : s3;
-        const T inv = T(1) / m;
-        const T r1 = s1 * inv, r2 = s2 * inv, r3 = s3 * inv;
-        const T q23 = r2 * r3, q13 = r1 * r3, q12 = r1 * r2;
-        w1 = T(0.1) * (q23 * q23);
-        w2 = T(0.6) * (q13 * q13);
-        w3 = T(0.3) * (q12 * q12);
-    }
+    // w_q proportional to d_q / s_q^2, rewritten as d_q (r_a r_b)^2 with r = s / max(s):
+    // one division instead of three and no overflow.  In FP64 an underflow would need two
+    // indicators below 1e-155 of the largest, which only exact zeros reach; the FP32 path
+    // runs on populations scaled by 1/(w_i w_j), which are O(1), so its indicators stay
+    // far from the FP32 range limits.  Exactly vanishing indicators take the limits of
+    // Table weno instead (selected without branching; the unused product form may be NaN
+    // when every indicator vanishes and is discarded by the select).
+    T m = s1 > s2 ? s1 : s2;
+    m = m > s3 ? m : s3;
+    const T inv = T(1) / m;
+    const T r1 = s1 * inv, r2 = s2 * inv, r3 = s3 * inv;
+    const T q23 = r2 * r3, q13 = r1 * r3, q12 = r1 * r2;
+    const bool z1 = s1 == T(0), z2 = s2 == T(0), z3 = s3 == T(0), zany = z1 || z2 || z3;
+    const T w1 = zany ? (z1 ? T(0.1) : T(0)) : T(0.1) * (q23 * q23);
+    const T w2 = zany ? (z2 ? T(0.6) : T(0)) : T(0.6) * (q13 * q13);
+    const T w3 = zany ? (z3 ? T(0.3) : T(0)) : T(0.3) * (q12 * q12);
     return (w1 * f1 + w2 * f2 + w3 * f3) / (w1 + w2 + w3);
 }
 
@@ -76,7 +105,7 @@ __device__ __forceinline__ T weno5(T a, T b, T c, T d, T e) {
 // half range: coefficient of phi_l is sum_s C[l][s] M_s with the half-line moments
 //   M_s = int_0^inf x^s N(x; +-u, T) dx:  M_0 = (1+erf(zeta))/2, M_1 = u M_0 + T g(0),
 //   M_s = u M_{s-1} + (s-1) T M_{s-2}.  Writes plus- and minus-side coefficients.
-__device__ void axis_coef(int kind, int N, double u, double T, const double* C, const double* isf,
+__device__ __noinline__ void axis_coef(int kind, int N, double u, double T, const double* C, const double* isf,
                           double* cp, double* cm) {
     if (kind == 0) {
         double a0 = 1.0, a1 = u;
@@ -112,140 +141,138 @@ __device__ __forceinline__ double tau_of(int model, double Kn, double n, double 
     return Kn / n;
 }
 
-// Bytes of LDS a stage launch needs: kernel tables, then per wavefront the cell row, the
-// per-cell equilibrium factors and the equilibrium coefficients of its cell run.
-__host__ __device__ inline size_t stage_lds_bytes(int kmax, int nvmax, int elem) {
-    const size_t kb = ((size_t)kmax * elem + 7) & ~size_t(7);
-    const size_t wb = (((size_t)(nvmax + kWave) * elem + 7) & ~size_t(7)) + (size_t)kTileCells * kEqStride * 8;
-    return kb + kWavesPerBlock * wb;
-}
+// LDS layout of a stage block (bytes): kernel tables | two cell-row buffers | two
+// equilibrium-factor buffers | equilibrium coefficients of every (run, cell) | moment
+// and residual partials per wavefront (two buffers) | wall-flux partials per wavefront.
+template <typename T>
+struct StageLds {
+    size_t ks, rows, gbuf, eqc, mpart, nwpart, total;
+    __host__ __device__ StageLds(int kmax) {
+        auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
+        ks = 0;
+        rows = al(ks + (size_t)kmax * sizeof(T));
+        gbuf = al(rows + 2 * (size_t)kStageThreads * sizeof(T));
+        eqc = al(gbuf + 2 * (size_t)kMaxRuns * kWave * sizeof(T));
+        mpart = al(eqc + (size_t)kMaxRuns * kTileCells * kEqStride * sizeof(double));
+        nwpart = al(mpart + 2 * (size_t)(kStageThreads / kWave) * 8 * sizeof(double));
+        total = al(nwpart + (size_t)(kStageThreads / kWave) * 2 * sizeof(double));
+    }
+};
 
-template <typename T, int VPT>
-__global__ __launch_bounds__(256) void couette_stage(StageArgs A) {
+template <typename T>
+__global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     extern __shared__ double smem_d[];
     char* smem = reinterpret_cast<char*>(smem_d);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const WorkItem* wp = A.work + (size_t)blockIdx.x * kWavesPerBlock + wave;
-    const int inst = __builtin_amdgcn_readfirstlane(wp->inst);
-    const int dist = __builtin_amdgcn_readfirstlane(wp->dist);
-    const int s0 = __builtin_amdgcn_readfirstlane(wp->s0);
-    const int ncell = __builtin_amdgcn_readfirstlane(wp->ncell);
+    const StageLds<T> lay(A.kmax);
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const BlockWork* bw = A.blocks + blockIdx.x;
+    const int inst = __builtin_amdgcn_readfirstlane(bw->inst);
+    const int dist = __builtin_amdgcn_readfirstlane(bw->dist);
+    const int s0 = __builtin_amdgcn_readfirstlane(bw->s0);
+    const int R = __builtin_amdgcn_readfirstlane(bw->R);
+    const int TC = __builtin_amdgcn_readfirstlane(bw->TC);
+    const int nvpad = __builtin_amdgcn_readfirstlane(bw->nvpad);
     const InstDesc& I = A.inst[inst];
     const double* tab = A.tab + I.offT;
     const int NR = I.NR, Q1 = I.Q1, Q2 = I.Q2, NV = I.NV;
 
-    // kernels of the block's instance into LDS (all waves of a block share it)
-    T* Ks = reinterpret_cast<T*>(smem);
+    T* Ks = reinterpret_cast<T*>(smem + lay.ks);
+    T* rows = reinterpret_cast<T*>(smem + lay.rows);
+    T* gbuf = reinterpret_cast<T*>(smem + lay.gbuf);
+    double* eqc = reinterpret_cast<double*>(smem + lay.eqc);
+    double* mpart = reinterpret_cast<double*>(smem + lay.mpart);
+    double* nwpart = reinterpret_cast<double*>(smem + lay.nwpart);
+
+    // thread -> (run r, velocity k); nvpad is a multiple of 64, so r is wavefront-uniform
+    const int r = __builtin_amdgcn_readfirstlane(t / nvpad), k = t - r * nvpad;
+    const int rs0 = s0 + r * TC;
+    const int rlen = r < R ? max(0, min(TC, NR - rs0)) : 0;
+    const bool act = rlen > 0 && k < NV;
+    const int kk = k < NV ? k : 0;
+    const int vi = kk / Q2, vj = kk - vi * Q2;
+    const T p1 = T(tab[I.tp1 + vi]), p2 = T(tab[I.tp2 + vj]);
+
+    // ---- prologue: kernels into LDS; equilibrium coefficients of every (run, cell)
     const int n1 = Q1 * Q1, n2 = Q2 * Q2;
-    for (int x = threadIdx.x; x < n1 + n2; x += blockDim.x) Ks[x] = T(x < n1 ? tab[I.tK1 + x] : tab[I.tKt2 + x - n1]);
-    __syncthreads();
-    if (ncell <= 0) return;
-
-    const size_t kb = ((size_t)A.kmax * sizeof(T) + 7) & ~size_t(7);
-    const size_t wb = (((size_t)(A.nvmax + kWave) * sizeof(T) + 7) & ~size_t(7)) + (size_t)kTileCells * kEqStride * 8;
-    T* row = reinterpret_cast<T*>(smem + kb + wave * wb);
-    T* gbuf = row + A.nvmax;
-    double* eqc = reinterpret_cast<double*>(smem + kb + wave * wb + wb - (size_t)kTileCells * kEqStride * 8);
-
-    const size_t dsz = (size_t)NR * NV;
-    const T* Fd = static_cast<const T*>(A.Fin) + I.offF + (size_t)dist * dsz;   // this distribution
-    const T* Fp = static_cast<const T*>(A.Fin) + I.offF;                        // f' (wall density)
-    const T* Fnd = static_cast<const T*>(A.Fn) + I.offF + (size_t)dist * dsz;
-    T* Fo = static_cast<T*>(A.Fout) + I.offF + (size_t)dist * dsz;
-    const T* Cd = A.C ? static_cast<const T*>(A.C) + I.offF + (size_t)dist * dsz : nullptr;
-
-    // ---- per-lane velocities
-    int vi[VPT], vj[VPT];
-    T p1[VPT], p2[VPT];
-    bool ok[VPT];
-#pragma unroll
-    for (int v = 0; v < VPT; ++v) {
-        const int k = lane + kWave * v;
-        ok[v] = k < NV;
-        const int kk = ok[v] ? k : 0;
-        vi[v] = kk / Q2;
-        vj[v] = kk - vi[v] * Q2;
-        p1[v] = T(tab[I.tp1 + vi[v]]);
-        p2[v] = T(tab[I.tp2 + vj[v]]);
-    }
-
-    // ---- equilibrium coefficients of the run's cells (lane c -> cell s0 + c), FP64
+    for (int x = t; x < n1 + n2; x += kStageThreads) Ks[x] = T(x < n1 ? tab[I.tK1 + x] : tab[I.tKt2 + x - n1]);
     const int N1 = I.N1, N2 = I.N2;
-    if (lane < ncell) {
-        const double* ms = A.msum_in + (size_t)(I.offC + s0 + lane) * 5;
+    for (int x = t; x < R * TC; x += kStageThreads) {
+        const int rr = x / TC, cc = x - rr * TC, s = s0 + rr * TC + cc;
+        if (s >= NR) continue;
+        const double* ms = A.msum_in + (size_t)(I.offC + s) * 5;
         const double n = ms[0], u1 = ms[1] / n, u2 = ms[2] / n;
         const double T_ = (ms[3] + ms[4] - n * (u1 * u1 + u2 * u2)) / (3.0 * n);
-        double* e = eqc + lane * kEqStride;
+        double* e = eqc + (size_t)x * kEqStride;
         e[0] = n;
         e[1] = T_;
         e[2] = 1.0 / tau_of(I.tau_model, I.Kn, n, T_);
         axis_coef(I.kind1, N1, u1, T_, tab + I.tC1, tab + I.tisf1, e + 3, e + 3 + (N1 + 1));
         axis_coef(I.kind2, N2, u2, T_, tab + I.tC2, tab + I.tisf2, e + 3 + 2 * (N1 + 1), e + 3 + 2 * (N1 + 1) + (N2 + 1));
     }
-    // lane role for the per-cell factor table: g1 (lane < Q1) or g2 (Q1 <= lane < Q1+Q2)
-    double brow[kMaxN + 1];
+    // node role for the per-cell factor table: g1 (k < Q1) or g2 (Q1 <= k < Q1+Q2)
+    const double* brow = nullptr;
     int coff = -1, nb = 0;
-    if (lane < Q1) {
+    if (rlen > 0 && k < Q1) {
         nb = N1 + 1;
-        for (int l = 0; l < nb; ++l) brow[l] = tab[I.tB1 + lane * nb + l];
-        coff = 3 + ((I.kind1 == 1 && lane >= I.Qh1) ? nb : 0);
-    } else if (lane < Q1 + Q2) {
-        const int j = lane - Q1;
+        brow = tab + I.tB1 + k * nb;
+        coff = 3 + ((I.kind1 == 1 && k >= I.Qh1) ? nb : 0);
+    } else if (rlen > 0 && k < Q1 + Q2) {
+        const int j = k - Q1;
         nb = N2 + 1;
-        for (int l = 0; l < nb; ++l) brow[l] = tab[I.tB2 + j * nb + l];
+        brow = tab + I.tB2 + j * nb;
         coff = 3 + 2 * (N1 + 1) + ((I.kind2 == 1 && j >= I.Qh2) ? nb : 0);
     }
-    __syncwarp();
 
-    // ---- diffuse walls: n_w from the zero-mass-flux balance (Eq. nw), FP64 sums
-    const double* Wm = tab + I.tWm;   // quadrature weight of a stored population (1 when unscaled)
-    const bool near_in = s0 < 3, near_out = s0 + ncell > NR - 3;
-    double nw_in = 0.0, nw_out = 0.0;
-    if (near_in) {
-        double acc = 0.0;
-#pragma unroll
-        for (int v = 0; v < VPT; ++v) {
-            const int k = lane + kWave * v;
-            if (ok[v] && p1[v] < T(0)) {
-                const T F1 = Fp[k], F2 = Fp[NV + k], F3 = Fp[2 * NV + k];
-                const T g0 = T(3) * F1 - T(3) * F2 + F3, gm1 = T(6) * F1 - T(8) * F2 + T(3) * F3;
-                acc += (double)p1[v] * Wm[k] * (double)weno5<T>(F3, F2, F1, g0, gm1);
-            }
+    // ---- diffuse walls: n_w of Eq. nw, FP64 half-range sums reduced over the run
+    const T* Fd = static_cast<const T*>(A.Fin) + I.offF + (size_t)dist * NR * NV;
+    const T* Fp = static_cast<const T*>(A.Fin) + I.offF;
+    const T* Fnd = static_cast<const T*>(A.Fn) + I.offF + (size_t)dist * NR * NV;
+    T* Fo = static_cast<T*>(A.Fout) + I.offF + (size_t)dist * NR * NV;
+    const T* Cd = A.C ? static_cast<const T*>(A.C) + I.offF + (size_t)dist * NR * NV : nullptr;
+    const double* Wm = tab + I.tWm;
+    const bool near_in = rlen > 0 && rs0 < 3, near_out = rlen > 0 && rs0 + rlen > NR - 3;
+    {
+        double ain = 0.0, aout = 0.0;
+        if (act && near_in && p1 < T(0)) {
+            const T F1 = Fp[k], F2 = Fp[NV + k], F3 = Fp[2 * NV + k];
+            const T g0 = T(3) * F1 - T(3) * F2 + F3, gm1 = T(6) * F1 - T(8) * F2 + T(3) * F3;
+            ain = (double)p1 * Wm[k] * (double)weno5<T>(F3, F2, F1, g0, gm1);
         }
-        nw_in = -wave_sum(acc) / I.den_in;
+        if (act && near_out && p1 > T(0)) {
+            const T G1 = Fp[(size_t)(NR - 1) * NV + k], G2 = Fp[(size_t)(NR - 2) * NV + k],
+                    G3 = Fp[(size_t)(NR - 3) * NV + k];
+            const T g0 = T(3) * G1 - T(3) * G2 + G3, gp1 = T(6) * G1 - T(8) * G2 + T(3) * G3;
+            aout = (double)p1 * Wm[k] * (double)weno5<T>(G3, G2, G1, g0, gp1);
+        }
+        ain = wave_sum(ain);
+        aout = wave_sum(aout);
+        if (lane == 0) { nwpart[wave * 2] = ain; nwpart[wave * 2 + 1] = aout; }
     }
-    if (near_out) {
-        double acc = 0.0;
-#pragma unroll
-        for (int v = 0; v < VPT; ++v) {
-            const int k = lane + kWave * v;
-            if (ok[v] && p1[v] > T(0)) {
-                const T G1 = Fp[(size_t)(NR - 1) * NV + k], G2 = Fp[(size_t)(NR - 2) * NV + k],
-                        G3 = Fp[(size_t)(NR - 3) * NV + k];
-                const T g0 = T(3) * G1 - T(3) * G2 + G3, gp1 = T(6) * G1 - T(8) * G2 + T(3) * G3;
-                acc += (double)p1[v] * Wm[k] * (double)weno5<T>(G3, G2, G1, g0, gp1);
-            }
-        }
-        nw_out = -wave_sum(acc) / I.den_out;
+    __syncthreads();
+    const int w0 = r * (nvpad / kWave), nw_waves = nvpad / kWave;
+    double nw_in = 0.0, nw_out = 0.0;
+    if (rlen > 0) {
+        double sin_ = 0.0, sout = 0.0;
+        for (int w = 0; w < nw_waves; ++w) { sin_ += nwpart[(w0 + w) * 2]; sout += nwpart[(w0 + w) * 2 + 1]; }
+        if (near_in) nw_in = -sin_ / I.den_in;
+        if (near_out) nw_out = -sout / I.den_out;
     }
     const T wi_scale = T(dist ? I.T_in * nw_in : nw_in);
     const T wo_scale = T(dist ? I.T_out * nw_out : nw_out);
     const double* fin = tab + I.tfin;
     const double* fout = tab + I.tfout;
 
-    // value of cell c (0-based; ghosts outside [0, NR)) for lane velocity v
-    auto cell = [&](int c, int v) -> T {
-        const int k = lane + kWave * v;
-        if (!ok[v]) return T(0);
+    // value of cell c (0-based; ghosts outside [0, NR)) for this thread's velocity
+    auto cell = [&](int c) -> T {
         if (c >= 0 && c < NR) return Fd[(size_t)c * NV + k];
         if (c < 0) {
-            if (p1[v] > T(0)) return wi_scale * T(fin[k]);             // Eq. weno_populate
+            if (p1 > T(0)) return wi_scale * T(fin[k]);                 // Eq. weno_populate
             const T F1 = Fd[k], F2 = Fd[NV + k], F3 = Fd[2 * NV + k];
-            if (c == -1) return T(3) * F1 - T(3) * F2 + F3;            // Eq. extrapol
+            if (c == -1) return T(3) * F1 - T(3) * F2 + F3;             // Eq. extrapol
             if (c == -2) return T(6) * F1 - T(8) * F2 + T(3) * F3;
             return T(0);
         }
-        if (p1[v] < T(0)) return wo_scale * T(fout[k]);
+        if (p1 < T(0)) return wo_scale * T(fout[k]);
         const T G1 = Fd[(size_t)(NR - 1) * NV + k], G2 = Fd[(size_t)(NR - 2) * NV + k],
                 G3 = Fd[(size_t)(NR - 3) * NV + k];
         if (c == NR) return T(3) * G1 - T(3) * G2 + G3;
@@ -254,101 +281,122 @@ __global__ __launch_bounds__(256) void couette_stage(StageArgs A) {
     };
 
     // ---- window over cells s-3 .. s+2 and the flux at the first face
-    T win[VPT][6], fl[VPT];
-#pragma unroll
-    for (int v = 0; v < VPT; ++v) {
-#pragma unroll
-        for (int q = 0; q < 6; ++q) win[v][q] = cell(s0 - 3 + q, v);
-        fl[v] = p1[v] > T(0) ? weno5<T>(win[v][0], win[v][1], win[v][2], win[v][3], win[v][4])
-                             : weno5<T>(win[v][5], win[v][4], win[v][3], win[v][2], win[v][1]);
+    T w0v = 0, w1v = 0, w2v = 0, w3v = 0, w4v = 0, w5v = 0, fl = 0;
+    const bool pos = p1 > T(0);
+    if (act) {
+        w0v = cell(rs0 - 3); w1v = cell(rs0 - 2); w2v = cell(rs0 - 1);
+        w3v = cell(rs0);     w4v = cell(rs0 + 1); w5v = cell(rs0 + 2);
+        fl = weno_face<T>(pos, w0v, w1v, w2v, w3v, w4v, w5v);
     }
 
     const double dt = A.l_only ? 1.0 : I.dt;
     const T cdt = T(A.cc * dt), ca = T(A.ca), cb = T(A.cb);
     const double* resW = tab + I.tresW;
     const T* Kt = Ks + n1;
+    const T* K1row = Ks + vi * Q1;
+    const T* Ktrow = Kt + vj * Q2;
+    const double pw1 = (double)p1, pw2 = (double)p2;
+    const double wmk = Wm[kk], rwk = resW[kk];
 
-    for (int c = 0; c < ncell; ++c) {
-        const int s = s0 + c;
-#pragma unroll
-        for (int v = 0; v < VPT; ++v) {
-#pragma unroll
-            for (int q = 0; q < 5; ++q) win[v][q] = win[v][q + 1];
-            win[v][5] = cell(s + 3, v);
-            if (ok[v]) row[lane + kWave * v] = win[v][2];
+    // moments (and residual partials) of cell c of this run: summed over the run's
+    // wavefronts by the run's first thread, one cell behind the sweep
+    // lane q < 6 of the run's first wavefront sums quantity q over the run's wavefronts
+    auto finish = [&](int c, int buf) {
+        if (k >= 6 || c >= rlen) return;
+        const double* mp = mpart + (size_t)buf * (kStageThreads / kWave) * 8 + (size_t)w0 * 8 + k;
+        double m = 0.0;
+        for (int w = 0; w < nw_waves; ++w) m += mp[w * 8];
+        const int s = rs0 + c;
+        if (k < 4) {
+            if (dist == 0) A.msum_out[(size_t)(I.offC + s) * 5 + k] = m;
+            else if (k == 0) A.msum_out[(size_t)(I.offC + s) * 5 + 4] = m;
+        } else if (A.rpart) {
+            A.rpart[((size_t)(I.offC + s) * 2 + dist) * 2 + (k - 4)] = tab[I.tdchi + s] * m;
         }
-        const double* e = eqc + c * kEqStride;
-        if (coff >= 0) {
+    };
+
+    // values of the next cell fetched one iteration ahead (F_n and the cell geometry)
+    const bool need_fn = !A.l_only && ca != T(0);
+    T fn_next = (act && need_fn) ? Fnd[(size_t)rs0 * NV + k] : T(0);
+    double g_next[4] = {0, 0, 0, 0};
+    if (rlen > 0) {
+        g_next[0] = tab[I.tRf + rs0]; g_next[1] = tab[I.tRf + rs0 + 1];
+        g_next[2] = tab[I.tdchi + rs0]; g_next[3] = tab[I.tGam + rs0];
+    }
+    for (int c = 0; c < TC; ++c) {
+        const int buf = c & 1;
+        const bool cv = act && c < rlen;
+        const int s = rs0 + c;
+        const T fn_cur = fn_next;
+        const double g_cur[4] = {g_next[0], g_next[1], g_next[2], g_next[3]};
+        if (c + 1 < rlen) {
+            if (act && need_fn) fn_next = Fnd[(size_t)(s + 1) * NV + k];
+            g_next[0] = g_cur[1]; g_next[1] = tab[I.tRf + s + 2];
+            g_next[2] = tab[I.tdchi + s + 1]; g_next[3] = tab[I.tGam + s + 1];
+        }
+        T* row = rows + (size_t)buf * kStageThreads + (size_t)r * nvpad;
+        T* gb = gbuf + (size_t)buf * kMaxRuns * kWave + (size_t)r * kWave;
+        const double* e = eqc + (size_t)(r * TC + c) * kEqStride;
+        if (cv) {
+            w0v = w1v; w1v = w2v; w2v = w3v; w3v = w4v; w4v = w5v;
+            // s is wavefront-uniform: interior cells take a plain load
+            w5v = s + 3 < NR ? Fd[(size_t)(s + 3) * NV + k] : cell(s + 3);
+            row[k] = w2v;
+        }
+        if (coff >= 0 && c < rlen) {
             double g = 0.0;
             for (int l = 0; l < nb; ++l) g += brow[l] * e[coff + l];
-            gbuf[lane] = T(g);
+            gb[k] = T(g);
         }
-        __syncwarp();
-        const T Rl = T(tab[I.tRf + s]), Rr = T(tab[I.tRf + s + 1]);
-        const T dchi = T(tab[I.tdchi + s]), gam = T(tab[I.tGam + s]);
-        const T n = T(e[0]), Tc = T(e[1]), itau = T(e[2]);
+        __syncthreads();
+        if (c > 0) finish(c - 1, buf ^ 1);
         double m0 = 0, m1 = 0, m2 = 0, m3 = 0, rd = 0, rn = 0;
-#pragma unroll
-        for (int v = 0; v < VPT; ++v) {
-            const int k = lane + kWave * v;
-            const T fr = p1[v] > T(0) ? weno5<T>(win[v][0], win[v][1], win[v][2], win[v][3], win[v][4])
-                                      : weno5<T>(win[v][5], win[v][4], win[v][3], win[v][2], win[v][1]);
-            if (ok[v]) {
-                const int i = vi[v], j = vj[v];
-                const T adv = p1[v] * (Rr * fr - Rl * fl[v]) / dchi;
-                T kf = T(0), ktf = T(0);
-                for (int ip = 0; ip < Q1; ++ip) kf += Ks[i * Q1 + ip] * row[ip * Q2 + j];
-                for (int jp = 0; jp < Q2; ++jp) ktf += Kt[j * Q2 + jp] * row[i * Q2 + jp];
-                const T force = gam * (p2[v] * p2[v] * kf - p1[v] * ktf);
-                T fe = n * gbuf[i] * gbuf[Q1 + j];
-                if (dist) fe = Tc * fe;
-                const T Fc = win[v][2];
-                T L = -adv - force - (Fc - fe) * itau;
-                if (Cd) L += Cd[(size_t)s * NV + k];
-                T out;
-                if (A.l_only) {
-                    out = L;
-                } else {
-                    const T fn = ca != T(0) ? Fnd[(size_t)s * NV + k] : T(0);
-                    out = ca * fn + cb * Fc + cdt * L;
-                    if (A.rpart) {
-                        const double d = (double)out - (double)fn;
-                        rd += d * d * resW[k];
-                        rn += (double)fn * (double)fn * resW[k];
-                    }
-                }
-                Fo[(size_t)s * NV + k] = out;
-                const double wo = Wm[k] * (double)out;
-                m0 += wo;
-                if (dist == 0) {
-                    m1 += (double)p1[v] * wo;
-                    m2 += (double)p2[v] * wo;
-                    m3 += ((double)p1[v] * (double)p1[v] + (double)p2[v] * (double)p2[v]) * wo;
+        if (cv) {
+            const T fr = weno_face<T>(pos, w0v, w1v, w2v, w3v, w4v, w5v);
+            const T Rl = T(g_cur[0]), Rr = T(g_cur[1]);
+            const T dchi = T(g_cur[2]), gam = T(g_cur[3]);
+            const T adv = p1 * (Rr * fr - Rl * fl) / dchi;
+            T kf = T(0), ktf = T(0);
+            for (int ip = 0; ip < Q1; ++ip) kf += K1row[ip] * row[ip * Q2 + vj];
+            for (int jp = 0; jp < Q2; ++jp) ktf += Ktrow[jp] * row[vi * Q2 + jp];
+            const T force = gam * (p2 * p2 * kf - p1 * ktf);
+            T fe = T(e[0]) * gb[vi] * gb[Q1 + vj];
+            if (dist) fe = T(e[1]) * fe;
+            const T Fc = w2v;
+            T L = -adv - force - (Fc - fe) * T(e[2]);
+            if (Cd) L += Cd[(size_t)s * NV + k];
+            T out;
+            if (A.l_only) {
+                out = L;
+            } else {
+                const T fn = fn_cur;
+                out = ca * fn + cb * Fc + cdt * L;
+                if (A.rpart) {
+                    const double d = (double)out - (double)fn;
+                    rd = d * d * rwk;
+                    rn = (double)fn * (double)fn * rwk;
                 }
             }
-            fl[v] = fr;
+            Fo[(size_t)s * NV + k] = out;
+            const double wo = wmk * (double)out;
+            m0 = wo;
+            if (dist == 0) {
+                m1 = pw1 * wo;
+                m2 = pw2 * wo;
+                m3 = (pw1 * pw1 + pw2 * pw2) * wo;
+            }
+            fl = fr;
         }
         m0 = wave_sum(m0);
-        double* mo = A.msum_out + (size_t)(I.offC + s) * 5;
-        if (dist == 0) {
-            m1 = wave_sum(m1);
-            m2 = wave_sum(m2);
-            m3 = wave_sum(m3);
-            if (lane == 0) { mo[0] = m0; mo[1] = m1; mo[2] = m2; mo[3] = m3; }
-        } else if (lane == 0) {
-            mo[4] = m0;
+        if (dist == 0) { m1 = wave_sum(m1); m2 = wave_sum(m2); m3 = wave_sum(m3); }
+        if (A.rpart) { rd = wave_sum(rd); rn = wave_sum(rn); }
+        if (lane == 0) {
+            double* mp = mpart + ((size_t)buf * (kStageThreads / kWave) + wave) * 8;
+            mp[0] = m0; mp[1] = m1; mp[2] = m2; mp[3] = m3; mp[4] = rd; mp[5] = rn;
         }
-        if (A.rpart) {
-            rd = wave_sum(rd);
-            rn = wave_sum(rn);
-            if (lane == 0) {
-                double* rp = A.rpart + ((size_t)(I.offC + s) * 2 + dist) * 2;
-                rp[0] = (double)dchi * rd;
-                rp[1] = (double)dchi * rn;
-            }
-        }
-        __syncwarp();
     }
+    __syncthreads();
+    finish(TC - 1, (TC - 1) & 1);
 }
 
 // Moment sums [n, sum p1 f', sum p2 f', sum |p|^2 f', sum f''] of a state, per cell
@@ -494,26 +542,38 @@ __global__ __launch_bounds__(256) void couette_reduce_f64(const InstDesc* insts,
     }
 }
 
+// Rescale every instance's FP64 state by target[b] / current[b] (particle-number
+// restoration after the FP32 phase; both distributions, so u and T are unchanged).
+__global__ __launch_bounds__(256) void couette_rescale(const InstDesc* insts, const WorkItem* work,
+                                                       const double* target, const double* current, double* F) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const WorkItem* wp = work + (size_t)blockIdx.x * kWavesPerBlock + wave;
+    const int inst = __builtin_amdgcn_readfirstlane(wp->inst);
+    const int dist = __builtin_amdgcn_readfirstlane(wp->dist);
+    const int s0 = __builtin_amdgcn_readfirstlane(wp->s0);
+    const int ncell = __builtin_amdgcn_readfirstlane(wp->ncell);
+    if (ncell <= 0) return;
+    const InstDesc& I = insts[inst];
+    const double f = target[inst] / current[inst];
+    const size_t base = I.offF + (size_t)dist * I.NR * I.NV;
+    for (int c = 0; c < ncell; ++c) {
+        const size_t row = base + (size_t)(s0 + c) * I.NV;
+        for (int k = lane; k < I.NV; k += kWave) F[row + k] *= f;
+    }
+}
+
 // ------------------------------------------------------------------ host launchers
 template <typename T>
-static hipError_t launch_stage_t(int vpt, int nblocks, hipStream_t st, const StageArgs& A) {
-    dim3 grid(nblocks), block(kWave * kWavesPerBlock);
-    const size_t lds = stage_lds_bytes(A.kmax, A.nvmax, sizeof(T));
-    switch (vpt) {
-#define VLB_CASE(V) \
-    case V: hipLaunchKernelGGL((couette_stage<T, V>), grid, block, lds, st, A); break;
-        VLB_CASE(1) VLB_CASE(2) VLB_CASE(3) VLB_CASE(4) VLB_CASE(5)
-        VLB_CASE(6) VLB_CASE(7) VLB_CASE(8) VLB_CASE(9) VLB_CASE(10)
-#undef VLB_CASE
-        default: return hipErrorInvalidValue;
-    }
+static hipError_t launch_stage_t(int nblocks, hipStream_t st, const StageArgs& A) {
+    const StageLds<T> lay(A.kmax);
+    hipLaunchKernelGGL(couette_stage<T>, dim3(nblocks), dim3(kStageThreads), lay.total, st, A);
     return hipGetLastError();
 }
 
-size_t stage_lds(int kmax, int nvmax, int elem) { return stage_lds_bytes(kmax, nvmax, elem); }
+size_t stage_lds(int kmax, int elem) { return elem == 4 ? StageLds<float>(kmax).total : StageLds<double>(kmax).total; }
 
-hipError_t launch_stage(int fp32, int vpt, int nblocks, hipStream_t st, const StageArgs& A) {
-    return fp32 ? launch_stage_t<float>(vpt, nblocks, st, A) : launch_stage_t<double>(vpt, nblocks, st, A);
+hipError_t launch_stage(int fp32, int nblocks, hipStream_t st, const StageArgs& A) {
+    return fp32 ? launch_stage_t<float>(nblocks, st, A) : launch_stage_t<double>(nblocks, st, A);
 }
 
 hipError_t launch_moments(int fp32, int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
@@ -535,6 +595,13 @@ hipError_t launch_convert(int to32, int nblocks, hipStream_t st, const InstDesc*
     else
         hipLaunchKernelGGL(couette_convert<false>, dim3(nblocks), dim3(kWave * kWavesPerBlock), 0, st, insts32, work,
                            tab, F64, F32);
+    return hipGetLastError();
+}
+
+hipError_t launch_rescale(int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
+                          const double* target, const double* current, double* F) {
+    hipLaunchKernelGGL(couette_rescale, dim3(nblocks), dim3(kWave * kWavesPerBlock), 0, st, insts, work, target,
+                       current, F);
     return hipGetLastError();
 }
 

@@ -10,9 +10,11 @@ namespace vlb {
 constexpr int kMaxQ = 64;      // quadrature order per axis (nodes <= 128)
 constexpr int kMaxN = 4;       // equilibrium expansion order (Eq. norder_limit: N < Q)
 constexpr int kWave = 64;      // CDNA wavefront width
-constexpr int kWavesPerBlock = 4;
-constexpr int kMaxVPT = 10;    // velocities per lane -> at most 640 velocities per cell
-constexpr int kTileCells = 16; // cells swept by one wavefront
+constexpr int kWavesPerBlock = 4;   // blocks of the auxiliary (per-wavefront work) kernels
+constexpr int kStageThreads = 1024; // stage kernel block: one thread per velocity
+constexpr int kMaxNV = kStageThreads;
+constexpr int kTileCells = 16; // cells swept by one cell run
+constexpr int kMaxRuns = 16;   // cell runs per stage block
 constexpr int kEqStride = 24;  // doubles of equilibrium coefficients kept per cell
 
 // Host-side tables of one momentum axis (velocity_set.cpp).
@@ -48,6 +50,14 @@ struct WorkItem {
     int inst, dist, s0, ncell;
 };
 
+// One stage-kernel block: R runs of up to TC consecutive cells starting at s0 (run r
+// covers [s0 + r TC, s0 + (r+1) TC) clipped to the grid), one distribution, one
+// instance; run r is held by threads [r nvpad, (r+1) nvpad), nvpad = NV rounded up to
+// whole wavefronts.
+struct BlockWork {
+    int inst, dist, s0, R, TC, nvpad, pad0, pad1;
+};
+
 // Arguments of one RK stage launch: out = ca*Fn + cb*Fin + cc*dt*(L[Fin] + C).
 // F pointers are double* (FP64 path) or float* (FP32 path).
 struct StageArgs {
@@ -64,7 +74,7 @@ struct StageArgs {
     double ca, cb, cc;
     int l_only;              // 1: Fout = L[Fin] (dt taken as 1)
     int kmax;                // kernel-table elements reserved in LDS
-    int nvmax;               // largest NV among the launch's instances
+    const BlockWork* blocks; // stage-kernel block list
 };
 
 }  // namespace vlb
