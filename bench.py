@@ -91,6 +91,8 @@ def main():
 
     def measure(precision):
         batch = Batch(descs, precision=precision)
+        batch.step(1)                          # moves a mixed batch into its FP32 buffers
+        tile, _ = batch.autotune(3)            # cells per run of the stage kernel, by timing
         batch.step(args.warmup)
         torch.cuda.synchronize()
         batch.timing_enable(True)
@@ -105,7 +107,7 @@ def main():
         batch.close()
         dom = max(groups, key=lambda g: g["total_ms"])
         return dict(value=updates_per_step * args.steps / el, ms_per_step=el / args.steps * 1e3, dom=dom,
-                    max_residual=float(r.max()))
+                    max_residual=float(r.max()), tile=tile)
 
     fp64 = measure(0)
     mixed = measure(VLB_MIXED)
@@ -118,12 +120,15 @@ def main():
     tts = {}
     for name, prec in (("fp64", 0), ("mixed", VLB_MIXED)):
         b = Batch([workloads.single_couette()], precision=prec)
+        b.step(0 if prec == 0 else 1)
+        single_tile, _ = b.autotune(20)
+        b.init_equilibrium(0, 1.0, 0.0, 0.0, 1.0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         steps, r, ok = b.run_to_steady(1e-10, 100000, 500)
         torch.cuda.synchronize()
         tts[name] = dict(seconds=time.perf_counter() - t0, steps=int(steps[0]), converged=bool(ok),
-                         fp32_steps=b.fp32_steps() if prec else 0)
+                         fp32_steps=b.fp32_steps() if prec else 0, tile=single_tile)
         b.close()
 
     out = {
@@ -142,13 +147,15 @@ def main():
         "config": {"workload": "batched circular-Couette sweep: 256 seeded instances (PCG64 seed 20261203), "
                                "64-512 cells, HH(N;4..16) x H(N;4..20) velocity sets (32-640 velocities), "
                                "Kn 0.01-10; FP32 stage kernels with FP64 moment/wall/residual sums",
-                   "instances": len(descs), "site_velocities_per_step": updates_per_step},
+                   "instances": len(descs), "site_velocities_per_step": updates_per_step,
+                   "cells_per_run": mixed["tile"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "couette_stage<float>", "launches": dom["launches"],
                      "avg_launch_ms": dom["total_ms"] / dom["launches"],
                      "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"]},
         "fp64": {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"], "kernel": "couette_stage<double>",
+                 "cells_per_run": fp64["tile"],
                  "achieved_GBps": achieved64, "frac": achieved64 / HBM_PEAK_GBS,
                  "avg_launch_ms": dom64["total_ms"] / dom64["launches"]},
         "time_to_steady_state_single": tts,

@@ -184,6 +184,23 @@ vlb_status vlb_mixed_fp32_steps(const vlb_batch* b, long* n);
  * kernel Kt (nodes x nodes, row-major; Sec. IV.C).  nodes = Q (kind 0) or 2Q. */
 vlb_status vlb_axis_tables(vlb_axis ax, double* p, double* w, double* K, double* Kt);
 
+/* Cells per run of the stage kernel (2..32; default 16): each block sweeps runs of this
+ * many consecutive cells, one thread per velocity.  Short runs give small instances more
+ * parallel blocks; long runs amortise the 3-cell halo at each run end.
+ * vlb_batch_autotune times `steps` steps for each of 2, 4, 8, 16, 32 on the batch itself
+ * (on a copy of the state, which is restored), keeps the fastest, and returns it with its
+ * time per step in ms.  Allocates a temporary device copy of the state. */
+vlb_status vlb_batch_set_tile(vlb_batch* b, int cells_per_run);
+vlb_status vlb_batch_get_tile(const vlb_batch* b, int* cells_per_run);
+vlb_status vlb_batch_autotune(vlb_batch* b, int steps, int* chosen, double* ms_per_step);
+
+/* Step graphs.  By default vlb_step replays a HIP graph of 10 captured RK3 steps
+ * (captured once per precision on a private non-blocking stream at first use, then
+ * launched on the batch's stream) for all but the last step of a call, which runs as
+ * plain launches and records the residual.  enable = 0 makes every step plain
+ * launches (bitwise the same results). */
+vlb_status vlb_batch_set_graphs(vlb_batch* b, int enable);
+
 /* Kernel timing for roofline reports.  When enabled, every launch of the stage kernel
  * is bracketed by HIP events recorded on the batch's stream; launches are grouped by
  * kernel instantiation (velocities per lane, VPT).  vlb_timing_query synchronises the

@@ -85,6 +85,8 @@ struct vlb_batch {
     std::vector<InstDesc> desc;
     std::vector<WorkItem> work;        // per-wavefront list of the auxiliary kernels
     std::vector<BlockWork> blocks;     // stage-kernel blocks
+    size_t max_blocks = 0;             // device capacity of the block list
+    int tile = 0;                      // cells per run of the current block list
     std::vector<LaunchGroup> groups;
     std::vector<double> tab;
     size_t state_n = 0, ncells = 0;
@@ -99,6 +101,9 @@ struct vlb_batch {
     bool owns = false;
     bool have_resid = false;
     bool timing = false;
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;   // private stream used only to capture step graphs
+    hipGraphExec_t graph[2] = {nullptr, nullptr};   // [fp32]: kGraphSteps steps without residual
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
 
@@ -277,7 +282,7 @@ vlb_status layout_and_alloc(vlb_batch* b, bool alloc) {
     b->off_desc = off; off = align256(off + b->desc.size() * sizeof(InstDesc));
     b->off_desc32 = off; off = align256(off + b->desc32.size() * sizeof(InstDesc));
     b->off_work = off; off = align256(off + b->work.size() * sizeof(WorkItem));
-    b->off_blocks = off; off = align256(off + b->blocks.size() * sizeof(BlockWork));
+    b->off_blocks = off; off = align256(off + b->max_blocks * sizeof(BlockWork));
     b->total_bytes = off;
     if (!alloc) return VLB_OK;
     void* p = nullptr;
@@ -288,13 +293,17 @@ vlb_status layout_and_alloc(vlb_batch* b, bool alloc) {
     return VLB_OK;
 }
 
+vlb_status upload_blocks(vlb_batch* b);
+
 vlb_status finish_setup(vlb_batch* b) {
     vlb_status st = upload_tables(b);
     if (st != VLB_OK) return st;
     HIP_TRY(hipMemcpyAsync(b->dwork(), b->work.data(), b->work.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
                            b->stream));
-    HIP_TRY(hipMemcpyAsync(b->dblocks(), b->blocks.data(), b->blocks.size() * sizeof(BlockWork),
-                           hipMemcpyHostToDevice, b->stream));
+    {
+        vlb_status s2 = upload_blocks(b);
+        if (s2 != VLB_OK) return s2;
+    }
     // rest state n = 1, u = 0, T = T_in
     std::vector<double> host(b->state_n);
     for (int i = 0; i < b->B; ++i) {
@@ -367,7 +376,80 @@ vlb_status run_stage(vlb_batch* b, int stage, bool last, bool l_only) {
     return VLB_OK;
 }
 
+constexpr int kGraphSteps = 10;
+
+void drop_graphs(vlb_batch* b) {
+    for (hipGraphExec_t& g : b->graph)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+}
+
+// Capture kGraphSteps RK3 steps (3 stage launches each, no residual) of the current
+// precision into an executable graph, on a private stream.
+vlb_status capture_steps(vlb_batch* b, hipGraphExec_t* out) {
+    if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = b->stream;
+    b->stream = b->cap_stream;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+    vlb_status st = VLB_OK;
+    if (e == hipSuccess) {
+        for (int it = 0; it < kGraphSteps && st == VLB_OK; ++it)
+            for (int stage = 0; stage < 3 && st == VLB_OK; ++stage) st = run_stage(b, stage, false, false);
+        e = hipStreamEndCapture(b->cap_stream, &g);
+    }
+    b->stream = user;
+    if (st != VLB_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) return fail(VLB_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(VLB_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    return VLB_OK;
+}
+
+// Stage-kernel blocks for cell runs of about `tile` cells: per instance and distribution,
+// the grid is cut into runs of equal length <= tile; a block holds R runs (one group of
+// whole wavefronts per run, R <= kMaxRuns and R * tile <= kMaxRuns * kTileCells); the
+// heaviest blocks go first so the tail of a launch is made of small blocks.
+void build_blocks(vlb_batch* b, int tile) {
+    b->blocks.clear();
+    for (int i = 0; i < b->B; ++i) {
+        const InstDesc& D = b->desc[i];
+        const int nruns = (D.NR + tile - 1) / tile;
+        const int per = (D.NR + nruns - 1) / nruns;
+        const int nvpad = (D.NV + kWave - 1) / kWave * kWave;
+        const int rmax = std::max(1, std::min({kMaxRuns, kStageThreads / nvpad, kMaxRuns * kTileCells / per}));
+        for (int dist = 0; dist < 2; ++dist)
+            for (int r0 = 0; r0 < nruns; r0 += rmax)
+                b->blocks.push_back({i, dist, r0 * per, std::min(rmax, nruns - r0), per, nvpad, 0, 0});
+    }
+    std::stable_sort(b->blocks.begin(), b->blocks.end(), [&](const BlockWork& x, const BlockWork& y) {
+        const double wx = (double)x.R * x.TC * b->desc[x.inst].NV, wy = (double)y.R * y.TC * b->desc[y.inst].NV;
+        return wx > wy;
+    });
+    for (LaunchGroup& g : b->groups) g.nblocks = (int)b->blocks.size();
+    b->tile = tile;
+}
+
+vlb_status upload_blocks(vlb_batch* b) {
+    HIP_TRY(hipMemcpyAsync(b->dblocks(), b->blocks.data(), b->blocks.size() * sizeof(BlockWork),
+                           hipMemcpyHostToDevice, b->stream));
+    drop_graphs(b);   // captured launches carry the old grid size
+    return VLB_OK;
+}
+
 vlb_status step_current(vlb_batch* b, long nsteps) {
+    // all but the last step: replay captured chunks of kGraphSteps steps
+    if (b->use_graphs && !b->timing && nsteps > kGraphSteps) {
+        hipGraphExec_t& g = b->graph[b->cur32 ? 1 : 0];
+        if (!g) {
+            vlb_status s = capture_steps(b, &g);
+            if (s != VLB_OK) return s;
+        }
+        while (nsteps > kGraphSteps) {
+            HIP_TRY(hipGraphLaunch(g, b->stream));
+            nsteps -= kGraphSteps;
+        }
+    }
     for (long it = 0; it < nsteps; ++it) {
         const bool last = it + 1 == nsteps;
         for (int st = 0; st < 3; ++st) {
@@ -581,29 +663,20 @@ vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_de
                 ++made;
             }
             while (made % kWavesPerBlock) { b->work.push_back({i, dist, 0, 0}); ++made; }
-            // stage-kernel blocks: R runs of `per` cells, one thread per velocity
-            const int nvpad = (D.NV + kWave - 1) / kWave * kWave;
-            const int rmax = std::min(kMaxRuns, kStageThreads / nvpad);
-            for (int r0 = 0; r0 < nruns; r0 += rmax) {
-                const int R = std::min(rmax, nruns - r0);
-                b->blocks.push_back({i, dist, r0 * per, R, per, nvpad, 0, 0});
-            }
         }
         g.kmax = std::max(g.kmax, D.Q1 * D.Q1 + D.Q2 * D.Q2);
         g.pops += 2.0 * D.NR * D.NV;
     }
-    // heaviest blocks first, so the tail of a launch is made of small blocks
-    std::stable_sort(b->blocks.begin(), b->blocks.end(), [&](const BlockWork& x, const BlockWork& y) {
-        const double wx = (double)x.R * x.TC * b->desc[x.inst].NV, wy = (double)y.R * y.TC * b->desc[y.inst].NV;
-        return wx > wy;
-    });
     g.kmax = (g.kmax + 1) & ~1;
-    g.nblocks = (int)b->blocks.size();
     if (stage_lds(g.kmax, sizeof(double)) > 160 * 1024) {
         delete b;
         return fail(VLB_EINVAL, "velocity sets too large for LDS (%zu bytes)", stage_lds(g.kmax, sizeof(double)));
     }
     b->groups.push_back(g);
+    // stage-kernel block list: sized for the shortest cell run, built for the default
+    build_blocks(b, kMinTile);
+    b->max_blocks = b->blocks.size();
+    build_blocks(b, kTileCells);
 
     vlb_status st = layout_and_alloc(b, defer_alloc == 0);
     if (st != VLB_OK) { delete b; return st; }
@@ -618,6 +691,8 @@ vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_de
 void vlb_batch_destroy(vlb_batch* b) {
     if (!b) return;
     (void)hipStreamSynchronize(b->stream);
+    drop_graphs(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     for (TimedLaunch& t : b->timed) { (void)hipEventDestroy(t.start); (void)hipEventDestroy(t.stop); }
     for (hipEvent_t e : b->event_pool) (void)hipEventDestroy(e);
     if (b->owns && b->ws) {
@@ -641,6 +716,7 @@ vlb_status vlb_batch_bind_workspace(vlb_batch* b, void* dev_ptr, size_t bytes) {
         HIP_TRY(hipStreamSynchronize(b->stream));
         HIP_TRY(hipFree(b->ws));
     }
+    drop_graphs(b);   // captured kernels point into the old workspace
     b->ws = (char*)dev_ptr;
     b->owns = false;
     return finish_setup(b);
@@ -871,6 +947,75 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
 vlb_status vlb_mixed_fp32_steps(const vlb_batch* b, long* n) {
     if (!b || !n) return fail(VLB_EINVAL, "null argument");
     *n = b->fp32_steps;
+    return VLB_OK;
+}
+
+vlb_status vlb_batch_set_tile(vlb_batch* b, int cells_per_run) {
+    if (!b || cells_per_run < kMinTile || cells_per_run > kMaxTile) return fail(VLB_EINVAL, "tile out of range");
+    if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    build_blocks(b, cells_per_run);
+    return upload_blocks(b);
+}
+
+vlb_status vlb_batch_get_tile(const vlb_batch* b, int* cells_per_run) {
+    if (!b || !cells_per_run) return fail(VLB_EINVAL, "null argument");
+    *cells_per_run = b->tile;
+    return VLB_OK;
+}
+
+vlb_status vlb_batch_autotune(vlb_batch* b, int steps, int* chosen, double* ms_per_step) {
+    if (!b || steps < 1) return fail(VLB_EINVAL, "bad arguments");
+    if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
+    // keep the state: the trial steps run on a copy and the original is put back
+    const bool f32 = b->cur32;
+    const size_t bytes = b->state_n * (f32 ? sizeof(float) : sizeof(double));
+    void* keep = nullptr;
+    HIP_TRY(hipMalloc(&keep, bytes));
+    void* cur = f32 ? (void*)b->F32(0) : (void*)b->F(0);
+    HIP_TRY(hipMemcpyAsync(keep, cur, bytes, hipMemcpyDeviceToDevice, b->stream));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const bool timing = b->timing;
+    b->timing = false;
+    int best = b->tile;
+    float best_ms = 1e30f;
+    vlb_status st = VLB_OK;
+    for (int tile : {2, 4, 8, 16, 32}) {
+        build_blocks(b, tile);
+        st = upload_blocks(b);
+        if (st != VLB_OK) break;
+        st = step_current(b, 1);   // warm-up (also captures nothing: single plain step)
+        if (st != VLB_OK) break;
+        HIP_TRY(hipEventRecord(e0, b->stream));
+        st = step_current(b, steps);
+        if (st != VLB_OK) break;
+        HIP_TRY(hipEventRecord(e1, b->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) { best_ms = ms; best = tile; }
+    }
+    b->timing = timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    build_blocks(b, best);
+    vlb_status s2 = upload_blocks(b);
+    HIP_TRY(hipMemcpyAsync(cur, keep, bytes, hipMemcpyDeviceToDevice, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    (void)hipFree(keep);
+    if (st != VLB_OK) return st;
+    if (s2 != VLB_OK) return s2;
+    b->have_resid = false;
+    if (chosen) *chosen = best;
+    if (ms_per_step) *ms_per_step = best_ms / steps;
+    return refresh_moments(b);
+}
+
+vlb_status vlb_batch_set_graphs(vlb_batch* b, int enable) {
+    if (!b) return fail(VLB_EINVAL, "null batch");
+    b->use_graphs = enable != 0;
     return VLB_OK;
 }
 

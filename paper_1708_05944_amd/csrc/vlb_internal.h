@@ -13,7 +13,8 @@ constexpr int kWave = 64;      // CDNA wavefront width
 constexpr int kWavesPerBlock = 4;   // blocks of the auxiliary (per-wavefront work) kernels
 constexpr int kStageThreads = 1024; // stage kernel block: one thread per velocity
 constexpr int kMaxNV = kStageThreads;
-constexpr int kTileCells = 16; // cells swept by one cell run
+constexpr int kTileCells = 16; // default cells per run (auxiliary kernels and stage kernel)
+constexpr int kMinTile = 2, kMaxTile = 32;   // range of the stage kernel's cells per run
 constexpr int kMaxRuns = 16;   // cell runs per stage block
 constexpr int kEqStride = 24;  // doubles of equilibrium coefficients kept per cell
 

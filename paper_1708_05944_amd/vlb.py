@@ -93,6 +93,10 @@ _SIGS = {
                           ctypes.POINTER(ctypes.c_long), _dp],
     "vlb_axis_tables": [_Axis, _dp, _dp, _dp, _dp],
     "vlb_timing_enable": [ctypes.c_void_p, ctypes.c_int],
+    "vlb_batch_set_graphs": [ctypes.c_void_p, ctypes.c_int],
+    "vlb_batch_set_tile": [ctypes.c_void_p, ctypes.c_int],
+    "vlb_batch_get_tile": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
+    "vlb_batch_autotune": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _dp],
     "vlb_timing_query": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                          ctypes.POINTER(ctypes.c_long), _dp, _dp],
     "vlb_status_string": [ctypes.c_int],
@@ -259,6 +263,25 @@ class Batch:
         m = np.empty(self.B)
         _check(load_library().vlb_total_mass(self._h, _ptr(m)), "vlb_total_mass")
         return m
+
+    def set_tile(self, cells_per_run: int):
+        _check(load_library().vlb_batch_set_tile(self._h, cells_per_run), "vlb_batch_set_tile")
+
+    def tile(self) -> int:
+        t = ctypes.c_int()
+        _check(load_library().vlb_batch_get_tile(self._h, ctypes.byref(t)), "vlb_batch_get_tile")
+        return t.value
+
+    def autotune(self, steps: int = 5):
+        """Pick the cells-per-run of the stage kernel by timing; returns (tile, ms/step)."""
+        t = ctypes.c_int()
+        ms = ctypes.c_double()
+        _check(load_library().vlb_batch_autotune(self._h, steps, ctypes.byref(t), ctypes.byref(ms)),
+               "vlb_batch_autotune")
+        return t.value, ms.value
+
+    def set_graphs(self, on: bool = True):
+        _check(load_library().vlb_batch_set_graphs(self._h, 1 if on else 0), "vlb_batch_set_graphs")
 
     def timing_enable(self, on: bool = True):
         _check(load_library().vlb_timing_enable(self._h, 1 if on else 0), "vlb_timing_enable")

@@ -177,3 +177,58 @@ def test_unstable_dt_is_rejected():
     with pytest.raises(VlbError) as e:
         Batch([CouetteDesc(N_R=50, ax1=(1, 16, 4), ax2=(0, 20, 4), Kn=10.0, u_in=0.5, R_out=3.0, dt=2e-3)])
     assert e.value.status == -7
+
+
+def test_step_graph_replay_is_bitwise_identical():
+    """Steps replayed from the captured HIP graph equal plain launches bit for bit, for
+    several replays with host work and synchronisation in between, in both precisions."""
+    from paper_1708_05944_amd import VLB_MIXED, Batch
+    cases = [L_CASES[0], L_CASES[5], L_CASES[6]]
+    for prec in (0, VLB_MIXED):
+        runs = []
+        for graphs in (True, False):
+            b = Batch([_pair(**dict(c))[1] for c in cases], precision=prec)
+            b.set_graphs(graphs)
+            states = []
+            for rep in range(3):
+                b.step(25)                  # two graph replays + 5 plain steps per call
+                states.append(b.get_state())
+            runs.append((states, b.residual()))
+            b.close()
+        for a, c in zip(runs[0][0], runs[1][0]):
+            assert np.array_equal(a, c), prec
+        assert np.array_equal(runs[0][1], runs[1][1])
+
+
+@pytest.mark.parametrize("tile", [2, 5, 32])
+def test_tile_choice_does_not_change_results(tile):
+    """Every cells-per-run choice gives the oracle's result (uneven batch, 20 steps)."""
+    from paper_1708_05944_amd import Batch
+    cases = [L_CASES[0], L_CASES[2], L_CASES[5], L_CASES[6]]
+    pairs = [_pair(**dict(c)) for c in cases]
+    b = Batch([p[1] for p in pairs])
+    b.set_tile(tile)
+    st = b.get_state()
+    inits = []
+    for i, (ora, _) in enumerate(pairs):
+        F = _perturbed(ora, 20 + i)
+        b.instance_view(st, i)[...] = F
+        inits.append(F)
+    b.set_state(st)
+    b.step(20)
+    got = b.get_state()
+    for i, (ora, _) in enumerate(pairs):
+        want = ora.step(inits[i], b.info[i]["dt"], 20)
+        assert _relerr(b.instance_view(got, i), want) <= TOL, (tile, i)
+    b.close()
+
+
+def test_autotune_keeps_state_and_picks_a_tile():
+    from paper_1708_05944_amd import Batch
+    b = Batch([_pair(**dict(L_CASES[0]))[1], _pair(**dict(L_CASES[5]))[1]])
+    b.step(3)
+    before = b.get_state()
+    tile, ms = b.autotune(3)
+    assert tile in (2, 4, 8, 16, 32) and ms > 0 and b.tile() == tile
+    assert np.array_equal(b.get_state(), before)
+    b.close()
