@@ -27,6 +27,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak with plain (non-packed) FMAs, 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz;
+# the library is built with packed FP32 instructions disabled, so 157.3 TFLOP/s is out of reach
+VALU_FP32_TFLOPS = 78.6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "couette_stage_traffic.json")
+
+
+def stage_flops(descs) -> float:
+    """Algorithmic flops of one RK stage over the batch: per site-velocity, two
+    distributions x (WENO-5 face ~54, force 2 x 2 Q_R + 2 Q_phi + 5, BGK/combine ~8),
+    plus ~13 for moments and the equilibrium factor product."""
+    tot = 0.0
+    for d in descs:
+        n1 = d.ax1[1] * (2 if d.ax1[0] == 1 else 1)
+        n2 = d.ax2[1] * (2 if d.ax2[0] == 1 else 1)
+        tot += d.N_R * n1 * n2 * (2 * (54 + 2 * n1 + 2 * n2 + 5 + 8) + 13)
+    return tot
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE profile, or None
+    when the kernel sources have changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        for rel, want in rec["source_sha256"].items():
+            if hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest() != want:
+                return None
+        return float(rec[kernel]["bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def _cpu_worker(args):
@@ -74,6 +104,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-instances", type=int, default=64)
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-tts", action="store_true",
+                    help="skip the single-instance time-to-steady-state leg (profiling runs)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="after the run, one plain device copy of this many MiB (reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -115,10 +147,12 @@ def main():
     achieved = dom["alg_bytes"] / (dom["total_ms"] * 1e-3) / 1e9
     dom64 = fp64["dom"]
     achieved64 = dom64["alg_bytes"] / (dom64["total_ms"] * 1e-3) / 1e9
+    flops_launch = stage_flops(descs)
+    alu = flops_launch / (dom["total_ms"] / dom["launches"] * 1e-3) / 1e12
 
     # time to steady state (r < 1e-10) of the single-instance workload, FP64 vs mixed
     tts = {}
-    for name, prec in (("fp64", 0), ("mixed", VLB_MIXED)):
+    for name, prec in (() if args.no_tts else (("fp64", 0), ("mixed", VLB_MIXED))):
         b = Batch([workloads.single_couette()], precision=prec)
         b.step(0 if prec == 0 else 1)
         single_tile, _ = b.autotune(20)
@@ -150,13 +184,16 @@ def main():
                    "instances": len(descs), "site_velocities_per_step": updates_per_step,
                    "cells_per_run": mixed["tile"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("couette_stage<float>"),
                      "kernel": "couette_stage<float>", "launches": dom["launches"],
                      "avg_launch_ms": dom["total_ms"] / dom["launches"],
-                     "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"]},
+                     "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"],
+                     "alu": {"achieved_TFLOPs": alu, "peak_TFLOPs": VALU_FP32_TFLOPS, "frac": alu / VALU_FP32_TFLOPS,
+                             "alg_flops_per_launch": flops_launch}},
         "fp64": {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"], "kernel": "couette_stage<double>",
                  "cells_per_run": fp64["tile"],
                  "achieved_GBps": achieved64, "frac": achieved64 / HBM_PEAK_GBS,
+                 "traffic": measured_traffic("couette_stage<double>"),
                  "avg_launch_ms": dom64["total_ms"] / dom64["launches"]},
         "time_to_steady_state_single": tts,
     }
