@@ -50,6 +50,8 @@ def lib():
             _lib.oracle_feq.argtypes = [ctypes.c_void_p] + [ctypes.c_double] * 4 + [dp, dp]
             _lib.oracle_weno5.argtypes = [ctypes.c_double] * 5
             _lib.oracle_weno5.restype = ctypes.c_double
+            _lib.oracle_weno5_eps.argtypes = [ctypes.c_double] * 6
+            _lib.oracle_weno5_eps.restype = ctypes.c_double
             _lib.oracle_weno5_omega.argtypes = [ctypes.c_double] * 3 + [dp]
             _lib.oracle_weno5_sigma.argtypes = [ctypes.c_double] * 5 + [dp]
         return _lib
@@ -60,7 +62,7 @@ class _Params(ctypes.Structure):
                 + [(n, ctypes.POINTER(ctypes.c_double)) for n in
                    ("p1", "w1", "p2", "w2", "B1", "B2", "K1", "Kt2", "Rf", "dchi", "Gam")]
                 + [("Kn", ctypes.c_double), ("tau_model", ctypes.c_int)]
-                + [(n, ctypes.c_double) for n in ("u_in", "T_in", "u_out", "T_out")])
+                + [(n, ctypes.c_double) for n in ("u_in", "T_in", "u_out", "T_out", "weno_eps")])
 
 
 def _ptr(a: np.ndarray):
@@ -70,6 +72,12 @@ def _ptr(a: np.ndarray):
 def weno5(a, b, c, d, e) -> float:
     """The oracle's epsilon-free WENO-5 flux (upwind cell c), Sec. III.C."""
     return lib().oracle_weno5(a, b, c, d, e)
+
+
+def weno5_eps(a, b, c, d, e, eps) -> float:
+    """Regularised WENO-5 flux (an extension; eps = 0 is the paper's scheme): when no
+    indicator vanishes exactly, each gets eps * mean(a^2 .. e^2) added."""
+    return lib().oracle_weno5_eps(a, b, c, d, e, eps)
 
 
 def weno5_omega(s1, s2, s3) -> np.ndarray:
@@ -107,10 +115,12 @@ class CouetteOracle:
 
     ax1 / ax2 are (kind, Q, N) for the radial and azimuthal momentum axes
     (kind 0 = full-range H, 1 = half-range HH), e.g. HH(2;4) x H(2;4) is
-    ax1=(1, 4, 2), ax2=(0, 4, 2)."""
+    ax1=(1, 4, 2), ax2=(0, 4, 2).  weno_eps > 0 selects the regularised WENO weights
+    (an extension for reaching steady states; 0 is the paper's epsilon-free scheme)."""
 
     def __init__(self, R_in=1.0, R_out=2.0, N_R=64, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.1,
-                 tau_model=TAU_AOKI, u_in=0.1, T_in=1.0, u_out=0.0, T_out=1.0, A=0.0, delta=0.5):
+                 tau_model=TAU_AOKI, u_in=0.1, T_in=1.0, u_out=0.0, T_out=1.0, A=0.0, delta=0.5,
+                 weno_eps=0.0):
         if N_R < 3:
             raise ValueError("need at least 3 cells (wall extrapolation uses 3)")
         self.a1, self.a2 = quad.axis(*ax1), quad.axis(*ax2)
@@ -137,6 +147,7 @@ class CouetteOracle:
             setattr(P, name, _ptr(arr))
         P.Kn, P.tau_model = Kn, tau_model
         P.u_in, P.T_in, P.u_out, P.T_out = u_in, T_in, u_out, T_out
+        P.weno_eps = weno_eps
         self._P = P
         self.W = np.outer(self.a1.w, self.a2.w).ravel()      # quadrature weight per velocity
 

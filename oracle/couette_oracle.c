@@ -46,6 +46,7 @@ typedef struct {
     double Kn;
     int tau_model;           /* 0: Kn sqrt(pi/8)/n, 1: Kn/(nT), 2: Kn/n */
     double u_in, T_in, u_out, T_out;   /* tangential wall speeds and temperatures */
+    double weno_eps;         /* 0: the epsilon-free weights of Table weno; > 0: regularised */
 } couette_params;
 
 /* ------------------------------------------------------------------ equilibrium */
@@ -182,16 +183,31 @@ void oracle_weno5_sigma(double a, double b, double c, double d, double e, double
     s[2] = 13.0 / 12.0 * (x3 * x3) + 0.25 * (y3 * y3);
 }
 
-double oracle_weno5(double a, double b, double c, double d, double e) {
+/* WENO-5 face value with an optional regularisation (an extension; the paper's scheme
+ * is eps = 0): when no indicator vanishes exactly, every indicator gets
+ * eps (a^2 + b^2 + c^2 + d^2 + e^2) / 5 added before the weights are formed.  The added
+ * term scales like the indicators, so the flux stays homogeneous of degree one in the
+ * data; exactly vanishing indicators (e.g. the all-ghost wall stencil, which makes the
+ * emitted flux exactly the ghost Maxwellian, Sec. III.F) keep the limits of Table weno.
+ * eps -> infinity gives the ideal weights (0.1, 0.6, 0.3). */
+double oracle_weno5_eps(double a, double b, double c, double d, double e, double eps) {
     double f1 = a / 3.0 - 7.0 / 6.0 * b + 11.0 / 6.0 * c;
     double f2 = -b / 6.0 + 5.0 / 6.0 * c + d / 3.0;
     double f3 = c / 3.0 + 5.0 / 6.0 * d - e / 6.0;
     double s[3];
     oracle_weno5_sigma(a, b, c, d, e, s);
+    if (eps > 0.0 && s[0] != 0.0 && s[1] != 0.0 && s[2] != 0.0) {
+        const double add = eps * (a * a + b * b + c * c + d * d + e * e) / 5.0;
+        s[0] += add;
+        s[1] += add;
+        s[2] += add;
+    }
     double w[3];
     oracle_weno5_omega(s[0], s[1], s[2], w);
     return w[0] * f1 + w[1] * f2 + w[2] * f3;
 }
+
+double oracle_weno5(double a, double b, double c, double d, double e) { return oracle_weno5_eps(a, b, c, d, e, 0.0); }
 
 /* ------------------------------------------------------------------ L[F] */
 /* L[F] of Eq. L_def for the Couette chi formulation.  nw_res (may be NULL) gets the
@@ -241,12 +257,12 @@ void oracle_couette_L(const couette_params* P, const double* F, double* L, doubl
             if (pr > 0) {
                 den_in += pr * feqw_in[k];
                 /* outer wall, wall-bound (V > 0): flux at face NR+1/2 from cells NR-2..NR+2 */
-                num_out += pr * oracle_weno5(EX(0, NR - 3, k), EX(0, NR - 2, k), EX(0, NR - 1, k),
-                                             EX(0, NR, k), EX(0, NR + 1, k));
+                num_out += pr * oracle_weno5_eps(EX(0, NR - 3, k), EX(0, NR - 2, k), EX(0, NR - 1, k),
+                                                 EX(0, NR, k), EX(0, NR + 1, k), P->weno_eps);
             } else if (pr < 0) {
                 den_out += pr * feqw_out[k];
                 /* inner wall, wall-bound (V < 0): mirrored stencil F_3, F_2, F_1, F_0, F_-1 */
-                num_in += pr * oracle_weno5(EX(0, 2, k), EX(0, 1, k), EX(0, 0, k), EX(0, -1, k), EX(0, -2, k));
+                num_in += pr * oracle_weno5_eps(EX(0, 2, k), EX(0, 1, k), EX(0, 0, k), EX(0, -1, k), EX(0, -2, k), P->weno_eps);
             }
         }
     double nw_in = -num_in / den_in, nw_out = -num_out / den_out;
@@ -281,11 +297,11 @@ void oracle_couette_L(const couette_params* P, const double* F, double* L, doubl
                     double pr = P->p1[i], pp = P->p2[j];
                     double fl, fr;   /* fluxes at faces s-1/2 and s+1/2 (paper cells s+1) */
                     if (pr > 0) {
-                        fl = oracle_weno5(EX(d, s - 3, k), EX(d, s - 2, k), EX(d, s - 1, k), EX(d, s, k), EX(d, s + 1, k));
-                        fr = oracle_weno5(EX(d, s - 2, k), EX(d, s - 1, k), EX(d, s, k), EX(d, s + 1, k), EX(d, s + 2, k));
+                        fl = oracle_weno5_eps(EX(d, s - 3, k), EX(d, s - 2, k), EX(d, s - 1, k), EX(d, s, k), EX(d, s + 1, k), P->weno_eps);
+                        fr = oracle_weno5_eps(EX(d, s - 2, k), EX(d, s - 1, k), EX(d, s, k), EX(d, s + 1, k), EX(d, s + 2, k), P->weno_eps);
                     } else {
-                        fl = oracle_weno5(EX(d, s + 2, k), EX(d, s + 1, k), EX(d, s, k), EX(d, s - 1, k), EX(d, s - 2, k));
-                        fr = oracle_weno5(EX(d, s + 3, k), EX(d, s + 2, k), EX(d, s + 1, k), EX(d, s, k), EX(d, s - 1, k));
+                        fl = oracle_weno5_eps(EX(d, s + 2, k), EX(d, s + 1, k), EX(d, s, k), EX(d, s - 1, k), EX(d, s - 2, k), P->weno_eps);
+                        fr = oracle_weno5_eps(EX(d, s + 3, k), EX(d, s + 2, k), EX(d, s + 1, k), EX(d, s, k), EX(d, s - 1, k), P->weno_eps);
                     }
                     double adv = pr * (P->Rf[s + 1] * fr - P->Rf[s] * fl) / P->dchi[s];
                     double kf = 0.0, ktf = 0.0;
