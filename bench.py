@@ -106,6 +106,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-tts", action="store_true",
                     help="skip the single-instance time-to-steady-state leg (profiling runs)")
+    ap.add_argument("--no-warm", action="store_true",
+                    help="skip the learned warm-start leg (training solves, training, held-out runs)")
+    ap.add_argument("--warm-train", type=int, default=128, help="training instances of the warm-start leg")
+    ap.add_argument("--warm-heldout", type=int, default=32, help="held-out instances of the warm-start leg")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="after the run, one plain device copy of this many MiB (reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -165,6 +169,23 @@ def main():
                          fp32_steps=b.fp32_steps() if prec else 0, tile=single_tile)
         b.close()
 
+    warm = None
+    if not args.no_warm:
+        # learned warm start: surrogate trained on the solver's own steady states (sweep
+        # generator, seed 1), judged on held-out instances (seed 2) against the plain FP64
+        # solver from rest; family Kn <= 0.2, 32 cells, regularised WENO weights (1e-6)
+        from paper_1708_05944_amd import surrogate
+        tr = workloads.surrogate_descs(args.warm_train, workloads.SURROGATE_TRAIN_SEED, N_R=32, Kn_max=0.2)
+        ho = workloads.surrogate_descs(args.warm_heldout, workloads.SURROGATE_HELDOUT_SEED, N_R=32, Kn_max=0.2)
+        for d in tr + ho:
+            d.weno_eps = 1e-6
+        warm = surrogate.warm_start_comparison(tr, ho, epochs=1000, batch=256, lr=1e-3, probe=500,
+                                               max_steps=200_000, chunk=5_000,
+                                               log=lambda m: print(m, file=sys.stderr, flush=True))
+        warm["workload"] = (f"{len(tr)} training / {len(ho)} held-out Couette instances of the sweep generator "
+                            f"(seeds 1 / 2) with Kn <= 0.2, 32 cells, weno_eps 1e-6; cold = FP64 from rest, "
+                            f"warm = surrogate (bf16 inference) + judge probe, mixed precision")
+
     out = {
         "metric": "site-velocity updates/s (batched Couette sweep, mixed precision: FP32 streaming)",
         "value": mixed["value"],
@@ -196,6 +217,7 @@ def main():
                  "traffic": measured_traffic("couette_stage<double>"),
                  "avg_launch_ms": dom64["total_ms"] / dom64["launches"]},
         "time_to_steady_state_single": tts,
+        "time_to_steady_state_warm_start": warm,
     }
     if args.copy_ref_mib:
         n = args.copy_ref_mib << 20

@@ -83,7 +83,14 @@ enum { VLB_FP64 = 0, VLB_MIXED = 1 };
  * axis, ax2 the azimuthal one; ax1.kind = 1 (half range) is the choice that resolves
  * the wall discontinuity (Sec. IV.B).  dt = 0 picks dt = cfl * min_s dchi_s /
  * (R_{s+1/2} max|p^R|).  Walls: tangential speeds u_in / u_out and temperatures
- * T_in / T_out of the inner and outer cylinder (Sec. III.F, Eq. diffuse_f). */
+ * T_in / T_out of the inner and outer cylinder (Sec. III.F, Eq. diffuse_f).
+ * weno_eps: 0 (the paper's epsilon-free WENO weights of Table weno), or > 0 for
+ * regularised weights (an extension): when no smoothness indicator of a stencil
+ * vanishes exactly, each gets weno_eps * (a^2 + b^2 + c^2 + d^2 + e^2) / 5 added (a..e
+ * the stencil values), which removes the chatter of the epsilon-free weights that
+ * stalls the residual near some steady states; stencils with a vanishing indicator
+ * (the all-ghost wall stencil) keep the Table weno limits, so the wall mass balance
+ * stays exact. */
 typedef struct {
     double R_in, R_out;
     int N_R;
@@ -93,6 +100,7 @@ typedef struct {
     int tau_model;
     double dt, cfl;
     double u_in, T_in, u_out, T_out;
+    double weno_eps;
 } vlb_couette_desc;
 
 typedef struct vlb_batch vlb_batch;
@@ -169,13 +177,16 @@ vlb_status vlb_residual(vlb_batch* b, double* r);
 vlb_status vlb_total_mass(vlb_batch* b, double* Ntot);
 
 /* Step every instance until its residual is below tol, checking every check_every
- * steps, at most max_steps steps.  Converged instances keep stepping while others
- * run.  steps / r (host arrays of B, may be NULL) receive the step count at which
- * each instance first reached tol (or -1) and its last residual.  Returns
+ * steps, at most max_steps steps.  An instance whose residual is below tol at a check
+ * retires: the stage kernels stop advancing it while the others run, so its state,
+ * moments and residual stay those of the step at which it converged.  steps / r (host
+ * arrays of B, may be NULL) receive that step count (or -1) and the last residual.  Returns
  * VLB_ENOTCONV if some instance did not converge.  For VLB_MIXED batches the run
  * starts with FP32 steps until the largest residual is below max(tol, 1e-5) or stops
  * falling (the FP32 rounding floor is about 6e-8/dt), then continues in FP64, so the
- * final state is an FP64 fixed point; vlb_mixed_fp32_steps reports the FP32 steps. */
+ * final state is an FP64 fixed point; vlb_mixed_fp32_steps reports the FP32 steps.  A
+ * call that follows one which ended in its FP64 phase, with no state change in between
+ * (set_state, init_equilibrium, warm_start, set_wall, vlb_step), continues in FP64. */
 vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check_every, long* steps, double* r);
 vlb_status vlb_mixed_fp32_steps(const vlb_batch* b, long* n);
 
@@ -203,16 +214,76 @@ vlb_status vlb_batch_set_graphs(vlb_batch* b, int enable);
 
 /* Kernel timing for roofline reports.  When enabled, every launch of the stage kernel
  * is bracketed by HIP events recorded on the batch's stream; launches are grouped by
- * kernel instantiation (velocities per lane, VPT).  vlb_timing_query synchronises the
- * stream and returns, for up to max_groups groups: the VPT of the instantiation (negated
- * for the FP32 instantiation), the
- * number of launches recorded, their summed duration in ms, and the algorithmic HBM
+ * kernel instantiation.  vlb_timing_query synchronises the stream and returns, for up
+ * to max_groups groups: the element width in bits of the instantiation (64 for the FP64
+ * kernel, 32 for the FP32 kernel), the number of launches recorded, their summed duration in ms, and the algorithmic HBM
  * bytes they moved (each launch: per population of the instances it covers, one read
  * of the stage input, one read of F_n in stages 2 and 3, one write).  Querying clears
  * the record.  ngroups receives the number of groups with launches. */
 vlb_status vlb_timing_enable(vlb_batch* b, int enable);
-vlb_status vlb_timing_query(vlb_batch* b, int max_groups, int* ngroups, int* vpt, long* launches, double* total_ms,
+vlb_status vlb_timing_query(vlb_batch* b, int max_groups, int* ngroups, int* bits, long* launches, double* total_ms,
                             double* alg_bytes);
+
+/* ---- Learned warm start (an addition to the method: the paper has no surrogate) ----
+ *
+ * A multilayer perceptron maps, per cell, the inputs
+ *   (log10 Kn, u_w, beta = R_in/R_out, rho = (R - R_in)/(R_out - R_in)),
+ * each mapped affinely from the box [-2, 1] x [0.05, 0.5] x [0.3, 0.8] x [0, 1] to
+ * [-1, 1], to the steady fields ((n - 1) 10, u^R 10, u^phi / u_w, (T - 1) 10) at the
+ * cell centre R.  Network: 4 inputs -> depth hidden layers of width units with SiLU
+ * activations, silu(z) = z / (1 + e^-z) -> 4 linear outputs.  Parameters are FP32, in
+ * the same order on host and device: for each layer, W[fan_in][fan_out] row-major, then
+ * b[fan_out].  Training minimises the mean squared error over all outputs of a
+ * mini-batch with Adam (b1 = 0.9, b2 = 0.999, eps = 1e-8, bias-corrected; Kingma & Ba
+ * 2015) using FP32 matrix-core products; inference uses bfloat16 operands with FP32
+ * accumulation.  The network works on its stream (created with), one call at a time.
+ * The surrogate's family: inner wall moving tangentially (u_in > 0), outer wall at rest,
+ * both walls at T_w = 1, VLB_TAU_AOKI. */
+typedef struct vlb_mlp vlb_mlp;
+
+/* Parameter count of a width x depth network (width 1..1024, depth 1..8). */
+vlb_status vlb_mlp_param_count(int width, int depth, size_t* n);
+/* Network with the given initial parameters (host array, param_count floats; the
+ * caller draws them).  Allocates its parameters, Adam moments and gradient on the
+ * device; activation buffers grow with the largest batch seen. */
+vlb_status vlb_mlp_create(vlb_mlp** out, int width, int depth, const float* params, void* hip_stream);
+vlb_status vlb_mlp_destroy(vlb_mlp* m);
+vlb_status vlb_mlp_get_params(vlb_mlp* m, float* host, size_t n);
+/* Replaces the parameters and clears the Adam state (moments and step count). */
+vlb_status vlb_mlp_set_params(vlb_mlp* m, const float* host, size_t n);
+/* Y[n][4] = network(X[n][4]), device arrays; bf16 = 1 rounds every layer's operands
+ * (inputs and weights) to bfloat16 (nearest, ties to even), 0 computes in FP32. */
+vlb_status vlb_mlp_forward(vlb_mlp* m, const float* X, long n, float* Y, int bf16);
+/* Mean squared error of the network on device rows X[n][4] against T[n][4] and its
+ * gradient (FP32 forward and reverse passes).  loss (host scalar) and grad (host,
+ * param_count floats) may be NULL; the gradient also stays on the device for
+ * vlb_mlp_adam_step.  Synchronises. */
+vlb_status vlb_mlp_loss_grad(vlb_mlp* m, const float* X, const float* T, long n, float* loss, float* grad);
+/* One Adam step with learning rate lr on the given host gradient (param_count floats,
+ * e.g. one summed over several devices), or on the last device gradient if grad is NULL. */
+vlb_status vlb_mlp_adam_step(vlb_mlp* m, const float* grad, float lr);
+/* Adam steps over mini-batches: rows order[0..norder) of the device samples X, T
+ * (nsamples rows each) taken batch rows at a time (the last mini-batch may be
+ * shorter); every order entry must be in [0, nsamples).  mean_loss (may be NULL)
+ * receives the mean of the mini-batch losses.  Synchronises. */
+vlb_status vlb_mlp_train(vlb_mlp* m, const float* X, const float* T, long nsamples, const int* order, long norder,
+                         int batch, float lr, float* mean_loss);
+/* Training samples from the batch's current state (normally a steady state): the
+ * inputs and targets above for every cell of every instance, host arrays X[ncells][4],
+ * T[ncells][4] with ncells the batch's total cell count.  Every instance must be in
+ * the surrogate's family (VLB_EINVAL otherwise).  Synchronises. */
+vlb_status vlb_batch_surrogate_samples(vlb_batch* b, float* X, float* T, size_t ncells);
+/* Replaces every instance's state by an initial state: for an instance in the
+ * surrogate's family, the local equilibrium of the network's fields (bfloat16
+ * inference) with n rescaled so that sum_s dchi_s n_s equals the cold start's (the
+ * steady state of the closed cell depends on this conserved particle number, Eq.
+ * Ntot_def) and u^R = 0; for the others, and for any instance the judge rejects, the
+ * cold rest state (n = 1, u = 0, T = T_in).  The judge (probe_steps > 0): run
+ * probe_steps FP64 steps from the cold start and from the warm start; the warm start is
+ * kept only where its residual is then strictly lower (a non-finite warm residual
+ * rejects it).  used_warm (host array of B, may be NULL) receives 1 where the warm
+ * start is kept.  Leaves the state in the FP64 buffers.  Synchronises. */
+vlb_status vlb_batch_warm_start(vlb_batch* b, vlb_mlp* m, int probe_steps, int* used_warm);
 
 const char* vlb_status_string(vlb_status s);
 const char* vlb_last_error(void);

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/vlb.h"
+#include "mlp_internal.h"
 #include "vlb_internal.h"
 
 namespace vlb {
@@ -30,6 +31,10 @@ hipError_t launch_rescale(int nblocks, hipStream_t st, const InstDesc* insts, co
                           const double* target, const double* current, double* F);
 hipError_t launch_diag(int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
                        const double* tab, const double* F, double* diag);
+hipError_t launch_warm_profile(int ninst, hipStream_t st, const InstDesc* insts, const double* tab, const float* Y,
+                               const double* par, double* prof);
+hipError_t launch_init_profile(int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
+                               const double* tab, const double* prof, double* F);
 }  // namespace vlb
 
 using namespace vlb;
@@ -38,13 +43,18 @@ namespace {
 
 thread_local std::string g_err;
 
-vlb_status fail(vlb_status s, const char* fmt, ...) {
+vlb_status vfail(vlb_status s, const char* fmt, va_list ap) {
     char buf[512];
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    g_err = buf;
+    return s;
+}
+
+vlb_status fail(vlb_status s, const char* fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vfail(s, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return s;
 }
 
@@ -78,6 +88,16 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
+namespace vlb {
+vlb_status set_error(vlb_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vfail(s, fmt, ap);
+    va_end(ap);
+    return s;
+}
+}  // namespace vlb
+
 struct vlb_batch {
     int B = 0;
     hipStream_t stream = nullptr;
@@ -92,10 +112,12 @@ struct vlb_batch {
     size_t state_n = 0, ncells = 0;
     // workspace layout (byte offsets)
     size_t off_F[3], off_F32[3], off_M[3], off_rpart, off_resid, off_mass, off_tab, off_desc, off_desc32, off_work,
-        off_diag, off_mass0, off_blocks, total_bytes;
+        off_diag, off_mass0, off_blocks, off_prof, off_wpar, off_sfeat, off_sy, total_bytes;
+    std::vector<char> active;          // instances the stage kernels advance (run_to_steady retires converged ones)
     int precision = VLB_FP64;
     bool cur32 = false;                 // the current state lives in the FP32 buffers
     long fp32_steps = 0;                // steps of the FP32 phase of the last run_to_steady
+    bool polishing = false;             // the last run_to_steady ended in its FP64 phase, state untouched since
     std::vector<InstDesc> desc32;       // FP32 descriptors (rescaled tables)
     char* ws = nullptr;
     bool owns = false;
@@ -119,6 +141,10 @@ struct vlb_batch {
     InstDesc* ddesc() { return (InstDesc*)(ws + off_desc); }
     WorkItem* dwork() { return (WorkItem*)(ws + off_work); }
     BlockWork* dblocks() { return (BlockWork*)(ws + off_blocks); }
+    double* prof() { return (double*)(ws + off_prof); }
+    double* wpar() { return (double*)(ws + off_wpar); }
+    float* sfeat() { return (float*)(ws + off_sfeat); }
+    float* sy() { return (float*)(ws + off_sy); }
     double* diag() { return (double*)(ws + off_diag); }
 };
 
@@ -244,6 +270,7 @@ vlb_status set_state_device(vlb_batch* b, const double* host) {
     HIP_TRY(hipMemcpyAsync(b->F(0), host, b->state_n * sizeof(double), hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     b->cur32 = false;
+    b->polishing = false;
     b->have_resid = false;
     return refresh_moments(b);
 }
@@ -283,6 +310,10 @@ vlb_status layout_and_alloc(vlb_batch* b, bool alloc) {
     b->off_desc32 = off; off = align256(off + b->desc32.size() * sizeof(InstDesc));
     b->off_work = off; off = align256(off + b->work.size() * sizeof(WorkItem));
     b->off_blocks = off; off = align256(off + b->max_blocks * sizeof(BlockWork));
+    b->off_prof = off; off = align256(off + b->ncells * 4 * sizeof(double));
+    b->off_wpar = off; off = align256(off + b->B * 2 * sizeof(double));
+    b->off_sfeat = off; off = align256(off + b->ncells * 4 * sizeof(float));
+    b->off_sy = off; off = align256(off + b->ncells * 4 * sizeof(float));
     b->total_bytes = off;
     if (!alloc) return VLB_OK;
     void* p = nullptr;
@@ -413,6 +444,7 @@ vlb_status capture_steps(vlb_batch* b, hipGraphExec_t* out) {
 void build_blocks(vlb_batch* b, int tile) {
     b->blocks.clear();
     for (int i = 0; i < b->B; ++i) {
+        if (!b->active.empty() && !b->active[i]) continue;
         const InstDesc& D = b->desc[i];
         const int nruns = (D.NR + tile - 1) / tile;
         const int per = (D.NR + nruns - 1) / nruns;
@@ -523,7 +555,8 @@ vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_de
         const vlb_couette_desc& d = descs[i];
         if (!(d.N_R >= 3 && d.R_in > 0 && d.R_out > d.R_in && d.Kn > 0 && d.dt >= 0 && d.A >= 0 && d.A < 1 &&
               d.delta >= 0 && d.delta <= 1 && d.T_in > 0 && d.T_out > 0 && d.tau_model >= 0 && d.tau_model <= 2 &&
-              axis_ok(d.ax1) && axis_ok(d.ax2) && (d.dt > 0 || d.cfl > 0))) {
+              axis_ok(d.ax1) && axis_ok(d.ax2) && (d.dt > 0 || d.cfl > 0) && d.weno_eps >= 0 &&
+              std::isfinite(d.weno_eps))) {
             delete b;
             return fail(VLB_EINVAL, "invalid descriptor for instance %d", i);
         }
@@ -585,6 +618,7 @@ vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_de
         D.tau_model = d.tau_model;
         D.vpt = (h.NV + kWave - 1) / kWave;
         D.Kn = d.Kn;
+        D.weno_eps = d.weno_eps;
         D.dt = dt;
         D.T_in = d.T_in;
         D.T_out = d.T_out;
@@ -773,6 +807,7 @@ vlb_status vlb_set_wall(vlb_batch* b, int inst, int side, double u, double T) {
         InstDesc& E = b->desc32[inst];
         E.den_in = D.den_in; E.den_out = D.den_out; E.T_in = D.T_in; E.T_out = D.T_out;
     }
+    b->polishing = false;
     HIP_TRY(hipStreamSynchronize(b->stream));
     return upload_tables(b);
 }
@@ -824,6 +859,7 @@ vlb_status vlb_step(vlb_batch* b, long nsteps) {
     if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
     vlb_status s = ensure_precision(b, b->precision == VLB_MIXED);
     if (s != VLB_OK) return s;
+    b->polishing = false;
     return step_current(b, nsteps);
 }
 
@@ -892,7 +928,7 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
     std::vector<double> res(b->B, INFINITY);
     long done = 0;
     vlb_status s = VLB_OK;
-    if (b->precision == VLB_MIXED) {
+    if (b->precision == VLB_MIXED && !b->polishing) {
         // FP32 phase: stream the scaled FP32 state while every instance's residual still
         // falls; stop at 1e-5 (the FP32 rounding floor is eps32/dt) or when the largest
         // residual stops improving by 5% over three checks.
@@ -928,6 +964,18 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
     }
     s = ensure_precision(b, false);
     if (s != VLB_OK) return s;
+    // converged instances retire: the stage kernels stop advancing them (their state,
+    // moments and residual stay at the converged step); all are reinstated on return
+    struct Reinstate {
+        vlb_batch* b;
+        bool dirty = false;
+        ~Reinstate() {
+            if (!dirty) return;
+            b->active.clear();
+            build_blocks(b, b->tile);
+            (void)upload_blocks(b);
+        }
+    } guard{b};
     int remaining = b->B;
     while (done < max_steps && remaining > 0) {
         const long n = std::min<long>(check_every, max_steps - done);
@@ -936,9 +984,22 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
         done += n;
         s = read_residual(b, res.data());
         if (s != VLB_OK) return s;
+        bool retired = false;
         for (int i = 0; i < b->B; ++i)
-            if (conv[i] < 0 && res[i] < tol) { conv[i] = done; --remaining; }
+            if (conv[i] < 0 && res[i] < tol) {
+                conv[i] = done;
+                --remaining;
+                if (b->active.empty()) b->active.assign(b->B, 1);
+                b->active[i] = 0;
+                retired = guard.dirty = true;
+            }
+        if (retired && remaining > 0) {
+            build_blocks(b, b->tile);
+            s = upload_blocks(b);
+            if (s != VLB_OK) return s;
+        }
     }
+    b->polishing = true;
     if (steps) std::copy(conv.begin(), conv.end(), steps);
     if (r) std::copy(res.begin(), res.end(), r);
     return remaining ? fail(VLB_ENOTCONV, "%d instance(s) above tol after %ld steps", remaining, done) : VLB_OK;
@@ -1025,7 +1086,7 @@ vlb_status vlb_timing_enable(vlb_batch* b, int enable) {
     return VLB_OK;
 }
 
-vlb_status vlb_timing_query(vlb_batch* b, int max_groups, int* ngroups, int* vpt, long* launches, double* total_ms,
+vlb_status vlb_timing_query(vlb_batch* b, int max_groups, int* ngroups, int* bits, long* launches, double* total_ms,
                             double* alg_bytes) {
     if (!b || max_groups < 0 || !ngroups) return fail(VLB_EINVAL, "bad arguments");
     HIP_TRY(hipStreamSynchronize(b->stream));
@@ -1047,7 +1108,7 @@ vlb_status vlb_timing_query(vlb_batch* b, int max_groups, int* ngroups, int* vpt
     for (int g = 0; g < G; ++g) {
         if (n[g] == 0) continue;
         if (out < max_groups) {
-            if (vpt) vpt[out] = (g & 1) ? 32 : 64;
+            if (bits) bits[out] = (g & 1) ? 32 : 64;
             if (launches) launches[out] = n[g];
             if (total_ms) total_ms[out] = ms[g];
             if (alg_bytes) alg_bytes[out] = by[g];
@@ -1055,6 +1116,126 @@ vlb_status vlb_timing_query(vlb_batch* b, int max_groups, int* ngroups, int* vpt
         ++out;
     }
     *ngroups = out;
+    return VLB_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ learned warm start
+
+namespace {
+
+// The surrogate covers the Couette family it was trained on: inner wall moving, outer
+// wall at rest, both at T_w = 1, tau = Kn sqrt(pi/8)/n.
+bool surrogate_eligible(const vlb_couette_desc& d) {
+    return d.T_in == 1.0 && d.T_out == 1.0 && d.u_out == 0.0 && d.u_in > 0.0 && d.tau_model == VLB_TAU_AOKI &&
+           d.Kn > 0.0 && d.R_in > 0.0;
+}
+
+// Inputs of every cell: (log10 Kn, u_w, beta, rho) mapped affinely from the box
+// [-2, 1] x [0.05, 0.5] x [0.3, 0.8] x [0, 1] to [-1, 1]^4.
+void surrogate_features(const vlb_batch* b, float* X) {
+    size_t c = 0;
+    for (int i = 0; i < b->B; ++i) {
+        const vlb_couette_desc& d = b->inst[i].d;
+        const std::vector<double>& Rf = b->inst[i].Rf;
+        const double f0 = (std::log10(d.Kn) + 0.5) / 1.5, f1 = (d.u_in - 0.275) / 0.225,
+                     f2 = (d.R_in / d.R_out - 0.55) / 0.25;
+        for (int s = 0; s < d.N_R; ++s, ++c) {
+            const double rho = (0.5 * (Rf[s] + Rf[s + 1]) - d.R_in) / (d.R_out - d.R_in);
+            X[4 * c] = (float)f0;
+            X[4 * c + 1] = (float)f1;
+            X[4 * c + 2] = (float)f2;
+            X[4 * c + 3] = (float)(2.0 * rho - 1.0);
+        }
+    }
+}
+
+// State of every instance from the surrogate outputs in sy(): warm (use[i] = 1) or the
+// cold rest state; FP64 buffers.
+vlb_status init_from_surrogate(vlb_batch* b, const std::vector<int>& use) {
+    std::vector<double> par(2 * (size_t)b->B);
+    for (int i = 0; i < b->B; ++i) {
+        par[2 * i] = b->inst[i].d.u_in;
+        par[2 * i + 1] = use[i] ? 1.0 : 0.0;
+    }
+    HIP_TRY(hipMemcpyAsync(b->wpar(), par.data(), par.size() * sizeof(double), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(launch_warm_profile(b->B, b->stream, b->ddesc(), b->dtab(), b->sy(), b->wpar(), b->prof()));
+    const int nblocks = (int)(b->work.size() / kWavesPerBlock);
+    HIP_TRY(launch_init_profile(nblocks, b->stream, b->ddesc(), b->dwork(), b->dtab(), b->prof(), b->F(0)));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->cur32 = false;
+    b->have_resid = false;
+    b->polishing = false;
+    return refresh_moments(b);
+}
+
+}  // namespace
+
+extern "C" {
+
+vlb_status vlb_batch_surrogate_samples(vlb_batch* b, float* X, float* T, size_t ncells) {
+    if (!b || !X || !T || ncells != b->ncells) return fail(VLB_EINVAL, "need arrays of %zu cells", b ? b->ncells : 0);
+    if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
+    for (int i = 0; i < b->B; ++i)
+        if (!surrogate_eligible(b->inst[i].d))
+            return fail(VLB_EINVAL, "instance %d is outside the surrogate's Couette family", i);
+    vlb_status es = ensure_precision(b, false);
+    if (es != VLB_OK) return es;
+    const int nblocks = (int)(b->work.size() / kWavesPerBlock);
+    HIP_TRY(launch_diag(nblocks, b->stream, b->ddesc(), b->dwork(), b->dtab(), b->F(0), b->diag()));
+    std::vector<double> h(b->ncells * 7);
+    HIP_TRY(hipMemcpyAsync(h.data(), b->diag(), h.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    surrogate_features(b, X);
+    size_t c = 0;
+    for (int i = 0; i < b->B; ++i) {
+        const double uw = b->inst[i].d.u_in;
+        for (int s = 0; s < b->inst[i].d.N_R; ++s, ++c) {
+            const double* o = &h[c * 7];
+            T[4 * c] = (float)((o[0] - 1.0) * 10.0);
+            T[4 * c + 1] = (float)(o[1] * 10.0);
+            T[4 * c + 2] = (float)(o[2] / uw);
+            T[4 * c + 3] = (float)((o[3] - 1.0) * 10.0);
+        }
+    }
+    return VLB_OK;
+}
+
+vlb_status vlb_batch_warm_start(vlb_batch* b, vlb_mlp* m, int probe_steps, int* used_warm) {
+    if (!b || !m || probe_steps < 0) return fail(VLB_EINVAL, "bad arguments");
+    if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
+    vlb_status s = ensure_precision(b, false);
+    if (s != VLB_OK) return s;
+    std::vector<float> X(b->ncells * 4);
+    surrogate_features(b, X.data());
+    std::vector<int> elig(b->B), use(b->B, 0);
+    bool any = false;
+    for (int i = 0; i < b->B; ++i) any |= (elig[i] = surrogate_eligible(b->inst[i].d) ? 1 : 0) != 0;
+    HIP_TRY(hipMemcpyAsync(b->sfeat(), X.data(), X.size() * sizeof(float), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    HIP_TRY(hipStreamSynchronize(mlp_stream(m)));
+    s = mlp_infer(m, b->sfeat(), (long)b->ncells, b->sy(), 1, b->stream);
+    if (s != VLB_OK) return s;
+    if (any && probe_steps > 0) {
+        // the judge: the FP64 residual after probe_steps steps from each start
+        std::vector<double> rc(b->B), rw(b->B);
+        s = init_from_surrogate(b, use);
+        if (s == VLB_OK) s = step_current(b, probe_steps);
+        if (s == VLB_OK) s = read_residual(b, rc.data());
+        if (s == VLB_OK) s = init_from_surrogate(b, elig);
+        if (s == VLB_OK) s = step_current(b, probe_steps);
+        if (s != VLB_OK) return s;
+        // a warm start that diverges is rejected, not reported as an error
+        HIP_TRY(hipMemcpyAsync(rw.data(), b->resid(), b->B * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        for (int i = 0; i < b->B; ++i) use[i] = elig[i] && std::isfinite(rw[i]) && rw[i] < rc[i];
+    } else {
+        use = elig;
+    }
+    s = init_from_surrogate(b, use);
+    if (s != VLB_OK) return s;
+    if (used_warm) std::copy(use.begin(), use.end(), used_warm);
     return VLB_OK;
 }
 

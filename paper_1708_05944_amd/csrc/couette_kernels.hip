@@ -56,30 +56,42 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Flux at the face between c and d, upwinded from c (a, b, c, d, e in upwind order).
 template <typename T>
-__device__ __forceinline__ T weno5(T a, T b, T c, T d, T e);
+__device__ __forceinline__ T weno5(T a, T b, T c, T d, T e, T eps);
 
 // Face flux between window cells 2 and 3 of a six-cell window (cells s-2 .. s+3):
 // upwinded from cell 2 when the advection velocity is positive, from cell 3 otherwise
 // (the mirror image of the printed stencil).  The five stencil values are selected
 // first, so a wavefront holding both signs evaluates WENO once.
 template <typename T>
-__device__ __forceinline__ T weno_face(bool pos, T w0, T w1, T w2, T w3, T w4, T w5) {
-    return weno5<T>(pos ? w0 : w5, pos ? w1 : w4, pos ? w2 : w3, pos ? w3 : w2, pos ? w4 : w1);
+__device__ __forceinline__ T weno_face(bool pos, T w0, T w1, T w2, T w3, T w4, T w5, T eps) {
+    return weno5<T>(pos ? w0 : w5, pos ? w1 : w4, pos ? w2 : w3, pos ? w3 : w2, pos ? w4 : w1, eps);
 }
 
 template <typename T>
-__device__ __forceinline__ T weno5(T a, T b, T c, T d, T e) {
+__device__ __forceinline__ T weno5(T a, T b, T c, T d, T e, T eps) {
     const T f1 = a * T(1.0 / 3.0) - b * T(7.0 / 6.0) + c * T(11.0 / 6.0);
     const T f2 = -b * T(1.0 / 6.0) + c * T(5.0 / 6.0) + d * T(1.0 / 3.0);
     const T f3 = c * T(1.0 / 3.0) + d * T(5.0 / 6.0) - e * T(1.0 / 6.0);
     T t1 = a - T(2) * b + c, t2 = a - T(4) * b + T(3) * c;
-    const T s1 = T(13.0 / 12.0) * (t1 * t1) + T(0.25) * (t2 * t2);
+    T s1 = T(13.0 / 12.0) * (t1 * t1) + T(0.25) * (t2 * t2);
     t1 = b - T(2) * c + d;
     t2 = b - d;
-    const T s2 = T(13.0 / 12.0) * (t1 * t1) + T(0.25) * (t2 * t2);
+    T s2 = T(13.0 / 12.0) * (t1 * t1) + T(0.25) * (t2 * t2);
     t1 = c - T(2) * d + e;
     t2 = T(3) * c - T(4) * d + e;
-    const T s3 = T(13.0 / 12.0) * (t1 * t1) + T(0.25) * (t2 * t2);
+    T s3 = T(13.0 / 12.0) * (t1 * t1) + T(0.25) * (t2 * t2);
+    // an indicator vanishes exactly when its three values are equal (Eq. weno_sigma is a
+    // sum of squares of two independent differences); the equality test is immune to the
+    // compiler fusing the products that form the values into the indicator arithmetic
+    // (identical ghost values must select the Table weno limit, whatever eps)
+    const bool z1 = (a == b && b == c) || s1 == T(0), z2 = (b == c && c == d) || s2 == T(0),
+               z3 = (c == d && d == e) || s3 == T(0), zany = z1 || z2 || z3;
+    if (eps != T(0)) {   // optional regularisation (eps is uniform over the instance)
+        const T add = zany ? T(0) : eps * T(0.2) * (a * a + b * b + c * c + d * d + e * e);
+        s1 += add;
+        s2 += add;
+        s3 += add;
+    }
     // w_q proportional to d_q / s_q^2, rewritten as d_q (r_a r_b)^2 with r = s / max(s):
     // one division instead of three and no overflow.  In FP64 an underflow would need two
     // indicators below 1e-155 of the largest, which only exact zeros reach; the FP32 path
@@ -92,7 +104,6 @@ __device__ __forceinline__ T weno5(T a, T b, T c, T d, T e) {
     const T inv = T(1) / m;
     const T r1 = s1 * inv, r2 = s2 * inv, r3 = s3 * inv;
     const T q23 = r2 * r3, q13 = r1 * r3, q12 = r1 * r2;
-    const bool z1 = s1 == T(0), z2 = s2 == T(0), z3 = s3 == T(0), zany = z1 || z2 || z3;
     const T w1 = zany ? (z1 ? T(0.1) : T(0)) : T(0.1) * (q23 * q23);
     const T w2 = zany ? (z2 ? T(0.6) : T(0)) : T(0.6) * (q13 * q13);
     const T w3 = zany ? (z3 ? T(0.3) : T(0)) : T(0.3) * (q12 * q12);
@@ -230,19 +241,20 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     T* Fo = static_cast<T*>(A.Fout) + I.offF + (size_t)dist * NR * NV;
     const T* Cd = A.C ? static_cast<const T*>(A.C) + I.offF + (size_t)dist * NR * NV : nullptr;
     const double* Wm = tab + I.tWm;
+    const T weps = T(I.weno_eps);
     const bool near_in = rlen > 0 && rs0 < 3, near_out = rlen > 0 && rs0 + rlen > NR - 3;
     {
         double ain = 0.0, aout = 0.0;
         if (act && near_in && p1 < T(0)) {
             const T F1 = Fp[k], F2 = Fp[NV + k], F3 = Fp[2 * NV + k];
             const T g0 = T(3) * F1 - T(3) * F2 + F3, gm1 = T(6) * F1 - T(8) * F2 + T(3) * F3;
-            ain = (double)p1 * Wm[k] * (double)weno5<T>(F3, F2, F1, g0, gm1);
+            ain = (double)p1 * Wm[k] * (double)weno5<T>(F3, F2, F1, g0, gm1, weps);
         }
         if (act && near_out && p1 > T(0)) {
             const T G1 = Fp[(size_t)(NR - 1) * NV + k], G2 = Fp[(size_t)(NR - 2) * NV + k],
                     G3 = Fp[(size_t)(NR - 3) * NV + k];
             const T g0 = T(3) * G1 - T(3) * G2 + G3, gp1 = T(6) * G1 - T(8) * G2 + T(3) * G3;
-            aout = (double)p1 * Wm[k] * (double)weno5<T>(G3, G2, G1, g0, gp1);
+            aout = (double)p1 * Wm[k] * (double)weno5<T>(G3, G2, G1, g0, gp1, weps);
         }
         ain = wave_sum(ain);
         aout = wave_sum(aout);
@@ -286,7 +298,7 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     if (act) {
         w0v = cell(rs0 - 3); w1v = cell(rs0 - 2); w2v = cell(rs0 - 1);
         w3v = cell(rs0);     w4v = cell(rs0 + 1); w5v = cell(rs0 + 2);
-        fl = weno_face<T>(pos, w0v, w1v, w2v, w3v, w4v, w5v);
+        fl = weno_face<T>(pos, w0v, w1v, w2v, w3v, w4v, w5v, weps);
     }
 
     const double dt = A.l_only ? 1.0 : I.dt;
@@ -352,7 +364,7 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
         if (c > 0) finish(c - 1, buf ^ 1);
         double m0 = 0, m1 = 0, m2 = 0, m3 = 0, rd = 0, rn = 0;
         if (cv) {
-            const T fr = weno_face<T>(pos, w0v, w1v, w2v, w3v, w4v, w5v);
+            const T fr = weno_face<T>(pos, w0v, w1v, w2v, w3v, w4v, w5v, weps);
             const T Rl = T(g_cur[0]), Rr = T(g_cur[1]);
             const T dchi = T(g_cur[2]), gam = T(g_cur[3]);
             const T adv = p1 * (Rr * fr - Rl * fl) / dchi;
@@ -562,6 +574,82 @@ __global__ __launch_bounds__(256) void couette_rescale(const InstDesc* insts, co
     }
 }
 
+// Warm-start fields per cell from the surrogate outputs Y[cell][4] = ((n-1) S, u^R S,
+// u^phi/u_w, (T-1) S), S = 10; one block per instance.  par[inst] = (u_w, use): with use,
+// n is rescaled so that sum_s dchi_s n_s equals the cold start's sum_s dchi_s (n = 1)
+// -- the particle number the dynamics conserve (Eq. Ntot_def) -- and u^R = 0; without,
+// the cold start n = 1, u = 0, T = T_in.  Writes prof[cell][4] = (n, u^R, u^phi, T).
+__global__ __launch_bounds__(256) void couette_warm_profile(const InstDesc* insts, const double* tab_all,
+                                                            const float* Y, const double* par, double* prof) {
+    __shared__ double sh[2][256];
+    const int inst = blockIdx.x, t = threadIdx.x;
+    const InstDesc& I = insts[inst];
+    const double* dchi = tab_all + I.offT + I.tdchi;
+    const double uw = par[2 * inst], use = par[2 * inst + 1];
+    const float* y = Y + (size_t)I.offC * 4;
+    double* pr = prof + (size_t)I.offC * 4;
+    if (use == 0.0) {
+        for (int s = t; s < I.NR; s += 256) {
+            pr[4 * s] = 1.0; pr[4 * s + 1] = 0.0; pr[4 * s + 2] = 0.0; pr[4 * s + 3] = I.T_in;
+        }
+        return;
+    }
+    double a = 0.0, c = 0.0;
+    for (int s = t; s < I.NR; s += 256) {
+        a += dchi[s] * (1.0 + (double)y[4 * s] / 10.0);
+        c += dchi[s];
+    }
+    sh[0][t] = a;
+    sh[1][t] = c;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) { sh[0][t] += sh[0][t + w]; sh[1][t] += sh[1][t + w]; }
+        __syncthreads();
+    }
+    const double scale = sh[1][0] / sh[0][0];
+    for (int s = t; s < I.NR; s += 256) {
+        pr[4 * s] = (1.0 + (double)y[4 * s] / 10.0) * scale;
+        pr[4 * s + 1] = 0.0;
+        pr[4 * s + 2] = (double)y[4 * s + 2] * uw;
+        pr[4 * s + 3] = 1.0 + (double)y[4 * s + 3] / 10.0;
+    }
+}
+
+// FP64 state at local equilibrium f' = n g1 g2, f'' = T f' (Sec. IV.D, Eq. feq_red) of
+// the per-cell fields prof[cell][4] = (n, u^R, u^phi, T); one wavefront per work item.
+__global__ __launch_bounds__(256) void couette_init_profile(const InstDesc* insts, const WorkItem* work,
+                                                            const double* tab_all, const double* prof, double* F) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const WorkItem* wp = work + (size_t)blockIdx.x * kWavesPerBlock + wave;
+    const int inst = __builtin_amdgcn_readfirstlane(wp->inst);
+    const int dist = __builtin_amdgcn_readfirstlane(wp->dist);
+    const int s0 = __builtin_amdgcn_readfirstlane(wp->s0);
+    const int ncell = __builtin_amdgcn_readfirstlane(wp->ncell);
+    if (ncell <= 0) return;
+    const InstDesc& I = insts[inst];
+    const double* tab = tab_all + I.offT;
+    const int NV = I.NV, Q2 = I.Q2, N1 = I.N1, N2 = I.N2;
+    double c1[2 * (kMaxN + 1)], c2[2 * (kMaxN + 1)];
+    for (int c = 0; c < ncell; ++c) {
+        const int s = s0 + c;
+        const double* pr = prof + (size_t)(I.offC + s) * 4;
+        const double n = pr[0], T_ = pr[3];
+        axis_coef(I.kind1, N1, pr[1], T_, tab + I.tC1, tab + I.tisf1, c1, c1 + (N1 + 1));
+        axis_coef(I.kind2, N2, pr[2], T_, tab + I.tC2, tab + I.tisf2, c2, c2 + (N2 + 1));
+        double* out = F + I.offF + ((size_t)dist * I.NR + s) * NV;
+        for (int k = lane; k < NV; k += kWave) {
+            const int i = k / Q2, j = k - i * Q2;
+            const double* e1 = c1 + ((I.kind1 == 1 && i >= I.Qh1) ? N1 + 1 : 0);
+            const double* e2 = c2 + ((I.kind2 == 1 && j >= I.Qh2) ? N2 + 1 : 0);
+            double g1 = 0.0, g2 = 0.0;
+            for (int l = 0; l <= N1; ++l) g1 += tab[I.tB1 + i * (N1 + 1) + l] * e1[l];
+            for (int l = 0; l <= N2; ++l) g2 += tab[I.tB2 + j * (N2 + 1) + l] * e2[l];
+            const double v = n * g1 * g2;
+            out[k] = dist ? T_ * v : v;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host launchers
 template <typename T>
 static hipError_t launch_stage_t(int nblocks, hipStream_t st, const StageArgs& A) {
@@ -616,6 +704,19 @@ hipError_t launch_reduce(int ninst, hipStream_t st, const InstDesc* insts, const
                          const double* msum, double* resid, double* mass, int want_resid) {
     hipLaunchKernelGGL(couette_reduce_f64, dim3(ninst), dim3(256), 0, st, insts, tab, rpart, msum, resid, mass,
                        want_resid);
+    return hipGetLastError();
+}
+
+hipError_t launch_warm_profile(int ninst, hipStream_t st, const InstDesc* insts, const double* tab, const float* Y,
+                               const double* par, double* prof) {
+    hipLaunchKernelGGL(couette_warm_profile, dim3(ninst), dim3(256), 0, st, insts, tab, Y, par, prof);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_profile(int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
+                               const double* tab, const double* prof, double* F) {
+    hipLaunchKernelGGL(couette_init_profile, dim3(nblocks), dim3(kWave * kWavesPerBlock), 0, st, insts, work, tab,
+                       prof, F);
     return hipGetLastError();
 }
 

@@ -39,7 +39,7 @@ struct InstDesc {
     int NR, Q1, Q2, NV;
     int kind1, kind2, N1, N2;
     int Qh1, Qh2, tau_model, vpt;
-    double Kn, dt, T_in, T_out, den_in, den_out;
+    double Kn, dt, T_in, T_out, den_in, den_out, weno_eps;
     long long offF, offC, offT;
     // table offsets relative to offT
     int tp1, tp2, tK1, tKt2, tB1, tB2, tC1, tC2, tisf1, tisf2;

@@ -38,7 +38,7 @@ class _CouetteDesc(ctypes.Structure):
                 ("A", ctypes.c_double), ("delta", ctypes.c_double), ("ax1", _Axis), ("ax2", _Axis),
                 ("Kn", ctypes.c_double), ("tau_model", ctypes.c_int), ("dt", ctypes.c_double),
                 ("cfl", ctypes.c_double), ("u_in", ctypes.c_double), ("T_in", ctypes.c_double),
-                ("u_out", ctypes.c_double), ("T_out", ctypes.c_double)]
+                ("u_out", ctypes.c_double), ("T_out", ctypes.c_double), ("weno_eps", ctypes.c_double)]
 
 
 @dataclass
@@ -60,14 +60,16 @@ class CouetteDesc:
     T_out: float = 1.0
     A: float = 0.0
     delta: float = 0.5
+    weno_eps: float = 0.0
 
     def _c(self) -> _CouetteDesc:
         return _CouetteDesc(self.R_in, self.R_out, self.N_R, self.A, self.delta, _Axis(*self.ax1),
                             _Axis(*self.ax2), self.Kn, self.tau_model, self.dt, self.cfl, self.u_in,
-                            self.T_in, self.u_out, self.T_out)
+                            self.T_in, self.u_out, self.T_out, self.weno_eps)
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
 _SIGS = {
     "vlb_batch_create_couette": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(_CouetteDesc),
                                  ctypes.c_int, ctypes.c_void_p, ctypes.c_int],
@@ -99,6 +101,18 @@ _SIGS = {
     "vlb_batch_autotune": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _dp],
     "vlb_timing_query": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                          ctypes.POINTER(ctypes.c_long), _dp, _dp],
+    "vlb_mlp_param_count": [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+    "vlb_mlp_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int, _fp, ctypes.c_void_p],
+    "vlb_mlp_destroy": [ctypes.c_void_p],
+    "vlb_mlp_get_params": [ctypes.c_void_p, _fp, ctypes.c_size_t],
+    "vlb_mlp_set_params": [ctypes.c_void_p, _fp, ctypes.c_size_t],
+    "vlb_mlp_forward": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long, ctypes.c_void_p, ctypes.c_int],
+    "vlb_mlp_loss_grad": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long, _fp, _fp],
+    "vlb_mlp_adam_step": [ctypes.c_void_p, _fp, ctypes.c_float],
+    "vlb_mlp_train": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long,
+                      ctypes.POINTER(ctypes.c_int), ctypes.c_long, ctypes.c_int, ctypes.c_float, _fp],
+    "vlb_batch_surrogate_samples": [ctypes.c_void_p, _fp, _fp, ctypes.c_size_t],
+    "vlb_batch_warm_start": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
     "vlb_status_string": [ctypes.c_int],
     "vlb_last_error": [],
 }
@@ -287,16 +301,16 @@ class Batch:
         _check(load_library().vlb_timing_enable(self._h, 1 if on else 0), "vlb_timing_enable")
 
     def timing_query(self):
-        """List of dicts per stage-kernel instantiation: vpt (negative for FP32), launches,
+        """List of dicts per stage-kernel instantiation: bits (64 FP64, 32 FP32), launches,
         total_ms, alg_bytes."""
         G = 64
         ng = ctypes.c_int()
-        vpt = (ctypes.c_int * G)()
+        bits = (ctypes.c_int * G)()
         launches = (ctypes.c_long * G)()
         ms, by = np.zeros(G), np.zeros(G)
-        _check(load_library().vlb_timing_query(self._h, G, ctypes.byref(ng), vpt, launches, _ptr(ms), _ptr(by)),
+        _check(load_library().vlb_timing_query(self._h, G, ctypes.byref(ng), bits, launches, _ptr(ms), _ptr(by)),
                "vlb_timing_query")
-        return [dict(vpt=vpt[i], launches=launches[i], total_ms=ms[i], alg_bytes=by[i]) for i in range(ng.value)]
+        return [dict(bits=bits[i], launches=launches[i], total_ms=ms[i], alg_bytes=by[i]) for i in range(ng.value)]
 
     def velocities(self, b: int):
         i = self.info[b]
@@ -304,3 +318,118 @@ class Batch:
         _check(load_library().vlb_batch_velocities(self._h, b, _ptr(p1), _ptr(w1), _ptr(p2), _ptr(w2)),
                "vlb_batch_velocities")
         return p1, w1, p2, w2
+
+    # ------------------------------------------------------------------ warm start
+    @property
+    def ncells(self) -> int:
+        return sum(i["N_R"] for i in self.info)
+
+    def surrogate_samples(self):
+        """(X, T) float32 arrays [cells][4]: surrogate inputs and targets of the current state."""
+        X = np.empty((self.ncells, 4), dtype=np.float32)
+        T = np.empty((self.ncells, 4), dtype=np.float32)
+        _check(load_library().vlb_batch_surrogate_samples(self._h, _fptr(X), _fptr(T), self.ncells),
+               "vlb_batch_surrogate_samples")
+        return X, T
+
+    def warm_start(self, mlp: "Mlp", probe_steps: int = 1000) -> np.ndarray:
+        """Initial states from the surrogate (cold start where the judge rejects it);
+        returns the per-instance 0/1 array of warm starts kept."""
+        used = (ctypes.c_int * self.B)()
+        _check(load_library().vlb_batch_warm_start(self._h, mlp._h, probe_steps, used), "vlb_batch_warm_start")
+        return np.array(list(used), dtype=np.int32)
+
+
+def _fptr(a: np.ndarray):
+    assert a.dtype == np.float32 and a.flags.c_contiguous
+    return a.ctypes.data_as(_fp)
+
+
+def mlp_param_count(width: int = 128, depth: int = 3) -> int:
+    n = ctypes.c_size_t()
+    _check(load_library().vlb_mlp_param_count(width, depth, ctypes.byref(n)), "vlb_mlp_param_count")
+    return n.value
+
+
+class Mlp:
+    """The warm-start surrogate network on the GPU (parameters, Adam state, buffers in
+    library-owned device memory; work on torch's current stream)."""
+
+    def __init__(self, params: np.ndarray, width: int = 128, depth: int = 3, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the surrogate runs on the GPU only")
+        self._torch = torch
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.width, self.depth = width, depth
+        self.n_params = mlp_param_count(width, depth)
+        p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        if p.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {p.size}")
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(load_library().vlb_mlp_create(ctypes.byref(h), width, depth, _fptr(p),
+                                             ctypes.c_void_p(self.stream.cuda_stream)), "vlb_mlp_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().vlb_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(load_library().vlb_mlp_get_params(self._h, _fptr(out), out.size), "vlb_mlp_get_params")
+        return out
+
+    def set_params(self, params: np.ndarray):
+        p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        _check(load_library().vlb_mlp_set_params(self._h, _fptr(p), p.size), "vlb_mlp_set_params")
+
+    def _dev(self, a):
+        """float32 [n][4] device tensor of a (host array or device tensor)."""
+        t = self._torch
+        if isinstance(a, t.Tensor):
+            a = a.to(device=self.device, dtype=t.float32).contiguous()
+        else:
+            a = t.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(self.device)
+        if a.dim() != 2 or a.shape[1] != 4:
+            raise ValueError("expected an [n][4] array")
+        return a
+
+    def forward(self, X, bf16: bool = False) -> np.ndarray:
+        Xd = self._dev(X)
+        Y = self._torch.empty_like(Xd)
+        _check(load_library().vlb_mlp_forward(self._h, ctypes.c_void_p(Xd.data_ptr()), Xd.shape[0],
+                                              ctypes.c_void_p(Y.data_ptr()), 1 if bf16 else 0), "vlb_mlp_forward")
+        self.stream.synchronize()
+        return Y.cpu().numpy()
+
+    def loss_grad(self, X, T):
+        Xd, Td = self._dev(X), self._dev(T)
+        loss = ctypes.c_float()
+        g = np.empty(self.n_params, dtype=np.float32)
+        _check(load_library().vlb_mlp_loss_grad(self._h, ctypes.c_void_p(Xd.data_ptr()), ctypes.c_void_p(Td.data_ptr()),
+                                                Xd.shape[0], ctypes.byref(loss), _fptr(g)), "vlb_mlp_loss_grad")
+        return loss.value, g
+
+    def adam_step(self, grad=None, lr: float = 1e-3):
+        gp = _fptr(np.ascontiguousarray(grad, dtype=np.float32)) if grad is not None else None
+        _check(load_library().vlb_mlp_adam_step(self._h, gp, lr), "vlb_mlp_adam_step")
+
+    def train(self, X, T, order: np.ndarray, batch: int = 512, lr: float = 1e-3) -> float:
+        """Adam over the mini-batches of rows `order` of the samples (X, T): one call per
+        epoch with a fresh permutation.  Returns the mean mini-batch loss."""
+        Xd, Td = self._dev(X), self._dev(T)
+        o = np.ascontiguousarray(order, dtype=np.int32)
+        loss = ctypes.c_float()
+        _check(load_library().vlb_mlp_train(self._h, ctypes.c_void_p(Xd.data_ptr()), ctypes.c_void_p(Td.data_ptr()),
+                                            Xd.shape[0], o.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), o.size,
+                                            batch, lr, ctypes.byref(loss)), "vlb_mlp_train")
+        return loss.value

@@ -60,3 +60,43 @@ def site_velocities(descs) -> int:
         n2 = d.ax2[1] * (2 if d.ax2[0] == 1 else 1)
         tot += d.N_R * n1 * n2
     return tot
+
+
+# ---------------------------------------------------------------- learned warm start
+# Training and held-out instances come from the sweep generator with their own seeds
+# (1 and 2); the surrogate's inputs are position-normalised, so the training solves may
+# use a coarser grid than the instances they warm-start.
+SURROGATE_TRAIN_SEED, SURROGATE_HELDOUT_SEED = 1, 2
+
+
+def surrogate_descs(B: int, seed: int, N_R: int | None = None, Kn_min: float = 0.0, Kn_max: float = np.inf):
+    """Sweep instances of the given seed; N_R overrides the drawn grid size; instances
+    with Kn outside [Kn_min, Kn_max] are skipped (drawn in order until B are kept)."""
+    out, draw = [], max(B, 16)
+    while len(out) < B:
+        out = [d for d in couette_sweep(draw, seed) if Kn_min <= d.Kn <= Kn_max][:B]
+        draw *= 2
+    if N_R is not None:
+        for d in out:
+            d.N_R = int(N_R)
+    return out
+
+
+def mlp_init_params(width: int = 128, depth: int = 3, seed: int = 0, d_in: int = 4, d_out: int = 4):
+    """Initial surrogate parameters, layer by layer W[fan_in][fan_out] then b[fan_out]:
+    W ~ U(-a, a), a = sqrt(6 / (fan_in + fan_out)) (Glorot & Bengio 2010), b = 0."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dims = [d_in] + [width] * depth + [d_out]
+    parts = []
+    for a, b in zip(dims[:-1], dims[1:]):
+        lim = np.sqrt(6.0 / (a + b))
+        parts.append(rng.uniform(-lim, lim, a * b))
+        parts.append(np.zeros(b))
+    return np.concatenate(parts)
+
+
+def epoch_orders(n: int, epochs: int, seed: int = 0):
+    """One random permutation of range(n) per epoch."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    for _ in range(epochs):
+        yield rng.permutation(n).astype(np.int32)

@@ -98,3 +98,21 @@ def test_fp32_phase_profile_error_is_stated():
     _say(f"FP32 floor residual {r:.2e}; profile errors {errs}")
     assert max(errs.values()) < 5e-3
     b.close()
+
+
+def test_fp32_regularised_operator_matches_oracle():
+    """The relative regularisation is scale-invariant, so the FP32 path on scaled
+    populations takes the same weights as the FP64 oracle."""
+    from paper_1708_05944_amd import VLB_MIXED, Batch, CouetteDesc
+    case = dict(N_R=45, ax1=(1, 11, 4), ax2=(0, 13, 4), Kn=0.45, u_in=0.43, R_out=1.42, weno_eps=1e-6)
+    ora = CouetteOracle(**case)
+    b = Batch([CouetteDesc(**case)], precision=VLB_MIXED)
+    F = _perturbed(ora, 7)
+    b.set_state(F.ravel())
+    b.step(0)
+    L = b.instance_view(b.apply_L(), 0)
+    Lw, _ = ora.L(F)
+    err = max(np.abs(L[d] - Lw[d]).max() / np.abs(Lw[d]).max() for d in range(2))
+    _say(f"fp32 regularised operator rel err {err:.2e}")
+    assert err <= 2e-6
+    b.close()
