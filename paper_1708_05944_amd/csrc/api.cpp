@@ -449,7 +449,8 @@ void build_blocks(vlb_batch* b, int tile) {
         const int nruns = (D.NR + tile - 1) / tile;
         const int per = (D.NR + nruns - 1) / nruns;
         const int nvpad = (D.NV + kWave - 1) / kWave * kWave;
-        const int rmax = std::max(1, std::min({kMaxRuns, kStageThreads / nvpad, kMaxRuns * kTileCells / per}));
+        const int rmax = std::max(1, std::min({kMaxRuns, kStageThreads / nvpad, kMaxRuns * kTileCells / per,
+                                               kRowElems / (2 * row_slot(D.Q1, D.Q2))}));
         for (int dist = 0; dist < 2; ++dist)
             for (int r0 = 0; r0 < nruns; r0 += rmax)
                 b->blocks.push_back({i, dist, r0 * per, std::min(rmax, nruns - r0), per, nvpad, 0, 0});
@@ -698,10 +699,14 @@ vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_de
             }
             while (made % kWavesPerBlock) { b->work.push_back({i, dist, 0, 0}); ++made; }
         }
-        g.kmax = std::max(g.kmax, D.Q1 * D.Q1 + D.Q2 * D.Q2);
+        g.kmax = std::max(g.kmax, D.Q1 * pad4(D.Q1) + D.Q2 * pad4(D.Q2));
+        if (2 * row_slot(D.Q1, D.Q2) > kRowElems) {
+            delete b;
+            return fail(VLB_EINVAL, "instance %d: velocity set too large for the stage kernel's LDS rows", i);
+        }
         g.pops += 2.0 * D.NR * D.NV;
     }
-    g.kmax = (g.kmax + 1) & ~1;
+    g.kmax = pad4(g.kmax);
     if (stage_lds(g.kmax, sizeof(double)) > 160 * 1024) {
         delete b;
         return fail(VLB_EINVAL, "velocity sets too large for LDS (%zu bytes)", stage_lds(g.kmax, sizeof(double)));

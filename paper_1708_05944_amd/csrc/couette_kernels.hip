@@ -152,19 +152,54 @@ __device__ __forceinline__ double tau_of(int model, double Kn, double n, double 
     return Kn / n;
 }
 
-// LDS layout of a stage block (bytes): kernel tables | two cell-row buffers | two
-// equilibrium-factor buffers | equilibrium coefficients of every (run, cell) | moment
-// and residual partials per wavefront (two buffers) | wall-flux partials per wavefront.
+__device__ __forceinline__ int pad4_d(int x) { return (x + 3) & ~3; }
+__device__ __forceinline__ int row_slot_d(int Q1, int Q2) {
+    const int a = Q1 * pad4_d(Q2), b = Q2 * pad4_d(Q1);
+    return pad4_d(a > b ? a : b);
+}
+
+// sum_i a[i] b[i], i < n (n a multiple of 4, both pointers 16-byte aligned LDS), in
+// index order with 16-byte vector reads
+template <typename T>
+__device__ __forceinline__ T dot_lds(const T* a, const T* b, int n);
+template <>
+__device__ __forceinline__ float dot_lds<float>(const float* a, const float* b, int n) {
+    float acc = 0.f;
+    for (int i = 0; i < n; i += 4) {
+        const float4 x = *reinterpret_cast<const float4*>(a + i), y = *reinterpret_cast<const float4*>(b + i);
+        acc += x.x * y.x;
+        acc += x.y * y.y;
+        acc += x.z * y.z;
+        acc += x.w * y.w;
+    }
+    return acc;
+}
+template <>
+__device__ __forceinline__ double dot_lds<double>(const double* a, const double* b, int n) {
+    double acc = 0.0;
+    for (int i = 0; i < n; i += 2) {
+        const double2 x = *reinterpret_cast<const double2*>(a + i), y = *reinterpret_cast<const double2*>(b + i);
+        acc += x.x * y.x;
+        acc += x.y * y.y;
+    }
+    return acc;
+}
+
+// LDS layout of a stage block (bytes): kernel tables | two cell-row buffers (row-major
+// and transposed copies per run) | two equilibrium-factor buffers | per (run, cell):
+// n, T, 1/tau, equilibrium coefficients and geometry | equilibrium bases | moment and
+// residual partials per wavefront (two buffers) | wall-flux partials per wavefront.
 template <typename T>
 struct StageLds {
-    size_t ks, rows, gbuf, eqc, mpart, nwpart, total;
+    size_t ks, rows, gbuf, eqc, btab, mpart, nwpart, total;
     __host__ __device__ StageLds(int kmax) {
         auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
         ks = 0;
         rows = al(ks + (size_t)kmax * sizeof(T));
-        gbuf = al(rows + 2 * (size_t)kStageThreads * sizeof(T));
+        gbuf = al(rows + 2 * (size_t)kRowElems * sizeof(T));
         eqc = al(gbuf + 2 * (size_t)kMaxRuns * kWave * sizeof(T));
-        mpart = al(eqc + (size_t)kMaxRuns * kTileCells * kEqStride * sizeof(double));
+        btab = al(eqc + (size_t)kMaxRuns * kTileCells * kEqStride * sizeof(double));
+        mpart = al(btab + (size_t)kWave * (kMaxN + 1) * sizeof(double));
         nwpart = al(mpart + 2 * (size_t)(kStageThreads / kWave) * 8 * sizeof(double));
         total = al(nwpart + (size_t)(kStageThreads / kWave) * 2 * sizeof(double));
     }
@@ -191,6 +226,7 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     T* rows = reinterpret_cast<T*>(smem + lay.rows);
     T* gbuf = reinterpret_cast<T*>(smem + lay.gbuf);
     double* eqc = reinterpret_cast<double*>(smem + lay.eqc);
+    double* btab = reinterpret_cast<double*>(smem + lay.btab);
     double* mpart = reinterpret_cast<double*>(smem + lay.mpart);
     double* nwpart = reinterpret_cast<double*>(smem + lay.nwpart);
 
@@ -203,9 +239,23 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     const int vi = kk / Q2, vj = kk - vi * Q2;
     const T p1 = T(tab[I.tp1 + vi]), p2 = T(tab[I.tp2 + vj]);
 
-    // ---- prologue: kernels into LDS; equilibrium coefficients of every (run, cell)
-    const int n1 = Q1 * Q1, n2 = Q2 * Q2;
-    for (int x = t; x < n1 + n2; x += kStageThreads) Ks[x] = T(x < n1 ? tab[I.tK1 + x] : tab[I.tKt2 + x - n1]);
+    // ---- prologue: kernels into LDS (rows padded with zeros to Q1p / Q2p entries), both
+    // row buffers cleared (their padding stays zero); equilibrium coefficients of every
+    // (run, cell)
+    const int Q1p = pad4_d(Q1), Q2p = pad4_d(Q2), S = row_slot_d(Q1, Q2);
+    const int n1 = Q1 * Q1p, n2 = Q2 * Q2p;
+    for (int x = t; x < n1 + n2; x += kStageThreads) {
+        T v = T(0);
+        if (x < n1) {
+            const int a = x / Q1p, c = x - a * Q1p;
+            if (c < Q1) v = T(tab[I.tK1 + a * Q1 + c]);
+        } else {
+            const int a = (x - n1) / Q2p, c = (x - n1) - a * Q2p;
+            if (c < Q2) v = T(tab[I.tKt2 + a * Q2 + c]);
+        }
+        Ks[x] = v;
+    }
+    for (int x = t; x < 2 * kRowElems; x += kStageThreads) rows[x] = T(0);
     const int N1 = I.N1, N2 = I.N2;
     for (int x = t; x < R * TC; x += kStageThreads) {
         const int rr = x / TC, cc = x - rr * TC, s = s0 + rr * TC + cc;
@@ -219,18 +269,26 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
         e[2] = 1.0 / tau_of(I.tau_model, I.Kn, n, T_);
         axis_coef(I.kind1, N1, u1, T_, tab + I.tC1, tab + I.tisf1, e + 3, e + 3 + (N1 + 1));
         axis_coef(I.kind2, N2, u2, T_, tab + I.tC2, tab + I.tisf2, e + 3 + 2 * (N1 + 1), e + 3 + 2 * (N1 + 1) + (N2 + 1));
+        e[kEqGeo] = tab[I.tRf + s];
+        e[kEqGeo + 1] = tab[I.tRf + s + 1];
+        e[kEqGeo + 2] = tab[I.tdchi + s];
+        e[kEqGeo + 3] = tab[I.tGam + s];
     }
+    // equilibrium bases of both axes: rows of Q1 x (N1+1) then Q2 x (N2+1)
+    const int nbt = Q1 * (N1 + 1) + Q2 * (N2 + 1);
+    for (int x = t; x < nbt; x += kStageThreads)
+        btab[x] = x < Q1 * (N1 + 1) ? tab[I.tB1 + x] : tab[I.tB2 + x - Q1 * (N1 + 1)];
     // node role for the per-cell factor table: g1 (k < Q1) or g2 (Q1 <= k < Q1+Q2)
     const double* brow = nullptr;
     int coff = -1, nb = 0;
     if (rlen > 0 && k < Q1) {
         nb = N1 + 1;
-        brow = tab + I.tB1 + k * nb;
+        brow = btab + k * nb;
         coff = 3 + ((I.kind1 == 1 && k >= I.Qh1) ? nb : 0);
     } else if (rlen > 0 && k < Q1 + Q2) {
         const int j = k - Q1;
         nb = N2 + 1;
-        brow = tab + I.tB2 + j * nb;
+        brow = btab + Q1 * (N1 + 1) + j * nb;
         coff = 3 + 2 * (N1 + 1) + ((I.kind2 == 1 && j >= I.Qh2) ? nb : 0);
     }
 
@@ -305,8 +363,8 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     const T cdt = T(A.cc * dt), ca = T(A.ca), cb = T(A.cb);
     const double* resW = tab + I.tresW;
     const T* Kt = Ks + n1;
-    const T* K1row = Ks + vi * Q1;
-    const T* Ktrow = Kt + vj * Q2;
+    const T* K1row = Ks + vi * Q1p;
+    const T* Ktrow = Kt + vj * Q2p;
     const double pw1 = (double)p1, pw2 = (double)p2;
     const double wmk = Wm[kk], rwk = resW[kk];
 
@@ -323,37 +381,45 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
             if (dist == 0) A.msum_out[(size_t)(I.offC + s) * 5 + k] = m;
             else if (k == 0) A.msum_out[(size_t)(I.offC + s) * 5 + 4] = m;
         } else if (A.rpart) {
-            A.rpart[((size_t)(I.offC + s) * 2 + dist) * 2 + (k - 4)] = tab[I.tdchi + s] * m;
+            A.rpart[((size_t)(I.offC + s) * 2 + dist) * 2 + (k - 4)] = eqc[(size_t)(r * TC + c) * kEqStride + kEqGeo + 2] * m;
         }
     };
 
-    // values of the next cell fetched one iteration ahead (F_n and the cell geometry)
+    // loads issued kAhead cells before their use (the window's leading cell and F_n), so
+    // that each wavefront keeps 2 kAhead loads in flight; the cell geometry one ahead
     const bool need_fn = !A.l_only && ca != T(0);
-    T fn_next = (act && need_fn) ? Fnd[(size_t)rs0 * NV + k] : T(0);
-    double g_next[4] = {0, 0, 0, 0};
-    if (rlen > 0) {
-        g_next[0] = tab[I.tRf + rs0]; g_next[1] = tab[I.tRf + rs0 + 1];
-        g_next[2] = tab[I.tdchi + rs0]; g_next[3] = tab[I.tGam + rs0];
+    constexpr int kAhead = sizeof(T) == 4 ? 4 : 2;
+    T pw[kAhead], fnr[kAhead];
+#pragma unroll
+    for (int q = 0; q < kAhead; ++q) {
+        const int x = rs0 + 3 + q;
+        pw[q] = (act && q < rlen && x < NR) ? Fd[(size_t)x * NV + k] : T(0);
+        fnr[q] = (act && need_fn && q < rlen) ? Fnd[(size_t)(rs0 + q) * NV + k] : T(0);
     }
+
     for (int c = 0; c < TC; ++c) {
         const int buf = c & 1;
         const bool cv = act && c < rlen;
         const int s = rs0 + c;
-        const T fn_cur = fn_next;
-        const double g_cur[4] = {g_next[0], g_next[1], g_next[2], g_next[3]};
-        if (c + 1 < rlen) {
-            if (act && need_fn) fn_next = Fnd[(size_t)(s + 1) * NV + k];
-            g_next[0] = g_cur[1]; g_next[1] = tab[I.tRf + s + 2];
-            g_next[2] = tab[I.tdchi + s + 1]; g_next[3] = tab[I.tGam + s + 1];
+        const T fn_cur = fnr[0];
+        const T lead = pw[0];
+        if (cv) {
+#pragma unroll
+            for (int q = 0; q < kAhead - 1; ++q) { pw[q] = pw[q + 1]; fnr[q] = fnr[q + 1]; }
+            const int x = s + 3 + kAhead;
+            pw[kAhead - 1] = (c + kAhead < rlen && x < NR) ? Fd[(size_t)x * NV + k] : T(0);
+            fnr[kAhead - 1] = (need_fn && c + kAhead < rlen) ? Fnd[(size_t)(s + kAhead) * NV + k] : T(0);
         }
-        T* row = rows + (size_t)buf * kStageThreads + (size_t)r * nvpad;
+        T* row = rows + (size_t)buf * kRowElems + (size_t)r * 2 * S;
+        T* rowT = row + S;
         T* gb = gbuf + (size_t)buf * kMaxRuns * kWave + (size_t)r * kWave;
         const double* e = eqc + (size_t)(r * TC + c) * kEqStride;
         if (cv) {
             w0v = w1v; w1v = w2v; w2v = w3v; w3v = w4v; w4v = w5v;
             // s is wavefront-uniform: interior cells take a plain load
-            w5v = s + 3 < NR ? Fd[(size_t)(s + 3) * NV + k] : cell(s + 3);
-            row[k] = w2v;
+            w5v = s + 3 < NR ? lead : cell(s + 3);
+            row[vi * Q2p + vj] = w2v;
+            rowT[vj * Q1p + vi] = w2v;
         }
         if (coff >= 0 && c < rlen) {
             double g = 0.0;
@@ -365,12 +431,12 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
         double m0 = 0, m1 = 0, m2 = 0, m3 = 0, rd = 0, rn = 0;
         if (cv) {
             const T fr = weno_face<T>(pos, w0v, w1v, w2v, w3v, w4v, w5v, weps);
-            const T Rl = T(g_cur[0]), Rr = T(g_cur[1]);
-            const T dchi = T(g_cur[2]), gam = T(g_cur[3]);
+            const T Rl = T(e[kEqGeo]), Rr = T(e[kEqGeo + 1]);
+            const T dchi = T(e[kEqGeo + 2]), gam = T(e[kEqGeo + 3]);
             const T adv = p1 * (Rr * fr - Rl * fl) / dchi;
             T kf = T(0), ktf = T(0);
-            for (int ip = 0; ip < Q1; ++ip) kf += K1row[ip] * row[ip * Q2 + vj];
-            for (int jp = 0; jp < Q2; ++jp) ktf += Ktrow[jp] * row[vi * Q2 + jp];
+            kf = dot_lds<T>(K1row, rowT + vj * Q1p, Q1p);
+            ktf = dot_lds<T>(Ktrow, row + vi * Q2p, Q2p);
             const T force = gam * (p2 * p2 * kf - p1 * ktf);
             T fe = T(e[0]) * gb[vi] * gb[Q1 + vj];
             if (dist) fe = T(e[1]) * fe;
