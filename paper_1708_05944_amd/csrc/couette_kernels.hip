@@ -31,8 +31,10 @@ namespace vlb {
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double v) {
     const long long x = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, 0xF, 0xF, false);
+    // every lane's source lane exists for the permutations used here (quad permutes and
+    // mirrors within a row), so no fallback value is needed
+    const int lo = __builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, 0xF, 0xF, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -53,6 +55,25 @@ __device__ __forceinline__ double wave_sum(double v) {
     v += dpp_mov<0x140>(v);   // row_mirror
     return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
+
+// Sum over each 16-lane row of a wavefront (the row total in every lane of the row), in
+// a fixed order: quad butterflies and the half-row and row mirrors by DPP.
+__device__ __forceinline__ double row_sum(double v) {
+    v += dpp_mov<0xB1>(v);
+    v += dpp_mov<0x4E>(v);
+    v += dpp_mov<0x141>(v);
+    v += dpp_mov<0x140>(v);
+    return v;
+}
+
+// 1/x: the hardware reciprocal in FP32 (about 1 ulp, the FP32 path's tolerance is far
+// wider); a correctly rounded division in FP64.
+template <typename T>
+__device__ __forceinline__ T recip(T x);
+template <>
+__device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <>
+__device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
 
 // Flux at the face between c and d, upwinded from c (a, b, c, d, e in upwind order).
 template <typename T>
@@ -101,13 +122,13 @@ __device__ __forceinline__ T weno5(T a, T b, T c, T d, T e, T eps) {
     // when every indicator vanishes and is discarded by the select).
     T m = s1 > s2 ? s1 : s2;
     m = m > s3 ? m : s3;
-    const T inv = T(1) / m;
+    const T inv = recip<T>(m);
     const T r1 = s1 * inv, r2 = s2 * inv, r3 = s3 * inv;
     const T q23 = r2 * r3, q13 = r1 * r3, q12 = r1 * r2;
     const T w1 = zany ? (z1 ? T(0.1) : T(0)) : T(0.1) * (q23 * q23);
     const T w2 = zany ? (z2 ? T(0.6) : T(0)) : T(0.6) * (q13 * q13);
     const T w3 = zany ? (z3 ? T(0.3) : T(0)) : T(0.3) * (q12 * q12);
-    return (w1 * f1 + w2 * f2 + w3 * f3) / (w1 + w2 + w3);
+    return (w1 * f1 + w2 * f2 + w3 * f3) * recip<T>(w1 + w2 + w3);
 }
 
 // Expansion coefficients of one axis' equilibrium factor at (u, T) (Sec. IV.D):
@@ -200,7 +221,7 @@ struct StageLds {
         eqc = al(gbuf + 2 * (size_t)kMaxRuns * kWave * sizeof(T));
         btab = al(eqc + (size_t)kMaxRuns * kTileCells * kEqStride * sizeof(double));
         mpart = al(btab + (size_t)kWave * (kMaxN + 1) * sizeof(double));
-        nwpart = al(mpart + 2 * (size_t)(kStageThreads / kWave) * 8 * sizeof(double));
+        nwpart = al(mpart + 2 * (size_t)(kStageThreads / kWave) * 8 * 4 * sizeof(double));
         total = al(nwpart + (size_t)(kStageThreads / kWave) * 2 * sizeof(double));
     }
 };
@@ -269,8 +290,8 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
         e[2] = 1.0 / tau_of(I.tau_model, I.Kn, n, T_);
         axis_coef(I.kind1, N1, u1, T_, tab + I.tC1, tab + I.tisf1, e + 3, e + 3 + (N1 + 1));
         axis_coef(I.kind2, N2, u2, T_, tab + I.tC2, tab + I.tisf2, e + 3 + 2 * (N1 + 1), e + 3 + 2 * (N1 + 1) + (N2 + 1));
-        e[kEqGeo] = tab[I.tRf + s];
-        e[kEqGeo + 1] = tab[I.tRf + s + 1];
+        e[kEqGeo] = tab[I.tRf + s] / tab[I.tdchi + s];
+        e[kEqGeo + 1] = tab[I.tRf + s + 1] / tab[I.tdchi + s];
         e[kEqGeo + 2] = tab[I.tdchi + s];
         e[kEqGeo + 3] = tab[I.tGam + s];
     }
@@ -373,9 +394,15 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     // lane q < 6 of the run's first wavefront sums quantity q over the run's wavefronts
     auto finish = [&](int c, int buf) {
         if (k >= 6 || c >= rlen) return;
-        const double* mp = mpart + (size_t)buf * (kStageThreads / kWave) * 8 + (size_t)w0 * 8 + k;
+        const double* mp = mpart + (((size_t)buf * (kStageThreads / kWave) + w0) * 8 + k) * 4;
         double m = 0.0;
-        for (int w = 0; w < nw_waves; ++w) m += mp[w * 8];
+        for (int w = 0; w < nw_waves; ++w) {
+            const double* q = mp + (size_t)w * 32;
+            m += q[0];
+            m += q[1];
+            m += q[2];
+            m += q[3];
+        }
         const int s = rs0 + c;
         if (k < 4) {
             if (dist == 0) A.msum_out[(size_t)(I.offC + s) * 5 + k] = m;
@@ -393,8 +420,8 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
 #pragma unroll
     for (int q = 0; q < kAhead; ++q) {
         const int x = rs0 + 3 + q;
-        pw[q] = (act && q < rlen && x < NR) ? Fd[(size_t)x * NV + k] : T(0);
-        fnr[q] = (act && need_fn && q < rlen) ? Fnd[(size_t)(rs0 + q) * NV + k] : T(0);
+        pw[q] = (act && q < rlen && x < NR) ? (Fd + (size_t)x * NV)[k] : T(0);
+        fnr[q] = (act && need_fn && q < rlen) ? (Fnd + (size_t)(rs0 + q) * NV)[k] : T(0);
     }
 
     for (int c = 0; c < TC; ++c) {
@@ -407,8 +434,8 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
 #pragma unroll
             for (int q = 0; q < kAhead - 1; ++q) { pw[q] = pw[q + 1]; fnr[q] = fnr[q + 1]; }
             const int x = s + 3 + kAhead;
-            pw[kAhead - 1] = (c + kAhead < rlen && x < NR) ? Fd[(size_t)x * NV + k] : T(0);
-            fnr[kAhead - 1] = (need_fn && c + kAhead < rlen) ? Fnd[(size_t)(s + kAhead) * NV + k] : T(0);
+            pw[kAhead - 1] = (c + kAhead < rlen && x < NR) ? (Fd + (size_t)x * NV)[k] : T(0);
+            fnr[kAhead - 1] = (need_fn && c + kAhead < rlen) ? (Fnd + (size_t)(s + kAhead) * NV)[k] : T(0);
         }
         T* row = rows + (size_t)buf * kRowElems + (size_t)r * 2 * S;
         T* rowT = row + S;
@@ -431,9 +458,8 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
         double m0 = 0, m1 = 0, m2 = 0, m3 = 0, rd = 0, rn = 0;
         if (cv) {
             const T fr = weno_face<T>(pos, w0v, w1v, w2v, w3v, w4v, w5v, weps);
-            const T Rl = T(e[kEqGeo]), Rr = T(e[kEqGeo + 1]);
-            const T dchi = T(e[kEqGeo + 2]), gam = T(e[kEqGeo + 3]);
-            const T adv = p1 * (Rr * fr - Rl * fl) / dchi;
+            const T Rl = T(e[kEqGeo]), Rr = T(e[kEqGeo + 1]), gam = T(e[kEqGeo + 3]);   // R_{s-+1/2}/dchi_s
+            const T adv = p1 * (Rr * fr - Rl * fl);
             T kf = T(0), ktf = T(0);
             kf = dot_lds<T>(K1row, rowT + vj * Q1p, Q1p);
             ktf = dot_lds<T>(Ktrow, row + vi * Q2p, Q2p);
@@ -455,7 +481,7 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
                     rn = (double)fn * (double)fn * rwk;
                 }
             }
-            Fo[(size_t)s * NV + k] = out;
+            (Fo + (size_t)s * NV)[k] = out;
             const double wo = wmk * (double)out;
             m0 = wo;
             if (dist == 0) {
@@ -465,12 +491,13 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
             }
             fl = fr;
         }
-        m0 = wave_sum(m0);
-        if (dist == 0) { m1 = wave_sum(m1); m2 = wave_sum(m2); m3 = wave_sum(m3); }
-        if (A.rpart) { rd = wave_sum(rd); rn = wave_sum(rn); }
-        if (lane == 0) {
-            double* mp = mpart + ((size_t)buf * (kStageThreads / kWave) + wave) * 8;
-            mp[0] = m0; mp[1] = m1; mp[2] = m2; mp[3] = m3; mp[4] = rd; mp[5] = rn;
+        // row totals; lanes 0, 16, 32, 48 store them, the finishing lanes add the rows
+        m0 = row_sum(m0);
+        if (dist == 0) { m1 = row_sum(m1); m2 = row_sum(m2); m3 = row_sum(m3); }
+        if (A.rpart) { rd = row_sum(rd); rn = row_sum(rn); }
+        if ((lane & 15) == 0) {
+            double* mp = mpart + ((size_t)buf * (kStageThreads / kWave) + wave) * 32 + (lane >> 4);
+            mp[0] = m0; mp[4] = m1; mp[8] = m2; mp[12] = m3; mp[16] = rd; mp[20] = rn;
         }
     }
     __syncthreads();

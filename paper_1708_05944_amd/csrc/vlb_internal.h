@@ -17,7 +17,7 @@ constexpr int kTileCells = 16; // default cells per run (auxiliary kernels and s
 constexpr int kMinTile = 2, kMaxTile = 32;   // range of the stage kernel's cells per run
 constexpr int kMaxRuns = 16;   // cell runs per stage block
 constexpr int kEqStride = 28;  // doubles kept per cell: n, T, 1/tau, coefficients, geometry (last 4)
-constexpr int kEqGeo = kEqStride - 4;   // R_{s-1/2}, R_{s+1/2}, dchi_s, Gamma_s
+constexpr int kEqGeo = kEqStride - 4;   // R_{s-1/2}/dchi_s, R_{s+1/2}/dchi_s, dchi_s, Gamma_s
 // LDS copies of a cell's populations for the force contractions: row-major [i][Q2p] and
 // transposed [j][Q1p] with strides padded to multiples of 4 (16-byte vector reads), both
 // in one run slot of 2 S elements, S = max(Q1 Q2p, Q2 Q1p) rounded up to 4.
