@@ -196,6 +196,12 @@ double oracle_weno5_eps(double a, double b, double c, double d, double e, double
     double f3 = c / 3.0 + 5.0 / 6.0 * d - e / 6.0;
     double s[3];
     oracle_weno5_sigma(a, b, c, d, e, s);
+    /* an indicator vanishes exactly when its three values are equal (Eq. weno_sigma is a
+     * sum of squares of two independent differences); evaluating 3c - 4d + e in floating
+     * point can leave a residue for equal values, which must not count as non-zero */
+    if (a == b && b == c) s[0] = 0.0;
+    if (b == c && c == d) s[1] = 0.0;
+    if (c == d && d == e) s[2] = 0.0;
     if (eps > 0.0 && s[0] != 0.0 && s[1] != 0.0 && s[2] != 0.0) {
         const double add = eps * (a * a + b * b + c * c + d * d + e * e) / 5.0;
         s[0] += add;
