@@ -285,6 +285,57 @@ vlb_status vlb_batch_surrogate_samples(vlb_batch* b, float* X, float* T, size_t 
  * start is kept.  Leaves the state in the FP64 buffers.  Synchronises. */
 vlb_status vlb_batch_warm_start(vlb_batch* b, vlb_mlp* m, int probe_steps, int* used_warm);
 
+/* ---- Expanding channel (Sec. VI) ------------------------------------------------
+ *
+ * A 2-D channel with walls at x = +-(1 + phi(y)), 1 + phi(xi) = 1 + (r - 1)(1 +
+ * tanh(4 xi / L - 2)) / 2 (half-width 1 upstream, r downstream: the tanh wall of Eq.
+ * canalie_phi rescaled to these asymptotes), in the coordinates lambda = x / (1 + phi)
+ * in [-1, 1] and xi = y in [xi_in, xi_out], with the orthonormal triad of Sec. VI.A so
+ * that p^lambda is normal to both walls.  N_lambda x N_xi equal cells in (lambda, xi).
+ * Diffuse walls at rest with temperature T_w at lambda = -1 and +1 (Sec. VI.B.4, both
+ * walls: the full channel width); reservoir ends: populations entering through the
+ * inlet (outlet) see ghost cells at the Maxwellian f_eq(n_in (n_out), 0, T_w), leaving
+ * ones the nearest interior cell (the construction of Sec. VI.B.1 with the density
+ * fixed).  ax1 is the p^lambda axis and must be half range (kind 1); ax2 the p^xi axis.
+ * tau_model as for the Couette instances (Sec. VI uses VLB_TAU_HYDRO, Eq. canalie_tau).
+ * State of an instance: [2][N_xi][N_lambda][NV] doubles (f', f''; xi cell; lambda cell;
+ * k = i * Q2 + j); the initial state is the rest Maxwellian n = 1, u = 0, T = T_w.
+ * FP64 only; one block per cell and distribution.  dt = 0 picks cfl / (max advective
+ * rate + force-operator bound / sqrt(3)), capped at 2 tau of the rest state. */
+typedef struct {
+    int N_lambda, N_xi;
+    double xi_in, xi_out;
+    double r, L;
+    vlb_axis ax1, ax2;
+    double Kn;
+    int tau_model;
+    double dt, cfl;
+    double n_in, n_out, T_w;
+    double weno_eps;
+} vlb_channel_desc;
+typedef struct vlb_channel vlb_channel;
+
+vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* descs, int precision,
+                              void* hip_stream);
+vlb_status vlb_channel_destroy(vlb_channel* c);
+vlb_status vlb_channel_info(const vlb_channel* c, int inst, int* N_lambda, int* N_xi, int* NV, double* dt,
+                            size_t* state_offset);
+vlb_status vlb_channel_state_size(const vlb_channel* c, size_t* n_doubles);
+vlb_status vlb_channel_set_state(vlb_channel* c, const double* host, size_t n);
+vlb_status vlb_channel_get_state(vlb_channel* c, double* host, size_t n);
+/* nsteps RK3 steps; the last records the residual (same definition as for Couette,
+ * volumes dchi dlambda). */
+vlb_status vlb_channel_step(vlb_channel* c, long nsteps);
+/* L[F] of the current state (host array of state size). */
+vlb_status vlb_channel_apply_L(vlb_channel* c, double* L, size_t n);
+vlb_status vlb_channel_residual(vlb_channel* c, double* r);
+/* Per cell of instance inst ([N_xi][N_lambda] host arrays, each may be NULL): n,
+ * u^lambda, u^xi, T and the particle content dchi dlambda n. */
+vlb_status vlb_channel_moments(vlb_channel* c, int inst, double* n, double* u1, double* u2, double* T,
+                               double* content);
+vlb_status vlb_channel_run_to_steady(vlb_channel* c, double tol, long max_steps, int check_every, long* steps,
+                                     double* r);
+
 const char* vlb_status_string(vlb_status s);
 const char* vlb_last_error(void);
 

@@ -1245,3 +1245,7 @@ vlb_status vlb_batch_warm_start(vlb_batch* b, vlb_mlp* m, int probe_steps, int* 
 }
 
 }  // extern "C"
+
+namespace vlb {
+double force_operator_norm(const AxisTables& a1, const AxisTables& a2) { return force_norm(a1, a2); }
+}  // namespace vlb

@@ -1,0 +1,426 @@
+// Host side of the expanding-channel path: channel geometry and connection
+// coefficients (Sec. VI.A), velocity-set tables, dt limits, device buffers and the RK3
+// driver of the channel stage kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "channel_internal.h"
+#include "mlp_internal.h"
+#include "vlb_internal.h"
+
+using namespace vlb;
+
+struct vlb_channel {
+    int B = 0;
+    hipStream_t stream = nullptr;
+    std::vector<vlb_channel_desc> d;
+    std::vector<ChanDesc> desc;
+    std::vector<double> tab;
+    std::vector<long long> base, cbase;   // first stage block / first cell of each instance
+    size_t state_n = 0, ncells = 0;
+    int threads = 64;
+    char* ws = nullptr;
+    size_t off_F[3], off_rpart, off_resid, off_diag, off_tab, off_desc, off_base, off_cbase, total;
+    bool have_resid = false;
+
+    double* F(int i) { return (double*)(ws + off_F[i]); }
+    double* rpart() { return (double*)(ws + off_rpart); }
+    double* resid() { return (double*)(ws + off_resid); }
+    double* diag() { return (double*)(ws + off_diag); }
+    double* dtab() { return (double*)(ws + off_tab); }
+    ChanDesc* ddesc() { return (ChanDesc*)(ws + off_desc); }
+    long long* dbase() { return (long long*)(ws + off_base); }
+    long long* dcbase() { return (long long*)(ws + off_cbase); }
+};
+
+namespace {
+
+bool axis_ok(const vlb_axis& a) {
+    return (a.kind == 0 || a.kind == 1) && a.Q >= 1 && a.Q <= kMaxQ && a.N >= 0 && a.N < a.Q && a.N <= kMaxN;
+}
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Wall of the expanding channel: 1 + phi(xi) = 1 + (r - 1)(1 + tanh(4 xi / L - 2)) / 2,
+// phi' = (r - 1)(2 / L) sech^2(4 xi / L - 2), and chi(xi) = xi + (r - 1)(xi + (L/4) ln cosh(4 xi / L - 2)) / 2
+// with d chi = (1 + phi) d xi (Eq. chi_canalie), in long double.
+struct Wall {
+    long double r, L;
+    long double phi(long double x) const { return (r - 1) * (1 + std::tanh(4 * x / L - 2)) / 2; }
+    long double dphi(long double x) const {
+        const long double c = std::cosh(4 * x / L - 2);
+        return (r - 1) * 2 / L / (c * c);
+    }
+    long double chi(long double x) const {
+        const long double z = std::fabs(4 * x / L - 2);
+        const long double lncosh = z + std::log1p(std::exp(-2 * z)) - std::log(2.0L);
+        return x + (r - 1) * (x + L / 4 * lncosh) / 2;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* descs, int precision,
+                              void* hip_stream) {
+    if (!out || B < 1 || !descs) return set_error(VLB_EINVAL, "need out, B >= 1 and descriptors");
+    *out = nullptr;
+    if (precision != VLB_FP64) return set_error(VLB_EINVAL, "channels run in FP64 (precision %d unsupported)", precision);
+    vlb_channel* c = new (std::nothrow) vlb_channel;
+    if (!c) return set_error(VLB_ENOMEM, "host allocation failed");
+    c->B = B;
+    c->stream = (hipStream_t)hip_stream;
+    c->d.assign(descs, descs + B);
+    c->desc.resize(B);
+    std::map<std::tuple<int, int, int>, AxisTables> cache;
+    auto get_axis = [&](const vlb_axis& a) -> const AxisTables* {
+        auto key = std::make_tuple(a.kind, a.Q, a.N);
+        auto it = cache.find(key);
+        if (it == cache.end()) {
+            AxisTables t;
+            if (!build_axis(a.kind, a.Q, a.N, t)) return nullptr;
+            it = cache.emplace(key, std::move(t)).first;
+        }
+        return &it->second;
+    };
+    size_t offF = 0, offC = 0;
+    long long blocks = 0, cells = 0;
+    for (int i = 0; i < B; ++i) {
+        const vlb_channel_desc& d = descs[i];
+        if (!(d.N_lambda >= 6 && d.N_xi >= 3 && d.xi_out > d.xi_in && d.r > 0 && d.L > 0 && d.Kn > 0 &&
+              d.tau_model >= 0 && d.tau_model <= 2 && axis_ok(d.ax1) && d.ax1.kind == 1 && axis_ok(d.ax2) &&
+              d.dt >= 0 && (d.dt > 0 || d.cfl > 0) && d.n_in > 0 && d.n_out > 0 && d.T_w > 0 && d.weno_eps >= 0 &&
+              std::isfinite(d.weno_eps))) {
+            delete c;
+            return set_error(VLB_EINVAL, "invalid channel descriptor for instance %d (ax1 must be half range)", i);
+        }
+        const AxisTables* a1 = get_axis(d.ax1);
+        const AxisTables* a2 = get_axis(d.ax2);
+        if (!a1 || !a2) {
+            delete c;
+            return set_error(VLB_EINVAL, "instance %d: velocity set construction failed", i);
+        }
+        const int n1 = a1->nodes, n2 = a2->nodes, NV = n1 * n2, NL = d.N_lambda, NX = d.N_xi;
+        if (NV > kMaxNV || n1 + n2 > kWave) {
+            delete c;
+            return set_error(VLB_EINVAL, "instance %d: %d velocities exceed the kernel limits", i, NV);
+        }
+        ChanDesc& D = c->desc[i];
+        D = ChanDesc{};
+        D.NL = NL; D.NX = NX; D.Q1 = n1; D.Q2 = n2; D.NV = NV;
+        D.kind1 = a1->kind; D.kind2 = a2->kind; D.N1 = a1->N; D.N2 = a2->N; D.Qh1 = a1->Q; D.Qh2 = a2->Q;
+        D.tau_model = d.tau_model;
+        D.Kn = d.Kn;
+        D.weno_eps = d.weno_eps;
+        D.offF = (long long)offF;
+        D.offC = (long long)offC;
+        D.offT = (long long)c->tab.size();
+        auto put = [&](const std::vector<double>& v) {
+            const int o = (int)(c->tab.size() - D.offT);
+            c->tab.insert(c->tab.end(), v.begin(), v.end());
+            return o;
+        };
+        D.tp1 = put(a1->p); D.tp2 = put(a2->p);
+        D.tK1 = put(a1->K); D.tKt1 = put(a1->Kt); D.tK2 = put(a2->K); D.tKt2 = put(a2->Kt);
+        D.tB1 = put(a1->B); D.tB2 = put(a2->B); D.tC1 = put(a1->C); D.tC2 = put(a2->C);
+        D.tisf1 = put(a1->invsqrtfact); D.tisf2 = put(a2->invsqrtfact);
+        // Maxwellians at rest with T_w: wall (n = 1), inlet, outlet reservoirs; [f' | f'']
+        std::vector<double> g1(n1), g2(n2), fw(2 * NV), fin(2 * NV), fout(2 * NV), iW(NV);
+        axis_equilibrium_host(*a1, 0.0, d.T_w, g1.data());
+        axis_equilibrium_host(*a2, 0.0, d.T_w, g2.data());
+        double den_lo = 0.0, den_hi = 0.0;
+        for (int a = 0; a < n1; ++a)
+            for (int b = 0; b < n2; ++b) {
+                const int k = a * n2 + b;
+                fw[k] = g1[a] * g2[b];
+                fw[NV + k] = d.T_w * fw[k];
+                if (a1->p[a] > 0) den_lo += a1->p[a] * fw[k];
+                if (a1->p[a] < 0) den_hi += a1->p[a] * fw[k];
+                iW[k] = 1.0 / (a1->w[a] * a2->w[b]);
+            }
+        for (int k = 0; k < 2 * NV; ++k) { fin[k] = d.n_in * fw[k]; fout[k] = d.n_out * fw[k]; }
+        D.den_lo = den_lo;
+        D.den_hi = den_hi;
+        D.tfw = put(fw); D.tfin = put(fin); D.tfout = put(fout); D.tiW = put(iW);
+        // geometry (Sec. VI.A): lambda in [-1, 1] and xi on equal cells
+        const Wall w{(long double)d.r, (long double)d.L};
+        std::vector<long double> lf(NL + 1), xf(NX + 1);
+        for (int s = 0; s <= NL; ++s) lf[s] = -1.0L + 2.0L * s / NL;
+        for (int p = 0; p <= NX; ++p) xf[p] = (long double)d.xi_in + ((long double)d.xi_out - d.xi_in) * p / NX;
+        std::vector<double> al(NX * NL), ar(NX * NL), glxx(NX * NL), glxl(NX * NL), xc((NX + 1) * NL),
+            xa((NX + 1) * NL), dlam(NL), dchi(NX), vol(NX * NL);
+        double vmax = 0.0, fmax1 = 0.0, fmax2 = 0.0;
+        double pl_abs = 0.0, px_abs = 0.0;
+        for (double v : a1->p) pl_abs = std::max(pl_abs, std::fabs(v));
+        for (double v : a2->p) px_abs = std::max(px_abs, std::fabs(v));
+        for (int s = 0; s < NL; ++s) dlam[s] = (double)(lf[s + 1] - lf[s]);
+        for (int p = 0; p < NX; ++p) dchi[p] = (double)(w.chi(xf[p + 1]) - w.chi(xf[p]));
+        for (int f = 0; f <= NX; ++f)
+            for (int s = 0; s < NL; ++s) {
+                const long double lam = (lf[s] + lf[s + 1]) / 2, a = lam * w.dphi(xf[f]);
+                xa[f * NL + s] = (double)a;
+                xc[f * NL + s] = (double)((1 + w.phi(xf[f])) / std::sqrt(1 + a * a));
+            }
+        for (int p = 0; p < NX; ++p) {
+            const long double xcen = (xf[p] + xf[p + 1]) / 2, ph = w.phi(xcen), dph = w.dphi(xcen);
+            for (int s = 0; s < NL; ++s) {
+                const int cidx = p * NL + s;
+                const long double lam = (lf[s] + lf[s + 1]) / 2;
+                const long double sl = std::sqrt(1 + lf[s] * lf[s] * dph * dph);
+                const long double sr = std::sqrt(1 + lf[s + 1] * lf[s + 1] * dph * dph);
+                al[cidx] = (double)(sl / (1 + ph));
+                ar[cidx] = (double)(sr / (1 + ph));
+                // connection coefficients, discretised so that a uniform Maxwellian is exact
+                const long double ql = xc[p * NL + s], qr = xc[(p + 1) * NL + s];
+                glxl[cidx] = (double)((qr - ql) / dchi[p]);
+                glxx[cidx] = (double)(-(sr - sl) / ((long double)dlam[s] * (1 + ph)) +
+                                      lam / dchi[p] * (w.dphi(xf[p + 1]) * qr - w.dphi(xf[p]) * ql));
+                vol[cidx] = dchi[p] * dlam[s];
+                // advective rate bound of the cell: |V^lambda| / dlambda + |V^xi| / dchi
+                double vx = 0.0;
+                for (int e = 0; e < 2; ++e) {
+                    const double cc = xc[(p + e) * NL + s], aa = xa[(p + e) * NL + s];
+                    vx = std::max(vx, cc * (px_abs + std::fabs(aa) * pl_abs));
+                }
+                vmax = std::max(vmax, std::max(al[cidx], ar[cidx]) * pl_abs / dlam[s] + vx / dchi[p]);
+                fmax1 = std::max(fmax1, std::fabs(glxx[cidx]));
+                fmax2 = std::max(fmax2, std::fabs(glxl[cidx]));
+            }
+        }
+        D.tal = put(al); D.tar = put(ar); D.tglxx = put(glxx); D.tglxl = put(glxl);
+        D.txc = put(xc); D.txa = put(xa); D.tdlam = put(dlam); D.tdchi = put(dchi); D.tvol = put(vol);
+        // dt: advection CFL combined with the force limit |lambda dt| <= sqrt(3) of RK3, capped
+        // at 2 tau of the rest state (as for the Couette instances)
+        const double rho = fmax1 * force_operator_norm(*a1, *a2) + fmax2 * force_operator_norm(*a2, *a1);
+        const double inv1 = vmax + rho / std::sqrt(3.0);
+        const double tau0 = d.tau_model == 0 ? d.Kn * 0.62665706865775012 : d.Kn;
+        double dt = d.dt;
+        if (dt == 0.0) {
+            dt = std::min(d.cfl / inv1, 2.0 * tau0);
+        } else if (dt > 1.0 / inv1 || dt > 2.5 * tau0) {
+            delete c;
+            return set_error(VLB_EUNSTABLE, "instance %d: dt=%g exceeds the stability limit %g", i, dt, 1.0 / inv1);
+        }
+        D.dt = dt;
+        c->base.push_back(blocks);
+        c->cbase.push_back(cells);
+        blocks += 2LL * NX * NL;
+        cells += (long long)NX * NL;
+        offF += (size_t)2 * NX * NL * NV;
+        offC += (size_t)NX * NL;
+        c->threads = std::max(c->threads, (NV + kWave - 1) / kWave * kWave);
+    }
+    c->base.push_back(blocks);
+    c->cbase.push_back(cells);
+    c->state_n = offF;
+    c->ncells = offC;
+    size_t off = 0;
+    for (int k = 0; k < 3; ++k) { c->off_F[k] = off; off = al256(off + c->state_n * sizeof(double)); }
+    c->off_rpart = off; off = al256(off + c->ncells * 4 * sizeof(double));
+    c->off_resid = off; off = al256(off + B * sizeof(double));
+    c->off_diag = off; off = al256(off + c->ncells * 5 * sizeof(double));
+    c->off_tab = off; off = al256(off + c->tab.size() * sizeof(double));
+    c->off_desc = off; off = al256(off + B * sizeof(ChanDesc));
+    c->off_base = off; off = al256(off + (B + 1) * sizeof(long long));
+    c->off_cbase = off; off = al256(off + (B + 1) * sizeof(long long));
+    c->total = off;
+    void* p = nullptr;
+    if (hipMalloc(&p, c->total) != hipSuccess) {
+        delete c;
+        return set_error(VLB_ENOMEM, "hipMalloc(%zu) failed", c->total);
+    }
+    c->ws = (char*)p;
+    hipError_t e = hipMemcpyAsync(c->dtab(), c->tab.data(), c->tab.size() * sizeof(double), hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->ddesc(), c->desc.data(), B * sizeof(ChanDesc), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->dbase(), c->base.data(), (B + 1) * sizeof(long long), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->dcbase(), c->cbase.data(), (B + 1) * sizeof(long long), hipMemcpyHostToDevice,
+                           c->stream);
+    // rest state n = 1, u = 0, T = T_w
+    std::vector<double> host(c->state_n);
+    for (int i = 0; i < B; ++i) {
+        const ChanDesc& D = c->desc[i];
+        const double* fw = c->tab.data() + D.offT + D.tfw;
+        for (int dd = 0; dd < 2; ++dd)
+            for (long long x = 0; x < (long long)D.NX * D.NL; ++x)
+                std::copy(fw + dd * D.NV, fw + (dd + 1) * D.NV,
+                          host.begin() + D.offF + ((size_t)dd * D.NX * D.NL + x) * D.NV);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->F(0), host.data(), c->state_n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(c->ws);
+        delete c;
+        return set_error(VLB_EDEVICE, "channel set-up failed: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return VLB_OK;
+}
+
+vlb_status vlb_channel_destroy(vlb_channel* c) {
+    if (!c) return VLB_OK;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->ws) (void)hipFree(c->ws);
+    delete c;
+    return VLB_OK;
+}
+
+vlb_status vlb_channel_info(const vlb_channel* c, int inst, int* N_lambda, int* N_xi, int* NV, double* dt,
+                            size_t* state_offset) {
+    if (!c || inst < 0 || inst >= c->B) return set_error(VLB_EINVAL, "bad instance");
+    const ChanDesc& D = c->desc[inst];
+    if (N_lambda) *N_lambda = D.NL;
+    if (N_xi) *N_xi = D.NX;
+    if (NV) *NV = D.NV;
+    if (dt) *dt = D.dt;
+    if (state_offset) *state_offset = (size_t)D.offF;
+    return VLB_OK;
+}
+
+vlb_status vlb_channel_state_size(const vlb_channel* c, size_t* n) {
+    if (!c || !n) return set_error(VLB_EINVAL, "null argument");
+    *n = c->state_n;
+    return VLB_OK;
+}
+
+vlb_status vlb_channel_set_state(vlb_channel* c, const double* host, size_t n) {
+    if (!c || !host || n != c->state_n) return set_error(VLB_EINVAL, "state size mismatch");
+    for (size_t x = 0; x < n; ++x)
+        if (!std::isfinite(host[x])) return set_error(VLB_ENONFINITE, "non-finite value at element %zu", x);
+    VLB_HIP_TRY(hipMemcpyAsync(c->F(0), host, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    VLB_HIP_TRY(hipStreamSynchronize(c->stream));
+    c->have_resid = false;
+    return VLB_OK;
+}
+
+vlb_status vlb_channel_get_state(vlb_channel* c, double* host, size_t n) {
+    if (!c || !host || n != c->state_n) return set_error(VLB_EINVAL, "state size mismatch");
+    VLB_HIP_TRY(hipMemcpyAsync(host, c->F(0), n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    VLB_HIP_TRY(hipStreamSynchronize(c->stream));
+    return VLB_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+vlb_status channel_stage(vlb_channel* c, int stage, bool last, bool l_only, double* Lout) {
+    ChanArgs A{};
+    A.inst = c->ddesc();
+    A.base = c->dbase();
+    A.B = c->B;
+    A.tab = c->dtab();
+    A.rpart = nullptr;
+    if (l_only) {
+        A.Fin = c->F(0); A.Fn = nullptr; A.Fout = Lout;
+        A.ca = 0; A.cb = 0; A.cc = 0; A.l_only = 1;
+    } else if (stage == 0) {
+        A.Fin = c->F(0); A.Fn = nullptr; A.Fout = c->F(1);
+        A.ca = 0.0; A.cb = 1.0; A.cc = 1.0;
+    } else if (stage == 1) {
+        A.Fin = c->F(1); A.Fn = c->F(0); A.Fout = c->F(2);
+        A.ca = 0.75; A.cb = 0.25; A.cc = 0.25;
+    } else {
+        A.Fin = c->F(2); A.Fn = c->F(0); A.Fout = c->F(0);
+        A.ca = 1.0 / 3.0; A.cb = 2.0 / 3.0; A.cc = 2.0 / 3.0;
+        if (last) A.rpart = c->rpart();
+    }
+    VLB_HIP_TRY(launch_channel_stage(c->base.back(), c->threads, c->stream, A));
+    return VLB_OK;
+}
+
+vlb_status channel_steps(vlb_channel* c, long nsteps) {
+    for (long it = 0; it < nsteps; ++it) {
+        const bool last = it + 1 == nsteps;
+        for (int st = 0; st < 3; ++st) {
+            vlb_status s = channel_stage(c, st, last, false, nullptr);
+            if (s != VLB_OK) return s;
+        }
+        if (last) {
+            VLB_HIP_TRY(launch_channel_reduce(c->B, c->stream, c->ddesc(), c->dtab(), c->rpart(), c->resid()));
+            c->have_resid = true;
+        }
+    }
+    return VLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vlb_status vlb_channel_step(vlb_channel* c, long nsteps) {
+    if (!c || nsteps < 0) return set_error(VLB_EINVAL, "bad arguments");
+    return channel_steps(c, nsteps);
+}
+
+vlb_status vlb_channel_apply_L(vlb_channel* c, double* L, size_t n) {
+    if (!c || !L || n != c->state_n) return set_error(VLB_EINVAL, "state size mismatch");
+    vlb_status s = channel_stage(c, 0, false, true, c->F(1));
+    if (s != VLB_OK) return s;
+    VLB_HIP_TRY(hipMemcpyAsync(L, c->F(1), n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    VLB_HIP_TRY(hipStreamSynchronize(c->stream));
+    return VLB_OK;
+}
+
+vlb_status vlb_channel_residual(vlb_channel* c, double* r) {
+    if (!c || !r) return set_error(VLB_EINVAL, "null argument");
+    if (!c->have_resid) return set_error(VLB_ESTATE, "no step has recorded a residual yet");
+    VLB_HIP_TRY(hipMemcpyAsync(r, c->resid(), c->B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    VLB_HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < c->B; ++i)
+        if (!std::isfinite(r[i])) return set_error(VLB_ENONFINITE, "non-finite residual in instance %d", i);
+    return VLB_OK;
+}
+
+vlb_status vlb_channel_moments(vlb_channel* c, int inst, double* n, double* u1, double* u2, double* T,
+                               double* content) {
+    if (!c || inst < 0 || inst >= c->B) return set_error(VLB_EINVAL, "bad instance");
+    VLB_HIP_TRY(launch_channel_diag(c->cbase.back(), c->threads, c->stream, c->ddesc(), c->dcbase(), c->B, c->dtab(),
+                                    c->F(0), c->diag()));
+    const ChanDesc& D = c->desc[inst];
+    const size_t nc = (size_t)D.NX * D.NL;
+    std::vector<double> h(nc * 5);
+    VLB_HIP_TRY(hipMemcpyAsync(h.data(), c->diag() + (size_t)D.offC * 5, h.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, c->stream));
+    VLB_HIP_TRY(hipStreamSynchronize(c->stream));
+    double* outs[5] = {n, u1, u2, T, content};
+    for (int q = 0; q < 5; ++q)
+        if (outs[q])
+            for (size_t x = 0; x < nc; ++x) outs[q][x] = h[x * 5 + q];
+    return VLB_OK;
+}
+
+vlb_status vlb_channel_run_to_steady(vlb_channel* c, double tol, long max_steps, int check_every, long* steps,
+                                     double* r) {
+    if (!c || !(tol > 0) || max_steps < 1 || check_every < 1) return set_error(VLB_EINVAL, "bad arguments");
+    std::vector<long> conv(c->B, -1);
+    std::vector<double> res(c->B, INFINITY);
+    long done = 0;
+    int remaining = c->B;
+    while (done < max_steps && remaining > 0) {
+        const long n = std::min<long>(check_every, max_steps - done);
+        vlb_status s = channel_steps(c, n);
+        if (s != VLB_OK) return s;
+        done += n;
+        s = vlb_channel_residual(c, res.data());
+        if (s != VLB_OK) return s;
+        for (int i = 0; i < c->B; ++i)
+            if (conv[i] < 0 && res[i] < tol) { conv[i] = done; --remaining; }
+    }
+    if (steps) std::copy(conv.begin(), conv.end(), steps);
+    if (r) std::copy(res.begin(), res.end(), r);
+    return remaining ? set_error(VLB_ENOTCONV, "%d channel(s) above tol after %ld steps", remaining, done) : VLB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,44 @@
+// Internal declarations of the expanding-channel path (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace vlb {
+
+// Per-instance descriptor in device memory.  State block of an instance:
+// F[2][NX][NL][NV] (distribution, xi cell, lambda cell, velocity k = i Q2 + j).
+// Table offsets are relative to offT, in doubles.
+struct ChanDesc {
+    int NL, NX, Q1, Q2, NV, kind1, kind2, N1, N2, Qh1, Qh2, tau_model;
+    double Kn, dt, den_lo, den_hi, weno_eps, pad0;
+    long long offF, offC, offT;
+    int tp1, tp2, tK1, tKt1, tK2, tKt2, tB1, tB2, tC1, tC2, tisf1, tisf2;
+    int tfw, tfin, tfout, tiW;    // wall / inlet / outlet Maxwellians [2][NV] (f', f''), 1/(w_i w_j) [NV]
+    int tal, tar, tglxx, tglxl;   // per cell [NX][NL]: V^lambda factors of the left / right lambda
+                                  // faces, connection coefficients G_lxx, G_lxl
+    int txc, txa;                 // per (xi face, lambda row) [NX+1][NL]: V^xi = c (p^xi - a p^lambda)
+    int tdlam, tdchi, tvol, pad1; // [NL], [NX], cell volumes dchi dlambda [NX][NL]
+};
+
+struct ChanArgs {
+    const ChanDesc* inst;
+    const long long* base;   // [B+1] first block of each instance (2 NX NL blocks each)
+    int B;
+    const double* tab;
+    const void* Fin;
+    const void* Fn;
+    void* Fout;
+    double* rpart;           // [cells][2][2] residual partials (nullable)
+    double ca, cb, cc;       // out = ca Fn + cb Fin + cc dt L[Fin]
+    int l_only;              // 1: out = L[Fin]
+};
+
+hipError_t launch_channel_stage(long long nblocks, int threads, hipStream_t st, const ChanArgs& A);
+hipError_t launch_channel_reduce(int ninst, hipStream_t st, const ChanDesc* insts, const double* tab,
+                                 const double* rpart, double* resid);
+hipError_t launch_channel_diag(long long ncells_total, int threads, hipStream_t st, const ChanDesc* insts,
+                               const long long* cbase, int B, const double* tab, const double* F, double* diag);
+
+}  // namespace vlb

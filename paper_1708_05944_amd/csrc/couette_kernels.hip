@@ -1,12 +1,12 @@
-// FP64 HIP kernels of the circular-Couette vielbein LB hot path (gfx950).
+// HIP kernels of the circular-Couette vielbein LB hot path (gfx950), FP64 and FP32.
 //
 // One launch = one stage of the third-order TVD Runge-Kutta scheme (Sec. III.A,
-// Eq. rk3) for every instance of a batch.  A wavefront owns a run of consecutive
-// cells of one distribution (f' or f'') of one instance and all of that cell run's
-// velocities: lane l holds velocities k = l + 64 v, v < VPT.  It sweeps the cells in
-// order with a six-cell register window per velocity, so every population of the
-// stage input is read from HBM once (plus a three-cell halo on each side of the run)
-// and every output population is written once.  Per cell it
+// Eq. rk3) for every instance of a batch.  A 1024-thread block holds runs of
+// consecutive cells of one distribution (f' or f'') of one instance, one thread per
+// velocity; each run sweeps its cells in order with a six-cell register window per
+// velocity, so every population of the stage input is read from HBM once (plus a
+// three-cell halo at each run end) and every output population is written once.  Per
+// cell it
 //   * takes n, u, T of the stage input from the moment sums its producer left
 //     (Sec. IV.A, Eq. macro_red) and builds the polynomial equilibrium
 //     f'_eq = n g1 g2, f''_eq = T f'_eq (Sec. IV.D, Eqs. feq_red, eq_gak_H, eq_gak_hh);
@@ -14,164 +14,20 @@
 //     weno5_omega, weno_sigma, Table weno), upwinded by the sign of p^R, and the chi-form
 //     flux difference (Sec. V.C.1, Eqs. flux_kom_R / flux_kom_eta);
 //   * applies the projected momentum derivatives of the inertial force
-//     (Sec. V.A, Eq. boltz_couette_kom; kernels of Sec. IV.C) from an LDS copy of the
+//     (Sec. V.A, Eq. boltz_couette_kom; kernels of Sec. IV.C) from LDS copies of the
 //     cell's populations;
 //   * relaxes with BGK (Eq. BGK), combines the RK stage, stores, and reduces the
-//     moment sums of its output for the next stage (wavefront shuffles, fixed order).
+//     moment sums of its output for the next stage (DPP row sums, fixed order).
 // Diffuse walls (Sec. III.F, Eqs. weno_flux_eq, weno_populate, extrapol, nw): the
-// wavefronts whose window reaches a wall recompute n_w from the wall-bound WENO flux
-// (a half-range sum reduced across the wavefront) and fill the ghost cells.
+// runs that reach a wall recompute n_w from the wall-bound WENO flux (a half-range sum
+// reduced across the run) and fill the ghost cells.
 #include <hip/hip_runtime.h>
 
+#include "vlb_device.h"
 #include "vlb_internal.h"
 
 namespace vlb {
 
-// Lane permutation of a double by a DPP control (applied to both 32-bit halves).
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v) {
-    const long long x = __double_as_longlong(v);
-    // every lane's source lane exists for the permutations used here (quad permutes and
-    // mirrors within a row), so no fallback value is needed
-    const int lo = __builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, 0xF, 0xF, true);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-__device__ __forceinline__ double read_lane(double v, int l) {
-    const long long x = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)x, l);
-    const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Sum over the 64 lanes of a wavefront, returned in every lane, in a fixed order:
-// quad butterflies (xor 1, xor 2) and the half-row and row mirrors by DPP give every
-// lane its 16-lane row total; the four row totals are then added in lane order.
-__device__ __forceinline__ double wave_sum(double v) {
-    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
-    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
-    v += dpp_mov<0x141>(v);   // row_half_mirror
-    v += dpp_mov<0x140>(v);   // row_mirror
-    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
-}
-
-// Sum over each 16-lane row of a wavefront (the row total in every lane of the row), in
-// a fixed order: quad butterflies and the half-row and row mirrors by DPP.
-__device__ __forceinline__ double row_sum(double v) {
-    v += dpp_mov<0xB1>(v);
-    v += dpp_mov<0x4E>(v);
-    v += dpp_mov<0x141>(v);
-    v += dpp_mov<0x140>(v);
-    return v;
-}
-
-// 1/x: the hardware reciprocal in FP32 (about 1 ulp, the FP32 path's tolerance is far
-// wider); a correctly rounded division in FP64.
-template <typename T>
-__device__ __forceinline__ T recip(T x);
-template <>
-__device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <>
-__device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
-
-// Flux at the face between c and d, upwinded from c (a, b, c, d, e in upwind order).
-template <typename T>
-__device__ __forceinline__ T weno5(T a, T b, T c, T d, T e, T eps);
-
-// Face flux between window cells 2 and 3 of a six-cell window (cells s-2 .. s+3):
-// upwinded from cell 2 when the advection velocity is positive, from cell 3 otherwise
-// (the mirror image of the printed stencil).  The five stencil values are selected
-// first, so a wavefront holding both signs evaluates WENO once.
-template <typename T>
-__device__ __forceinline__ T weno_face(bool pos, T w0, T w1, T w2, T w3, T w4, T w5, T eps) {
-    return weno5<T>(pos ? w0 : w5, pos ? w1 : w4, pos ? w2 : w3, pos ? w3 : w2, pos ? w4 : w1, eps);
-}
-
-template <typename T>
-__device__ __forceinline__ T weno5(T a, T b, T c, T d, T e, T eps) {
-    const T f1 = a * T(1.0 / 3.0) - b * T(7.0 / 6.0) + c * T(11.0 / 6.0);
-    const T f2 = -b * T(1.0 / 6.0) + c * T(5.0 / 6.0) + d * T(1.0 / 3.0);
-    const T f3 = c * T(1.0 / 3.0) + d * T(5.0 / 6.0) - e * T(1.0 / 6.0);
-    T t1 = a - T(2) * b + c, t2 = a - T(4) * b + T(3) * c;
-    T s1 = T(13.0 / 12.0) * (t1 * t1) + T(0.25) * (t2 * t2);
-    t1 = b - T(2) * c + d;
-    t2 = b - d;
-    T s2 = T(13.0 / 12.0) * (t1 * t1) + T(0.25) * (t2 * t2);
-    t1 = c - T(2) * d + e;
-    t2 = T(3) * c - T(4) * d + e;
-    T s3 = T(13.0 / 12.0) * (t1 * t1) + T(0.25) * (t2 * t2);
-    // an indicator vanishes exactly when its three values are equal (Eq. weno_sigma is a
-    // sum of squares of two independent differences); the equality test is immune to the
-    // compiler fusing the products that form the values into the indicator arithmetic
-    // (identical ghost values must select the Table weno limit, whatever eps)
-    const bool z1 = (a == b && b == c) || s1 == T(0), z2 = (b == c && c == d) || s2 == T(0),
-               z3 = (c == d && d == e) || s3 == T(0), zany = z1 || z2 || z3;
-    if (eps != T(0)) {   // optional regularisation (eps is uniform over the instance)
-        const T add = zany ? T(0) : eps * T(0.2) * (a * a + b * b + c * c + d * d + e * e);
-        s1 += add;
-        s2 += add;
-        s3 += add;
-    }
-    // w_q proportional to d_q / s_q^2, rewritten as d_q (r_a r_b)^2 with r = s / max(s):
-    // one division instead of three and no overflow.  In FP64 an underflow would need two
-    // indicators below 1e-155 of the largest, which only exact zeros reach; the FP32 path
-    // runs on populations scaled by 1/(w_i w_j), which are O(1), so its indicators stay
-    // far from the FP32 range limits.  Exactly vanishing indicators take the limits of
-    // Table weno instead (selected without branching; the unused product form may be NaN
-    // when every indicator vanishes and is discarded by the select).
-    T m = s1 > s2 ? s1 : s2;
-    m = m > s3 ? m : s3;
-    const T inv = recip<T>(m);
-    const T r1 = s1 * inv, r2 = s2 * inv, r3 = s3 * inv;
-    const T q23 = r2 * r3, q13 = r1 * r3, q12 = r1 * r2;
-    const T w1 = zany ? (z1 ? T(0.1) : T(0)) : T(0.1) * (q23 * q23);
-    const T w2 = zany ? (z2 ? T(0.6) : T(0)) : T(0.6) * (q13 * q13);
-    const T w3 = zany ? (z3 ? T(0.3) : T(0)) : T(0.3) * (q12 * q12);
-    return (w1 * f1 + w2 * f2 + w3 * f3) * recip<T>(w1 + w2 + w3);
-}
-
-// Expansion coefficients of one axis' equilibrium factor at (u, T) (Sec. IV.D):
-// full range: coefficient of phi_l = He_l/sqrt(l!) is E[He_l(X)]/sqrt(l!), X ~ N(u, T),
-//   with a_l = E[He_l]/l! from l a_l = u a_{l-1} + (T-1) a_{l-2};
-// half range: coefficient of phi_l is sum_s C[l][s] M_s with the half-line moments
-//   M_s = int_0^inf x^s N(x; +-u, T) dx:  M_0 = (1+erf(zeta))/2, M_1 = u M_0 + T g(0),
-//   M_s = u M_{s-1} + (s-1) T M_{s-2}.  Writes plus- and minus-side coefficients.
-__device__ __noinline__ void axis_coef(int kind, int N, double u, double T, const double* C, const double* isf,
-                          double* cp, double* cm) {
-    if (kind == 0) {
-        double a0 = 1.0, a1 = u;
-        cp[0] = cm[0] = a0 / isf[0];
-        if (N >= 1) cp[1] = cm[1] = a1 / isf[1];
-        for (int l = 2; l <= N; ++l) {
-            const double a2 = (u * a1 + (T - 1.0) * a0) / l;
-            cp[l] = cm[l] = a2 / isf[l];
-            a0 = a1;
-            a1 = a2;
-        }
-        return;
-    }
-    for (int sg = 0; sg < 2; ++sg) {
-        const double uu = sg == 0 ? u : -u;
-        double M[kMaxN + 1];
-        const double g0 = exp(-uu * uu / (2.0 * T)) / sqrt(2.0 * M_PI * T);
-        M[0] = 0.5 * (1.0 + erf(uu / sqrt(2.0 * T)));
-        if (N >= 1) M[1] = uu * M[0] + T * g0;
-        for (int s = 2; s <= N; ++s) M[s] = uu * M[s - 1] + (s - 1) * T * M[s - 2];
-        double* co = sg == 0 ? cp : cm;
-        for (int l = 0; l <= N; ++l) {
-            double acc = 0.0;
-            for (int s = 0; s <= l; ++s) acc += C[l * (N + 1) + s] * M[s];
-            co[l] = acc;
-        }
-    }
-}
-
-__device__ __forceinline__ double tau_of(int model, double Kn, double n, double T) {
-    if (model == 0) return Kn * 0.62665706865775012 / n;   // Kn sqrt(pi/8)/n, Eq. tau_aoki
-    if (model == 1) return Kn / (n * T);                   // Eq. hydro_tau
-    return Kn / n;
-}
 
 __device__ __forceinline__ int pad4_d(int x) { return (x + 3) & ~3; }
 __device__ __forceinline__ int row_slot_d(int Q1, int Q2) {

@@ -39,6 +39,9 @@ struct AxisTables {
 };
 
 bool build_axis(int kind, int Q, int N, AxisTables& t);
+// Largest singular value of K1 (x) diag(p2^2) - diag(p1) (x) Kt2 in the quadrature-weighted
+// norm (the inertial-force operator with unit connection coefficient).
+double force_operator_norm(const AxisTables& a1, const AxisTables& a2);
 void axis_equilibrium_host(const AxisTables& t, double u, double T, double* g);
 
 // Per-instance descriptor in device memory.  Offsets: F in elements of the state

@@ -70,6 +70,42 @@ class CouetteDesc:
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _fp = ctypes.POINTER(ctypes.c_float)
+
+
+class _ChannelDesc(ctypes.Structure):
+    _fields_ = [("N_lambda", ctypes.c_int), ("N_xi", ctypes.c_int), ("xi_in", ctypes.c_double),
+                ("xi_out", ctypes.c_double), ("r", ctypes.c_double), ("L", ctypes.c_double), ("ax1", _Axis),
+                ("ax2", _Axis), ("Kn", ctypes.c_double), ("tau_model", ctypes.c_int), ("dt", ctypes.c_double),
+                ("cfl", ctypes.c_double), ("n_in", ctypes.c_double), ("n_out", ctypes.c_double),
+                ("T_w", ctypes.c_double), ("weno_eps", ctypes.c_double)]
+
+
+@dataclass
+class ChannelDesc:
+    """One expanding channel: N_lambda x N_xi cells, lambda in [-1, 1], xi in
+    [xi_in, xi_out], wall 1 + phi(xi) with expansion ratio r over length L; ax1 (p^lambda,
+    half range) and ax2 (p^xi) as (kind, Q, N); reservoir densities n_in / n_out."""
+    N_lambda: int = 8
+    N_xi: int = 12
+    xi_in: float = -4.0
+    xi_out: float = 12.0
+    r: float = 2.0
+    L: float = 4.0
+    ax1: tuple = (1, 4, 2)
+    ax2: tuple = (0, 4, 2)
+    Kn: float = 0.05
+    tau_model: int = 1
+    dt: float = 0.0
+    cfl: float = 0.5
+    n_in: float = 1.1
+    n_out: float = 0.9
+    T_w: float = 1.0
+    weno_eps: float = 0.0
+
+    def _c(self) -> _ChannelDesc:
+        return _ChannelDesc(self.N_lambda, self.N_xi, self.xi_in, self.xi_out, self.r, self.L, _Axis(*self.ax1),
+                            _Axis(*self.ax2), self.Kn, self.tau_model, self.dt, self.cfl, self.n_in, self.n_out,
+                            self.T_w, self.weno_eps)
 _SIGS = {
     "vlb_batch_create_couette": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(_CouetteDesc),
                                  ctypes.c_int, ctypes.c_void_p, ctypes.c_int],
@@ -113,6 +149,20 @@ _SIGS = {
                       ctypes.POINTER(ctypes.c_int), ctypes.c_long, ctypes.c_int, ctypes.c_float, _fp],
     "vlb_batch_surrogate_samples": [ctypes.c_void_p, _fp, _fp, ctypes.c_size_t],
     "vlb_batch_warm_start": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
+    "vlb_channel_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(_ChannelDesc), ctypes.c_int,
+                           ctypes.c_void_p],
+    "vlb_channel_destroy": [ctypes.c_void_p],
+    "vlb_channel_info": [ctypes.c_void_p, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 3
+    + [_dp, ctypes.POINTER(ctypes.c_size_t)],
+    "vlb_channel_state_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "vlb_channel_set_state": [ctypes.c_void_p, _dp, ctypes.c_size_t],
+    "vlb_channel_get_state": [ctypes.c_void_p, _dp, ctypes.c_size_t],
+    "vlb_channel_step": [ctypes.c_void_p, ctypes.c_long],
+    "vlb_channel_apply_L": [ctypes.c_void_p, _dp, ctypes.c_size_t],
+    "vlb_channel_residual": [ctypes.c_void_p, _dp],
+    "vlb_channel_moments": [ctypes.c_void_p, ctypes.c_int] + [_dp] * 5,
+    "vlb_channel_run_to_steady": [ctypes.c_void_p, ctypes.c_double, ctypes.c_long, ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_long), _dp],
     "vlb_status_string": [ctypes.c_int],
     "vlb_last_error": [],
 }
@@ -433,3 +483,84 @@ class Mlp:
                                             Xd.shape[0], o.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), o.size,
                                             batch, lr, ctypes.byref(loss)), "vlb_mlp_train")
         return loss.value
+
+
+class Channel:
+    """B expanding channels advanced together on one GPU (FP64)."""
+
+    def __init__(self, descs, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the vielbein LB library runs on the GPU only")
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.descs = list(descs)
+        self.B = len(self.descs)
+        arr = (_ChannelDesc * self.B)(*[d._c() for d in self.descs])
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(load_library().vlb_channel_create(ctypes.byref(h), self.B, arr, VLB_FP64,
+                                                 ctypes.c_void_p(self.stream.cuda_stream)), "vlb_channel_create")
+        self._h = h
+        n = ctypes.c_size_t()
+        _check(load_library().vlb_channel_state_size(h, ctypes.byref(n)), "vlb_channel_state_size")
+        self.state_size = n.value
+        self.info = []
+        for b in range(self.B):
+            NL, NX, NV = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+            dt, off = ctypes.c_double(), ctypes.c_size_t()
+            _check(load_library().vlb_channel_info(h, b, ctypes.byref(NL), ctypes.byref(NX), ctypes.byref(NV),
+                                                   ctypes.byref(dt), ctypes.byref(off)), "vlb_channel_info")
+            self.info.append(dict(N_lambda=NL.value, N_xi=NX.value, NV=NV.value, dt=dt.value, offset=off.value))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().vlb_channel_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def instance_view(self, state, b):
+        i = self.info[b]
+        n = 2 * i["N_xi"] * i["N_lambda"] * i["NV"]
+        return state[i["offset"]:i["offset"] + n].reshape(2, i["N_xi"], i["N_lambda"], i["NV"])
+
+    def get_state(self):
+        out = np.empty(self.state_size)
+        _check(load_library().vlb_channel_get_state(self._h, _ptr(out), out.size), "vlb_channel_get_state")
+        return out
+
+    def set_state(self, state):
+        s = np.ascontiguousarray(state, dtype=np.float64).ravel()
+        _check(load_library().vlb_channel_set_state(self._h, _ptr(s), s.size), "vlb_channel_set_state")
+
+    def step(self, nsteps: int = 1):
+        _check(load_library().vlb_channel_step(self._h, nsteps), "vlb_channel_step")
+
+    def apply_L(self):
+        out = np.empty(self.state_size)
+        _check(load_library().vlb_channel_apply_L(self._h, _ptr(out), out.size), "vlb_channel_apply_L")
+        return out
+
+    def residual(self):
+        r = np.empty(self.B)
+        _check(load_library().vlb_channel_residual(self._h, _ptr(r)), "vlb_channel_residual")
+        return r
+
+    def moments(self, b: int):
+        i = self.info[b]
+        shp = (i["N_xi"], i["N_lambda"])
+        outs = [np.empty(shp) for _ in range(5)]
+        _check(load_library().vlb_channel_moments(self._h, b, *[_ptr(o) for o in outs]), "vlb_channel_moments")
+        return dict(zip(("n", "u1", "u2", "T", "content"), outs))
+
+    def run_to_steady(self, tol: float, max_steps: int, check_every: int = 100):
+        steps = (ctypes.c_long * self.B)()
+        r = np.empty(self.B)
+        st = load_library().vlb_channel_run_to_steady(self._h, tol, max_steps, check_every, steps, _ptr(r))
+        if st not in (0, -5):
+            _check(st, "vlb_channel_run_to_steady")
+        return np.array(list(steps)), r, st == 0

@@ -1,0 +1,129 @@
+"""GPU parity of the expanding-channel path against the FP64 CPU oracle, through the C
+ABI.  Bar: max-norm difference per distribution, relative to the oracle's max-norm,
+at most 1e-12 (both sides follow the same arithmetic; the GPU fuses multiply-adds)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.channel import ChannelOracle
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _pair(**kw):
+    from paper_1708_05944_amd import ChannelDesc
+    o = ChannelOracle(NL=kw.pop("N_lambda"), NX=kw.pop("N_xi"), **kw)
+    d = ChannelDesc(N_lambda=o.NL, N_xi=o.NX, **kw)
+    return o, d
+
+
+def _perturbed(o, seed, amp=0.15):
+    rng = np.random.default_rng(seed)
+    X, S = np.meshgrid(o.xi_c, o.lam_c, indexing="ij")
+    F = o.equilibrium(1 + 0.1 * np.sin(X) * np.cos(2 * S), 0.05 * np.sin(3 * S), 0.2 * np.cos(S) * (1 - S ** 2),
+                      1 + 0.05 * np.cos(X + S))
+    return F * rng.uniform(1 - amp, 1 + amp, F.shape)
+
+
+def _relerr(a, b):
+    a = np.asarray(a).reshape(2, -1)
+    b = np.asarray(b).reshape(2, -1)
+    return max(np.abs(a[d] - b[d]).max() / np.abs(b[d]).max() for d in range(2))
+
+
+CASES = [
+    dict(N_lambda=8, N_xi=10, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.05),                         # smallest set
+    dict(N_lambda=12, N_xi=9, ax1=(1, 8, 4), ax2=(0, 16, 4), Kn=0.05),                        # 256 velocities (config 3)
+    dict(N_lambda=7, N_xi=13, ax1=(1, 5, 4), ax2=(0, 7, 4), Kn=0.3, r=3.0, L=2.0),            # p^xi = 0 node, steep
+    dict(N_lambda=10, N_xi=6, ax1=(1, 6, 4), ax2=(0, 8, 4), Kn=0.1, r=1.0),                   # straight channel
+    dict(N_lambda=6, N_xi=11, ax1=(1, 4, 3), ax2=(0, 5, 4), Kn=0.2, weno_eps=1e-6, n_in=1.2),  # regularised WENO
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_channel_operator_matches_oracle(case):
+    from paper_1708_05944_amd import Channel
+    _say(f"case {case}")
+    o, d = _pair(**dict(case))
+    c = Channel([d])
+    F = _perturbed(o, 5)
+    c.set_state(F.ravel())
+    L = c.instance_view(c.apply_L(), 0)
+    Lw, _, _ = o.L(F)
+    err = _relerr(L, Lw)
+    _say(f"L rel err {err:.2e}")
+    assert err <= TOL
+    c.close()
+
+
+def test_channel_initial_state_and_rest_stationarity():
+    """The library starts from the rest Maxwellian, which with equal reservoirs is a
+    fixed point of the curved-channel scheme to rounding."""
+    from paper_1708_05944_amd import Channel
+    o, d = _pair(N_lambda=12, N_xi=9, ax1=(1, 8, 4), ax2=(0, 16, 4), Kn=0.05, n_in=1.0, n_out=1.0)
+    c = Channel([d])
+    F0 = c.instance_view(c.get_state(), 0)
+    assert _relerr(F0, o.equilibrium(1.0, 0.0, 0.0, 1.0)) <= 1e-14
+    L = c.instance_view(c.apply_L(), 0)
+    assert np.abs(L).max() <= 1e-13 * np.abs(F0).max()
+    c.close()
+
+
+def test_channel_steps_match_oracle():
+    """20 RK3 steps of the pressure-driven flow from a perturbed state."""
+    from paper_1708_05944_amd import Channel
+    o, d = _pair(N_lambda=8, N_xi=12, ax1=(1, 4, 3), ax2=(0, 6, 4), Kn=0.1)
+    c = Channel([d])
+    F = _perturbed(o, 7)
+    c.set_state(F.ravel())
+    c.step(20)
+    want = o.step(F, c.info[0]["dt"], 20)
+    err = _relerr(c.instance_view(c.get_state(), 0), want)
+    _say(f"20 steps rel err {err:.2e}")
+    assert err <= TOL
+    r = c.residual()[0]
+    Fm = o.step(F, c.info[0]["dt"], 19)
+    assert abs(r / o.residual(want, Fm, c.info[0]["dt"]) - 1) <= 1e-9
+    c.close()
+
+
+def test_channel_uneven_batch_matches_oracle():
+    from paper_1708_05944_amd import Channel
+    pairs = [_pair(**dict(CASES[0])), _pair(**dict(CASES[2])), _pair(**dict(CASES[1]))]
+    c = Channel([p[1] for p in pairs])
+    st = c.get_state()
+    inits = []
+    for i, (o, _) in enumerate(pairs):
+        F = _perturbed(o, 20 + i)
+        c.instance_view(st, i)[...] = F
+        inits.append(F)
+    c.set_state(st)
+    c.step(5)
+    got = c.get_state()
+    for i, (o, _) in enumerate(pairs):
+        want = o.step(inits[i], c.info[i]["dt"], 5)
+        err = _relerr(c.instance_view(got, i), want)
+        _say(f"instance {i}: rel err {err:.2e}")
+        assert err <= TOL
+    c.close()
+
+
+def test_channel_moments_and_content():
+    from paper_1708_05944_amd import Channel
+    o, d = _pair(**dict(CASES[2]))
+    c = Channel([d])
+    F = _perturbed(o, 9)
+    c.set_state(F.ravel())
+    m = c.moments(0)
+    mw = o.moments(F)
+    for key in ("n", "u1", "u2", "T"):
+        assert np.abs(m[key] - mw[key]).max() <= 1e-12 * max(np.abs(mw[key]).max(), 1e-3), key
+    assert m["content"].sum() == pytest.approx(o.mass(F), rel=1e-13)
+    c.close()
