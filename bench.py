@@ -108,6 +108,7 @@ def main():
                     help="skip the single-instance time-to-steady-state leg (profiling runs)")
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the learned warm-start leg (training solves, training, held-out runs)")
+    ap.add_argument("--no-channel", action="store_true", help="skip the expanding-channel leg")
     ap.add_argument("--warm-train", type=int, default=128, help="training instances of the warm-start leg")
     ap.add_argument("--warm-heldout", type=int, default=32, help="held-out instances of the warm-start leg")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
@@ -169,6 +170,30 @@ def main():
                          fp32_steps=b.fp32_steps() if prec else 0, tile=single_tile)
         b.close()
 
+    channel = None
+    if not args.no_channel:
+        # expanding channel, 512 x 128 cells, HH(4;8) x H(4;16) = 256 velocities, Kn = 0.05,
+        # pressure-driven (n 1.1 -> 0.9), expansion ratio 2 over 4 widths; FP64
+        from paper_1708_05944_amd import Channel, ChannelDesc
+        cd = ChannelDesc(N_lambda=128, N_xi=512, xi_in=-4.0, xi_out=12.0, r=2.0, L=4.0, ax1=(1, 8, 4),
+                         ax2=(0, 16, 4), Kn=0.05, tau_model=1, n_in=1.1, n_out=0.9, T_w=1.0)
+        ch = Channel([cd])
+        ch.step(2)
+        torch.cuda.synchronize()
+        nst = max(2, args.steps // 2)
+        t0 = time.perf_counter()
+        ch.step(nst)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sv = cd.N_lambda * cd.N_xi * 16 * 16
+        gbs = sv * nst * 128 / el / 1e9
+        channel = {"workload": "expanding channel 512 x 128 cells, HH(4;8) x H(4;16) (256 velocities), Kn 0.05, "
+                               "ratio 2 over 4 widths, reservoirs n 1.1 / 0.9, FP64",
+                   "value": sv * nst / el, "unit": "site-velocity updates/s", "ms_per_step": el / nst * 1e3,
+                   "steps": nst, "achieved_GBps_wallclock": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
+                   "dt": ch.info[0]["dt"]}
+        ch.close()
+
     warm = None
     if not args.no_warm:
         # learned warm start: surrogate trained on the solver's own steady states (sweep
@@ -218,6 +243,7 @@ def main():
                  "avg_launch_ms": dom64["total_ms"] / dom64["launches"]},
         "time_to_steady_state_single": tts,
         "time_to_steady_state_warm_start": warm,
+        "channel": channel,
     }
     if args.copy_ref_mib:
         n = args.copy_ref_mib << 20
