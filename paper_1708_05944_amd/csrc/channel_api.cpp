@@ -22,11 +22,19 @@ struct vlb_channel {
     std::vector<vlb_channel_desc> d;
     std::vector<ChanDesc> desc;
     std::vector<double> tab;
-    std::vector<long long> base, cbase;   // first stage block / first cell of each instance
+    std::vector<long long> cbase;   // first cell of each instance
+    // stage launches: one per velocity-tile class (T1, T2), its instances and block offsets
+    struct Group {
+        int T1, T2;
+        std::vector<int> ilist;
+        std::vector<long long> base;
+        size_t off_ilist, off_base;
+    };
+    std::vector<Group> groups;
     size_t state_n = 0, ncells = 0;
     int threads = 64;
     char* ws = nullptr;
-    size_t off_F[3], off_rpart, off_resid, off_diag, off_tab, off_desc, off_base, off_cbase, total;
+    size_t off_F[3], off_rpart, off_resid, off_diag, off_tab, off_desc, off_cbase, total;
     bool have_resid = false;
 
     double* F(int i) { return (double*)(ws + off_F[i]); }
@@ -35,7 +43,8 @@ struct vlb_channel {
     double* diag() { return (double*)(ws + off_diag); }
     double* dtab() { return (double*)(ws + off_tab); }
     ChanDesc* ddesc() { return (ChanDesc*)(ws + off_desc); }
-    long long* dbase() { return (long long*)(ws + off_base); }
+    const int* gilist(const Group& g) { return (const int*)(ws + g.off_ilist); }
+    const long long* gbase(const Group& g) { return (const long long*)(ws + g.off_base); }
     long long* dcbase() { return (long long*)(ws + off_cbase); }
 };
 
@@ -91,7 +100,7 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         return &it->second;
     };
     size_t offF = 0, offC = 0;
-    long long blocks = 0, cells = 0;
+    long long cells = 0;
     for (int i = 0; i < B; ++i) {
         const vlb_channel_desc& d = descs[i];
         if (!(d.N_lambda >= 6 && d.N_xi >= 3 && d.xi_out > d.xi_in && d.r > 0 && d.L > 0 && d.Kn > 0 &&
@@ -108,9 +117,13 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
             return set_error(VLB_EINVAL, "instance %d: velocity set construction failed", i);
         }
         const int n1 = a1->nodes, n2 = a2->nodes, NV = n1 * n2, NL = d.N_lambda, NX = d.N_xi;
-        if (NV > kMaxNV || n1 + n2 > kWave) {
+        // velocity tiles of 16 x 16: at most two along one axis, not both
+        const int T1 = (n1 + 15) / 16, T2 = (n2 + 15) / 16;
+        if (T1 * T2 > 2) {
             delete c;
-            return set_error(VLB_EINVAL, "instance %d: %d velocities exceed the kernel limits", i, NV);
+            return set_error(VLB_EINVAL,
+                             "instance %d: %d x %d velocities exceed the kernel limits (16-node tiles: 1 x 1, 2 x 1 "
+                             "or 1 x 2)", i, n1, n2);
         }
         ChanDesc& D = c->desc[i];
         D = ChanDesc{};
@@ -209,15 +222,22 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
             return set_error(VLB_EUNSTABLE, "instance %d: dt=%g exceeds the stability limit %g", i, dt, 1.0 / inv1);
         }
         D.dt = dt;
-        c->base.push_back(blocks);
+        {
+            auto it = std::find_if(c->groups.begin(), c->groups.end(),
+                                   [&](const vlb_channel::Group& g) { return g.T1 == T1 && g.T2 == T2; });
+            if (it == c->groups.end()) {
+                c->groups.push_back(vlb_channel::Group{T1, T2, {}, {0}, 0, 0});
+                it = c->groups.end() - 1;
+            }
+            it->ilist.push_back(i);
+            it->base.push_back(it->base.back() + ((long long)NX * NL + kChanWaves - 1) / kChanWaves);
+        }
         c->cbase.push_back(cells);
-        blocks += 2LL * NX * NL;
         cells += (long long)NX * NL;
         offF += (size_t)2 * NX * NL * NV;
         offC += (size_t)NX * NL;
         c->threads = std::max(c->threads, (NV + kWave - 1) / kWave * kWave);
     }
-    c->base.push_back(blocks);
     c->cbase.push_back(cells);
     c->state_n = offF;
     c->ncells = offC;
@@ -228,7 +248,10 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
     c->off_diag = off; off = al256(off + c->ncells * 5 * sizeof(double));
     c->off_tab = off; off = al256(off + c->tab.size() * sizeof(double));
     c->off_desc = off; off = al256(off + B * sizeof(ChanDesc));
-    c->off_base = off; off = al256(off + (B + 1) * sizeof(long long));
+    for (auto& g : c->groups) {
+        g.off_ilist = off; off = al256(off + g.ilist.size() * sizeof(int));
+        g.off_base = off; off = al256(off + g.base.size() * sizeof(long long));
+    }
     c->off_cbase = off; off = al256(off + (B + 1) * sizeof(long long));
     c->total = off;
     void* p = nullptr;
@@ -241,8 +264,14 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
                                   c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->ddesc(), c->desc.data(), B * sizeof(ChanDesc), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(c->dbase(), c->base.data(), (B + 1) * sizeof(long long), hipMemcpyHostToDevice, c->stream);
+    for (auto& g : c->groups) {
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->ws + g.off_ilist, g.ilist.data(), g.ilist.size() * sizeof(int),
+                               hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->ws + g.off_base, g.base.data(), g.base.size() * sizeof(long long),
+                               hipMemcpyHostToDevice, c->stream);
+    }
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->dcbase(), c->cbase.data(), (B + 1) * sizeof(long long), hipMemcpyHostToDevice,
                            c->stream);
@@ -318,8 +347,6 @@ namespace {
 vlb_status channel_stage(vlb_channel* c, int stage, bool last, bool l_only, double* Lout) {
     ChanArgs A{};
     A.inst = c->ddesc();
-    A.base = c->dbase();
-    A.B = c->B;
     A.tab = c->dtab();
     A.rpart = nullptr;
     if (l_only) {
@@ -336,7 +363,12 @@ vlb_status channel_stage(vlb_channel* c, int stage, bool last, bool l_only, doub
         A.ca = 1.0 / 3.0; A.cb = 2.0 / 3.0; A.cc = 2.0 / 3.0;
         if (last) A.rpart = c->rpart();
     }
-    VLB_HIP_TRY(launch_channel_stage(c->base.back(), c->threads, c->stream, A));
+    for (const auto& g : c->groups) {
+        A.ilist = c->gilist(g);
+        A.base = c->gbase(g);
+        A.B = (int)g.ilist.size();
+        VLB_HIP_TRY(launch_channel_stage(g.T1, g.T2, g.base.back(), c->stream, A));
+    }
     return VLB_OK;
 }
 

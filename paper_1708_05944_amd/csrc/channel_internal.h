@@ -22,9 +22,15 @@ struct ChanDesc {
     int tdlam, tdchi, tvol, pad1; // [NL], [NX], cell volumes dchi dlambda [NX][NL]
 };
 
+constexpr int kChanWaves = 4;   // stage kernel: cells (one wavefront each) per block
+
+// One stage launch covers the instances of one velocity-tile class (T1 x T2 tiles of
+// 16 x 16 velocities): ilist[g] is the g-th instance of the class, whose cells occupy
+// blocks [base[g], base[g+1]) in groups of kChanWaves.
 struct ChanArgs {
     const ChanDesc* inst;
-    const long long* base;   // [B+1] first block of each instance (2 NX NL blocks each)
+    const int* ilist;        // [B] instance indices of the class
+    const long long* base;   // [B+1] first block of each listed instance
     int B;
     const double* tab;
     const void* Fin;
@@ -35,7 +41,7 @@ struct ChanArgs {
     int l_only;              // 1: out = L[Fin]
 };
 
-hipError_t launch_channel_stage(long long nblocks, int threads, hipStream_t st, const ChanArgs& A);
+hipError_t launch_channel_stage(int T1, int T2, long long nblocks, hipStream_t st, const ChanArgs& A);
 hipError_t launch_channel_reduce(int ninst, hipStream_t st, const ChanDesc* insts, const double* tab,
                                  const double* rpart, double* resid);
 hipError_t launch_channel_diag(long long ncells_total, int threads, hipStream_t st, const ChanDesc* insts,

@@ -3,18 +3,32 @@
 // Busuioc & Ambrus, arXiv:1708.05944, Sec. VI: the reduced BGK equation in the
 // coordinates (lambda, xi) with the orthonormal triad of Sec. VI.A, in conservative
 // form with respect to (lambda, chi^xi) (Eqs. canalie_boltz, canalie_V, chi_canalie).
-// One launch = one RK3 stage (Sec. III.A, Eq. rk3) for every cell of every instance.
-// A block owns one cell and one distribution (f' or f''), one thread per velocity:
-//   * FP64 block sums of the cell's moments (Sec. IV.A) -> n, u, T, tau = Kn/(nT)
-//     (Eq. canalie_tau) and the polynomial equilibrium (Sec. IV.D);
-//   * for cells within three of a wall, the wall density n_w of its xi column from the
-//     wall-bound WENO flux (Sec. VI.B.4 with Eq. nw, applied at lambda = -1 and +1);
+// One launch = one RK3 stage (Sec. III.A, Eq. rk3) for every cell of every instance of
+// one velocity-tile class.  A wavefront owns one cell and both distributions (f', f'');
+// a block is four independent wavefronts (four cells) and never synchronises.
+//
+// Velocities of a cell as 16 x 16 tiles of the (p^lambda node i, p^xi node j) grid,
+// zero-padded to whole tiles.  Lane l = 16 g + n, register c of tile (I, J) holds
+// i = 16 I + 4 c + g, j = 16 J + n.  With 16 p^xi nodes this is velocity k = 64 c + l:
+// every load and store of a register moves 512 contiguous bytes.
+//
+// Per cell:
+//   * FP64 wavefront sums of the cell's moments (Sec. IV.A) -> n, u, T and
+//     tau = Kn/(nT) (Eq. canalie_tau); the polynomial equilibrium (Sec. IV.D);
+//   * within three cells of a wall, the wall density n_w of the xi column from the
+//     wall-bound WENO flux (Sec. VI.B.4 with Eq. nw, at lambda = -1 and +1);
 //   * epsilon-free WENO-5 face values (Sec. III.C) on both lambda faces (upwinded by
 //     the sign of p^lambda) and both xi faces (upwinded by the sign of V^xi, which
 //     varies with the face and the velocity), reservoir ghosts at the channel ends;
-//   * the two connection terms with the four projected momentum derivatives
-//     (Sec. IV.C kernels) from an LDS copy of the cell's populations;
-//   * BGK, the Shu-Osher combination, and FP64 residual partials when asked.
+//   * the four projected momentum derivatives (Sec. IV.C kernels) as FP64 16x16x4
+//     MFMA products on the tiles, which land in the register layout above: the
+//     derivatives along p^lambda contract the tile rows (F is the second operand, in its
+//     own registers); those along p^xi contract the tile columns, with F as the first
+//     operand read back through a wavefront-private LDS transpose;
+//   * the two connection terms, BGK, the Shu-Osher combination and FP64 residual
+//     partials when asked.
+// Block b runs on XCD b mod 8; blocks are renumbered so that each XCD sweeps one
+// contiguous band of cells and the xi-neighbour columns stay in its L2.
 #include <hip/hip_runtime.h>
 
 #include "channel_internal.h"
@@ -25,9 +39,22 @@ namespace vlb {
 
 namespace {
 
-constexpr int kChanThreads = kMaxNV;   // upper bound of the block size (NV rounded to 64)
+typedef double dvec4 __attribute__((ext_vector_type(4)));
 
-// NQ sums over all threads of the block, in a fixed order (wavefront DPP sums, then the
+// order of the LDS operations of one wavefront (no cross-wavefront sharing)
+__device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+__device__ __forceinline__ int find_instance(const long long* base, int B, long long b) {
+    int lo = 0, hi = B - 1;   // largest i with base[i] <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// NQ sums over all threads of a block, in a fixed order (wavefront sums, then the
 // wavefront totals in wavefront order); every thread receives the totals.  sh holds
 // 16 NQ doubles.
 template <int NQ>
@@ -48,190 +75,331 @@ __device__ __forceinline__ void block_sums(double (&v)[NQ], double* sh) {
     __syncthreads();
 }
 
-__device__ __forceinline__ int find_instance(const long long* base, int B, long long b) {
-    int i = 0;
-    while (i + 1 < B && base[i + 1] <= b) ++i;
-    return i;
-}
+// Row order of the first MFMA operand that lands product row 4 r + g (the node of
+// register r in lane group g) where the register layout wants it.  The FP64 16x16x4
+// product holds row g + 4 r in register r of lane group g: already the wanted order.
+// (The FP32 16x16x4 product holds row 4 g + r there; its operand rows would be
+// permuted by m -> 4 (m mod 4) + m / 4.)
+__device__ __forceinline__ int mfma_row_f64(int m) { return m; }
 
 }  // namespace
 
-template <typename T>
-__global__ __launch_bounds__(kChanThreads) void channel_stage(ChanArgs A) {
-    __shared__ double sh[16 * 5];
-    __shared__ double ecoef[kEqStride];
-    __shared__ double gfac[kWave];
-    __shared__ T row[kMaxNV];
+template <int T1, int T2>
+__global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs A) {
+    constexpr int NT = T1 * T2, NI = 4 * NT;   // items (tile registers) per lane per distribution
+    constexpr int RS = 16 * T2 + 2;           // LDS row stride of the transpose buffer (doubles)
+    constexpr int S1 = 16 * T1 + 1, S2 = 16 * T2 + 1;   // LDS row strides of the kernel copies
+    __shared__ double k1s[16 * T1 * S1], kt1s[16 * T1 * S1], k2s[16 * T2 * S2], kt2s[16 * T2 * S2];
+    __shared__ double trs[kChanWaves][16 * T1 * RS];   // F of the cell, [i][j] (this distribution)
+    __shared__ double lcs[kChanWaves][16 * T1 * RS];   // L of the cell, [i][j]
+    __shared__ double gsh[kChanWaves][kWave];
+    __shared__ double ecs[kChanWaves][4 * (kMaxN + 1)];
 
-    const long long b = blockIdx.x;
-    const int inst = find_instance(A.base, A.B, b);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: scalar cell indexing
+    const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
+    // XCD-contiguous block numbering (blocks are dispatched to the 8 XCDs round robin)
+    const long long nb = gridDim.x, b = blockIdx.x;
+    const long long xcd = b & 7, q8 = nb >> 3, r8 = nb & 7;
+    const long long lb = xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3);
+    const int gi = find_instance(A.base, A.B, lb);
+    const int inst = A.ilist[gi];
     const ChanDesc& I = A.inst[inst];
     const int NL = I.NL, NX = I.NX, NV = I.NV, Q1 = I.Q1, Q2 = I.Q2;
-    const int ncell = NX * NL;
-    const long long loc = b - A.base[inst];
-    const int d = (int)(loc / ncell);
-    const int cell = (int)(loc - (long long)d * ncell);
-    const int p = cell / NL, s = cell - p * NL;
     const double* tab = A.tab + I.offT;
-    const int k = threadIdx.x;
-    const bool act = k < NV;
-    const int kk = act ? k : 0, vi = kk / Q2, vj = kk - vi * Q2;
-    const double pl = tab[I.tp1 + vi], px = tab[I.tp2 + vj];
-    const T* F = static_cast<const T*>(A.Fin) + I.offF;
-    auto at = [&](int dd, int pp, int ss) -> const T* { return F + (((size_t)dd * NX + pp) * NL + ss) * NV; };
-    const T eps = T(I.weno_eps);
 
-    // ---- moments of the cell (both distributions)
-    double m[5];
-    {
-        const double f0 = act ? (double)at(0, p, s)[k] : 0.0, f1 = act ? (double)at(1, p, s)[k] : 0.0;
-        m[0] = f0;
-        m[1] = pl * f0;
-        m[2] = px * f0;
-        m[3] = (pl * pl + px * px) * f0;
-        m[4] = f1;
+    // ---- the block's instance: momentum-derivative kernels into LDS, zero-padded
+    for (int x = threadIdx.x; x < 16 * T1 * 16 * T1; x += kChanWaves * kWave) {
+        const int r = x / (16 * T1), c = x - r * (16 * T1);
+        const bool ok = r < Q1 && c < Q1;
+        k1s[r * S1 + c] = ok ? tab[I.tK1 + r * Q1 + c] : 0.0;
+        kt1s[r * S1 + c] = ok ? tab[I.tKt1 + r * Q1 + c] : 0.0;
     }
-    block_sums<5>(m, sh);
+    for (int x = threadIdx.x; x < 16 * T2 * 16 * T2; x += kChanWaves * kWave) {
+        const int r = x / (16 * T2), c = x - r * (16 * T2);
+        const bool ok = r < Q2 && c < Q2;
+        k2s[r * S2 + c] = ok ? tab[I.tK2 + r * Q2 + c] : 0.0;
+        kt2s[r * S2 + c] = ok ? tab[I.tKt2 + r * Q2 + c] : 0.0;
+    }
+    __syncthreads();   // the only block-wide barrier; the wavefronts are independent below
+
+    const int cell = (int)((lb - A.base[gi]) * kChanWaves) + wave;
+    if (cell >= NX * NL) return;
+    const int p = cell / NL, s = cell - p * NL;
+    const double eps = I.weno_eps;
+    double* tr = trs[wave];
+    double* lcb = lcs[wave];
+    double* gf = gsh[wave];
+    double* ec = ecs[wave];
+
+    // ---- lane items: item t = (I T2 + J) 4 + c is node i = 16 I + 4 c + g, j = 16 J + n
+    double plv[T1][4], pxv[T2];
+#pragma unroll
+    for (int I_ = 0; I_ < T1; ++I_)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = 16 * I_ + 4 * c + g;
+            plv[I_][c] = i < Q1 ? tab[I.tp1 + i] : 0.0;
+        }
+#pragma unroll
+    for (int J = 0; J < T2; ++J) pxv[J] = 16 * J + n < Q2 ? tab[I.tp2 + 16 * J + n] : 0.0;
+    auto item_i = [&](int t) { return 16 * (t / (4 * T2)) + 4 * (t & 3) + g; };
+    auto item_j = [&](int t) { return 16 * ((t >> 2) % T2) + n; };
+    auto item_ok = [&](int t) { return item_i(t) < Q1 && item_j(t) < Q2; };
+    auto item_k = [&](int t) { return item_ok(t) ? item_i(t) * Q2 + item_j(t) : 0; };
+    auto item_pl = [&](int t) { return plv[t / (4 * T2)][t & 3]; };
+    auto item_px = [&](int t) { return pxv[(t >> 2) % T2]; };
+
+    const double* F = static_cast<const double*>(A.Fin) + I.offF;
+    const size_t dstride = (size_t)NX * NL * NV, xstride = (size_t)NL * NV;
+    const double* Fcell = F + ((size_t)p * NL + s) * NV;
+
+    // ---- moments of the cell (FP64 wavefront sums)
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0;
+#pragma unroll
+    for (int t = 0; t < NI; ++t) {
+        if (!item_ok(t)) continue;
+        const double f0 = Fcell[item_k(t)], f1 = Fcell[dstride + item_k(t)];
+        const double a = item_pl(t), c = item_px(t);
+        m0 += f0;
+        m1 += a * f0;
+        m2 += c * f0;
+        m3 += (a * a + c * c) * f0;
+        m4 += f1;
+    }
+    const double nd = wave_sum(m0), u1 = wave_sum(m1) / nd, u2 = wave_sum(m2) / nd;
+    const double Tc = (wave_sum(m3) + wave_sum(m4) - nd * (u1 * u1 + u2 * u2)) / (3.0 * nd);
+    const double itau = 1.0 / tau_of(I.tau_model, I.Kn, nd, Tc);
+
+    // ---- equilibrium factors g1(p^lambda_i), g2(p^xi_j) of the cell (LDS, this wavefront)
+    if (lane == 0) axis_coef(I.kind1, I.N1, u1, Tc, tab + I.tC1, tab + I.tisf1, ec, ec + (I.N1 + 1));
+    if (lane == 1)
+        axis_coef(I.kind2, I.N2, u2, Tc, tab + I.tC2, tab + I.tisf2, ec + 2 * (kMaxN + 1),
+                  ec + 2 * (kMaxN + 1) + (I.N2 + 1));
+    wave_lds_fence();
+    if (lane < Q1 + Q2) {
+        const bool ax1 = lane < Q1;
+        const int node = ax1 ? lane : lane - Q1;
+        const int nbas = ax1 ? I.N1 + 1 : I.N2 + 1;
+        const double* brow = tab + (ax1 ? I.tB1 : I.tB2) + node * nbas;
+        const double* co = ec + (ax1 ? 0 : 2 * (kMaxN + 1)) +
+                           (((ax1 ? I.kind1 : I.kind2) == 1 && node >= (ax1 ? I.Qh1 : I.Qh2)) ? nbas : 0);
+        double acc = 0.0;
+        for (int l = 0; l < nbas; ++l) acc += brow[l] * co[l];
+        gf[lane] = acc;
+    }
 
     // ---- wall densities of this xi column (lambda = -1: emitted p^lambda > 0; +1: < 0)
     double nw_lo = 0.0, nw_hi = 0.0;
-    const bool near_lo = s < 3, near_hi = s >= NL - 3;
-    if (near_lo || near_hi) {
-        double w[2] = {0.0, 0.0};
-        if (act && near_lo && pl < 0) {
-            const T F1 = at(0, p, 0)[k], F2 = at(0, p, 1)[k], F3 = at(0, p, 2)[k];
-            const T g0 = T(3) * F1 - T(3) * F2 + F3, gm1 = T(6) * F1 - T(8) * F2 + T(3) * F3;
-            w[0] = pl * (double)weno5<T>(F3, F2, F1, g0, gm1, eps);
-        }
-        if (act && near_hi && pl > 0) {
-            const T G1 = at(0, p, NL - 1)[k], G2 = at(0, p, NL - 2)[k], G3 = at(0, p, NL - 3)[k];
-            const T g0 = T(3) * G1 - T(3) * G2 + G3, gp1 = T(6) * G1 - T(8) * G2 + T(3) * G3;
-            w[1] = pl * (double)weno5<T>(G3, G2, G1, g0, gp1, eps);
-        }
-        block_sums<2>(w, sh);
-        nw_lo = -w[0] / I.den_lo;
-        nw_hi = -w[1] / I.den_hi;
-    }
-
-    // ---- equilibrium of the cell, and its populations in LDS for the force terms
-    if (threadIdx.x == 0) {
-        const double n = m[0], u1 = m[1] / n, u2 = m[2] / n;
-        const double T_ = (m[3] + m[4] - n * (u1 * u1 + u2 * u2)) / (3.0 * n);
-        ecoef[0] = n;
-        ecoef[1] = T_;
-        ecoef[2] = 1.0 / tau_of(I.tau_model, I.Kn, n, T_);
-        axis_coef(I.kind1, I.N1, u1, T_, tab + I.tC1, tab + I.tisf1, ecoef + 3, ecoef + 3 + (I.N1 + 1));
-        axis_coef(I.kind2, I.N2, u2, T_, tab + I.tC2, tab + I.tisf2, ecoef + 3 + 2 * (I.N1 + 1),
-                  ecoef + 3 + 2 * (I.N1 + 1) + (I.N2 + 1));
-    }
-    const T Fc = act ? at(d, p, s)[k] : T(0);
-    if (act) row[k] = Fc;
-    __syncthreads();
-    if (threadIdx.x < Q1 + Q2) {
-        const bool ax1 = threadIdx.x < Q1;
-        const int node = ax1 ? threadIdx.x : threadIdx.x - Q1;
-        const int nb = ax1 ? I.N1 + 1 : I.N2 + 1;
-        const double* brow = tab + (ax1 ? I.tB1 : I.tB2) + node * nb;
-        const int coff = ax1 ? 3 + ((I.kind1 == 1 && node >= I.Qh1) ? nb : 0)
-                             : 3 + 2 * (I.N1 + 1) + ((I.kind2 == 1 && node >= I.Qh2) ? nb : 0);
-        double g = 0.0;
-        for (int l = 0; l < nb; ++l) g += brow[l] * ecoef[coff + l];
-        gfac[threadIdx.x] = g;
-    }
-    __syncthreads();
-
-    double rd = 0.0, rn = 0.0;
-    T out = T(0);
-    if (act) {
-        // lambda stencil of column p: walls at both ends
-        const double fw = tab[I.tfw + d * NV + k];
-        auto lam_cell = [&](int c) -> T {
-            if (c >= 0 && c < NL) return at(d, p, c)[k];
-            if (c < 0) {
-                if (pl > 0) return T(nw_lo * fw);                         // Eq. weno_populate
-                const T F1 = at(d, p, 0)[k], F2 = at(d, p, 1)[k], F3 = at(d, p, 2)[k];
-                if (c == -1) return T(3) * F1 - T(3) * F2 + F3;           // Eq. extrapol
-                if (c == -2) return T(6) * F1 - T(8) * F2 + T(3) * F3;
-                return T(0);
+    if (s < 3) {
+        double w = 0.0;
+        const double* C0 = F + (size_t)p * NL * NV;
+#pragma unroll
+        for (int t = 0; t < NI; ++t)
+            if (item_ok(t) && item_pl(t) < 0) {
+                const int k = item_k(t);
+                const double F1 = C0[k], F2 = C0[NV + k], F3 = C0[2 * NV + k];
+                const double g0 = 3.0 * F1 - 3.0 * F2 + F3, gm1 = 6.0 * F1 - 8.0 * F2 + 3.0 * F3;
+                w += item_pl(t) * weno5<double>(F3, F2, F1, g0, gm1, eps);
             }
-            if (pl < 0) return T(nw_hi * fw);
-            const T G1 = at(d, p, NL - 1)[k], G2 = at(d, p, NL - 2)[k], G3 = at(d, p, NL - 3)[k];
-            if (c == NL) return T(3) * G1 - T(3) * G2 + G3;
-            if (c == NL + 1) return T(6) * G1 - T(8) * G2 + T(3) * G3;
-            return T(0);
-        };
-        T lw[7];
-#pragma unroll
-        for (int q = 0; q < 7; ++q) lw[q] = lam_cell(s - 3 + q);
-        T Fl, Fr;
-        if (pl > 0) {
-            Fl = weno5<T>(lw[0], lw[1], lw[2], lw[3], lw[4], eps);
-            Fr = weno5<T>(lw[1], lw[2], lw[3], lw[4], lw[5], eps);
-        } else {
-            Fl = weno5<T>(lw[5], lw[4], lw[3], lw[2], lw[1], eps);
-            Fr = weno5<T>(lw[6], lw[5], lw[4], lw[3], lw[2], eps);
-        }
-        // xi stencil of row s: reservoir Maxwellian for entering, the end cell for leaving
-        const double* xc = tab + I.txc;
-        const double* xa = tab + I.txa;
-        const double vin = xc[s] * (px - xa[s] * pl);
-        const double vout = xc[(size_t)NX * NL + s] * (px - xa[(size_t)NX * NL + s] * pl);
-        auto xi_cell = [&](int c) -> T {
-            if (c >= 0 && c < NX) return at(d, c, s)[k];
-            if (c < 0) return vin > 0 ? T(tab[I.tfin + d * NV + k]) : at(d, 0, s)[k];
-            return vout < 0 ? T(tab[I.tfout + d * NV + k]) : at(d, NX - 1, s)[k];
-        };
-        T xw[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) xw[q] = (q < 7) ? xi_cell(p - 3 + q) : T(0);
-        double Vx[2];
-        T Fx[2];
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int f = p + e;   // face between cells f - 1 and f; stencil index of cell c is c - p + 3
-            Vx[e] = xc[(size_t)f * NL + s] * (px - xa[(size_t)f * NL + s] * pl);
-            Fx[e] = Vx[e] > 0 ? weno5<T>(xw[e], xw[e + 1], xw[e + 2], xw[e + 3], xw[e + 4], eps)
-                              : weno5<T>(xw[e + 5], xw[e + 4], xw[e + 3], xw[e + 2], xw[e + 1], eps);
-        }
-        const double al = tab[I.tal + cell], ar = tab[I.tar + cell];
-        const double adv_l = pl * (ar * (double)Fr - al * (double)Fl) / tab[I.tdlam + s];
-        const double adv_x = (Vx[1] * (double)Fx[1] - Vx[0] * (double)Fx[0]) / tab[I.tdchi + p];
-        // momentum derivatives (Sec. IV.C) along p^lambda (i) and p^xi (j)
-        double k1 = 0.0, kt1 = 0.0, k2 = 0.0, kt2 = 0.0;
-        for (int ip = 0; ip < Q1; ++ip) {
-            const double r_ = (double)row[ip * Q2 + vj];
-            k1 += tab[I.tK1 + vi * Q1 + ip] * r_;
-            kt1 += tab[I.tKt1 + vi * Q1 + ip] * r_;
-        }
-        for (int jp = 0; jp < Q2; ++jp) {
-            const double r_ = (double)row[vi * Q2 + jp];
-            k2 += tab[I.tK2 + vj * Q2 + jp] * r_;
-            kt2 += tab[I.tKt2 + vj * Q2 + jp] * r_;
-        }
-        const double glxx = tab[I.tglxx + cell], gxll = -tab[I.tglxl + cell];
-        const double force = glxx * (px * px * k1 - pl * kt2) + gxll * (pl * pl * k2 - px * kt1);
-        double fe = ecoef[0] * gfac[vi] * gfac[Q1 + vj];
-        if (d) fe *= ecoef[1];
-        const double L = -adv_l - adv_x + force - ((double)Fc - fe) * ecoef[2];
-        if (A.l_only) {
-            out = T(L);
-        } else {
-            const size_t idx = (((size_t)d * NX + p) * NL + s) * NV + k;
-            const T fn = A.ca != 0.0 ? (static_cast<const T*>(A.Fn) + I.offF)[idx] : T(0);
-            out = T(A.ca) * fn + T(A.cb) * Fc + T(A.cc * I.dt) * T(L);
-            const double iw = tab[I.tiW + k];
-            rd = ((double)out - (double)fn) * ((double)out - (double)fn) * iw;
-            rn = (double)fn * (double)fn * iw;
-        }
-        (static_cast<T*>(A.Fout) + I.offF)[(((size_t)d * NX + p) * NL + s) * NV + k] = out;
+        nw_lo = -wave_sum(w) / I.den_lo;
     }
-    if (A.rpart) {
-        double r[2] = {rd, rn};
-        block_sums<2>(r, sh);
-        if (threadIdx.x == 0) {
-            const double vol = tab[I.tvol + cell];
-            A.rpart[((size_t)(I.offC + cell) * 2 + d) * 2] = vol * r[0];
-            A.rpart[((size_t)(I.offC + cell) * 2 + d) * 2 + 1] = vol * r[1];
+    if (s >= NL - 3) {
+        double w = 0.0;
+        const double* C0 = F + ((size_t)p * NL + NL - 1) * NV;
+#pragma unroll
+        for (int t = 0; t < NI; ++t)
+            if (item_ok(t) && item_pl(t) > 0) {
+                const int k = item_k(t);
+                const double G1 = C0[k], G2 = C0[k - NV], G3 = C0[k - 2 * NV];
+                const double g0 = 3.0 * G1 - 3.0 * G2 + G3, gp1 = 6.0 * G1 - 8.0 * G2 + 3.0 * G3;
+                w += item_pl(t) * weno5<double>(G3, G2, G1, g0, gp1, eps);
+            }
+        nw_hi = -wave_sum(w) / I.den_hi;
+    }
+
+    // ---- per-cell geometry
+    const double glxx = tab[I.tglxx + cell], gxll = -tab[I.tglxl + cell];
+    const double al = tab[I.tal + cell], ar = tab[I.tar + cell];
+    const double idl = 1.0 / tab[I.tdlam + s], idx = 1.0 / tab[I.tdchi + p];
+    const double* xc = tab + I.txc;
+    const double* xa = tab + I.txa;
+    const double xc0 = xc[(size_t)p * NL + s], xa0 = xa[(size_t)p * NL + s];
+    const double xc1 = xc[(size_t)(p + 1) * NL + s], xa1 = xa[(size_t)(p + 1) * NL + s];
+    const double xcin = xc[s], xain = xa[s], xcout = xc[(size_t)NX * NL + s], xaout = xa[(size_t)NX * NL + s];
+    const bool lam_interior = s >= 3 && s < NL - 3, xi_interior = p >= 3 && p < NX - 3;
+    const bool lonly = A.l_only != 0;
+    const double dt = lonly ? 1.0 : I.dt, ca = A.ca, cb = A.cb, ccdt = A.cc * dt;
+    const double* iW = tab + I.tiW;
+    wave_lds_fence();
+    double g1v[T1][4], g2v[T2];
+#pragma unroll
+    for (int I_ = 0; I_ < T1; ++I_)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) g1v[I_][c] = 16 * I_ + 4 * c + g < Q1 ? gf[16 * I_ + 4 * c + g] : 0.0;
+#pragma unroll
+    for (int J = 0; J < T2; ++J) g2v[J] = 16 * J + n < Q2 ? gf[Q1 + 16 * J + n] : 0.0;
+
+#pragma unroll 1
+    for (int d = 0; d < 2; ++d) {
+        const double* Fd = Fcell + d * dstride;
+        const double* fw = tab + I.tfw + d * NV;
+        double fc[NI];
+#pragma unroll
+        for (int t = 0; t < NI; ++t) fc[t] = item_ok(t) ? Fd[item_k(t)] : 0.0;
+
+        // momentum derivatives (Sec. IV.C) as 16x16x4 MFMA products:
+        //   d/dp^lambda: K1 F, Kt1 F (F in its own registers);
+        //   d/dp^xi:     F K2^T, F Kt2^T (F from the transpose buffer)
+#pragma unroll
+        for (int t = 0; t < NI; ++t) tr[item_i(t) * RS + item_j(t)] = fc[t];
+        wave_lds_fence();
+#pragma unroll
+        for (int I_ = 0; I_ < T1; ++I_)
+#pragma unroll
+            for (int J = 0; J < T2; ++J) {
+                dvec4 k1 = {0, 0, 0, 0}, kt1 = {0, 0, 0, 0}, k2 = {0, 0, 0, 0}, kt2 = {0, 0, 0, 0};
+                const int prow = 16 * I_ + mfma_row_f64(n);
+#pragma unroll
+                for (int I2 = 0; I2 < T1; ++I2)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const double bf = fc[(I2 * T2 + J) * 4 + c];
+                        const int col = 16 * I2 + 4 * c + g;
+                        k1 = __builtin_amdgcn_mfma_f64_16x16x4f64(k1s[prow * S1 + col], bf, k1, 0, 0, 0);
+                        kt1 = __builtin_amdgcn_mfma_f64_16x16x4f64(kt1s[prow * S1 + col], bf, kt1, 0, 0, 0);
+                    }
+#pragma unroll
+                for (int J2 = 0; J2 < T2; ++J2)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int col = 16 * J2 + 4 * c + g;
+                        const double af = tr[prow * RS + col];
+                        k2 = __builtin_amdgcn_mfma_f64_16x16x4f64(af, k2s[(16 * J + n) * S2 + col], k2, 0, 0, 0);
+                        kt2 = __builtin_amdgcn_mfma_f64_16x16x4f64(af, kt2s[(16 * J + n) * S2 + col], kt2, 0, 0, 0);
+                    }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int t = (I_ * T2 + J) * 4 + c;
+                    const double a = item_pl(t), q = item_px(t);
+                    lcb[item_i(t) * RS + item_j(t)] =
+                        glxx * (q * q * k1[c] - a * kt2[c]) + gxll * (a * a * k2[c] - q * kt1[c]);
+                }
+            }
+        wave_lds_fence();   // the buffer is rewritten for the next distribution
+
+        // advection through the four faces: a rolled loop over the lane's items (their F
+        // and L live in this lane's slots of the LDS rows), one item in registers at a time
+#pragma unroll 1
+        for (int t = 0; t < NI; ++t) {
+            const int i = 16 * (t / (4 * T2)) + 4 * (t & 3) + g, j = 16 * ((t >> 2) % T2) + n;
+            if (i >= Q1 || j >= Q2) continue;
+            const int k = i * Q2 + j;
+            const double plt = tab[I.tp1 + i], pxt = tab[I.tp2 + j];
+            const double fct = tr[i * RS + j];
+            double lw[7];
+            if (lam_interior) {
+#pragma unroll
+                for (int q = 0; q < 7; ++q) lw[q] = q == 3 ? fct : Fd[(q - 3) * NV + k];
+            } else {
+                const double* Col = Fd - (size_t)s * NV;   // cell (p, 0)
+#pragma unroll
+                for (int q = 0; q < 7; ++q) {
+                    const int cc = s - 3 + q;
+                    double v;
+                    if (cc >= 0 && cc < NL) {
+                        v = Col[(size_t)cc * NV + k];
+                    } else if (cc < 0) {
+                        if (plt > 0) {
+                            v = nw_lo * fw[k];                                   // Eq. weno_populate
+                        } else {
+                            const double F1 = Col[k], F2 = Col[NV + k], F3 = Col[2 * NV + k];
+                            v = cc == -1 ? 3.0 * F1 - 3.0 * F2 + F3                // Eq. extrapol
+                                         : cc == -2 ? 6.0 * F1 - 8.0 * F2 + 3.0 * F3 : 0.0;
+                        }
+                    } else {
+                        if (plt < 0) {
+                            v = nw_hi * fw[k];
+                        } else {
+                            const double G1 = Col[(size_t)(NL - 1) * NV + k], G2 = Col[(size_t)(NL - 2) * NV + k],
+                                         G3 = Col[(size_t)(NL - 3) * NV + k];
+                            v = cc == NL ? 3.0 * G1 - 3.0 * G2 + G3
+                                         : cc == NL + 1 ? 6.0 * G1 - 8.0 * G2 + 3.0 * G3 : 0.0;
+                        }
+                    }
+                    lw[q] = v;
+                }
+            }
+            double xw[7];
+            if (xi_interior) {
+#pragma unroll
+                for (int q = 0; q < 7; ++q)
+                    xw[q] = q == 3 ? fct : Fd[(ptrdiff_t)(q - 3) * (ptrdiff_t)xstride + k];
+            } else {
+                const double vin = xcin * (pxt - xain * plt), vout = xcout * (pxt - xaout * plt);
+                const double* Row = Fd - (size_t)p * xstride;   // cell (0, s)
+#pragma unroll
+                for (int q = 0; q < 7; ++q) {
+                    const int cc = p - 3 + q;
+                    double v;
+                    if (cc >= 0 && cc < NX) v = Row[(size_t)cc * xstride + k];
+                    else if (cc < 0) v = vin > 0 ? tab[I.tfin + d * NV + k] : Row[k];
+                    else v = vout < 0 ? tab[I.tfout + d * NV + k] : Row[(size_t)(NX - 1) * xstride + k];
+                    xw[q] = v;
+                }
+            }
+            // faces s -+ 1/2 between window cells 2|3 and 3|4, upwinded by the sign of p^lambda;
+            // faces p -+ 1/2 likewise by the sign of V^xi on each face
+            // (one face at a time: the four WENO chains are kept from being interleaved, which
+            // would raise the register demand past four wavefronts per SIMD)
+            const bool pos = plt > 0;
+            const double Fl = weno_face<double>(pos, lw[0], lw[1], lw[2], lw[3], lw[4], lw[5], eps);
+            double adv_l = -al * Fl;
+            __builtin_amdgcn_sched_barrier(0);
+            const double Fr = weno_face<double>(pos, lw[1], lw[2], lw[3], lw[4], lw[5], lw[6], eps);
+            adv_l += ar * Fr;
+            __builtin_amdgcn_sched_barrier(0);
+            const double V0 = xc0 * (pxt - xa0 * plt), V1 = xc1 * (pxt - xa1 * plt);
+            const double X0 = weno_face<double>(V0 > 0, xw[0], xw[1], xw[2], xw[3], xw[4], xw[5], eps);
+            double adv_x = -V0 * X0;
+            __builtin_amdgcn_sched_barrier(0);
+            const double X1 = weno_face<double>(V1 > 0, xw[1], xw[2], xw[3], xw[4], xw[5], xw[6], eps);
+            adv_x += V1 * X1;
+            lcb[i * RS + j] -= plt * adv_l * idl + adv_x * idx;
+        }
+
+        // BGK, RK combination, store, residual partials
+        const double* Fn = A.Fn ? static_cast<const double*>(A.Fn) + I.offF + d * dstride +
+                                      ((size_t)p * NL + s) * NV
+                                : nullptr;
+        double* Fo = static_cast<double*>(A.Fout) + I.offF + d * dstride + ((size_t)p * NL + s) * NV;
+        double rd = 0.0, rn = 0.0;
+#pragma unroll
+        for (int t = 0; t < NI; ++t) {
+            if (!item_ok(t)) continue;
+            const int k = item_k(t);
+            double fe = nd * g1v[t / (4 * T2)][t & 3] * g2v[(t >> 2) % T2];
+            if (d) fe *= Tc;
+            const double L = lcb[item_i(t) * RS + item_j(t)] - (fc[t] - fe) * itau;
+            double out;
+            if (lonly) {
+                out = L;
+            } else {
+                const double fn = ca != 0.0 ? Fn[k] : 0.0;
+                out = ca * fn + cb * fc[t] + ccdt * L;
+                const double iw = iW[k];
+                rd += (out - fn) * (out - fn) * iw;
+                rn += fn * fn * iw;
+            }
+            Fo[k] = out;
+        }
+        if (A.rpart) {
+            rd = wave_sum(rd);
+            rn = wave_sum(rn);
+            if (lane == 0) {
+                const double vol = tab[I.tvol + cell];
+                A.rpart[((size_t)(I.offC + cell) * 2 + d) * 2] = vol * rd;
+                A.rpart[((size_t)(I.offC + cell) * 2 + d) * 2 + 1] = vol * rn;
+            }
         }
     }
 }
@@ -260,7 +428,7 @@ __global__ __launch_bounds__(256) void channel_reduce(const ChanDesc* insts, con
 }
 
 // n, u^lambda, u^xi, T and the particle content vol * n of every cell.
-__global__ __launch_bounds__(kChanThreads) void channel_diag(const ChanDesc* insts, const long long* cbase, int B,
+__global__ __launch_bounds__(kMaxNV) void channel_diag(const ChanDesc* insts, const long long* cbase, int B,
                                                              const double* tab_all, const double* F, double* diag) {
     __shared__ double sh[16 * 5];
     const long long b = blockIdx.x;
@@ -288,8 +456,12 @@ __global__ __launch_bounds__(kChanThreads) void channel_diag(const ChanDesc* ins
     }
 }
 
-hipError_t launch_channel_stage(long long nblocks, int threads, hipStream_t st, const ChanArgs& A) {
-    hipLaunchKernelGGL(channel_stage<double>, dim3((unsigned)nblocks), dim3(threads), 0, st, A);
+hipError_t launch_channel_stage(int T1, int T2, long long nblocks, hipStream_t st, const ChanArgs& A) {
+    const dim3 grid((unsigned)nblocks), block(kChanWaves * kWave);
+    if (T1 == 1 && T2 == 1) hipLaunchKernelGGL((channel_stage<1, 1>), grid, block, 0, st, A);
+    else if (T1 == 2 && T2 == 1) hipLaunchKernelGGL((channel_stage<2, 1>), grid, block, 0, st, A);
+    else if (T1 == 1 && T2 == 2) hipLaunchKernelGGL((channel_stage<1, 2>), grid, block, 0, st, A);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -44,6 +44,8 @@ CASES = [
     dict(N_lambda=7, N_xi=13, ax1=(1, 5, 4), ax2=(0, 7, 4), Kn=0.3, r=3.0, L=2.0),            # p^xi = 0 node, steep
     dict(N_lambda=10, N_xi=6, ax1=(1, 6, 4), ax2=(0, 8, 4), Kn=0.1, r=1.0),                   # straight channel
     dict(N_lambda=6, N_xi=11, ax1=(1, 4, 3), ax2=(0, 5, 4), Kn=0.2, weno_eps=1e-6, n_in=1.2),  # regularised WENO
+    dict(N_lambda=7, N_xi=8, ax1=(1, 12, 4), ax2=(0, 8, 4), Kn=0.08),                         # 24 x 8: two p^lambda tiles
+    dict(N_lambda=6, N_xi=7, ax1=(1, 4, 3), ax2=(0, 20, 4), Kn=0.15, r=2.5),                  # 8 x 20: two p^xi tiles
 ]
 
 
@@ -96,7 +98,9 @@ def test_channel_steps_match_oracle():
 
 def test_channel_uneven_batch_matches_oracle():
     from paper_1708_05944_amd import Channel
-    pairs = [_pair(**dict(CASES[0])), _pair(**dict(CASES[2])), _pair(**dict(CASES[1]))]
+    # three velocity-tile classes in one batch (one launch per class)
+    pairs = [_pair(**dict(CASES[0])), _pair(**dict(CASES[5])), _pair(**dict(CASES[2])), _pair(**dict(CASES[6])),
+             _pair(**dict(CASES[1]))]
     c = Channel([p[1] for p in pairs])
     st = c.get_state()
     inits = []
