@@ -229,8 +229,11 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
                 c->groups.push_back(vlb_channel::Group{T1, T2, {}, {0}, 0, 0});
                 it = c->groups.end() - 1;
             }
+            // lambda strips of up to kChanStrip cells (a multiple of kChanWaves)
+            D.strip = std::min(kChanStrip, (NL + kChanWaves - 1) / kChanWaves * kChanWaves);
+            const long long nstrips = (NL + D.strip - 1) / D.strip;
             it->ilist.push_back(i);
-            it->base.push_back(it->base.back() + ((long long)NX * NL + kChanWaves - 1) / kChanWaves);
+            it->base.push_back(it->base.back() + nstrips * NX * (D.strip / kChanWaves));
         }
         c->cbase.push_back(cells);
         cells += (long long)NX * NL;

@@ -19,10 +19,12 @@ struct ChanDesc {
     int tal, tar, tglxx, tglxl;   // per cell [NX][NL]: V^lambda factors of the left / right lambda
                                   // faces, connection coefficients G_lxx, G_lxl
     int txc, txa;                 // per (xi face, lambda row) [NX+1][NL]: V^xi = c (p^xi - a p^lambda)
-    int tdlam, tdchi, tvol, pad1; // [NL], [NX], cell volumes dchi dlambda [NX][NL]
+    int tdlam, tdchi, tvol;       // [NL], [NX], cell volumes dchi dlambda [NX][NL]
+    int strip;                    // stage-kernel traversal: lambda strips of `strip` cells, swept along xi
 };
 
 constexpr int kChanWaves = 4;   // stage kernel: cells (one wavefront each) per block
+constexpr int kChanStrip = 32;  // stage kernel: lambda-strip width of the traversal (cells)
 
 // One stage launch covers the instances of one velocity-tile class (T1 x T2 tiles of
 // 16 x 16 velocities): ilist[g] is the g-th instance of the class, whose cells occupy

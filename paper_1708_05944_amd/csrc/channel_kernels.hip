@@ -122,9 +122,15 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
     }
     __syncthreads();   // the only block-wide barrier; the wavefronts are independent below
 
-    const int cell = (int)((lb - A.base[gi]) * kChanWaves) + wave;
-    if (cell >= NX * NL) return;
-    const int p = cell / NL, s = cell - p * NL;
+    // blocks of an instance: lambda strips of W cells, each swept along xi, kChanWaves
+    // consecutive lambda cells per block (the stencil neighbours of a block are then
+    // recent blocks of the same XCD)
+    const int W = I.strip, bpw = W / kChanWaves;
+    const int lbi = (int)(lb - A.base[gi]);
+    const int strip = lbi / (NX * bpw), rem = lbi - strip * (NX * bpw);
+    const int p = rem / bpw, s = strip * W + (rem - p * bpw) * kChanWaves + wave;
+    if (s >= NL) return;
+    const int cell = p * NL + s;
     const double eps = I.weno_eps;
     double* tr = trs[wave];
     double* lcb = lcs[wave];

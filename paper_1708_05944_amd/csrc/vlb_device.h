@@ -49,13 +49,21 @@ __device__ __forceinline__ double row_sum(double v) {
 }
 
 // 1/x: the hardware reciprocal in FP32 (about 1 ulp, the FP32 path's tolerance is far
-// wider); a correctly rounded division in FP64.
+// wider); in FP64 the hardware estimate refined by two Newton steps r <- r + r (1 - x r)
+// (each squares the relative error; the result is within an ulp or so of 1/x, for the
+// normal, positive arguments the WENO weights take; x = 0 gives NaN, like 0 * (1/0)).
 template <typename T>
 __device__ __forceinline__ T recip(T x);
 template <>
 __device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <>
-__device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
+__device__ __forceinline__ double recip<double>(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
 
 // Flux at the face between c and d, upwinded from c (a, b, c, d, e in upwind order).
 template <typename T>
