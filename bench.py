@@ -30,6 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # FP32 vector peak with plain (non-packed) FMAs, 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz;
 # the library is built with packed FP32 instructions disabled, so 157.3 TFLOP/s is out of reach
 VALU_FP32_TFLOPS = 78.6
+VALU_FP64_TFLOPS = 78.6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "couette_stage_traffic.json")
 
 
@@ -43,6 +44,13 @@ def stage_flops(descs) -> float:
         n2 = d.ax2[1] * (2 if d.ax2[0] == 1 else 1)
         tot += d.N_R * n1 * n2 * (2 * (54 + 2 * n1 + 2 * n2 + 5 + 8) + 13)
     return tot
+
+
+def channel_stage_flops(cells: int, q1: int, q2: int) -> float:
+    """Algorithmic flops of one channel RK stage: per site-velocity, two distributions x
+    (four WENO-5 faces ~4 x 54, the four momentum-derivative contractions 2 (2 Q1 + 2 Q2),
+    advection, BGK and combination ~18), plus ~13 for moments and the equilibrium."""
+    return cells * q1 * q2 * (2 * (4 * 54 + 4 * (q1 + q2) + 18) + 13)
 
 
 def measured_traffic(kernel: str):
@@ -181,17 +189,31 @@ def main():
         ch.step(2)
         torch.cuda.synchronize()
         nst = max(2, args.steps // 2)
+        # HIP events on the stream the library launches on (the current torch stream): the
+        # nst steps are 3 nst stage launches plus one residual reduction (~0.15 ms)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
+        e0.record()
         ch.step(nst)
+        e1.record()
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        stage_ms = e0.elapsed_time(e1) / (3 * nst)
         sv = cd.N_lambda * cd.N_xi * 16 * 16
-        gbs = sv * nst * 128 / el / 1e9
+        bytes_launch = sv * 128 / 3          # FP64: read F (16 B), F_n in 2 of 3 stages, write (16 B)
+        flops_launch = channel_stage_flops(cd.N_lambda * cd.N_xi, 16, 16)
+        gbs = bytes_launch / (stage_ms * 1e-3) / 1e9
+        tfs = flops_launch / (stage_ms * 1e-3) / 1e12
         channel = {"workload": "expanding channel 512 x 128 cells, HH(4;8) x H(4;16) (256 velocities), Kn 0.05, "
                                "ratio 2 over 4 widths, reservoirs n 1.1 / 0.9, FP64",
                    "value": sv * nst / el, "unit": "site-velocity updates/s", "ms_per_step": el / nst * 1e3,
-                   "steps": nst, "achieved_GBps_wallclock": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
-                   "dt": ch.info[0]["dt"]}
+                   "steps": nst, "dt": ch.info[0]["dt"],
+                   "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic("channel_stage<1, 1>"),
+                                "kernel": "channel_stage<1, 1>", "avg_launch_ms": stage_ms,
+                                "alg_bytes_per_launch": bytes_launch,
+                                "alu": {"achieved_TFLOPs": tfs, "peak_TFLOPs": VALU_FP64_TFLOPS,
+                                        "frac": tfs / VALU_FP64_TFLOPS, "alg_flops_per_launch": flops_launch}}}
         ch.close()
 
     warm = None
