@@ -292,10 +292,10 @@ vlb_status vlb_batch_warm_start(vlb_batch* b, vlb_mlp* m, int probe_steps, int* 
  * canalie_phi rescaled to these asymptotes), in the coordinates lambda = x / (1 + phi)
  * in [-1, 1] and xi = y in [xi_in, xi_out], with the orthonormal triad of Sec. VI.A so
  * that p^lambda is normal to both walls.  N_lambda x N_xi equal cells in (lambda, xi).
- * Diffuse walls at rest with temperature T_w at lambda = -1 and +1 (Sec. VI.B.4, both
+ * Diffuse walls at rest with temperature T_w at lambda = -1 and +1 (Sec. VI.C.4, both
  * walls: the full channel width); reservoir ends: populations entering through the
  * inlet (outlet) see ghost cells at the Maxwellian f_eq(n_in (n_out), 0, T_w), leaving
- * ones the nearest interior cell (the construction of Sec. VI.B.1 with the density
+ * ones the nearest interior cell (the construction of Sec. VI.C.1 with the density
  * fixed).  ax1 is the p^lambda axis and must be half range (kind 1); ax2 the p^xi axis.
  * tau_model as for the Couette instances (Sec. VI uses VLB_TAU_HYDRO, Eq. canalie_tau).
  * State of an instance: [2][N_xi][N_lambda][NV] doubles (f', f''; xi cell; lambda cell;

@@ -10,10 +10,10 @@
  * with G_xll = -G_lxl (antisymmetry of the connection), G_lxl and G_lxx discretised as
  * in Sec. VI.A so that a uniform Maxwellian is an exact solution, tau = Kn/(nT)
  * (Eq. canalie_tau), epsilon-free WENO-5 fluxes (Sec. III.C) upwinded by the sign of the
- * face velocity, diffuse walls at lambda = -1 and +1 (Sec. VI.B.4 applied at both walls:
+ * face velocity, diffuse walls at lambda = -1 and +1 (Sec. VI.C.4 applied at both walls:
  * the full channel width), and reservoir ends: at the inlet (outlet) the populations
  * entering the domain see ghost cells at f_eq(n_in (n_out), 0, T_w) and the leaving
- * ones a zeroth-order extrapolation (the construction of Sec. VI.B.1 with the
+ * ones a zeroth-order extrapolation (the construction of Sec. VI.C.1 with the
  * density fixed instead of the flow rate).
  *
  * State layout: F[d][p][s][k], d = f' / f'', p = xi cell (0..NX-1), s = lambda cell

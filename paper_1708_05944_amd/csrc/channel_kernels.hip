@@ -16,7 +16,7 @@
 //   * FP64 wavefront sums of the cell's moments (Sec. IV.A) -> n, u, T and
 //     tau = Kn/(nT) (Eq. canalie_tau); the polynomial equilibrium (Sec. IV.D);
 //   * within three cells of a wall, the wall density n_w of the xi column from the
-//     wall-bound WENO flux (Sec. VI.B.4 with Eq. nw, at lambda = -1 and +1);
+//     wall-bound WENO flux (Sec. VI.C.4 with Eq. nw, at lambda = -1 and +1);
 //   * epsilon-free WENO-5 face values (Sec. III.C) on both lambda faces (upwinded by
 //     the sign of p^lambda) and both xi faces (upwinded by the sign of V^xi, which
 //     varies with the face and the velocity), reservoir ghosts at the channel ends;
