@@ -181,40 +181,48 @@ def main():
     channel = None
     if not args.no_channel:
         # expanding channel, 512 x 128 cells, HH(4;8) x H(4;16) = 256 velocities, Kn = 0.05,
-        # pressure-driven (n 1.1 -> 0.9), expansion ratio 2 over 4 widths; FP64
+        # pressure-driven (n 1.1 -> 0.9), expansion ratio 2 over 4 widths; mixed precision
+        # (FP32 stage kernel with FP32 MFMA contractions, FP64 sums) and FP64
         from paper_1708_05944_amd import Channel, ChannelDesc
         cd = ChannelDesc(N_lambda=128, N_xi=512, xi_in=-4.0, xi_out=12.0, r=2.0, L=4.0, ax1=(1, 8, 4),
                          ax2=(0, 16, 4), Kn=0.05, tau_model=1, n_in=1.1, n_out=0.9, T_w=1.0)
-        ch = Channel([cd])
-        ch.step(2)
-        torch.cuda.synchronize()
-        nst = max(2, args.steps // 2)
-        # HIP events on the stream the library launches on (the current torch stream): the
-        # nst steps are 3 nst stage launches plus one residual reduction (~0.15 ms)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        e0.record()
-        ch.step(nst)
-        e1.record()
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        stage_ms = e0.elapsed_time(e1) / (3 * nst)
         sv = cd.N_lambda * cd.N_xi * 16 * 16
-        bytes_launch = sv * 128 / 3          # FP64: read F (16 B), F_n in 2 of 3 stages, write (16 B)
         flops_launch = channel_stage_flops(cd.N_lambda * cd.N_xi, 16, 16)
-        gbs = bytes_launch / (stage_ms * 1e-3) / 1e9
-        tfs = flops_launch / (stage_ms * 1e-3) / 1e12
+
+        def channel_leg(precision, elem_bytes, kernel, peak_tf):
+            ch = Channel([cd], precision=precision)
+            ch.step(2)
+            torch.cuda.synchronize()
+            nst = max(2, args.steps // 2)
+            # HIP events on the stream the library launches on (the current torch stream):
+            # the nst steps are 3 nst stage launches plus one residual reduction (~0.15 ms)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record()
+            ch.step(nst)
+            e1.record()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            stage_ms = e0.elapsed_time(e1) / (3 * nst)
+            dt = ch.info[0]["dt"]
+            ch.close()
+            bytes_launch = sv * 16 * elem_bytes / 3      # read F, F_n in 2 of 3 stages, write
+            gbs = bytes_launch / (stage_ms * 1e-3) / 1e9
+            tfs = flops_launch / (stage_ms * 1e-3) / 1e12
+            return {"value": sv * nst / el, "unit": "site-velocity updates/s", "ms_per_step": el / nst * 1e3,
+                    "steps": nst, "dt": dt,
+                    "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(kernel), "kernel": kernel,
+                                 "avg_launch_ms": stage_ms, "alg_bytes_per_launch": bytes_launch,
+                                 "alu": {"achieved_TFLOPs": tfs, "peak_TFLOPs": peak_tf, "frac": tfs / peak_tf,
+                                         "alg_flops_per_launch": flops_launch}}}
+
+        mixed_ch = channel_leg(VLB_MIXED, 4, "channel_stage<float, 1, 1>", VALU_FP32_TFLOPS)
+        fp64_ch = channel_leg(0, 8, "channel_stage<double, 1, 1>", VALU_FP64_TFLOPS)
         channel = {"workload": "expanding channel 512 x 128 cells, HH(4;8) x H(4;16) (256 velocities), Kn 0.05, "
-                               "ratio 2 over 4 widths, reservoirs n 1.1 / 0.9, FP64",
-                   "value": sv * nst / el, "unit": "site-velocity updates/s", "ms_per_step": el / nst * 1e3,
-                   "steps": nst, "dt": ch.info[0]["dt"],
-                   "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic("channel_stage<1, 1>"),
-                                "kernel": "channel_stage<1, 1>", "avg_launch_ms": stage_ms,
-                                "alg_bytes_per_launch": bytes_launch,
-                                "alu": {"achieved_TFLOPs": tfs, "peak_TFLOPs": VALU_FP64_TFLOPS,
-                                        "frac": tfs / VALU_FP64_TFLOPS, "alg_flops_per_launch": flops_launch}}}
-        ch.close()
+                               "ratio 2 over 4 widths, reservoirs n 1.1 / 0.9; mixed = FP32 stage kernel on "
+                               "weight-scaled populations with FP32 MFMA contractions and FP64 sums",
+                   **mixed_ch, "dtype": "f32", "fp64": fp64_ch}
 
     warm = None
     if not args.no_warm:

@@ -300,8 +300,14 @@ vlb_status vlb_batch_warm_start(vlb_batch* b, vlb_mlp* m, int probe_steps, int* 
  * tau_model as for the Couette instances (Sec. VI uses VLB_TAU_HYDRO, Eq. canalie_tau).
  * State of an instance: [2][N_xi][N_lambda][NV] doubles (f', f''; xi cell; lambda cell;
  * k = i * Q2 + j); the initial state is the rest Maxwellian n = 1, u = 0, T = T_w.
- * FP64 only; one block per cell and distribution.  dt = 0 picks cfl / (max advective
- * rate + force-operator bound / sqrt(3)), capped at 2 tau of the rest state. */
+ * Velocity sets of at most 32 x 16 or 16 x 32 nodes (tiles of 16 x 16, at most two).
+ * precision VLB_FP64 or VLB_MIXED; the mixed form keeps a second state in FP32, scaled
+ * by 1/(w_i w_j), on which vlb_channel_step runs (moment, wall-flux and residual sums
+ * stay FP64), and finishes vlb_channel_run_to_steady in FP64.  The state crosses this
+ * interface in FP64 in both forms.  dt = 0 picks cfl / (max advective rate +
+ * force-operator bound / sqrt(3)), capped at 2 tau of the rest state.  Errors:
+ * VLB_EINVAL (bad descriptor or velocity set too large), VLB_EUNSTABLE (explicit dt
+ * above the limit), VLB_ENOMEM, VLB_EDEVICE. */
 typedef struct {
     int N_lambda, N_xi;
     double xi_in, xi_out;
@@ -323,11 +329,17 @@ vlb_status vlb_channel_info(const vlb_channel* c, int inst, int* N_lambda, int* 
 vlb_status vlb_channel_state_size(const vlb_channel* c, size_t* n_doubles);
 vlb_status vlb_channel_set_state(vlb_channel* c, const double* host, size_t n);
 vlb_status vlb_channel_get_state(vlb_channel* c, double* host, size_t n);
-/* nsteps RK3 steps; the last records the residual (same definition as for Couette,
- * volumes dchi dlambda). */
+/* nsteps RK3 steps in the batch's precision (FP32 for VLB_MIXED); the last records the
+ * residual (same definition as for Couette, volumes dchi dlambda).  Enqueued on the
+ * stream; does not synchronise. */
 vlb_status vlb_channel_step(vlb_channel* c, long nsteps);
-/* L[F] of the current state (host array of state size). */
+/* nsteps RK3 steps in FP64 (moves a mixed batch's state to its FP64 buffers). */
+vlb_status vlb_channel_step_fp64(vlb_channel* c, long nsteps);
+/* L[F] of the current state in the current precision (host array of state size, FP64
+ * populations). Synchronises. */
 vlb_status vlb_channel_apply_L(vlb_channel* c, double* L, size_t n);
+/* FP32 steps taken by the last vlb_channel_run_to_steady (0 for FP64 batches). */
+vlb_status vlb_channel_fp32_steps(const vlb_channel* c, long* n);
 vlb_status vlb_channel_residual(vlb_channel* c, double* r);
 /* Per cell of instance inst ([N_xi][N_lambda] host arrays, each may be NULL): n,
  * u^lambda, u^xi, T and the particle content dchi dlambda n. */

@@ -33,11 +33,20 @@ struct vlb_channel {
     std::vector<Group> groups;
     size_t state_n = 0, ncells = 0;
     int threads = 64;
+    int precision = VLB_FP64;
+    std::vector<ChanDesc> desc32;   // FP32 descriptors (rescaled tables), mixed precision only
+    bool cur32 = false;             // the current state lives in the FP32 buffers
+    bool polishing = false;         // the last run_to_steady ended in FP64, state untouched since
+    long fp32_steps = 0;            // steps of the FP32 phase of the last run_to_steady
     char* ws = nullptr;
-    size_t off_F[3], off_rpart, off_resid, off_diag, off_tab, off_desc, off_cbase, total;
+    size_t off_F[3], off_F32[3], off_rpart, off_resid, off_diag, off_tab, off_desc, off_desc32, off_cbase,
+        off_sbase, total;
     bool have_resid = false;
 
     double* F(int i) { return (double*)(ws + off_F[i]); }
+    float* F32(int i) { return (float*)(ws + off_F32[i]); }
+    ChanDesc* ddesc32() { return (ChanDesc*)(ws + off_desc32); }
+    long long* dsbase() { return (long long*)(ws + off_sbase); }
     double* rpart() { return (double*)(ws + off_rpart); }
     double* resid() { return (double*)(ws + off_resid); }
     double* diag() { return (double*)(ws + off_diag); }
@@ -73,6 +82,17 @@ struct Wall {
     }
 };
 
+// Move the current state between the FP64 buffer and the scaled FP32 buffer.
+vlb_status channel_precision(vlb_channel* c, bool want32) {
+    if (c->cur32 == want32) return VLB_OK;
+    if (want32 && c->precision != VLB_MIXED) return set_error(VLB_ESTATE, "channel batch has no FP32 buffers");
+    VLB_HIP_TRY(launch_channel_convert(want32 ? 1 : 0, (long long)c->state_n, c->stream,
+                                       c->precision == VLB_MIXED ? c->ddesc32() : c->ddesc(), c->dsbase(), c->B,
+                                       c->dtab(), c->F(0), c->F32(0)));
+    c->cur32 = want32;
+    return VLB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -81,13 +101,15 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
                               void* hip_stream) {
     if (!out || B < 1 || !descs) return set_error(VLB_EINVAL, "need out, B >= 1 and descriptors");
     *out = nullptr;
-    if (precision != VLB_FP64) return set_error(VLB_EINVAL, "channels run in FP64 (precision %d unsupported)", precision);
+    if (precision != VLB_FP64 && precision != VLB_MIXED) return set_error(VLB_EINVAL, "unsupported precision %d", precision);
     vlb_channel* c = new (std::nothrow) vlb_channel;
     if (!c) return set_error(VLB_ENOMEM, "host allocation failed");
     c->B = B;
     c->stream = (hipStream_t)hip_stream;
     c->d.assign(descs, descs + B);
     c->desc.resize(B);
+    c->precision = precision;
+    if (precision == VLB_MIXED) c->desc32.resize(B);
     std::map<std::tuple<int, int, int>, AxisTables> cache;
     auto get_axis = [&](const vlb_axis& a) -> const AxisTables* {
         auto key = std::make_tuple(a.kind, a.Q, a.N);
@@ -145,7 +167,7 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         D.tB1 = put(a1->B); D.tB2 = put(a2->B); D.tC1 = put(a1->C); D.tC2 = put(a2->C);
         D.tisf1 = put(a1->invsqrtfact); D.tisf2 = put(a2->invsqrtfact);
         // Maxwellians at rest with T_w: wall (n = 1), inlet, outlet reservoirs; [f' | f'']
-        std::vector<double> g1(n1), g2(n2), fw(2 * NV), fin(2 * NV), fout(2 * NV), iW(NV);
+        std::vector<double> g1(n1), g2(n2), fw(2 * NV), fin(2 * NV), fout(2 * NV), iW(NV), Wk(NV);
         axis_equilibrium_host(*a1, 0.0, d.T_w, g1.data());
         axis_equilibrium_host(*a2, 0.0, d.T_w, g2.data());
         double den_lo = 0.0, den_hi = 0.0;
@@ -156,12 +178,45 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
                 fw[NV + k] = d.T_w * fw[k];
                 if (a1->p[a] > 0) den_lo += a1->p[a] * fw[k];
                 if (a1->p[a] < 0) den_hi += a1->p[a] * fw[k];
-                iW[k] = 1.0 / (a1->w[a] * a2->w[b]);
+                Wk[k] = a1->w[a] * a2->w[b];
+                iW[k] = 1.0 / Wk[k];
             }
         for (int k = 0; k < 2 * NV; ++k) { fin[k] = d.n_in * fw[k]; fout[k] = d.n_out * fw[k]; }
         D.den_lo = den_lo;
         D.den_hi = den_hi;
-        D.tfw = put(fw); D.tfin = put(fin); D.tfout = put(fout); D.tiW = put(iW);
+        D.tfw = put(fw); D.tfin = put(fin); D.tfout = put(fout); D.tiW = put(iW); D.tWm = put(Wk);
+        if (precision == VLB_MIXED) {
+            // FP32 path: populations scaled by 1/W_k (O(1) values); the kernels become
+            // diag(1/w) K diag(w), the equilibrium bases lose their w factor, the ghost
+            // Maxwellians are divided by W_k and the residual weight becomes W_k
+            ChanDesc& E = c->desc32[i];
+            E = D;
+            std::vector<double> K1s(a1->K), Kt1s(a1->Kt), K2s(a2->K), Kt2s(a2->Kt), B1s(a1->B), B2s(a2->B);
+            for (int a = 0; a < n1; ++a)
+                for (int b = 0; b < n1; ++b) {
+                    K1s[a * n1 + b] *= a1->w[b] / a1->w[a];
+                    Kt1s[a * n1 + b] *= a1->w[b] / a1->w[a];
+                }
+            for (int a = 0; a < n2; ++a)
+                for (int b = 0; b < n2; ++b) {
+                    K2s[a * n2 + b] *= a2->w[b] / a2->w[a];
+                    Kt2s[a * n2 + b] *= a2->w[b] / a2->w[a];
+                }
+            for (int a = 0; a < n1; ++a)
+                for (int l = 0; l <= a1->N; ++l) B1s[a * (a1->N + 1) + l] /= a1->w[a];
+            for (int a = 0; a < n2; ++a)
+                for (int l = 0; l <= a2->N; ++l) B2s[a * (a2->N + 1) + l] /= a2->w[a];
+            std::vector<double> fws(fw), fins(fin), fouts(fout);
+            for (int k = 0; k < 2 * NV; ++k) {
+                fws[k] *= iW[k % NV];
+                fins[k] *= iW[k % NV];
+                fouts[k] *= iW[k % NV];
+            }
+            E.tK1 = put(K1s); E.tKt1 = put(Kt1s); E.tK2 = put(K2s); E.tKt2 = put(Kt2s);
+            E.tB1 = put(B1s); E.tB2 = put(B2s);
+            E.tfw = put(fws); E.tfin = put(fins); E.tfout = put(fouts);
+            E.tiW = D.tWm;
+        }
         // geometry (Sec. VI.A): lambda in [-1, 1] and xi on equal cells
         const Wall w{(long double)d.r, (long double)d.L};
         std::vector<long double> lf(NL + 1), xf(NX + 1);
@@ -209,6 +264,11 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         }
         D.tal = put(al); D.tar = put(ar); D.tglxx = put(glxx); D.tglxl = put(glxl);
         D.txc = put(xc); D.txa = put(xa); D.tdlam = put(dlam); D.tdchi = put(dchi); D.tvol = put(vol);
+        if (precision == VLB_MIXED) {
+            ChanDesc& E = c->desc32[i];
+            E.tal = D.tal; E.tar = D.tar; E.tglxx = D.tglxx; E.tglxl = D.tglxl;
+            E.txc = D.txc; E.txa = D.txa; E.tdlam = D.tdlam; E.tdchi = D.tdchi; E.tvol = D.tvol;
+        }
         // dt: advection CFL combined with the force limit |lambda dt| <= sqrt(3) of RK3, capped
         // at 2 tau of the rest state (as for the Couette instances)
         const double rho = fmax1 * force_operator_norm(*a1, *a2) + fmax2 * force_operator_norm(*a2, *a1);
@@ -235,6 +295,11 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
             it->ilist.push_back(i);
             it->base.push_back(it->base.back() + nstrips * NX * (D.strip / kChanWaves));
         }
+        if (precision == VLB_MIXED) {   // fields set after the table section
+            ChanDesc& E = c->desc32[i];
+            E.dt = D.dt;
+            E.strip = D.strip;
+        }
         c->cbase.push_back(cells);
         cells += (long long)NX * NL;
         offF += (size_t)2 * NX * NL * NV;
@@ -246,6 +311,12 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
     c->ncells = offC;
     size_t off = 0;
     for (int k = 0; k < 3; ++k) { c->off_F[k] = off; off = al256(off + c->state_n * sizeof(double)); }
+    for (int k = 0; k < 3; ++k) {
+        c->off_F32[k] = off;
+        if (precision == VLB_MIXED) off = al256(off + c->state_n * sizeof(float));
+    }
+    c->off_desc32 = off; off = al256(off + (precision == VLB_MIXED ? B * sizeof(ChanDesc) : 0));
+    c->off_sbase = off; off = al256(off + (B + 1) * sizeof(long long));
     c->off_rpart = off; off = al256(off + c->ncells * 4 * sizeof(double));
     c->off_resid = off; off = al256(off + B * sizeof(double));
     c->off_diag = off; off = al256(off + c->ncells * 5 * sizeof(double));
@@ -267,6 +338,13 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
                                   c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->ddesc(), c->desc.data(), B * sizeof(ChanDesc), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && precision == VLB_MIXED)
+        e = hipMemcpyAsync(c->ddesc32(), c->desc32.data(), B * sizeof(ChanDesc), hipMemcpyHostToDevice, c->stream);
+    std::vector<long long> sbase(B + 1);
+    for (int i = 0; i < B; ++i) sbase[i] = c->desc[i].offF;
+    sbase[B] = (long long)c->state_n;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->dsbase(), sbase.data(), (B + 1) * sizeof(long long), hipMemcpyHostToDevice, c->stream);
     for (auto& g : c->groups) {
         if (e == hipSuccess)
             e = hipMemcpyAsync(c->ws + g.off_ilist, g.ilist.data(), g.ilist.size() * sizeof(int),
@@ -333,11 +411,15 @@ vlb_status vlb_channel_set_state(vlb_channel* c, const double* host, size_t n) {
     VLB_HIP_TRY(hipMemcpyAsync(c->F(0), host, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
     VLB_HIP_TRY(hipStreamSynchronize(c->stream));
     c->have_resid = false;
+    c->cur32 = false;
+    c->polishing = false;
     return VLB_OK;
 }
 
 vlb_status vlb_channel_get_state(vlb_channel* c, double* host, size_t n) {
     if (!c || !host || n != c->state_n) return set_error(VLB_EINVAL, "state size mismatch");
+    vlb_status s = channel_precision(c, false);
+    if (s != VLB_OK) return s;
     VLB_HIP_TRY(hipMemcpyAsync(host, c->F(0), n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     VLB_HIP_TRY(hipStreamSynchronize(c->stream));
     return VLB_OK;
@@ -347,22 +429,26 @@ vlb_status vlb_channel_get_state(vlb_channel* c, double* host, size_t n) {
 
 namespace {
 
-vlb_status channel_stage(vlb_channel* c, int stage, bool last, bool l_only, double* Lout) {
+// One RK stage (or one application of L into the scratch buffer 1) on the current
+// precision's buffers.
+vlb_status channel_stage(vlb_channel* c, int stage, bool last, bool l_only) {
+    const bool f32 = c->cur32;
+    auto buf = [&](int k) -> void* { return f32 ? (void*)c->F32(k) : (void*)c->F(k); };
     ChanArgs A{};
-    A.inst = c->ddesc();
+    A.inst = f32 ? c->ddesc32() : c->ddesc();
     A.tab = c->dtab();
     A.rpart = nullptr;
     if (l_only) {
-        A.Fin = c->F(0); A.Fn = nullptr; A.Fout = Lout;
+        A.Fin = buf(0); A.Fn = nullptr; A.Fout = buf(1);
         A.ca = 0; A.cb = 0; A.cc = 0; A.l_only = 1;
     } else if (stage == 0) {
-        A.Fin = c->F(0); A.Fn = nullptr; A.Fout = c->F(1);
+        A.Fin = buf(0); A.Fn = nullptr; A.Fout = buf(1);
         A.ca = 0.0; A.cb = 1.0; A.cc = 1.0;
     } else if (stage == 1) {
-        A.Fin = c->F(1); A.Fn = c->F(0); A.Fout = c->F(2);
+        A.Fin = buf(1); A.Fn = buf(0); A.Fout = buf(2);
         A.ca = 0.75; A.cb = 0.25; A.cc = 0.25;
     } else {
-        A.Fin = c->F(2); A.Fn = c->F(0); A.Fout = c->F(0);
+        A.Fin = buf(2); A.Fn = buf(0); A.Fout = buf(0);
         A.ca = 1.0 / 3.0; A.cb = 2.0 / 3.0; A.cc = 2.0 / 3.0;
         if (last) A.rpart = c->rpart();
     }
@@ -370,7 +456,7 @@ vlb_status channel_stage(vlb_channel* c, int stage, bool last, bool l_only, doub
         A.ilist = c->gilist(g);
         A.base = c->gbase(g);
         A.B = (int)g.ilist.size();
-        VLB_HIP_TRY(launch_channel_stage(g.T1, g.T2, g.base.back(), c->stream, A));
+        VLB_HIP_TRY(launch_channel_stage(f32 ? 1 : 0, g.T1, g.T2, g.base.back(), c->stream, A));
     }
     return VLB_OK;
 }
@@ -379,7 +465,7 @@ vlb_status channel_steps(vlb_channel* c, long nsteps) {
     for (long it = 0; it < nsteps; ++it) {
         const bool last = it + 1 == nsteps;
         for (int st = 0; st < 3; ++st) {
-            vlb_status s = channel_stage(c, st, last, false, nullptr);
+            vlb_status s = channel_stage(c, st, last, false);
             if (s != VLB_OK) return s;
         }
         if (last) {
@@ -396,15 +482,34 @@ extern "C" {
 
 vlb_status vlb_channel_step(vlb_channel* c, long nsteps) {
     if (!c || nsteps < 0) return set_error(VLB_EINVAL, "bad arguments");
+    vlb_status s = channel_precision(c, c->precision == VLB_MIXED);
+    if (s != VLB_OK) return s;
+    c->polishing = false;
+    return channel_steps(c, nsteps);
+}
+
+vlb_status vlb_channel_step_fp64(vlb_channel* c, long nsteps) {
+    if (!c || nsteps < 0) return set_error(VLB_EINVAL, "bad arguments");
+    vlb_status s = channel_precision(c, false);
+    if (s != VLB_OK) return s;
     return channel_steps(c, nsteps);
 }
 
 vlb_status vlb_channel_apply_L(vlb_channel* c, double* L, size_t n) {
     if (!c || !L || n != c->state_n) return set_error(VLB_EINVAL, "state size mismatch");
-    vlb_status s = channel_stage(c, 0, false, true, c->F(1));
+    vlb_status s = channel_stage(c, 0, false, true);
     if (s != VLB_OK) return s;
+    if (c->cur32)   // L of the scaled populations times W_k is L of the populations
+        VLB_HIP_TRY(launch_channel_convert(0, (long long)c->state_n, c->stream, c->ddesc32(), c->dsbase(), c->B,
+                                           c->dtab(), c->F(1), c->F32(1)));
     VLB_HIP_TRY(hipMemcpyAsync(L, c->F(1), n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     VLB_HIP_TRY(hipStreamSynchronize(c->stream));
+    return VLB_OK;
+}
+
+vlb_status vlb_channel_fp32_steps(const vlb_channel* c, long* n) {
+    if (!c || !n) return set_error(VLB_EINVAL, "null argument");
+    *n = c->fp32_steps;
     return VLB_OK;
 }
 
@@ -421,6 +526,8 @@ vlb_status vlb_channel_residual(vlb_channel* c, double* r) {
 vlb_status vlb_channel_moments(vlb_channel* c, int inst, double* n, double* u1, double* u2, double* T,
                                double* content) {
     if (!c || inst < 0 || inst >= c->B) return set_error(VLB_EINVAL, "bad instance");
+    vlb_status s = channel_precision(c, false);
+    if (s != VLB_OK) return s;
     VLB_HIP_TRY(launch_channel_diag(c->cbase.back(), c->threads, c->stream, c->ddesc(), c->dcbase(), c->B, c->dtab(),
                                     c->F(0), c->diag()));
     const ChanDesc& D = c->desc[inst];
@@ -442,10 +549,39 @@ vlb_status vlb_channel_run_to_steady(vlb_channel* c, double tol, long max_steps,
     std::vector<long> conv(c->B, -1);
     std::vector<double> res(c->B, INFINITY);
     long done = 0;
+    vlb_status s = VLB_OK;
+    if (c->precision == VLB_MIXED && !c->polishing) {
+        // FP32 phase: stream the scaled FP32 state while the largest residual still falls;
+        // stop at max(tol, 1e-5) or when it has not improved by 5% over three checks (the
+        // FP32 rounding floor, about eps32 / dt), then continue in FP64
+        s = channel_precision(c, true);
+        if (s != VLB_OK) return s;
+        double best = INFINITY;
+        int stall = 0;
+        while (done < max_steps) {
+            const long n = std::min<long>(check_every, max_steps - done);
+            s = channel_steps(c, n);
+            if (s != VLB_OK) return s;
+            done += n;
+            s = vlb_channel_residual(c, res.data());
+            if (s != VLB_OK) return s;
+            const double worst = *std::max_element(res.begin(), res.end());
+            if (worst < std::max(tol, 1e-5)) break;
+            if (worst < 0.95 * best) {
+                best = worst;
+                stall = 0;
+            } else if (++stall >= 3) {
+                break;
+            }
+        }
+        c->fp32_steps = done;
+    }
+    s = channel_precision(c, false);
+    if (s != VLB_OK) return s;
     int remaining = c->B;
     while (done < max_steps && remaining > 0) {
         const long n = std::min<long>(check_every, max_steps - done);
-        vlb_status s = channel_steps(c, n);
+        s = channel_steps(c, n);
         if (s != VLB_OK) return s;
         done += n;
         s = vlb_channel_residual(c, res.data());
@@ -453,6 +589,7 @@ vlb_status vlb_channel_run_to_steady(vlb_channel* c, double tol, long max_steps,
         for (int i = 0; i < c->B; ++i)
             if (conv[i] < 0 && res[i] < tol) { conv[i] = done; --remaining; }
     }
+    c->polishing = true;
     if (steps) std::copy(conv.begin(), conv.end(), steps);
     if (r) std::copy(res.begin(), res.end(), r);
     return remaining ? set_error(VLB_ENOTCONV, "%d channel(s) above tol after %ld steps", remaining, done) : VLB_OK;

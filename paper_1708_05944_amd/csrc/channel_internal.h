@@ -15,12 +15,15 @@ struct ChanDesc {
     double Kn, dt, den_lo, den_hi, weno_eps, pad0;
     long long offF, offC, offT;
     int tp1, tp2, tK1, tKt1, tK2, tKt2, tB1, tB2, tC1, tC2, tisf1, tisf2;
-    int tfw, tfin, tfout, tiW;    // wall / inlet / outlet Maxwellians [2][NV] (f', f''), 1/(w_i w_j) [NV]
+    int tfw, tfin, tfout, tiW;    // wall / inlet / outlet Maxwellians [2][NV] (f', f''), residual weights [NV]
+                                  // (1/W_k for FP64 populations, W_k for FP32 ones scaled by 1/W_k)
     int tal, tar, tglxx, tglxl;   // per cell [NX][NL]: V^lambda factors of the left / right lambda
                                   // faces, connection coefficients G_lxx, G_lxl
     int txc, txa;                 // per (xi face, lambda row) [NX+1][NL]: V^xi = c (p^xi - a p^lambda)
     int tdlam, tdchi, tvol;       // [NL], [NX], cell volumes dchi dlambda [NX][NL]
     int strip;                    // stage-kernel traversal: lambda strips of `strip` cells, swept along xi
+    int tWm;                      // [NV] W_k = w_i w_j (FP32 scaling and moment weights)
+    int pad2;
 };
 
 constexpr int kChanWaves = 4;   // stage kernel: cells (one wavefront each) per block
@@ -35,7 +38,7 @@ struct ChanArgs {
     const long long* base;   // [B+1] first block of each listed instance
     int B;
     const double* tab;
-    const void* Fin;
+    const void* Fin;         // double* (FP64 descriptors) or float* (FP32 descriptors)
     const void* Fn;
     void* Fout;
     double* rpart;           // [cells][2][2] residual partials (nullable)
@@ -43,7 +46,9 @@ struct ChanArgs {
     int l_only;              // 1: out = L[Fin]
 };
 
-hipError_t launch_channel_stage(int T1, int T2, long long nblocks, hipStream_t st, const ChanArgs& A);
+hipError_t launch_channel_stage(int fp32, int T1, int T2, long long nblocks, hipStream_t st, const ChanArgs& A);
+hipError_t launch_channel_convert(int to32, long long nelems, hipStream_t st, const ChanDesc* insts,
+                                  const long long* sbase, int B, const double* tab, double* F64, float* F32);
 hipError_t launch_channel_reduce(int ninst, hipStream_t st, const ChanDesc* insts, const double* tab,
                                  const double* rpart, double* resid);
 hipError_t launch_channel_diag(long long ncells_total, int threads, hipStream_t st, const ChanDesc* insts,

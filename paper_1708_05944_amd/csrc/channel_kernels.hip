@@ -39,8 +39,6 @@ namespace vlb {
 
 namespace {
 
-typedef double dvec4 __attribute__((ext_vector_type(4)));
-
 // order of the LDS operations of one wavefront (no cross-wavefront sharing)
 __device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
@@ -78,20 +76,51 @@ __device__ __forceinline__ void block_sums(double (&v)[NQ], double* sh) {
 // Row order of the first MFMA operand that lands product row 4 r + g (the node of
 // register r in lane group g) where the register layout wants it.  The FP64 16x16x4
 // product holds row g + 4 r in register r of lane group g: already the wanted order.
-// (The FP32 16x16x4 product holds row 4 g + r there; its operand rows would be
-// permuted by m -> 4 (m mod 4) + m / 4.)
-__device__ __forceinline__ int mfma_row_f64(int m) { return m; }
+// The FP32 16x16x4 product holds row 4 g + r there, so its operand rows are permuted by
+// m -> 4 (m mod 4) + m / 4.
+template <typename T>
+__device__ __forceinline__ int mfma_row(int m);
+template <>
+__device__ __forceinline__ int mfma_row<double>(int m) { return m; }
+template <>
+__device__ __forceinline__ int mfma_row<float>(int m) { return 4 * (m & 3) + (m >> 2); }
+
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct Acc4;
+template <>
+struct Acc4<double> {
+    typedef dvec4 type;
+    static __device__ __forceinline__ dvec4 mfma(double a, double b, dvec4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Acc4<float> {
+    typedef fvec4 type;
+    static __device__ __forceinline__ fvec4 mfma(float a, float b, fvec4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
 
 }  // namespace
 
-template <int T1, int T2>
+// T = double: populations f'_k, f''_k as stored (quadrature weights included).
+// T = float: populations divided by W_k = w_i w_j (O(1) values); the tables of the FP32
+// descriptor are rescaled to match (kernels diag(1/w) K diag(w), bases and ghost
+// Maxwellians over w or W, residual weight W), and the moment and wall-flux sums
+// multiply by W_k in FP64.
+template <typename T, int T1, int T2>
 __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs A) {
+    constexpr bool F32 = sizeof(T) == 4;
     constexpr int NT = T1 * T2, NI = 4 * NT;   // items (tile registers) per lane per distribution
-    constexpr int RS = 16 * T2 + 2;           // LDS row stride of the transpose buffer (doubles)
+    constexpr int RS = 16 * T2 + 2;           // LDS row stride of the transpose buffer
     constexpr int S1 = 16 * T1 + 1, S2 = 16 * T2 + 1;   // LDS row strides of the kernel copies
-    __shared__ double k1s[16 * T1 * S1], kt1s[16 * T1 * S1], k2s[16 * T2 * S2], kt2s[16 * T2 * S2];
-    __shared__ double trs[kChanWaves][16 * T1 * RS];   // F of the cell, [i][j] (this distribution)
-    __shared__ double lcs[kChanWaves][16 * T1 * RS];   // L of the cell, [i][j]
+    typedef typename Acc4<T>::type acc_t;
+    __shared__ T k1s[16 * T1 * S1], kt1s[16 * T1 * S1], k2s[16 * T2 * S2], kt2s[16 * T2 * S2];
+    __shared__ T trs[kChanWaves][16 * T1 * RS];   // F of the cell, [i][j] (this distribution)
+    __shared__ T lcs[kChanWaves][16 * T1 * RS];   // L of the cell, [i][j]
     __shared__ double gsh[kChanWaves][kWave];
     __shared__ double ecs[kChanWaves][4 * (kMaxN + 1)];
 
@@ -111,14 +140,14 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
     for (int x = threadIdx.x; x < 16 * T1 * 16 * T1; x += kChanWaves * kWave) {
         const int r = x / (16 * T1), c = x - r * (16 * T1);
         const bool ok = r < Q1 && c < Q1;
-        k1s[r * S1 + c] = ok ? tab[I.tK1 + r * Q1 + c] : 0.0;
-        kt1s[r * S1 + c] = ok ? tab[I.tKt1 + r * Q1 + c] : 0.0;
+        k1s[r * S1 + c] = T(ok ? tab[I.tK1 + r * Q1 + c] : 0.0);
+        kt1s[r * S1 + c] = T(ok ? tab[I.tKt1 + r * Q1 + c] : 0.0);
     }
     for (int x = threadIdx.x; x < 16 * T2 * 16 * T2; x += kChanWaves * kWave) {
         const int r = x / (16 * T2), c = x - r * (16 * T2);
         const bool ok = r < Q2 && c < Q2;
-        k2s[r * S2 + c] = ok ? tab[I.tK2 + r * Q2 + c] : 0.0;
-        kt2s[r * S2 + c] = ok ? tab[I.tKt2 + r * Q2 + c] : 0.0;
+        k2s[r * S2 + c] = T(ok ? tab[I.tK2 + r * Q2 + c] : 0.0);
+        kt2s[r * S2 + c] = T(ok ? tab[I.tKt2 + r * Q2 + c] : 0.0);
     }
     __syncthreads();   // the only block-wide barrier; the wavefronts are independent below
 
@@ -131,11 +160,12 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
     const int p = rem / bpw, s = strip * W + (rem - p * bpw) * kChanWaves + wave;
     if (s >= NL) return;
     const int cell = p * NL + s;
-    const double eps = I.weno_eps;
-    double* tr = trs[wave];
-    double* lcb = lcs[wave];
+    const T eps = T(I.weno_eps);
+    T* tr = trs[wave];
+    T* lcb = lcs[wave];
     double* gf = gsh[wave];
     double* ec = ecs[wave];
+    const double* Wm = tab + I.tWm;   // moment weights W_k (FP32 path only)
 
     // ---- lane items: item t = (I T2 + J) 4 + c is node i = 16 I + 4 c + g, j = 16 J + n
     double plv[T1][4], pxv[T2];
@@ -155,16 +185,21 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
     auto item_pl = [&](int t) { return plv[t / (4 * T2)][t & 3]; };
     auto item_px = [&](int t) { return pxv[(t >> 2) % T2]; };
 
-    const double* F = static_cast<const double*>(A.Fin) + I.offF;
+    const T* F = static_cast<const T*>(A.Fin) + I.offF;
     const size_t dstride = (size_t)NX * NL * NV, xstride = (size_t)NL * NV;
-    const double* Fcell = F + ((size_t)p * NL + s) * NV;
+    const T* Fcell = F + ((size_t)p * NL + s) * NV;
 
     // ---- moments of the cell (FP64 wavefront sums)
     double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0;
 #pragma unroll
     for (int t = 0; t < NI; ++t) {
         if (!item_ok(t)) continue;
-        const double f0 = Fcell[item_k(t)], f1 = Fcell[dstride + item_k(t)];
+        const int k = item_k(t);
+        double f0 = (double)Fcell[k], f1 = (double)Fcell[dstride + k];
+        if (F32) {
+            f0 *= Wm[k];
+            f1 *= Wm[k];
+        }
         const double a = item_pl(t), c = item_px(t);
         m0 += f0;
         m1 += a * f0;
@@ -194,64 +229,71 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
         gf[lane] = acc;
     }
 
-    // ---- wall densities of this xi column (lambda = -1: emitted p^lambda > 0; +1: < 0)
+    // ---- wall densities of this xi column (lambda = -1: emitted p^lambda > 0; +1: < 0),
+    // FP64 sums of the wall-bound flux
     double nw_lo = 0.0, nw_hi = 0.0;
     if (s < 3) {
         double w = 0.0;
-        const double* C0 = F + (size_t)p * NL * NV;
+        const T* C0 = F + (size_t)p * NL * NV;
 #pragma unroll
         for (int t = 0; t < NI; ++t)
             if (item_ok(t) && item_pl(t) < 0) {
                 const int k = item_k(t);
-                const double F1 = C0[k], F2 = C0[NV + k], F3 = C0[2 * NV + k];
-                const double g0 = 3.0 * F1 - 3.0 * F2 + F3, gm1 = 6.0 * F1 - 8.0 * F2 + 3.0 * F3;
-                w += item_pl(t) * weno5<double>(F3, F2, F1, g0, gm1, eps);
+                const T F1 = C0[k], F2 = C0[NV + k], F3 = C0[2 * NV + k];
+                const T g0 = T(3) * F1 - T(3) * F2 + F3, gm1 = T(6) * F1 - T(8) * F2 + T(3) * F3;
+                const double fl = (double)weno5<T>(F3, F2, F1, g0, gm1, eps);
+                w += item_pl(t) * (F32 ? Wm[k] * fl : fl);
             }
         nw_lo = -wave_sum(w) / I.den_lo;
     }
     if (s >= NL - 3) {
         double w = 0.0;
-        const double* C0 = F + ((size_t)p * NL + NL - 1) * NV;
+        const T* C0 = F + ((size_t)p * NL + NL - 1) * NV;
 #pragma unroll
         for (int t = 0; t < NI; ++t)
             if (item_ok(t) && item_pl(t) > 0) {
                 const int k = item_k(t);
-                const double G1 = C0[k], G2 = C0[k - NV], G3 = C0[k - 2 * NV];
-                const double g0 = 3.0 * G1 - 3.0 * G2 + G3, gp1 = 6.0 * G1 - 8.0 * G2 + 3.0 * G3;
-                w += item_pl(t) * weno5<double>(G3, G2, G1, g0, gp1, eps);
+                const T G1 = C0[k], G2 = C0[k - NV], G3 = C0[k - 2 * NV];
+                const T g0 = T(3) * G1 - T(3) * G2 + G3, gp1 = T(6) * G1 - T(8) * G2 + T(3) * G3;
+                const double fl = (double)weno5<T>(G3, G2, G1, g0, gp1, eps);
+                w += item_pl(t) * (F32 ? Wm[k] * fl : fl);
             }
         nw_hi = -wave_sum(w) / I.den_hi;
     }
 
     // ---- per-cell geometry
-    const double glxx = tab[I.tglxx + cell], gxll = -tab[I.tglxl + cell];
-    const double al = tab[I.tal + cell], ar = tab[I.tar + cell];
-    const double idl = 1.0 / tab[I.tdlam + s], idx = 1.0 / tab[I.tdchi + p];
+    const T glxx = T(tab[I.tglxx + cell]), gxll = T(-tab[I.tglxl + cell]);
+    const T al = T(tab[I.tal + cell]), ar = T(tab[I.tar + cell]);
+    const T idl = T(1.0 / tab[I.tdlam + s]), idx = T(1.0 / tab[I.tdchi + p]);
     const double* xc = tab + I.txc;
     const double* xa = tab + I.txa;
-    const double xc0 = xc[(size_t)p * NL + s], xa0 = xa[(size_t)p * NL + s];
-    const double xc1 = xc[(size_t)(p + 1) * NL + s], xa1 = xa[(size_t)(p + 1) * NL + s];
-    const double xcin = xc[s], xain = xa[s], xcout = xc[(size_t)NX * NL + s], xaout = xa[(size_t)NX * NL + s];
+    const T xc0 = T(xc[(size_t)p * NL + s]), xa0 = T(xa[(size_t)p * NL + s]);
+    const T xc1 = T(xc[(size_t)(p + 1) * NL + s]), xa1 = T(xa[(size_t)(p + 1) * NL + s]);
+    const T xcin = T(xc[s]), xain = T(xa[s]), xcout = T(xc[(size_t)NX * NL + s]),
+            xaout = T(xa[(size_t)NX * NL + s]);
     const bool lam_interior = s >= 3 && s < NL - 3, xi_interior = p >= 3 && p < NX - 3;
     const bool lonly = A.l_only != 0;
-    const double dt = lonly ? 1.0 : I.dt, ca = A.ca, cb = A.cb, ccdt = A.cc * dt;
+    const double dt = lonly ? 1.0 : I.dt;
+    const T ca = T(A.ca), cb = T(A.cb), ccdt = T(A.cc * dt);
+    const T Tcell = T(Tc), itauT = T(itau);
     const double* iW = tab + I.tiW;
     wave_lds_fence();
-    double g1v[T1][4], g2v[T2];
+    T g1v[T1][4], g2v[T2];
 #pragma unroll
     for (int I_ = 0; I_ < T1; ++I_)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) g1v[I_][c] = 16 * I_ + 4 * c + g < Q1 ? gf[16 * I_ + 4 * c + g] : 0.0;
+        for (int c = 0; c < 4; ++c)
+            g1v[I_][c] = T(16 * I_ + 4 * c + g < Q1 ? nd * gf[16 * I_ + 4 * c + g] : 0.0);
 #pragma unroll
-    for (int J = 0; J < T2; ++J) g2v[J] = 16 * J + n < Q2 ? gf[Q1 + 16 * J + n] : 0.0;
+    for (int J = 0; J < T2; ++J) g2v[J] = T(16 * J + n < Q2 ? gf[Q1 + 16 * J + n] : 0.0);
 
 #pragma unroll 1
     for (int d = 0; d < 2; ++d) {
-        const double* Fd = Fcell + d * dstride;
+        const T* Fd = Fcell + d * dstride;
         const double* fw = tab + I.tfw + d * NV;
-        double fc[NI];
+        T fc[NI];
 #pragma unroll
-        for (int t = 0; t < NI; ++t) fc[t] = item_ok(t) ? Fd[item_k(t)] : 0.0;
+        for (int t = 0; t < NI; ++t) fc[t] = item_ok(t) ? Fd[item_k(t)] : T(0);
 
         // momentum derivatives (Sec. IV.C) as 16x16x4 MFMA products:
         //   d/dp^lambda: K1 F, Kt1 F (F in its own registers);
@@ -263,30 +305,30 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
         for (int I_ = 0; I_ < T1; ++I_)
 #pragma unroll
             for (int J = 0; J < T2; ++J) {
-                dvec4 k1 = {0, 0, 0, 0}, kt1 = {0, 0, 0, 0}, k2 = {0, 0, 0, 0}, kt2 = {0, 0, 0, 0};
-                const int prow = 16 * I_ + mfma_row_f64(n);
+                acc_t k1 = {0, 0, 0, 0}, kt1 = {0, 0, 0, 0}, k2 = {0, 0, 0, 0}, kt2 = {0, 0, 0, 0};
+                const int prow = 16 * I_ + mfma_row<T>(n);
 #pragma unroll
                 for (int I2 = 0; I2 < T1; ++I2)
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
-                        const double bf = fc[(I2 * T2 + J) * 4 + c];
+                        const T bf = fc[(I2 * T2 + J) * 4 + c];
                         const int col = 16 * I2 + 4 * c + g;
-                        k1 = __builtin_amdgcn_mfma_f64_16x16x4f64(k1s[prow * S1 + col], bf, k1, 0, 0, 0);
-                        kt1 = __builtin_amdgcn_mfma_f64_16x16x4f64(kt1s[prow * S1 + col], bf, kt1, 0, 0, 0);
+                        k1 = Acc4<T>::mfma(k1s[prow * S1 + col], bf, k1);
+                        kt1 = Acc4<T>::mfma(kt1s[prow * S1 + col], bf, kt1);
                     }
 #pragma unroll
                 for (int J2 = 0; J2 < T2; ++J2)
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
                         const int col = 16 * J2 + 4 * c + g;
-                        const double af = tr[prow * RS + col];
-                        k2 = __builtin_amdgcn_mfma_f64_16x16x4f64(af, k2s[(16 * J + n) * S2 + col], k2, 0, 0, 0);
-                        kt2 = __builtin_amdgcn_mfma_f64_16x16x4f64(af, kt2s[(16 * J + n) * S2 + col], kt2, 0, 0, 0);
+                        const T af = tr[prow * RS + col];
+                        k2 = Acc4<T>::mfma(af, k2s[(16 * J + n) * S2 + col], k2);
+                        kt2 = Acc4<T>::mfma(af, kt2s[(16 * J + n) * S2 + col], kt2);
                     }
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const int t = (I_ * T2 + J) * 4 + c;
-                    const double a = item_pl(t), q = item_px(t);
+                    const T a = T(item_pl(t)), q = T(item_px(t));
                     lcb[item_i(t) * RS + item_j(t)] =
                         glxx * (q * q * k1[c] - a * kt2[c]) + gxll * (a * a * k2[c] - q * kt1[c]);
                 }
@@ -300,56 +342,56 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
             const int i = 16 * (t / (4 * T2)) + 4 * (t & 3) + g, j = 16 * ((t >> 2) % T2) + n;
             if (i >= Q1 || j >= Q2) continue;
             const int k = i * Q2 + j;
-            const double plt = tab[I.tp1 + i], pxt = tab[I.tp2 + j];
-            const double fct = tr[i * RS + j];
-            double lw[7];
+            const T plt = T(tab[I.tp1 + i]), pxt = T(tab[I.tp2 + j]);
+            const T fct = tr[i * RS + j];
+            T lw[7];
             if (lam_interior) {
 #pragma unroll
                 for (int q = 0; q < 7; ++q) lw[q] = q == 3 ? fct : Fd[(q - 3) * NV + k];
             } else {
-                const double* Col = Fd - (size_t)s * NV;   // cell (p, 0)
+                const T* Col = Fd - (size_t)s * NV;   // cell (p, 0)
 #pragma unroll
                 for (int q = 0; q < 7; ++q) {
                     const int cc = s - 3 + q;
-                    double v;
+                    T v;
                     if (cc >= 0 && cc < NL) {
                         v = Col[(size_t)cc * NV + k];
                     } else if (cc < 0) {
-                        if (plt > 0) {
-                            v = nw_lo * fw[k];                                   // Eq. weno_populate
+                        if (plt > T(0)) {
+                            v = T(nw_lo * fw[k]);                                // Eq. weno_populate
                         } else {
-                            const double F1 = Col[k], F2 = Col[NV + k], F3 = Col[2 * NV + k];
-                            v = cc == -1 ? 3.0 * F1 - 3.0 * F2 + F3                // Eq. extrapol
-                                         : cc == -2 ? 6.0 * F1 - 8.0 * F2 + 3.0 * F3 : 0.0;
+                            const T F1 = Col[k], F2 = Col[NV + k], F3 = Col[2 * NV + k];
+                            v = cc == -1 ? T(3) * F1 - T(3) * F2 + F3              // Eq. extrapol
+                                         : cc == -2 ? T(6) * F1 - T(8) * F2 + T(3) * F3 : T(0);
                         }
                     } else {
-                        if (plt < 0) {
-                            v = nw_hi * fw[k];
+                        if (plt < T(0)) {
+                            v = T(nw_hi * fw[k]);
                         } else {
-                            const double G1 = Col[(size_t)(NL - 1) * NV + k], G2 = Col[(size_t)(NL - 2) * NV + k],
-                                         G3 = Col[(size_t)(NL - 3) * NV + k];
-                            v = cc == NL ? 3.0 * G1 - 3.0 * G2 + G3
-                                         : cc == NL + 1 ? 6.0 * G1 - 8.0 * G2 + 3.0 * G3 : 0.0;
+                            const T G1 = Col[(size_t)(NL - 1) * NV + k], G2 = Col[(size_t)(NL - 2) * NV + k],
+                                    G3 = Col[(size_t)(NL - 3) * NV + k];
+                            v = cc == NL ? T(3) * G1 - T(3) * G2 + G3
+                                         : cc == NL + 1 ? T(6) * G1 - T(8) * G2 + T(3) * G3 : T(0);
                         }
                     }
                     lw[q] = v;
                 }
             }
-            double xw[7];
+            T xw[7];
             if (xi_interior) {
 #pragma unroll
                 for (int q = 0; q < 7; ++q)
                     xw[q] = q == 3 ? fct : Fd[(ptrdiff_t)(q - 3) * (ptrdiff_t)xstride + k];
             } else {
-                const double vin = xcin * (pxt - xain * plt), vout = xcout * (pxt - xaout * plt);
-                const double* Row = Fd - (size_t)p * xstride;   // cell (0, s)
+                const T vin = xcin * (pxt - xain * plt), vout = xcout * (pxt - xaout * plt);
+                const T* Row = Fd - (size_t)p * xstride;   // cell (0, s)
 #pragma unroll
                 for (int q = 0; q < 7; ++q) {
                     const int cc = p - 3 + q;
-                    double v;
+                    T v;
                     if (cc >= 0 && cc < NX) v = Row[(size_t)cc * xstride + k];
-                    else if (cc < 0) v = vin > 0 ? tab[I.tfin + d * NV + k] : Row[k];
-                    else v = vout < 0 ? tab[I.tfout + d * NV + k] : Row[(size_t)(NX - 1) * xstride + k];
+                    else if (cc < 0) v = vin > T(0) ? T(tab[I.tfin + d * NV + k]) : Row[k];
+                    else v = vout < T(0) ? T(tab[I.tfout + d * NV + k]) : Row[(size_t)(NX - 1) * xstride + k];
                     xw[q] = v;
                 }
             }
@@ -357,44 +399,43 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
             // faces p -+ 1/2 likewise by the sign of V^xi on each face
             // (one face at a time: the four WENO chains are kept from being interleaved, which
             // would raise the register demand past four wavefronts per SIMD)
-            const bool pos = plt > 0;
-            const double Fl = weno_face<double>(pos, lw[0], lw[1], lw[2], lw[3], lw[4], lw[5], eps);
-            double adv_l = -al * Fl;
+            const bool pos = plt > T(0);
+            const T Fl = weno_face<T>(pos, lw[0], lw[1], lw[2], lw[3], lw[4], lw[5], eps);
+            T adv_l = -al * Fl;
             __builtin_amdgcn_sched_barrier(0);
-            const double Fr = weno_face<double>(pos, lw[1], lw[2], lw[3], lw[4], lw[5], lw[6], eps);
+            const T Fr = weno_face<T>(pos, lw[1], lw[2], lw[3], lw[4], lw[5], lw[6], eps);
             adv_l += ar * Fr;
             __builtin_amdgcn_sched_barrier(0);
-            const double V0 = xc0 * (pxt - xa0 * plt), V1 = xc1 * (pxt - xa1 * plt);
-            const double X0 = weno_face<double>(V0 > 0, xw[0], xw[1], xw[2], xw[3], xw[4], xw[5], eps);
-            double adv_x = -V0 * X0;
+            const T V0 = xc0 * (pxt - xa0 * plt), V1 = xc1 * (pxt - xa1 * plt);
+            const T X0 = weno_face<T>(V0 > T(0), xw[0], xw[1], xw[2], xw[3], xw[4], xw[5], eps);
+            T adv_x = -V0 * X0;
             __builtin_amdgcn_sched_barrier(0);
-            const double X1 = weno_face<double>(V1 > 0, xw[1], xw[2], xw[3], xw[4], xw[5], xw[6], eps);
+            const T X1 = weno_face<T>(V1 > T(0), xw[1], xw[2], xw[3], xw[4], xw[5], xw[6], eps);
             adv_x += V1 * X1;
             lcb[i * RS + j] -= plt * adv_l * idl + adv_x * idx;
         }
 
-        // BGK, RK combination, store, residual partials
-        const double* Fn = A.Fn ? static_cast<const double*>(A.Fn) + I.offF + d * dstride +
-                                      ((size_t)p * NL + s) * NV
-                                : nullptr;
-        double* Fo = static_cast<double*>(A.Fout) + I.offF + d * dstride + ((size_t)p * NL + s) * NV;
+        // BGK, RK combination, store, residual partials (FP64)
+        const T* Fn = A.Fn ? static_cast<const T*>(A.Fn) + I.offF + d * dstride + ((size_t)p * NL + s) * NV
+                           : nullptr;
+        T* Fo = static_cast<T*>(A.Fout) + I.offF + d * dstride + ((size_t)p * NL + s) * NV;
         double rd = 0.0, rn = 0.0;
 #pragma unroll
         for (int t = 0; t < NI; ++t) {
             if (!item_ok(t)) continue;
             const int k = item_k(t);
-            double fe = nd * g1v[t / (4 * T2)][t & 3] * g2v[(t >> 2) % T2];
-            if (d) fe *= Tc;
-            const double L = lcb[item_i(t) * RS + item_j(t)] - (fc[t] - fe) * itau;
-            double out;
+            T fe = g1v[t / (4 * T2)][t & 3] * g2v[(t >> 2) % T2];
+            if (d) fe *= Tcell;
+            const T L = lcb[item_i(t) * RS + item_j(t)] - (fc[t] - fe) * itauT;
+            T out;
             if (lonly) {
                 out = L;
             } else {
-                const double fn = ca != 0.0 ? Fn[k] : 0.0;
+                const T fn = ca != T(0) ? Fn[k] : T(0);
                 out = ca * fn + cb * fc[t] + ccdt * L;
-                const double iw = iW[k];
-                rd += (out - fn) * (out - fn) * iw;
-                rn += fn * fn * iw;
+                const double iw = iW[k], dd = (double)out - (double)fn;
+                rd += dd * dd * iw;
+                rn += (double)fn * (double)fn * iw;
             }
             Fo[k] = out;
         }
@@ -408,6 +449,22 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
             }
         }
     }
+}
+
+// FP64 state <-> FP32 state scaled by 1/W_k (one thread per population).
+template <bool TO32>
+__global__ __launch_bounds__(256) void channel_convert(const ChanDesc* insts, const long long* sbase, int B,
+                                                       const double* tab_all, double* F64, float* F32) {
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= sbase[B]) return;
+    const int inst = find_instance(sbase, B, e);
+    const ChanDesc& I = insts[inst];
+    const long long loc = e - sbase[inst];
+    const int k = (int)(loc % I.NV);
+    const double w = tab_all[I.offT + I.tWm + k];
+    const size_t x = (size_t)I.offF + (size_t)loc;
+    if (TO32) F32[x] = (float)(F64[x] / w);
+    else F64[x] = (double)F32[x] * w;
 }
 
 // Residual per instance: sqrt(sum of weighted squared changes / sum of weighted squares)
@@ -462,12 +519,27 @@ __global__ __launch_bounds__(kMaxNV) void channel_diag(const ChanDesc* insts, co
     }
 }
 
-hipError_t launch_channel_stage(int T1, int T2, long long nblocks, hipStream_t st, const ChanArgs& A) {
+hipError_t launch_channel_stage(int fp32, int T1, int T2, long long nblocks, hipStream_t st, const ChanArgs& A) {
     const dim3 grid((unsigned)nblocks), block(kChanWaves * kWave);
-    if (T1 == 1 && T2 == 1) hipLaunchKernelGGL((channel_stage<1, 1>), grid, block, 0, st, A);
-    else if (T1 == 2 && T2 == 1) hipLaunchKernelGGL((channel_stage<2, 1>), grid, block, 0, st, A);
-    else if (T1 == 1 && T2 == 2) hipLaunchKernelGGL((channel_stage<1, 2>), grid, block, 0, st, A);
-    else return hipErrorInvalidValue;
+    if (fp32) {
+        if (T1 == 1 && T2 == 1) hipLaunchKernelGGL((channel_stage<float, 1, 1>), grid, block, 0, st, A);
+        else if (T1 == 2 && T2 == 1) hipLaunchKernelGGL((channel_stage<float, 2, 1>), grid, block, 0, st, A);
+        else if (T1 == 1 && T2 == 2) hipLaunchKernelGGL((channel_stage<float, 1, 2>), grid, block, 0, st, A);
+        else return hipErrorInvalidValue;
+    } else {
+        if (T1 == 1 && T2 == 1) hipLaunchKernelGGL((channel_stage<double, 1, 1>), grid, block, 0, st, A);
+        else if (T1 == 2 && T2 == 1) hipLaunchKernelGGL((channel_stage<double, 2, 1>), grid, block, 0, st, A);
+        else if (T1 == 1 && T2 == 2) hipLaunchKernelGGL((channel_stage<double, 1, 2>), grid, block, 0, st, A);
+        else return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_channel_convert(int to32, long long nelems, hipStream_t st, const ChanDesc* insts,
+                                  const long long* sbase, int B, const double* tab, double* F64, float* F32) {
+    const dim3 grid((unsigned)((nelems + 255) / 256)), block(256);
+    if (to32) hipLaunchKernelGGL(channel_convert<true>, grid, block, 0, st, insts, sbase, B, tab, F64, F32);
+    else hipLaunchKernelGGL(channel_convert<false>, grid, block, 0, st, insts, sbase, B, tab, F64, F32);
     return hipGetLastError();
 }
 

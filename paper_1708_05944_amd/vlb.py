@@ -158,6 +158,8 @@ _SIGS = {
     "vlb_channel_set_state": [ctypes.c_void_p, _dp, ctypes.c_size_t],
     "vlb_channel_get_state": [ctypes.c_void_p, _dp, ctypes.c_size_t],
     "vlb_channel_step": [ctypes.c_void_p, ctypes.c_long],
+    "vlb_channel_step_fp64": [ctypes.c_void_p, ctypes.c_long],
+    "vlb_channel_fp32_steps": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_long)],
     "vlb_channel_apply_L": [ctypes.c_void_p, _dp, ctypes.c_size_t],
     "vlb_channel_residual": [ctypes.c_void_p, _dp],
     "vlb_channel_moments": [ctypes.c_void_p, ctypes.c_int] + [_dp] * 5,
@@ -486,9 +488,10 @@ class Mlp:
 
 
 class Channel:
-    """B expanding channels advanced together on one GPU (FP64)."""
+    """B expanding channels advanced together on one GPU, in FP64 or (VLB_MIXED) with
+    FP32 stage kernels on weight-scaled populations."""
 
-    def __init__(self, descs, device=None):
+    def __init__(self, descs, precision: int = VLB_FP64, device=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the vielbein LB library runs on the GPU only")
@@ -498,7 +501,8 @@ class Channel:
         arr = (_ChannelDesc * self.B)(*[d._c() for d in self.descs])
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
-        _check(load_library().vlb_channel_create(ctypes.byref(h), self.B, arr, VLB_FP64,
+        self.precision = precision
+        _check(load_library().vlb_channel_create(ctypes.byref(h), self.B, arr, precision,
                                                  ctypes.c_void_p(self.stream.cuda_stream)), "vlb_channel_create")
         self._h = h
         n = ctypes.c_size_t()
@@ -539,6 +543,14 @@ class Channel:
 
     def step(self, nsteps: int = 1):
         _check(load_library().vlb_channel_step(self._h, nsteps), "vlb_channel_step")
+
+    def step_fp64(self, nsteps: int = 1):
+        _check(load_library().vlb_channel_step_fp64(self._h, nsteps), "vlb_channel_step_fp64")
+
+    def fp32_steps(self) -> int:
+        n = ctypes.c_long()
+        _check(load_library().vlb_channel_fp32_steps(self._h, ctypes.byref(n)), "vlb_channel_fp32_steps")
+        return n.value
 
     def apply_L(self):
         out = np.empty(self.state_size)

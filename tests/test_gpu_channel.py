@@ -131,3 +131,51 @@ def test_channel_moments_and_content():
         assert np.abs(m[key] - mw[key]).max() <= 1e-12 * max(np.abs(mw[key]).max(), 1e-3), key
     assert m["content"].sum() == pytest.approx(o.mass(F), rel=1e-13)
     c.close()
+
+
+# ---------------------------------------------------------------- mixed precision
+# FP32 stage kernel on populations scaled by 1/(w_i w_j), FP64 moment / wall-flux /
+# residual sums.  Operator bar: relative max-norm 2e-6 (about 30 ulp of float), against
+# the oracle evaluated on the FP32-rounded state the kernel actually reads.
+MIXED_CASES = [CASES[1], CASES[0], CASES[4], CASES[5], CASES[6]]
+
+
+@pytest.mark.parametrize("case", MIXED_CASES)
+def test_channel_fp32_operator_matches_oracle(case):
+    from paper_1708_05944_amd import VLB_MIXED, Channel
+    _say(f"fp32 case {case}")
+    o, d = _pair(**dict(case))
+    c = Channel([d], precision=VLB_MIXED)
+    c.set_state(_perturbed(o, 11).ravel())
+    c.step(0)                                   # moves the state into the FP32 buffers
+    Fr = c.instance_view(c.get_state(), 0).copy()   # the rounded state, back in FP64
+    c.step(0)
+    L = c.instance_view(c.apply_L(), 0)
+    Lw, _, _ = o.L(Fr)
+    err = _relerr(L, Lw)
+    _say(f"fp32 L rel err {err:.2e}")
+    assert err <= 2e-6
+    c.close()
+
+
+def test_channel_mixed_steady_state_matches_fp64():
+    """Pressure-driven flow to r < 1e-10: FP32 phase + FP64 polish against FP64 alone;
+    every moment profile within 1e-5 (relative to max(|profile|, 1e-3))."""
+    from paper_1708_05944_amd import VLB_MIXED, Channel
+    kw = dict(N_lambda=6, N_xi=8, ax1=(1, 3, 2), ax2=(0, 4, 3), Kn=0.3, r=1.5, n_in=1.05, n_out=0.95)
+    runs = {}
+    for name, prec in (("fp64", 0), ("mixed", VLB_MIXED)):
+        o, d = _pair(**dict(kw))
+        c = Channel([d], precision=prec)
+        steps, r, ok = c.run_to_steady(1e-10, 400_000, 500)
+        _say(f"{name}: steps {steps[0]} r {r[0]:.2e} fp32 steps {c.fp32_steps()}")
+        assert ok
+        runs[name] = c.moments(0)
+        if prec:
+            assert c.fp32_steps() > 0
+        c.close()
+    for key in ("n", "u1", "u2", "T"):
+        a, b = runs["mixed"][key], runs["fp64"][key]
+        err = np.abs(a - b).max() / max(np.abs(b).max(), 1e-3)
+        _say(f"{key}: mixed vs fp64 {err:.2e}")
+        assert err <= 1e-5, key

@@ -6,8 +6,9 @@
   oracle's RK3 step from the same state -- FP64 at 1e-12, mixed precision (FP32 stage
   kernels on weight-scaled populations) at 2e-6 (FP32 rounding, as for the operator).
 * Expanding channel 512 x 128 cells, HH(4;8) x H(4;16): every cell, both the operator
-  L[F] and one RK3 step, against the oracle at 1e-12.  The grid is wider than one
-  32-cell lambda strip, so this covers the multi-strip traversal of the stage kernel.
+  L[F] and one RK3 step, against the oracle at 1e-12 (FP64), and one FP32 step against
+  the oracle's step from the FP32-rounded state at 2e-6 (mixed).  The grid is wider than
+  one 32-cell lambda strip, so this covers the multi-strip traversal of the stage kernel.
 """
 import sys
 
@@ -99,4 +100,24 @@ def test_channel_full_size_matches_oracle():
     err = _relerr(G, want)
     _say(f"channel 512 x 128 step rel err {err:.2e}")
     assert err <= 1e-12
+    c.close()
+
+
+def test_channel_mixed_full_size_matches_oracle():
+    import torch
+    from oracle.channel import ChannelOracle
+    from paper_1708_05944_amd import VLB_MIXED, Channel, ChannelDesc
+    kw = dict(xi_in=-4.0, xi_out=12.0, r=2.0, L=4.0, ax1=(1, 8, 4), ax2=(0, 16, 4), Kn=0.05, tau_model=1, n_in=1.1,
+              n_out=0.9, T_w=1.0)
+    c = Channel([ChannelDesc(N_lambda=128, N_xi=512, **kw)], precision=VLB_MIXED)
+    o = ChannelOracle(NL=128, NX=512, **kw)
+    c.step(3)
+    torch.cuda.synchronize()
+    F = c.instance_view(c.get_state(), 0).copy()   # FP32 state in FP64 (moves it to FP64)
+    c.step(1)                                       # back to FP32 (exactly), one FP32 step
+    G = c.instance_view(c.get_state(), 0)
+    want = o.step(F, c.info[0]["dt"], 1)
+    err = _relerr(G, want)
+    _say(f"channel 512 x 128 FP32 step rel err {err:.2e}")
+    assert err <= 2e-6
     c.close()
