@@ -450,7 +450,7 @@ void build_blocks(vlb_batch* b, int tile) {
         const int per = (D.NR + nruns - 1) / nruns;
         const int nvpad = (D.NV + kWave - 1) / kWave * kWave;
         const int rmax = std::max(1, std::min({kMaxRuns, kStageThreads / nvpad, kMaxRuns * kTileCells / per,
-                                               kRowElems / (2 * row_slot(D.Q1, D.Q2))}));
+                                               kRowElems / (2 * row_slot_any(D.Q1, D.Q2))}));
         for (int dist = 0; dist < 2; ++dist)
             for (int r0 = 0; r0 < nruns; r0 += rmax)
                 b->blocks.push_back({i, dist, r0 * per, std::min(rmax, nruns - r0), per, nvpad, 0, 0});
@@ -699,8 +699,8 @@ vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_de
             }
             while (made % kWavesPerBlock) { b->work.push_back({i, dist, 0, 0}); ++made; }
         }
-        g.kmax = std::max(g.kmax, D.Q1 * pad4(D.Q1) + D.Q2 * pad4(D.Q2));
-        if (2 * row_slot(D.Q1, D.Q2) > kRowElems) {
+        g.kmax = std::max({g.kmax, ktab_elems(D.Q1, D.Q2, 4), ktab_elems(D.Q1, D.Q2, 8)});
+        if (2 * row_slot_any(D.Q1, D.Q2) > kRowElems) {
             delete b;
             return fail(VLB_EINVAL, "instance %d: velocity set too large for the stage kernel's LDS rows", i);
         }

@@ -29,11 +29,6 @@
 namespace vlb {
 
 
-__device__ __forceinline__ int pad4_d(int x) { return (x + 3) & ~3; }
-__device__ __forceinline__ int row_slot_d(int Q1, int Q2) {
-    const int a = Q1 * pad4_d(Q2), b = Q2 * pad4_d(Q1);
-    return pad4_d(a > b ? a : b);
-}
 
 // sum_i a[i] b[i], i < n (n a multiple of 4, both pointers 16-byte aligned LDS), in
 // index order with 16-byte vector reads
@@ -116,18 +111,21 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     const int vi = kk / Q2, vj = kk - vi * Q2;
     const T p1 = T(tab[I.tp1 + vi]), p2 = T(tab[I.tp2 + vj]);
 
-    // ---- prologue: kernels into LDS (rows padded with zeros to Q1p / Q2p entries), both
+    // ---- prologue: kernels into LDS (rows of stride P1 / P2, zero beyond Q1 / Q2), both
     // row buffers cleared (their padding stays zero); equilibrium coefficients of every
     // (run, cell)
-    const int Q1p = pad4_d(Q1), Q2p = pad4_d(Q2), S = row_slot_d(Q1, Q2);
-    const int n1 = Q1 * Q1p, n2 = Q2 * Q2p;
+    constexpr int E = sizeof(T);
+    const int L1 = lds_len(Q1, E), L2 = lds_len(Q2, E);        // dot-product lengths
+    const int P1 = lds_stride(Q1, E), P2 = lds_stride(Q2, E);  // LDS row strides
+    const int S = row_slot(Q1, Q2, E);
+    const int n1 = Q1 * P1, n2 = Q2 * P2;
     for (int x = t; x < n1 + n2; x += kStageThreads) {
         T v = T(0);
         if (x < n1) {
-            const int a = x / Q1p, c = x - a * Q1p;
+            const int a = x / P1, c = x - a * P1;
             if (c < Q1) v = T(tab[I.tK1 + a * Q1 + c]);
         } else {
-            const int a = (x - n1) / Q2p, c = (x - n1) - a * Q2p;
+            const int a = (x - n1) / P2, c = (x - n1) - a * P2;
             if (c < Q2) v = T(tab[I.tKt2 + a * Q2 + c]);
         }
         Ks[x] = v;
@@ -240,8 +238,8 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     const T cdt = T(A.cc * dt), ca = T(A.ca), cb = T(A.cb);
     const double* resW = tab + I.tresW;
     const T* Kt = Ks + n1;
-    const T* K1row = Ks + vi * Q1p;
-    const T* Ktrow = Kt + vj * Q2p;
+    const T* K1row = Ks + vi * P1;
+    const T* Ktrow = Kt + vj * P2;
     const double pw1 = (double)p1, pw2 = (double)p2;
     const double wmk = Wm[kk], rwk = resW[kk];
 
@@ -301,8 +299,8 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
             w0v = w1v; w1v = w2v; w2v = w3v; w3v = w4v; w4v = w5v;
             // s is wavefront-uniform: interior cells take a plain load
             w5v = s + 3 < NR ? lead : cell(s + 3);
-            row[vi * Q2p + vj] = w2v;
-            rowT[vj * Q1p + vi] = w2v;
+            row[vi * P2 + vj] = w2v;
+            rowT[vj * P1 + vi] = w2v;
         }
         if (coff >= 0 && c < rlen) {
             double g = 0.0;
@@ -317,8 +315,8 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
             const T Rl = T(e[kEqGeo]), Rr = T(e[kEqGeo + 1]), gam = T(e[kEqGeo + 3]);   // R_{s-+1/2}/dchi_s
             const T adv = p1 * (Rr * fr - Rl * fl);
             T kf = T(0), ktf = T(0);
-            kf = dot_lds<T>(K1row, rowT + vj * Q1p, Q1p);
-            ktf = dot_lds<T>(Ktrow, row + vi * Q2p, Q2p);
+            kf = dot_lds<T>(K1row, rowT + vj * P1, L1);
+            ktf = dot_lds<T>(Ktrow, row + vi * P2, L2);
             const T force = gam * (p2 * p2 * kf - p1 * ktf);
             T fe = T(e[0]) * gb[vi] * gb[Q1 + vj];
             if (dist) fe = T(e[1]) * fe;

@@ -18,15 +18,27 @@ constexpr int kMinTile = 2, kMaxTile = 32;   // range of the stage kernel's cell
 constexpr int kMaxRuns = 16;   // cell runs per stage block
 constexpr int kEqStride = 28;  // doubles kept per cell: n, T, 1/tau, coefficients, geometry (last 4)
 constexpr int kEqGeo = kEqStride - 4;   // R_{s-1/2}/dchi_s, R_{s+1/2}/dchi_s, dchi_s, Gamma_s
-// LDS copies of a cell's populations for the force contractions: row-major [i][Q2p] and
-// transposed [j][Q1p] with strides padded to multiples of 4 (16-byte vector reads), both
-// in one run slot of 2 S elements, S = max(Q1 Q2p, Q2 Q1p) rounded up to 4.
-constexpr int kRowElems = 2816;   // per buffer: >= 2 S for every NV <= kMaxNV
-inline int pad4(int x) { return (x + 3) & ~3; }
-inline int row_slot(int Q1, int Q2) {
-    const int a = Q1 * pad4(Q2), b = Q2 * pad4(Q1);
-    return pad4(a > b ? a : b);
+// LDS copies of a cell's populations for the force contractions: row-major [i][P2] and
+// transposed [j][P1], and the kernel rows K1 [i][P1], Kt2 [j][P2].  A dot product runs
+// over len(Q) elements (whole 16-byte vectors: 4 floats or 2 doubles, zero-padded); the
+// row stride P(Q) is an odd number of 16-byte vectors, so the distinct rows one
+// wavefront reads fall on distinct bank groups.  Both copies share one run slot of 2 S
+// elements, S = max(Q1 P2, Q2 P1) rounded up to 4.
+constexpr int kRowElems = 3136;   // per buffer: >= 2 S for every velocity set of <= kMaxNV nodes
+constexpr int pad4(int x) { return (x + 3) & ~3; }
+constexpr int lds_len(int Q, int elem) { return (Q + 16 / elem - 1) / (16 / elem) * (16 / elem); }
+constexpr int lds_stride(int Q, int elem) {
+    return ((Q + 16 / elem - 1) / (16 / elem) | 1) * (16 / elem);
 }
+constexpr int row_slot(int Q1, int Q2, int elem) {
+    return pad4(Q1 * lds_stride(Q2, elem) > Q2 * lds_stride(Q1, elem) ? Q1 * lds_stride(Q2, elem)
+                                                                      : Q2 * lds_stride(Q1, elem));
+}
+// the block lists serve both element sizes (a mixed batch polishes in FP64)
+constexpr int row_slot_any(int Q1, int Q2) {
+    return row_slot(Q1, Q2, 4) > row_slot(Q1, Q2, 8) ? row_slot(Q1, Q2, 4) : row_slot(Q1, Q2, 8);
+}
+constexpr int ktab_elems(int Q1, int Q2, int elem) { return Q1 * lds_stride(Q1, elem) + Q2 * lds_stride(Q2, elem); }
 
 // Host-side tables of one momentum axis (velocity_set.cpp).
 struct AxisTables {
