@@ -299,7 +299,8 @@ vlb_status vlb_batch_warm_start(vlb_batch* b, vlb_mlp* m, int probe_steps, int* 
  * fixed).  ax1 is the p^lambda axis and must be half range (kind 1); ax2 the p^xi axis.
  * tau_model as for the Couette instances (Sec. VI uses VLB_TAU_HYDRO, Eq. canalie_tau).
  * State of an instance: [2][N_xi][N_lambda][NV] doubles (f', f''; xi cell; lambda cell;
- * k = i * Q2 + j); the initial state is the rest Maxwellian n = 1, u = 0, T = T_w.
+ * k = i * Q2 + j); the initial state is the rest Maxwellian n = 1, u = 0, T = T_w
+ * (written on the device).
  * Velocity sets of at most 32 x 16 or 16 x 32 nodes (tiles of 16 x 16, at most two).
  * precision VLB_FP64 or VLB_MIXED; the mixed form keeps a second state in FP32, scaled
  * by 1/(w_i w_j), on which vlb_channel_step runs (moment, wall-flux and residual sums
@@ -329,6 +330,10 @@ vlb_status vlb_channel_info(const vlb_channel* c, int inst, int* N_lambda, int* 
 vlb_status vlb_channel_state_size(const vlb_channel* c, size_t* n_doubles);
 vlb_status vlb_channel_set_state(vlb_channel* c, const double* host, size_t n);
 vlb_status vlb_channel_get_state(vlb_channel* c, double* host, size_t n);
+/* One instance's state ([2][N_xi][N_lambda][NV] doubles, n must match), in FP64 (a mixed
+ * batch's FP32 state is converted first).  Synchronise. */
+vlb_status vlb_channel_get_instance_state(vlb_channel* c, int inst, double* host, size_t n);
+vlb_status vlb_channel_set_instance_state(vlb_channel* c, int inst, const double* host, size_t n);
 /* nsteps RK3 steps in the batch's precision (FP32 for VLB_MIXED); the last records the
  * residual (same definition as for Couette, volumes dchi dlambda).  Enqueued on the
  * stream; does not synchronise. */

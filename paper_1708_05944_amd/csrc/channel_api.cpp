@@ -307,6 +307,11 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         c->threads = std::max(c->threads, (NV + kWave - 1) / kWave * kWave);
     }
     c->cbase.push_back(cells);
+    for (const auto& g : c->groups)   // one dispatch covers fewer than 2^32 work-items
+        if (g.base.back() * kChanWaves * kWave >= (1LL << 32)) {
+            delete c;
+            return set_error(VLB_EINVAL, "batch too large for one stage launch (%lld blocks)", g.base.back());
+        }
     c->state_n = offF;
     c->ncells = offC;
     size_t off = 0;
@@ -356,18 +361,9 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->dcbase(), c->cbase.data(), (B + 1) * sizeof(long long), hipMemcpyHostToDevice,
                            c->stream);
-    // rest state n = 1, u = 0, T = T_w
-    std::vector<double> host(c->state_n);
-    for (int i = 0; i < B; ++i) {
-        const ChanDesc& D = c->desc[i];
-        const double* fw = c->tab.data() + D.offT + D.tfw;
-        for (int dd = 0; dd < 2; ++dd)
-            for (long long x = 0; x < (long long)D.NX * D.NL; ++x)
-                std::copy(fw + dd * D.NV, fw + (dd + 1) * D.NV,
-                          host.begin() + D.offF + ((size_t)dd * D.NX * D.NL + x) * D.NV);
-    }
+    // rest state n = 1, u = 0, T = T_w, written on the device
     if (e == hipSuccess)
-        e = hipMemcpyAsync(c->F(0), host.data(), c->state_n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        e = launch_channel_rest((long long)c->state_n, c->stream, c->ddesc(), c->dsbase(), B, c->dtab(), c->F(0));
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         (void)hipFree(c->ws);
@@ -412,6 +408,32 @@ vlb_status vlb_channel_set_state(vlb_channel* c, const double* host, size_t n) {
     VLB_HIP_TRY(hipStreamSynchronize(c->stream));
     c->have_resid = false;
     c->cur32 = false;
+    c->polishing = false;
+    return VLB_OK;
+}
+
+vlb_status vlb_channel_get_instance_state(vlb_channel* c, int inst, double* host, size_t n) {
+    if (!c || inst < 0 || inst >= c->B || !host) return set_error(VLB_EINVAL, "bad instance");
+    const ChanDesc& D = c->desc[inst];
+    if (n != (size_t)2 * D.NX * D.NL * D.NV) return set_error(VLB_EINVAL, "instance state size mismatch");
+    vlb_status s = channel_precision(c, false);
+    if (s != VLB_OK) return s;
+    VLB_HIP_TRY(hipMemcpyAsync(host, c->F(0) + D.offF, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    VLB_HIP_TRY(hipStreamSynchronize(c->stream));
+    return VLB_OK;
+}
+
+vlb_status vlb_channel_set_instance_state(vlb_channel* c, int inst, const double* host, size_t n) {
+    if (!c || inst < 0 || inst >= c->B || !host) return set_error(VLB_EINVAL, "bad instance");
+    const ChanDesc& D = c->desc[inst];
+    if (n != (size_t)2 * D.NX * D.NL * D.NV) return set_error(VLB_EINVAL, "instance state size mismatch");
+    for (size_t x = 0; x < n; ++x)
+        if (!std::isfinite(host[x])) return set_error(VLB_ENONFINITE, "non-finite value at element %zu", x);
+    vlb_status s = channel_precision(c, false);
+    if (s != VLB_OK) return s;
+    VLB_HIP_TRY(hipMemcpyAsync(c->F(0) + D.offF, host, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    VLB_HIP_TRY(hipStreamSynchronize(c->stream));
+    c->have_resid = false;
     c->polishing = false;
     return VLB_OK;
 }

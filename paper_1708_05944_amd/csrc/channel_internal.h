@@ -47,6 +47,8 @@ struct ChanArgs {
 };
 
 hipError_t launch_channel_stage(int fp32, int T1, int T2, long long nblocks, hipStream_t st, const ChanArgs& A);
+hipError_t launch_channel_rest(long long nelems, hipStream_t st, const ChanDesc* insts, const long long* sbase, int B,
+                               const double* tab, double* F64);
 hipError_t launch_channel_convert(int to32, long long nelems, hipStream_t st, const ChanDesc* insts,
                                   const long long* sbase, int B, const double* tab, double* F64, float* F32);
 hipError_t launch_channel_reduce(int ninst, hipStream_t st, const ChanDesc* insts, const double* tab,

@@ -31,6 +31,8 @@
 // contiguous band of cells and the xi-neighbour columns stay in its L2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "channel_internal.h"
 #include "vlb_device.h"
 #include "vlb_internal.h"
@@ -451,20 +453,37 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
     }
 }
 
-// FP64 state <-> FP32 state scaled by 1/W_k (one thread per population).
+// Rest state of every instance: the wall Maxwellian f_eq(1, 0, T_w) in every cell (FP64;
+// grid-stride over the populations, since a batch may hold more than 2^32 of them while
+// one dispatch covers fewer work-items).
+__global__ __launch_bounds__(256) void channel_rest(const ChanDesc* insts, const long long* sbase, int B,
+                                                    const double* tab_all, double* F64) {
+    const long long total = sbase[B], stride = (long long)gridDim.x * 256;
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < total; e += stride) {
+        const int inst = find_instance(sbase, B, e);
+        const ChanDesc& I = insts[inst];
+        const long long loc = e - sbase[inst];
+        const int k = (int)(loc % I.NV);
+        const int d = loc >= (long long)I.NX * I.NL * I.NV ? 1 : 0;
+        F64[(size_t)I.offF + (size_t)loc] = tab_all[I.offT + I.tfw + d * I.NV + k];
+    }
+}
+
+// FP64 state <-> FP32 state scaled by 1/W_k (grid-stride over the populations).
 template <bool TO32>
 __global__ __launch_bounds__(256) void channel_convert(const ChanDesc* insts, const long long* sbase, int B,
                                                        const double* tab_all, double* F64, float* F32) {
-    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (e >= sbase[B]) return;
-    const int inst = find_instance(sbase, B, e);
-    const ChanDesc& I = insts[inst];
-    const long long loc = e - sbase[inst];
-    const int k = (int)(loc % I.NV);
-    const double w = tab_all[I.offT + I.tWm + k];
-    const size_t x = (size_t)I.offF + (size_t)loc;
-    if (TO32) F32[x] = (float)(F64[x] / w);
-    else F64[x] = (double)F32[x] * w;
+    const long long total = sbase[B], stride = (long long)gridDim.x * 256;
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < total; e += stride) {
+        const int inst = find_instance(sbase, B, e);
+        const ChanDesc& I = insts[inst];
+        const long long loc = e - sbase[inst];
+        const int k = (int)(loc % I.NV);
+        const double w = tab_all[I.offT + I.tWm + k];
+        const size_t x = (size_t)I.offF + (size_t)loc;
+        if (TO32) F32[x] = (float)(F64[x] / w);
+        else F64[x] = (double)F32[x] * w;
+    }
 }
 
 // Residual per instance: sqrt(sum of weighted squared changes / sum of weighted squares)
@@ -494,7 +513,7 @@ __global__ __launch_bounds__(256) void channel_reduce(const ChanDesc* insts, con
 __global__ __launch_bounds__(kMaxNV) void channel_diag(const ChanDesc* insts, const long long* cbase, int B,
                                                              const double* tab_all, const double* F, double* diag) {
     __shared__ double sh[16 * 5];
-    const long long b = blockIdx.x;
+    for (long long b = blockIdx.x; b < cbase[B]; b += gridDim.x) {   // uniform per block
     const int inst = find_instance(cbase, B, b);
     const ChanDesc& I = insts[inst];
     const int cell = (int)(b - cbase[inst]);
@@ -517,6 +536,7 @@ __global__ __launch_bounds__(kMaxNV) void channel_diag(const ChanDesc* insts, co
         o[3] = (m[3] + m[4] - n * (u1 * u1 + u2 * u2)) / (3.0 * n);
         o[4] = tab[I.tvol + cell] * n;
     }
+    }
 }
 
 hipError_t launch_channel_stage(int fp32, int T1, int T2, long long nblocks, hipStream_t st, const ChanArgs& A) {
@@ -535,9 +555,22 @@ hipError_t launch_channel_stage(int fp32, int T1, int T2, long long nblocks, hip
     return hipGetLastError();
 }
 
+// grid of the grid-stride kernels: enough blocks to fill the chip, far below 2^32 work-items
+static dim3 stride_grid(long long n, long long per_block) {
+    const long long want = (n + per_block - 1) / per_block;
+    return dim3((unsigned)std::max(1LL, std::min(want, 1LL << 20)));
+}
+
+hipError_t launch_channel_rest(long long nelems, hipStream_t st, const ChanDesc* insts, const long long* sbase, int B,
+                               const double* tab, double* F64) {
+    const dim3 grid = stride_grid(nelems, 256), block(256);
+    hipLaunchKernelGGL(channel_rest, grid, block, 0, st, insts, sbase, B, tab, F64);
+    return hipGetLastError();
+}
+
 hipError_t launch_channel_convert(int to32, long long nelems, hipStream_t st, const ChanDesc* insts,
                                   const long long* sbase, int B, const double* tab, double* F64, float* F32) {
-    const dim3 grid((unsigned)((nelems + 255) / 256)), block(256);
+    const dim3 grid = stride_grid(nelems, 256), block(256);
     if (to32) hipLaunchKernelGGL(channel_convert<true>, grid, block, 0, st, insts, sbase, B, tab, F64, F32);
     else hipLaunchKernelGGL(channel_convert<false>, grid, block, 0, st, insts, sbase, B, tab, F64, F32);
     return hipGetLastError();
@@ -551,8 +584,7 @@ hipError_t launch_channel_reduce(int ninst, hipStream_t st, const ChanDesc* inst
 
 hipError_t launch_channel_diag(long long ncells_total, int threads, hipStream_t st, const ChanDesc* insts,
                                const long long* cbase, int B, const double* tab, const double* F, double* diag) {
-    hipLaunchKernelGGL(channel_diag, dim3((unsigned)ncells_total), dim3(threads), 0, st, insts, cbase, B, tab, F,
-                       diag);
+    hipLaunchKernelGGL(channel_diag, stride_grid(ncells_total, 1), dim3(threads), 0, st, insts, cbase, B, tab, F, diag);
     return hipGetLastError();
 }
 

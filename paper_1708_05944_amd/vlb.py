@@ -157,6 +157,8 @@ _SIGS = {
     "vlb_channel_state_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
     "vlb_channel_set_state": [ctypes.c_void_p, _dp, ctypes.c_size_t],
     "vlb_channel_get_state": [ctypes.c_void_p, _dp, ctypes.c_size_t],
+    "vlb_channel_get_instance_state": [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_size_t],
+    "vlb_channel_set_instance_state": [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_size_t],
     "vlb_channel_step": [ctypes.c_void_p, ctypes.c_long],
     "vlb_channel_step_fp64": [ctypes.c_void_p, ctypes.c_long],
     "vlb_channel_fp32_steps": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_long)],
@@ -540,6 +542,18 @@ class Channel:
     def set_state(self, state):
         s = np.ascontiguousarray(state, dtype=np.float64).ravel()
         _check(load_library().vlb_channel_set_state(self._h, _ptr(s), s.size), "vlb_channel_set_state")
+
+    def get_instance_state(self, b: int) -> np.ndarray:
+        i = self.info[b]
+        out = np.empty((2, i["N_xi"], i["N_lambda"], i["NV"]))
+        _check(load_library().vlb_channel_get_instance_state(self._h, b, _ptr(out), out.size),
+               "vlb_channel_get_instance_state")
+        return out
+
+    def set_instance_state(self, b: int, F):
+        s = np.ascontiguousarray(F, dtype=np.float64).ravel()
+        _check(load_library().vlb_channel_set_instance_state(self._h, b, _ptr(s), s.size),
+               "vlb_channel_set_instance_state")
 
     def step(self, nsteps: int = 1):
         _check(load_library().vlb_channel_step(self._h, nsteps), "vlb_channel_step")

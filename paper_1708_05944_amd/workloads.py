@@ -11,14 +11,22 @@ These generators produce instance descriptors with the shapes of those runs:
   N_R ~ randint(64, 513); quadrature orders grow with Kn:
   t = (log10 Kn + 2)/3, Q_R = 4 + round(12 t) (half range on p^R),
   Q_phi = 4 + round(16 t) (full range on p^phi), expansion order N = min(Q - 1, 4).
+* ``channel_512x128()``: the expanding channel of Sec. VI, 512 (xi) x 128 (lambda) cells,
+  xi in [-4, 12], expansion ratio 2 over L = 4, HH(4;8) x H(4;16) (256 velocities),
+  Kn = 0.05 with tau = Kn/(nT), reservoirs n = 1.1 / 0.9, T_w = 1.
+* ``channel_sweep(B, seed)``: B channels drawn with numpy PCG64(seed): N_lambda =
+  16 randint(4, 17), N_xi = 4 N_lambda, Kn = 10^U(-2, 0), r ~ U(1.5, 3); the p^lambda
+  order grows with Kn: t = (log10 Kn + 2)/2, Q_lambda = 8 + round(8 t) (half range),
+  Q_xi = 16 (full range), N = 4: 256 to 512 velocities.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .vlb import VLB_TAU_AOKI, CouetteDesc
+from .vlb import VLB_TAU_AOKI, VLB_TAU_HYDRO, ChannelDesc, CouetteDesc
 
 SWEEP_SEED = 20261203
+CHANNEL_SWEEP_SEED = 3
 
 
 def single_couette(dt: float = 0.0) -> CouetteDesc:
@@ -100,3 +108,24 @@ def epoch_orders(n: int, epochs: int, seed: int = 0):
     rng = np.random.Generator(np.random.PCG64(seed))
     for _ in range(epochs):
         yield rng.permutation(n).astype(np.int32)
+
+
+# ---------------------------------------------------------------- expanding channel
+def channel_512x128(Kn: float = 0.05) -> ChannelDesc:
+    return ChannelDesc(N_lambda=128, N_xi=512, xi_in=-4.0, xi_out=12.0, r=2.0, L=4.0, ax1=(1, 8, 4), ax2=(0, 16, 4),
+                       Kn=Kn, tau_model=VLB_TAU_HYDRO, n_in=1.1, n_out=0.9, T_w=1.0)
+
+
+def channel_sweep(B: int = 64, seed: int = CHANNEL_SWEEP_SEED):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    NL = 16 * rng.integers(4, 17, B)
+    Kn = 10.0 ** rng.uniform(-2.0, 0.0, B)
+    r = rng.uniform(1.5, 3.0, B)
+    out = []
+    for b in range(B):
+        t = (np.log10(Kn[b]) + 2.0) / 2.0
+        Ql = 8 + int(round(8 * t))
+        out.append(ChannelDesc(N_lambda=int(NL[b]), N_xi=4 * int(NL[b]), xi_in=-4.0, xi_out=12.0, r=float(r[b]),
+                               L=4.0, ax1=(1, Ql, 4), ax2=(0, 16, 4), Kn=float(Kn[b]), tau_model=VLB_TAU_HYDRO,
+                               n_in=1.1, n_out=0.9, T_w=1.0))
+    return out

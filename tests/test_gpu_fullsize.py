@@ -121,3 +121,46 @@ def test_channel_mixed_full_size_matches_oracle():
     _say(f"channel 512 x 128 FP32 step rel err {err:.2e}")
     assert err <= 2e-6
     c.close()
+
+
+def _channel_sweep_parity(precision, tol):
+    """The 64-channel sweep (seed 3: 64..256 x 256..1024 cells, 256..512 velocities, both
+    velocity-tile classes) advanced together; the smallest instance of each tile class is
+    compared with the oracle's step from the same state."""
+    import torch
+    from oracle.channel import ChannelOracle
+    from paper_1708_05944_amd import Channel, workloads
+    descs = workloads.channel_sweep()
+    c = Channel(descs, precision=precision)
+    c.step(2)
+    torch.cuda.synchronize()
+    size = [d.N_lambda * d.N_xi * d.ax1[1] for d in descs]
+    picks = []
+    for cls in (lambda d: d.ax1[1] <= 8, lambda d: d.ax1[1] > 8):
+        idx = [i for i, d in enumerate(descs) if cls(d)]
+        if idx:
+            picks.append(min(idx, key=lambda i: size[i]))
+    _say(f"channel sweep precision {precision}: {c.state_size} values, checking instances {picks}")
+    states = {i: c.get_instance_state(i) for i in picks}   # FP64 (for a mixed batch: its FP32 state)
+    c.step(1)
+    # every instance (the batch holds more than 2^32 populations) has a finite residual
+    assert np.isfinite(c.residual()).all()
+    for i in picks:
+        d = descs[i]
+        G = c.get_instance_state(i)
+        o = ChannelOracle(NL=d.N_lambda, NX=d.N_xi, ax1=d.ax1, ax2=d.ax2, Kn=d.Kn, tau_model=d.tau_model, r=d.r, L=d.L,
+                          xi_in=d.xi_in, xi_out=d.xi_out, n_in=d.n_in, n_out=d.n_out, T_w=d.T_w)
+        want = o.step(states[i], c.info[i]["dt"], 1)
+        err = _relerr(G, want)
+        _say(f"instance {i} ({d.N_lambda} x {d.N_xi}, ax1 {d.ax1}): rel err {err:.2e}")
+        assert err <= tol
+    c.close()
+
+
+def test_channel_sweep_full_size_mixed_matches_oracle():
+    from paper_1708_05944_amd import VLB_MIXED
+    _channel_sweep_parity(VLB_MIXED, 2e-6)
+
+
+def test_channel_sweep_full_size_fp64_matches_oracle():
+    _channel_sweep_parity(0, 1e-12)
