@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "channel_internal.h"
 #include "vlb_device.h"
@@ -214,10 +215,13 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
     const double itau = 1.0 / tau_of(I.tau_model, I.Kn, nd, Tc);
 
     // ---- equilibrium factors g1(p^lambda_i), g2(p^xi_j) of the cell (LDS, this wavefront)
-    if (lane == 0) axis_coef(I.kind1, I.N1, u1, Tc, tab + I.tC1, tab + I.tisf1, ec, ec + (I.N1 + 1));
-    if (lane == 1)
-        axis_coef(I.kind2, I.N2, u2, Tc, tab + I.tC2, tab + I.tisf2, ec + 2 * (kMaxN + 1),
-                  ec + 2 * (kMaxN + 1) + (I.N2 + 1));
+    // lane 2 a + sg: axis a, side sg (a half-range axis has two coefficient sets)
+    if (lane < 4) {
+        const int ax = lane >> 1, sg = lane & 1, kind = ax ? I.kind2 : I.kind1, N = ax ? I.N2 : I.N1;
+        if (kind == 1 || sg == 0)
+            axis_coef_side(kind, N, ax ? u2 : u1, Tc, tab + (ax ? I.tC2 : I.tC1), tab + (ax ? I.tisf2 : I.tisf1), sg,
+                           ec + ax * 2 * (kMaxN + 1) + sg * (N + 1));
+    }
     wave_lds_fence();
     if (lane < Q1 + Q2) {
         const bool ax1 = lane < Q1;
@@ -338,84 +342,90 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
         wave_lds_fence();   // the buffer is rewritten for the next distribution
 
         // advection through the four faces: a rolled loop over the lane's items (their F
-        // and L live in this lane's slots of the LDS rows), one item in registers at a time
+        // and L live in this lane's slots of the LDS rows), one item in registers at a time.
+        // Cells whose stencils stay inside the grid (most of them) take a loop without the
+        // ghost logic, so its conditions and offsets do not occupy registers there.
+        auto advect = [&](auto interior_tag) {
+            constexpr bool interior = decltype(interior_tag)::value;
 #pragma unroll 1
-        for (int t = 0; t < NI; ++t) {
-            const int i = 16 * (t / (4 * T2)) + 4 * (t & 3) + g, j = 16 * ((t >> 2) % T2) + n;
-            if (i >= Q1 || j >= Q2) continue;
-            const int k = i * Q2 + j;
-            const T plt = T(tab[I.tp1 + i]), pxt = T(tab[I.tp2 + j]);
-            const T fct = tr[i * RS + j];
-            T lw[7];
-            if (lam_interior) {
+            for (int t = 0; t < NI; ++t) {
+                const int i = 16 * (t / (4 * T2)) + 4 * (t & 3) + g, j = 16 * ((t >> 2) % T2) + n;
+                if (i >= Q1 || j >= Q2) continue;
+                const int k = i * Q2 + j;
+                const T plt = T(tab[I.tp1 + i]), pxt = T(tab[I.tp2 + j]);
+                const T fct = tr[i * RS + j];
+                T lw[7], xw[7];
+                if (interior || lam_interior) {
 #pragma unroll
-                for (int q = 0; q < 7; ++q) lw[q] = q == 3 ? fct : Fd[(q - 3) * NV + k];
-            } else {
-                const T* Col = Fd - (size_t)s * NV;   // cell (p, 0)
+                    for (int q = 0; q < 7; ++q) lw[q] = q == 3 ? fct : Fd[(q - 3) * NV + k];
+                } else {
+                    const T* Col = Fd - (size_t)s * NV;   // cell (p, 0)
 #pragma unroll
-                for (int q = 0; q < 7; ++q) {
-                    const int cc = s - 3 + q;
-                    T v;
-                    if (cc >= 0 && cc < NL) {
-                        v = Col[(size_t)cc * NV + k];
-                    } else if (cc < 0) {
-                        if (plt > T(0)) {
-                            v = T(nw_lo * fw[k]);                                // Eq. weno_populate
+                    for (int q = 0; q < 7; ++q) {
+                        const int cc = s - 3 + q;
+                        T v;
+                        if (cc >= 0 && cc < NL) {
+                            v = Col[(size_t)cc * NV + k];
+                        } else if (cc < 0) {
+                            if (plt > T(0)) {
+                                v = T(nw_lo * fw[k]);                                // Eq. weno_populate
+                            } else {
+                                const T F1 = Col[k], F2 = Col[NV + k], F3 = Col[2 * NV + k];
+                                v = cc == -1 ? T(3) * F1 - T(3) * F2 + F3              // Eq. extrapol
+                                             : cc == -2 ? T(6) * F1 - T(8) * F2 + T(3) * F3 : T(0);
+                            }
                         } else {
-                            const T F1 = Col[k], F2 = Col[NV + k], F3 = Col[2 * NV + k];
-                            v = cc == -1 ? T(3) * F1 - T(3) * F2 + F3              // Eq. extrapol
-                                         : cc == -2 ? T(6) * F1 - T(8) * F2 + T(3) * F3 : T(0);
+                            if (plt < T(0)) {
+                                v = T(nw_hi * fw[k]);
+                            } else {
+                                const T G1 = Col[(size_t)(NL - 1) * NV + k], G2 = Col[(size_t)(NL - 2) * NV + k],
+                                        G3 = Col[(size_t)(NL - 3) * NV + k];
+                                v = cc == NL ? T(3) * G1 - T(3) * G2 + G3
+                                             : cc == NL + 1 ? T(6) * G1 - T(8) * G2 + T(3) * G3 : T(0);
+                            }
                         }
-                    } else {
-                        if (plt < T(0)) {
-                            v = T(nw_hi * fw[k]);
-                        } else {
-                            const T G1 = Col[(size_t)(NL - 1) * NV + k], G2 = Col[(size_t)(NL - 2) * NV + k],
-                                    G3 = Col[(size_t)(NL - 3) * NV + k];
-                            v = cc == NL ? T(3) * G1 - T(3) * G2 + G3
-                                         : cc == NL + 1 ? T(6) * G1 - T(8) * G2 + T(3) * G3 : T(0);
-                        }
+                        lw[q] = v;
                     }
-                    lw[q] = v;
                 }
-            }
-            T xw[7];
-            if (xi_interior) {
+                if (interior || xi_interior) {
 #pragma unroll
-                for (int q = 0; q < 7; ++q)
-                    xw[q] = q == 3 ? fct : Fd[(ptrdiff_t)(q - 3) * (ptrdiff_t)xstride + k];
-            } else {
-                const T vin = xcin * (pxt - xain * plt), vout = xcout * (pxt - xaout * plt);
-                const T* Row = Fd - (size_t)p * xstride;   // cell (0, s)
+                    for (int q = 0; q < 7; ++q)
+                        xw[q] = q == 3 ? fct : Fd[(ptrdiff_t)(q - 3) * (ptrdiff_t)xstride + k];
+                } else {
+                    const T vin = xcin * (pxt - xain * plt), vout = xcout * (pxt - xaout * plt);
+                    const T* Row = Fd - (size_t)p * xstride;   // cell (0, s)
 #pragma unroll
-                for (int q = 0; q < 7; ++q) {
-                    const int cc = p - 3 + q;
-                    T v;
-                    if (cc >= 0 && cc < NX) v = Row[(size_t)cc * xstride + k];
-                    else if (cc < 0) v = vin > T(0) ? T(tab[I.tfin + d * NV + k]) : Row[k];
-                    else v = vout < T(0) ? T(tab[I.tfout + d * NV + k]) : Row[(size_t)(NX - 1) * xstride + k];
-                    xw[q] = v;
+                    for (int q = 0; q < 7; ++q) {
+                        const int cc = p - 3 + q;
+                        T v;
+                        if (cc >= 0 && cc < NX) v = Row[(size_t)cc * xstride + k];
+                        else if (cc < 0) v = vin > T(0) ? T(tab[I.tfin + d * NV + k]) : Row[k];
+                        else v = vout < T(0) ? T(tab[I.tfout + d * NV + k]) : Row[(size_t)(NX - 1) * xstride + k];
+                        xw[q] = v;
+                    }
                 }
+                // faces s -+ 1/2 between window cells 2|3 and 3|4, upwinded by the sign of
+                // p^lambda; faces p -+ 1/2 likewise by the sign of V^xi on each face (one face
+                // at a time: the four WENO chains are kept from being interleaved, which would
+                // raise the register demand)
+                const bool pos = plt > T(0);
+                const T Fl = weno_face<T>(pos, lw[0], lw[1], lw[2], lw[3], lw[4], lw[5], eps);
+                T adv_l = -al * Fl;
+                __builtin_amdgcn_sched_barrier(0);
+                const T Fr = weno_face<T>(pos, lw[1], lw[2], lw[3], lw[4], lw[5], lw[6], eps);
+                adv_l += ar * Fr;
+                __builtin_amdgcn_sched_barrier(0);
+                const T V0 = xc0 * (pxt - xa0 * plt), V1 = xc1 * (pxt - xa1 * plt);
+                const T X0 = weno_face<T>(V0 > T(0), xw[0], xw[1], xw[2], xw[3], xw[4], xw[5], eps);
+                T adv_x = -V0 * X0;
+                __builtin_amdgcn_sched_barrier(0);
+                const T X1 = weno_face<T>(V1 > T(0), xw[1], xw[2], xw[3], xw[4], xw[5], xw[6], eps);
+                adv_x += V1 * X1;
+                lcb[i * RS + j] -= plt * adv_l * idl + adv_x * idx;
             }
-            // faces s -+ 1/2 between window cells 2|3 and 3|4, upwinded by the sign of p^lambda;
-            // faces p -+ 1/2 likewise by the sign of V^xi on each face
-            // (one face at a time: the four WENO chains are kept from being interleaved, which
-            // would raise the register demand past four wavefronts per SIMD)
-            const bool pos = plt > T(0);
-            const T Fl = weno_face<T>(pos, lw[0], lw[1], lw[2], lw[3], lw[4], lw[5], eps);
-            T adv_l = -al * Fl;
-            __builtin_amdgcn_sched_barrier(0);
-            const T Fr = weno_face<T>(pos, lw[1], lw[2], lw[3], lw[4], lw[5], lw[6], eps);
-            adv_l += ar * Fr;
-            __builtin_amdgcn_sched_barrier(0);
-            const T V0 = xc0 * (pxt - xa0 * plt), V1 = xc1 * (pxt - xa1 * plt);
-            const T X0 = weno_face<T>(V0 > T(0), xw[0], xw[1], xw[2], xw[3], xw[4], xw[5], eps);
-            T adv_x = -V0 * X0;
-            __builtin_amdgcn_sched_barrier(0);
-            const T X1 = weno_face<T>(V1 > T(0), xw[1], xw[2], xw[3], xw[4], xw[5], xw[6], eps);
-            adv_x += V1 * X1;
-            lcb[i * RS + j] -= plt * adv_l * idl + adv_x * idx;
-        }
+        };
+        if (lam_interior && xi_interior) advect(std::true_type{});
+        else advect(std::false_type{});
 
         // BGK, RK combination, store, residual partials (FP64)
         const T* Fn = A.Fn ? static_cast<const T*>(A.Fn) + I.offF + d * dstride + ((size_t)p * NL + s) * NV

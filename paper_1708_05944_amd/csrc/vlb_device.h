@@ -157,6 +157,36 @@ static __device__ __noinline__ void axis_coef(int kind, int N, double u, double 
     }
 }
 
+// One side of axis_coef: for a half-range axis (kind 1) the coefficients of the side sg
+// (0: +u, 1: -u); for a full-range axis (kind 0) its coefficients (sg ignored).  Lanes of
+// a wavefront that take different sides run the same instructions together.
+static __device__ __noinline__ void axis_coef_side(int kind, int N, double u, double T, const double* C,
+                                                   const double* isf, int sg, double* co) {
+    if (kind == 0) {
+        double a0 = 1.0, a1 = u;
+        co[0] = a0 / isf[0];
+        if (N >= 1) co[1] = a1 / isf[1];
+        for (int l = 2; l <= N; ++l) {
+            const double a2 = (u * a1 + (T - 1.0) * a0) / l;
+            co[l] = a2 / isf[l];
+            a0 = a1;
+            a1 = a2;
+        }
+        return;
+    }
+    const double uu = sg == 0 ? u : -u;
+    double M[kMaxN + 1];
+    const double g0 = exp(-uu * uu / (2.0 * T)) / sqrt(2.0 * M_PI * T);
+    M[0] = 0.5 * (1.0 + erf(uu / sqrt(2.0 * T)));
+    if (N >= 1) M[1] = uu * M[0] + T * g0;
+    for (int s = 2; s <= N; ++s) M[s] = uu * M[s - 1] + (s - 1) * T * M[s - 2];
+    for (int l = 0; l <= N; ++l) {
+        double acc = 0.0;
+        for (int s = 0; s <= l; ++s) acc += C[l * (N + 1) + s] * M[s];
+        co[l] = acc;
+    }
+}
+
 __device__ __forceinline__ double tau_of(int model, double Kn, double n, double T) {
     if (model == 0) return Kn * 0.62665706865775012 / n;   // Kn sqrt(pi/8)/n, Eq. tau_aoki
     if (model == 1) return Kn / (n * T);                   // Eq. hydro_tau
