@@ -44,3 +44,36 @@ def test_status_strings():
     lib = load_library()
     assert lib.vlb_status_string(0) == b"ok"
     assert lib.vlb_status_string(-6) == b"non-finite value"
+
+
+def _channel_create_status(**kw):
+    """vlb_channel_create on one descriptor through the C ABI; invalid descriptors are
+    rejected before any device call, so this runs without a GPU."""
+    from paper_1708_05944_amd import ChannelDesc
+    from paper_1708_05944_amd.vlb import _ChannelDesc
+    prec = kw.pop("precision", 0)
+    d = ChannelDesc(**kw)
+    arr = (_ChannelDesc * 1)(d._c())
+    h = ctypes.c_void_p()
+    st = load_library().vlb_channel_create(ctypes.byref(h), 1, arr, prec, None)
+    return st, load_library().vlb_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(N_lambda=5, N_xi=8), "invalid channel descriptor"),                     # fewer than 6 cells across
+    (dict(N_lambda=8, N_xi=8, ax1=(0, 4, 2)), "half range"),                       # p^lambda axis must be half range
+    (dict(N_lambda=8, N_xi=8, xi_in=3.0, xi_out=1.0), "invalid channel descriptor"),
+    (dict(N_lambda=8, N_xi=8, tau_model=3), "invalid channel descriptor"),
+    (dict(N_lambda=8, N_xi=8, weno_eps=-1.0), "invalid channel descriptor"),
+    (dict(N_lambda=8, N_xi=8, ax1=(1, 20, 4), ax2=(0, 20, 4)), "exceed the kernel limits"),   # 40 x 20 nodes
+    (dict(N_lambda=8, N_xi=8, precision=7), "unsupported precision"),
+])
+def test_channel_create_rejects_invalid_descriptors(kw, needle):
+    st, msg = _channel_create_status(**kw)
+    assert st == -1, (st, msg)
+    assert needle in msg, msg
+
+
+def test_channel_create_rejects_unstable_dt():
+    st, msg = _channel_create_status(N_lambda=8, N_xi=8, dt=10.0)
+    assert st == -7 and "stability limit" in msg, (st, msg)
