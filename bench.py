@@ -104,6 +104,27 @@ def cpu_baseline(n_inst: int, nsteps: int):
                        f"(wall {wall:.1f} s incl. table set-up)")
 
 
+def channel_cpu_baseline():
+    """The channel oracle (plain C FP64, one thread; a single instance is one serial sweep)
+    for one RK3 step of the 512 x 128 channel from rest."""
+    import numpy as np
+    from oracle.channel import ChannelOracle
+    from paper_1708_05944_amd import workloads
+    d = workloads.channel_512x128()
+    o = ChannelOracle(NL=d.N_lambda, NX=d.N_xi, ax1=d.ax1, ax2=d.ax2, Kn=d.Kn, tau_model=d.tau_model, r=d.r, L=d.L,
+                      xi_in=d.xi_in, xi_out=d.xi_out, n_in=d.n_in, n_out=d.n_out, T_w=d.T_w)
+    F = o.equilibrium(1.0, 0.0, 0.0, 1.0)
+    dt = o.cfl_dt(0.5)
+    t0 = time.perf_counter()
+    F = o.step(F, dt, 1)
+    el = time.perf_counter() - t0
+    assert np.isfinite(F).all()
+    sv = d.N_lambda * d.N_xi * o.NV
+    return dict(value=sv / el, unit="site-velocity updates/s", cores=1, kind="oracle",
+                sample=f"one RK3 step of the 512 x 128 channel (256 velocities) from rest, one thread "
+                       f"({el:.1f} s)")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -285,6 +306,8 @@ def main():
         out["copy_ref_bytes"] = n
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_instances, args.cpu_steps)
+        if channel is not None:
+            channel["cpu_baseline"] = channel_cpu_baseline()
     print(json.dumps(out), flush=True)
 
 
