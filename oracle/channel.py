@@ -10,7 +10,9 @@ with gcc -O2 -ffp-contract=off, fills its parameter struct with the mpmath table
 * chi(xi) = xi + (r - 1) [xi + (L/4) ln cosh(4 xi / L - 2)] / 2, so d chi = (1 + phi) d xi
   (Eq. chi_canalie), cell widths dchi_p = chi(xi_{p+1/2}) - chi(xi_{p-1/2});
 * lambda in [-1, 1] (the full channel width, walls at both ends) on equal cells, xi on
-  equal cells in [xi_in, xi_out].
+  equal cells in [xi_in, xi_out]; or, with ``half``, lambda in [0, 1] with a specular
+  centreline (Sec. VI.C.3).  ``ends = 1`` replaces the reservoirs by the flow-rate
+  profile of Sec. VI.C.1-2 with flow rate Q0 through half of the cross-section.
 
 State layout: float64 F[2][NX][NL][NV] (f' then f''), NV = Q1*Q2, k = i*Q2 + j with i
 the p^lambda node (axis 1) and j the p^xi node (axis 2).
@@ -53,7 +55,8 @@ _DP = ctypes.POINTER(ctypes.c_double)
 class _CParams(ctypes.Structure):
     _fields_ = ([("vs", _Params), ("NL", ctypes.c_int), ("NX", ctypes.c_int)]
                 + [(n, _DP) for n in ("Kt1", "K2", "lam_f", "phi_c", "dphi_c", "phi_f", "dphi_f", "dchi")]
-                + [(n, ctypes.c_double) for n in ("n_in", "n_out", "T_w")])
+                + [(n, ctypes.c_double) for n in ("n_in", "n_out", "T_w")]
+                + [("half", ctypes.c_int), ("ends", ctypes.c_int), ("Q0", ctypes.c_double)])
 
 
 def lib():
@@ -63,6 +66,7 @@ def lib():
             _lib = ctypes.CDLL(build())
             dp = ctypes.POINTER(ctypes.c_double)
             _lib.oracle_channel_L.argtypes = [ctypes.c_void_p, dp, dp, dp, dp]
+            _lib.oracle_channel_L2.argtypes = [ctypes.c_void_p, dp, dp, dp, dp, dp]
             _lib.oracle_channel_rk3.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_long]
             _lib.oracle_feq.argtypes = [ctypes.c_void_p] + [ctypes.c_double] * 4 + [dp, dp]
         return _lib
@@ -94,14 +98,15 @@ class ChannelOracle:
     (p^xi) as (kind, Q, N)."""
 
     def __init__(self, NL=8, NX=12, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.05, tau_model=TAU_HYDRO, r=2.0, L=4.0,
-                 xi_in=-4.0, xi_out=12.0, n_in=1.1, n_out=0.9, T_w=1.0, weno_eps=0.0):
-        if NL < 6 or NX < 3:
-            raise ValueError("need at least 6 lambda cells (two walls) and 3 xi cells")
+                 xi_in=-4.0, xi_out=12.0, n_in=1.1, n_out=0.9, T_w=1.0, weno_eps=0.0, half=False, ends=0, Q0=0.0):
+        if NL < (3 if half else 6) or NX < 3:
+            raise ValueError("need at least 6 lambda cells (two walls; 3 for the half channel) and 3 xi cells")
         self.a1, self.a2 = quad.axis(*ax1), quad.axis(*ax2)
         self.Q1, self.Q2 = self.a1.n_nodes, self.a2.n_nodes
         self.NV = self.Q1 * self.Q2
         self.NL, self.NX = NL, NX
-        self.lam_f = np.array([-1.0 + 2.0 * s / NL for s in range(NL + 1)])
+        self.half, self.ends, self.Q0 = bool(half), int(ends), float(Q0)
+        self.lam_f = np.array([(s / NL) if half else (-1.0 + 2.0 * s / NL) for s in range(NL + 1)])
         self.lam_c = 0.5 * (self.lam_f[1:] + self.lam_f[:-1])
         self.dlam = np.diff(self.lam_f)
         self.xi_f = np.array([xi_in + (xi_out - xi_in) * p / NX for p in range(NX + 1)])
@@ -138,6 +143,7 @@ class ChannelOracle:
             self._keep["c_" + name] = arr
             setattr(P, name, _ptr(arr))
         P.n_in, P.n_out, P.T_w = n_in, n_out, T_w
+        P.half, P.ends, P.Q0 = int(bool(half)), int(ends), float(Q0)
         self._P = P
         self.W = np.outer(self.a1.w, self.a2.w).ravel()
         self.vol = np.outer(self.dchi, self.dlam)          # [NX][NL] cell volumes dchi_p dlambda_s
@@ -149,6 +155,20 @@ class ChannelOracle:
         nw = np.empty((self.NX, 2))
         lib().oracle_channel_L(ctypes.byref(self._P), _ptr(F), _ptr(out), _ptr(flux), _ptr(nw))
         return out, flux, nw
+
+    def end_flow(self, F):
+        """Flow rate sum_k p^y F_face of f' of every lambda row at the inlet and outlet
+        faces, [2][NL]."""
+        F = np.ascontiguousarray(F, dtype=np.float64).reshape(2, self.NX, self.NL, self.NV)
+        out = np.empty_like(F)
+        rf = np.empty((2, self.NL))
+        lib().oracle_channel_L2(ctypes.byref(self._P), _ptr(F), _ptr(out), None, None, _ptr(rf))
+        return rf
+
+    def profile(self, face: int):
+        """Prescribed flow rate of every lambda row at xi face 0 or NX (ends = 1)."""
+        H = 2.0
+        return 3.0 * self.Q0 / (H * (1.0 + self.phi_f[face])) * (1.0 - 4.0 * self.lam_c ** 2 / H ** 2)
 
     def step(self, F, dt: float, nsteps: int = 1):
         F = np.ascontiguousarray(F, dtype=np.float64).reshape(2, self.NX, self.NL, self.NV).copy()

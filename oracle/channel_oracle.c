@@ -16,6 +16,15 @@
  * ones a zeroth-order extrapolation (the construction of Sec. VI.C.1 with the
  * density fixed instead of the flow rate).
  *
+ * The paper's own boundary conditions are options: the upper half of the channel,
+ * lambda in [0, 1], with specular reflection at the centreline (Sec. VI.C.3: ghost cells
+ * -1, -2, -3 hold cells 0, 1, 2 with p^lambda reversed), and flow-rate ends (Sec. VI.C.1,
+ * VI.C.2): per lambda row s the entering populations see f_eq(n_s, u_s, T_w) with the
+ * Cartesian velocity (u^x, u^y) = (0, Q(lambda_s)) of the parabolic profile Q(lambda) =
+ * 3 Q0 / (H (1 + phi)) (1 - 4 lambda^2 / H^2), H = 2 (Eqs. canalie_inlet, canalie_outlet),
+ * the leaving ones a zeroth-order extrapolation, and n_s makes the row's flow rate
+ * sum_k p^y F_face equal Q(lambda_s) (p^y = V^xi / (1 + phi) at the face).
+ *
  * State layout: F[d][p][s][k], d = f' / f'', p = xi cell (0..NX-1), s = lambda cell
  * (0..NL-1), k = i*Q2 + j (i: p^lambda node, j: p^xi node).  Compiled together with
  * couette_oracle.c (velocity-set machinery shared within the oracle). */
@@ -31,6 +40,9 @@ typedef struct {
     const double *phi_f, *dphi_f;   /* [NX+1] at the xi faces */
     const double *dchi;       /* [NX] chi(xi_{p+1/2}) - chi(xi_{p-1/2}), d chi = (1 + phi) d xi */
     double n_in, n_out, T_w;  /* reservoir densities, wall / reservoir temperature */
+    int half;                 /* 1: lambda in [0, 1], specular centreline at lambda = 0 */
+    int ends;                 /* 0: reservoirs at n_in / n_out; 1: flow-rate profile of Q0 */
+    double Q0;                /* flow rate through half of the cross-section (ends = 1) */
 } channel_params;
 
 /* V^xi at xi-face f of lambda cell s for the velocity (pl, px), Eq. canalie_V */
@@ -40,10 +52,29 @@ static double v_xi(const channel_params* P, int s, int f, double pl, double px) 
     return (1.0 + P->phi_f[f]) * (px - a * pl) / sqrt(1.0 + a * a);
 }
 
+/* Cartesian flow velocity (0, Q) in the triad at an xi face: with a = lambda phi' and
+ * c = 1 / sqrt(1 + a^2), p^x = c (p^lambda + a p^xi), p^y = c (p^xi - a p^lambda), so
+ * u^lambda = -a c Q and u^xi = c Q. */
+static void end_velocity(const channel_params* P, int s, int f, double Q, double* ul, double* ux) {
+    const double lam = 0.5 * (P->lam_f[s] + P->lam_f[s + 1]);
+    const double a = lam * P->dphi_f[f], c = 1.0 / sqrt(1.0 + a * a);
+    *ul = -a * c * Q;
+    *ux = c * Q;
+}
+
+/* prescribed flow rate of row s at the end face f (0 or NX), H = 2 */
+static double end_flow_rate(const channel_params* P, int s, int f) {
+    const double lam = 0.5 * (P->lam_f[s] + P->lam_f[s + 1]), H = 2.0;
+    return 3.0 * P->Q0 / (H * (1.0 + P->phi_f[f])) * (1.0 - 4.0 * lam * lam / (H * H));
+}
+
 /* L[F] (Eq. canalie_boltz for f' and f''); xi_flux (may be NULL) gets, for every xi
  * face f = 0..NX, sum_s dlambda_s sum_k V^xi F_face of f' (particle flux through the
- * cross-section); nw (may be NULL) the wall densities [NX][2] (lower, upper). */
-void oracle_channel_L(const channel_params* P, const double* F, double* L, double* xi_flux, double* nw) {
+ * cross-section); nw (may be NULL) the wall densities [NX][2] (lower, upper; 0 for the
+ * specular centreline); row_flow (may be NULL) the flow rate sum_k p^y F_face of every
+ * lambda row at the inlet and outlet faces [2][NL]. */
+void oracle_channel_L2(const channel_params* P, const double* F, double* L, double* xi_flux, double* nw,
+                       double* row_flow) {
     const couette_params* V = &P->vs;
     const int NL = P->NL, NX = P->NX, Q1 = V->Q1, Q2 = V->Q2, NV = Q1 * Q2;
     const int EL = NL + 6, EX = NX + 6;
@@ -103,17 +134,23 @@ void oracle_channel_L(const channel_params* P, const double* F, double* L, doubl
                                                     GX(0, p, -2, k), V->weno_eps);
                 }
             }
-        const double nw_lo = -num_lo / den_lo, nw_hi = -num_hi / den_hi;
+        const double nw_lo = P->half ? 0.0 : -num_lo / den_lo, nw_hi = -num_hi / den_hi;
         if (nw) { nw[2 * p] = nw_lo; nw[2 * p + 1] = nw_hi; }
         for (int i = 0; i < Q1; ++i)
             for (int j = 0; j < Q2; ++j) {
                 const int k = i * Q2 + j;
                 const double pl = V->p1[i];
                 for (int g = 1; g <= 3; ++g) {
-                    if (pl > 0) {
+                    if (P->half) {
+                        /* specular centreline: cell g - 1 with p^lambda reversed */
+                        const int kbar = ((i + V->Qh1) % Q1) * Q2 + j;
+                        GX(0, p, -g, k) = GX(0, p, g - 1, kbar);
+                        GX(1, p, -g, k) = GX(1, p, g - 1, kbar);
+                    } else if (pl > 0) {
                         GX(0, p, -g, k) = nw_lo * feq_w[k];
                         GX(1, p, -g, k) = nw_lo * feq_w[NV + k];
-                    } else if (pl < 0) {
+                    }
+                    if (pl < 0) {
                         GX(0, p, NL - 1 + g, k) = nw_hi * feq_w[k];
                         GX(1, p, NL - 1 + g, k) = nw_hi * feq_w[NV + k];
                     }
@@ -123,7 +160,33 @@ void oracle_channel_L(const channel_params* P, const double* F, double* L, doubl
     /* 2b. reservoir ends, per lambda row: entering populations (V^xi > 0 at the inlet
      * face, < 0 at the outlet face) see the reservoir Maxwellian, leaving ones the
      * nearest interior cell */
-    for (int s = 0; s < NL; ++s)
+    for (int s = 0; s < NL; ++s) {
+        if (P->ends == 1) {
+            /* flow-rate ends: the Maxwellians of the row's profile velocity at unit density,
+             * scaled by the density that makes the row's flow rate the prescribed one */
+            double ul, ux;
+            end_velocity(P, s, 0, end_flow_rate(P, s, 0), &ul, &ux);
+            oracle_feq(V, 1.0, ul, ux, P->T_w, feq_in, feq_in + NV);
+            end_velocity(P, s, NX, end_flow_rate(P, s, NX), &ul, &ux);
+            oracle_feq(V, 1.0, ul, ux, P->T_w, feq_out, feq_out + NV);
+            double lin = 0, din = 0, lout = 0, dout = 0;
+            for (int i = 0; i < Q1; ++i)
+                for (int j = 0; j < Q2; ++j) {
+                    const int k = i * Q2 + j;
+                    const double pyi = v_xi(P, s, 0, V->p1[i], V->p2[j]) / (1.0 + P->phi_f[0]);
+                    const double pyo = v_xi(P, s, NX, V->p1[i], V->p2[j]) / (1.0 + P->phi_f[NX]);
+                    if (pyi > 0) din += feq_in[k] * pyi;
+                    else lin += GX(0, 0, s, k) * pyi;
+                    if (pyo < 0) dout += feq_out[k] * pyo;
+                    else lout += GX(0, NX - 1, s, k) * pyo;
+                }
+            const double nin = (end_flow_rate(P, s, 0) - lin) / din;
+            const double nout = (end_flow_rate(P, s, NX) - lout) / dout;
+            for (int k = 0; k < 2 * NV; ++k) {
+                feq_in[k] *= nin;
+                feq_out[k] *= nout;
+            }
+        }
         for (int i = 0; i < Q1; ++i)
             for (int j = 0; j < Q2; ++j) {
                 const int k = i * Q2 + j;
@@ -135,6 +198,9 @@ void oracle_channel_L(const channel_params* P, const double* F, double* L, doubl
                         GX(d, NX - 1 + g, s, k) = vout < 0 ? feq_out[d * NV + k] : GX(d, NX - 1, s, k);
                     }
             }
+    }
+    if (row_flow)
+        for (int x = 0; x < 2 * NL; ++x) row_flow[x] = 0.0;
 
     /* face values of the xi-fluxes of f' for the cross-section fluxes */
     if (xi_flux)
@@ -195,6 +261,10 @@ void oracle_channel_L(const channel_params* P, const double* F, double* L, doubl
                                                          GX(d, f - 1, s, k), GX(d, f - 2, s, k), V->weno_eps);
                         }
                         const double adv_x = (Vx[1] * Fx[1] - Vx[0] * Fx[0]) / P->dchi[p];
+                        if (row_flow && d == 0) {
+                            if (p == 0) row_flow[s] += Vx[0] * Fx[0] / (1.0 + P->phi_f[0]);
+                            if (p == NX - 1) row_flow[NL + s] += Vx[1] * Fx[1] / (1.0 + P->phi_f[NX]);
+                        }
                         if (xi_flux && d == 0) {
                             xi_flux[p + 1] += dlam * Vx[1] * Fx[1] / (p + 1 < NX ? 2.0 : 1.0);
                             xi_flux[p] += dlam * Vx[0] * Fx[0] / (p > 0 ? 2.0 : 1.0);
@@ -217,6 +287,10 @@ void oracle_channel_L(const channel_params* P, const double* F, double* L, doubl
 #undef GX
 #undef FX
     free(G); free(mom); free(fe); free(feq_w); free(feq_in); free(feq_out);
+}
+
+void oracle_channel_L(const channel_params* P, const double* F, double* L, double* xi_flux, double* nw) {
+    oracle_channel_L2(P, F, L, xi_flux, nw, NULL);
 }
 
 /* nsteps SSP-RK3 steps (Eq. rk3) in place */

@@ -96,3 +96,58 @@ def test_steady_flux_is_the_same_through_every_cross_section():
     assert flux.min() > 0
     # at r < 1e-10 the mass between two faces still changes by ~ r |F|, about 1e-9 here
     assert (flux.max() - flux.min()) <= 1e-6 * flux.max()
+
+
+# ---------------------------------------------------------------- the paper's own boundary conditions
+def _mirror(o, F):
+    """(lambda, p^lambda) -> (-lambda, -p^lambda) of a full-width state."""
+    Qh = o.a1.Q
+    mi = np.array([(i + Qh) % (2 * Qh) for i in range(2 * Qh)])
+    G = F.reshape(2, o.NX, o.NL, o.Q1, o.Q2)[:, :, ::-1, mi, :]
+    return G.reshape(2, o.NX, o.NL, o.NV)
+
+
+@pytest.mark.parametrize("ends,Q0", [(0, 0.0), (1, 0.08)])
+def test_half_channel_is_the_upper_half_of_the_full_channel(ends, Q0):
+    """Specular centreline (Sec. VI.C.3): for a mirror-symmetric full-width state the
+    half channel's L equals the upper half of the full channel's L (the ghost cells hold
+    exactly the values the full channel has there)."""
+    kw = dict(NX=7, ax1=(1, 4, 3), ax2=(0, 5, 4), Kn=0.1, r=1.8, n_in=1.05, n_out=0.95, ends=ends, Q0=Q0)
+    full = ChannelOracle(NL=8, **kw)
+    half = ChannelOracle(NL=4, half=True, **kw)
+    assert np.array_equal(half.lam_f, full.lam_f[4:])
+    F = _perturbed(full, 4)
+    F = 0.5 * (F + _mirror(full, F))
+    Lf, _, _ = full.L(F)
+    Lh, _, nwh = half.L(np.ascontiguousarray(F[:, :, 4:]))
+    assert np.abs(Lh - Lf[:, :, 4:]).max() <= 1e-14 * np.abs(Lf).max()
+    assert np.all(nwh[:, 0] == 0.0)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_flow_rate_ends_impose_the_profile(seed):
+    """Sec. VI.C.1-2: with the entering populations at f_eq(n_s, u_s, T_w) and n_s from the
+    row balance, every lambda row carries exactly the prescribed flow rate through both end
+    faces, whatever the state inside."""
+    o = ChannelOracle(NL=8, NX=9, ax1=(1, 4, 3), ax2=(0, 5, 4), Kn=0.2, ends=1, Q0=0.1)
+    F = _perturbed(o, seed)
+    rf = o.end_flow(F)
+    assert np.abs(rf[0] - o.profile(0)).max() <= 1e-13
+    assert np.abs(rf[1] - o.profile(o.NX)).max() <= 1e-13
+    # (1 + phi) Q(lambda) does not depend on phi: the same flux enters and leaves, so the
+    # particle content is constant for any state (walls pass nothing, force and collision
+    # conserve particles)
+    L, flux, _ = o.L(F)
+    dN = float((o.vol * L[0].sum(-1)).sum())
+    assert abs(flux[0] - flux[-1]) <= 1e-14
+    assert abs(dN) <= 1e-12 * abs(flux[0])
+    assert flux[0] > 0.05
+
+
+def test_half_channel_particle_balance():
+    """Half channel with reservoir ends: the centreline passes no particles either."""
+    o = ChannelOracle(NL=5, NX=8, ax1=(1, 4, 3), ax2=(0, 5, 4), Kn=0.2, half=True, n_in=1.1, n_out=0.9)
+    F = _perturbed(o, 3)
+    L, flux, _ = o.L(F)
+    dN = float((o.vol * L[0].sum(-1)).sum())
+    assert dN == pytest.approx(flux[0] - flux[-1], rel=1e-11, abs=1e-14)
