@@ -296,7 +296,12 @@ vlb_status vlb_batch_warm_start(vlb_batch* b, vlb_mlp* m, int probe_steps, int* 
  * walls: the full channel width); reservoir ends: populations entering through the
  * inlet (outlet) see ghost cells at the Maxwellian f_eq(n_in (n_out), 0, T_w), leaving
  * ones the nearest interior cell (the construction of Sec. VI.C.1 with the density
- * fixed).  ax1 is the p^lambda axis and must be half range (kind 1); ax2 the p^xi axis.
+ * fixed).  The paper's own conditions are options: half = 1 simulates lambda in [0, 1]
+ * with specular reflection at the centreline; ends = 1 makes every lambda row carry the
+ * parabolic flow rate Q(lambda) = 3 Q0 / (H (1 + phi)) (1 - 4 lambda^2 / H^2), H = 2, through
+ * both end faces (entering populations at f_eq(n_s, u_s, T_w), u_s the profile velocity,
+ * n_s from the row balance; leaving ones extrapolated at zeroth order).
+ * ax1 is the p^lambda axis and must be half range (kind 1); ax2 the p^xi axis.
  * tau_model as for the Couette instances (Sec. VI uses VLB_TAU_HYDRO, Eq. canalie_tau).
  * State of an instance: [2][N_xi][N_lambda][NV] doubles (f', f''; xi cell; lambda cell;
  * k = i * Q2 + j); the initial state is the rest Maxwellian n = 1, u = 0, T = T_w
@@ -319,6 +324,9 @@ typedef struct {
     double dt, cfl;
     double n_in, n_out, T_w;
     double weno_eps;
+    int half;     /* 1: the upper half lambda in [0, 1] with a specular centreline (Sec. VI.C.3) */
+    int ends;     /* 0: reservoirs at n_in / n_out; 1: the flow-rate profile of Sec. VI.C.1-2 */
+    double Q0;    /* ends = 1: flow rate through half of the cross-section */
 } vlb_channel_desc;
 typedef struct vlb_channel vlb_channel;
 

@@ -27,8 +27,8 @@ struct vlb_channel {
     struct Group {
         int T1, T2;
         std::vector<int> ilist;
-        std::vector<long long> base;
-        size_t off_ilist, off_base;
+        std::vector<long long> base, bbase;   // blocks of the interior and of the edge-band launch
+        size_t off_ilist, off_base, off_bbase;
     };
     std::vector<Group> groups;
     size_t state_n = 0, ncells = 0;
@@ -54,6 +54,7 @@ struct vlb_channel {
     ChanDesc* ddesc() { return (ChanDesc*)(ws + off_desc); }
     const int* gilist(const Group& g) { return (const int*)(ws + g.off_ilist); }
     const long long* gbase(const Group& g) { return (const long long*)(ws + g.off_base); }
+    const long long* gbbase(const Group& g) { return (const long long*)(ws + g.off_bbase); }
     long long* dcbase() { return (long long*)(ws + off_cbase); }
 };
 
@@ -125,7 +126,8 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
     long long cells = 0;
     for (int i = 0; i < B; ++i) {
         const vlb_channel_desc& d = descs[i];
-        if (!(d.N_lambda >= 6 && d.N_xi >= 3 && d.xi_out > d.xi_in && d.r > 0 && d.L > 0 && d.Kn > 0 &&
+        if (!(d.N_lambda >= (d.half ? 3 : 6) && (d.half == 0 || d.half == 1) && (d.ends == 0 || d.ends == 1) &&
+              std::isfinite(d.Q0) && d.N_xi >= 3 && d.xi_out > d.xi_in && d.r > 0 && d.L > 0 && d.Kn > 0 &&
               d.tau_model >= 0 && d.tau_model <= 2 && axis_ok(d.ax1) && d.ax1.kind == 1 && axis_ok(d.ax2) &&
               d.dt >= 0 && (d.dt > 0 || d.cfl > 0) && d.n_in > 0 && d.n_out > 0 && d.T_w > 0 && d.weno_eps >= 0 &&
               std::isfinite(d.weno_eps))) {
@@ -154,6 +156,8 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         D.tau_model = d.tau_model;
         D.Kn = d.Kn;
         D.weno_eps = d.weno_eps;
+        D.half = d.half;
+        D.ends = d.ends;
         D.offF = (long long)offF;
         D.offC = (long long)offC;
         D.offT = (long long)c->tab.size();
@@ -217,10 +221,11 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
             E.tfw = put(fws); E.tfin = put(fins); E.tfout = put(fouts);
             E.tiW = D.tWm;
         }
-        // geometry (Sec. VI.A): lambda in [-1, 1] and xi on equal cells
+        // geometry (Sec. VI.A): lambda in [-1, 1] (the upper half [0, 1] with a specular
+        // centreline) and xi on equal cells
         const Wall w{(long double)d.r, (long double)d.L};
         std::vector<long double> lf(NL + 1), xf(NX + 1);
-        for (int s = 0; s <= NL; ++s) lf[s] = -1.0L + 2.0L * s / NL;
+        for (int s = 0; s <= NL; ++s) lf[s] = d.half ? (long double)s / NL : -1.0L + 2.0L * s / NL;
         for (int p = 0; p <= NX; ++p) xf[p] = (long double)d.xi_in + ((long double)d.xi_out - d.xi_in) * p / NX;
         std::vector<double> al(NX * NL), ar(NX * NL), glxx(NX * NL), glxl(NX * NL), xc((NX + 1) * NL),
             xa((NX + 1) * NL), dlam(NL), dchi(NX), vol(NX * NL);
@@ -264,10 +269,47 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         }
         D.tal = put(al); D.tar = put(ar); D.tglxx = put(glxx); D.tglxl = put(glxl);
         D.txc = put(xc); D.txa = put(xa); D.tdlam = put(dlam); D.tdchi = put(dchi); D.tvol = put(vol);
+        D.ipf_in = (double)(1 / (1 + w.phi(xf[0])));
+        D.ipf_out = (double)(1 / (1 + w.phi(xf[NX])));
+        if (d.ends == 1) {
+            // flow-rate ends (Sec. VI.C.1-2): per end and lambda row the prescribed flow rate
+            // Q(lambda_s) = 3 Q0 / (H (1 + phi)) (1 - 4 lambda_s^2 / H^2), H = 2, the unit-density
+            // Maxwellian of the Cartesian velocity (0, Q) in the face's triad (a = lambda phi',
+            // c = 1 / sqrt(1 + a^2): u^lambda = -a c Q, u^xi = c Q), and its entering flow
+            std::vector<double> Qrow(2 * NL), den(2 * NL), frow((size_t)2 * NL * 2 * NV), gl(n1), gx(n2);
+            for (int e = 0; e < 2; ++e) {
+                const int f = e ? NX : 0;
+                for (int s = 0; s < NL; ++s) {
+                    const long double lam = (lf[s] + lf[s + 1]) / 2, a = lam * w.dphi(xf[f]);
+                    const long double cc = 1 / std::sqrt(1 + a * a);
+                    const double Q = (double)(3 * (long double)d.Q0 / (2 * (1 + w.phi(xf[f]))) * (1 - lam * lam));
+                    axis_equilibrium_host(*a1, (double)(-a * cc * Q), d.T_w, gl.data());
+                    axis_equilibrium_host(*a2, (double)(cc * Q), d.T_w, gx.data());
+                    double dd = 0.0;
+                    for (int ia = 0; ia < n1; ++ia)
+                        for (int jb = 0; jb < n2; ++jb) {
+                            const int k = ia * n2 + jb;
+                            const double fe = gl[ia] * gx[jb];
+                            frow[((size_t)(e * NL + s) * 2) * NV + k] = fe;
+                            frow[((size_t)(e * NL + s) * 2 + 1) * NV + k] = d.T_w * fe;
+                            const double py = (double)(cc * (a2->p[jb] - a * a1->p[ia]));
+                            if (e == 0 ? py > 0 : py < 0) dd += fe * py;
+                        }
+                    Qrow[e * NL + s] = Q;
+                    den[e * NL + s] = dd;
+                }
+            }
+            D.tQrow = put(Qrow); D.tden = put(den); D.tfrow = put(frow);
+            if (precision == VLB_MIXED) {
+                for (size_t x = 0; x < frow.size(); ++x) frow[x] *= iW[x % NV];
+                c->desc32[i].tfrow = put(frow);
+            }
+        }
         if (precision == VLB_MIXED) {
             ChanDesc& E = c->desc32[i];
             E.tal = D.tal; E.tar = D.tar; E.tglxx = D.tglxx; E.tglxl = D.tglxl;
             E.txc = D.txc; E.txa = D.txa; E.tdlam = D.tdlam; E.tdchi = D.tdchi; E.tvol = D.tvol;
+            E.ipf_in = D.ipf_in; E.ipf_out = D.ipf_out; E.tQrow = D.tQrow; E.tden = D.tden;
         }
         // dt: advection CFL combined with the force limit |lambda dt| <= sqrt(3) of RK3, capped
         // at 2 tau of the rest state (as for the Couette instances)
@@ -286,14 +328,18 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
             auto it = std::find_if(c->groups.begin(), c->groups.end(),
                                    [&](const vlb_channel::Group& g) { return g.T1 == T1 && g.T2 == T2; });
             if (it == c->groups.end()) {
-                c->groups.push_back(vlb_channel::Group{T1, T2, {}, {0}, 0, 0});
+                c->groups.push_back(vlb_channel::Group{T1, T2, {}, {0}, {0}, 0, 0, 0});
                 it = c->groups.end() - 1;
             }
-            // lambda strips of up to kChanStrip cells (a multiple of kChanWaves)
-            D.strip = std::min(kChanStrip, (NL + kChanWaves - 1) / kChanWaves * kChanWaves);
-            const long long nstrips = (NL + D.strip - 1) / D.strip;
+            // interior cells (3 <= s < NL - 3, 3 <= p < NX - 3) in lambda strips of up to
+            // kChanStrip cells (a multiple of kChanWaves); edge-band cells in order
+            const int NLi = std::max(NL - 6, 0), NXi = std::max(NX - 6, 0);
+            D.strip = std::max(kChanWaves, std::min(kChanStrip, (NLi + kChanWaves - 1) / kChanWaves * kChanWaves));
+            const long long nstrips = (NLi + D.strip - 1) / D.strip;
+            const long long bcells = (long long)std::min(NL, 6) * NX + (long long)NLi * std::min(NX, 6);
             it->ilist.push_back(i);
-            it->base.push_back(it->base.back() + nstrips * NX * (D.strip / kChanWaves));
+            it->base.push_back(it->base.back() + (NXi > 0 ? nstrips * NXi * (D.strip / kChanWaves) : 0));
+            it->bbase.push_back(it->bbase.back() + (bcells + kChanWaves - 1) / kChanWaves);
         }
         if (precision == VLB_MIXED) {   // fields set after the table section
             ChanDesc& E = c->desc32[i];
@@ -308,7 +354,7 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
     }
     c->cbase.push_back(cells);
     for (const auto& g : c->groups)   // one dispatch covers fewer than 2^32 work-items
-        if (g.base.back() * kChanWaves * kWave >= (1LL << 32)) {
+        if (std::max(g.base.back(), g.bbase.back()) * kChanWaves * kWave >= (1LL << 32)) {
             delete c;
             return set_error(VLB_EINVAL, "batch too large for one stage launch (%lld blocks)", g.base.back());
         }
@@ -330,6 +376,7 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
     for (auto& g : c->groups) {
         g.off_ilist = off; off = al256(off + g.ilist.size() * sizeof(int));
         g.off_base = off; off = al256(off + g.base.size() * sizeof(long long));
+        g.off_bbase = off; off = al256(off + g.bbase.size() * sizeof(long long));
     }
     c->off_cbase = off; off = al256(off + (B + 1) * sizeof(long long));
     c->total = off;
@@ -356,6 +403,9 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
                                hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(c->ws + g.off_base, g.base.data(), g.base.size() * sizeof(long long),
+                               hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->ws + g.off_bbase, g.bbase.data(), g.bbase.size() * sizeof(long long),
                                hipMemcpyHostToDevice, c->stream);
     }
     if (e == hipSuccess)
@@ -476,9 +526,11 @@ vlb_status channel_stage(vlb_channel* c, int stage, bool last, bool l_only) {
     }
     for (const auto& g : c->groups) {
         A.ilist = c->gilist(g);
-        A.base = c->gbase(g);
         A.B = (int)g.ilist.size();
-        VLB_HIP_TRY(launch_channel_stage(f32 ? 1 : 0, g.T1, g.T2, g.base.back(), c->stream, A));
+        A.base = c->gbase(g);
+        VLB_HIP_TRY(launch_channel_stage(f32 ? 1 : 0, g.T1, g.T2, 0, g.base.back(), c->stream, A));
+        A.base = c->gbbase(g);
+        VLB_HIP_TRY(launch_channel_stage(f32 ? 1 : 0, g.T1, g.T2, 1, g.bbase.back(), c->stream, A));
     }
     return VLB_OK;
 }

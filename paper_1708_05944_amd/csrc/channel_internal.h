@@ -23,7 +23,12 @@ struct ChanDesc {
     int tdlam, tdchi, tvol;       // [NL], [NX], cell volumes dchi dlambda [NX][NL]
     int strip;                    // stage-kernel traversal: lambda strips of `strip` cells, swept along xi
     int tWm;                      // [NV] W_k = w_i w_j (FP32 scaling and moment weights)
-    int pad2;
+    int half;                     // 1: lambda in [0, 1], specular centreline at lambda = 0
+    int ends;                     // 0: reservoir ends; 1: flow-rate ends
+    int tQrow, tden, tfrow, pad3; // flow-rate ends: prescribed row flow [2][NL] (inlet, outlet),
+                                  // sum over entering k of p^y f_eq(1, u_s) [2][NL], the unit-density
+                                  // Maxwellians of the rows [2][NL][2][NV] (end, row, f' / f'')
+    double ipf_in, ipf_out;       // 1 / (1 + phi) at the inlet and outlet faces
 };
 
 constexpr int kChanWaves = 4;   // stage kernel: cells (one wavefront each) per block
@@ -46,7 +51,9 @@ struct ChanArgs {
     int l_only;              // 1: out = L[Fin]
 };
 
-hipError_t launch_channel_stage(int fp32, int T1, int T2, long long nblocks, hipStream_t st, const ChanArgs& A);
+// bnd = 0: the interior cells; bnd = 1: the edge bands (base[] of the matching block list)
+hipError_t launch_channel_stage(int fp32, int T1, int T2, int bnd, long long nblocks, hipStream_t st,
+                                const ChanArgs& A);
 hipError_t launch_channel_rest(long long nelems, hipStream_t st, const ChanDesc* insts, const long long* sbase, int B,
                                const double* tab, double* F64);
 hipError_t launch_channel_convert(int to32, long long nelems, hipStream_t st, const ChanDesc* insts,

@@ -114,8 +114,11 @@ struct Acc4<float> {
 // descriptor are rescaled to match (kernels diag(1/w) K diag(w), bases and ghost
 // Maxwellians over w or W, residual weight W), and the moment and wall-flux sums
 // multiply by W_k in FP64.
-template <typename T, int T1, int T2>
-__global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs A) {
+// BND = false: the interior cells (3 <= s < NL - 3, 3 <= p < NX - 3), whose stencils stay
+// inside the grid, without any ghost logic; BND = true: the cells of the edge bands (walls,
+// centreline, ends).  The two launches of a stage write disjoint cells.
+template <typename T, int T1, int T2, bool BND>
+__global__ __launch_bounds__(kChanWaves * kWave, T1 * T2 == 1 ? (sizeof(T) == 4 ? 4 : (BND ? 2 : 3)) : 2) void channel_stage(ChanArgs A) {
     constexpr bool F32 = sizeof(T) == 4;
     constexpr int NT = T1 * T2, NI = 4 * NT;   // items (tile registers) per lane per distribution
     constexpr int RS = 16 * T2 + 2;           // LDS row stride of the transpose buffer
@@ -154,14 +157,35 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
     }
     __syncthreads();   // the only block-wide barrier; the wavefronts are independent below
 
-    // blocks of an instance: lambda strips of W cells, each swept along xi, kChanWaves
-    // consecutive lambda cells per block (the stencil neighbours of a block are then
-    // recent blocks of the same XCD)
-    const int W = I.strip, bpw = W / kChanWaves;
     const int lbi = (int)(lb - A.base[gi]);
-    const int strip = lbi / (NX * bpw), rem = lbi - strip * (NX * bpw);
-    const int p = rem / bpw, s = strip * W + (rem - p * bpw) * kChanWaves + wave;
-    if (s >= NL) return;
+    const int NLi = NL > 6 ? NL - 6 : 0, NXi = NX > 6 ? NX - 6 : 0;   // interior extent
+    int p, s;
+    if (!BND) {
+        // interior cells in lambda strips of W cells, each swept along xi, kChanWaves
+        // consecutive lambda cells per block (the stencil neighbours of a block are then
+        // recent blocks of the same XCD)
+        const int W = I.strip, bpw = W / kChanWaves;
+        const int strip = lbi / (NXi * bpw), rem = lbi - strip * (NXi * bpw);
+        p = 3 + rem / bpw;
+        s = 3 + strip * W + (rem - (rem / bpw) * bpw) * kChanWaves + wave;
+        if (s >= NL - 3) return;
+    } else {
+        // edge bands: the rows s < 3, s >= NL - 3 across all columns, then the columns
+        // p < 3, p >= NX - 3 of the interior rows
+        const int rA = NL < 6 ? NL : 6, cA = NX < 6 ? NX : 6;
+        const int c = lbi * kChanWaves + wave;
+        if (c < rA * NX) {
+            const int r = c % rA;
+            p = c / rA;
+            s = r < 3 ? r : NL - rA + r;
+        } else {
+            const int c2 = c - rA * NX;
+            if (c2 >= NLi * cA) return;
+            const int r = c2 % cA;
+            p = r < 3 ? r : NX - cA + r;
+            s = 3 + c2 / cA;
+        }
+    }
     const int cell = p * NL + s;
     const T eps = T(I.weno_eps);
     T* tr = trs[wave];
@@ -238,7 +262,7 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
     // ---- wall densities of this xi column (lambda = -1: emitted p^lambda > 0; +1: < 0),
     // FP64 sums of the wall-bound flux
     double nw_lo = 0.0, nw_hi = 0.0;
-    if (s < 3) {
+    if (BND && s < 3 && !I.half) {
         double w = 0.0;
         const T* C0 = F + (size_t)p * NL * NV;
 #pragma unroll
@@ -252,7 +276,7 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
             }
         nw_lo = -wave_sum(w) / I.den_lo;
     }
-    if (s >= NL - 3) {
+    if (BND && s >= NL - 3) {
         double w = 0.0;
         const T* C0 = F + ((size_t)p * NL + NL - 1) * NV;
 #pragma unroll
@@ -267,6 +291,33 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
         nw_hi = -wave_sum(w) / I.den_hi;
     }
 
+    // ---- flow-rate ends (Sec. VI.C.1-2): the density of the row's entering Maxwellian that
+    // makes the row's flow rate sum_k p^y F_face the prescribed one, from FP64 sums of the
+    // leaving populations of the end cell (p^y = V^xi / (1 + phi) at the end face)
+    double nin_row = 0.0, nout_row = 0.0;
+    if (BND && I.ends == 1 && (p < 3 || p >= NX - 3)) {
+        const bool at_in = p < 3;
+        const int f = at_in ? 0 : NX;
+        const double cf = tab[I.txc + (size_t)f * NL + s], af = tab[I.txa + (size_t)f * NL + s];
+        const double ipf = at_in ? I.ipf_in : I.ipf_out;
+        const T* C0 = F + ((size_t)(at_in ? 0 : NX - 1) * NL + s) * NV;
+        double w = 0.0;
+#pragma unroll
+        for (int t = 0; t < NI; ++t)
+            if (item_ok(t)) {
+                const int k = item_k(t);
+                const double py = cf * (item_px(t) - af * item_pl(t)) * ipf;
+                if (at_in ? py <= 0.0 : py >= 0.0) {
+                    const double fv = (double)C0[k];
+                    w += py * (F32 ? Wm[k] * fv : fv);
+                }
+            }
+        w = wave_sum(w);
+        const double nr = (tab[I.tQrow + (at_in ? 0 : NL) + s] - w) / tab[I.tden + (at_in ? 0 : NL) + s];
+        if (at_in) nin_row = nr;
+        else nout_row = nr;
+    }
+
     // ---- per-cell geometry
     const T glxx = T(tab[I.tglxx + cell]), gxll = T(-tab[I.tglxl + cell]);
     const T al = T(tab[I.tal + cell]), ar = T(tab[I.tar + cell]);
@@ -277,7 +328,7 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
     const T xc1 = T(xc[(size_t)(p + 1) * NL + s]), xa1 = T(xa[(size_t)(p + 1) * NL + s]);
     const T xcin = T(xc[s]), xain = T(xa[s]), xcout = T(xc[(size_t)NX * NL + s]),
             xaout = T(xa[(size_t)NX * NL + s]);
-    const bool lam_interior = s >= 3 && s < NL - 3, xi_interior = p >= 3 && p < NX - 3;
+    const bool lam_interior = !BND || (s >= 3 && s < NL - 3), xi_interior = !BND || (p >= 3 && p < NX - 3);
     const bool lonly = A.l_only != 0;
     const double dt = lonly ? 1.0 : I.dt;
     const T ca = T(A.ca), cb = T(A.cb), ccdt = T(A.cc * dt);
@@ -367,7 +418,10 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
                         if (cc >= 0 && cc < NL) {
                             v = Col[(size_t)cc * NV + k];
                         } else if (cc < 0) {
-                            if (plt > T(0)) {
+                            if (I.half) {
+                                // specular centreline (Sec. VI.C.3): cell -1 - cc, p^lambda reversed
+                                v = Col[(size_t)(-1 - cc) * NV + ((i + I.Qh1) % Q1) * Q2 + j];
+                            } else if (plt > T(0)) {
                                 v = T(nw_lo * fw[k]);                                // Eq. weno_populate
                             } else {
                                 const T F1 = Col[k], F2 = Col[NV + k], F3 = Col[2 * NV + k];
@@ -398,9 +452,18 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
                     for (int q = 0; q < 7; ++q) {
                         const int cc = p - 3 + q;
                         T v;
-                        if (cc >= 0 && cc < NX) v = Row[(size_t)cc * xstride + k];
-                        else if (cc < 0) v = vin > T(0) ? T(tab[I.tfin + d * NV + k]) : Row[k];
-                        else v = vout < T(0) ? T(tab[I.tfout + d * NV + k]) : Row[(size_t)(NX - 1) * xstride + k];
+                        if (cc >= 0 && cc < NX) {
+                            v = Row[(size_t)cc * xstride + k];
+                        } else if (cc < 0) {
+                            const T ent = I.ends == 1 ? T(nin_row * tab[I.tfrow + ((size_t)s * 2 + d) * NV + k])
+                                                      : T(tab[I.tfin + d * NV + k]);
+                            v = vin > T(0) ? ent : Row[k];
+                        } else {
+                            const T ent = I.ends == 1
+                                              ? T(nout_row * tab[I.tfrow + ((size_t)(NL + s) * 2 + d) * NV + k])
+                                              : T(tab[I.tfout + d * NV + k]);
+                            v = vout < T(0) ? ent : Row[(size_t)(NX - 1) * xstride + k];
+                        }
                         xw[q] = v;
                     }
                 }
@@ -424,7 +487,7 @@ __global__ __launch_bounds__(kChanWaves * kWave, 2) void channel_stage(ChanArgs 
                 lcb[i * RS + j] -= plt * adv_l * idl + adv_x * idx;
             }
         };
-        if (lam_interior && xi_interior) advect(std::true_type{});
+        if (!BND) advect(std::true_type{});
         else advect(std::false_type{});
 
         // BGK, RK combination, store, residual partials (FP64)
@@ -549,19 +612,27 @@ __global__ __launch_bounds__(kMaxNV) void channel_diag(const ChanDesc* insts, co
     }
 }
 
-hipError_t launch_channel_stage(int fp32, int T1, int T2, long long nblocks, hipStream_t st, const ChanArgs& A) {
+hipError_t launch_channel_stage(int fp32, int T1, int T2, int bnd, long long nblocks, hipStream_t st,
+                                const ChanArgs& A) {
+    if (nblocks == 0) return hipSuccess;
     const dim3 grid((unsigned)nblocks), block(kChanWaves * kWave);
+#define VLB_CHAN_LAUNCH(TT, A1, A2)                                                                  \
+    do {                                                                                             \
+        if (bnd) hipLaunchKernelGGL((channel_stage<TT, A1, A2, true>), grid, block, 0, st, A);        \
+        else hipLaunchKernelGGL((channel_stage<TT, A1, A2, false>), grid, block, 0, st, A);           \
+    } while (0)
     if (fp32) {
-        if (T1 == 1 && T2 == 1) hipLaunchKernelGGL((channel_stage<float, 1, 1>), grid, block, 0, st, A);
-        else if (T1 == 2 && T2 == 1) hipLaunchKernelGGL((channel_stage<float, 2, 1>), grid, block, 0, st, A);
-        else if (T1 == 1 && T2 == 2) hipLaunchKernelGGL((channel_stage<float, 1, 2>), grid, block, 0, st, A);
+        if (T1 == 1 && T2 == 1) VLB_CHAN_LAUNCH(float, 1, 1);
+        else if (T1 == 2 && T2 == 1) VLB_CHAN_LAUNCH(float, 2, 1);
+        else if (T1 == 1 && T2 == 2) VLB_CHAN_LAUNCH(float, 1, 2);
         else return hipErrorInvalidValue;
     } else {
-        if (T1 == 1 && T2 == 1) hipLaunchKernelGGL((channel_stage<double, 1, 1>), grid, block, 0, st, A);
-        else if (T1 == 2 && T2 == 1) hipLaunchKernelGGL((channel_stage<double, 2, 1>), grid, block, 0, st, A);
-        else if (T1 == 1 && T2 == 2) hipLaunchKernelGGL((channel_stage<double, 1, 2>), grid, block, 0, st, A);
+        if (T1 == 1 && T2 == 1) VLB_CHAN_LAUNCH(double, 1, 1);
+        else if (T1 == 2 && T2 == 1) VLB_CHAN_LAUNCH(double, 2, 1);
+        else if (T1 == 1 && T2 == 2) VLB_CHAN_LAUNCH(double, 1, 2);
         else return hipErrorInvalidValue;
     }
+#undef VLB_CHAN_LAUNCH
     return hipGetLastError();
 }
 

@@ -77,14 +77,16 @@ class _ChannelDesc(ctypes.Structure):
                 ("xi_out", ctypes.c_double), ("r", ctypes.c_double), ("L", ctypes.c_double), ("ax1", _Axis),
                 ("ax2", _Axis), ("Kn", ctypes.c_double), ("tau_model", ctypes.c_int), ("dt", ctypes.c_double),
                 ("cfl", ctypes.c_double), ("n_in", ctypes.c_double), ("n_out", ctypes.c_double),
-                ("T_w", ctypes.c_double), ("weno_eps", ctypes.c_double)]
+                ("T_w", ctypes.c_double), ("weno_eps", ctypes.c_double),
+                ("half", ctypes.c_int), ("ends", ctypes.c_int), ("Q0", ctypes.c_double)]
 
 
 @dataclass
 class ChannelDesc:
     """One expanding channel: N_lambda x N_xi cells, lambda in [-1, 1], xi in
     [xi_in, xi_out], wall 1 + phi(xi) with expansion ratio r over length L; ax1 (p^lambda,
-    half range) and ax2 (p^xi) as (kind, Q, N); reservoir densities n_in / n_out."""
+    half range) and ax2 (p^xi) as (kind, Q, N); reservoir densities n_in / n_out; half:
+    lambda in [0, 1] with a specular centreline; ends = 1: flow-rate profile of Q0."""
     N_lambda: int = 8
     N_xi: int = 12
     xi_in: float = -4.0
@@ -101,11 +103,14 @@ class ChannelDesc:
     n_out: float = 0.9
     T_w: float = 1.0
     weno_eps: float = 0.0
+    half: bool = False
+    ends: int = 0
+    Q0: float = 0.0
 
     def _c(self) -> _ChannelDesc:
         return _ChannelDesc(self.N_lambda, self.N_xi, self.xi_in, self.xi_out, self.r, self.L, _Axis(*self.ax1),
                             _Axis(*self.ax2), self.Kn, self.tau_model, self.dt, self.cfl, self.n_in, self.n_out,
-                            self.T_w, self.weno_eps)
+                            self.T_w, self.weno_eps, int(bool(self.half)), int(self.ends), float(self.Q0))
 _SIGS = {
     "vlb_batch_create_couette": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(_CouetteDesc),
                                  ctypes.c_int, ctypes.c_void_p, ctypes.c_int],

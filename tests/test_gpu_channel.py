@@ -46,6 +46,9 @@ CASES = [
     dict(N_lambda=6, N_xi=11, ax1=(1, 4, 3), ax2=(0, 5, 4), Kn=0.2, weno_eps=1e-6, n_in=1.2),  # regularised WENO
     dict(N_lambda=7, N_xi=8, ax1=(1, 12, 4), ax2=(0, 8, 4), Kn=0.08),                         # 24 x 8: two p^lambda tiles
     dict(N_lambda=6, N_xi=7, ax1=(1, 4, 3), ax2=(0, 20, 4), Kn=0.15, r=2.5),                  # 8 x 20: two p^xi tiles
+    dict(N_lambda=5, N_xi=9, ax1=(1, 4, 3), ax2=(0, 5, 4), Kn=0.1, half=True),                 # specular centreline
+    dict(N_lambda=8, N_xi=9, ax1=(1, 4, 3), ax2=(0, 5, 4), Kn=0.2, ends=1, Q0=0.1),            # flow-rate ends
+    dict(N_lambda=6, N_xi=8, ax1=(1, 8, 4), ax2=(0, 16, 4), Kn=0.05, half=True, ends=1, Q0=0.08),  # the paper's set-up
 ]
 
 
@@ -119,6 +122,20 @@ def test_channel_uneven_batch_matches_oracle():
     c.close()
 
 
+def test_channel_paper_boundary_conditions_steps_match_oracle():
+    """20 RK3 steps of the half channel with flow-rate ends from rest."""
+    from paper_1708_05944_amd import Channel
+    o, d = _pair(**dict(CASES[9]))
+    c = Channel([d])
+    F0 = c.instance_view(c.get_state(), 0).copy()
+    c.step(20)
+    want = o.step(F0, c.info[0]["dt"], 20)
+    err = _relerr(c.instance_view(c.get_state(), 0), want)
+    _say(f"half channel, flow-rate ends, 20 steps rel err {err:.2e}")
+    assert err <= TOL
+    c.close()
+
+
 def test_channel_moments_and_content():
     from paper_1708_05944_amd import Channel
     o, d = _pair(**dict(CASES[2]))
@@ -137,7 +154,7 @@ def test_channel_moments_and_content():
 # FP32 stage kernel on populations scaled by 1/(w_i w_j), FP64 moment / wall-flux /
 # residual sums.  Operator bar: relative max-norm 2e-6 (about 30 ulp of float), against
 # the oracle evaluated on the FP32-rounded state the kernel actually reads.
-MIXED_CASES = [CASES[1], CASES[0], CASES[4], CASES[5], CASES[6]]
+MIXED_CASES = [CASES[1], CASES[0], CASES[4], CASES[5], CASES[6], CASES[7], CASES[8], CASES[9]]
 
 
 @pytest.mark.parametrize("case", MIXED_CASES)
