@@ -91,6 +91,30 @@ def wall_chi(xi, r: float, L: float = 4.0):
         return (x + (r - 1) * (x + mp.mpf(L) / 4 * mp.log(mp.cosh(4 * x / L - 2))) / 2)
 
 
+def d3(f, x, axis):
+    """First derivative of samples f at the (possibly unequally spaced) nodes x along
+    `axis`, by the three-point Lagrange formulas of Sec. VI.F (vorticity): centred on the
+    nodes 1 .. n-2, one-sided second order on the first and last node (the last-node
+    formula with the sign that makes it exact for constants).  Exact for quadratics."""
+    f = np.moveaxis(np.asarray(f, dtype=np.float64), axis, 0)
+    x = np.asarray(x, dtype=np.float64)
+    n = len(x)
+    if n < 3:
+        raise ValueError("need three nodes")
+    out = np.empty_like(f)
+    for s in range(1, n - 1):
+        hm, hp = x[s] - x[s - 1], x[s + 1] - x[s]
+        out[s] = (hm * f[s + 1] / (hp * (hp + hm)) + (hp - hm) * f[s] / (hp * hm)
+                  - hp * f[s - 1] / ((hp + hm) * hm))
+    a, b, c = x[0], x[1], x[2]
+    out[0] = (-(b + c - 2 * a) * f[0] / ((b - a) * (c - a)) + (c - a) * f[1] / ((b - a) * (c - b))
+              - (b - a) * f[2] / ((c - a) * (c - b)))
+    a, b, c = x[n - 1], x[n - 2], x[n - 3]
+    out[n - 1] = ((2 * a - b - c) * f[n - 1] / ((a - b) * (a - c)) - (a - c) * f[n - 2] / ((a - b) * (b - c))
+                  + (a - b) * f[n - 3] / ((a - c) * (b - c)))
+    return np.moveaxis(out, 0, axis)
+
+
 class ChannelOracle:
     """One expanding channel: NL cells across lambda in [-1, 1], NX cells along
     xi in [xi_in, xi_out], expansion ratio r over length L, reservoir densities n_in /
@@ -201,6 +225,44 @@ class ChannelOracle:
         e = ((p1 ** 2 + p2 ** 2) * F[0]).sum(-1) + F[1].sum(-1)
         T = (e - n * (u1 ** 2 + u2 ** 2)) / (3 * n)
         return dict(n=n, u1=u1, u2=u2, T=T)
+
+    def flow_fields(self, F):
+        """Diagnostics of Sec. VI.D and VI.F (plain numpy from the cell moments):
+        ux, uy: Cartesian velocity from the triad components (Eq. canalie_u), [NX][NL];
+        P = n T, [NX][NL];
+        psi: stream function on the lambda faces, [NX][NL + 1], from rho u_y = -d psi / dx
+          (Eq. canalie_psi) integrated across each xi column with dx = (1 + phi) d lambda,
+          psi = 0 on the centreline (lambda = 0);
+        omega: vorticity (Eq. canalie_vorti) at the cell centres, both derivatives by the
+          three-point formulas of d3;
+        Pw: pressure on the lambda faces 0 and NL (the lower wall, or the centreline of the
+          half channel; the upper wall) by linear extrapolation from the two outermost cells
+          (the construction before Eq. canalie_wall_pressure), [2][NX]."""
+        m = self.moments(F)
+        n, ul, ux_hat, T = m["n"], m["u1"], m["u2"], m["T"]
+        lam = np.broadcast_to(self.lam_c[None, :], n.shape)
+        a = lam * self.dphi_c[:, None]
+        c = 1.0 / np.sqrt(1.0 + a * a)
+        ux = (ul + a * ux_hat) * c
+        uy = (ux_hat - a * ul) * c
+        P = n * T
+        # stream function: d psi = -rho u_y dx across each xi column, dx = (1 + phi) d lambda;
+        # the running sum from the lower face, shifted to vanish at lambda = 0 (linear inside
+        # the cell holding it when that is not a face)
+        width = (1.0 + self.phi_c)[:, None] * self.dlam[None, :]
+        cum = np.concatenate([np.zeros((self.NX, 1)), np.cumsum(n * uy * width, axis=1)], axis=1)
+        s0 = min(int(np.searchsorted(self.lam_f, 0.0, side="right")) - 1, self.NL - 1)
+        frac = (0.0 - self.lam_f[s0]) / self.dlam[s0]
+        psi = -(cum - ((1 - frac) * cum[:, s0:s0 + 1] + frac * cum[:, s0 + 1:s0 + 2]))
+        omega = (-d3(ux, self.xi_c, 0) + (d3(uy, self.lam_c, 1) + a * d3(ux, self.lam_c, 1))
+                 / (1.0 + self.phi_c)[:, None])
+        # wall pressure: the line through the two outermost cell values, at the face; the
+        # ratio of the physical offsets x = lambda (1 + phi) equals that of the lambda offsets
+        Pw = np.empty((2, self.NX))
+        for side, (e, i1, i2) in enumerate(((0, 0, 1), (self.NL, self.NL - 1, self.NL - 2))):
+            lw, l1, l2 = self.lam_f[e], self.lam_c[i1], self.lam_c[i2]
+            Pw[side] = ((lw - l2) * P[:, i1] - (lw - l1) * P[:, i2]) / (l1 - l2)
+        return dict(ux=ux, uy=uy, P=P, psi=psi, omega=omega, Pw=Pw)
 
     def mass(self, F):
         F = np.asarray(F).reshape(2, self.NX, self.NL, self.NV)

@@ -151,3 +151,108 @@ def test_half_channel_particle_balance():
     L, flux, _ = o.L(F)
     dN = float((o.vol * L[0].sum(-1)).sum())
     assert dN == pytest.approx(flux[0] - flux[-1], rel=1e-11, abs=1e-14)
+
+
+# ---------------------------------------------------------------- diagnostics (Sec. VI.D, VI.F)
+def test_d3_exact_for_quadratics_on_unequal_nodes():
+    """The three-point formulas (bulk, first and last node) differentiate any quadratic
+    exactly on unequally spaced nodes -- the property they are built on.  A sign slip in
+    any weight (the printed last-node formula has one on its first term) fails this."""
+    from oracle.channel import d3
+    rng = np.random.default_rng(5)
+    x = np.sort(rng.uniform(-1, 1, 9))
+    a, b, c = rng.normal(size=(3, 4))
+    f = a[:, None] + b[:, None] * x[None, :] + c[:, None] * x[None, :] ** 2     # [4][9]
+    want = b[:, None] + 2 * c[:, None] * x[None, :]
+    assert np.allclose(d3(f, x, 1), want, rtol=0, atol=1e-11)
+    assert np.allclose(d3(f.T, x, 0), want.T, rtol=0, atol=1e-11)
+    cubic = x ** 3                                                               # and not beyond
+    assert np.abs(d3(cubic, x, 0) - 3 * x ** 2).max() > 1e-6
+
+
+def test_flow_fields_closed_forms():
+    """Straight channel (r = 1, phi = 0), n = 1 + 0.1 lambda, u^lambda = 0,
+    u^xi = U (1 - lambda^2): u^y = u^xi and u^x = 0; the vorticity d u^y / dx is -2 U lambda
+    (the three-point formulas are exact for quadratics); the wall pressures are the linear
+    extrapolation of P; psi vanishes on the centreline and steps by -n u^y d lambda."""
+    o = ChannelOracle(NL=8, NX=6, ax1=(1, 4, 3), ax2=(0, 6, 4), r=1.0, Kn=0.1)
+    U = 0.05
+    X, S = np.meshgrid(o.xi_c, o.lam_c, indexing="ij")
+    F = o.equilibrium(1 + 0.1 * S, 0.0, U * (1 - S ** 2), 1.0)
+    f = o.flow_fields(F)
+    m = o.moments(F)
+    assert np.abs(f["ux"]).max() <= 1e-15 and np.allclose(f["uy"], m["u2"], rtol=0, atol=1e-15)
+    assert np.allclose(f["omega"], -2 * U * S, rtol=0, atol=1e-12)
+    P = f["P"]
+    for side, (e, i1, i2) in enumerate(((0, 0, 1), (o.NL, o.NL - 1, o.NL - 2))):
+        slope = (P[:, i1] - P[:, i2]) / (o.lam_c[i1] - o.lam_c[i2])
+        assert np.allclose(f["Pw"][side], P[:, i1] + slope * (o.lam_f[e] - o.lam_c[i1]), rtol=0, atol=1e-14)
+    assert abs(f["Pw"][1].mean() - 1.1) < 2e-3 and abs(f["Pw"][0].mean() - 0.9) < 2e-3   # P = n T, T ~ 1
+    assert np.abs(f["psi"][:, o.NL // 2]).max() <= 1e-16
+    assert np.allclose(np.diff(f["psi"], axis=1), -(m["n"] * f["uy"]) * o.dlam[None, :], rtol=0, atol=1e-16)
+
+
+def _solenoidal_state(o, U=0.05):
+    """Unit density and the Cartesian velocity of the stream function
+    psi = -U (lambda - lambda^3 / 3), lambda = x / (1 + phi(y)): the walls are streamlines
+    and the flow through every cross-section is the same; written in the cell triads."""
+    X, S = np.meshgrid(o.xi_c, o.lam_c, indexing="ij")
+    ph = o.phi_c[:, None]
+    dph = o.dphi_c[:, None]
+    uy = U * (1 - S ** 2) / (1 + ph)
+    ux = U * S * dph * (1 - S ** 2) / (1 + ph)
+    a = S * dph
+    c = 1 / np.sqrt(1 + a * a)
+    return o.equilibrium(np.ones_like(S), c * (ux - a * uy), c * (uy + a * ux), 1.0)
+
+
+def test_stream_function_counts_flow_through_the_expansion():
+    """For the solenoidal field the flow -(psi_wall - psi_centre) through every column is
+    the midpoint sum of U (1 - lambda^2) over [0, 1], U (2/3 + h^2/12), whatever phi(xi):
+    this fixes the width element (1 + phi) d lambda of the column integral."""
+    o = ChannelOracle(NL=10, NX=12, ax1=(1, 4, 3), ax2=(0, 6, 4), r=2.0, L=4.0, xi_in=-1.0, xi_out=5.0)
+    U, h = 0.05, 0.2
+    f = o.flow_fields(_solenoidal_state(o, U))
+    want = U * (2 / 3 + h * h / 12)
+    assert np.allclose(f["psi"][:, -1], -want, rtol=1e-13, atol=0)
+    assert np.allclose(f["psi"][:, 0], want, rtol=1e-13, atol=0)
+    assert np.abs(np.diff(o.phi_c)).max() > 0.1        # the columns really differ in width
+
+
+def test_vorticity_converges_to_curl_at_second_order():
+    """Eq. canalie_vorti on the grid against omega = d_x u_y - d_y u_x of the solenoidal
+    field, differentiated in Cartesian coordinates (fine central differences of the closed
+    form): the error falls by about 4 when both spacings halve."""
+    from oracle.channel import wall_phi
+    U, r, L = 0.05, 2.0, 4.0
+
+    def cart(x, y):
+        ph = wall_phi(y, r, L)
+        lam = x / (1 + ph)
+        dph = wall_phi(y, r, L, 1)
+        return U * lam * dph * (1 - lam ** 2) / (1 + ph), U * (1 - lam ** 2) / (1 + ph)
+
+    errs = []
+    for NL, NX in ((16, 24), (32, 48)):
+        o = ChannelOracle(NL=NL, NX=NX, ax1=(1, 4, 3), ax2=(0, 6, 4), r=r, L=L, xi_in=-1.0, xi_out=5.0)
+        f = o.flow_fields(_solenoidal_state(o, U))
+        e = 1e-5
+        want = np.empty((NX, NL))
+        for p in range(NX):
+            for s in range(NL):
+                y = o.xi_c[p]
+                x = o.lam_c[s] * (1 + o.phi_c[p])
+                want[p, s] = ((cart(x + e, y)[1] - cart(x - e, y)[1]) - (cart(x, y + e)[0] - cart(x, y - e)[0])) / (2 * e)
+        errs.append(np.abs(f["omega"] - want).max())
+    assert errs[0] / errs[1] > 3.2, errs
+    assert errs[1] < 2e-3 * U, errs
+
+
+def test_flow_fields_rotation_keeps_speed():
+    """The triad-to-Cartesian rotation of Eq. canalie_u preserves |u| in the expansion."""
+    o = ChannelOracle(NL=8, NX=9, ax1=(1, 4, 3), ax2=(0, 5, 4), r=2.5, xi_in=-1.0, xi_out=3.0)
+    F = _perturbed(o, 6)
+    f = o.flow_fields(F)
+    m = o.moments(F)
+    assert np.allclose(f["ux"] ** 2 + f["uy"] ** 2, m["u1"] ** 2 + m["u2"] ** 2, rtol=1e-13, atol=1e-18)
+    assert np.abs(o.dphi_c).max() > 0.1          # the triad is really tilted here
