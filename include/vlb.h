@@ -358,6 +358,23 @@ vlb_status vlb_channel_residual(vlb_channel* c, double* r);
  * u^lambda, u^xi, T and the particle content dchi dlambda n. */
 vlb_status vlb_channel_moments(vlb_channel* c, int inst, double* n, double* u1, double* u2, double* T,
                                double* content);
+/* Flow diagnostics of instance inst (Sec. VI.D, VI.F), computed on the device from the
+ * FP64 state (a mixed batch's FP32 state is moved there first) into host arrays, each of
+ * which may be NULL:
+ *   ux, uy  [N_xi][N_lambda]  Cartesian velocity (Eq. canalie_u; y along the channel);
+ *   P       [N_xi][N_lambda]  pressure n T;
+ *   psi     [N_xi][N_lambda + 1] stream function on the lambda faces, rho u_y = -d psi / dx
+ *           (Eq. canalie_psi) summed across each xi column with dx = (1 + phi) d lambda,
+ *           zero at lambda = 0 (linear inside the middle cell for odd N_lambda);
+ *   omega   [N_xi][N_lambda]  vorticity of Eq. canalie_vorti at the cell centres, first
+ *           derivatives by three-point formulas (centred inside, one-sided second order on
+ *           the first and last cells);
+ *   Pw      [2][N_xi]         P extrapolated linearly from the two outermost cells to the
+ *           lambda faces 0 (lower wall, or the centreline of the half channel) and N_lambda
+ *           (upper wall).
+ * Synchronises.  Errors: VLB_EINVAL (bad instance), VLB_EDEVICE. */
+vlb_status vlb_channel_flow_fields(vlb_channel* c, int inst, double* ux, double* uy, double* P, double* psi,
+                                   double* omega, double* Pw);
 vlb_status vlb_channel_run_to_steady(vlb_channel* c, double tol, long max_steps, int check_every, long* steps,
                                      double* r);
 

@@ -40,7 +40,8 @@ struct vlb_channel {
     long fp32_steps = 0;            // steps of the FP32 phase of the last run_to_steady
     char* ws = nullptr;
     size_t off_F[3], off_F32[3], off_rpart, off_resid, off_diag, off_tab, off_desc, off_desc32, off_cbase,
-        off_sbase, total;
+        off_sbase, off_fld, total;
+    size_t fld_n = 0;               // doubles of the largest instance's flow diagnostics
     bool have_resid = false;
 
     double* F(int i) { return (double*)(ws + off_F[i]); }
@@ -50,6 +51,7 @@ struct vlb_channel {
     double* rpart() { return (double*)(ws + off_rpart); }
     double* resid() { return (double*)(ws + off_resid); }
     double* diag() { return (double*)(ws + off_diag); }
+    double* fld() { return (double*)(ws + off_fld); }
     double* dtab() { return (double*)(ws + off_tab); }
     ChanDesc* ddesc() { return (ChanDesc*)(ws + off_desc); }
     const int* gilist(const Group& g) { return (const int*)(ws + g.off_ilist); }
@@ -269,6 +271,18 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         }
         D.tal = put(al); D.tar = put(ar); D.tglxx = put(glxx); D.tglxl = put(glxl);
         D.txc = put(xc); D.txa = put(xa); D.tdlam = put(dlam); D.tdchi = put(dchi); D.tvol = put(vol);
+        {   // flow diagnostics: phi, phi', xi at the cell centres, lambda faces and centres
+            std::vector<double> geo((size_t)3 * NX + 2 * NL + 1);
+            for (int p = 0; p < NX; ++p) {
+                const long double xcen = (xf[p] + xf[p + 1]) / 2;
+                geo[p] = (double)w.phi(xcen);
+                geo[NX + p] = (double)w.dphi(xcen);
+                geo[2 * NX + p] = (double)xcen;
+            }
+            for (int s = 0; s <= NL; ++s) geo[3 * NX + s] = (double)lf[s];
+            for (int s = 0; s < NL; ++s) geo[3 * NX + NL + 1 + s] = (double)((lf[s] + lf[s + 1]) / 2);
+            D.tgeo = put(geo);
+        }
         D.ipf_in = (double)(1 / (1 + w.phi(xf[0])));
         D.ipf_out = (double)(1 / (1 + w.phi(xf[NX])));
         if (d.ends == 1) {
@@ -347,6 +361,7 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
             E.strip = D.strip;
         }
         c->cbase.push_back(cells);
+        c->fld_n = std::max(c->fld_n, (size_t)4 * NX * NL + (size_t)NX * (NL + 1) + 2 * (size_t)NX);
         cells += (long long)NX * NL;
         offF += (size_t)2 * NX * NL * NV;
         offC += (size_t)NX * NL;
@@ -371,6 +386,7 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
     c->off_rpart = off; off = al256(off + c->ncells * 4 * sizeof(double));
     c->off_resid = off; off = al256(off + B * sizeof(double));
     c->off_diag = off; off = al256(off + c->ncells * 5 * sizeof(double));
+    c->off_fld = off; off = al256(off + c->fld_n * sizeof(double));
     c->off_tab = off; off = al256(off + c->tab.size() * sizeof(double));
     c->off_desc = off; off = al256(off + B * sizeof(ChanDesc));
     for (auto& g : c->groups) {
@@ -614,6 +630,27 @@ vlb_status vlb_channel_moments(vlb_channel* c, int inst, double* n, double* u1, 
     for (int q = 0; q < 5; ++q)
         if (outs[q])
             for (size_t x = 0; x < nc; ++x) outs[q][x] = h[x * 5 + q];
+    return VLB_OK;
+}
+
+vlb_status vlb_channel_flow_fields(vlb_channel* c, int inst, double* ux, double* uy, double* P, double* psi,
+                                   double* omega, double* Pw) {
+    if (!c || inst < 0 || inst >= c->B) return set_error(VLB_EINVAL, "bad instance");
+    vlb_status s = channel_precision(c, false);
+    if (s != VLB_OK) return s;
+    VLB_HIP_TRY(launch_channel_diag(c->cbase.back(), c->threads, c->stream, c->ddesc(), c->dcbase(), c->B, c->dtab(),
+                                    c->F(0), c->diag()));
+    const ChanDesc& D = c->desc[inst];
+    VLB_HIP_TRY(launch_channel_fields(D.NX, c->stream, c->ddesc() + inst, c->dtab(), c->diag(), c->fld()));
+    const size_t nc = (size_t)D.NX * D.NL;
+    const size_t len[6] = {nc, nc, nc, (size_t)D.NX * (D.NL + 1), nc, 2 * (size_t)D.NX};
+    const size_t at[6] = {0, nc, 2 * nc, 4 * nc, 3 * nc, 4 * nc + (size_t)D.NX * (D.NL + 1)};
+    double* outs[6] = {ux, uy, P, psi, omega, Pw};
+    for (int q = 0; q < 6; ++q)
+        if (outs[q])
+            VLB_HIP_TRY(hipMemcpyAsync(outs[q], c->fld() + at[q], len[q] * sizeof(double), hipMemcpyDeviceToHost,
+                                       c->stream));
+    VLB_HIP_TRY(hipStreamSynchronize(c->stream));
     return VLB_OK;
 }
 

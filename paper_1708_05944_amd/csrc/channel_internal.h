@@ -25,9 +25,11 @@ struct ChanDesc {
     int tWm;                      // [NV] W_k = w_i w_j (FP32 scaling and moment weights)
     int half;                     // 1: lambda in [0, 1], specular centreline at lambda = 0
     int ends;                     // 0: reservoir ends; 1: flow-rate ends
-    int tQrow, tden, tfrow, pad3; // flow-rate ends: prescribed row flow [2][NL] (inlet, outlet),
+    int tQrow, tden, tfrow;       // flow-rate ends: prescribed row flow [2][NL] (inlet, outlet),
                                   // sum over entering k of p^y f_eq(1, u_s) [2][NL], the unit-density
                                   // Maxwellians of the rows [2][NL][2][NV] (end, row, f' / f'')
+    int tgeo;                     // flow diagnostics: phi, phi' and xi at the cell centres [3][NX],
+                                  // lambda faces [NL + 1] and centres [NL]
     double ipf_in, ipf_out;       // 1 / (1 + phi) at the inlet and outlet faces
 };
 
@@ -62,5 +64,9 @@ hipError_t launch_channel_reduce(int ninst, hipStream_t st, const ChanDesc* inst
                                  const double* rpart, double* resid);
 hipError_t launch_channel_diag(long long ncells_total, int threads, hipStream_t st, const ChanDesc* insts,
                                const long long* cbase, int B, const double* tab, const double* F, double* diag);
+// flow diagnostics of the instance *inst (NX columns) from diag: out = ux, uy, P, omega
+// [NX][NL] each, psi [NX][NL + 1], Pw [2][NX]
+hipError_t launch_channel_fields(int NX, hipStream_t st, const ChanDesc* inst, const double* tab, const double* diag,
+                                 double* out);
 
 }  // namespace vlb

@@ -612,6 +612,90 @@ __global__ __launch_bounds__(kMaxNV) void channel_diag(const ChanDesc* insts, co
     }
 }
 
+// ---------------------------------------------------------------- flow diagnostics
+// Cartesian velocity of cell (p, s) from its triad components (Eq. canalie_u): the triad
+// of the cell is the Cartesian frame turned by the angle whose tangent is a = lambda phi'.
+__device__ __forceinline__ void cart_velocity(const double* dg, const double* lamc, const double* dphi, int NL, int p,
+                                              int s, double& ux, double& uy) {
+    const double* m = dg + ((size_t)p * NL + s) * 5;
+    const double a = lamc[s] * dphi[p], c = 1.0 / sqrt(1.0 + a * a);
+    ux = (m[1] + a * m[2]) * c;
+    uy = (m[2] - a * m[1]) * c;
+}
+
+// Derivative at xt of the quadratic through (x0, x1, x2): weights of the three samples
+// (derivatives of the Lagrange basis polynomials at xt).
+__device__ __forceinline__ void quad_deriv_weights(double xt, double x0, double x1, double x2, double* w) {
+    w[0] = ((xt - x1) + (xt - x2)) / ((x0 - x1) * (x0 - x2));
+    w[1] = ((xt - x0) + (xt - x2)) / ((x1 - x0) * (x1 - x2));
+    w[2] = ((xt - x0) + (xt - x1)) / ((x2 - x0) * (x2 - x1));
+}
+
+// First of the three nodes that differentiate at node i of n (n >= 3): the neighbours
+// inside, one-sided at the ends (Sec. VI.F).
+__device__ __forceinline__ int quad_first(int i, int n) { return i == 0 ? 0 : (i == n - 1 ? n - 3 : i - 1); }
+
+// Flow diagnostics of one instance (Sec. VI.D, VI.F), one thread per xi column p, from
+// the cell moments diag (n, u^lambda, u^xi, T, content): Cartesian velocity, P = n T,
+// vorticity (Eq. canalie_vorti, three-point derivatives on the cell centres), the stream
+// function on the lambda faces (d psi = -n u^y (1 + phi) d lambda, zero at lambda = 0)
+// and the pressure extrapolated linearly to the faces 0 and NL.
+__global__ __launch_bounds__(64) void channel_fields(const ChanDesc* inst, const double* tab_all, const double* diag,
+                                                     double* out) {
+    const ChanDesc& D = *inst;
+    const int NL = D.NL, NX = D.NX;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= NX) return;
+    const double* geo = tab_all + D.offT + D.tgeo;
+    const double *phi = geo, *dphi = geo + NX, *xic = geo + 2 * NX, *lamf = geo + 3 * NX, *lamc = lamf + NL + 1;
+    const double* dg = diag + (size_t)D.offC * 5;
+    const size_t nc = (size_t)NX * NL;
+    double *oux = out, *ouy = out + nc, *oP = out + 2 * nc, *oom = out + 3 * nc, *opsi = out + 4 * nc + (size_t)p * (NL + 1),
+           *oPw = out + 4 * nc + (size_t)NX * (NL + 1);
+    const double opf = 1.0 + phi[p];
+    const int q0 = quad_first(p, NX);
+    double wx[3];
+    quad_deriv_weights(xic[p], xic[q0], xic[q0 + 1], xic[q0 + 2], wx);
+    double cum = 0.0;
+    opsi[0] = 0.0;
+    for (int s = 0; s < NL; ++s) {
+        const size_t ci = (size_t)p * NL + s;
+        const double n = dg[ci * 5], T = dg[ci * 5 + 3];
+        double ux, uy;
+        cart_velocity(dg, lamc, dphi, NL, p, s, ux, uy);
+        oux[ci] = ux;
+        ouy[ci] = uy;
+        oP[ci] = n * T;
+        double dxi = 0.0, dlx = 0.0, dly = 0.0, wl[3];
+        const int r0 = quad_first(s, NL);
+        quad_deriv_weights(lamc[s], lamc[r0], lamc[r0 + 1], lamc[r0 + 2], wl);
+        for (int e = 0; e < 3; ++e) {
+            double vx, vy;
+            cart_velocity(dg, lamc, dphi, NL, q0 + e, s, vx, vy);
+            dxi += wx[e] * vx;
+            cart_velocity(dg, lamc, dphi, NL, p, r0 + e, vx, vy);
+            dlx += wl[e] * vx;
+            dly += wl[e] * vy;
+        }
+        oom[ci] = -dxi + (dly + lamc[s] * dphi[p] * dlx) / opf;
+        cum += n * uy * (opf * (lamf[s + 1] - lamf[s]));
+        opsi[s + 1] = cum;
+    }
+    // lambda = 0 is face NL / 2 of the full width (the middle of cell (NL - 1) / 2 for odd
+    // NL) and face 0 of the half channel
+    const int s0 = D.half ? 0 : NL / 2;
+    const double fr = (D.half || NL % 2 == 0) ? 0.0 : 0.5;
+    const double ref = (1.0 - fr) * opsi[s0] + fr * opsi[s0 + 1];
+    for (int s = 0; s <= NL; ++s) opsi[s] = ref - opsi[s];
+    for (int side = 0; side < 2; ++side) {
+        const int e = side ? NL : 0, i1 = side ? NL - 1 : 0, i2 = side ? NL - 2 : 1;
+        const size_t c1 = (size_t)p * NL + i1, c2 = (size_t)p * NL + i2;
+        const double P1 = dg[c1 * 5] * dg[c1 * 5 + 3], P2 = dg[c2 * 5] * dg[c2 * 5 + 3];
+        const double lw = lamf[e], l1 = lamc[i1], l2 = lamc[i2];
+        oPw[(size_t)side * NX + p] = ((lw - l2) * P1 - (lw - l1) * P2) / (l1 - l2);
+    }
+}
+
 hipError_t launch_channel_stage(int fp32, int T1, int T2, int bnd, long long nblocks, hipStream_t st,
                                 const ChanArgs& A) {
     if (nblocks == 0) return hipSuccess;
@@ -666,6 +750,12 @@ hipError_t launch_channel_reduce(int ninst, hipStream_t st, const ChanDesc* inst
 hipError_t launch_channel_diag(long long ncells_total, int threads, hipStream_t st, const ChanDesc* insts,
                                const long long* cbase, int B, const double* tab, const double* F, double* diag) {
     hipLaunchKernelGGL(channel_diag, stride_grid(ncells_total, 1), dim3(threads), 0, st, insts, cbase, B, tab, F, diag);
+    return hipGetLastError();
+}
+
+hipError_t launch_channel_fields(int NX, hipStream_t st, const ChanDesc* inst, const double* tab, const double* diag,
+                                 double* out) {
+    hipLaunchKernelGGL(channel_fields, dim3((unsigned)((NX + 63) / 64)), dim3(64), 0, st, inst, tab, diag, out);
     return hipGetLastError();
 }
 

@@ -170,6 +170,7 @@ _SIGS = {
     "vlb_channel_apply_L": [ctypes.c_void_p, _dp, ctypes.c_size_t],
     "vlb_channel_residual": [ctypes.c_void_p, _dp],
     "vlb_channel_moments": [ctypes.c_void_p, ctypes.c_int] + [_dp] * 5,
+    "vlb_channel_flow_fields": [ctypes.c_void_p, ctypes.c_int] + [_dp] * 6,
     "vlb_channel_run_to_steady": [ctypes.c_void_p, ctypes.c_double, ctypes.c_long, ctypes.c_int,
                                   ctypes.POINTER(ctypes.c_long), _dp],
     "vlb_status_string": [ctypes.c_int],
@@ -587,6 +588,19 @@ class Channel:
         outs = [np.empty(shp) for _ in range(5)]
         _check(load_library().vlb_channel_moments(self._h, b, *[_ptr(o) for o in outs]), "vlb_channel_moments")
         return dict(zip(("n", "u1", "u2", "T", "content"), outs))
+
+    def flow_fields(self, b: int) -> dict:
+        """Cartesian velocity ux, uy, pressure P, vorticity omega ([N_xi][N_lambda]), stream
+        function psi ([N_xi][N_lambda + 1]) and wall pressures Pw ([2][N_xi]) of instance b."""
+        i = self.info[b]
+        NX, NL = i["N_xi"], i["N_lambda"]
+        names = ("ux", "uy", "P", "psi", "omega", "Pw")
+        outs = {k: np.empty((NX, NL)) for k in ("ux", "uy", "P", "omega")}
+        outs["psi"] = np.empty((NX, NL + 1))
+        outs["Pw"] = np.empty((2, NX))
+        _check(load_library().vlb_channel_flow_fields(self._h, b, *[_ptr(outs[k]) for k in names]),
+               "vlb_channel_flow_fields")
+        return outs
 
     def run_to_steady(self, tol: float, max_steps: int, check_every: int = 100):
         steps = (ctypes.c_long * self.B)()

@@ -196,3 +196,46 @@ def test_channel_mixed_steady_state_matches_fp64():
         err = np.abs(a - b).max() / max(np.abs(b).max(), 1e-3)
         _say(f"{key}: mixed vs fp64 {err:.2e}")
         assert err <= 1e-5, key
+
+
+def test_channel_flow_fields_match_oracle():
+    """Diagnostics of Sec. VI.D / VI.F (Cartesian velocity, pressure, stream function,
+    vorticity, wall pressures) of every instance of a mixed batch -- odd and even N_lambda,
+    the half channel, the straight channel, the paper's set-up -- computed on the device
+    from seeded perturbed states, against the oracle's; per field, max difference over the
+    oracle's max-norm <= 1e-12."""
+    from paper_1708_05944_amd import Channel
+    picks = [CASES[2], CASES[7], CASES[9], CASES[3]]
+    pairs = [_pair(**dict(cs)) for cs in picks]
+    c = Channel([d for _, d in pairs])
+    states = [_perturbed(o, 11 + i) for i, (o, _) in enumerate(pairs)]
+    c.set_state(np.concatenate([F.ravel() for F in states]))
+    for i, (o, _) in enumerate(pairs):
+        _say(f"flow fields of instance {i}: {picks[i]}")
+        got = c.flow_fields(i)
+        want = o.flow_fields(states[i])
+        for k, w in want.items():
+            err = np.abs(got[k] - w).max() / np.abs(w).max()
+            _say(f"  {k}: rel err {err:.2e}")
+            assert got[k].shape == w.shape and err <= TOL, (k, err)
+    c.close()
+
+
+def test_channel_flow_fields_of_mixed_batch():
+    """A mixed-precision batch moves its FP32 state to FP64 and reports the fields of
+    that state.  Starting from rest, the cross-stream velocity is still far below the
+    streamwise one, so both velocity components are measured on the speed scale."""
+    from paper_1708_05944_amd import VLB_MIXED, Channel
+    o, d = _pair(**dict(CASES[9]))
+    c = Channel([d], precision=VLB_MIXED)
+    c.step(20)
+    F = c.get_instance_state(0)
+    got = c.flow_fields(0)
+    want = o.flow_fields(F)
+    speed = max(np.abs(want["ux"]).max(), np.abs(want["uy"]).max())
+    for k, w in want.items():
+        err = np.abs(got[k] - w).max() / (speed if k in ("ux", "uy") else np.abs(w).max())
+        _say(f"  {k}: rel err {err:.2e}")
+        assert err <= TOL, (k, err)
+    assert np.abs(want["psi"]).max() > 0                 # the flow-rate ends drive a flow
+    c.close()
