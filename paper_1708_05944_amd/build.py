@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvlb.so")
-SOURCES = ["velocity_set.cpp", "couette_kernels.hip", "api.cpp", "mlp_kernels.hip", "mlp_api.cpp",
+SOURCES = ["velocity_set.cpp", "couette_kernels.hip", "couette_wide.hip", "api.cpp", "mlp_kernels.hip", "mlp_api.cpp",
            "channel_kernels.hip", "channel_api.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -20,6 +20,7 @@
 
 namespace vlb {
 hipError_t launch_stage(int fp32, int nblocks, hipStream_t st, const StageArgs& A);
+hipError_t launch_wide_stage(int NR, int Q1, int Q2, hipStream_t st, const WideArgs& A);
 size_t stage_lds(int kmax, int elem);
 hipError_t launch_moments(int fp32, int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
                           const double* tab, const void* F, double* msum);
@@ -82,6 +83,8 @@ struct InstHost {
     AxisTables a1, a2;
     std::vector<double> Rf, dchi, Gam;
     int NV;
+    bool wide = false;   // velocity set beyond the one-block stage kernel: the four-launch stage
+    size_t wY = 0, wEq = 0, wNw = 0, wPart = 0;   // its scratch blocks (doubles into the wide region)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -112,7 +115,8 @@ struct vlb_batch {
     size_t state_n = 0, ncells = 0;
     // workspace layout (byte offsets)
     size_t off_F[3], off_F32[3], off_M[3], off_rpart, off_resid, off_mass, off_tab, off_desc, off_desc32, off_work,
-        off_diag, off_mass0, off_blocks, off_prof, off_wpar, off_sfeat, off_sy, total_bytes;
+        off_diag, off_mass0, off_blocks, off_prof, off_wpar, off_sfeat, off_sy, off_wide, total_bytes;
+    size_t wide_n = 0;                  // doubles of the large-velocity-set scratch region
     std::vector<char> active;          // instances the stage kernels advance (run_to_steady retires converged ones)
     int precision = VLB_FP64;
     bool cur32 = false;                 // the current state lives in the FP32 buffers
@@ -146,6 +150,7 @@ struct vlb_batch {
     float* sfeat() { return (float*)(ws + off_sfeat); }
     float* sy() { return (float*)(ws + off_sy); }
     double* diag() { return (double*)(ws + off_diag); }
+    double* wide() { return (double*)(ws + off_wide); }
 };
 
 namespace {
@@ -314,6 +319,7 @@ vlb_status layout_and_alloc(vlb_batch* b, bool alloc) {
     b->off_wpar = off; off = align256(off + b->B * 2 * sizeof(double));
     b->off_sfeat = off; off = align256(off + b->ncells * 4 * sizeof(float));
     b->off_sy = off; off = align256(off + b->ncells * 4 * sizeof(float));
+    b->off_wide = off; off = align256(off + b->wide_n * sizeof(double));
     b->total_bytes = off;
     if (!alloc) return VLB_OK;
     void* p = nullptr;
@@ -395,7 +401,7 @@ vlb_status run_stage(vlb_batch* b, int stage, bool last, bool l_only) {
             }
             HIP_TRY(hipEventRecord(t.start, b->stream));
         }
-        HIP_TRY(launch_stage(f32 ? 1 : 0, g.nblocks, b->stream, G));
+        if (g.nblocks > 0) HIP_TRY(launch_stage(f32 ? 1 : 0, g.nblocks, b->stream, G));
         if (b->timing) {
             HIP_TRY(hipEventRecord(t.stop, b->stream));
             t.group = (int)gi;
@@ -403,6 +409,29 @@ vlb_status run_stage(vlb_batch* b, int stage, bool last, bool l_only) {
             t.bytes = values * g.pops * elem;
             b->timed.push_back(t);
         }
+    }
+    // instances with large velocity sets (FP64 only): four launches each
+    for (int i = 0; i < b->B; ++i) {
+        const InstHost& h = b->inst[i];
+        if (!h.wide || (!b->active.empty() && !b->active[i])) continue;
+        WideArgs W;
+        W.inst = b->ddesc() + i;
+        W.tab = b->dtab();
+        W.Fin = static_cast<const double*>(A.Fin);
+        W.Fn = static_cast<const double*>(A.Fn);
+        W.Fout = static_cast<double*>(A.Fout);
+        W.C = nullptr;
+        W.msum_in = A.msum_in;
+        W.msum_out = A.msum_out;
+        W.rpart = A.rpart;
+        W.Y = b->wide() + h.wY;
+        W.eq = b->wide() + h.wEq;
+        W.nw = b->wide() + h.wNw;
+        W.part = b->wide() + h.wPart;
+        W.ca = A.ca; W.cb = A.cb; W.cc = A.cc;
+        W.l_only = A.l_only;
+        W.nchunk = wide_chunks(h.NV);
+        HIP_TRY(launch_wide_stage(h.d.N_R, h.a1.nodes, h.a2.nodes, b->stream, W));
     }
     return VLB_OK;
 }
@@ -444,7 +473,7 @@ vlb_status capture_steps(vlb_batch* b, hipGraphExec_t* out) {
 void build_blocks(vlb_batch* b, int tile) {
     b->blocks.clear();
     for (int i = 0; i < b->B; ++i) {
-        if (!b->active.empty() && !b->active[i]) continue;
+        if ((!b->active.empty() && !b->active[i]) || b->inst[i].wide) continue;
         const InstDesc& D = b->desc[i];
         const int nruns = (D.NR + tile - 1) / tile;
         const int per = (D.NR + nruns - 1) / nruns;
@@ -575,9 +604,15 @@ vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_de
             (ax == 0 ? h.a1 : h.a2) = it->second;
         }
         h.NV = h.a1.nodes * h.a2.nodes;
-        if (h.NV > kMaxNV || h.a1.nodes + h.a2.nodes > kWave) {
+        // the one-block stage kernel holds a cell's velocities in one block and both kernel
+        // tables in LDS; larger sets take the four-launch stage (FP64)
+        h.wide = h.NV > kMaxNV || h.a1.nodes + h.a2.nodes > kWave ||
+                 2 * row_slot_any(h.a1.nodes, h.a2.nodes) > kRowElems ||
+                 stage_lds(pad4(std::max(ktab_elems(h.a1.nodes, h.a2.nodes, 4), ktab_elems(h.a1.nodes, h.a2.nodes, 8))),
+                           sizeof(double)) > 160 * 1024;
+        if (h.wide && precision == VLB_MIXED) {
             delete b;
-            return fail(VLB_EINVAL, "instance %d: %d velocities / %d+%d nodes exceed the kernel limits", i, h.NV,
+            return fail(VLB_EINVAL, "instance %d: %d velocities (%d + %d nodes) run in FP64 only", i, h.NV,
                         h.a1.nodes, h.a2.nodes);
         }
         h.Rf = faces(d);
@@ -699,11 +734,15 @@ vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_de
             }
             while (made % kWavesPerBlock) { b->work.push_back({i, dist, 0, 0}); ++made; }
         }
-        g.kmax = std::max({g.kmax, ktab_elems(D.Q1, D.Q2, 4), ktab_elems(D.Q1, D.Q2, 8)});
-        if (2 * row_slot_any(D.Q1, D.Q2) > kRowElems) {
-            delete b;
-            return fail(VLB_EINVAL, "instance %d: velocity set too large for the stage kernel's LDS rows", i);
+        if (b->inst[i].wide) {   // scratch of the four-launch stage
+            InstHost& h = b->inst[i];
+            h.wY = b->wide_n; b->wide_n += (size_t)2 * D.NR * D.NV;
+            h.wEq = b->wide_n; b->wide_n += (size_t)D.NR * kEqStride;
+            h.wNw = b->wide_n; b->wide_n += (size_t)pad4(2 * wide_chunks(D.NV));
+            h.wPart = b->wide_n; b->wide_n += wide_part_doubles(D.NR, D.NV);
+            continue;
         }
+        g.kmax = std::max({g.kmax, ktab_elems(D.Q1, D.Q2, 4), ktab_elems(D.Q1, D.Q2, 8)});
         g.pops += 2.0 * D.NR * D.NV;
     }
     g.kmax = pad4(g.kmax);

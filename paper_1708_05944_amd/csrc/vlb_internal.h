@@ -7,7 +7,7 @@
 
 namespace vlb {
 
-constexpr int kMaxQ = 64;      // quadrature order per axis (nodes <= 128)
+constexpr int kMaxQ = 200;     // quadrature order per axis (nodes <= 400)
 constexpr int kMaxN = 4;       // equilibrium expansion order (Eq. norder_limit: N < Q)
 constexpr int kWave = 64;      // CDNA wavefront width
 constexpr int kWavesPerBlock = 4;   // blocks of the auxiliary (per-wavefront work) kernels
@@ -102,5 +102,30 @@ struct StageArgs {
     int kmax;                // kernel-table elements reserved in LDS
     const BlockWork* blocks; // stage-kernel block list
 };
+
+// Arguments of the large-velocity-set stage (one instance per launch sequence): the
+// same stage as StageArgs (FP64 only), plus the instance's scratch blocks: Y [2][NR][NV]
+// (K1 F), eq [NR][kEqStride], nw [nchunk][2] (wall-flux partial sums), part
+// [2][NR][nchunk][8].
+struct WideArgs {
+    const InstDesc* inst;    // this instance's descriptor (device)
+    const double* tab;
+    const double* Fin;
+    const double* Fn;
+    double* Fout;
+    const double* C;         // constant forcing added to L (nullable)
+    const double* msum_in;
+    double* msum_out;
+    double* rpart;           // nullable
+    double* Y;
+    double* eq;
+    double* nw;              // [nchunk][2] partial wall fluxes (inner, outer)
+    double* part;
+    double ca, cb, cc;
+    int l_only;
+    int nchunk;              // update blocks per (distribution, cell)
+};
+int wide_chunks(int NV);
+size_t wide_part_doubles(int NR, int NV);
 
 }  // namespace vlb

@@ -33,7 +33,7 @@ def test_axis_tables_match_oracle(kind, Q):
     assert np.abs(Kt - ax.Kt).max() <= 1e-14 * max(1e-300, np.abs(ax.Kt).max())
 
 
-@pytest.mark.parametrize("axis", [(2, 4, 2), (0, 0, 0), (1, 4, 4), (0, 65, 2), (1, 8, 5)])
+@pytest.mark.parametrize("axis", [(2, 4, 2), (0, 0, 0), (1, 4, 4), (0, 201, 2), (1, 8, 5)])
 def test_axis_tables_reject_invalid(axis):
     with pytest.raises(VlbError) as e:
         axis_tables(*axis)
@@ -77,3 +77,63 @@ def test_channel_create_rejects_invalid_descriptors(kw, needle):
 def test_channel_create_rejects_unstable_dt():
     st, msg = _channel_create_status(N_lambda=8, N_xi=8, dt=10.0)
     assert st == -7 and "stability limit" in msg, (st, msg)
+
+
+def test_large_half_range_axis_matches_oracle():
+    """HH(0;30): 60 nodes, past the one-block stage kernel, against the oracle's tables."""
+    p, w, K, Kt = axis_tables(1, 30, 0)
+    ax = q.axis(1, 30, 0)
+    assert np.abs(p - ax.p).max() <= 1e-13 * np.abs(ax.p).max()
+    assert np.abs(w / ax.w - 1).max() <= 1e-11
+    assert np.abs(K - ax.K).max() <= 1e-12 * np.abs(ax.K).max()
+    assert np.abs(Kt - ax.Kt).max() <= 1e-12 * np.abs(ax.Kt).max()
+
+
+def test_half_range_rule_of_order_200_is_gaussian():
+    """HH(4;200) (the ballistic velocity set of Sec. V.E): the positive half integrates
+    x^r exp(-x^2/2)/sqrt(2 pi) over [0, inf) exactly for r < 2Q -- checked against the
+    closed-form half moments 2^((r-1)/2) Gamma((r+1)/2)/sqrt(2 pi)."""
+    import mpmath as mp
+    Q = 200
+    p, w, _, _ = axis_tables(1, Q, 4)
+    assert np.all(p[:Q] > 0) and np.allclose(p[Q:], -p[:Q], rtol=0, atol=0)
+    with mp.workdps(40):
+        for r in list(range(0, 12)) + list(range(12, 2 * Q, 13)) + [2 * Q - 1]:
+            exact = mp.power(2, mp.mpf(r - 1) / 2) * mp.gamma(mp.mpf(r + 1) / 2) / mp.sqrt(2 * mp.pi)
+            approx = mp.fsum(mp.mpf(w[k]) * mp.mpf(p[k]) ** r for k in range(Q))
+            assert abs(approx / exact - 1) < 1e-13, r
+
+
+def _couette_create(descs, precision):
+    """vlb_batch_create_couette with deferred allocation: validation and host set-up
+    only, no device call."""
+    from paper_1708_05944_amd.vlb import _CouetteDesc
+    arr = (_CouetteDesc * len(descs))(*[d._c() for d in descs])
+    h = ctypes.c_void_p()
+    lib = load_library()
+    st = lib.vlb_batch_create_couette(ctypes.byref(h), len(descs), arr, precision, None, 1)
+    return st, lib.vlb_last_error().decode(), h
+
+
+def test_large_velocity_sets_are_fp64_only():
+    """Sets past the one-block stage kernel (here HH(4;36) x HH(4;10), 1440 velocities)
+    are accepted in FP64, with their scratch in the workspace, and rejected for the mixed
+    FP32 form."""
+    from paper_1708_05944_amd import CouetteDesc
+    lib = load_library()
+    small = CouetteDesc(N_R=8, ax1=(1, 4, 2), ax2=(0, 4, 2))
+    wide = CouetteDesc(N_R=8, ax1=(1, 36, 4), ax2=(1, 10, 4))
+    st, msg, h = _couette_create([small], 0)
+    assert st == 0, msg
+    n_small = ctypes.c_size_t()
+    assert lib.vlb_batch_workspace_bytes(h, ctypes.byref(n_small)) == 0
+    lib.vlb_batch_destroy(h)
+    st, msg, h = _couette_create([small, wide], 0)
+    assert st == 0, msg
+    n_both = ctypes.c_size_t()
+    assert lib.vlb_batch_workspace_bytes(h, ctypes.byref(n_both)) == 0
+    # at least the two state sets, the product block Y (2 N_R NV) of the wide instance
+    assert n_both.value - n_small.value >= (3 + 1) * 2 * 8 * 1440 * 8
+    lib.vlb_batch_destroy(h)
+    st, msg, _ = _couette_create([small, wide], 1)
+    assert st == -1 and "FP64 only" in msg, (st, msg)
