@@ -139,6 +139,7 @@ def main():
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the learned warm-start leg (training solves, training, held-out runs)")
     ap.add_argument("--no-channel", action="store_true", help="skip the expanding-channel leg")
+    ap.add_argument("--no-ballistic", action="store_true", help="skip the ballistic (8000-velocity) leg")
     ap.add_argument("--warm-train", type=int, default=128, help="training instances of the warm-start leg")
     ap.add_argument("--warm-heldout", type=int, default=32, help="held-out instances of the warm-start leg")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
@@ -250,6 +251,37 @@ def main():
                                "weight-scaled populations with FP32 MFMA contractions and FP64 sums",
                    **mixed_ch, "dtype": "f32", "fp64": fp64_ch}
 
+    ballistic = None
+    if not args.no_ballistic:
+        # ballistic regime of the free-molecular comparison: one instance, 16 stretched
+        # cells, HH(4;200) x HH(4;10) = 8000 velocities, FP64 on the large-velocity-set
+        # stage (K1 F product on the matrix cores, then the per-population update)
+        from paper_1708_05944_amd import Batch, CouetteDesc
+        bd = CouetteDesc(R_in=1.0, R_out=2.0, N_R=16, ax1=(1, 200, 4), ax2=(1, 10, 4), Kn=1e8, u_in=1.0, A=0.95,
+                         delta=0.75)
+        bb = Batch([bd])
+        bb.step(12)
+        torch.cuda.synchronize()
+        nst = max(100, 10 * args.steps)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        bb.step(nst)
+        e1.record()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        stage_ms = e0.elapsed_time(e1) / (3 * nst)
+        n1, n2, NR = 400, 20, 16
+        prod_flops = 2.0 * (2 * NR) * n1 * n1 * n2          # K1 F for both distributions, per stage
+        ballistic = {"workload": "ballistic circular Couette (Kn 1e8), R 1 -> 2, wall speed 1, 16 cells stretched "
+                                 "A 0.95 / delta 0.75, HH(4;200) x HH(4;10) = 8000 velocities, FP64",
+                     "value": NR * n1 * n2 * nst / el, "unit": "site-velocity updates/s",
+                     "ms_per_step": el / nst * 1e3, "steps": nst, "dt": bb.info[0]["dt"],
+                     "stage_ms": stage_ms,
+                     "product_TFLOPs_over_stage": prod_flops / (stage_ms * 1e-3) / 1e12,
+                     "product_flops_per_stage": prod_flops}
+        bb.close()
+
     warm = None
     if not args.no_warm:
         # learned warm start: surrogate trained on the solver's own steady states (sweep
@@ -300,6 +332,7 @@ def main():
         "time_to_steady_state_single": tts,
         "time_to_steady_state_warm_start": warm,
         "channel": channel,
+        "ballistic": ballistic,
     }
     if args.copy_ref_mib:
         n = args.copy_ref_mib << 20

@@ -5,18 +5,20 @@
 // one-block-per-run stage kernel (Sec. III.A Eq. rk3; Sec. V.A Eq. boltz_couette_kom;
 // walls of Sec. III.F; WENO-5 of Sec. III.C; equilibrium of Sec. IV.D), in three launches
 // per instance, because one cell's velocities no longer fit one block:
-//   wide_force_prep  the tile blocks form Y = K1 F for every (distribution, cell): the
-//                p^R derivative kernel of Sec. IV.C as a batched FP64 MFMA product
-//                (v_mfma_f64_16x16x4f64; a block per 16 x 16 output tile, its four
-//                wavefronts splitting the contraction and adding their partial tiles in
-//                wavefront order; ragged tiles zero-padded).  The prep blocks after them
+//   wide_force_prep  the product blocks form Y = K1 F for every (distribution, cell): the
+//                p^R derivative kernel of Sec. IV.C as one FP64 MFMA product over the
+//                flattened (distribution, cell, p^phi node) columns (v_mfma_f64_16x16x4f64;
+//                a block per 16 rows x 64 columns, each K1 fragment feeding four tiles,
+//                the four wavefronts splitting the contraction and adding their partial
+//                tiles in wavefront order; ragged tiles zero-padded).  The prep blocks after them
 //                take, per cell (first prep block), n, T, 1/tau, the equilibrium
 //                coefficients and the geometry from the moment sums of the stage input,
 //                and per 256 velocities the FP64 partial sums of the wall-bound WENO flux
 //                through both walls (Eq. nw), which every update block adds in chunk
 //                order into n_w;
 //   wide_update  one thread per population: two WENO faces, the flux difference, the
-//                force Gamma [(p^phi)^2 (K1 F) - p^R (F Kt2^T)], BGK, the RK combine, the
+//                force Gamma [(p^phi)^2 Y - p^R F Kt2^T] (the p^phi contraction from the
+//                block's rows of F staged in LDS), BGK, the RK combine, the
 //                store, and per-block FP64 partial sums of the output's moments and
 //                residual in a fixed order;
 //   wide_finish  per (distribution, cell): the partial sums added in chunk order into
@@ -35,6 +37,25 @@ namespace {
 
 constexpr int kWideThreads = 256;   // threads of the prep, update and finish blocks
 constexpr int kWidePart = 8;        // partial sums per update block: m0..m3, rd, rn, pad
+
+// Block-wide sums of NQ values in a fixed order: DPP wavefront sums, then the wavefronts
+// in index order; sh holds NQ x (waves per block) doubles.
+template <int NQ>
+__device__ void block_sums(double* v, double* sh) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = wave_sum(v[q]);
+    __syncthreads();
+    if (lane == 0)
+        for (int q = 0; q < NQ; ++q) sh[q * nw + wave] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += sh[q * nw + w];
+        v[q] = s;
+    }
+}
 
 // Block-wide sum in a fixed order: DPP wavefront sums, then the wavefronts in index order.
 __device__ double block_sum(double v, double* sh) {
@@ -97,62 +118,96 @@ __device__ void wide_prep(const WideArgs& A, int chunk, double* sh) {
     }
 }
 
-__device__ void wide_force(const WideArgs& A, long long tile, double (*part)[4][kWave]) {
+// Y = K1 F as one product over the flattened columns c = b n2 + j of all (distribution,
+// cell) blocks b: C[i][c] = sum_k K1[i][k] F_b[k][j].  A block owns rows 16 I0 .. 16 I0 + 15
+// and kWideCols consecutive columns (kWideCols / 16 MFMA tiles sharing each K1 fragment);
+// its four wavefronts split the contraction and add their partial tiles in wavefront order.
+constexpr int kWideCols = 64;
+__device__ void wide_force(const WideArgs& A, long long tile, double (*part)[kWideCols / 16][4][kWave]) {
+    constexpr int NT = kWideCols / 16;
     const InstDesc& I = *A.inst;
     const double* tab = A.tab + I.offT;
-    const int n1 = I.Q1, n2 = I.Q2;
-    const int TI = (n1 + 15) / 16, TJ = (n2 + 15) / 16;
+    const int n1 = I.Q1, n2 = I.Q2, NV = I.NV;
+    const int TI = (n1 + 15) / 16;
+    const long long NC = (long long)2 * I.NR * n2;   // flattened columns
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int J = (int)(tile % TJ), I0 = (int)((tile / TJ) % TI), b = (int)(tile / ((long long)TJ * TI));
+    const int I0 = (int)(tile % TI);
+    const long long c0 = tile / TI * kWideCols;
     // wavefront w contracts over k in [w kq, (w + 1) kq), kq a multiple of 4
     const int kq = (n1 + 15) / 16 * 4, kbeg = wave * kq, kend = min(n1, kbeg + kq);
     const int g = lane >> 4, n = lane & 15;
     const double* K1 = tab + I.tK1;
-    const double* Fb = A.Fin + I.offF + (size_t)b * I.NV;   // (distribution, cell) b: n1 x n2 row-major
-    const int row = 16 * I0 + n, col = 16 * J + n;
+    const int row = 16 * I0 + n;
+    // this lane's column of each tile: (distribution, cell) block and p^phi node
+    const double* Fc[NT];
+    bool cin[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const long long c = c0 + 16 * t + n;
+        cin[t] = c < NC;
+        const long long cc = cin[t] ? c : 0;
+        Fc[t] = A.Fin + I.offF + (size_t)(cc / n2) * NV + (size_t)(cc % n2);
+    }
     typedef double v4d __attribute__((ext_vector_type(4)));
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-    // kU steps of the contraction per round: all 2 kU operand loads are issued before the
-    // MFMA chain that consumes them, so their L2 latencies overlap
-    constexpr int kU = 8;
+    v4d acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    // kU contraction steps per round: their 5 kU operand loads are issued before the
+    // MFMAs that consume them, so the L2 latencies overlap
+    constexpr int kU = 4;
     for (int k0 = kbeg; k0 < kend; k0 += 4 * kU) {
-        double a[kU], bv[kU];
+        double a[kU], bv[kU][NT];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const int kc = k0 + 4 * u + g;
             const bool in = kc < kend;
             a[u] = (in && row < n1) ? K1[(size_t)row * n1 + kc] : 0.0;
-            bv[u] = (in && col < n2) ? Fb[(size_t)kc * n2 + col] : 0.0;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) bv[u][t] = (in && cin[t]) ? Fc[t][(size_t)kc * n2] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < kU; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bv[u], acc, 0, 0, 0);
+        for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bv[u][t], acc[t], 0, 0, 0);
     }
     if (wave > 0)
-        for (int r = 0; r < 4; ++r) part[wave - 1][r][lane] = acc[r];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part[wave - 1][t][r][lane] = acc[t][r];
     __syncthreads();
     if (wave != 0) return;
-    // register r of lane group g holds output row g + 4 r of the tile, column n; the
-    // partial tiles are added in wavefront order
-    double* Yb = A.Y + (size_t)b * I.NV;
+    // register r of lane group g holds output row g + 4 r of a tile, the lane's column
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        double v = acc[r];
-        for (int w = 0; w < kWideThreads / kWave - 1; ++w) v += part[w][r][lane];
-        const int i = 16 * I0 + g + 4 * r;
-        if (i < n1 && col < n2) Yb[(size_t)i * n2 + col] = v;
+    for (int t = 0; t < NT; ++t) {
+        const long long c = c0 + 16 * t + n;
+        if (!cin[t]) continue;
+        double* Yc = A.Y + (size_t)(c / n2) * NV + (size_t)(c % n2);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double v = acc[t][r];
+            for (int w = 0; w < kWideThreads / kWave - 1; ++w) v += part[w][t][r][lane];
+            const int i = 16 * I0 + g + 4 * r;
+            if (i < n1) Yc[(size_t)i * n2] = v;
+        }
     }
 }
 
-// grid: 2 NR TI TJ product tiles, then nchunk prep blocks
+// grid: TI x ceil(2 NR n2 / kWideCols) product blocks, then nchunk prep blocks
 __global__ __launch_bounds__(kWideThreads) void wide_force_prep(WideArgs A, long long tiles) {
-    __shared__ double part[kWideThreads / kWave - 1][4][kWave];
+    __shared__ double part[kWideThreads / kWave - 1][kWideCols / 16][4][kWave];
     __shared__ double sh[kWideThreads / kWave];
     if ((long long)blockIdx.x < tiles) wide_force(A, blockIdx.x, part);
     else wide_prep(A, (int)(blockIdx.x - tiles), sh);
 }
 
+// LDS rows of F an update block stages: its 256 velocities plus the rest of the first
+// and last p^R rows they touch (at most 2 (Q2 - 1) more values, Q2 <= 2 kMaxQ)
+constexpr int kWideRows = kWideThreads + 4 * kMaxQ;
+
 __global__ __launch_bounds__(kWideThreads) void wide_update(WideArgs A) {
-    __shared__ double sh[kWideThreads / kWave];
+    __shared__ double sh[6 * (kWideThreads / kWave)];
+    __shared__ double frow[kWideRows];
     const InstDesc& I = *A.inst;
     const double* tab = A.tab + I.offT;
     const int NR = I.NR, NV = I.NV, Q1 = I.Q1, Q2 = I.Q2, N1 = I.N1, N2 = I.N2;
@@ -164,6 +219,11 @@ __global__ __launch_bounds__(kWideThreads) void wide_update(WideArgs A) {
     const double p1 = tab[I.tp1 + vi], p2 = tab[I.tp2 + vj];
     const double* e = A.eq + (size_t)s * kEqStride;
     const double* Fd = A.Fin + I.offF + (size_t)dist * NR * NV;
+    // whole p^R rows [r0, r1] of this cell covering the block's velocities, into LDS
+    const int k_lo = chunk * kWideThreads, k_hi = min(NV, k_lo + kWideThreads) - 1;
+    const int r0 = k_lo / Q2, base = r0 * Q2, nrow = (k_hi / Q2 + 1) * Q2 - base;
+    for (int x = threadIdx.x; x < nrow; x += kWideThreads) frow[x] = Fd[(size_t)s * NV + base + x];
+    __syncthreads();
     // n_w of both walls (Eq. nw): the prep blocks' partial sums added in chunk order
     double si = 0.0, so = 0.0;
     for (int c = 0; c < A.nchunk; ++c) {
@@ -204,7 +264,7 @@ __global__ __launch_bounds__(kWideThreads) void wide_update(WideArgs A) {
         const double adv = p1 * (e[kEqGeo + 1] * fr - e[kEqGeo] * fl);
         // force: K1 F from the product launch, F Kt2^T by a short dot product along p^phi
         const double kf = A.Y[(size_t)ds * NV + kk];
-        const double* Frow = Fd + (size_t)s * NV + (size_t)vi * Q2;
+        const double* Frow = frow + (vi * Q2 - base);
         const double* Kt2 = tab + I.tKt2 + (size_t)vj * Q2;
         double ktf = 0.0;
         for (int jp = 0; jp < Q2; ++jp) ktf += Kt2[jp] * Frow[jp];
@@ -242,15 +302,11 @@ __global__ __launch_bounds__(kWideThreads) void wide_update(WideArgs A) {
             m3 = (p1 * p1 + p2 * p2) * wo;
         }
     }
-    m0 = block_sum(m0, sh);
-    m1 = block_sum(m1, sh);
-    m2 = block_sum(m2, sh);
-    m3 = block_sum(m3, sh);
-    rd = block_sum(rd, sh);
-    rn = block_sum(rn, sh);
+    double v[6] = {m0, m1, m2, m3, rd, rn};
+    block_sums<6>(v, sh);
     if (threadIdx.x == 0) {
         double* pp = A.part + (size_t)blockIdx.x * kWidePart;
-        pp[0] = m0; pp[1] = m1; pp[2] = m2; pp[3] = m3; pp[4] = rd; pp[5] = rn;
+        for (int q = 0; q < 6; ++q) pp[q] = v[q];
     }
 }
 
@@ -277,7 +333,7 @@ size_t wide_part_doubles(int NR, int NV) { return (size_t)2 * NR * wide_chunks(N
 hipError_t launch_wide_stage(int NR, int Q1, int Q2, hipStream_t st, const WideArgs& A) {
     const int NV = Q1 * Q2;
     if (A.nchunk != wide_chunks(NV)) return hipErrorInvalidValue;
-    const long long tiles = (long long)2 * NR * ((Q1 + 15) / 16) * ((Q2 + 15) / 16);
+    const long long tiles = (long long)((Q1 + 15) / 16) * (((long long)2 * NR * Q2 + kWideCols - 1) / kWideCols);
     hipLaunchKernelGGL(wide_force_prep, dim3((unsigned)(tiles + A.nchunk)), dim3(kWideThreads), 0, st, A, tiles);
     hipLaunchKernelGGL(wide_update, dim3((unsigned)(2 * NR * A.nchunk)), dim3(kWideThreads), 0, st, A);
     hipLaunchKernelGGL(wide_finish, dim3((unsigned)(2 * NR)), dim3(kWave), 0, st, A);
