@@ -327,6 +327,11 @@ typedef struct {
     int half;     /* 1: the upper half lambda in [0, 1] with a specular centreline (Sec. VI.C.3) */
     int ends;     /* 0: reservoirs at n_in / n_out; 1: the flow-rate profile of Sec. VI.C.1-2 */
     double Q0;    /* ends = 1: flow rate through half of the cross-section */
+    int cartesian; /* 1: the Cartesian-split form of Sec. VI.G: ax1 = p^x (across), ax2 = p^y
+                    * (along), no force terms, V^lambda = (p^x - lambda a p^y)/(1 + phi) with the
+                    * discrete metric a = (1 + phi)(phi_{p+1/2} - phi_{p-1/2})/dchi, V^xi = (1 + phi) p^y,
+                    * walls by the sign of V^lambda at the wall face (Eq. canalie_coord_nw).  FP64,
+                    * full width and reservoir ends only; up to 1024 velocities. */
 } vlb_channel_desc;
 typedef struct vlb_channel vlb_channel;
 

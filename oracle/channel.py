@@ -239,12 +239,10 @@ class ChannelOracle:
           half channel; the upper wall) by linear extrapolation from the two outermost cells
           (the construction before Eq. canalie_wall_pressure), [2][NX]."""
         m = self.moments(F)
-        n, ul, ux_hat, T = m["n"], m["u1"], m["u2"], m["T"]
+        n, T = m["n"], m["T"]
         lam = np.broadcast_to(self.lam_c[None, :], n.shape)
         a = lam * self.dphi_c[:, None]
-        c = 1.0 / np.sqrt(1.0 + a * a)
-        ux = (ul + a * ux_hat) * c
-        uy = (ux_hat - a * ul) * c
+        ux, uy = self.cartesian_velocity(m)
         P = n * T
         # stream function: d psi = -rho u_y dx across each xi column, dx = (1 + phi) d lambda;
         # the running sum from the lower face, shifted to vanish at lambda = 0 (linear inside
@@ -263,6 +261,13 @@ class ChannelOracle:
             lw, l1, l2 = self.lam_f[e], self.lam_c[i1], self.lam_c[i2]
             Pw[side] = ((lw - l2) * P[:, i1] - (lw - l1) * P[:, i2]) / (l1 - l2)
         return dict(ux=ux, uy=uy, P=P, psi=psi, omega=omega, Pw=Pw)
+
+    def cartesian_velocity(self, m):
+        """(u^x, u^y) of every cell from the triad components (Eq. canalie_u)."""
+        lam = np.broadcast_to(self.lam_c[None, :], m["n"].shape)
+        a = lam * self.dphi_c[:, None]
+        c = 1.0 / np.sqrt(1.0 + a * a)
+        return (m["u1"] + a * m["u2"]) * c, (m["u2"] - a * m["u1"]) * c
 
     def mass(self, F):
         F = np.asarray(F).reshape(2, self.NX, self.NL, self.NV)

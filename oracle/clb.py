@@ -46,6 +46,10 @@ class ClbOracle(ChannelOracle):
         self.px = np.repeat(self.a1.p, self.Q2)
         self.py = np.tile(self.a2.p, self.Q1)
 
+    def cartesian_velocity(self, m):
+        """The moments of the Cartesian-split populations are Cartesian already."""
+        return m["u1"], m["u2"]
+
     def _w(self, a, b, c, d, e):
         return weno5(a, b, c, d, e) if self.weno_eps == 0.0 else weno5_eps(a, b, c, d, e, self.weno_eps)
 

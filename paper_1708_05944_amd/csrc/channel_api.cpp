@@ -31,6 +31,10 @@ struct vlb_channel {
         size_t off_ilist, off_base, off_bbase;
     };
     std::vector<Group> groups;
+    std::vector<int> clb_ilist;           // Cartesian-split instances: one launch, a block per cell
+    std::vector<long long> clb_base{0};
+    size_t off_clb_ilist = 0, off_clb_base = 0;
+    int clb_threads = 64;
     size_t state_n = 0, ncells = 0;
     int threads = 64;
     int precision = VLB_FP64;
@@ -136,6 +140,11 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
             delete c;
             return set_error(VLB_EINVAL, "invalid channel descriptor for instance %d (ax1 must be half range)", i);
         }
+        if (d.cartesian != 0 && (d.cartesian != 1 || d.half || d.ends || precision != VLB_FP64)) {
+            delete c;
+            return set_error(VLB_EINVAL, "instance %d: the Cartesian-split channel runs in FP64 on the full width "
+                             "with reservoir ends", i);
+        }
         const AxisTables* a1 = get_axis(d.ax1);
         const AxisTables* a2 = get_axis(d.ax2);
         if (!a1 || !a2) {
@@ -145,7 +154,7 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         const int n1 = a1->nodes, n2 = a2->nodes, NV = n1 * n2, NL = d.N_lambda, NX = d.N_xi;
         // velocity tiles of 16 x 16: at most two along one axis, not both
         const int T1 = (n1 + 15) / 16, T2 = (n2 + 15) / 16;
-        if (T1 * T2 > 2) {
+        if (d.cartesian ? NV > kMaxNV : T1 * T2 > 2) {
             delete c;
             return set_error(VLB_EINVAL,
                              "instance %d: %d x %d velocities exceed the kernel limits (16-node tiles: 1 x 1, 2 x 1 "
@@ -160,6 +169,7 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         D.weno_eps = d.weno_eps;
         D.half = d.half;
         D.ends = d.ends;
+        D.cartesian = d.cartesian;
         D.offF = (long long)offF;
         D.offC = (long long)offC;
         D.offT = (long long)c->tab.size();
@@ -283,6 +293,30 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
             for (int s = 0; s < NL; ++s) geo[3 * NX + NL + 1 + s] = (double)((lf[s] + lf[s + 1]) / 2);
             D.tgeo = put(geo);
         }
+        double vclb = 0.0;   // Cartesian split: advective rate bound |V^lambda| / dlambda + |V^xi| / dchi
+        if (d.cartesian) {
+            // discrete metric a_p = (1 + phi_p)(phi_{p+1/2} - phi_{p-1/2}) / dchi_p (free-stream
+            // preserving) and phi at the xi faces
+            std::vector<double> clb(2 * (size_t)NX + 1);
+            for (int p = 0; p < NX; ++p) {
+                const long double xcen = (xf[p] + xf[p + 1]) / 2;
+                clb[p] = (double)((1 + w.phi(xcen)) * (w.phi(xf[p + 1]) - w.phi(xf[p])) / (long double)dchi[p]);
+            }
+            for (int f = 0; f <= NX; ++f) clb[NX + f] = (double)w.phi(xf[f]);
+            for (int p = 0; p < NX; ++p) {
+                const double opf = 1.0 + (double)w.phi((xf[p] + xf[p + 1]) / 2);
+                for (int s2 = 0; s2 < NL; ++s2)
+                    for (int ia = 0; ia < n1; ++ia)
+                        for (int jb = 0; jb < n2; ++jb) {
+                            double vl = 0.0;
+                            for (int e = 0; e < 2; ++e)
+                                vl = std::max(vl, std::fabs(a1->p[ia] - (double)lf[s2 + e] * clb[p] * a2->p[jb]) / opf);
+                            const double vx = std::max(1.0 + clb[NX + p], 1.0 + clb[NX + p + 1]) * std::fabs(a2->p[jb]);
+                            vclb = std::max(vclb, vl / dlam[s2] + vx / dchi[p]);
+                        }
+            }
+            D.tclb = put(clb);
+        }
         D.ipf_in = (double)(1 / (1 + w.phi(xf[0])));
         D.ipf_out = (double)(1 / (1 + w.phi(xf[NX])));
         if (d.ends == 1) {
@@ -327,8 +361,9 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         }
         // dt: advection CFL combined with the force limit |lambda dt| <= sqrt(3) of RK3, capped
         // at 2 tau of the rest state (as for the Couette instances)
-        const double rho = fmax1 * force_operator_norm(*a1, *a2) + fmax2 * force_operator_norm(*a2, *a1);
-        const double inv1 = vmax + rho / std::sqrt(3.0);
+        const double rho =
+            d.cartesian ? 0.0 : fmax1 * force_operator_norm(*a1, *a2) + fmax2 * force_operator_norm(*a2, *a1);
+        const double inv1 = d.cartesian ? vclb : vmax + rho / std::sqrt(3.0);
         const double tau0 = d.tau_model == 0 ? d.Kn * 0.62665706865775012 : d.Kn;
         double dt = d.dt;
         if (dt == 0.0) {
@@ -338,7 +373,11 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
             return set_error(VLB_EUNSTABLE, "instance %d: dt=%g exceeds the stability limit %g", i, dt, 1.0 / inv1);
         }
         D.dt = dt;
-        {
+        if (d.cartesian) {
+            c->clb_ilist.push_back(i);
+            c->clb_base.push_back(c->clb_base.back() + (long long)NX * NL);
+            c->clb_threads = std::max(c->clb_threads, (NV + kWave - 1) / kWave * kWave);
+        } else {
             auto it = std::find_if(c->groups.begin(), c->groups.end(),
                                    [&](const vlb_channel::Group& g) { return g.T1 == T1 && g.T2 == T2; });
             if (it == c->groups.end()) {
@@ -368,6 +407,10 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         c->threads = std::max(c->threads, (NV + kWave - 1) / kWave * kWave);
     }
     c->cbase.push_back(cells);
+    if (c->clb_base.back() * c->clb_threads >= (1LL << 32)) {
+        delete c;
+        return set_error(VLB_EINVAL, "batch too large for one Cartesian-split launch (%lld cells)", c->clb_base.back());
+    }
     for (const auto& g : c->groups)   // one dispatch covers fewer than 2^32 work-items
         if (std::max(g.base.back(), g.bbase.back()) * kChanWaves * kWave >= (1LL << 32)) {
             delete c;
@@ -395,6 +438,8 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         g.off_bbase = off; off = al256(off + g.bbase.size() * sizeof(long long));
     }
     c->off_cbase = off; off = al256(off + (B + 1) * sizeof(long long));
+    c->off_clb_ilist = off; off = al256(off + c->clb_ilist.size() * sizeof(int));
+    c->off_clb_base = off; off = al256(off + c->clb_base.size() * sizeof(long long));
     c->total = off;
     void* p = nullptr;
     if (hipMalloc(&p, c->total) != hipSuccess) {
@@ -427,6 +472,12 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->dcbase(), c->cbase.data(), (B + 1) * sizeof(long long), hipMemcpyHostToDevice,
                            c->stream);
+    if (e == hipSuccess && !c->clb_ilist.empty())
+        e = hipMemcpyAsync(c->ws + c->off_clb_ilist, c->clb_ilist.data(), c->clb_ilist.size() * sizeof(int),
+                           hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && !c->clb_ilist.empty())
+        e = hipMemcpyAsync(c->ws + c->off_clb_base, c->clb_base.data(), c->clb_base.size() * sizeof(long long),
+                           hipMemcpyHostToDevice, c->stream);
     // rest state n = 1, u = 0, T = T_w, written on the device
     if (e == hipSuccess)
         e = launch_channel_rest((long long)c->state_n, c->stream, c->ddesc(), c->dsbase(), B, c->dtab(), c->F(0));
@@ -547,6 +598,12 @@ vlb_status channel_stage(vlb_channel* c, int stage, bool last, bool l_only) {
         VLB_HIP_TRY(launch_channel_stage(f32 ? 1 : 0, g.T1, g.T2, 0, g.base.back(), c->stream, A));
         A.base = c->gbbase(g);
         VLB_HIP_TRY(launch_channel_stage(f32 ? 1 : 0, g.T1, g.T2, 1, g.bbase.back(), c->stream, A));
+    }
+    if (!c->clb_ilist.empty()) {   // Cartesian-split instances (FP64 only)
+        A.ilist = (const int*)(c->ws + c->off_clb_ilist);
+        A.B = (int)c->clb_ilist.size();
+        A.base = (const long long*)(c->ws + c->off_clb_base);
+        VLB_HIP_TRY(launch_clb_stage(c->clb_base.back(), c->clb_threads, c->stream, A));
     }
     return VLB_OK;
 }

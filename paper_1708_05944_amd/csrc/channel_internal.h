@@ -28,6 +28,8 @@ struct ChanDesc {
     int tQrow, tden, tfrow;       // flow-rate ends: prescribed row flow [2][NL] (inlet, outlet),
                                   // sum over entering k of p^y f_eq(1, u_s) [2][NL], the unit-density
                                   // Maxwellians of the rows [2][NL][2][NV] (end, row, f' / f'')
+    int cartesian;                // 1: Cartesian-split momentum space (Sec. VI.G), no force terms
+    int tclb;                     // cartesian: discrete metric a_p [NX], phi at the xi faces [NX + 1]
     int tgeo;                     // flow diagnostics: phi, phi' and xi at the cell centres [3][NX],
                                   // lambda faces [NL + 1] and centres [NL]
     double ipf_in, ipf_out;       // 1 / (1 + phi) at the inlet and outlet faces
@@ -64,6 +66,9 @@ hipError_t launch_channel_reduce(int ninst, hipStream_t st, const ChanDesc* inst
                                  const double* rpart, double* resid);
 hipError_t launch_channel_diag(long long ncells_total, int threads, hipStream_t st, const ChanDesc* insts,
                                const long long* cbase, int B, const double* tab, const double* F, double* diag);
+// Cartesian-split stage (FP64): one block of `threads` threads per cell of the listed
+// instances (A.ilist / A.base count cells)
+hipError_t launch_clb_stage(long long ncells, int threads, hipStream_t st, const ChanArgs& A);
 // flow diagnostics of the instance *inst (NX columns) from diag: out = ux, uy, P, omega
 // [NX][NL] each, psi [NX][NL + 1], Pw [2][NX]
 hipError_t launch_channel_fields(int NX, hipStream_t st, const ChanDesc* inst, const double* tab, const double* diag,

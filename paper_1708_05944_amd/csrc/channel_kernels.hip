@@ -618,6 +618,11 @@ __global__ __launch_bounds__(kMaxNV) void channel_diag(const ChanDesc* insts, co
 __device__ __forceinline__ void cart_velocity(const double* dg, const double* lamc, const double* dphi, int NL, int p,
                                               int s, double& ux, double& uy) {
     const double* m = dg + ((size_t)p * NL + s) * 5;
+    if (dphi == nullptr) {   // Cartesian-split instance: the moments are Cartesian already
+        ux = m[1];
+        uy = m[2];
+        return;
+    }
     const double a = lamc[s] * dphi[p], c = 1.0 / sqrt(1.0 + a * a);
     ux = (m[1] + a * m[2]) * c;
     uy = (m[2] - a * m[1]) * c;
@@ -647,7 +652,8 @@ __global__ __launch_bounds__(64) void channel_fields(const ChanDesc* inst, const
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= NX) return;
     const double* geo = tab_all + D.offT + D.tgeo;
-    const double *phi = geo, *dphi = geo + NX, *xic = geo + 2 * NX, *lamf = geo + 3 * NX, *lamc = lamf + NL + 1;
+    const double *phi = geo, *xic = geo + 2 * NX, *lamf = geo + 3 * NX, *lamc = lamf + NL + 1;
+    const double* dphi = D.cartesian ? nullptr : geo + NX;
     const double* dg = diag + (size_t)D.offC * 5;
     const size_t nc = (size_t)NX * NL;
     double *oux = out, *ouy = out + nc, *oP = out + 2 * nc, *oom = out + 3 * nc, *opsi = out + 4 * nc + (size_t)p * (NL + 1),
@@ -677,7 +683,8 @@ __global__ __launch_bounds__(64) void channel_fields(const ChanDesc* inst, const
             dlx += wl[e] * vx;
             dly += wl[e] * vy;
         }
-        oom[ci] = -dxi + (dly + lamc[s] * dphi[p] * dlx) / opf;
+        const double aa = lamc[s] * geo[NX + p];   // lambda phi'
+        oom[ci] = -dxi + (dly + aa * dlx) / opf;
         cum += n * uy * (opf * (lamf[s + 1] - lamf[s]));
         opsi[s + 1] = cum;
     }
@@ -693,6 +700,167 @@ __global__ __launch_bounds__(64) void channel_fields(const ChanDesc* inst, const
         const double P1 = dg[c1 * 5] * dg[c1 * 5 + 3], P2 = dg[c2 * 5] * dg[c2 * 5 + 3];
         const double lw = lamf[e], l1 = lamc[i1], l2 = lamc[i2];
         oPw[(size_t)side * NX + p] = ((lw - l2) * P1 - (lw - l1) * P2) / (l1 - l2);
+    }
+}
+
+// ---------------------------------------------------------------- Cartesian-split stage
+// Cartesian-split channel (Sec. VI.G, Eq. canalie_coord_beq_cons), FP64: the momentum
+// axes are p^x (across, ax1) and p^y (along, ax2); no force terms; the advection
+// velocities V^lambda = (p^x - lambda a_p p^y) / (1 + phi_p) at the lambda faces, with the
+// discrete metric a_p = (1 + phi_p)(phi_{p+1/2} - phi_{p-1/2}) / dchi_p (free-stream
+// preserving), and V^xi = (1 + phi) p^y at the xi faces.  A population is wall-bound or
+// emitted by the sign of V^lambda at the wall face; n_w by Eq. canalie_coord_nw.  One block
+// per cell, one thread per velocity; the block sums its cell's moments itself.
+__global__ __launch_bounds__(kMaxNV) void clb_stage(ChanArgs A) {
+    __shared__ double sh[16 * 5];
+    __shared__ double ec[4 * (kMaxN + 1)];
+    __shared__ double gq[4 * kMaxQ];   // g(p) of the nodes of both axes
+    const long long b = blockIdx.x;
+    const int gi = find_instance(A.base, A.B, b);
+    const ChanDesc& I = A.inst[A.ilist[gi]];
+    const int cell = (int)(b - A.base[gi]);
+    const int NL = I.NL, NX = I.NX, NV = I.NV, Q1 = I.Q1, Q2 = I.Q2, N1 = I.N1, N2 = I.N2;
+    const int p = cell / NL, s = cell - p * NL;
+    const double* tab = A.tab + I.offT;
+    const int k = threadIdx.x;
+    const bool act = k < NV;
+    const int kk = act ? k : 0, vi = kk / Q2, vj = kk - vi * Q2;
+    const double px = tab[I.tp1 + vi], py = tab[I.tp2 + vj];
+    const double* F = static_cast<const double*>(A.Fin) + I.offF;
+    const size_t dsz = (size_t)NX * NL * NV;
+    auto at = [&](int d, int pp, int ss) -> double { return F[d * dsz + ((size_t)pp * NL + ss) * NV + kk]; };
+
+    // moments of the cell (Sec. IV.A) and the relaxation time
+    double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (act) {
+        const double f0 = at(0, p, s);
+        m[0] = f0;
+        m[1] = px * f0;
+        m[2] = py * f0;
+        m[3] = (px * px + py * py) * f0;
+        m[4] = at(1, p, s);
+    }
+    block_sums<5>(m, sh);
+    const double n = m[0], ux = m[1] / n, uy = m[2] / n;
+    const double T = (m[3] + m[4] - n * (ux * ux + uy * uy)) / (3.0 * n);
+    const double itau = 1.0 / tau_of(I.tau_model, I.Kn, n, T);
+    // equilibrium coefficients (Sec. IV.D): thread 2 ax + sg, both sides of both axes
+    if (threadIdx.x < 4) {
+        const int ax = threadIdx.x >> 1, sg = threadIdx.x & 1, N = ax ? N2 : N1;
+        axis_coef_side(ax ? I.kind2 : I.kind1, N, ax ? uy : ux, T, tab + (ax ? I.tC2 : I.tC1),
+                       tab + (ax ? I.tisf2 : I.tisf1), sg, ec + ax * 2 * (kMaxN + 1) + sg * (N + 1));
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < Q1 + Q2; t += blockDim.x) {
+        const bool ax1 = t < Q1;
+        const int node = ax1 ? t : t - Q1, N = ax1 ? N1 : N2;
+        const bool minus = ax1 ? (I.kind1 == 1 && node >= I.Qh1) : (I.kind2 == 1 && node >= I.Qh2);
+        const double* co = ec + (ax1 ? 0 : 2 * (kMaxN + 1)) + (minus ? N + 1 : 0);
+        const double* brow = tab + (ax1 ? I.tB1 : I.tB2) + node * (N + 1);
+        double g = 0.0;
+        for (int l = 0; l <= N; ++l) g += brow[l] * co[l];
+        gq[t] = g;
+    }
+    __syncthreads();
+    const double fe1 = n * gq[vi] * gq[Q1 + vj];
+
+    // geometry of the column
+    const double* geo = tab + I.tgeo;
+    const double inv_opf = 1.0 / (1.0 + geo[p]);
+    const double* lamf = geo + 3 * NX;
+    const double am = tab[I.tclb + p];
+    const double* phif = tab + I.tclb + NX;
+    const double vlo = (px + am * py) * inv_opf, vhi = (px - am * py) * inv_opf;   // V^lambda at lambda = -1, +1
+    const double* fw = tab + I.tfw;
+    const double weps = I.weno_eps;
+    // n_w of the walls this cell's stencil reaches (Eq. canalie_coord_nw; f' only)
+    double nw_lo = 0.0, nw_hi = 0.0;
+    if (s < 3 || s >= NL - 3) {
+        double w[4] = {0.0, 0.0, 0.0, 0.0};
+        if (act) {
+            if (vlo < 0.0) {
+                const double F1 = at(0, p, 0), F2 = at(0, p, 1), F3 = at(0, p, 2);
+                w[0] = vlo * weno5<double>(F3, F2, F1, 3.0 * F1 - 3.0 * F2 + F3, 6.0 * F1 - 8.0 * F2 + 3.0 * F3, weps);
+            } else if (vlo > 0.0) {
+                w[1] = vlo * fw[kk];
+            }
+            if (vhi > 0.0) {
+                const double G1 = at(0, p, NL - 1), G2 = at(0, p, NL - 2), G3 = at(0, p, NL - 3);
+                w[2] = vhi * weno5<double>(G3, G2, G1, 3.0 * G1 - 3.0 * G2 + G3, 6.0 * G1 - 8.0 * G2 + 3.0 * G3, weps);
+            } else if (vhi < 0.0) {
+                w[3] = vhi * fw[kk];
+            }
+        }
+        block_sums<4>(w, sh);
+        nw_lo = -w[0] / w[1];
+        nw_hi = -w[2] / w[3];
+    }
+
+    double rp[4] = {0.0, 0.0, 0.0, 0.0};
+    if (act) {
+        const double dt = A.l_only ? 1.0 : I.dt;
+        const double dlam = tab[I.tdlam + s], dchi = tab[I.tdchi + p];
+        const double vl = (px - lamf[s] * am * py) * inv_opf, vr = (px - lamf[s + 1] * am * py) * inv_opf;
+        const double ul = (1.0 + phif[p]) * py, ur = (1.0 + phif[p + 1]) * py;
+        const double* fin = tab + I.tfin;
+        const double* fout = tab + I.tfout;
+        for (int d = 0; d < 2; ++d) {
+            // column values with wall ghosts, row values with reservoir ghosts
+            auto colv = [&](int c) -> double {
+                if (c >= 0 && c < NL) return at(d, p, c);
+                if (c < 0) {
+                    if (vlo > 0.0) return nw_lo * fw[d * NV + kk];
+                    const double F1 = at(d, p, 0), F2 = at(d, p, 1), F3 = at(d, p, 2);
+                    if (c == -1) return 3.0 * F1 - 3.0 * F2 + F3;
+                    if (c == -2) return 6.0 * F1 - 8.0 * F2 + 3.0 * F3;
+                    return 10.0 * F1 - 15.0 * F2 + 6.0 * F3;
+                }
+                if (vhi < 0.0) return nw_hi * fw[d * NV + kk];
+                const double G1 = at(d, p, NL - 1), G2 = at(d, p, NL - 2), G3 = at(d, p, NL - 3);
+                if (c == NL) return 3.0 * G1 - 3.0 * G2 + G3;
+                if (c == NL + 1) return 6.0 * G1 - 8.0 * G2 + 3.0 * G3;
+                return 10.0 * G1 - 15.0 * G2 + 6.0 * G3;
+            };
+            auto rowv = [&](int c) -> double {
+                if (c >= 0 && c < NX) return at(d, c, s);
+                if (c < 0) return py > 0.0 ? fin[d * NV + kk] : at(d, 0, s);
+                return py < 0.0 ? fout[d * NV + kk] : at(d, NX - 1, s);
+            };
+            double w[7], x[7];
+            for (int q = 0; q < 7; ++q) {
+                w[q] = colv(s - 3 + q);
+                x[q] = rowv(p - 3 + q);
+            }
+            const double Fl = weno_face<double>(vl > 0.0, w[0], w[1], w[2], w[3], w[4], w[5], weps);
+            const double Fr = weno_face<double>(vr > 0.0, w[1], w[2], w[3], w[4], w[5], w[6], weps);
+            const double Gl = weno_face<double>(py > 0.0, x[0], x[1], x[2], x[3], x[4], x[5], weps);
+            const double Gr = weno_face<double>(py > 0.0, x[1], x[2], x[3], x[4], x[5], x[6], weps);
+            const double adv = (vr * Fr - vl * Fl) / dlam + (ur * Gr - ul * Gl) / dchi;
+            const double fc = w[3], fe = d ? T * fe1 : fe1;
+            const double L = -adv - (fc - fe) * itau;
+            const size_t o = d * dsz + (size_t)cell * NV + kk;
+            double out;
+            if (A.l_only) {
+                out = L;
+            } else {
+                const double fn = A.ca != 0.0 ? static_cast<const double*>(A.Fn)[I.offF + o] : 0.0;
+                out = A.ca * fn + A.cb * fc + A.cc * dt * L;
+                const double iw = tab[I.tiW + kk], dd = out - fn;
+                rp[2 * d] = dd * dd * iw;
+                rp[2 * d + 1] = fn * fn * iw;
+            }
+            static_cast<double*>(A.Fout)[I.offF + o] = out;
+        }
+    }
+    if (A.rpart) {
+        block_sums<4>(rp, sh);
+        if (threadIdx.x == 0) {
+            const double vol = tab[I.tvol + cell];
+            for (int d = 0; d < 2; ++d) {
+                A.rpart[((size_t)(I.offC + cell) * 2 + d) * 2] = vol * rp[2 * d];
+                A.rpart[((size_t)(I.offC + cell) * 2 + d) * 2 + 1] = vol * rp[2 * d + 1];
+            }
+        }
     }
 }
 
@@ -756,6 +924,12 @@ hipError_t launch_channel_diag(long long ncells_total, int threads, hipStream_t 
 hipError_t launch_channel_fields(int NX, hipStream_t st, const ChanDesc* inst, const double* tab, const double* diag,
                                  double* out) {
     hipLaunchKernelGGL(channel_fields, dim3((unsigned)((NX + 63) / 64)), dim3(64), 0, st, inst, tab, diag, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_clb_stage(long long ncells, int threads, hipStream_t st, const ChanArgs& A) {
+    if (ncells == 0) return hipSuccess;
+    hipLaunchKernelGGL(clb_stage, dim3((unsigned)ncells), dim3(threads), 0, st, A);
     return hipGetLastError();
 }
 
