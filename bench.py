@@ -140,6 +140,7 @@ def main():
                     help="skip the learned warm-start leg (training solves, training, held-out runs)")
     ap.add_argument("--no-channel", action="store_true", help="skip the expanding-channel leg")
     ap.add_argument("--no-ballistic", action="store_true", help="skip the ballistic (8000-velocity) leg")
+    ap.add_argument("--no-clb", action="store_true", help="skip the vielbein vs Cartesian-split channel timing")
     ap.add_argument("--warm-train", type=int, default=128, help="training instances of the warm-start leg")
     ap.add_argument("--warm-heldout", type=int, default=32, help="held-out instances of the warm-start leg")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
@@ -282,6 +283,42 @@ def main():
                      "product_flops_per_stage": prod_flops}
         bb.close()
 
+    clb = None
+    if not args.no_clb:
+        # vielbein (HH(N;Q) x H(4;5)) against Cartesian-split (HH(N;Q) x HH(N;Q)) channels on the
+        # same grid -- 30 x 200 as in the paper's performance comparison of Sec. VI.G, and the
+        # 128 x 512 grid that fills the chip -- FP64, each at
+        # its own stable dt (the work per step does not depend on it)
+        from paper_1708_05944_amd import Channel, ChannelDesc
+        rows = []
+        for NL, NX, Q in ((30, 200, 4), (30, 200, 8), (30, 200, 12), (30, 200, 16), (128, 512, 8), (128, 512, 16)):
+            geo = dict(N_lambda=NL, N_xi=NX, xi_in=-10.0, xi_out=40.0, r=2.0, L=16.0, Kn=0.2, tau_model=1,
+                       n_in=1.05, n_out=0.95, T_w=1.0)
+            times = {}
+            N = min(Q - 1, 4)
+            for name, kw in (("vlb", dict(ax1=(1, Q, N), ax2=(0, 5, 4))),
+                             ("clb", dict(ax1=(1, Q, N), ax2=(1, Q, N), cartesian=True))):
+                ch = Channel([ChannelDesc(**geo, **kw)])
+                ch.step(2)
+                torch.cuda.synchronize()
+                nst = 20
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                ch.step(nst)
+                e1.record()
+                torch.cuda.synchronize()
+                times[name] = (e0.elapsed_time(e1) / nst, ch.info[0]["NV"])
+                ch.close()
+            rows.append({"grid": f"{NL} x {NX}", "Q": Q, "vlb_ms_per_step": times["vlb"][0],
+                         "vlb_velocities": times["vlb"][1],
+                         "clb_ms_per_step": times["clb"][0], "clb_velocities": times["clb"][1],
+                         "time_ratio_vlb_over_clb": times["vlb"][0] / times["clb"][0]})
+        clb = {"workload": "expanding channel 30 x 200 (the paper's grid) and 128 x 512 cells (r 2, L 16, "
+                           "xi -10..40), Kn 0.2, FP64; vielbein "
+                           "HH(N;Q) x H(4;5) vs Cartesian-split HH(N;Q) x HH(N;Q), N = min(Q - 1, 4); ms per RK3 step "
+                           "(HIP events)",
+               "rows": rows}
+
     warm = None
     if not args.no_warm:
         # learned warm start: surrogate trained on the solver's own steady states (sweep
@@ -333,6 +370,7 @@ def main():
         "time_to_steady_state_warm_start": warm,
         "channel": channel,
         "ballistic": ballistic,
+        "vlb_vs_clb": clb,
     }
     if args.copy_ref_mib:
         n = args.copy_ref_mib << 20
