@@ -351,6 +351,11 @@ vlb_status vlb_channel_set_instance_state(vlb_channel* c, int inst, const double
  * residual (same definition as for Couette, volumes dchi dlambda).  Enqueued on the
  * stream; does not synchronise. */
 vlb_status vlb_channel_step(vlb_channel* c, long nsteps);
+/* Step graphs (default on): runs of more than 10 steps replay a captured HIP graph of 10
+ * steps (every stage launch of the batch, per precision, captured on a private stream at
+ * first use) for all but the last chunk, which runs as plain launches and records the
+ * residual.  enable = 0 makes every step plain launches (bitwise the same results). */
+vlb_status vlb_channel_set_graphs(vlb_channel* c, int enable);
 /* nsteps RK3 steps in FP64 (moves a mixed batch's state to its FP64 buffers). */
 vlb_status vlb_channel_step_fp64(vlb_channel* c, long nsteps);
 /* L[F] of the current state in the current precision (host array of state size, FP64

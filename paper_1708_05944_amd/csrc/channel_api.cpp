@@ -19,6 +19,9 @@ using namespace vlb;
 struct vlb_channel {
     int B = 0;
     hipStream_t stream = nullptr;
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;                  // private stream used only to capture step graphs
+    hipGraphExec_t graph[2] = {nullptr, nullptr};      // [FP32 state]: kChanGraphSteps steps, no residual
     std::vector<vlb_channel_desc> d;
     std::vector<ChanDesc> desc;
     std::vector<double> tab;
@@ -494,8 +497,17 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
 vlb_status vlb_channel_destroy(vlb_channel* c) {
     if (!c) return VLB_OK;
     (void)hipStreamSynchronize(c->stream);
+    for (hipGraphExec_t& g : c->graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->ws) (void)hipFree(c->ws);
     delete c;
+    return VLB_OK;
+}
+
+vlb_status vlb_channel_set_graphs(vlb_channel* c, int enable) {
+    if (!c) return set_error(VLB_EINVAL, "null channel batch");
+    c->use_graphs = enable != 0;
     return VLB_OK;
 }
 
@@ -608,7 +620,44 @@ vlb_status channel_stage(vlb_channel* c, int stage, bool last, bool l_only) {
     return VLB_OK;
 }
 
+constexpr int kChanGraphSteps = 10;
+
+// Capture kChanGraphSteps RK3 steps (every stage launch of the batch, no residual) of the
+// current precision into an executable graph, on a private stream.
+vlb_status channel_capture(vlb_channel* c, hipGraphExec_t* out) {
+    if (!c->cap_stream) VLB_HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    vlb_status st = VLB_OK;
+    if (e == hipSuccess) {
+        for (int it = 0; it < kChanGraphSteps && st == VLB_OK; ++it)
+            for (int stage = 0; stage < 3 && st == VLB_OK; ++stage) st = channel_stage(c, stage, false, false);
+        e = hipStreamEndCapture(c->cap_stream, &g);
+    }
+    c->stream = user;
+    if (st != VLB_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) return set_error(VLB_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return set_error(VLB_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    return VLB_OK;
+}
+
 vlb_status channel_steps(vlb_channel* c, long nsteps) {
+    // all but the last step: replay captured chunks of kChanGraphSteps steps
+    if (c->use_graphs && nsteps > kChanGraphSteps) {
+        hipGraphExec_t& g = c->graph[c->cur32 ? 1 : 0];
+        if (!g) {
+            vlb_status s = channel_capture(c, &g);
+            if (s != VLB_OK) return s;
+        }
+        while (nsteps > kChanGraphSteps) {
+            VLB_HIP_TRY(hipGraphLaunch(g, c->stream));
+            nsteps -= kChanGraphSteps;
+        }
+    }
     for (long it = 0; it < nsteps; ++it) {
         const bool last = it + 1 == nsteps;
         for (int st = 0; st < 3; ++st) {

@@ -174,6 +174,7 @@ _SIGS = {
     "vlb_channel_residual": [ctypes.c_void_p, _dp],
     "vlb_channel_moments": [ctypes.c_void_p, ctypes.c_int] + [_dp] * 5,
     "vlb_channel_flow_fields": [ctypes.c_void_p, ctypes.c_int] + [_dp] * 6,
+    "vlb_channel_set_graphs": [ctypes.c_void_p, ctypes.c_int],
     "vlb_channel_run_to_steady": [ctypes.c_void_p, ctypes.c_double, ctypes.c_long, ctypes.c_int,
                                   ctypes.POINTER(ctypes.c_long), _dp],
     "vlb_status_string": [ctypes.c_int],
@@ -591,6 +592,9 @@ class Channel:
         outs = [np.empty(shp) for _ in range(5)]
         _check(load_library().vlb_channel_moments(self._h, b, *[_ptr(o) for o in outs]), "vlb_channel_moments")
         return dict(zip(("n", "u1", "u2", "T", "content"), outs))
+
+    def set_graphs(self, enable: bool):
+        _check(load_library().vlb_channel_set_graphs(self._h, int(bool(enable))), "vlb_channel_set_graphs")
 
     def flow_fields(self, b: int) -> dict:
         """Cartesian velocity ux, uy, pressure P, vorticity omega ([N_xi][N_lambda]), stream
