@@ -122,7 +122,8 @@ class ChannelOracle:
     (p^xi) as (kind, Q, N)."""
 
     def __init__(self, NL=8, NX=12, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.05, tau_model=TAU_HYDRO, r=2.0, L=4.0,
-                 xi_in=-4.0, xi_out=12.0, n_in=1.1, n_out=0.9, T_w=1.0, weno_eps=0.0, half=False, ends=0, Q0=0.0):
+                 xi_in=-4.0, xi_out=12.0, n_in=1.1, n_out=0.9, T_w=1.0, weno_eps=0.0, half=False, ends=0, Q0=0.0,
+                 A=0.0):
         if NL < (3 if half else 6) or NX < 3:
             raise ValueError("need at least 6 lambda cells (two walls; 3 for the half channel) and 3 xi cells")
         self.a1, self.a2 = quad.axis(*ax1), quad.axis(*ax2)
@@ -130,7 +131,11 @@ class ChannelOracle:
         self.NV = self.Q1 * self.Q2
         self.NL, self.NX = NL, NX
         self.half, self.ends, self.Q0 = bool(half), int(ends), float(Q0)
-        self.lam_f = np.array([(s / NL) if half else (-1.0 + 2.0 * s / NL) for s in range(NL + 1)])
+        # equal cells, or equal cells in eta with lambda = tanh(eta) / A (Eq. canalie_stretch,
+        # H / 2 = 1), eta over [0, artanh A] (half channel) or [-artanh A, artanh A]
+        t = [(s / NL) if half else (-1.0 + 2.0 * s / NL) for s in range(NL + 1)]
+        with mp.workdps(40):
+            self.lam_f = np.array([float(mp.tanh(x * mp.atanh(A)) / A) if A > 0 else x for x in t])
         self.lam_c = 0.5 * (self.lam_f[1:] + self.lam_f[:-1])
         self.dlam = np.diff(self.lam_f)
         self.xi_f = np.array([xi_in + (xi_out - xi_in) * p / NX for p in range(NX + 1)])

@@ -34,6 +34,8 @@ def test_geometry_closed_forms():
     dict(NL=8, NX=10, ax1=(1, 4, 2), ax2=(0, 4, 2), r=2.0),
     dict(NL=6, NX=7, ax1=(1, 3, 2), ax2=(0, 5, 4), r=3.0, L=2.0, xi_in=-2.0, xi_out=5.0),
     dict(NL=10, NX=6, ax1=(1, 5, 4), ax2=(0, 6, 4), r=1.5, Kn=0.5),
+    dict(NL=10, NX=9, ax1=(1, 4, 3), ax2=(0, 5, 4), r=2.0, L=2.0, xi_in=-1.0, xi_out=3.0, A=0.95),   # stretched
+    dict(NL=7, NX=8, ax1=(1, 4, 3), ax2=(0, 5, 4), r=2.5, half=True, A=0.95),                    # paper's grid
 ])
 def test_rest_state_is_stationary(kw):
     """n = 1, u = 0, T = 1 with walls at rest and equal reservoirs: advection through the
@@ -42,7 +44,8 @@ def test_rest_state_is_stationary(kw):
     F = o.equilibrium(1.0, 0.0, 0.0, 1.0)
     L, flux, nw = o.L(F)
     assert np.abs(L).max() <= 1e-13 * np.abs(F).max()
-    assert np.allclose(nw, 1.0, rtol=0, atol=1e-13)
+    walls = nw[:, 1:] if kw.get("half") else nw          # the half channel has its wall at lambda = 1 only
+    assert np.allclose(walls, 1.0, rtol=0, atol=1e-13)
     assert np.abs(flux).max() <= 1e-14
 
 
@@ -107,12 +110,12 @@ def _mirror(o, F):
     return G.reshape(2, o.NX, o.NL, o.NV)
 
 
-@pytest.mark.parametrize("ends,Q0", [(0, 0.0), (1, 0.08)])
-def test_half_channel_is_the_upper_half_of_the_full_channel(ends, Q0):
+@pytest.mark.parametrize("ends,Q0,A", [(0, 0.0, 0.0), (1, 0.08, 0.0), (1, 0.08, 0.95)])
+def test_half_channel_is_the_upper_half_of_the_full_channel(ends, Q0, A):
     """Specular centreline (Sec. VI.C.3): for a mirror-symmetric full-width state the
     half channel's L equals the upper half of the full channel's L (the ghost cells hold
     exactly the values the full channel has there)."""
-    kw = dict(NX=7, ax1=(1, 4, 3), ax2=(0, 5, 4), Kn=0.1, r=1.8, n_in=1.05, n_out=0.95, ends=ends, Q0=Q0)
+    kw = dict(NX=7, ax1=(1, 4, 3), ax2=(0, 5, 4), Kn=0.1, r=1.8, n_in=1.05, n_out=0.95, ends=ends, Q0=Q0, A=A)
     full = ChannelOracle(NL=8, **kw)
     half = ChannelOracle(NL=4, half=True, **kw)
     assert np.array_equal(half.lam_f, full.lam_f[4:])
@@ -256,3 +259,18 @@ def test_flow_fields_rotation_keeps_speed():
     m = o.moments(F)
     assert np.allclose(f["ux"] ** 2 + f["uy"] ** 2, m["u1"] ** 2 + m["u2"] ** 2, rtol=1e-13, atol=1e-18)
     assert np.abs(o.dphi_c).max() > 0.1          # the triad is really tilted here
+
+
+def test_stretched_lambda_faces():
+    """Eq. canalie_stretch with H / 2 = 1: faces tanh(eta) / A on equal eta cells, the walls
+    at lambda = +-1 and the cells refined towards them; a mirror-symmetric state keeps its
+    symmetry on the stretched grid."""
+    o = ChannelOracle(NL=10, NX=7, ax1=(1, 4, 3), ax2=(0, 5, 4), r=2.0, Kn=0.1, A=0.95)
+    eta = np.linspace(-np.arctanh(0.95), np.arctanh(0.95), 11)
+    assert np.allclose(o.lam_f, np.tanh(eta) / 0.95, rtol=0, atol=1e-15)
+    assert o.lam_f[0] == -1.0 and o.lam_f[-1] == 1.0 and o.lam_f[5] == 0.0
+    assert o.dlam[0] < 0.2 * o.dlam[4]
+    F = _perturbed(o, 9)
+    F = 0.5 * (F + _mirror(o, F))
+    L, _, _ = o.L(F)
+    assert np.abs(L - _mirror(o, L)).max() <= 1e-13 * np.abs(L).max()

@@ -27,7 +27,7 @@ def test_rest_state_is_stationary_in_the_expansion():
     assert 3.0 < e1 / e2 < 5.0, (e1, e2)
     F = o.equilibrium(1.0, 0.0, 0.0, 1.0)
     L, nw = o.L(F)
-    assert np.abs(L).max() <= 1e-14 * np.abs(F).max()
+    assert np.abs(L).max() <= 1e-13 * np.abs(F).max()
     assert np.abs(nw - 1.0).max() <= 1e-14
 
 
@@ -56,3 +56,11 @@ def test_mirror_symmetric_state_stays_symmetric():
     Fs = 0.5 * (F + mirror(F))
     L = o.L(Fs.reshape(2, o.NX, o.NL, -1))[0].reshape(Fs.shape)
     assert np.abs(L - mirror(L)).max() <= 1e-13 * np.abs(L).max()
+
+
+def test_rest_state_is_stationary_on_the_stretched_grid():
+    o = ClbOracle(NL=10, NX=9, ax1=(1, 4, 3), ax2=(1, 3, 2), r=2.0, L=2.0, xi_in=-1.0, xi_out=3.0, Kn=0.1,
+                  n_in=1.0, n_out=1.0, A=0.95)
+    F = o.equilibrium(1.0, 0.0, 0.0, 1.0)
+    L, nw = o.L(F)
+    assert np.abs(L).max() <= 1e-13 * np.abs(F).max()
