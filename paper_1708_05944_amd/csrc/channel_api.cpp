@@ -138,6 +138,7 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         if (!(d.N_lambda >= (d.half ? 3 : 6) && (d.half == 0 || d.half == 1) && (d.ends == 0 || d.ends == 1) &&
               std::isfinite(d.Q0) && d.N_xi >= 3 && d.xi_out > d.xi_in && d.r > 0 && d.L > 0 && d.Kn > 0 &&
               d.tau_model >= 0 && d.tau_model <= 2 && axis_ok(d.ax1) && d.ax1.kind == 1 && axis_ok(d.ax2) &&
+              d.A >= 0 && d.A < 1 &&
               d.dt >= 0 && (d.dt > 0 || d.cfl > 0) && d.n_in > 0 && d.n_out > 0 && d.T_w > 0 && d.weno_eps >= 0 &&
               std::isfinite(d.weno_eps))) {
             delete c;
@@ -240,7 +241,14 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         // centreline) and xi on equal cells
         const Wall w{(long double)d.r, (long double)d.L};
         std::vector<long double> lf(NL + 1), xf(NX + 1);
-        for (int s = 0; s <= NL; ++s) lf[s] = d.half ? (long double)s / NL : -1.0L + 2.0L * s / NL;
+        // lambda faces: equal cells, or equal cells in eta with lambda = tanh(eta) / A
+        // (Eq. canalie_stretch with H / 2 = 1; eta from 0 (half channel) or -artanh A to artanh A)
+        for (int s = 0; s <= NL; ++s) {
+            const long double t = d.half ? (long double)s / NL : -1.0L + 2.0L * s / NL;   // in [0, 1] or [-1, 1]
+            lf[s] = d.A > 0 ? std::tanh(t * std::atanh((long double)d.A)) / (long double)d.A : t;
+        }
+        lf[0] = d.half ? 0.0L : -1.0L;   // the walls (and the centreline) exactly
+        lf[NL] = 1.0L;
         for (int p = 0; p <= NX; ++p) xf[p] = (long double)d.xi_in + ((long double)d.xi_out - d.xi_in) * p / NX;
         std::vector<double> al(NX * NL), ar(NX * NL), glxx(NX * NL), glxl(NX * NL), xc((NX + 1) * NL),
             xa((NX + 1) * NL), dlam(NL), dchi(NX), vol(NX * NL);

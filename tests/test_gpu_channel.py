@@ -49,6 +49,10 @@ CASES = [
     dict(N_lambda=5, N_xi=9, ax1=(1, 4, 3), ax2=(0, 5, 4), Kn=0.1, half=True),                 # specular centreline
     dict(N_lambda=8, N_xi=9, ax1=(1, 4, 3), ax2=(0, 5, 4), Kn=0.2, ends=1, Q0=0.1),            # flow-rate ends
     dict(N_lambda=6, N_xi=8, ax1=(1, 8, 4), ax2=(0, 16, 4), Kn=0.05, half=True, ends=1, Q0=0.08),  # the paper's set-up
+    dict(N_lambda=10, N_xi=9, ax1=(1, 4, 3), ax2=(0, 5, 4), Kn=0.1, r=2.0, L=2.0, xi_in=-1.0, xi_out=3.0,
+         A=0.95),                                                                                   # stretched lambda
+    dict(N_lambda=6, N_xi=8, ax1=(1, 8, 4), ax2=(0, 16, 4), Kn=0.05, half=True, ends=1, Q0=0.08,
+         A=0.95),                                                                                   # paper's set-up and grid
 ]
 
 

@@ -41,6 +41,8 @@ CASES = [
     dict(N_lambda=7, N_xi=6, ax1=(1, 4, 3), ax2=(0, 5, 4), Kn=0.2, r=1.0),                                 # straight
     dict(N_lambda=6, N_xi=8, ax1=(1, 6, 4), ax2=(1, 6, 4), Kn=0.05, r=2.0, n_in=1.2, n_out=0.9),          # 144 velocities
     dict(N_lambda=9, N_xi=7, ax1=(1, 8, 4), ax2=(1, 8, 4), Kn=0.3, r=3.0, L=2.0, weno_eps=1e-6),          # 256, regularised
+    dict(N_lambda=10, N_xi=9, ax1=(1, 4, 3), ax2=(1, 4, 3), Kn=0.1, r=2.5, L=2.0, xi_in=-1.0, xi_out=3.0,
+         A=0.95),                                                                                           # stretched
 ]
 
 
