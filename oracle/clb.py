@@ -22,7 +22,12 @@ ends) with these choices:
   V^lambda has the other sign reach);
 * ends: reservoirs as for the vielbein channel (entering populations, p^y > 0 at the
   inlet and < 0 at the outlet, see three ghosts at f_eq(n_in / n_out, 0, T_w); leaving
-  ones a zeroth-order extrapolation).
+  ones a zeroth-order extrapolation), or the flow-rate ends of Sec. VI.C.1-2: every row s
+  carries Q_s = 3 Q0 / (H (1 + phi)) (1 - 4 lambda_s^2 / H^2) through both end faces, the
+  entering ghosts at n_s f_eq(1, (0, Q_s), T_w) (Cartesian components here), n_s from the
+  row balance with the leaving populations of the end cell;
+* the half channel (lambda in [0, 1]) mirrors p^x at the centreline: ghost -1-m of
+  population (i, j) is cell m's population of the mirrored p^x node (Sec. VI.C.3).
 
 WENO-5 face values come from the pinned C routine of ``oracle.couette`` (epsilon-free
 weights of Sec. III.C), one call per population and face.
@@ -37,14 +42,14 @@ from .couette import weno5, weno5_eps
 
 class ClbOracle(ChannelOracle):
     def __init__(self, NL=8, NX=12, ax1=(1, 4, 2), ax2=(1, 4, 2), **kw):
-        if kw.get("half") or kw.get("ends"):
-            raise ValueError("the Cartesian-split channel is built for the full width and reservoir ends")
         super().__init__(NL=NL, NX=NX, ax1=ax1, ax2=ax2, **kw)
         self.weno_eps = kw.get("weno_eps", 0.0)
         # discrete metric a_p (free-stream preserving form of phi')
         self.metric = (1.0 + self.phi_c) * np.diff(self.phi_f) / self.dchi
         self.px = np.repeat(self.a1.p, self.Q2)
         self.py = np.tile(self.a2.p, self.Q1)
+        Qh = self.a1.Q                                        # p^x -> -p^x on the half-range axis
+        self.mirror = np.array([((i + Qh) % (2 * Qh)) * self.Q2 + j for i in range(self.Q1) for j in range(self.Q2)])
 
     def cartesian_velocity(self, m):
         """The moments of the Cartesian-split populations are Cartesian already."""
@@ -71,6 +76,9 @@ class ClbOracle(ChannelOracle):
         NL = self.NL
         for p in range(self.NX):
             for side, lam in ((0, self.lam_f[0]), (1, self.lam_f[-1])):
+                if side == 0 and self.half:
+                    out[p, 0] = 0.0                           # specular centreline, no wall
+                    continue
                 v = self._vlam(lam, p)
                 bound = v < 0 if side == 0 else v > 0
                 G = self._column(F[0], p, None, None)
@@ -103,6 +111,8 @@ class ClbOracle(ChannelOracle):
             if nw is not None:
                 G[q] = np.where(lo > 0, nw[0] * fw, G[q])            # emitted upward from the lower wall
                 G[NL + 3 + q] = np.where(hi < 0, nw[1] * fw, G[NL + 3 + q])
+            if self.half:                                     # cell q - 3 = -1 - m mirrors cell m
+                G[q] = Fd[p, 2 - q][self.mirror]
         return G
 
     def wall_flux(self, F):
@@ -151,9 +161,10 @@ class ClbOracle(ChannelOracle):
             for s in range(NL):
                 H = np.zeros((NX + 6, NV))
                 H[3:NX + 3] = F[d, :, s]
+                gin, gout = (fin[d], fout[d]) if self.ends == 0 else self._end_ghosts(F, s, d)
                 for q in range(3):
-                    H[q] = np.where(self.py > 0, fin[d], F[d, 0, s])
-                    H[NX + 3 + q] = np.where(self.py < 0, fout[d], F[d, NX - 1, s])
+                    H[q] = np.where(self.py > 0, gin, F[d, 0, s])
+                    H[NX + 3 + q] = np.where(self.py < 0, gout, F[d, NX - 1, s])
                 flux = np.empty((NX + 1, NV))
                 for f in range(NX + 1):
                     v = (1.0 + self.phi_f[f]) * self.py
@@ -161,6 +172,36 @@ class ClbOracle(ChannelOracle):
                         flux[f, k] = v[k] * self._face(H, f + 2, v[k], k)
                 out[d, :, s] -= (flux[1:] - flux[:-1]) / self.dchi[:, None]
         return out, nw
+
+    def _end_ghosts(self, F, s, d):
+        """Entering ghosts of row s at the inlet and outlet for the flow-rate ends."""
+        out = []
+        for e, face, end in ((0, 0, 0), (1, self.NX, self.NX - 1)):
+            Q = self.profile(face)[s]
+            f1 = self.feq(1.0, 0.0, Q, self.T_w)
+            entering = self.py > 0 if e == 0 else self.py < 0
+            leave = np.sum(np.where(entering, 0.0, F[0, end, s] * self.py))
+            dens = np.sum(np.where(entering, f1[0] * self.py, 0.0))
+            out.append((Q - leave) / dens * f1[d])
+        return out
+
+    def end_flow(self, F):
+        """Flow rate sum_k p^y F_face of f' of every row at the inlet and outlet faces, [2][NL],
+        with the ghosts L uses."""
+        F = np.asarray(F, dtype=np.float64).reshape(2, self.NX, self.NL, self.NV)
+        fin = self.feq(self.n_in, 0.0, 0.0, self.T_w)[0]
+        fout = self.feq(self.n_out, 0.0, 0.0, self.T_w)[0]
+        out = np.empty((2, self.NL))
+        for s in range(self.NL):
+            H = np.zeros((self.NX + 6, self.NV))
+            H[3:self.NX + 3] = F[0, :, s]
+            gin, gout = (fin, fout) if self.ends == 0 else self._end_ghosts(F, s, 0)
+            for q in range(3):
+                H[q] = np.where(self.py > 0, gin, F[0, 0, s])
+                H[self.NX + 3 + q] = np.where(self.py < 0, gout, F[0, self.NX - 1, s])
+            for e, f in ((0, 0), (1, self.NX)):
+                out[e, s] = sum(self.py[k] * self._face(H, f + 2, self.py[k], k) for k in range(self.NV))
+        return out
 
     def step(self, F, dt: float, nsteps: int = 1):
         """SSP-RK3 steps (Eq. rk3) of the Cartesian-split channel."""

@@ -64,3 +64,33 @@ def test_rest_state_is_stationary_on_the_stretched_grid():
     F = o.equilibrium(1.0, 0.0, 0.0, 1.0)
     L, nw = o.L(F)
     assert np.abs(L).max() <= 1e-13 * np.abs(F).max()
+
+
+def test_straight_half_channel_with_flow_rate_ends_is_the_vielbein_channel():
+    """With phi = 0 the Cartesian split and the vielbein channel coincide also for the
+    paper's set-up: specular centreline and flow-rate ends (against the C oracle)."""
+    kw = dict(NL=5, NX=6, ax1=(1, 4, 3), ax2=(0, 5, 4), r=1.0, Kn=0.2, half=True, ends=1, Q0=0.08)
+    c, v = ClbOracle(**kw), ChannelOracle(**kw)
+    F = _perturbed(v, 1)
+    Lc, Lv = c.L(F)[0], v.L(F)[0]
+    assert np.abs(Lc - Lv).max() <= 1e-13 * np.abs(Lv).max()
+
+
+def test_flow_rate_ends_impose_the_profile():
+    o = ClbOracle(NL=6, NX=7, ax1=(1, 4, 3), ax2=(1, 3, 2), r=2.5, L=2.0, xi_in=-1.0, xi_out=3.0, Kn=0.1, half=True,
+                  ends=1, Q0=0.1, A=0.9)
+    rf = o.end_flow(_perturbed(o, 2))
+    assert np.abs(rf[0] - o.profile(0)).max() <= 1e-14
+    assert np.abs(rf[1] - o.profile(o.NX)).max() <= 1e-14
+
+
+def test_half_channel_is_the_upper_half_of_the_full_channel():
+    kw = dict(NX=7, ax1=(1, 4, 3), ax2=(1, 3, 2), r=2.5, L=2.0, xi_in=-1.0, xi_out=3.0, Kn=0.1, ends=1, Q0=0.1, A=0.9)
+    full, half = ClbOracle(NL=8, **kw), ClbOracle(NL=4, half=True, **kw)
+    F = _perturbed(full, 3).reshape(2, full.NX, full.NL, full.Q1, full.Q2)
+    Q = full.a1.Q
+    perm = np.r_[Q:2 * Q, 0:Q]
+    F = (0.5 * (F + F[:, :, ::-1][:, :, :, perm, :])).reshape(2, full.NX, full.NL, -1)
+    Lf = full.L(F)[0]
+    Lh = half.L(np.ascontiguousarray(F[:, :, 4:]))[0]
+    assert np.abs(Lh - Lf[:, :, 4:]).max() <= 1e-14 * np.abs(Lf).max()
