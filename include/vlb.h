@@ -330,8 +330,9 @@ typedef struct {
     int cartesian; /* 1: the Cartesian-split form of Sec. VI.G: ax1 = p^x (across), ax2 = p^y
                     * (along), no force terms, V^lambda = (p^x - lambda a p^y)/(1 + phi) with the
                     * discrete metric a = (1 + phi)(phi_{p+1/2} - phi_{p-1/2})/dchi, V^xi = (1 + phi) p^y,
-                    * walls by the sign of V^lambda at the wall face (Eq. canalie_coord_nw).  FP64,
-                    * full width and reservoir ends only; up to 1024 velocities. */
+                    * walls by the sign of V^lambda at the wall face (Eq. canalie_coord_nw); the half
+                    * channel mirrors p^x, flow-rate ends take the Cartesian profile velocity (0, Q).
+                    * FP64 only; up to 1024 velocities. */
     double A;      /* 0: equal lambda cells; 0 < A < 1: cells equal in eta with lambda = tanh(eta)/A
                     * (Eq. canalie_stretch, the paper uses A = 0.95), refined towards the walls */
 } vlb_channel_desc;

@@ -144,10 +144,9 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
             delete c;
             return set_error(VLB_EINVAL, "invalid channel descriptor for instance %d (ax1 must be half range)", i);
         }
-        if (d.cartesian != 0 && (d.cartesian != 1 || d.half || d.ends || precision != VLB_FP64)) {
+        if (d.cartesian != 0 && (d.cartesian != 1 || precision != VLB_FP64)) {
             delete c;
-            return set_error(VLB_EINVAL, "instance %d: the Cartesian-split channel runs in FP64 on the full width "
-                             "with reservoir ends", i);
+            return set_error(VLB_EINVAL, "instance %d: the Cartesian-split channel runs in FP64", i);
         }
         const AxisTables* a1 = get_axis(d.ax1);
         const AxisTables* a2 = get_axis(d.ax2);
@@ -339,7 +338,8 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
             for (int e = 0; e < 2; ++e) {
                 const int f = e ? NX : 0;
                 for (int s = 0; s < NL; ++s) {
-                    const long double lam = (lf[s] + lf[s + 1]) / 2, a = lam * w.dphi(xf[f]);
+                    // the Cartesian split takes the profile velocity (0, Q) as it is (a = 0)
+                    const long double lam = (lf[s] + lf[s + 1]) / 2, a = d.cartesian ? 0 : lam * w.dphi(xf[f]);
                     const long double cc = 1 / std::sqrt(1 + a * a);
                     const double Q = (double)(3 * (long double)d.Q0 / (2 * (1 + w.phi(xf[f]))) * (1 - lam * lam));
                     axis_equilibrium_host(*a1, (double)(-a * cc * Q), d.T_w, gl.data());

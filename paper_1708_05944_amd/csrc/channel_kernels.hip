@@ -709,8 +709,10 @@ __global__ __launch_bounds__(64) void channel_fields(const ChanDesc* inst, const
 // velocities V^lambda = (p^x - lambda a_p p^y) / (1 + phi_p) at the lambda faces, with the
 // discrete metric a_p = (1 + phi_p)(phi_{p+1/2} - phi_{p-1/2}) / dchi_p (free-stream
 // preserving), and V^xi = (1 + phi) p^y at the xi faces.  A population is wall-bound or
-// emitted by the sign of V^lambda at the wall face; n_w by Eq. canalie_coord_nw.  One block
-// per cell, one thread per velocity; the block sums its cell's moments itself.
+// emitted by the sign of V^lambda at the wall face; n_w by Eq. canalie_coord_nw.  The half
+// channel mirrors p^x at the centreline; flow-rate ends take the Cartesian profile velocity
+// (0, Q_s) and n_s from the row balance.  One block per cell, one thread per velocity; the
+// block sums its cell's moments itself.
 __global__ __launch_bounds__(kMaxNV) void clb_stage(ChanArgs A) {
     __shared__ double sh[16 * 5];
     __shared__ double ec[4 * (kMaxN + 1)];
@@ -729,6 +731,7 @@ __global__ __launch_bounds__(kMaxNV) void clb_stage(ChanArgs A) {
     const double* F = static_cast<const double*>(A.Fin) + I.offF;
     const size_t dsz = (size_t)NX * NL * NV;
     auto at = [&](int d, int pp, int ss) -> double { return F[d * dsz + ((size_t)pp * NL + ss) * NV + kk]; };
+    const int km = ((vi + I.Qh1) % Q1) * Q2 + vj;   // the p^x-mirrored velocity (half channel)
 
     // moments of the cell (Sec. IV.A) and the relaxation time
     double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -778,7 +781,9 @@ __global__ __launch_bounds__(kMaxNV) void clb_stage(ChanArgs A) {
     if (s < 3 || s >= NL - 3) {
         double w[4] = {0.0, 0.0, 0.0, 0.0};
         if (act) {
-            if (vlo < 0.0) {
+            if (I.half) {
+                // specular centreline: no lower wall
+            } else if (vlo < 0.0) {
                 const double F1 = at(0, p, 0), F2 = at(0, p, 1), F3 = at(0, p, 2);
                 w[0] = vlo * weno5<double>(F3, F2, F1, 3.0 * F1 - 3.0 * F2 + F3, 6.0 * F1 - 8.0 * F2 + 3.0 * F3, weps);
             } else if (vlo > 0.0) {
@@ -792,8 +797,20 @@ __global__ __launch_bounds__(kMaxNV) void clb_stage(ChanArgs A) {
             }
         }
         block_sums<4>(w, sh);
-        nw_lo = -w[0] / w[1];
+        nw_lo = I.half ? 0.0 : -w[0] / w[1];
         nw_hi = -w[2] / w[3];
+    }
+    // flow-rate ends (Sec. VI.C.1-2): densities of the entering ghosts of this row
+    double n_in = 0.0, n_out = 0.0;
+    if (I.ends == 1 && (p < 3 || p >= NX - 3)) {
+        double w[2] = {0.0, 0.0};
+        if (act) {
+            if (py <= 0.0) w[0] = at(0, 0, s) * py;          // leaving through the inlet face
+            if (py >= 0.0) w[1] = at(0, NX - 1, s) * py;     // leaving through the outlet face
+        }
+        block_sums<2>(w, sh);
+        n_in = (tab[I.tQrow + s] - w[0]) / tab[I.tden + s];
+        n_out = (tab[I.tQrow + NL + s] - w[1]) / tab[I.tden + NL + s];
     }
 
     double rp[4] = {0.0, 0.0, 0.0, 0.0};
@@ -808,6 +825,7 @@ __global__ __launch_bounds__(kMaxNV) void clb_stage(ChanArgs A) {
             // column values with wall ghosts, row values with reservoir ghosts
             auto colv = [&](int c) -> double {
                 if (c >= 0 && c < NL) return at(d, p, c);
+                if (c < 0 && I.half) return F[d * dsz + ((size_t)p * NL + (-1 - c)) * NV + km];
                 if (c < 0) {
                     if (vlo > 0.0) return nw_lo * fw[d * NV + kk];
                     const double F1 = at(d, p, 0), F2 = at(d, p, 1), F3 = at(d, p, 2);
@@ -821,10 +839,15 @@ __global__ __launch_bounds__(kMaxNV) void clb_stage(ChanArgs A) {
                 if (c == NL + 1) return 6.0 * G1 - 8.0 * G2 + 3.0 * G3;
                 return 10.0 * G1 - 15.0 * G2 + 6.0 * G3;
             };
+            const double* frow = tab + I.tfrow;
             auto rowv = [&](int c) -> double {
                 if (c >= 0 && c < NX) return at(d, c, s);
-                if (c < 0) return py > 0.0 ? fin[d * NV + kk] : at(d, 0, s);
-                return py < 0.0 ? fout[d * NV + kk] : at(d, NX - 1, s);
+                if (c < 0) {
+                    if (py <= 0.0) return at(d, 0, s);
+                    return I.ends == 1 ? n_in * frow[((size_t)s * 2 + d) * NV + kk] : fin[d * NV + kk];
+                }
+                if (py >= 0.0) return at(d, NX - 1, s);
+                return I.ends == 1 ? n_out * frow[((size_t)(NL + s) * 2 + d) * NV + kk] : fout[d * NV + kk];
             };
             double w[7], x[7];
             for (int q = 0; q < 7; ++q) {

@@ -43,6 +43,8 @@ CASES = [
     dict(N_lambda=9, N_xi=7, ax1=(1, 8, 4), ax2=(1, 8, 4), Kn=0.3, r=3.0, L=2.0, weno_eps=1e-6),          # 256, regularised
     dict(N_lambda=10, N_xi=9, ax1=(1, 4, 3), ax2=(1, 4, 3), Kn=0.1, r=2.5, L=2.0, xi_in=-1.0, xi_out=3.0,
          A=0.95),                                                                                           # stretched
+    dict(N_lambda=6, N_xi=9, ax1=(1, 6, 4), ax2=(1, 6, 4), Kn=0.2, r=2.0, L=2.0, xi_in=-1.0, xi_out=3.0,
+         half=True, ends=1, Q0=0.1, A=0.95),                                                              # paper's set-up
 ]
 
 
@@ -101,4 +103,19 @@ def test_clb_and_vielbein_channels_step_together():
     assert np.allclose(got["ux"], m["u1"], rtol=0, atol=1e-15) and np.allclose(got["uy"], m["u2"], rtol=0, atol=1e-15)
     for k in ("P", "psi", "Pw"):
         assert np.abs(got[k] - want[k]).max() <= 1e-12 * np.abs(want[k]).max(), k
+    c.close()
+
+
+def test_clb_paper_setup_steps_match_oracle():
+    """The paper's comparison set-up in the Cartesian split: half channel, flow-rate ends,
+    stretched lambda -- 4 RK3 steps from a perturbed state."""
+    from paper_1708_05944_amd import Channel
+    o, d = _pair(**dict(CASES[-1]))
+    c = Channel([d])
+    F = _perturbed(o, 21)
+    c.set_state(F.ravel())
+    c.step(4)
+    err = _relerr(c.instance_view(c.get_state(), 0), o.step(F, c.info[0]["dt"], 4))
+    _say(f"4 steps rel err {err:.2e}")
+    assert err <= TOL
     c.close()

@@ -67,9 +67,8 @@ def _channel_create_status(**kw):
     (dict(N_lambda=8, N_xi=8, weno_eps=-1.0), "invalid channel descriptor"),
     (dict(N_lambda=8, N_xi=8, ax1=(1, 20, 4), ax2=(0, 20, 4)), "exceed the kernel limits"),   # 40 x 20 nodes
     (dict(N_lambda=8, N_xi=8, precision=7), "unsupported precision"),
-    (dict(N_lambda=8, N_xi=8, cartesian=True, half=True), "Cartesian-split"),      # full width only
-    (dict(N_lambda=8, N_xi=8, cartesian=True, ends=1, Q0=0.1), "Cartesian-split"),  # reservoir ends only
     (dict(N_lambda=8, N_xi=8, cartesian=True, precision=1), "Cartesian-split"),    # FP64 only
+    (dict(N_lambda=8, N_xi=8, A=1.0), "invalid channel descriptor"),                # stretching 0 <= A < 1
     (dict(N_lambda=8, N_xi=8, cartesian=True, ax1=(1, 20, 4), ax2=(1, 20, 4)), "exceed the kernel limits"),
 ])
 def test_channel_create_rejects_invalid_descriptors(kw, needle):
