@@ -167,8 +167,10 @@ __device__ void wide_force(const WideArgs& A, long long tile, double (*part)[kWi
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u)
+            if (k0 + 4 * u < kend)   // wavefront-uniform: no all-zero steps past the slice
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bv[u][t], acc[t], 0, 0, 0);
+                for (int t = 0; t < NT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bv[u][t], acc[t], 0, 0, 0);
     }
     if (wave > 0)
 #pragma unroll
