@@ -37,7 +37,6 @@ struct vlb_channel {
     std::vector<int> clb_ilist;           // Cartesian-split instances: one launch, a block per cell
     std::vector<long long> clb_base{0};
     size_t off_clb_ilist = 0, off_clb_base = 0;
-    int clb_threads = 64;
     size_t state_n = 0, ncells = 0;
     int threads = 64;
     int precision = VLB_FP64;
@@ -387,7 +386,6 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         if (d.cartesian) {
             c->clb_ilist.push_back(i);
             c->clb_base.push_back(c->clb_base.back() + (long long)NX * NL);
-            c->clb_threads = std::max(c->clb_threads, (NV + kWave - 1) / kWave * kWave);
         } else {
             auto it = std::find_if(c->groups.begin(), c->groups.end(),
                                    [&](const vlb_channel::Group& g) { return g.T1 == T1 && g.T2 == T2; });
@@ -418,7 +416,7 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         c->threads = std::max(c->threads, (NV + kWave - 1) / kWave * kWave);
     }
     c->cbase.push_back(cells);
-    if (c->clb_base.back() * c->clb_threads >= (1LL << 32)) {
+    if (c->clb_base.back() * 256 >= (1LL << 32)) {   // Cartesian-split blocks of 256 threads
         delete c;
         return set_error(VLB_EINVAL, "batch too large for one Cartesian-split launch (%lld cells)", c->clb_base.back());
     }
@@ -623,7 +621,7 @@ vlb_status channel_stage(vlb_channel* c, int stage, bool last, bool l_only) {
         A.ilist = (const int*)(c->ws + c->off_clb_ilist);
         A.B = (int)c->clb_ilist.size();
         A.base = (const long long*)(c->ws + c->off_clb_base);
-        VLB_HIP_TRY(launch_clb_stage(c->clb_base.back(), c->clb_threads, c->stream, A));
+        VLB_HIP_TRY(launch_clb_stage(c->clb_base.back(), c->stream, A));
     }
     return VLB_OK;
 }

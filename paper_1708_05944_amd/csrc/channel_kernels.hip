@@ -711,9 +711,11 @@ __global__ __launch_bounds__(64) void channel_fields(const ChanDesc* inst, const
 // preserving), and V^xi = (1 + phi) p^y at the xi faces.  A population is wall-bound or
 // emitted by the sign of V^lambda at the wall face; n_w by Eq. canalie_coord_nw.  The half
 // channel mirrors p^x at the centreline; flow-rate ends take the Cartesian profile velocity
-// (0, Q_s) and n_s from the row balance.  One block per cell, one thread per velocity; the
-// block sums its cell's moments itself.
-__global__ __launch_bounds__(kMaxNV) void clb_stage(ChanArgs A) {
+// (0, Q_s) and n_s from the row balance.  One block of kClbThreads threads per cell, each
+// thread taking the velocities k = threadIdx.x + j kClbThreads; the block sums its cell's
+// moments itself.
+constexpr int kClbThreads = 256;
+__global__ __launch_bounds__(kClbThreads) void clb_stage(ChanArgs A) {
     __shared__ double sh[16 * 5];
     __shared__ double ec[4 * (kMaxN + 1)];
     __shared__ double gq[4 * kMaxQ];   // g(p) of the nodes of both axes
@@ -724,24 +726,21 @@ __global__ __launch_bounds__(kMaxNV) void clb_stage(ChanArgs A) {
     const int NL = I.NL, NX = I.NX, NV = I.NV, Q1 = I.Q1, Q2 = I.Q2, N1 = I.N1, N2 = I.N2;
     const int p = cell / NL, s = cell - p * NL;
     const double* tab = A.tab + I.offT;
-    const int k = threadIdx.x;
-    const bool act = k < NV;
-    const int kk = act ? k : 0, vi = kk / Q2, vj = kk - vi * Q2;
-    const double px = tab[I.tp1 + vi], py = tab[I.tp2 + vj];
     const double* F = static_cast<const double*>(A.Fin) + I.offF;
     const size_t dsz = (size_t)NX * NL * NV;
-    auto at = [&](int d, int pp, int ss) -> double { return F[d * dsz + ((size_t)pp * NL + ss) * NV + kk]; };
-    const int km = ((vi + I.Qh1) % Q1) * Q2 + vj;   // the p^x-mirrored velocity (half channel)
+    auto at = [&](int d, int pp, int ss, int k) -> double { return F[d * dsz + ((size_t)pp * NL + ss) * NV + k]; };
+    auto pxk = [&](int k) -> double { return tab[I.tp1 + k / Q2]; };
+    auto pyk = [&](int k) -> double { return tab[I.tp2 + k % Q2]; };
 
     // moments of the cell (Sec. IV.A) and the relaxation time
     double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (act) {
-        const double f0 = at(0, p, s);
-        m[0] = f0;
-        m[1] = px * f0;
-        m[2] = py * f0;
-        m[3] = (px * px + py * py) * f0;
-        m[4] = at(1, p, s);
+    for (int k = threadIdx.x; k < NV; k += kClbThreads) {
+        const double px = pxk(k), py = pyk(k), f0 = at(0, p, s, k);
+        m[0] += f0;
+        m[1] += px * f0;
+        m[2] += py * f0;
+        m[3] += (px * px + py * py) * f0;
+        m[4] += at(1, p, s, k);
     }
     block_sums<5>(m, sh);
     const double n = m[0], ux = m[1] / n, uy = m[2] / n;
@@ -754,7 +753,7 @@ __global__ __launch_bounds__(kMaxNV) void clb_stage(ChanArgs A) {
                        tab + (ax ? I.tisf2 : I.tisf1), sg, ec + ax * 2 * (kMaxN + 1) + sg * (N + 1));
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < Q1 + Q2; t += blockDim.x) {
+    for (int t = threadIdx.x; t < Q1 + Q2; t += kClbThreads) {
         const bool ax1 = t < Q1;
         const int node = ax1 ? t : t - Q1, N = ax1 ? N1 : N2;
         const bool minus = ax1 ? (I.kind1 == 1 && node >= I.Qh1) : (I.kind2 == 1 && node >= I.Qh2);
@@ -765,7 +764,6 @@ __global__ __launch_bounds__(kMaxNV) void clb_stage(ChanArgs A) {
         gq[t] = g;
     }
     __syncthreads();
-    const double fe1 = n * gq[vi] * gq[Q1 + vj];
 
     // geometry of the column
     const double* geo = tab + I.tgeo;
@@ -773,27 +771,28 @@ __global__ __launch_bounds__(kMaxNV) void clb_stage(ChanArgs A) {
     const double* lamf = geo + 3 * NX;
     const double am = tab[I.tclb + p];
     const double* phif = tab + I.tclb + NX;
-    const double vlo = (px + am * py) * inv_opf, vhi = (px - am * py) * inv_opf;   // V^lambda at lambda = -1, +1
     const double* fw = tab + I.tfw;
     const double weps = I.weno_eps;
     // n_w of the walls this cell's stencil reaches (Eq. canalie_coord_nw; f' only)
     double nw_lo = 0.0, nw_hi = 0.0;
     if (s < 3 || s >= NL - 3) {
         double w[4] = {0.0, 0.0, 0.0, 0.0};
-        if (act) {
+        for (int k = threadIdx.x; k < NV; k += kClbThreads) {
+            const double px = pxk(k), py = pyk(k);
+            const double vlo = (px + am * py) * inv_opf, vhi = (px - am * py) * inv_opf;   // at lambda = -1, +1
             if (I.half) {
                 // specular centreline: no lower wall
             } else if (vlo < 0.0) {
-                const double F1 = at(0, p, 0), F2 = at(0, p, 1), F3 = at(0, p, 2);
-                w[0] = vlo * weno5<double>(F3, F2, F1, 3.0 * F1 - 3.0 * F2 + F3, 6.0 * F1 - 8.0 * F2 + 3.0 * F3, weps);
+                const double F1 = at(0, p, 0, k), F2 = at(0, p, 1, k), F3 = at(0, p, 2, k);
+                w[0] += vlo * weno5<double>(F3, F2, F1, 3.0 * F1 - 3.0 * F2 + F3, 6.0 * F1 - 8.0 * F2 + 3.0 * F3, weps);
             } else if (vlo > 0.0) {
-                w[1] = vlo * fw[kk];
+                w[1] += vlo * fw[k];
             }
             if (vhi > 0.0) {
-                const double G1 = at(0, p, NL - 1), G2 = at(0, p, NL - 2), G3 = at(0, p, NL - 3);
-                w[2] = vhi * weno5<double>(G3, G2, G1, 3.0 * G1 - 3.0 * G2 + G3, 6.0 * G1 - 8.0 * G2 + 3.0 * G3, weps);
+                const double G1 = at(0, p, NL - 1, k), G2 = at(0, p, NL - 2, k), G3 = at(0, p, NL - 3, k);
+                w[2] += vhi * weno5<double>(G3, G2, G1, 3.0 * G1 - 3.0 * G2 + G3, 6.0 * G1 - 8.0 * G2 + 3.0 * G3, weps);
             } else if (vhi < 0.0) {
-                w[3] = vhi * fw[kk];
+                w[3] += vhi * fw[k];
             }
         }
         block_sums<4>(w, sh);
@@ -804,9 +803,10 @@ __global__ __launch_bounds__(kMaxNV) void clb_stage(ChanArgs A) {
     double n_in = 0.0, n_out = 0.0;
     if (I.ends == 1 && (p < 3 || p >= NX - 3)) {
         double w[2] = {0.0, 0.0};
-        if (act) {
-            if (py <= 0.0) w[0] = at(0, 0, s) * py;          // leaving through the inlet face
-            if (py >= 0.0) w[1] = at(0, NX - 1, s) * py;     // leaving through the outlet face
+        for (int k = threadIdx.x; k < NV; k += kClbThreads) {
+            const double py = pyk(k);
+            if (py <= 0.0) w[0] += at(0, 0, s, k) * py;          // leaving through the inlet face
+            if (py >= 0.0) w[1] += at(0, NX - 1, s, k) * py;     // leaving through the outlet face
         }
         block_sums<2>(w, sh);
         n_in = (tab[I.tQrow + s] - w[0]) / tab[I.tden + s];
@@ -814,63 +814,67 @@ __global__ __launch_bounds__(kMaxNV) void clb_stage(ChanArgs A) {
     }
 
     double rp[4] = {0.0, 0.0, 0.0, 0.0};
-    if (act) {
-        const double dt = A.l_only ? 1.0 : I.dt;
-        const double dlam = tab[I.tdlam + s], dchi = tab[I.tdchi + p];
+    const double dt = A.l_only ? 1.0 : I.dt;
+    const double dlam = tab[I.tdlam + s], dchi = tab[I.tdchi + p];
+    const double* fin = tab + I.tfin;
+    const double* fout = tab + I.tfout;
+    const double* frow = tab + I.tfrow;
+    for (int k = threadIdx.x; k < NV; k += kClbThreads) {
+        const int vi = k / Q2, vj = k - vi * Q2;
+        const int km = ((vi + I.Qh1) % Q1) * Q2 + vj;   // the p^x-mirrored velocity (half channel)
+        const double px = tab[I.tp1 + vi], py = tab[I.tp2 + vj];
+        const double vlo = (px + am * py) * inv_opf, vhi = (px - am * py) * inv_opf;
         const double vl = (px - lamf[s] * am * py) * inv_opf, vr = (px - lamf[s + 1] * am * py) * inv_opf;
         const double ul = (1.0 + phif[p]) * py, ur = (1.0 + phif[p + 1]) * py;
-        const double* fin = tab + I.tfin;
-        const double* fout = tab + I.tfout;
+        const double fe1 = n * gq[vi] * gq[Q1 + vj];
         for (int d = 0; d < 2; ++d) {
-            // column values with wall ghosts, row values with reservoir ghosts
+            // column values with wall ghosts, row values with reservoir / flow-rate ghosts
             auto colv = [&](int c) -> double {
-                if (c >= 0 && c < NL) return at(d, p, c);
-                if (c < 0 && I.half) return F[d * dsz + ((size_t)p * NL + (-1 - c)) * NV + km];
+                if (c >= 0 && c < NL) return at(d, p, c, k);
+                if (c < 0 && I.half) return at(d, p, -1 - c, km);
                 if (c < 0) {
-                    if (vlo > 0.0) return nw_lo * fw[d * NV + kk];
-                    const double F1 = at(d, p, 0), F2 = at(d, p, 1), F3 = at(d, p, 2);
+                    if (vlo > 0.0) return nw_lo * fw[d * NV + k];
+                    const double F1 = at(d, p, 0, k), F2 = at(d, p, 1, k), F3 = at(d, p, 2, k);
                     if (c == -1) return 3.0 * F1 - 3.0 * F2 + F3;
                     if (c == -2) return 6.0 * F1 - 8.0 * F2 + 3.0 * F3;
                     return 10.0 * F1 - 15.0 * F2 + 6.0 * F3;
                 }
-                if (vhi < 0.0) return nw_hi * fw[d * NV + kk];
-                const double G1 = at(d, p, NL - 1), G2 = at(d, p, NL - 2), G3 = at(d, p, NL - 3);
+                if (vhi < 0.0) return nw_hi * fw[d * NV + k];
+                const double G1 = at(d, p, NL - 1, k), G2 = at(d, p, NL - 2, k), G3 = at(d, p, NL - 3, k);
                 if (c == NL) return 3.0 * G1 - 3.0 * G2 + G3;
                 if (c == NL + 1) return 6.0 * G1 - 8.0 * G2 + 3.0 * G3;
                 return 10.0 * G1 - 15.0 * G2 + 6.0 * G3;
             };
-            const double* frow = tab + I.tfrow;
             auto rowv = [&](int c) -> double {
-                if (c >= 0 && c < NX) return at(d, c, s);
+                if (c >= 0 && c < NX) return at(d, c, s, k);
                 if (c < 0) {
-                    if (py <= 0.0) return at(d, 0, s);
-                    return I.ends == 1 ? n_in * frow[((size_t)s * 2 + d) * NV + kk] : fin[d * NV + kk];
+                    if (py <= 0.0) return at(d, 0, s, k);
+                    return I.ends == 1 ? n_in * frow[((size_t)s * 2 + d) * NV + k] : fin[d * NV + k];
                 }
-                if (py >= 0.0) return at(d, NX - 1, s);
-                return I.ends == 1 ? n_out * frow[((size_t)(NL + s) * 2 + d) * NV + kk] : fout[d * NV + kk];
+                if (py >= 0.0) return at(d, NX - 1, s, k);
+                return I.ends == 1 ? n_out * frow[((size_t)(NL + s) * 2 + d) * NV + k] : fout[d * NV + k];
             };
-            double w[7], x[7];
-            for (int q = 0; q < 7; ++q) {
-                w[q] = colv(s - 3 + q);
-                x[q] = rowv(p - 3 + q);
-            }
-            const double Fl = weno_face<double>(vl > 0.0, w[0], w[1], w[2], w[3], w[4], w[5], weps);
-            const double Fr = weno_face<double>(vr > 0.0, w[1], w[2], w[3], w[4], w[5], w[6], weps);
-            const double Gl = weno_face<double>(py > 0.0, x[0], x[1], x[2], x[3], x[4], x[5], weps);
-            const double Gr = weno_face<double>(py > 0.0, x[1], x[2], x[3], x[4], x[5], x[6], weps);
-            const double adv = (vr * Fr - vl * Fl) / dlam + (ur * Gr - ul * Gl) / dchi;
-            const double fc = w[3], fe = d ? T * fe1 : fe1;
+            // the two directions one after the other (seven stencil values live at a time)
+            double w[7];
+            for (int q = 0; q < 7; ++q) w[q] = colv(s - 3 + q);
+            const double fc = w[3];
+            double adv = (vr * weno_face<double>(vr > 0.0, w[1], w[2], w[3], w[4], w[5], w[6], weps) -
+                          vl * weno_face<double>(vl > 0.0, w[0], w[1], w[2], w[3], w[4], w[5], weps)) / dlam;
+            for (int q = 0; q < 7; ++q) w[q] = rowv(p - 3 + q);
+            adv += (ur * weno_face<double>(py > 0.0, w[1], w[2], w[3], w[4], w[5], w[6], weps) -
+                    ul * weno_face<double>(py > 0.0, w[0], w[1], w[2], w[3], w[4], w[5], weps)) / dchi;
+            const double fe = d ? T * fe1 : fe1;
             const double L = -adv - (fc - fe) * itau;
-            const size_t o = d * dsz + (size_t)cell * NV + kk;
+            const size_t o = d * dsz + (size_t)cell * NV + k;
             double out;
             if (A.l_only) {
                 out = L;
             } else {
                 const double fn = A.ca != 0.0 ? static_cast<const double*>(A.Fn)[I.offF + o] : 0.0;
                 out = A.ca * fn + A.cb * fc + A.cc * dt * L;
-                const double iw = tab[I.tiW + kk], dd = out - fn;
-                rp[2 * d] = dd * dd * iw;
-                rp[2 * d + 1] = fn * fn * iw;
+                const double iw = tab[I.tiW + k], dd = out - fn;
+                rp[2 * d] += dd * dd * iw;
+                rp[2 * d + 1] += fn * fn * iw;
             }
             static_cast<double*>(A.Fout)[I.offF + o] = out;
         }
@@ -950,9 +954,9 @@ hipError_t launch_channel_fields(int NX, hipStream_t st, const ChanDesc* inst, c
     return hipGetLastError();
 }
 
-hipError_t launch_clb_stage(long long ncells, int threads, hipStream_t st, const ChanArgs& A) {
+hipError_t launch_clb_stage(long long ncells, hipStream_t st, const ChanArgs& A) {
     if (ncells == 0) return hipSuccess;
-    hipLaunchKernelGGL(clb_stage, dim3((unsigned)ncells), dim3(threads), 0, st, A);
+    hipLaunchKernelGGL(clb_stage, dim3((unsigned)ncells), dim3(kClbThreads), 0, st, A);
     return hipGetLastError();
 }
 
