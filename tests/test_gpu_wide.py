@@ -100,3 +100,21 @@ def test_wide_rest_state_is_stationary_and_mass_is_conserved():
     assert abs(m1 - m0) <= 1e-13 * m0
     b.close()
     b2.close()
+
+
+def test_wide_instance_runs_to_steady_state_with_retirement():
+    """run_to_steady over a batch holding a one-block instance and a large-set instance:
+    both reach r < 1e-9 and the converged one is retired (not advanced) while the other
+    keeps stepping; the large-set steady state satisfies the oracle's L[F] = 0 to the
+    residual level."""
+    from paper_1708_05944_amd import Batch
+    o, d = _pair(N_R=6, ax1=(1, 20, 4), ax2=(0, 25, 4), Kn=0.5, u_in=0.2)   # 1000 velocities, 65 nodes
+    o2, d2 = _pair(N_R=16, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.1, u_in=0.1)
+    b = Batch([d, d2])
+    steps, r, ok = b.run_to_steady(1e-9, 200000, 500)
+    _say(f"steps {steps}, residuals {r}")
+    assert ok and (r < 1e-9).all() and (steps > 0).all()
+    F = b.instance_view(b.get_state(), 0).copy()
+    L, _ = o.L(F)
+    assert np.abs(L).max() <= 1e-6 * np.abs(F).max()
+    b.close()
