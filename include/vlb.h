@@ -335,6 +335,10 @@ typedef struct {
                     * FP64 only; up to 1024 velocities. */
     double A;      /* 0: equal lambda cells; 0 < A < 1: cells equal in eta with lambda = tanh(eta)/A
                     * (Eq. canalie_stretch, the paper uses A = 0.95), refined towards the walls */
+    int kernel;    /* 0: automatic; 1: velocity tiles of 16 x 16 on the matrix cores (at most two
+                    * tiles; FP64 or mixed); 2: the population kernel (a block per cell, a thread per
+                    * velocity, up to 1024 velocities; FP64).  Automatic picks the population kernel
+                    * in FP64 for sets that fill less than half their tiles or need more than two. */
 } vlb_channel_desc;
 typedef struct vlb_channel vlb_channel;
 

@@ -34,9 +34,9 @@ struct vlb_channel {
         size_t off_ilist, off_base, off_bbase;
     };
     std::vector<Group> groups;
-    std::vector<int> clb_ilist;           // Cartesian-split instances: one launch, a block per cell
-    std::vector<long long> clb_base{0};
-    size_t off_clb_ilist = 0, off_clb_base = 0;
+    std::vector<int> pop_ilist;           // instances of the population kernel: one launch, a block per cell
+    std::vector<long long> pop_base{0};
+    size_t off_pop_ilist = 0, off_pop_base = 0;
     size_t state_n = 0, ncells = 0;
     int threads = 64;
     int precision = VLB_FP64;
@@ -147,6 +147,11 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
             delete c;
             return set_error(VLB_EINVAL, "instance %d: the Cartesian-split channel runs in FP64", i);
         }
+        if (d.kernel < 0 || d.kernel > 2 || (d.kernel == 2 && precision != VLB_FP64)) {
+            delete c;
+            return set_error(VLB_EINVAL, "instance %d: kernel %d (0 auto, 1 velocity tiles, 2 population; the "
+                             "population kernel runs in FP64)", i, d.kernel);
+        }
         const AxisTables* a1 = get_axis(d.ax1);
         const AxisTables* a2 = get_axis(d.ax2);
         if (!a1 || !a2) {
@@ -154,9 +159,15 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
             return set_error(VLB_EINVAL, "instance %d: velocity set construction failed", i);
         }
         const int n1 = a1->nodes, n2 = a2->nodes, NV = n1 * n2, NL = d.N_lambda, NX = d.N_xi;
-        // velocity tiles of 16 x 16: at most two along one axis, not both
+        // velocity tiles of 16 x 16: at most two along one axis, not both.  The population
+        // kernel (a block per cell, a thread per velocity) takes the Cartesian split, FP64
+        // sets that fill less than half of their tiles (e.g. 5 p^xi nodes) or need more
+        // tiles, and any FP64 set on request
         const int T1 = (n1 + 15) / 16, T2 = (n2 + 15) / 16;
-        if (d.cartesian ? NV > kMaxNV : T1 * T2 > 2) {
+        const bool tiles_ok = T1 * T2 <= 2;
+        const bool pop = d.cartesian || d.kernel == 2 ||
+                         (d.kernel == 0 && precision == VLB_FP64 && (!tiles_ok || NV < 128 * T1 * T2));
+        if (pop ? NV > kMaxNV : !tiles_ok) {
             delete c;
             return set_error(VLB_EINVAL,
                              "instance %d: %d x %d velocities exceed the kernel limits (16-node tiles: 1 x 1, 2 x 1 "
@@ -383,9 +394,9 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
             return set_error(VLB_EUNSTABLE, "instance %d: dt=%g exceeds the stability limit %g", i, dt, 1.0 / inv1);
         }
         D.dt = dt;
-        if (d.cartesian) {
-            c->clb_ilist.push_back(i);
-            c->clb_base.push_back(c->clb_base.back() + (long long)NX * NL);
+        if (pop) {
+            c->pop_ilist.push_back(i);
+            c->pop_base.push_back(c->pop_base.back() + (long long)NX * NL);
         } else {
             auto it = std::find_if(c->groups.begin(), c->groups.end(),
                                    [&](const vlb_channel::Group& g) { return g.T1 == T1 && g.T2 == T2; });
@@ -416,9 +427,9 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         c->threads = std::max(c->threads, (NV + kWave - 1) / kWave * kWave);
     }
     c->cbase.push_back(cells);
-    if (c->clb_base.back() * 256 >= (1LL << 32)) {   // Cartesian-split blocks of 256 threads
+    if (c->pop_base.back() * 256 >= (1LL << 32)) {   // population-kernel blocks of 256 threads
         delete c;
-        return set_error(VLB_EINVAL, "batch too large for one Cartesian-split launch (%lld cells)", c->clb_base.back());
+        return set_error(VLB_EINVAL, "batch too large for one population-kernel launch (%lld cells)", c->pop_base.back());
     }
     for (const auto& g : c->groups)   // one dispatch covers fewer than 2^32 work-items
         if (std::max(g.base.back(), g.bbase.back()) * kChanWaves * kWave >= (1LL << 32)) {
@@ -447,8 +458,8 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         g.off_bbase = off; off = al256(off + g.bbase.size() * sizeof(long long));
     }
     c->off_cbase = off; off = al256(off + (B + 1) * sizeof(long long));
-    c->off_clb_ilist = off; off = al256(off + c->clb_ilist.size() * sizeof(int));
-    c->off_clb_base = off; off = al256(off + c->clb_base.size() * sizeof(long long));
+    c->off_pop_ilist = off; off = al256(off + c->pop_ilist.size() * sizeof(int));
+    c->off_pop_base = off; off = al256(off + c->pop_base.size() * sizeof(long long));
     c->total = off;
     void* p = nullptr;
     if (hipMalloc(&p, c->total) != hipSuccess) {
@@ -481,11 +492,11 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->dcbase(), c->cbase.data(), (B + 1) * sizeof(long long), hipMemcpyHostToDevice,
                            c->stream);
-    if (e == hipSuccess && !c->clb_ilist.empty())
-        e = hipMemcpyAsync(c->ws + c->off_clb_ilist, c->clb_ilist.data(), c->clb_ilist.size() * sizeof(int),
+    if (e == hipSuccess && !c->pop_ilist.empty())
+        e = hipMemcpyAsync(c->ws + c->off_pop_ilist, c->pop_ilist.data(), c->pop_ilist.size() * sizeof(int),
                            hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess && !c->clb_ilist.empty())
-        e = hipMemcpyAsync(c->ws + c->off_clb_base, c->clb_base.data(), c->clb_base.size() * sizeof(long long),
+    if (e == hipSuccess && !c->pop_ilist.empty())
+        e = hipMemcpyAsync(c->ws + c->off_pop_base, c->pop_base.data(), c->pop_base.size() * sizeof(long long),
                            hipMemcpyHostToDevice, c->stream);
     // rest state n = 1, u = 0, T = T_w, written on the device
     if (e == hipSuccess)
@@ -617,11 +628,11 @@ vlb_status channel_stage(vlb_channel* c, int stage, bool last, bool l_only) {
         A.base = c->gbbase(g);
         VLB_HIP_TRY(launch_channel_stage(f32 ? 1 : 0, g.T1, g.T2, 1, g.bbase.back(), c->stream, A));
     }
-    if (!c->clb_ilist.empty()) {   // Cartesian-split instances (FP64 only)
-        A.ilist = (const int*)(c->ws + c->off_clb_ilist);
-        A.B = (int)c->clb_ilist.size();
-        A.base = (const long long*)(c->ws + c->off_clb_base);
-        VLB_HIP_TRY(launch_clb_stage(c->clb_base.back(), c->stream, A));
+    if (!c->pop_ilist.empty()) {   // population-kernel instances (FP64 only)
+        A.ilist = (const int*)(c->ws + c->off_pop_ilist);
+        A.B = (int)c->pop_ilist.size();
+        A.base = (const long long*)(c->ws + c->off_pop_base);
+        VLB_HIP_TRY(launch_pop_stage(c->pop_base.back(), c->stream, A));
     }
     return VLB_OK;
 }

@@ -703,22 +703,32 @@ __global__ __launch_bounds__(64) void channel_fields(const ChanDesc* inst, const
     }
 }
 
-// ---------------------------------------------------------------- Cartesian-split stage
-// Cartesian-split channel (Sec. VI.G, Eq. canalie_coord_beq_cons), FP64: the momentum
-// axes are p^x (across, ax1) and p^y (along, ax2); no force terms; the advection
-// velocities V^lambda = (p^x - lambda a_p p^y) / (1 + phi_p) at the lambda faces, with the
-// discrete metric a_p = (1 + phi_p)(phi_{p+1/2} - phi_{p-1/2}) / dchi_p (free-stream
-// preserving), and V^xi = (1 + phi) p^y at the xi faces.  A population is wall-bound or
-// emitted by the sign of V^lambda at the wall face; n_w by Eq. canalie_coord_nw.  The half
-// channel mirrors p^x at the centreline; flow-rate ends take the Cartesian profile velocity
-// (0, Q_s) and n_s from the row balance.  One block of kClbThreads threads per cell, each
-// thread taking the velocities k = threadIdx.x + j kClbThreads; the block sums its cell's
-// moments itself.
-constexpr int kClbThreads = 256;
-__global__ __launch_bounds__(kClbThreads) void clb_stage(ChanArgs A) {
+// ---------------------------------------------------------------- population kernel
+// Channel stage with a block per cell and a thread per velocity (FP64), for both momentum
+// forms.  The block sums its cell's moments itself, builds the equilibrium factors in
+// LDS, finds n_w of the column's walls and the flow-rate densities of its row when its
+// stencil reaches them, then per population: the four WENO faces with wall, centreline
+// and end ghosts, the flux difference, the force (vielbein form), BGK, the RK combine.
+//   vielbein (Sec. VI.A-C): V^lambda = (face factor) p^lambda from the per-cell tables,
+//     V^xi = c_f (p^xi - a_f p^lambda) at the xi faces, the four projected derivatives
+//     Gamma_lxx [(p^xi)^2 K1 F - p^lambda Kt2 F] - Gamma_lxl [(p^lambda)^2 K2 F - p^xi Kt1 F]
+//     as dot products over the cell's populations staged in LDS -- the form for velocity
+//     sets too sparse for the 16 x 16 tiles of channel_stage (e.g. 5 p^xi nodes);
+//   Cartesian split (Sec. VI.G, Eq. canalie_coord_beq_cons): axes p^x / p^y, no force,
+//     V^lambda = (p^x - lambda a_p p^y) / (1 + phi_p) with the discrete metric
+//     a_p = (1 + phi_p)(phi_{p+1/2} - phi_{p-1/2}) / dchi_p (free-stream preserving),
+//     V^xi = (1 + phi) p^y; walls by the sign of V^lambda at the wall face
+//     (Eq. canalie_coord_nw); flow-rate ends with the Cartesian profile velocity (0, Q_s).
+// A population is wall-bound or emitted by the sign of V^lambda at the wall face (for the
+// vielbein form the sign of p^lambda; the positive face factor cancels in n_w).  The half
+// channel mirrors the ax1 momentum at the centreline.  Each thread takes the velocities
+// k = threadIdx.x + j kPopThreads.
+constexpr int kPopThreads = 256;
+__global__ __launch_bounds__(kPopThreads) void pop_stage(ChanArgs A) {
     __shared__ double sh[16 * 5];
     __shared__ double ec[4 * (kMaxN + 1)];
     __shared__ double gq[4 * kMaxQ];   // g(p) of the nodes of both axes
+    __shared__ double fl[2 * kMaxNV];  // the cell's populations (vielbein force contractions)
     const long long b = blockIdx.x;
     const int gi = find_instance(A.base, A.B, b);
     const ChanDesc& I = A.inst[A.ilist[gi]];
@@ -734,7 +744,7 @@ __global__ __launch_bounds__(kClbThreads) void clb_stage(ChanArgs A) {
 
     // moments of the cell (Sec. IV.A) and the relaxation time
     double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int k = threadIdx.x; k < NV; k += kClbThreads) {
+    for (int k = threadIdx.x; k < NV; k += kPopThreads) {
         const double px = pxk(k), py = pyk(k), f0 = at(0, p, s, k);
         m[0] += f0;
         m[1] += px * f0;
@@ -752,8 +762,11 @@ __global__ __launch_bounds__(kClbThreads) void clb_stage(ChanArgs A) {
         axis_coef_side(ax ? I.kind2 : I.kind1, N, ax ? uy : ux, T, tab + (ax ? I.tC2 : I.tC1),
                        tab + (ax ? I.tisf2 : I.tisf1), sg, ec + ax * 2 * (kMaxN + 1) + sg * (N + 1));
     }
+    const bool cart = I.cartesian != 0;
+    if (!cart)
+        for (int x = threadIdx.x; x < 2 * NV; x += kPopThreads) fl[x] = at(x >= NV, p, s, x >= NV ? x - NV : x);
     __syncthreads();
-    for (int t = threadIdx.x; t < Q1 + Q2; t += kClbThreads) {
+    for (int t = threadIdx.x; t < Q1 + Q2; t += kPopThreads) {
         const bool ax1 = t < Q1;
         const int node = ax1 ? t : t - Q1, N = ax1 ? N1 : N2;
         const bool minus = ax1 ? (I.kind1 == 1 && node >= I.Qh1) : (I.kind2 == 1 && node >= I.Qh2);
@@ -769,17 +782,27 @@ __global__ __launch_bounds__(kClbThreads) void clb_stage(ChanArgs A) {
     const double* geo = tab + I.tgeo;
     const double inv_opf = 1.0 / (1.0 + geo[p]);
     const double* lamf = geo + 3 * NX;
-    const double am = tab[I.tclb + p];
+    const double am = cart ? tab[I.tclb + p] : 0.0;
     const double* phif = tab + I.tclb + NX;
+    const double* xc = tab + I.txc;   // vielbein: V^xi = xc (p^xi - xa p^lambda) at [xi face][row]
+    const double* xa = tab + I.txa;
+    // V^lambda at the walls (vielbein: p^lambda, whose positive face factor cancels in n_w)
+    auto vwall = [&](double px, double py, bool upper) -> double {
+        return cart ? (px + (upper ? -am : am) * py) * inv_opf : px;
+    };
+    // V^xi at xi face f of this row
+    auto vxi = [&](double px, double py, int f) -> double {
+        return cart ? (1.0 + phif[f]) * py : xc[(size_t)f * NL + s] * (py - xa[(size_t)f * NL + s] * px);
+    };
     const double* fw = tab + I.tfw;
     const double weps = I.weno_eps;
     // n_w of the walls this cell's stencil reaches (Eq. canalie_coord_nw; f' only)
     double nw_lo = 0.0, nw_hi = 0.0;
     if (s < 3 || s >= NL - 3) {
         double w[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int k = threadIdx.x; k < NV; k += kClbThreads) {
+        for (int k = threadIdx.x; k < NV; k += kPopThreads) {
             const double px = pxk(k), py = pyk(k);
-            const double vlo = (px + am * py) * inv_opf, vhi = (px - am * py) * inv_opf;   // at lambda = -1, +1
+            const double vlo = vwall(px, py, false), vhi = vwall(px, py, true);   // at lambda = -1, +1
             if (I.half) {
                 // specular centreline: no lower wall
             } else if (vlo < 0.0) {
@@ -803,10 +826,12 @@ __global__ __launch_bounds__(kClbThreads) void clb_stage(ChanArgs A) {
     double n_in = 0.0, n_out = 0.0;
     if (I.ends == 1 && (p < 3 || p >= NX - 3)) {
         double w[2] = {0.0, 0.0};
-        for (int k = threadIdx.x; k < NV; k += kClbThreads) {
-            const double py = pyk(k);
-            if (py <= 0.0) w[0] += at(0, 0, s, k) * py;          // leaving through the inlet face
-            if (py >= 0.0) w[1] += at(0, NX - 1, s, k) * py;     // leaving through the outlet face
+        for (int k = threadIdx.x; k < NV; k += kPopThreads) {
+            const double px = pxk(k), py = pyk(k);
+            const double vin = vxi(px, py, 0), vout = vxi(px, py, NX);
+            // leaving populations carry p^y = V^xi / (1 + phi) through the end faces
+            if (vin <= 0.0) w[0] += at(0, 0, s, k) * (vin * I.ipf_in);
+            if (vout >= 0.0) w[1] += at(0, NX - 1, s, k) * (vout * I.ipf_out);
         }
         block_sums<2>(w, sh);
         n_in = (tab[I.tQrow + s] - w[0]) / tab[I.tden + s];
@@ -819,13 +844,15 @@ __global__ __launch_bounds__(kClbThreads) void clb_stage(ChanArgs A) {
     const double* fin = tab + I.tfin;
     const double* fout = tab + I.tfout;
     const double* frow = tab + I.tfrow;
-    for (int k = threadIdx.x; k < NV; k += kClbThreads) {
+    for (int k = threadIdx.x; k < NV; k += kPopThreads) {
         const int vi = k / Q2, vj = k - vi * Q2;
         const int km = ((vi + I.Qh1) % Q1) * Q2 + vj;   // the p^x-mirrored velocity (half channel)
         const double px = tab[I.tp1 + vi], py = tab[I.tp2 + vj];
-        const double vlo = (px + am * py) * inv_opf, vhi = (px - am * py) * inv_opf;
-        const double vl = (px - lamf[s] * am * py) * inv_opf, vr = (px - lamf[s + 1] * am * py) * inv_opf;
-        const double ul = (1.0 + phif[p]) * py, ur = (1.0 + phif[p + 1]) * py;
+        const double vlo = vwall(px, py, false), vhi = vwall(px, py, true);
+        const double vl = cart ? (px - lamf[s] * am * py) * inv_opf : tab[I.tal + cell] * px;
+        const double vr = cart ? (px - lamf[s + 1] * am * py) * inv_opf : tab[I.tar + cell] * px;
+        const double ul = vxi(px, py, p), ur = vxi(px, py, p + 1);
+        const double vin = vxi(px, py, 0), vout = vxi(px, py, NX);   // end faces of this row
         const double fe1 = n * gq[vi] * gq[Q1 + vj];
         for (int d = 0; d < 2; ++d) {
             // column values with wall ghosts, row values with reservoir / flow-rate ghosts
@@ -848,10 +875,10 @@ __global__ __launch_bounds__(kClbThreads) void clb_stage(ChanArgs A) {
             auto rowv = [&](int c) -> double {
                 if (c >= 0 && c < NX) return at(d, c, s, k);
                 if (c < 0) {
-                    if (py <= 0.0) return at(d, 0, s, k);
+                    if (vin <= 0.0) return at(d, 0, s, k);
                     return I.ends == 1 ? n_in * frow[((size_t)s * 2 + d) * NV + k] : fin[d * NV + k];
                 }
-                if (py >= 0.0) return at(d, NX - 1, s, k);
+                if (vout >= 0.0) return at(d, NX - 1, s, k);
                 return I.ends == 1 ? n_out * frow[((size_t)(NL + s) * 2 + d) * NV + k] : fout[d * NV + k];
             };
             // the two directions one after the other (seven stencil values live at a time)
@@ -861,10 +888,30 @@ __global__ __launch_bounds__(kClbThreads) void clb_stage(ChanArgs A) {
             double adv = (vr * weno_face<double>(vr > 0.0, w[1], w[2], w[3], w[4], w[5], w[6], weps) -
                           vl * weno_face<double>(vl > 0.0, w[0], w[1], w[2], w[3], w[4], w[5], weps)) / dlam;
             for (int q = 0; q < 7; ++q) w[q] = rowv(p - 3 + q);
-            adv += (ur * weno_face<double>(py > 0.0, w[1], w[2], w[3], w[4], w[5], w[6], weps) -
-                    ul * weno_face<double>(py > 0.0, w[0], w[1], w[2], w[3], w[4], w[5], weps)) / dchi;
+            adv += (ur * weno_face<double>(ur > 0.0, w[1], w[2], w[3], w[4], w[5], w[6], weps) -
+                    ul * weno_face<double>(ul > 0.0, w[0], w[1], w[2], w[3], w[4], w[5], weps)) / dchi;
+            double force = 0.0;
+            if (!cart) {   // projected momentum derivatives of the two connection terms
+                const double* Fd = fl + d * NV;
+                const double* K1 = tab + I.tK1 + (size_t)vi * Q1;
+                const double* Kt1 = tab + I.tKt1 + (size_t)vi * Q1;
+                const double* K2 = tab + I.tK2 + (size_t)vj * Q2;
+                const double* Kt2 = tab + I.tKt2 + (size_t)vj * Q2;
+                double k1 = 0.0, kt1 = 0.0, k2 = 0.0, kt2 = 0.0;
+                for (int ip = 0; ip < Q1; ++ip) {
+                    const double f = Fd[ip * Q2 + vj];
+                    k1 += K1[ip] * f;
+                    kt1 += Kt1[ip] * f;
+                }
+                for (int jp = 0; jp < Q2; ++jp) {
+                    const double f = Fd[vi * Q2 + jp];
+                    k2 += K2[jp] * f;
+                    kt2 += Kt2[jp] * f;
+                }
+                force = tab[I.tglxx + cell] * (py * py * k1 - px * kt2) - tab[I.tglxl + cell] * (px * px * k2 - py * kt1);
+            }
             const double fe = d ? T * fe1 : fe1;
-            const double L = -adv - (fc - fe) * itau;
+            const double L = -adv + force - (fc - fe) * itau;
             const size_t o = d * dsz + (size_t)cell * NV + k;
             double out;
             if (A.l_only) {
@@ -954,9 +1001,9 @@ hipError_t launch_channel_fields(int NX, hipStream_t st, const ChanDesc* inst, c
     return hipGetLastError();
 }
 
-hipError_t launch_clb_stage(long long ncells, hipStream_t st, const ChanArgs& A) {
+hipError_t launch_pop_stage(long long ncells, hipStream_t st, const ChanArgs& A) {
     if (ncells == 0) return hipSuccess;
-    hipLaunchKernelGGL(clb_stage, dim3((unsigned)ncells), dim3(kClbThreads), 0, st, A);
+    hipLaunchKernelGGL(pop_stage, dim3((unsigned)ncells), dim3(kPopThreads), 0, st, A);
     return hipGetLastError();
 }
 

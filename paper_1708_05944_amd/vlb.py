@@ -79,7 +79,7 @@ class _ChannelDesc(ctypes.Structure):
                 ("cfl", ctypes.c_double), ("n_in", ctypes.c_double), ("n_out", ctypes.c_double),
                 ("T_w", ctypes.c_double), ("weno_eps", ctypes.c_double),
                 ("half", ctypes.c_int), ("ends", ctypes.c_int), ("Q0", ctypes.c_double),
-                ("cartesian", ctypes.c_int), ("A", ctypes.c_double)]
+                ("cartesian", ctypes.c_int), ("A", ctypes.c_double), ("kernel", ctypes.c_int)]
 
 
 @dataclass
@@ -109,12 +109,13 @@ class ChannelDesc:
     Q0: float = 0.0
     cartesian: bool = False   # Cartesian-split momentum space (Sec. VI.G)
     A: float = 0.0            # lambda stretching towards the walls (Eq. canalie_stretch); 0 = equal cells
+    kernel: int = 0           # 0 automatic, 1 velocity tiles (matrix cores), 2 population kernel (FP64)
 
     def _c(self) -> _ChannelDesc:
         return _ChannelDesc(self.N_lambda, self.N_xi, self.xi_in, self.xi_out, self.r, self.L, _Axis(*self.ax1),
                             _Axis(*self.ax2), self.Kn, self.tau_model, self.dt, self.cfl, self.n_in, self.n_out,
                             self.T_w, self.weno_eps, int(bool(self.half)), int(self.ends), float(self.Q0),
-                            int(bool(self.cartesian)), float(self.A))
+                            int(bool(self.cartesian)), float(self.A), int(self.kernel))
 _SIGS = {
     "vlb_batch_create_couette": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(_CouetteDesc),
                                  ctypes.c_int, ctypes.c_void_p, ctypes.c_int],

@@ -56,11 +56,15 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("kernel", [1, 2])
 @pytest.mark.parametrize("case", CASES)
-def test_channel_operator_matches_oracle(case):
+def test_channel_operator_matches_oracle(case, kernel):
+    """Both FP64 kernels on every case: the velocity tiles on the matrix cores (1) and the
+    population kernel (2)."""
     from paper_1708_05944_amd import Channel
-    _say(f"case {case}")
+    _say(f"case {case}, kernel {kernel}")
     o, d = _pair(**dict(case))
+    d.kernel = kernel
     c = Channel([d])
     F = _perturbed(o, 5)
     c.set_state(F.ravel())
@@ -267,3 +271,26 @@ def test_channel_step_graphs_are_bitwise_identical():
             assert np.array_equal(a.residual(), b.residual())
         a.close()
         b.close()
+
+
+def test_population_kernel_takes_sets_beyond_two_tiles():
+    """HH(4;24) x H(4;5): 48 x 5 nodes need three 16-node tiles along p^lambda, which the
+    tile kernel does not take; the automatic choice runs it on the population kernel
+    (FP64) -- operator and three steps against the oracle, in the expansion with the
+    paper's half channel, flow-rate ends and stretched lambda."""
+    from paper_1708_05944_amd import Channel
+    kw = dict(N_lambda=6, N_xi=9, ax1=(1, 24, 4), ax2=(0, 5, 4), Kn=0.2, r=2.0, L=2.0, xi_in=-1.0, xi_out=3.0,
+              half=True, ends=1, Q0=0.1, A=0.95)
+    o, d = _pair(**dict(kw))
+    c = Channel([d])
+    F = _perturbed(o, 13)
+    c.set_state(F.ravel())
+    err = _relerr(c.instance_view(c.apply_L(), 0), o.L(F)[0])
+    _say(f"L rel err {err:.2e}")
+    assert err <= TOL
+    c.set_state(F.ravel())
+    c.step(3)
+    err = _relerr(c.instance_view(c.get_state(), 0), o.step(F, c.info[0]["dt"], 3))
+    _say(f"3 steps rel err {err:.2e}")
+    assert err <= TOL
+    c.close()

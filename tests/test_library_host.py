@@ -65,7 +65,10 @@ def _channel_create_status(**kw):
     (dict(N_lambda=8, N_xi=8, xi_in=3.0, xi_out=1.0), "invalid channel descriptor"),
     (dict(N_lambda=8, N_xi=8, tau_model=3), "invalid channel descriptor"),
     (dict(N_lambda=8, N_xi=8, weno_eps=-1.0), "invalid channel descriptor"),
-    (dict(N_lambda=8, N_xi=8, ax1=(1, 20, 4), ax2=(0, 20, 4)), "exceed the kernel limits"),   # 40 x 20 nodes
+    (dict(N_lambda=8, N_xi=8, ax1=(1, 20, 4), ax2=(0, 20, 4), kernel=1), "exceed the kernel limits"),  # 40 x 20 tiles
+    (dict(N_lambda=8, N_xi=8, ax1=(1, 24, 4), ax2=(0, 24, 4)), "exceed the kernel limits"),   # 1152 velocities
+    (dict(N_lambda=8, N_xi=8, kernel=2, precision=1), "population kernel runs in FP64"),
+    (dict(N_lambda=8, N_xi=8, kernel=3), "kernel 3"),
     (dict(N_lambda=8, N_xi=8, precision=7), "unsupported precision"),
     (dict(N_lambda=8, N_xi=8, cartesian=True, precision=1), "Cartesian-split"),    # FP64 only
     (dict(N_lambda=8, N_xi=8, A=1.0), "invalid channel descriptor"),                # stretching 0 <= A < 1
