@@ -34,9 +34,11 @@ struct vlb_channel {
         size_t off_ilist, off_base, off_bbase;
     };
     std::vector<Group> groups;
-    std::vector<int> pop_ilist;           // instances of the population kernel: one launch, a block per cell
-    std::vector<long long> pop_base{0};
-    size_t off_pop_ilist = 0, off_pop_base = 0;
+    // instances of the population kernel, [0] vielbein and [1] Cartesian split: one launch
+    // each, a block per cell
+    std::vector<int> pop_ilist[2];
+    std::vector<long long> pop_base[2] = {{0}, {0}};
+    size_t off_pop_ilist[2] = {0, 0}, off_pop_base[2] = {0, 0};
     size_t state_n = 0, ncells = 0;
     int threads = 64;
     int precision = VLB_FP64;
@@ -161,12 +163,11 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         const int n1 = a1->nodes, n2 = a2->nodes, NV = n1 * n2, NL = d.N_lambda, NX = d.N_xi;
         // velocity tiles of 16 x 16: at most two along one axis, not both.  The population
         // kernel (a block per cell, a thread per velocity) takes the Cartesian split, FP64
-        // sets that fill less than half of their tiles (e.g. 5 p^xi nodes) or need more
-        // tiles, and any FP64 set on request
+        // sets that need more tiles, and any FP64 set on request (measured slower than the
+        // tiles wherever both apply: at 40..160 velocities most of its 256 threads idle)
         const int T1 = (n1 + 15) / 16, T2 = (n2 + 15) / 16;
         const bool tiles_ok = T1 * T2 <= 2;
-        const bool pop = d.cartesian || d.kernel == 2 ||
-                         (d.kernel == 0 && precision == VLB_FP64 && (!tiles_ok || NV < 128 * T1 * T2));
+        const bool pop = d.cartesian || d.kernel == 2 || (d.kernel == 0 && precision == VLB_FP64 && !tiles_ok);
         if (pop ? NV > kMaxNV : !tiles_ok) {
             delete c;
             return set_error(VLB_EINVAL,
@@ -395,8 +396,9 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         }
         D.dt = dt;
         if (pop) {
-            c->pop_ilist.push_back(i);
-            c->pop_base.push_back(c->pop_base.back() + (long long)NX * NL);
+            const int fm = d.cartesian ? 1 : 0;
+            c->pop_ilist[fm].push_back(i);
+            c->pop_base[fm].push_back(c->pop_base[fm].back() + (long long)NX * NL);
         } else {
             auto it = std::find_if(c->groups.begin(), c->groups.end(),
                                    [&](const vlb_channel::Group& g) { return g.T1 == T1 && g.T2 == T2; });
@@ -427,9 +429,9 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         c->threads = std::max(c->threads, (NV + kWave - 1) / kWave * kWave);
     }
     c->cbase.push_back(cells);
-    if (c->pop_base.back() * 256 >= (1LL << 32)) {   // population-kernel blocks of 256 threads
+    if (std::max(c->pop_base[0].back(), c->pop_base[1].back()) * 256 >= (1LL << 32)) {   // blocks of 256 threads
         delete c;
-        return set_error(VLB_EINVAL, "batch too large for one population-kernel launch (%lld cells)", c->pop_base.back());
+        return set_error(VLB_EINVAL, "batch too large for one population-kernel launch");
     }
     for (const auto& g : c->groups)   // one dispatch covers fewer than 2^32 work-items
         if (std::max(g.base.back(), g.bbase.back()) * kChanWaves * kWave >= (1LL << 32)) {
@@ -458,8 +460,10 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         g.off_bbase = off; off = al256(off + g.bbase.size() * sizeof(long long));
     }
     c->off_cbase = off; off = al256(off + (B + 1) * sizeof(long long));
-    c->off_pop_ilist = off; off = al256(off + c->pop_ilist.size() * sizeof(int));
-    c->off_pop_base = off; off = al256(off + c->pop_base.size() * sizeof(long long));
+    for (int fm = 0; fm < 2; ++fm) {
+        c->off_pop_ilist[fm] = off; off = al256(off + c->pop_ilist[fm].size() * sizeof(int));
+        c->off_pop_base[fm] = off; off = al256(off + c->pop_base[fm].size() * sizeof(long long));
+    }
     c->total = off;
     void* p = nullptr;
     if (hipMalloc(&p, c->total) != hipSuccess) {
@@ -492,12 +496,14 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->dcbase(), c->cbase.data(), (B + 1) * sizeof(long long), hipMemcpyHostToDevice,
                            c->stream);
-    if (e == hipSuccess && !c->pop_ilist.empty())
-        e = hipMemcpyAsync(c->ws + c->off_pop_ilist, c->pop_ilist.data(), c->pop_ilist.size() * sizeof(int),
-                           hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess && !c->pop_ilist.empty())
-        e = hipMemcpyAsync(c->ws + c->off_pop_base, c->pop_base.data(), c->pop_base.size() * sizeof(long long),
-                           hipMemcpyHostToDevice, c->stream);
+    for (int fm = 0; fm < 2; ++fm) {
+        if (e == hipSuccess && !c->pop_ilist[fm].empty())
+            e = hipMemcpyAsync(c->ws + c->off_pop_ilist[fm], c->pop_ilist[fm].data(),
+                               c->pop_ilist[fm].size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess && !c->pop_ilist[fm].empty())
+            e = hipMemcpyAsync(c->ws + c->off_pop_base[fm], c->pop_base[fm].data(),
+                               c->pop_base[fm].size() * sizeof(long long), hipMemcpyHostToDevice, c->stream);
+    }
     // rest state n = 1, u = 0, T = T_w, written on the device
     if (e == hipSuccess)
         e = launch_channel_rest((long long)c->state_n, c->stream, c->ddesc(), c->dsbase(), B, c->dtab(), c->F(0));
@@ -628,12 +634,13 @@ vlb_status channel_stage(vlb_channel* c, int stage, bool last, bool l_only) {
         A.base = c->gbbase(g);
         VLB_HIP_TRY(launch_channel_stage(f32 ? 1 : 0, g.T1, g.T2, 1, g.bbase.back(), c->stream, A));
     }
-    if (!c->pop_ilist.empty()) {   // population-kernel instances (FP64 only)
-        A.ilist = (const int*)(c->ws + c->off_pop_ilist);
-        A.B = (int)c->pop_ilist.size();
-        A.base = (const long long*)(c->ws + c->off_pop_base);
-        VLB_HIP_TRY(launch_pop_stage(c->pop_base.back(), c->stream, A));
-    }
+    for (int fm = 0; fm < 2; ++fm)   // population-kernel instances (FP64 only), per momentum form
+        if (!c->pop_ilist[fm].empty()) {
+            A.ilist = (const int*)(c->ws + c->off_pop_ilist[fm]);
+            A.B = (int)c->pop_ilist[fm].size();
+            A.base = (const long long*)(c->ws + c->off_pop_base[fm]);
+            VLB_HIP_TRY(launch_pop_stage(fm, c->pop_base[fm].back(), c->stream, A));
+        }
     return VLB_OK;
 }
 

@@ -66,9 +66,10 @@ hipError_t launch_channel_reduce(int ninst, hipStream_t st, const ChanDesc* inst
                                  const double* rpart, double* resid);
 hipError_t launch_channel_diag(long long ncells_total, int threads, hipStream_t st, const ChanDesc* insts,
                                const long long* cbase, int B, const double* tab, const double* F, double* diag);
-// Population-kernel stage (FP64; vielbein or Cartesian-split instances): one block of 256
-// threads per cell of the listed instances (A.ilist / A.base count cells)
-hipError_t launch_pop_stage(long long ncells, hipStream_t st, const ChanArgs& A);
+// Population-kernel stage (FP64): one block of 256 threads per cell of the listed
+// instances (A.ilist / A.base count cells), all vielbein (cartesian = 0) or all
+// Cartesian-split (cartesian = 1)
+hipError_t launch_pop_stage(int cartesian, long long ncells, hipStream_t st, const ChanArgs& A);
 // flow diagnostics of the instance *inst (NX columns) from diag: out = ux, uy, P, omega
 // [NX][NL] each, psi [NX][NL + 1], Pw [2][NX]
 hipError_t launch_channel_fields(int NX, hipStream_t st, const ChanDesc* inst, const double* tab, const double* diag,

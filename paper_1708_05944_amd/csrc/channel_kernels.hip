@@ -724,6 +724,7 @@ __global__ __launch_bounds__(64) void channel_fields(const ChanDesc* inst, const
 // channel mirrors the ax1 momentum at the centreline.  Each thread takes the velocities
 // k = threadIdx.x + j kPopThreads.
 constexpr int kPopThreads = 256;
+template <bool CART>   // the momentum form of every listed instance
 __global__ __launch_bounds__(kPopThreads) void pop_stage(ChanArgs A) {
     __shared__ double sh[16 * 5];
     __shared__ double ec[4 * (kMaxN + 1)];
@@ -762,7 +763,7 @@ __global__ __launch_bounds__(kPopThreads) void pop_stage(ChanArgs A) {
         axis_coef_side(ax ? I.kind2 : I.kind1, N, ax ? uy : ux, T, tab + (ax ? I.tC2 : I.tC1),
                        tab + (ax ? I.tisf2 : I.tisf1), sg, ec + ax * 2 * (kMaxN + 1) + sg * (N + 1));
     }
-    const bool cart = I.cartesian != 0;
+    constexpr bool cart = CART;
     if (!cart)
         for (int x = threadIdx.x; x < 2 * NV; x += kPopThreads) fl[x] = at(x >= NV, p, s, x >= NV ? x - NV : x);
     __syncthreads();
@@ -1001,9 +1002,10 @@ hipError_t launch_channel_fields(int NX, hipStream_t st, const ChanDesc* inst, c
     return hipGetLastError();
 }
 
-hipError_t launch_pop_stage(long long ncells, hipStream_t st, const ChanArgs& A) {
+hipError_t launch_pop_stage(int cartesian, long long ncells, hipStream_t st, const ChanArgs& A) {
     if (ncells == 0) return hipSuccess;
-    hipLaunchKernelGGL(pop_stage, dim3((unsigned)ncells), dim3(kPopThreads), 0, st, A);
+    if (cartesian) hipLaunchKernelGGL(pop_stage<true>, dim3((unsigned)ncells), dim3(kPopThreads), 0, st, A);
+    else hipLaunchKernelGGL(pop_stage<false>, dim3((unsigned)ncells), dim3(kPopThreads), 0, st, A);
     return hipGetLastError();
 }
 
