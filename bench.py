@@ -53,6 +53,27 @@ def channel_stage_flops(cells: int, q1: int, q2: int) -> float:
     return cells * q1 * q2 * (2 * (4 * 54 + 4 * (q1 + q2) + 18) + 13)
 
 
+def roofline(kernel: str, ms: float, alg_bytes: float, alg_flops: float, peak_tflops: float, traffic, **extra):
+    """Roofline record of one launch of `kernel`: algorithmic bytes and flops per launch over
+    its mean duration.  The bound is the ceiling the kernel's arithmetic intensity reaches
+    first: ALU above the ridge (peak flop rate / HBM bandwidth), HBM below it; the other
+    ceiling is reported beside it."""
+    gbs = alg_bytes / (ms * 1e-3) / 1e9
+    tfs = alg_flops / (ms * 1e-3) / 1e12
+    ridge = peak_tflops * 1e3 / HBM_PEAK_GBS
+    intensity = alg_flops / alg_bytes
+    hbm = {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+           "alg_bytes_per_launch": alg_bytes}
+    alu = {"achieved": tfs, "peak": peak_tflops, "unit": "TFLOP/s", "frac": tfs / peak_tflops,
+           "alg_flops_per_launch": alg_flops}
+    main, bound = (alu, "alu") if intensity > ridge else (hbm, "hbm")
+    rec = {"bound": bound, "achieved": main["achieved"], "peak": main["peak"], "unit": main["unit"],
+           "frac": main["frac"], "traffic": traffic, "kernel": kernel, "avg_launch_ms": ms,
+           "intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge, "hbm": hbm, "alu": alu}
+    rec.update(extra)
+    return rec
+
+
 def measured_traffic(*kernels: str):
     """HBM bytes per launch (summed over the named kernels, which together make one
     launch of the timed unit) from the committed FETCH_SIZE / WRITE_SIZE profile, or None
@@ -180,12 +201,14 @@ def main():
 
     fp64 = measure(0)
     mixed = measure(VLB_MIXED)
-    dom = mixed["dom"]
-    achieved = dom["alg_bytes"] / (dom["total_ms"] * 1e-3) / 1e9
-    dom64 = fp64["dom"]
-    achieved64 = dom64["alg_bytes"] / (dom64["total_ms"] * 1e-3) / 1e9
-    flops_launch = stage_flops(descs)
-    alu = flops_launch / (dom["total_ms"] / dom["launches"] * 1e-3) / 1e12
+    dom, dom64 = mixed["dom"], fp64["dom"]
+    couette_flops_launch = stage_flops(descs)
+    roof = roofline("couette_stage<float>", dom["total_ms"] / dom["launches"], dom["alg_bytes"] / dom["launches"],
+                    couette_flops_launch, VALU_FP32_TFLOPS, measured_traffic("couette_stage<float>"),
+                    launches=dom["launches"])
+    roof64 = roofline("couette_stage<double>", dom64["total_ms"] / dom64["launches"],
+                      dom64["alg_bytes"] / dom64["launches"], couette_flops_launch, VALU_FP64_TFLOPS,
+                      measured_traffic("couette_stage<double>"), launches=dom64["launches"])
 
     # time to steady state (r < 1e-10) of the single-instance workload, FP64 vs mixed
     tts = {}
@@ -211,7 +234,7 @@ def main():
         cd = ChannelDesc(N_lambda=128, N_xi=512, xi_in=-4.0, xi_out=12.0, r=2.0, L=4.0, ax1=(1, 8, 4),
                          ax2=(0, 16, 4), Kn=0.05, tau_model=1, n_in=1.1, n_out=0.9, T_w=1.0)
         sv = cd.N_lambda * cd.N_xi * 16 * 16
-        flops_launch = channel_stage_flops(cd.N_lambda * cd.N_xi, 16, 16)
+        ch_flops_launch = channel_stage_flops(cd.N_lambda * cd.N_xi, 16, 16)
 
         def channel_leg(precision, elem_bytes, tname, peak_tf):
             # one RK3 stage = the interior launch and the edge-band launch
@@ -234,16 +257,10 @@ def main():
             dt = ch.info[0]["dt"]
             ch.close()
             bytes_launch = sv * 16 * elem_bytes / 3      # read F, F_n in 2 of 3 stages, write
-            gbs = bytes_launch / (stage_ms * 1e-3) / 1e9
-            tfs = flops_launch / (stage_ms * 1e-3) / 1e12
             return {"value": sv * nst / el, "unit": "site-velocity updates/s", "ms_per_step": el / nst * 1e3,
                     "steps": nst, "dt": dt,
-                    "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                 "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(*kernels),
-                                 "kernel": " + ".join(kernels),
-                                 "avg_launch_ms": stage_ms, "alg_bytes_per_launch": bytes_launch,
-                                 "alu": {"achieved_TFLOPs": tfs, "peak_TFLOPs": peak_tf, "frac": tfs / peak_tf,
-                                         "alg_flops_per_launch": flops_launch}}}
+                    "roofline": roofline(" + ".join(kernels), stage_ms, bytes_launch, ch_flops_launch, peak_tf,
+                                         measured_traffic(*kernels))}
 
         mixed_ch = channel_leg(VLB_MIXED, 4, "float", VALU_FP32_TFLOPS)
         fp64_ch = channel_leg(0, 8, "double", VALU_FP64_TFLOPS)
@@ -356,18 +373,9 @@ def main():
                                "Kn 0.01-10; FP32 stage kernels with FP64 moment/wall/residual sums",
                    "instances": len(descs), "site_velocities_per_step": updates_per_step,
                    "cells_per_run": mixed["tile"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("couette_stage<float>"),
-                     "kernel": "couette_stage<float>", "launches": dom["launches"],
-                     "avg_launch_ms": dom["total_ms"] / dom["launches"],
-                     "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"],
-                     "alu": {"achieved_TFLOPs": alu, "peak_TFLOPs": VALU_FP32_TFLOPS, "frac": alu / VALU_FP32_TFLOPS,
-                             "alg_flops_per_launch": flops_launch}},
-        "fp64": {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"], "kernel": "couette_stage<double>",
-                 "cells_per_run": fp64["tile"],
-                 "achieved_GBps": achieved64, "frac": achieved64 / HBM_PEAK_GBS,
-                 "traffic": measured_traffic("couette_stage<double>"),
-                 "avg_launch_ms": dom64["total_ms"] / dom64["launches"]},
+        "roofline": roof,
+        "fp64": {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"], "cells_per_run": fp64["tile"],
+                 "roofline": roof64},
         "time_to_steady_state_single": tts,
         "time_to_steady_state_warm_start": warm,
         "channel": channel,
