@@ -57,6 +57,48 @@ __device__ __forceinline__ double dot_lds<double>(const double* a, const double*
     return acc;
 }
 
+// The two contractions of the force term, sum_i a1[i] b1[i] (i < n1) and sum_i a2[i] b2[i]
+// (i < n2), each in index order exactly as dot_lds; over the common length the reads of
+// both are issued together, so that one LDS round trip serves both (FP32 kernel; the FP64
+// kernel has no registers to spare and calls dot_lds twice).
+__device__ __forceinline__ void dot2_lds(const float* a1, const float* b1, int n1, const float* a2,
+                                         const float* b2, int n2, float& r1, float& r2) {
+    float acc1 = 0.f, acc2 = 0.f;
+    const int nc = n1 < n2 ? n1 : n2;
+    int i = 0;
+#pragma unroll 1
+    for (; i < nc; i += 4) {
+        const float4 x1 = *reinterpret_cast<const float4*>(a1 + i), y1 = *reinterpret_cast<const float4*>(b1 + i);
+        const float4 x2 = *reinterpret_cast<const float4*>(a2 + i), y2 = *reinterpret_cast<const float4*>(b2 + i);
+        acc1 += x1.x * y1.x;
+        acc1 += x1.y * y1.y;
+        acc1 += x1.z * y1.z;
+        acc1 += x1.w * y1.w;
+        acc2 += x2.x * y2.x;
+        acc2 += x2.y * y2.y;
+        acc2 += x2.z * y2.z;
+        acc2 += x2.w * y2.w;
+    }
+#pragma unroll 1
+    for (int j = i; j < n1; j += 4) {
+        const float4 x = *reinterpret_cast<const float4*>(a1 + j), y = *reinterpret_cast<const float4*>(b1 + j);
+        acc1 += x.x * y.x;
+        acc1 += x.y * y.y;
+        acc1 += x.z * y.z;
+        acc1 += x.w * y.w;
+    }
+#pragma unroll 1
+    for (int j = i; j < n2; j += 4) {
+        const float4 x = *reinterpret_cast<const float4*>(a2 + j), y = *reinterpret_cast<const float4*>(b2 + j);
+        acc2 += x.x * y.x;
+        acc2 += x.y * y.y;
+        acc2 += x.z * y.z;
+        acc2 += x.w * y.w;
+    }
+    r1 = acc1;
+    r2 = acc2;
+}
+
 // LDS layout of a stage block (bytes): kernel tables | two cell-row buffers (row-major
 // and transposed copies per run) | two equilibrium-factor buffers | per (run, cell):
 // n, T, 1/tau, equilibrium coefficients and geometry | equilibrium bases | moment and
@@ -153,15 +195,18 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     const int nbt = Q1 * (N1 + 1) + Q2 * (N2 + 1);
     for (int x = t; x < nbt; x += kStageThreads)
         btab[x] = x < Q1 * (N1 + 1) ? tab[I.tB1 + x] : tab[I.tB2 + x - Q1 * (N1 + 1)];
-    // node role for the per-cell factor table: g1 (k < Q1) or g2 (Q1 <= k < Q1+Q2)
+    // node role for the per-cell factor table, taken by the run's last wavefront (its
+    // first one finishes the moment sums): lane kg of it builds g1 (kg < Q1) or g2
+    // (Q1 <= kg < Q1+Q2)
+    const int kg = k - (nvpad - kWave);
     const double* brow = nullptr;
     int coff = -1, nb = 0;
-    if (rlen > 0 && k < Q1) {
+    if (rlen > 0 && kg >= 0 && kg < Q1) {
         nb = N1 + 1;
-        brow = btab + k * nb;
-        coff = 3 + ((I.kind1 == 1 && k >= I.Qh1) ? nb : 0);
-    } else if (rlen > 0 && k < Q1 + Q2) {
-        const int j = k - Q1;
+        brow = btab + kg * nb;
+        coff = 3 + ((I.kind1 == 1 && kg >= I.Qh1) ? nb : 0);
+    } else if (rlen > 0 && kg >= 0 && kg < Q1 + Q2) {
+        const int j = kg - Q1;
         nb = N2 + 1;
         brow = btab + Q1 * (N1 + 1) + j * nb;
         coff = 3 + 2 * (N1 + 1) + ((I.kind2 == 1 && j >= I.Qh2) ? nb : 0);
@@ -243,26 +288,24 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     const double pw1 = (double)p1, pw2 = (double)p2;
     const double wmk = Wm[kk], rwk = resW[kk];
 
-    // moments (and residual partials) of cell c of this run: summed over the run's
-    // wavefronts by the run's first thread, one cell behind the sweep
-    // lane q < 6 of the run's first wavefront sums quantity q over the run's wavefronts
+    // moments (and residual partials) of cell c of this run, one cell behind the sweep:
+    // lane 4 q + j (q < 6, j < 4) of the run's first wavefront sums row total j of
+    // quantity q over the run's wavefronts (in wavefront order); lane 4 q adds the four
+    // row sums of its quad (in row order) and stores quantity q
     auto finish = [&](int c, int buf) {
-        if (k >= 6 || c >= rlen) return;
-        const double* mp = mpart + (((size_t)buf * (kStageThreads / kWave) + w0) * 8 + k) * 4;
+        if (k >= 24 || c >= rlen) return;
+        const double* mp = mpart + ((size_t)buf * (kStageThreads / kWave) + w0) * 32 + k;
         double m = 0.0;
-        for (int w = 0; w < nw_waves; ++w) {
-            const double* q = mp + (size_t)w * 32;
-            m += q[0];
-            m += q[1];
-            m += q[2];
-            m += q[3];
-        }
-        const int s = rs0 + c;
-        if (k < 4) {
-            if (dist == 0) A.msum_out[(size_t)(I.offC + s) * 5 + k] = m;
-            else if (k == 0) A.msum_out[(size_t)(I.offC + s) * 5 + 4] = m;
+        for (int w = 0; w < nw_waves; ++w) m += mp[(size_t)w * 32];
+        const double m1 = dpp_mov<0x55>(m), m2 = dpp_mov<0xAA>(m), m3 = dpp_mov<0xFF>(m);   // quad lanes 1, 2, 3
+        m = ((m + m1) + m2) + m3;
+        if (k & 3) return;
+        const int q = k >> 2, s = rs0 + c;
+        if (q < 4) {
+            if (dist == 0) A.msum_out[(size_t)(I.offC + s) * 5 + q] = m;
+            else if (q == 0) A.msum_out[(size_t)(I.offC + s) * 5 + 4] = m;
         } else if (A.rpart) {
-            A.rpart[((size_t)(I.offC + s) * 2 + dist) * 2 + (k - 4)] = eqc[(size_t)(r * TC + c) * kEqStride + kEqGeo + 2] * m;
+            A.rpart[((size_t)(I.offC + s) * 2 + dist) * 2 + (q - 4)] = eqc[(size_t)(r * TC + c) * kEqStride + kEqGeo + 2] * m;
         }
     };
 
@@ -278,6 +321,12 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
         fnr[q] = (act && need_fn && q < rlen) ? (Fnd + (size_t)(rs0 + q) * NV)[k] : T(0);
     }
 
+    // the run's first wavefront also finishes the previous cell's sums and its last one
+    // builds the equilibrium factors; they issue ahead of the run's other wavefronts,
+    // which would otherwise wait for them at every barrier
+    if (rlen > 0 && ((__builtin_amdgcn_readfirstlane(k) >> 6) == 0 ||
+                     (__builtin_amdgcn_readfirstlane(k) >> 6) == nw_waves - 1))
+        __builtin_amdgcn_s_setprio(2);
     for (int c = 0; c < TC; ++c) {
         const int buf = c & 1;
         const bool cv = act && c < rlen;
@@ -305,7 +354,7 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
         if (coff >= 0 && c < rlen) {
             double g = 0.0;
             for (int l = 0; l < nb; ++l) g += brow[l] * e[coff + l];
-            gb[k] = T(g);
+            gb[kg] = T(g);
         }
         __syncthreads();
         if (c > 0) finish(c - 1, buf ^ 1);
@@ -315,8 +364,12 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
             const T Rl = T(e[kEqGeo]), Rr = T(e[kEqGeo + 1]), gam = T(e[kEqGeo + 3]);   // R_{s-+1/2}/dchi_s
             const T adv = p1 * (Rr * fr - Rl * fl);
             T kf = T(0), ktf = T(0);
-            kf = dot_lds<T>(K1row, rowT + vj * P1, L1);
-            ktf = dot_lds<T>(Ktrow, row + vi * P2, L2);
+            if constexpr (sizeof(T) == 4) {
+                dot2_lds(K1row, rowT + vj * P1, L1, Ktrow, row + vi * P2, L2, kf, ktf);
+            } else {
+                kf = dot_lds<T>(K1row, rowT + vj * P1, L1);
+                ktf = dot_lds<T>(Ktrow, row + vi * P2, L2);
+            }
             const T force = gam * (p2 * p2 * kf - p1 * ktf);
             T fe = T(e[0]) * gb[vi] * gb[Q1 + vj];
             if (dist) fe = T(e[1]) * fe;
