@@ -278,6 +278,13 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
         w3v = cell(rs0);     w4v = cell(rs0 + 1); w5v = cell(rs0 + 2);
         fl = weno_face<T>(pos, w0v, w1v, w2v, w3v, w4v, w5v, weps);
     }
+    // ghosts past the outer wall, which the window's leading cell reaches in the last
+    // cells of the run next to it; the stage input is read-only, so they are built once
+    // here and the sweep only selects them (no loads inside the sweep's ghost path, which
+    // would make every cell wait for the prefetched loads)
+    T gh0 = 0, gh1 = 0, gh2 = 0;
+    if (act && near_out) { gh0 = cell(NR); gh1 = cell(NR + 1); gh2 = cell(NR + 2); }
+    const long long offC = I.offC;
 
     const double dt = A.l_only ? 1.0 : I.dt;
     const T cdt = T(A.cc * dt), ca = T(A.ca), cb = T(A.cb);
@@ -302,10 +309,10 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
         if (k & 3) return;
         const int q = k >> 2, s = rs0 + c;
         if (q < 4) {
-            if (dist == 0) A.msum_out[(size_t)(I.offC + s) * 5 + q] = m;
-            else if (q == 0) A.msum_out[(size_t)(I.offC + s) * 5 + 4] = m;
+            if (dist == 0) A.msum_out[(size_t)(offC + s) * 5 + q] = m;
+            else if (q == 0) A.msum_out[(size_t)(offC + s) * 5 + 4] = m;
         } else if (A.rpart) {
-            A.rpart[((size_t)(I.offC + s) * 2 + dist) * 2 + (q - 4)] = eqc[(size_t)(r * TC + c) * kEqStride + kEqGeo + 2] * m;
+            A.rpart[((size_t)(offC + s) * 2 + dist) * 2 + (q - 4)] = eqc[(size_t)(r * TC + c) * kEqStride + kEqGeo + 2] * m;
         }
     };
 
@@ -347,7 +354,7 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
         if (cv) {
             w0v = w1v; w1v = w2v; w2v = w3v; w3v = w4v; w4v = w5v;
             // s is wavefront-uniform: interior cells take a plain load
-            w5v = s + 3 < NR ? lead : cell(s + 3);
+            w5v = s + 3 < NR ? lead : (s + 3 == NR ? gh0 : (s + 3 == NR + 1 ? gh1 : gh2));
             row[vi * P2 + vj] = w2v;
             rowT[vj * P1 + vi] = w2v;
         }
