@@ -334,6 +334,11 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     if (rlen > 0 && ((__builtin_amdgcn_readfirstlane(k) >> 6) == 0 ||
                      (__builtin_amdgcn_readfirstlane(k) >> 6) == nw_waves - 1))
         __builtin_amdgcn_s_setprio(2);
+    // each cell's output is stored at the start of the next cell, beside the prefetch
+    // loads: stores count against the same wait as loads, and the loop latch waits for
+    // the ring (a store issued late in the cell would be waited for there)
+    T out_prev = T(0);
+    T* st_prev = nullptr;
     for (int c = 0; c < TC; ++c) {
         const int buf = c & 1;
         const bool cv = act && c < rlen;
@@ -347,6 +352,7 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
             pw[kAhead - 1] = (c + kAhead < rlen && x < NR) ? (Fd + (size_t)x * NV)[k] : T(0);
             fnr[kAhead - 1] = (need_fn && c + kAhead < rlen) ? (Fnd + (size_t)(s + kAhead) * NV)[k] : T(0);
         }
+        if (st_prev) { *st_prev = out_prev; st_prev = nullptr; }
         T* row = rows + (size_t)buf * kRowElems + (size_t)r * 2 * S;
         T* rowT = row + S;
         T* gb = gbuf + (size_t)buf * kMaxRuns * kWave + (size_t)r * kWave;
@@ -395,7 +401,8 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
                     rn = (double)fn * (double)fn * rwk;
                 }
             }
-            (Fo + (size_t)s * NV)[k] = out;
+            out_prev = out;
+            st_prev = Fo + (size_t)s * NV + k;
             const double wo = wmk * (double)out;
             m0 = wo;
             if (dist == 0) {
@@ -414,6 +421,7 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
             mp[0] = m0; mp[4] = m1; mp[8] = m2; mp[12] = m3; mp[16] = rd; mp[20] = rn;
         }
     }
+    if (st_prev) *st_prev = out_prev;
     __syncthreads();
     finish(TC - 1, (TC - 1) & 1);
 }
