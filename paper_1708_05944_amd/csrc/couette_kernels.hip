@@ -316,8 +316,9 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
         }
     };
 
-    // loads issued kAhead cells before their use (the window's leading cell and F_n), so
-    // that each wavefront keeps 2 kAhead loads in flight; the cell geometry one ahead
+    // loads issued kAhead cells before their use (the window's leading cell and F_n); the
+    // ring shifts through registers, so the loop latch waits for the loads each cell
+    // issued at its start, and that cell's work is what covers their latency
     const bool need_fn = !A.l_only && ca != T(0);
     constexpr int kAhead = sizeof(T) == 4 ? 4 : 2;
     T pw[kAhead], fnr[kAhead];
