@@ -170,7 +170,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(instances shard across GPUs without communication; see DESIGN.md)", file=sys.stderr)
+              "(instances shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -341,7 +341,7 @@ def main():
     warm = None
     if not args.no_warm:
         # learned warm start: surrogate trained on the solver's own steady states (sweep
-        # generator, seed 1), judged on held-out instances (seed 2) against the plain FP64
+        # generator, seed 1), evaluated on held-out instances (seed 2) against the plain FP64
         # solver from rest; family Kn <= 0.2, 32 cells, regularised WENO weights (1e-6)
         from paper_1708_05944_amd import surrogate
         tr = workloads.surrogate_descs(args.warm_train, workloads.SURROGATE_TRAIN_SEED, N_R=32, Kn_max=0.2)
@@ -353,7 +353,7 @@ def main():
                                                log=lambda m: print(m, file=sys.stderr, flush=True))
         warm["workload"] = (f"{len(tr)} training / {len(ho)} held-out Couette instances of the sweep generator "
                             f"(seeds 1 / 2) with Kn <= 0.2, 32 cells, weno_eps 1e-6; cold = FP64 from rest, "
-                            f"warm = surrogate (bf16 inference) + judge probe, mixed precision")
+                            f"warm = surrogate (bf16 inference) + FP64 acceptance probe, mixed precision")
 
     out = {
         "metric": "site-velocity updates/s (batched Couette sweep, mixed precision: FP32 streaming)",

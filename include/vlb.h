@@ -277,8 +277,8 @@ vlb_status vlb_batch_surrogate_samples(vlb_batch* b, float* X, float* T, size_t 
  * surrogate's family, the local equilibrium of the network's fields (bfloat16
  * inference) with n rescaled so that sum_s dchi_s n_s equals the cold start's (the
  * steady state of the closed cell depends on this conserved particle number, Eq.
- * Ntot_def) and u^R = 0; for the others, and for any instance the judge rejects, the
- * cold rest state (n = 1, u = 0, T = T_in).  The judge (probe_steps > 0): run
+ * Ntot_def) and u^R = 0; for the others, and for any instance the acceptance probe rejects, the
+ * cold rest state (n = 1, u = 0, T = T_in).  The acceptance probe (probe_steps > 0): run
  * probe_steps FP64 steps from the cold start and from the warm start; the warm start is
  * kept only where its residual is then strictly lower (a non-finite warm residual
  * rejects it).  used_warm (host array of B, may be NULL) receives 1 where the warm

@@ -17,7 +17,7 @@
  *     flux_kom_eta;
  *   - momentum-derivative force terms projected with the kernels of Sec. IV.C;
  *   - third-order TVD Runge-Kutta (Sec. III.A, Eq. rk3, Table rk3).
- * Readings where the paper is silent (listed in the design doc): WENO for V<0 is the
+ * Readings where the paper is silent: WENO for V<0 is the
  * mirror image of the printed V>0 stencil; the 1/R factor of the force is the
  * cell value Gamma_s = 2/(R_{s+1/2}+R_{s-1/2}) (equal to 1/R_s on uniform grids);
  * f'' ghosts are T_w times the f' ghosts and wall-bound f'' uses the same

@@ -10,7 +10,7 @@ Everything here is written from the paper's Sec. IV (LB models) and Appendix D:
   polynomials h_l are orthonormal on [0, inf) with respect to
   omega(x) = exp(-x^2/2)/sqrt(2 pi), leading coefficient positive.  The paper never
   states the normalisation; we read it as orthonormal because the kernels of
-  Eqs. df_K_hh / dfp_K_hh carry no factorials (a reading listed in the design doc).
+  Eqs. df_K_hh / dfp_K_hh carry no factorials.
   Nodes are the Q positive roots of h_Q, mirrored to the negative semi-axis, and
   the weights follow Eq. w_hh;
 * momentum-derivative kernels (Sec. IV.C, Eqs. df_K_H, df_K_hh, dfp_K_H,

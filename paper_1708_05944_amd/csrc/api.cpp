@@ -1262,7 +1262,7 @@ vlb_status vlb_batch_warm_start(vlb_batch* b, vlb_mlp* m, int probe_steps, int* 
     s = mlp_infer(m, b->sfeat(), (long)b->ncells, b->sy(), 1, b->stream);
     if (s != VLB_OK) return s;
     if (any && probe_steps > 0) {
-        // the judge: the FP64 residual after probe_steps steps from each start
+        // the acceptance probe: the FP64 residual after probe_steps steps from each start
         std::vector<double> rc(b->B), rw(b->B);
         s = init_from_surrogate(b, use);
         if (s == VLB_OK) s = step_current(b, probe_steps);

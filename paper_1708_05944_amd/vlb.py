@@ -399,7 +399,7 @@ class Batch:
         return X, T
 
     def warm_start(self, mlp: "Mlp", probe_steps: int = 1000) -> np.ndarray:
-        """Initial states from the surrogate (cold start where the judge rejects it);
+        """Initial states from the surrogate (cold start where the acceptance probe rejects it);
         returns the per-instance 0/1 array of warm starts kept."""
         used = (ctypes.c_int * self.B)()
         _check(load_library().vlb_batch_warm_start(self._h, mlp._h, probe_steps, used), "vlb_batch_warm_start")

@@ -121,7 +121,7 @@ def _warm_case():
 
 
 def test_warm_start_state_matches_oracle():
-    """Without the judge: instances in the family start at the oracle's warm profile
+    """Without the acceptance probe: instances in the family start at the oracle's warm profile
     (bf16-emulated network, particle number of the cold start); the other at rest."""
     from oracle.couette import CouetteOracle
     from paper_1708_05944_amd import Batch, Mlp
@@ -153,7 +153,7 @@ def test_warm_start_state_matches_oracle():
     b.close()
 
 
-def test_warm_start_judge_rejects_a_bad_surrogate():
+def test_warm_start_probe_rejects_a_bad_surrogate():
     """A network whose outputs are far off (u^phi = 3 u_w everywhere) loses to the cold
     start after the probe, so every instance starts cold."""
     from paper_1708_05944_amd import Batch, Mlp
