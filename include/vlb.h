@@ -198,8 +198,8 @@ vlb_status vlb_axis_tables(vlb_axis ax, double* p, double* w, double* K, double*
 /* Cells per run of the stage kernel (2..32; default 16): each block sweeps runs of this
  * many consecutive cells, one thread per velocity.  Short runs give small instances more
  * parallel blocks; long runs amortise the 3-cell halo at each run end.
- * vlb_batch_autotune times `steps` steps for each of 2, 4, 8, 16, 32 on the batch itself
- * (on a copy of the state, which is restored), keeps the fastest, and returns it with its
+ * vlb_batch_autotune times `steps` steps for each cells-per-run value from 2 to 32 on the
+ * batch itself (on a copy of the state, which is restored), keeps the fastest, and returns it with its
  * time per step in ms.  Allocates a temporary device copy of the state. */
 vlb_status vlb_batch_set_tile(vlb_batch* b, int cells_per_run);
 vlb_status vlb_batch_get_tile(const vlb_batch* b, int* cells_per_run);

@@ -1087,7 +1087,10 @@ vlb_status vlb_batch_autotune(vlb_batch* b, int steps, int* chosen, double* ms_p
     int best = b->tile;
     float best_ms = 1e30f;
     vlb_status st = VLB_OK;
-    for (int tile : {2, 4, 8, 16, 32}) {
+    // every length: the launch's block count against the 256 CUs (a last, nearly empty
+    // round of blocks costs a whole block time), the halo reads and the per-block set-up
+    // all move with it, not monotonically
+    for (int tile = kMinTile; tile <= kMaxTile; ++tile) {
         build_blocks(b, tile);
         st = upload_blocks(b);
         if (st != VLB_OK) break;

@@ -229,7 +229,7 @@ def test_autotune_keeps_state_and_picks_a_tile():
     b.step(3)
     before = b.get_state()
     tile, ms = b.autotune(3)
-    assert tile in (2, 4, 8, 16, 32) and ms > 0 and b.tile() == tile
+    assert 2 <= tile <= 32 and ms > 0 and b.tile() == tile
     assert np.array_equal(b.get_state(), before)
     b.close()
 
