@@ -285,6 +285,31 @@ vlb_status vlb_batch_surrogate_samples(vlb_batch* b, float* X, float* T, size_t 
  * start is kept.  Leaves the state in the FP64 buffers.  Synchronises. */
 vlb_status vlb_batch_warm_start(vlb_batch* b, vlb_mlp* m, int probe_steps, int* used_warm);
 
+/* ---- Steps without device allocation --------------------------------------------
+ *
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Advances B Couette instances (the
+ * descriptors of vlb_batch_create_couette) by nsteps >= 1 RK3 steps in FP64, exactly as
+ * a batch created from the same descriptors would with vlb_set_state (F), vlb_step
+ * (nsteps) and vlb_residual: same kernels, same default cells per run.
+ *   F      device array of the state, the layout of vlb_get_state (sum over instances of
+ *          2 N_R NV doubles), read and overwritten in place; owned by the caller.
+ *   resid  host array of B (may be NULL): the residual of the last step (vlb_residual).
+ *   hip_stream  a hipStream_t (may be NULL); the call synchronises it before returning.
+ * Every other device buffer (RK stage buffers, moment sums, residual partials, tables,
+ * descriptors, block lists) lives in a fixed scratch array of the library of
+ * VLB_NOALLOC_SCRATCH_BYTES bytes, one per GPU, held from the first call on that GPU
+ * until the process ends; the call allocates no device memory and uses no
+ * allocating library routine.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (other threads, other streams) race and must be serialised by the
+ * caller.  Errors: VLB_EINVAL (B < 1, NULL descriptors or state, nsteps < 1, invalid
+ * descriptors), VLB_EUNSTABLE (explicit dt above the limits), VLB_ENOMEM when the
+ * instances need more scratch than VLB_NOALLOC_SCRATCH_BYTES (checked before any device
+ * work), VLB_ENONFINITE (non-finite residual), VLB_EDEVICE. */
+#define VLB_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+vlb_status vlb_couette_step_noalloc(int B, const vlb_couette_desc* descs, double* F, long nsteps, double* resid,
+                                    void* hip_stream);
+
 /* ---- Expanding channel (Sec. VI) ------------------------------------------------
  *
  * A 2-D channel with walls at x = +-(1 + phi(y)), 1 + phi(xi) = 1 + (r - 1)(1 +

@@ -5,8 +5,8 @@ of ``include/vlb.h``); this package only marshals arguments to it.  There is no 
 fallback: if the library is missing or no GPU is visible, calls fail loudly.
 """
 from .vlb import (VLB_FP64, VLB_MIXED, VLB_TAU_AOKI, VLB_TAU_HYDRO, VLB_TAU_KN, Batch, CouetteDesc, VlbError,  # noqa: F401
-                  Channel, ChannelDesc, Mlp, axis_tables, library_path, load_library,
-                  mlp_param_count)
+                  Channel, ChannelDesc, Mlp, axis_tables, couette_step_noalloc, library_path,
+                  load_library, mlp_param_count)
 
-__all__ = ["Batch", "CouetteDesc", "Channel", "ChannelDesc", "Mlp", "mlp_param_count", "VlbError", "axis_tables", "load_library", "library_path",
+__all__ = ["Batch", "CouetteDesc", "Channel", "ChannelDesc", "Mlp", "mlp_param_count", "VlbError", "axis_tables", "couette_step_noalloc", "load_library", "library_path",
            "VLB_FP64", "VLB_MIXED", "VLB_TAU_AOKI", "VLB_TAU_HYDRO", "VLB_TAU_KN"]

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvlb.so")
 SOURCES = ["velocity_set.cpp", "couette_kernels.hip", "couette_wide.hip", "api.cpp", "mlp_kernels.hip", "mlp_api.cpp",
-           "channel_kernels.hip", "channel_api.cpp"]
+           "channel_kernels.hip", "channel_api.cpp", "noalloc.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          # keep hipcc from emitting packed FP32 instructions (v_pk_*_f32)

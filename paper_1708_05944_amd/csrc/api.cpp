@@ -125,6 +125,7 @@ struct vlb_batch {
     std::vector<InstDesc> desc32;       // FP32 descriptors (rescaled tables)
     char* ws = nullptr;
     bool owns = false;
+    double* ext_F0 = nullptr;           // caller-owned device state in place of F_n (no-allocation entry point)
     bool have_resid = false;
     bool timing = false;
     bool use_graphs = true;
@@ -133,7 +134,7 @@ struct vlb_batch {
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
 
-    double* F(int i) { return (double*)(ws + off_F[i]); }
+    double* F(int i) { return (i == 0 && ext_F0) ? ext_F0 : (double*)(ws + off_F[i]); }
     float* F32(int i) { return (float*)(ws + off_F32[i]); }
     InstDesc* ddesc32() { return (InstDesc*)(ws + off_desc32); }
     double* M(int i) { return (double*)(ws + off_M[i]); }
@@ -297,9 +298,12 @@ void equilibrium_state(const InstHost& h, const double* n, const double* u1, con
     }
 }
 
-vlb_status layout_and_alloc(vlb_batch* b, bool alloc) {
+vlb_status layout_and_alloc(vlb_batch* b, bool alloc, bool ext_state = false) {
     size_t off = 0;
-    for (int i = 0; i < 3; ++i) { b->off_F[i] = off; off = align256(off + b->state_n * sizeof(double)); }
+    for (int i = 0; i < 3; ++i) {
+        b->off_F[i] = off;
+        if (!(i == 0 && ext_state)) off = align256(off + b->state_n * sizeof(double));
+    }
     for (int i = 0; i < 3; ++i) {
         b->off_F32[i] = off;
         if (b->precision == VLB_MIXED) off = align256(off + b->state_n * sizeof(float));
@@ -1290,4 +1294,50 @@ vlb_status vlb_batch_warm_start(vlb_batch* b, vlb_mlp* m, int probe_steps, int* 
 
 namespace vlb {
 double force_operator_norm(const AxisTables& a1, const AxisTables& a2) { return force_norm(a1, a2); }
+}  // namespace vlb
+
+// ------------------------------------------------------------------ steps in caller scratch
+
+namespace vlb {
+
+// Host-side set-up of a batch that runs in caller-supplied device memory: velocity sets,
+// grids, descriptors and block lists are built (host memory only, no HIP call) and the
+// device bytes it needs, with the state kept in the caller's array, are returned.
+vlb_status couette_noalloc_plan(int B, const vlb_couette_desc* descs, vlb_batch** out, size_t* bytes) {
+    vlb_status st = vlb_batch_create_couette(out, B, descs, VLB_FP64, nullptr, 1);
+    if (st != VLB_OK) return st;
+    vlb_batch* b = *out;
+    st = layout_and_alloc(b, false, true);
+    if (st != VLB_OK) { vlb_batch_destroy(b); *out = nullptr; return st; }
+    b->use_graphs = false;
+    *bytes = b->total_bytes;
+    return VLB_OK;
+}
+
+// nsteps RK3 steps of a planned batch on the caller's FP64 state F (device, the layout of
+// vlb_get_state) with every other device buffer in scratch (>= the planned bytes,
+// 256-byte aligned); resid (host, B entries, may be NULL) receives the residual of the
+// last step.  Every scratch byte a kernel reads is written earlier in the same call.
+// Synchronises the stream before returning.
+vlb_status couette_noalloc_run(vlb_batch* b, double* F, long nsteps, double* resid, hipStream_t stream,
+                               char* scratch) {
+    b->stream = stream;
+    b->ws = scratch;
+    b->owns = false;
+    b->ext_F0 = F;
+    vlb_status st = upload_tables(b);
+    if (st == VLB_OK) {
+        hipError_t e = hipMemcpyAsync(b->dwork(), b->work.data(), b->work.size() * sizeof(WorkItem),
+                                      hipMemcpyHostToDevice, b->stream);
+        if (e != hipSuccess) st = fail(VLB_EDEVICE, "work list upload failed: %s", hipGetErrorString(e));
+    }
+    if (st == VLB_OK) st = upload_blocks(b);
+    if (st == VLB_OK) st = refresh_moments(b);
+    if (st == VLB_OK) st = step_current(b, nsteps);
+    if (st == VLB_OK && resid) st = read_residual(b, resid);
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (st == VLB_OK && e != hipSuccess) st = fail(VLB_EDEVICE, "stream synchronisation failed: %s", hipGetErrorString(e));
+    return st;
+}
+
 }  // namespace vlb

@@ -179,6 +179,8 @@ _SIGS = {
     "vlb_channel_set_graphs": [ctypes.c_void_p, ctypes.c_int],
     "vlb_channel_run_to_steady": [ctypes.c_void_p, ctypes.c_double, ctypes.c_long, ctypes.c_int,
                                   ctypes.POINTER(ctypes.c_long), _dp],
+    "vlb_couette_step_noalloc": [ctypes.c_int, ctypes.POINTER(_CouetteDesc), ctypes.c_void_p, ctypes.c_long, _dp,
+                                 ctypes.c_void_p],
     "vlb_status_string": [ctypes.c_int],
     "vlb_last_error": [],
 }
@@ -404,6 +406,22 @@ class Batch:
         used = (ctypes.c_int * self.B)()
         _check(load_library().vlb_batch_warm_start(self._h, mlp._h, probe_steps, used), "vlb_batch_warm_start")
         return np.array(list(used), dtype=np.int32)
+
+
+def couette_step_noalloc(descs, F, nsteps: int, stream=None) -> np.ndarray:
+    """nsteps FP64 RK3 steps of the instances `descs` on the device state F (a contiguous
+    float64 torch tensor in the layout of Batch.get_state, updated in place) through the
+    library's no-allocation entry point; returns the residual of the last step per instance."""
+    import torch
+    if not (isinstance(F, torch.Tensor) and F.is_cuda and F.dtype == torch.float64 and F.is_contiguous()):
+        raise TypeError("F must be a contiguous float64 CUDA tensor")
+    descs = list(descs)
+    arr = (_CouetteDesc * len(descs))(*[d._c() for d in descs])
+    st = stream if stream is not None else torch.cuda.current_stream(F.device)
+    r = np.empty(len(descs))
+    _check(load_library().vlb_couette_step_noalloc(len(descs), arr, ctypes.c_void_p(F.data_ptr()), nsteps, _ptr(r),
+                                                   ctypes.c_void_p(st.cuda_stream)), "vlb_couette_step_noalloc")
+    return r
 
 
 def _fptr(a: np.ndarray):

@@ -143,3 +143,25 @@ def test_large_velocity_sets_are_fp64_only():
     lib.vlb_batch_destroy(h)
     st, msg, _ = _couette_create([small, wide], 1)
     assert st == -1 and "FP64 only" in msg, (st, msg)
+
+
+def test_noalloc_entry_point_rejects_oversized_and_invalid_calls():
+    """The no-allocation entry point checks its arguments and the scratch its instances
+    need (here one instance of 4096 cells x 640 velocities, 2 x 21 MB of RK stage buffers
+    alone, above the 64 MiB array) before any device work, so this runs without a GPU."""
+    from paper_1708_05944_amd import CouetteDesc
+    from paper_1708_05944_amd.vlb import _CouetteDesc
+    lib = load_library()
+    host = np.zeros(8)
+    fake = ctypes.c_void_p(host.ctypes.data)   # never dereferenced: every call below fails first
+    big = CouetteDesc(N_R=4096, ax1=(1, 16, 4), ax2=(0, 20, 4))
+    arr = (_CouetteDesc * 1)(big._c())
+    st = lib.vlb_couette_step_noalloc(1, arr, fake, 1, None, None)
+    msg = lib.vlb_last_error().decode()
+    assert st == -2 and "scratch" in msg and str(64 << 20) in msg, (st, msg)
+    small = (_CouetteDesc * 1)(CouetteDesc(N_R=8)._c())
+    assert lib.vlb_couette_step_noalloc(1, small, fake, 0, None, None) == -1
+    assert lib.vlb_couette_step_noalloc(0, small, fake, 1, None, None) == -1
+    assert lib.vlb_couette_step_noalloc(1, small, None, 1, None, None) == -1
+    bad = (_CouetteDesc * 1)(CouetteDesc(N_R=2)._c())
+    assert lib.vlb_couette_step_noalloc(1, bad, fake, 1, None, None) == -1
