@@ -89,41 +89,111 @@ def measured_traffic(*kernels: str):
         return None
 
 
-def _cpu_worker(args):
-    """Oracle (plain C FP64, one thread) on one instance for a few steps; returns
-    (site-velocity updates, seconds)."""
-    idx, nsteps = args
+_BARRIER = None
+
+
+def _cpu_init(barrier):
+    global _BARRIER
+    _BARRIER = barrier
+
+
+def _oracle_for(idx):
     from oracle.couette import CouetteOracle
     from paper_1708_05944_amd import workloads
     d = workloads.couette_sweep()[idx]
-    o = CouetteOracle(R_in=d.R_in, R_out=d.R_out, N_R=d.N_R, ax1=d.ax1, ax2=d.ax2, Kn=d.Kn,
-                      tau_model=d.tau_model, u_in=d.u_in, T_in=d.T_in, u_out=d.u_out, T_out=d.T_out)
-    F = o.equilibrium(1.0, 0.0, 0.0, 1.0)
-    dt = o.cfl_dt(d.cfl)
-    o.step(F, dt, 1)                       # warm (tables, page faults)
-    t0 = time.perf_counter()
-    o.step(F, dt, nsteps)
-    el = time.perf_counter() - t0
-    return o.NR * o.NV * nsteps, el
+    return CouetteOracle(R_in=d.R_in, R_out=d.R_out, N_R=d.N_R, ax1=d.ax1, ax2=d.ax2, Kn=d.Kn,
+                         tau_model=d.tau_model, u_in=d.u_in, T_in=d.T_in, u_out=d.u_out, T_out=d.T_out)
 
 
-def cpu_baseline(n_inst: int, nsteps: int):
-    """The oracle on the first n_inst instances of the sweep, nsteps RK3 steps each, one
-    process per host core (instances are independent)."""
+def _cpu_worker(args):
+    """Oracle (plain C FP64, one thread per process) on a list of sweep instances: build
+    them (mpmath tables, not timed), wait for every worker, then step each nsteps RK3
+    steps from rest; returns (site-velocity updates, wall-clock start, end)."""
+    idxs, nsteps = args
+    work = []
+    for idx in idxs:
+        o = _oracle_for(idx)
+        work.append((o, o.equilibrium(1.0, 0.0, 0.0, 1.0), o.cfl_dt(0.5)))
+    _BARRIER.wait()
+    t0 = time.time()
+    upd = 0
+    for o, F, dt in work:
+        o.step(F, dt, nsteps)
+        upd += o.NR * o.NV * nsteps
+    return upd, t0, time.time()
+
+
+def host_cores():
+    """Host threads this process may use (affinity), capped at the GPU machine's CPU share of 16,
+    and the CPU model."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return min(n, 16), os.cpu_count(), model
+
+
+def cpu_baseline(n_inst: int, nsteps: int, single_inst: int, tts: bool = True):
+    """The oracle as it stands, timed on the host by wall clock: all cores (one process per
+    core over the first n_inst sweep instances, nsteps steps each, started together
+    after their set-up), one thread (the first single_inst instances in turn), and the
+    single-instance workload from rest to r < 1e-10 (residual checked every 500 steps)."""
     import multiprocessing as mp
     from oracle import couette as oc
     oc.build()
-    cores = min(os.cpu_count() or 1, 16)
-    t0 = time.perf_counter()
-    with mp.get_context("spawn").Pool(cores) as pool:
-        res = pool.map(_cpu_worker, [(i, nsteps) for i in range(n_inst)])
-    wall = time.perf_counter() - t0
+    cores, nproc, model = host_cores()
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(cores)
+    chunks = [(list(range(c, n_inst, cores)), nsteps) for c in range(cores)]
+    with ctx.Pool(cores, initializer=_cpu_init, initargs=(barrier,)) as pool:
+        res = pool.map(_cpu_worker, chunks, chunksize=1)
     upd = sum(r[0] for r in res)
-    busy = sum(r[1] for r in res)
-    return dict(value=upd / busy * min(cores, n_inst), unit="site-velocity updates/s", cores=cores, kind="oracle",
-                sample=f"first {n_inst} of the 256 sweep instances, {nsteps} RK3 steps each from rest, "
-                       f"{cores} worker processes x 1 thread; value = updates / per-process busy time x workers "
-                       f"(wall {wall:.1f} s incl. table set-up)")
+    wall = max(r[2] for r in res) - min(r[1] for r in res)
+    # one thread
+    work = []
+    for idx in range(single_inst):
+        o = _oracle_for(idx)
+        work.append((o, o.equilibrium(1.0, 0.0, 0.0, 1.0), o.cfl_dt(0.5)))
+    t0 = time.perf_counter()
+    upd1 = 0
+    for o, F, dt in work:
+        o.step(F, dt, nsteps)
+        upd1 += o.NR * o.NV * nsteps
+    single = upd1 / (time.perf_counter() - t0)
+    out = dict(value=upd / wall, unit="site-velocity updates/s", cores=cores, kind="oracle",
+               sample=f"sweep instances 0..{n_inst - 1}, {nsteps} RK3 steps each from rest, {cores} processes x 1 "
+                      f"thread started together after their table set-up; value = updates / wall-clock "
+                      f"({wall:.2f} s)",
+               single_thread_value=single,
+               single_thread_sample=f"sweep instances 0..{single_inst - 1}, {nsteps} steps each, one thread",
+               host={"nproc": nproc, "cpu_model": model})
+    if tts:
+        from oracle.couette import CouetteOracle
+        from paper_1708_05944_amd import workloads
+        d = workloads.single_couette()
+        o = CouetteOracle(R_in=d.R_in, R_out=d.R_out, N_R=d.N_R, ax1=d.ax1, ax2=d.ax2, Kn=d.Kn,
+                          tau_model=d.tau_model, u_in=d.u_in, T_in=d.T_in, u_out=d.u_out, T_out=d.T_out)
+        F = o.equilibrium(1.0, 0.0, 0.0, 1.0)
+        dt = o.cfl_dt(0.5)
+        t0 = time.perf_counter()
+        steps, r = 0, float("inf")
+        while r >= 1e-10 and steps < 100_000:
+            F = o.step(F, dt, 499)
+            G = o.step(F, dt, 1)
+            r = o.residual(G, F, dt)
+            F = G
+            steps += 500
+        out["time_to_steady_state_single"] = dict(seconds=time.perf_counter() - t0, steps=steps, residual=r, dt=dt,
+                                                  converged=bool(r < 1e-10), threads=1)
+    return out
 
 
 def channel_cpu_baseline():
@@ -154,7 +224,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-instances", type=int, default=64)
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-single", type=int, default=8, help="sweep instances of the single-thread oracle timing")
     ap.add_argument("--no-tts", action="store_true",
                     help="skip the single-instance time-to-steady-state leg (profiling runs)")
     ap.add_argument("--no-warm", action="store_true",
@@ -162,8 +233,10 @@ def main():
     ap.add_argument("--no-channel", action="store_true", help="skip the expanding-channel leg")
     ap.add_argument("--no-ballistic", action="store_true", help="skip the ballistic (8000-velocity) leg")
     ap.add_argument("--no-clb", action="store_true", help="skip the vielbein vs Cartesian-split channel timing")
-    ap.add_argument("--warm-train", type=int, default=128, help="training instances of the warm-start leg")
-    ap.add_argument("--warm-heldout", type=int, default=32, help="held-out instances of the warm-start leg")
+    ap.add_argument("--warm-train", type=int, default=4096, help="training instances of the warm-start leg")
+    ap.add_argument("--warm-heldout", type=int, default=256, help="held-out instances of the warm-start leg")
+    ap.add_argument("--warm-epochs", type=int, default=100, help="training epochs of the warm-start leg")
+    ap.add_argument("--no-eps-free", action="store_true", help="skip the epsilon-free held-out runs of the warm leg")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="after the run, one plain device copy of this many MiB (reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -341,19 +414,29 @@ def main():
     warm = None
     if not args.no_warm:
         # learned warm start: surrogate trained on the solver's own steady states (sweep
-        # generator, seed 1), evaluated on held-out instances (seed 2) against the plain FP64
-        # solver from rest; family Kn <= 0.2, 32 cells, regularised WENO weights (1e-6)
+        # generator, seed 1), evaluated on held-out instances (seed 2), cold and warm, in FP64
+        # and by the mixed defect correction; family Kn <= 0.2, 32 cells; the regularised WENO
+        # weights (1e-6) give every instance of the family a steady state, and the held-out set
+        # is also run with the paper's epsilon-free weights
         from paper_1708_05944_amd import surrogate
+        log = lambda m: print(m, file=sys.stderr, flush=True)
         tr = workloads.surrogate_descs(args.warm_train, workloads.SURROGATE_TRAIN_SEED, N_R=32, Kn_max=0.2)
         ho = workloads.surrogate_descs(args.warm_heldout, workloads.SURROGATE_HELDOUT_SEED, N_R=32, Kn_max=0.2)
         for d in tr + ho:
             d.weno_eps = 1e-6
-        warm = surrogate.warm_start_comparison(tr, ho, epochs=1000, batch=256, lr=1e-3, probe=500,
-                                               max_steps=200_000, chunk=5_000,
-                                               log=lambda m: print(m, file=sys.stderr, flush=True))
-        warm["workload"] = (f"{len(tr)} training / {len(ho)} held-out Couette instances of the sweep generator "
-                            f"(seeds 1 / 2) with Kn <= 0.2, 32 cells, weno_eps 1e-6; cold = FP64 from rest, "
-                            f"warm = surrogate (bf16 inference) + FP64 acceptance probe, mixed precision")
+        ho0 = workloads.surrogate_descs(args.warm_heldout, workloads.SURROGATE_HELDOUT_SEED, N_R=32, Kn_max=0.2)
+        log(f"warm start: {len(tr)} training solves")
+        warm = surrogate.warm_start_comparison(tr, ho, epochs=args.warm_epochs, batch=256, lr=1e-3, probe=500,
+                                               max_steps=200_000, chunk=10_000, log=log,
+                                               extra=None if args.no_eps_free else {"epsilon_free": ho0})
+        warm["workload"] = (f"learned warm start, weno_eps 1e-6: {len(tr)} training / {len(ho)} held-out Couette "
+                            f"instances of the sweep generator (seeds 1 / 2) restricted to Kn <= 0.2 and 32 cells; "
+                            f"cold = rest state, warm = surrogate (bf16 inference) + 500-step FP64 acceptance probe "
+                            f"+ stall watch (cold restart after 10000 steps without a new residual low); each in FP64 "
+                            f"and in mixed precision (defect correction); non-converged instances count the whole "
+                            f"200000-step budget; 'extra.epsilon_free': the same held-out instances with the paper's "
+                            f"epsilon-free WENO weights, warm-started by the same network")
+        log("warm start done")
 
     out = {
         "metric": "site-velocity updates/s (batched Couette sweep, mixed precision: FP32 streaming)",
@@ -391,7 +474,7 @@ def main():
         torch.cuda.synchronize()
         out["copy_ref_bytes"] = n
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_instances, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_instances, args.cpu_steps, args.cpu_single, tts=not args.no_tts)
         if channel is not None:
             channel["cpu_baseline"] = channel_cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -181,12 +181,21 @@ vlb_status vlb_total_mass(vlb_batch* b, double* Ntot);
  * retires: the stage kernels stop advancing it while the others run, so its state,
  * moments and residual stay those of the step at which it converged.  steps / r (host
  * arrays of B, may be NULL) receive that step count (or -1) and the last residual.  Returns
- * VLB_ENOTCONV if some instance did not converge.  For VLB_MIXED batches the run
- * starts with FP32 steps until the largest residual is below max(tol, 1e-5) or stops
- * falling (the FP32 rounding floor is about 6e-8/dt), then continues in FP64, so the
- * final state is an FP64 fixed point; vlb_mixed_fp32_steps reports the FP32 steps.  A
- * call that follows one which ended in its FP64 phase, with no state change in between
- * (set_state, init_equilibrium, warm_start, set_wall, vlb_step), continues in FP64. */
+ * VLB_ENOTCONV if some instance did not converge.  The residual judged is always the
+ * FP64 one of the plain solver (one FP64 RK3 step of the current iterate).
+ * VLB_MIXED batches reach the FP64 steady state by defect correction: each check takes
+ * one FP64 step (the residual), then the FP64 defect R = L[F] (Eq. L_def, one FP64
+ * operator application) drives check_every - 1 FP32 steps of the correction equation
+ * d delta/dt = R + J delta from delta = 0, J being the operator linearised about F
+ * (advection, force and walls as for a state, BGK linearised about the FP64 moments),
+ * with delta stored and streamed in FP32 at its own scale; then F += delta in FP64.  The
+ * fixed point is the FP64 one (R = 0), so the final state is an FP64 steady state while
+ * nearly every step streams FP32; vlb_mixed_fp32_steps reports the FP32 steps taken since
+ * the state was last replaced.  Consecutive calls continue the same iteration.
+ * Instances started from the surrogate (vlb_batch_warm_start) are watched: one whose
+ * residual has set no new low (by 1 %) for the stall window (vlb_batch_set_stall_window,
+ * default 10000 steps) is restarted from the cold rest state and continues as a cold
+ * start (vlb_batch_warm_report). */
 vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check_every, long* steps, double* r);
 vlb_status vlb_mixed_fp32_steps(const vlb_batch* b, long* n);
 
@@ -284,6 +293,13 @@ vlb_status vlb_batch_surrogate_samples(vlb_batch* b, float* X, float* T, size_t 
  * rejects it).  used_warm (host array of B, may be NULL) receives 1 where the warm
  * start is kept.  Leaves the state in the FP64 buffers.  Synchronises. */
 vlb_status vlb_batch_warm_start(vlb_batch* b, vlb_mlp* m, int probe_steps, int* used_warm);
+/* The cold-start fallback of warm-started instances in vlb_run_to_steady: steps >= 1 of
+ * the stall window (default 10000).  The report gives, per instance (host arrays of B,
+ * each may be NULL), 1 while it still runs from its warm start, and the number of
+ * vlb_run_to_steady steps (summed over calls since the state was replaced) at which it
+ * was restarted cold (-1: never).  The stall watch also spans calls. */
+vlb_status vlb_batch_set_stall_window(vlb_batch* b, long steps);
+vlb_status vlb_batch_warm_report(const vlb_batch* b, int* on_warm, long* fallback_at);
 
 /* ---- Steps without device allocation --------------------------------------------
  *

@@ -24,18 +24,18 @@ hipError_t launch_wide_stage(int NR, int Q1, int Q2, hipStream_t st, const WideA
 size_t stage_lds(int kmax, int elem);
 hipError_t launch_moments(int fp32, int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
                           const double* tab, const void* F, double* msum);
-hipError_t launch_convert(int to32, int nblocks, hipStream_t st, const InstDesc* insts32, const WorkItem* work,
-                          const double* tab, double* F64, float* F32);
+hipError_t launch_convert(int mode, int nblocks, hipStream_t st, const InstDesc* insts32, const WorkItem* work,
+                          const double* tab, double* F64, float* F32, const double* theta = nullptr);
 hipError_t launch_reduce(int ninst, hipStream_t st, const InstDesc* insts, const double* tab, const double* rpart,
                          const double* msum, double* resid, double* mass, int want_resid);
-hipError_t launch_rescale(int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
-                          const double* target, const double* current, double* F);
 hipError_t launch_diag(int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
                        const double* tab, const double* F, double* diag);
 hipError_t launch_warm_profile(int ninst, hipStream_t st, const InstDesc* insts, const double* tab, const float* Y,
                                const double* par, double* prof);
 hipError_t launch_init_profile(int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
-                               const double* tab, const double* prof, double* F);
+                               const double* tab, const double* prof, const double* par, double* F);
+hipError_t launch_lin_prep(int nblocks, hipStream_t st, const InstDesc* insts32, const WorkItem* work,
+                           const double* tab, const double* msum, double* lin_cell, float4* lin_node);
 }  // namespace vlb
 
 using namespace vlb;
@@ -114,14 +114,34 @@ struct vlb_batch {
     std::vector<double> tab;
     size_t state_n = 0, ncells = 0;
     // workspace layout (byte offsets)
-    size_t off_F[3], off_F32[3], off_M[3], off_rpart, off_resid, off_mass, off_tab, off_desc, off_desc32, off_work,
-        off_diag, off_mass0, off_blocks, off_prof, off_wpar, off_sfeat, off_sy, off_wide, total_bytes;
+    size_t off_F[3], off_F32[4], off_M[3], off_rpart, off_lincell, off_linnode, off_theta, off_resid, off_mass, off_tab, off_desc, off_desc32, off_work,
+        off_diag, off_blocks, off_prof, off_wpar, off_sfeat, off_sy, off_wide, total_bytes;
     size_t wide_n = 0;                  // doubles of the large-velocity-set scratch region
     std::vector<char> active;          // instances the stage kernels advance (run_to_steady retires converged ones)
     int precision = VLB_FP64;
     bool cur32 = false;                 // the current state lives in the FP32 buffers
-    long fp32_steps = 0;                // steps of the FP32 phase of the last run_to_steady
-    bool polishing = false;             // the last run_to_steady ended in its FP64 phase, state untouched since
+    long fp32_steps = 0;                // FP32 (defect-correction) steps of run_to_steady since the state was set
+    bool lin = false;                   // stage launches run the linearised FP32 kernel (defect correction)
+    size_t lin_nodes = 0;               // entries of the per-node table of the linearised kernel
+    // learned warm start: instances still on their warm start, the step of a cold restart
+    // (-1: none) and the stall window that triggers one
+    std::vector<char> warm;
+    std::vector<long> fallback_at;
+    long stall_window = 10000;
+    // run_to_steady steps since the state was replaced, and per warm instance the lowest
+    // residual so far and the step count at which it was reached (kept across calls)
+    long run_steps = 0;
+    std::vector<double> best_res;
+    std::vector<long> best_at;
+    // defect correction: per-instance relaxation of the update (halved, down to 1/8, after
+    // three checks in a row without a new residual low, doubled back towards 1 after eight
+    // in a row with one), the lowest residual, when it was set and the run of checks
+    // without / with a new low, and the switch to FP64 steps for the rest of the run when
+    // some instance sets no new low for kDcWindow steps
+    std::vector<double> theta, dc_best;
+    std::vector<long> dc_best_at;
+    std::vector<int> dc_miss, dc_hit;
+    bool dc_off = false;
     std::vector<InstDesc> desc32;       // FP32 descriptors (rescaled tables)
     char* ws = nullptr;
     bool owns = false;
@@ -130,18 +150,20 @@ struct vlb_batch {
     bool timing = false;
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;   // private stream used only to capture step graphs
-    hipGraphExec_t graph[2] = {nullptr, nullptr};   // [fp32]: kGraphSteps steps without residual
+    hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};   // [FP64, FP32, linearised FP32]: kGraphSteps steps
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
 
     double* F(int i) { return (i == 0 && ext_F0) ? ext_F0 : (double*)(ws + off_F[i]); }
     float* F32(int i) { return (float*)(ws + off_F32[i]); }
+    double* lincell() { return (double*)(ws + off_lincell); }
+    double* dtheta() { return (double*)(ws + off_theta); }
+    float4* linnode() { return (float4*)(ws + off_linnode); }
     InstDesc* ddesc32() { return (InstDesc*)(ws + off_desc32); }
     double* M(int i) { return (double*)(ws + off_M[i]); }
     double* rpart() { return (double*)(ws + off_rpart); }
     double* resid() { return (double*)(ws + off_resid); }
     double* massv() { return (double*)(ws + off_mass); }
-    double* mass0() { return (double*)(ws + off_mass0); }
     double* dtab() { return (double*)(ws + off_tab); }
     InstDesc* ddesc() { return (InstDesc*)(ws + off_desc); }
     WorkItem* dwork() { return (WorkItem*)(ws + off_work); }
@@ -266,18 +288,39 @@ vlb_status ensure_precision(vlb_batch* b, bool want32) {
     if (b->cur32 == want32) return VLB_OK;
     if (want32 && b->precision != VLB_MIXED) return fail(VLB_ESTATE, "batch has no FP32 buffers");
     const int nblocks = (int)(b->work.size() / kWavesPerBlock);
-    HIP_TRY(launch_convert(want32 ? 1 : 0, nblocks, b->stream, b->ddesc32(), b->dwork(), b->dtab(), b->F(0),
+    HIP_TRY(launch_convert(want32 ? kConvTo32 : kConvFrom32, nblocks, b->stream, b->ddesc32(), b->dwork(), b->dtab(), b->F(0),
                            b->F32(0)));
     b->cur32 = want32;
     return refresh_moments(b);
 }
 
+// A replaced state starts a new run: no FP32 steps, no steps, warm flags from `warm`
+// (NULL: none), no cold restarts, no stall record.
+void reset_run_state(vlb_batch* b, const int* warm) {
+    b->fp32_steps = 0;
+    b->run_steps = 0;
+    b->warm.assign(b->B, 0);
+    if (warm) for (int i = 0; i < b->B; ++i) b->warm[i] = warm[i] > 0;
+    b->fallback_at.assign(b->B, -1);
+    b->best_res.assign(b->B, INFINITY);
+    b->best_at.assign(b->B, 0);
+    b->theta.assign(b->B, 1.0);
+    b->dc_miss.assign(b->B, 0);
+    b->dc_hit.assign(b->B, 0);
+    b->dc_best.assign(b->B, INFINITY);
+    b->dc_best_at.assign(b->B, 0);
+    b->dc_off = false;
+}
+
+vlb_status init_from_surrogate(vlb_batch* b, const std::vector<int>& use);
+
 vlb_status set_state_device(vlb_batch* b, const double* host) {
     HIP_TRY(hipMemcpyAsync(b->F(0), host, b->state_n * sizeof(double), hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     b->cur32 = false;
-    b->polishing = false;
+    b->lin = false;
     b->have_resid = false;
+    reset_run_state(b, nullptr);
     return refresh_moments(b);
 }
 
@@ -304,16 +347,21 @@ vlb_status layout_and_alloc(vlb_batch* b, bool alloc, bool ext_state = false) {
         b->off_F[i] = off;
         if (!(i == 0 && ext_state)) off = align256(off + b->state_n * sizeof(double));
     }
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < 4; ++i) {   // three RK buffers and the defect correction's forcing
         b->off_F32[i] = off;
         if (b->precision == VLB_MIXED) off = align256(off + b->state_n * sizeof(float));
     }
+    b->off_lincell = off;
+    if (b->precision == VLB_MIXED) off = align256(off + b->ncells * kLinCell * sizeof(double));
+    b->off_linnode = off;
+    if (b->precision == VLB_MIXED) off = align256(off + b->lin_nodes * sizeof(float4));
+    b->off_theta = off;
+    off = align256(off + b->B * sizeof(double));
     for (int i = 0; i < 3; ++i) { b->off_M[i] = off; off = align256(off + b->ncells * 5 * sizeof(double)); }
     b->off_rpart = off; off = align256(off + b->ncells * 4 * sizeof(double));
     b->off_diag = off; off = align256(off + b->ncells * 7 * sizeof(double));
     b->off_resid = off; off = align256(off + b->B * sizeof(double));
     b->off_mass = off; off = align256(off + b->B * sizeof(double));
-    b->off_mass0 = off; off = align256(off + b->B * sizeof(double));
     b->off_tab = off; off = align256(off + b->tab.size() * sizeof(double));
     b->off_desc = off; off = align256(off + b->desc.size() * sizeof(InstDesc));
     b->off_desc32 = off; off = align256(off + b->desc32.size() * sizeof(InstDesc));
@@ -345,14 +393,12 @@ vlb_status finish_setup(vlb_batch* b) {
         vlb_status s2 = upload_blocks(b);
         if (s2 != VLB_OK) return s2;
     }
-    // rest state n = 1, u = 0, T = T_in
-    std::vector<double> host(b->state_n);
-    for (int i = 0; i < b->B; ++i) {
-        const InstHost& h = b->inst[i];
-        std::vector<double> n(h.d.N_R, 1.0), z(h.d.N_R, 0.0), T(h.d.N_R, h.d.T_in);
-        equilibrium_state(h, n.data(), z.data(), z.data(), T.data(), host.data() + b->desc[i].offF);
-    }
-    return set_state_device(b, host.data());
+    // rest state n = 1, u = 0, T = T_in, built on the device exactly as the cold restart
+    // of a stuck warm start
+    st = init_from_surrogate(b, std::vector<int>(b->B, 0));
+    if (st != VLB_OK) return st;
+    reset_run_state(b, nullptr);
+    return VLB_OK;
 }
 
 bool check_instance(vlb_batch* b, int inst) { return b && inst >= 0 && inst < b->B; }
@@ -367,6 +413,13 @@ vlb_status run_stage(vlb_batch* b, int stage, bool last, bool l_only) {
     A.tab = b->dtab();
     A.rpart = nullptr;
     A.C = nullptr;
+    A.lin_cell = nullptr;
+    A.lin_node = nullptr;
+    if (b->lin && f32) {   // linearised FP32 stage about the defect correction's base state
+        A.lin_cell = b->lincell();
+        A.lin_node = b->linnode();
+        A.C = b->F32(3);
+    }
     A.l_only = l_only ? 1 : 0;
     if (l_only) {
         A.Fin = Fb(0); A.Fn = Fb(0); A.Fout = Fb(1);
@@ -384,7 +437,7 @@ vlb_status run_stage(vlb_batch* b, int stage, bool last, bool l_only) {
         A.Fin = Fb(2); A.Fn = Fb(0); A.Fout = Fb(0);
         A.msum_in = b->M(2); A.msum_out = b->M(0);
         A.ca = 1.0 / 3.0; A.cb = 2.0 / 3.0; A.cc = 2.0 / 3.0;
-        if (last) A.rpart = b->rpart();
+        if (last && !A.lin_cell) A.rpart = b->rpart();
     }
     const double values = (l_only || stage == 0) ? 2.0 : 3.0;   // algorithmic HBM values per population
     const double elem = f32 ? sizeof(float) : sizeof(double);
@@ -441,6 +494,7 @@ vlb_status run_stage(vlb_batch* b, int stage, bool last, bool l_only) {
 }
 
 constexpr int kGraphSteps = 10;
+constexpr long kDcWindow = 20000;   // steps without a new residual low that end the defect correction
 
 void drop_graphs(vlb_batch* b) {
     for (hipGraphExec_t& g : b->graph)
@@ -506,7 +560,7 @@ vlb_status upload_blocks(vlb_batch* b) {
 vlb_status step_current(vlb_batch* b, long nsteps) {
     // all but the last step: replay captured chunks of kGraphSteps steps
     if (b->use_graphs && !b->timing && nsteps > kGraphSteps) {
-        hipGraphExec_t& g = b->graph[b->cur32 ? 1 : 0];
+        hipGraphExec_t& g = b->graph[b->cur32 ? (b->lin ? 2 : 1) : 0];
         if (!g) {
             vlb_status s = capture_steps(b, &g);
             if (s != VLB_OK) return s;
@@ -522,7 +576,7 @@ vlb_status step_current(vlb_batch* b, long nsteps) {
             vlb_status s = run_stage(b, st, last, false);
             if (s != VLB_OK) return s;
         }
-        if (last) {
+        if (last && !b->lin) {
             HIP_TRY(launch_reduce(b->B, b->stream, b->cur32 ? b->ddesc32() : b->ddesc(), b->dtab(), b->rpart(), b->M(0),
                                   b->resid(), b->massv(), 1));
             b->have_resid = true;
@@ -537,6 +591,35 @@ vlb_status read_residual(vlb_batch* b, double* r) {
     for (int i = 0; i < b->B; ++i)
         if (!std::isfinite(r[i])) return fail(VLB_ENONFINITE, "non-finite residual in instance %d", i);
     return VLB_OK;
+}
+
+// One defect-correction pass of the mixed path, on the FP64 iterate F64 in F(0) (with
+// its moment sums in M(0)): the FP64 defect R = L64[F64]; then m RK3 steps in FP32 of the
+// correction equation d delta/dt = R + J delta from delta = 0, where J is the FP32
+// operator linearised about F64 (linearised FP32 stage kernel); then F64 += delta.  The
+// correction is stored and streamed in FP32 at its own scale, so its rounding is
+// relative to delta, not to F; at a fixed point of the outer iteration R = 0, i.e. the
+// FP64 steady state.  Leaves F(0) and M(0) current in FP64.
+vlb_status defect_correction(vlb_batch* b, long m) {
+    const int nblocks = (int)(b->work.size() / kWavesPerBlock);
+    HIP_TRY(launch_lin_prep(nblocks, b->stream, b->ddesc32(), b->dwork(), b->dtab(), b->M(0), b->lincell(),
+                            b->linnode()));
+    vlb_status s = run_stage(b, 0, false, true);   // R = L64[F64] into F(1)
+    if (s != VLB_OK) return s;
+    HIP_TRY(launch_convert(kConvTo32, nblocks, b->stream, b->ddesc32(), b->dwork(), b->dtab(), b->F(1), b->F32(3)));
+    HIP_TRY(launch_convert(kConvZero32, nblocks, b->stream, b->ddesc32(), b->dwork(), b->dtab(), b->F(0), b->F32(0)));
+    HIP_TRY(launch_moments(1, nblocks, b->stream, b->ddesc32(), b->dwork(), b->dtab(), b->F32(0), b->M(0)));
+    b->cur32 = true;
+    b->lin = true;
+    s = step_current(b, m);
+    b->cur32 = false;
+    b->lin = false;
+    if (s != VLB_OK) return s;
+    HIP_TRY(hipMemcpyAsync(b->dtheta(), b->theta.data(), b->B * sizeof(double), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(launch_convert(kConvAdd, nblocks, b->stream, b->ddesc32(), b->dwork(), b->dtab(), b->F(0), b->F32(0),
+                           b->dtheta()));
+    b->have_resid = false;
+    return refresh_moments(b);
 }
 
 }  // namespace
@@ -664,6 +747,8 @@ vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_de
         D.T_out = d.T_out;
         D.offF = (long long)offF;
         D.offC = (long long)offC;
+        D.offG = (long long)b->lin_nodes;
+        b->lin_nodes += (size_t)d.N_R * (h.a1.nodes + h.a2.nodes);
         D.offT = (long long)b->tab.size();
         auto put = [&](const std::vector<double>& v) {
             int o = (int)(b->tab.size() - D.offT);
@@ -855,7 +940,6 @@ vlb_status vlb_set_wall(vlb_batch* b, int inst, int side, double u, double T) {
         InstDesc& E = b->desc32[inst];
         E.den_in = D.den_in; E.den_out = D.den_out; E.T_in = D.T_in; E.T_out = D.T_out;
     }
-    b->polishing = false;
     HIP_TRY(hipStreamSynchronize(b->stream));
     return upload_tables(b);
 }
@@ -907,7 +991,6 @@ vlb_status vlb_step(vlb_batch* b, long nsteps) {
     if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
     vlb_status s = ensure_precision(b, b->precision == VLB_MIXED);
     if (s != VLB_OK) return s;
-    b->polishing = false;
     return step_current(b, nsteps);
 }
 
@@ -927,7 +1010,7 @@ vlb_status vlb_apply_L(vlb_batch* b, double* L, size_t n) {
     if (b->cur32) {
         // unscale the FP32 result into the FP64 scratch buffer (F * W on the device)
         const int nblocks = (int)(b->work.size() / kWavesPerBlock);
-        HIP_TRY(launch_convert(0, nblocks, b->stream, b->ddesc32(), b->dwork(), b->dtab(), b->F(1), b->F32(1)));
+        HIP_TRY(launch_convert(kConvFrom32, nblocks, b->stream, b->ddesc32(), b->dwork(), b->dtab(), b->F(1), b->F32(1)));
     }
     HIP_TRY(hipMemcpyAsync(L, b->F(1), n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
@@ -975,43 +1058,16 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
     std::vector<long> conv(b->B, -1);
     std::vector<double> res(b->B, INFINITY);
     long done = 0;
-    vlb_status s = VLB_OK;
-    if (b->precision == VLB_MIXED && !b->polishing) {
-        // FP32 phase: stream the scaled FP32 state while every instance's residual still
-        // falls; stop at 1e-5 (the FP32 rounding floor is eps32/dt) or when the largest
-        // residual stops improving by 5% over three checks.
-        // the steady state of a closed Couette cell depends on its particle number, which
-        // FP32 rounding lets drift: record it in FP64 first
-        s = ensure_precision(b, false);
-        if (s != VLB_OK) return s;
-        HIP_TRY(launch_reduce(b->B, b->stream, b->ddesc(), b->dtab(), b->rpart(), b->M(0), b->resid(), b->mass0(), 0));
-        s = ensure_precision(b, true);
-        if (s != VLB_OK) return s;
-        double best = INFINITY;
-        int stall = 0;
-        while (done < max_steps) {
-            const long n = std::min<long>(check_every, max_steps - done);
-            s = step_current(b, n);
-            if (s != VLB_OK) return s;
-            done += n;
-            s = read_residual(b, res.data());
-            if (s != VLB_OK) return s;
-            const double worst = *std::max_element(res.begin(), res.end());
-            if (worst < std::max(tol, 1e-5)) break;
-            if (worst < 0.95 * best) { best = worst; stall = 0; } else if (++stall >= 3) break;
-        }
-        b->fp32_steps = done;
-        s = ensure_precision(b, false);
-        if (s != VLB_OK) return s;
-        // restore the particle number of every instance (scale both distributions)
-        const int nblocks = (int)(b->work.size() / kWavesPerBlock);
-        HIP_TRY(launch_reduce(b->B, b->stream, b->ddesc(), b->dtab(), b->rpart(), b->M(0), b->resid(), b->massv(), 0));
-        HIP_TRY(launch_rescale(nblocks, b->stream, b->ddesc(), b->dwork(), b->mass0(), b->massv(), b->F(0)));
-        s = refresh_moments(b);
-        if (s != VLB_OK) return s;
-    }
-    s = ensure_precision(b, false);
+    vlb_status s = ensure_precision(b, false);
     if (s != VLB_OK) return s;
+    const bool mixed = b->precision == VLB_MIXED;
+    if (b->theta.size() != (size_t)b->B) reset_run_state(b, nullptr);
+    if (b->warm.size() != (size_t)b->B) b->warm.assign(b->B, 0);
+    if (b->fallback_at.size() != (size_t)b->B) b->fallback_at.assign(b->B, -1);
+    if (b->best_res.size() != (size_t)b->B) b->best_res.assign(b->B, INFINITY);
+    if (b->best_at.size() != (size_t)b->B) b->best_at.assign(b->B, 0);
+    std::vector<double>& best = b->best_res;
+    std::vector<long>& best_at = b->best_at;
     // converged instances retire: the stage kernels stop advancing them (their state,
     // moments and residual stay at the converged step); all are reinstated on return
     struct Reinstate {
@@ -1026,28 +1082,97 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
     } guard{b};
     int remaining = b->B;
     while (done < max_steps && remaining > 0) {
-        const long n = std::min<long>(check_every, max_steps - done);
+        // FP64 steps: the plain solver's residual of the current iterate (mixed batches
+        // take one, then check_every - 1 defect-correction steps in FP32)
+        const bool dc = mixed && !b->dc_off;
+        const long n = dc ? 1 : std::min<long>(check_every, max_steps - done);
         s = step_current(b, n);
         if (s != VLB_OK) return s;
         done += n;
+        b->run_steps += n;
         s = read_residual(b, res.data());
         if (s != VLB_OK) return s;
         bool retired = false;
-        for (int i = 0; i < b->B; ++i)
-            if (conv[i] < 0 && res[i] < tol) {
+        std::vector<int> restart(b->B, -1);
+        bool any_restart = false;
+        for (int i = 0; i < b->B; ++i) {
+            if (conv[i] >= 0) continue;
+            if (res[i] < tol) {
                 conv[i] = done;
                 --remaining;
                 if (b->active.empty()) b->active.assign(b->B, 1);
                 b->active[i] = 0;
                 retired = guard.dirty = true;
+                continue;
             }
+            if (!b->warm[i]) continue;
+            // a warm start whose residual has not set a new low (by 1 %) for stall_window
+            // steps is judged stuck and restarted from the cold rest state
+            if (res[i] < 0.99 * best[i]) {
+                best[i] = res[i];
+                best_at[i] = b->run_steps;
+            } else if (b->run_steps - best_at[i] >= b->stall_window) {
+                restart[i] = 0;
+                any_restart = true;
+                b->warm[i] = 0;
+                b->fallback_at[i] = b->run_steps;
+            }
+        }
+        if (any_restart) {
+            s = init_from_surrogate(b, restart);
+            if (s != VLB_OK) return s;
+            for (int i = 0; i < b->B; ++i)
+                if (restart[i] == 0) {
+                    b->theta[i] = 1.0;
+                    b->dc_miss[i] = 0;
+                    b->dc_hit[i] = 0;
+                    b->dc_best[i] = INFINITY;
+                    b->dc_best_at[i] = b->run_steps;
+                }
+        }
+        if (dc) {
+            // relaxation of the defect correction: an instance that sets no new residual low
+            // (by 1 %) at three checks in a row has its update halved (a mode the linearised
+            // operator overshoots otherwise makes the iteration cycle), one that sets eight
+            // in a row has it doubled back towards the full correction; no new low for
+            // kDcWindow steps on any instance ends the correction for this run: FP64 steps
+            // from then on
+            for (int i = 0; i < b->B; ++i) {
+                if (conv[i] >= 0) continue;
+                if (res[i] < 0.99 * b->dc_best[i]) {
+                    b->dc_best[i] = res[i];
+                    b->dc_best_at[i] = b->run_steps;
+                    b->dc_miss[i] = 0;
+                    if (++b->dc_hit[i] >= 8) {
+                        b->theta[i] = std::min(1.0, 2.0 * b->theta[i]);
+                        b->dc_hit[i] = 0;
+                    }
+                    continue;
+                }
+                b->dc_hit[i] = 0;
+                if (++b->dc_miss[i] >= 3) {
+                    b->theta[i] = std::max(0.125, 0.5 * b->theta[i]);
+                    b->dc_miss[i] = 0;
+                }
+                if (b->run_steps - b->dc_best_at[i] >= kDcWindow) b->dc_off = true;
+            }
+        }
         if (retired && remaining > 0) {
             build_blocks(b, b->tile);
             s = upload_blocks(b);
             if (s != VLB_OK) return s;
         }
+        if (dc && !b->dc_off && remaining > 0 && done < max_steps) {
+            const long m = std::min<long>(check_every - 1, max_steps - done);
+            if (m > 0) {
+                s = defect_correction(b, m);
+                if (s != VLB_OK) return s;
+                done += m;
+                b->run_steps += m;
+                b->fp32_steps += m;
+            }
+        }
     }
-    b->polishing = true;
     if (steps) std::copy(conv.begin(), conv.end(), steps);
     if (r) std::copy(res.begin(), res.end(), r);
     return remaining ? fail(VLB_ENOTCONV, "%d instance(s) above tol after %ld steps", remaining, done) : VLB_OK;
@@ -1202,22 +1327,23 @@ void surrogate_features(const vlb_batch* b, float* X) {
     }
 }
 
-// State of every instance from the surrogate outputs in sy(): warm (use[i] = 1) or the
-// cold rest state; FP64 buffers.
+// Initial state of the instances from the surrogate outputs in sy(): use[i] = 1 warm,
+// 0 the cold rest state, -1 left as it is; FP64 buffers.
 vlb_status init_from_surrogate(vlb_batch* b, const std::vector<int>& use) {
     std::vector<double> par(2 * (size_t)b->B);
     for (int i = 0; i < b->B; ++i) {
         par[2 * i] = b->inst[i].d.u_in;
-        par[2 * i + 1] = use[i] ? 1.0 : 0.0;
+        par[2 * i + 1] = use[i] > 0 ? 1.0 : (use[i] == 0 ? 0.0 : -1.0);
     }
     HIP_TRY(hipMemcpyAsync(b->wpar(), par.data(), par.size() * sizeof(double), hipMemcpyHostToDevice, b->stream));
     HIP_TRY(launch_warm_profile(b->B, b->stream, b->ddesc(), b->dtab(), b->sy(), b->wpar(), b->prof()));
     const int nblocks = (int)(b->work.size() / kWavesPerBlock);
-    HIP_TRY(launch_init_profile(nblocks, b->stream, b->ddesc(), b->dwork(), b->dtab(), b->prof(), b->F(0)));
+    HIP_TRY(launch_init_profile(nblocks, b->stream, b->ddesc(), b->dwork(), b->dtab(), b->prof(), b->wpar(),
+                                b->F(0)));
     HIP_TRY(hipStreamSynchronize(b->stream));
     b->cur32 = false;
+    b->lin = false;
     b->have_resid = false;
-    b->polishing = false;
     return refresh_moments(b);
 }
 
@@ -1286,7 +1412,23 @@ vlb_status vlb_batch_warm_start(vlb_batch* b, vlb_mlp* m, int probe_steps, int* 
     }
     s = init_from_surrogate(b, use);
     if (s != VLB_OK) return s;
+    reset_run_state(b, use.data());
     if (used_warm) std::copy(use.begin(), use.end(), used_warm);
+    return VLB_OK;
+}
+
+vlb_status vlb_batch_set_stall_window(vlb_batch* b, long steps) {
+    if (!b || steps < 1) return fail(VLB_EINVAL, "stall window must be >= 1 step");
+    b->stall_window = steps;
+    return VLB_OK;
+}
+
+vlb_status vlb_batch_warm_report(const vlb_batch* b, int* on_warm, long* fallback_at) {
+    if (!b) return fail(VLB_EINVAL, "null batch");
+    for (int i = 0; i < b->B; ++i) {
+        if (on_warm) on_warm[i] = i < (int)b->warm.size() ? b->warm[i] : 0;
+        if (fallback_at) fallback_at[i] = i < (int)b->fallback_at.size() ? b->fallback_at[i] : -1;
+    }
     return VLB_OK;
 }
 

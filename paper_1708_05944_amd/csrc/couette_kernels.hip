@@ -30,88 +30,109 @@ namespace vlb {
 
 
 
-// sum_i a[i] b[i], i < n (n a multiple of 4, both pointers 16-byte aligned LDS), in
-// index order with 16-byte vector reads
+// 16 x 16 x 4 matrix-core products (one per wavefront): the A operand of lane l is
+// element (l mod 16, l / 16) of a 16 x 4 block, the B operand element (l / 16, l mod 16)
+// of a 4 x 16 block; register r of lane group g = l / 16 returns row 4 g + r (FP32 form)
+// or g + 4 r (FP64 form) of the 16 x 16 product, column l mod 16.
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
 template <typename T>
-__device__ __forceinline__ T dot_lds(const T* a, const T* b, int n);
+struct Mfma;
 template <>
-__device__ __forceinline__ float dot_lds<float>(const float* a, const float* b, int n) {
-    float acc = 0.f;
-    for (int i = 0; i < n; i += 4) {
-        const float4 x = *reinterpret_cast<const float4*>(a + i), y = *reinterpret_cast<const float4*>(b + i);
-        acc += x.x * y.x;
-        acc += x.y * y.y;
-        acc += x.z * y.z;
-        acc += x.w * y.w;
+struct Mfma<float> {
+    typedef mf_f4 V;
+    static __device__ __forceinline__ V op(float a, float b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
-    return acc;
-}
+    static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
+};
 template <>
-__device__ __forceinline__ double dot_lds<double>(const double* a, const double* b, int n) {
-    double acc = 0.0;
-    for (int i = 0; i < n; i += 2) {
-        const double2 x = *reinterpret_cast<const double2*>(a + i), y = *reinterpret_cast<const double2*>(b + i);
-        acc += x.x * y.x;
-        acc += x.y * y.y;
+struct Mfma<double> {
+    typedef mf_d4 V;
+    static __device__ __forceinline__ V op(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
-    return acc;
+    static __device__ __forceinline__ int row(int g, int r) { return g + 4 * r; }
+};
+
+// The two momentum-derivative contractions of the force term for one cell of a run,
+// on the matrix cores (Sec. IV.C, Eqs. df_K_hh, dfp_K_H with the kernels of the axes):
+//   r1[i][j] = sum_i' K1[i][i'] F[i'][j]   and   r2[i][j] = sum_j' Kt2[j][j'] F[i][j'],
+// F the cell's populations as a Q1 x Q2 matrix (k = i Q2 + j) in LDS, K1 / Kt2 the kernel
+// rows in LDS with strides P1 / P2, results in LDS in the population order.  The 16 x 16
+// output tiles of both products are jobs, dealt round robin to the run's nw wavefronts
+// (lw = this wavefront's index in the run); the contraction index i' (j') of k-step kk is
+// KS g + kk in lane group g, so each lane group walks its own contiguous quarter of the
+// index range.  Operands outside the matrices are zero.
+template <typename T>
+__device__ __forceinline__ void force_mfma(const T* Fr, const T* K1s, const T* Kt2s, int P1, int P2, int Q1,
+                                           int Q2, int lw, int nw, int lane, T* r1, T* r2) {
+    typedef typename Mfma<T>::V V;
+    const int g = lane >> 4, n = lane & 15;
+    const int MT = (Q1 + 15) >> 4, NT = (Q2 + 15) >> 4;
+    const int KS1 = (Q1 + 3) >> 2, KS2 = (Q2 + 3) >> 2;
+    const int njob = 2 * MT * NT;
+    for (int jb = lw; jb < njob; jb += nw) {
+        const bool first = jb < MT * NT;
+        const int tj = first ? jb : jb - MT * NT;
+        const int Mt = tj / NT, Nt = tj - Mt * NT;
+        const int im = 16 * Mt + n, jn = 16 * Nt + n;
+        V acc = {T(0), T(0), T(0), T(0)};
+        if (first) {
+            // A = K1 rows im, B = F rows i' (columns jn)
+            const int i0 = KS1 * g, nk = min(KS1, Q1 - i0);
+            const T* pa = K1s + im * P1 + i0;
+            const T* pb = Fr + i0 * Q2 + jn;
+            const bool ra = im < Q1, rb = jn < Q2;
+            for (int kk = 0; kk < KS1; ++kk) {
+                T a = T(0), b = T(0);
+                if (kk < nk) {
+                    if (ra) a = pa[kk];
+                    if (rb) b = pb[kk * Q2];
+                }
+                acc = Mfma<T>::op(a, b, acc);
+            }
+        } else {
+            // A = F rows im (columns j'), B = Kt2 rows jn transposed
+            const int j0 = KS2 * g, nk = min(KS2, Q2 - j0);
+            const T* pa = Fr + im * Q2 + j0;
+            const T* pb = Kt2s + jn * P2 + j0;
+            const bool ra = im < Q1, rb = jn < Q2;
+            for (int kk = 0; kk < KS2; ++kk) {
+                T a = T(0), b = T(0);
+                if (kk < nk) {
+                    if (ra) a = pa[kk];
+                    if (rb) b = pb[kk];
+                }
+                acc = Mfma<T>::op(a, b, acc);
+            }
+        }
+        T* out = first ? r1 : r2;
+        if (jn < Q2) {
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int i = 16 * Mt + Mfma<T>::row(g, rr);
+                if (i < Q1) out[i * Q2 + jn] = acc[rr];
+            }
+        }
+    }
 }
 
-// The two contractions of the force term, sum_i a1[i] b1[i] (i < n1) and sum_i a2[i] b2[i]
-// (i < n2), each in index order exactly as dot_lds; over the common length the reads of
-// both are issued together, so that one LDS round trip serves both (FP32 kernel; the FP64
-// kernel has no registers to spare and calls dot_lds twice).
-__device__ __forceinline__ void dot2_lds(const float* a1, const float* b1, int n1, const float* a2,
-                                         const float* b2, int n2, float& r1, float& r2) {
-    float acc1 = 0.f, acc2 = 0.f;
-    const int nc = n1 < n2 ? n1 : n2;
-    int i = 0;
-#pragma unroll 1
-    for (; i < nc; i += 4) {
-        const float4 x1 = *reinterpret_cast<const float4*>(a1 + i), y1 = *reinterpret_cast<const float4*>(b1 + i);
-        const float4 x2 = *reinterpret_cast<const float4*>(a2 + i), y2 = *reinterpret_cast<const float4*>(b2 + i);
-        acc1 += x1.x * y1.x;
-        acc1 += x1.y * y1.y;
-        acc1 += x1.z * y1.z;
-        acc1 += x1.w * y1.w;
-        acc2 += x2.x * y2.x;
-        acc2 += x2.y * y2.y;
-        acc2 += x2.z * y2.z;
-        acc2 += x2.w * y2.w;
-    }
-#pragma unroll 1
-    for (int j = i; j < n1; j += 4) {
-        const float4 x = *reinterpret_cast<const float4*>(a1 + j), y = *reinterpret_cast<const float4*>(b1 + j);
-        acc1 += x.x * y.x;
-        acc1 += x.y * y.y;
-        acc1 += x.z * y.z;
-        acc1 += x.w * y.w;
-    }
-#pragma unroll 1
-    for (int j = i; j < n2; j += 4) {
-        const float4 x = *reinterpret_cast<const float4*>(a2 + j), y = *reinterpret_cast<const float4*>(b2 + j);
-        acc2 += x.x * y.x;
-        acc2 += x.y * y.y;
-        acc2 += x.z * y.z;
-        acc2 += x.w * y.w;
-    }
-    r1 = acc1;
-    r2 = acc2;
-}
-
-// LDS layout of a stage block (bytes): kernel tables | two cell-row buffers (row-major
-// and transposed copies per run) | two equilibrium-factor buffers | per (run, cell):
+// LDS layout of a stage block (bytes): kernel tables | two buffers of three population
+// rows (one entry per thread: a cell's input, and the two force contractions of it) |
+// two equilibrium-factor buffers | per (run, cell):
 // n, T, 1/tau, equilibrium coefficients and geometry | equilibrium bases | moment and
 // residual partials per wavefront (two buffers) | wall-flux partials per wavefront.
-template <typename T>
+template <typename T, bool LIN = false>
 struct StageLds {
-    size_t ks, rows, gbuf, eqc, btab, mpart, nwpart, total;
+    size_t ks, rows, gbuf, gbd, eqc, btab, mpart, nwpart, total;
     __host__ __device__ StageLds(int kmax) {
         auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
         ks = 0;
         rows = al(ks + (size_t)kmax * sizeof(T));
-        gbuf = al(rows + 2 * (size_t)kRowElems * sizeof(T));
-        eqc = al(gbuf + 2 * (size_t)kMaxRuns * kWave * sizeof(T));
+        gbuf = al(rows + 2 * 3 * (size_t)kStageThreads * sizeof(T));
+        gbd = al(gbuf + 2 * (size_t)kMaxRuns * kWave * sizeof(T));
+        eqc = LIN ? al(gbd + 2 * (size_t)kMaxRuns * kWave * sizeof(T)) : gbd;
         btab = al(eqc + (size_t)kMaxRuns * kTileCells * kEqStride * sizeof(double));
         mpart = al(btab + (size_t)kWave * (kMaxN + 1) * sizeof(double));
         nwpart = al(mpart + 2 * (size_t)(kStageThreads / kWave) * 8 * 4 * sizeof(double));
@@ -119,11 +140,18 @@ struct StageLds {
     }
 };
 
-template <typename T>
+// LIN = true (FP32 only): the linearised stage of the defect correction.  The state is
+// a correction delta about a fixed base state; advection, force and walls act on it as
+// on a state (they are linear, apart from the WENO weights, which delta's own stencils
+// set); the BGK term is linearised about the base: -(delta - d f_eq)/tau_base with
+// d f'_eq = dn g1 g2 + n (dg1 g2 + g1 dg2), d f''_eq = T d f'_eq + dT n g1 g2, where dn, du,
+// dT follow from delta's moment sums and dg = du g_u + dT g_T from the per-node factors
+// of lin_prep (the variation of tau itself is left to the outer FP64 iteration).
+template <typename T, bool LIN>
 __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     extern __shared__ double smem_d[];
     char* smem = reinterpret_cast<char*>(smem_d);
-    const StageLds<T> lay(A.kmax);
+    const StageLds<T, LIN> lay(A.kmax);
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const BlockWork* bw = A.blocks + blockIdx.x;
     const int inst = __builtin_amdgcn_readfirstlane(bw->inst);
@@ -139,6 +167,7 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     T* Ks = reinterpret_cast<T*>(smem + lay.ks);
     T* rows = reinterpret_cast<T*>(smem + lay.rows);
     T* gbuf = reinterpret_cast<T*>(smem + lay.gbuf);
+    T* gbdb = reinterpret_cast<T*>(smem + lay.gbd);
     double* eqc = reinterpret_cast<double*>(smem + lay.eqc);
     double* btab = reinterpret_cast<double*>(smem + lay.btab);
     double* mpart = reinterpret_cast<double*>(smem + lay.mpart);
@@ -153,13 +182,10 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     const int vi = kk / Q2, vj = kk - vi * Q2;
     const T p1 = T(tab[I.tp1 + vi]), p2 = T(tab[I.tp2 + vj]);
 
-    // ---- prologue: kernels into LDS (rows of stride P1 / P2, zero beyond Q1 / Q2), both
-    // row buffers cleared (their padding stays zero); equilibrium coefficients of every
-    // (run, cell)
+    // ---- prologue: kernels into LDS (rows of stride P1 / P2, zero beyond Q1 / Q2);
+    // equilibrium coefficients of every (run, cell)
     constexpr int E = sizeof(T);
-    const int L1 = lds_len(Q1, E), L2 = lds_len(Q2, E);        // dot-product lengths
     const int P1 = lds_stride(Q1, E), P2 = lds_stride(Q2, E);  // LDS row strides
-    const int S = row_slot(Q1, Q2, E);
     const int n1 = Q1 * P1, n2 = Q2 * P2;
     for (int x = t; x < n1 + n2; x += kStageThreads) {
         T v = T(0);
@@ -172,20 +198,37 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
         }
         Ks[x] = v;
     }
-    for (int x = t; x < 2 * kRowElems; x += kStageThreads) rows[x] = T(0);
     const int N1 = I.N1, N2 = I.N2;
     for (int x = t; x < R * TC; x += kStageThreads) {
         const int rr = x / TC, cc = x - rr * TC, s = s0 + rr * TC + cc;
         if (s >= NR) continue;
         const double* ms = A.msum_in + (size_t)(I.offC + s) * 5;
-        const double n = ms[0], u1 = ms[1] / n, u2 = ms[2] / n;
-        const double T_ = (ms[3] + ms[4] - n * (u1 * u1 + u2 * u2)) / (3.0 * n);
         double* e = eqc + (size_t)x * kEqStride;
-        e[0] = n;
-        e[1] = T_;
-        e[2] = 1.0 / tau_of(I.tau_model, I.Kn, n, T_);
-        axis_coef(I.kind1, N1, u1, T_, tab + I.tC1, tab + I.tisf1, e + 3, e + 3 + (N1 + 1));
-        axis_coef(I.kind2, N2, u2, T_, tab + I.tC2, tab + I.tisf2, e + 3 + 2 * (N1 + 1), e + 3 + 2 * (N1 + 1) + (N2 + 1));
+        if constexpr (LIN) {
+            // base fields, and the first-order changes of n, u, T that delta's sums carry:
+            // E = sum(|p|^2 f' + f'') = 3 n T + n |u|^2
+            const double* lc = A.lin_cell + (size_t)(I.offC + s) * kLinCell;
+            const double n = lc[0], T_ = lc[1], u1 = lc[3], u2 = lc[4];
+            const double dn = ms[0], du1 = (ms[1] - u1 * dn) / n, du2 = (ms[2] - u2 * dn) / n;
+            const double dT = (ms[3] + ms[4] - (3.0 * T_ + u1 * u1 + u2 * u2) * dn - 2.0 * n * (u1 * du1 + u2 * du2)) /
+                              (3.0 * n);
+            e[0] = n;
+            e[1] = T_;
+            e[2] = lc[2];
+            e[3] = dn;
+            e[4] = dT;
+            e[5] = du1;
+            e[6] = du2;
+        } else {
+            const double n = ms[0], u1 = ms[1] / n, u2 = ms[2] / n;
+            const double T_ = (ms[3] + ms[4] - n * (u1 * u1 + u2 * u2)) / (3.0 * n);
+            e[0] = n;
+            e[1] = T_;
+            e[2] = 1.0 / tau_of(I.tau_model, I.Kn, n, T_);
+            axis_coef(I.kind1, N1, u1, T_, tab + I.tC1, tab + I.tisf1, e + 3, e + 3 + (N1 + 1));
+            axis_coef(I.kind2, N2, u2, T_, tab + I.tC2, tab + I.tisf2, e + 3 + 2 * (N1 + 1),
+                      e + 3 + 2 * (N1 + 1) + (N2 + 1));
+        }
         e[kEqGeo] = tab[I.tRf + s] / tab[I.tdchi + s];
         e[kEqGeo + 1] = tab[I.tRf + s + 1] / tab[I.tdchi + s];
         e[kEqGeo + 2] = tab[I.tdchi + s];
@@ -212,6 +255,13 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
         coff = 3 + 2 * (N1 + 1) + ((I.kind2 == 1 && j >= I.Qh2) ? nb : 0);
     }
 
+    // the run's first cell into row buffer 1: its force contractions are the matrix-core
+    // jobs before the sweep (each cell's are computed a cell ahead, into the buffer the
+    // sweep reads in the next cell)
+    const T* Kt = Ks + n1;
+    if (rlen > 0 && k < NV) rows[3 * kStageThreads + t] = (static_cast<const T*>(A.Fin) + I.offF +
+                                                        (size_t)dist * NR * NV + (size_t)rs0 * NV)[k];
+
     // ---- diffuse walls: n_w of Eq. nw, FP64 half-range sums reduced over the run
     const T* Fd = static_cast<const T*>(A.Fin) + I.offF + (size_t)dist * NR * NV;
     const T* Fp = static_cast<const T*>(A.Fin) + I.offF;
@@ -226,13 +276,13 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
         if (act && near_in && p1 < T(0)) {
             const T F1 = Fp[k], F2 = Fp[NV + k], F3 = Fp[2 * NV + k];
             const T g0 = T(3) * F1 - T(3) * F2 + F3, gm1 = T(6) * F1 - T(8) * F2 + T(3) * F3;
-            ain = (double)p1 * Wm[k] * (double)weno5<T>(F3, F2, F1, g0, gm1, weps);
+            ain = (double)p1 * Wm[k] * (double)weno5<T, LIN>(F3, F2, F1, g0, gm1, weps);
         }
         if (act && near_out && p1 > T(0)) {
             const T G1 = Fp[(size_t)(NR - 1) * NV + k], G2 = Fp[(size_t)(NR - 2) * NV + k],
                     G3 = Fp[(size_t)(NR - 3) * NV + k];
             const T g0 = T(3) * G1 - T(3) * G2 + G3, gp1 = T(6) * G1 - T(8) * G2 + T(3) * G3;
-            aout = (double)p1 * Wm[k] * (double)weno5<T>(G3, G2, G1, g0, gp1, weps);
+            aout = (double)p1 * Wm[k] * (double)weno5<T, LIN>(G3, G2, G1, g0, gp1, weps);
         }
         ain = wave_sum(ain);
         aout = wave_sum(aout);
@@ -240,6 +290,11 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     }
     __syncthreads();
     const int w0 = r * (nvpad / kWave), nw_waves = nvpad / kWave;
+    if (rlen > 0) {
+        T* rb = rows + 3 * kStageThreads + r * nvpad;
+        force_mfma<T>(rb, Ks, Kt, P1, P2, Q1, Q2, wave - w0, nw_waves, lane, rb + kStageThreads,
+                      rb + 2 * kStageThreads);
+    }
     double nw_in = 0.0, nw_out = 0.0;
     if (rlen > 0) {
         double sin_ = 0.0, sout = 0.0;
@@ -276,7 +331,7 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     if (act) {
         w0v = cell(rs0 - 3); w1v = cell(rs0 - 2); w2v = cell(rs0 - 1);
         w3v = cell(rs0);     w4v = cell(rs0 + 1); w5v = cell(rs0 + 2);
-        fl = weno_face<T>(pos, w0v, w1v, w2v, w3v, w4v, w5v, weps);
+        fl = weno_face<T, LIN>(pos, w0v, w1v, w2v, w3v, w4v, w5v, weps);
     }
     // ghosts past the outer wall, which the window's leading cell reaches in the last
     // cells of the run next to it; the stage input is read-only, so they are built once
@@ -289,9 +344,6 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     const double dt = A.l_only ? 1.0 : I.dt;
     const T cdt = T(A.cc * dt), ca = T(A.ca), cb = T(A.cb);
     const double* resW = tab + I.tresW;
-    const T* Kt = Ks + n1;
-    const T* K1row = Ks + vi * P1;
-    const T* Ktrow = Kt + vj * P2;
     const double pw1 = (double)p1, pw2 = (double)p2;
     const double wmk = Wm[kk], rwk = resW[kk];
 
@@ -354,39 +406,50 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
             fnr[kAhead - 1] = (need_fn && c + kAhead < rlen) ? (Fnd + (size_t)(s + kAhead) * NV)[k] : T(0);
         }
         if (st_prev) { *st_prev = out_prev; st_prev = nullptr; }
-        T* row = rows + (size_t)buf * kRowElems + (size_t)r * 2 * S;
-        T* rowT = row + S;
+        T* rowb = rows + (size_t)buf * 3 * kStageThreads;   // cell s+1's row and its contractions (jobs)
+        const T* rowp = rows + (size_t)(buf ^ 1) * 3 * kStageThreads;   // cell s's contractions
         T* gb = gbuf + (size_t)buf * kMaxRuns * kWave + (size_t)r * kWave;
+        T* gd = gbdb + (size_t)buf * kMaxRuns * kWave + (size_t)r * kWave;
         const double* e = eqc + (size_t)(r * TC + c) * kEqStride;
         if (cv) {
             w0v = w1v; w1v = w2v; w2v = w3v; w3v = w4v; w4v = w5v;
             // s is wavefront-uniform: interior cells take a plain load
             w5v = s + 3 < NR ? lead : (s + 3 == NR ? gh0 : (s + 3 == NR + 1 ? gh1 : gh2));
-            row[vi * P2 + vj] = w2v;
-            rowT[vj * P1 + vi] = w2v;
+            rowb[t] = w3v;
         }
         if (coff >= 0 && c < rlen) {
-            double g = 0.0;
-            for (int l = 0; l < nb; ++l) g += brow[l] * e[coff + l];
-            gb[kg] = T(g);
+            if constexpr (LIN) {
+                const float4 t4 = A.lin_node[(size_t)I.offG + (size_t)s * (Q1 + Q2) + kg];
+                const double du = kg < Q1 ? e[5] : e[6];
+                gb[kg] = T(t4.x);
+                gd[kg] = T(du * (double)t4.y + e[4] * (double)t4.z);
+            } else {
+                double g = 0.0;
+                for (int l = 0; l < nb; ++l) g += brow[l] * e[coff + l];
+                gb[kg] = T(g);
+            }
         }
         __syncthreads();
         if (c > 0) finish(c - 1, buf ^ 1);
+        if (c + 1 < rlen)
+            force_mfma<T>(rowb + r * nvpad, Ks, Kt, P1, P2, Q1, Q2, wave - w0, nw_waves, lane,
+                          rowb + kStageThreads + r * nvpad, rowb + 2 * kStageThreads + r * nvpad);
         double m0 = 0, m1 = 0, m2 = 0, m3 = 0, rd = 0, rn = 0;
         if (cv) {
-            const T fr = weno_face<T>(pos, w0v, w1v, w2v, w3v, w4v, w5v, weps);
+            const T fr = weno_face<T, LIN>(pos, w0v, w1v, w2v, w3v, w4v, w5v, weps);
             const T Rl = T(e[kEqGeo]), Rr = T(e[kEqGeo + 1]), gam = T(e[kEqGeo + 3]);   // R_{s-+1/2}/dchi_s
             const T adv = p1 * (Rr * fr - Rl * fl);
-            T kf = T(0), ktf = T(0);
-            if constexpr (sizeof(T) == 4) {
-                dot2_lds(K1row, rowT + vj * P1, L1, Ktrow, row + vi * P2, L2, kf, ktf);
-            } else {
-                kf = dot_lds<T>(K1row, rowT + vj * P1, L1);
-                ktf = dot_lds<T>(Ktrow, row + vi * P2, L2);
-            }
+            const T kf = rowp[kStageThreads + t], ktf = rowp[2 * kStageThreads + t];
             const T force = gam * (p2 * p2 * kf - p1 * ktf);
-            T fe = T(e[0]) * gb[vi] * gb[Q1 + vj];
-            if (dist) fe = T(e[1]) * fe;
+            T fe;
+            if constexpr (LIN) {
+                const T g1 = gb[vi], g2 = gb[Q1 + vj], g12 = g1 * g2;
+                fe = T(e[3]) * g12 + T(e[0]) * (gd[vi] * g2 + g1 * gd[Q1 + vj]);
+                if (dist) fe = T(e[1]) * fe + T(e[4] * e[0]) * g12;
+            } else {
+                fe = T(e[0]) * gb[vi] * gb[Q1 + vj];
+                if (dist) fe = T(e[1]) * fe;
+            }
             const T Fc = w2v;
             T L = -adv - force - (Fc - fe) * T(e[2]);
             if (Cd) L += Cd[(size_t)s * NV + k];
@@ -467,10 +530,13 @@ __global__ __launch_bounds__(256) void couette_moments(const InstDesc* insts, co
 }
 
 // Conversions between the FP64 state and the scaled FP32 state F/(w_i w_j) of the
-// reduced-precision path (to32: F32 = F64 / W; from32: F64 = W * F32), element-wise.
-template <bool TO32>
+// reduced-precision path, element-wise: kConvTo32 F32 = F64 / W; kConvFrom32 F64 = W F32;
+// kConvAdd F64 += theta_inst W F32 (the defect correction's relaxed update); kConvZero32
+// F32 = 0.
+template <int MODE>
 __global__ __launch_bounds__(256) void couette_convert(const InstDesc* insts32, const WorkItem* work,
-                                                       const double* tab_all, double* F64, float* F32) {
+                                                       const double* tab_all, double* F64, float* F32,
+                                                       const double* theta) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const WorkItem* wp = work + (size_t)blockIdx.x * kWavesPerBlock + wave;
     const int inst = __builtin_amdgcn_readfirstlane(wp->inst);
@@ -481,11 +547,14 @@ __global__ __launch_bounds__(256) void couette_convert(const InstDesc* insts32, 
     const InstDesc& I = insts32[inst];
     const double* W = tab_all + I.offT + I.tWm;
     const size_t base = I.offF + (size_t)dist * I.NR * I.NV;
+    const double th = MODE == kConvAdd ? theta[inst] : 1.0;
     for (int c = 0; c < ncell; ++c) {
         const size_t row = base + (size_t)(s0 + c) * I.NV;
         for (int k = lane; k < I.NV; k += kWave) {
-            if (TO32) F32[row + k] = (float)(F64[row + k] / W[k]);
-            else F64[row + k] = W[k] * (double)F32[row + k];
+            if (MODE == kConvTo32) F32[row + k] = (float)(F64[row + k] / W[k]);
+            else if (MODE == kConvFrom32) F64[row + k] = W[k] * (double)F32[row + k];
+            else if (MODE == kConvAdd) F64[row + k] += th * (W[k] * (double)F32[row + k]);
+            else F32[row + k] = 0.f;
         }
     }
 }
@@ -570,31 +639,12 @@ __global__ __launch_bounds__(256) void couette_reduce_f64(const InstDesc* insts,
     }
 }
 
-// Rescale every instance's FP64 state by target[b] / current[b] (particle-number
-// restoration after the FP32 phase; both distributions, so u and T are unchanged).
-__global__ __launch_bounds__(256) void couette_rescale(const InstDesc* insts, const WorkItem* work,
-                                                       const double* target, const double* current, double* F) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const WorkItem* wp = work + (size_t)blockIdx.x * kWavesPerBlock + wave;
-    const int inst = __builtin_amdgcn_readfirstlane(wp->inst);
-    const int dist = __builtin_amdgcn_readfirstlane(wp->dist);
-    const int s0 = __builtin_amdgcn_readfirstlane(wp->s0);
-    const int ncell = __builtin_amdgcn_readfirstlane(wp->ncell);
-    if (ncell <= 0) return;
-    const InstDesc& I = insts[inst];
-    const double f = target[inst] / current[inst];
-    const size_t base = I.offF + (size_t)dist * I.NR * I.NV;
-    for (int c = 0; c < ncell; ++c) {
-        const size_t row = base + (size_t)(s0 + c) * I.NV;
-        for (int k = lane; k < I.NV; k += kWave) F[row + k] *= f;
-    }
-}
-
 // Warm-start fields per cell from the surrogate outputs Y[cell][4] = ((n-1) S, u^R S,
-// u^phi/u_w, (T-1) S), S = 10; one block per instance.  par[inst] = (u_w, use): with use,
-// n is rescaled so that sum_s dchi_s n_s equals the cold start's sum_s dchi_s (n = 1)
-// -- the particle number the dynamics conserve (Eq. Ntot_def) -- and u^R = 0; without,
-// the cold start n = 1, u = 0, T = T_in.  Writes prof[cell][4] = (n, u^R, u^phi, T).
+// u^phi/u_w, (T-1) S), S = 10; one block per instance.  par[inst] = (u_w, use): with use
+// = 1, n is rescaled so that sum_s dchi_s n_s equals the cold start's sum_s dchi_s (n = 1)
+// -- the particle number the dynamics conserve (Eq. Ntot_def) -- and u^R = 0; with use =
+// 0, the cold start n = 1, u = 0, T = T_in; use < 0 leaves the instance alone.  Writes
+// prof[cell][4] = (n, u^R, u^phi, T).
 __global__ __launch_bounds__(256) void couette_warm_profile(const InstDesc* insts, const double* tab_all,
                                                             const float* Y, const double* par, double* prof) {
     __shared__ double sh[2][256];
@@ -604,6 +654,7 @@ __global__ __launch_bounds__(256) void couette_warm_profile(const InstDesc* inst
     const double uw = par[2 * inst], use = par[2 * inst + 1];
     const float* y = Y + (size_t)I.offC * 4;
     double* pr = prof + (size_t)I.offC * 4;
+    if (use < 0.0) return;
     if (use == 0.0) {
         for (int s = t; s < I.NR; s += 256) {
             pr[4 * s] = 1.0; pr[4 * s + 1] = 0.0; pr[4 * s + 2] = 0.0; pr[4 * s + 3] = I.T_in;
@@ -632,16 +683,18 @@ __global__ __launch_bounds__(256) void couette_warm_profile(const InstDesc* inst
 }
 
 // FP64 state at local equilibrium f' = n g1 g2, f'' = T f' (Sec. IV.D, Eq. feq_red) of
-// the per-cell fields prof[cell][4] = (n, u^R, u^phi, T); one wavefront per work item.
+// the per-cell fields prof[cell][4] = (n, u^R, u^phi, T); one wavefront per work item;
+// instances with par[2 inst + 1] < 0 are left alone.
 __global__ __launch_bounds__(256) void couette_init_profile(const InstDesc* insts, const WorkItem* work,
-                                                            const double* tab_all, const double* prof, double* F) {
+                                                            const double* tab_all, const double* prof,
+                                                            const double* par, double* F) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const WorkItem* wp = work + (size_t)blockIdx.x * kWavesPerBlock + wave;
     const int inst = __builtin_amdgcn_readfirstlane(wp->inst);
     const int dist = __builtin_amdgcn_readfirstlane(wp->dist);
     const int s0 = __builtin_amdgcn_readfirstlane(wp->s0);
     const int ncell = __builtin_amdgcn_readfirstlane(wp->ncell);
-    if (ncell <= 0) return;
+    if (ncell <= 0 || par[2 * inst + 1] < 0.0) return;
     const InstDesc& I = insts[inst];
     const double* tab = tab_all + I.offT;
     const int NV = I.NV, Q2 = I.Q2, N1 = I.N1, N2 = I.N2;
@@ -666,18 +719,108 @@ __global__ __launch_bounds__(256) void couette_init_profile(const InstDesc* inst
     }
 }
 
+// Equilibrium coefficients of one axis side (as axis_coef_side) together with their
+// partial derivatives with respect to the axis velocity u and the temperature T, for
+// the linearised equilibrium of the defect correction (Sec. IV.D):
+// full range: a_l = E[He_l(X)]/l!, X ~ N(u, T), has d a_l/du = a_{l-1} and
+//   d a_l/dT = a_{l-2}/2 (He_l' = l He_{l-1}; d/dT E[f(X)] = E[f''(X)]/2);
+// half range: M_s = int_0^inf x^s N(x; m, T) dx with m = +-u has
+//   dM_s/dm = (M_{s+1} - m M_s)/T and dM_s/dT = (M_{s+2} - 2 m M_{s+1} + m^2 M_s)/(2 T^2) - M_s/(2 T)
+//   (derivatives of the Gaussian density under the integral), and dm/du = +-1.
+static __device__ __noinline__ void axis_coef_deriv(int kind, int N, double u, double T, const double* C,
+                                                    const double* isf, int sg, double* co, double* cu, double* cT) {
+    if (kind == 0) {
+        double a[kMaxN + 1];
+        a[0] = 1.0;
+        if (N >= 1) a[1] = u;
+        for (int l = 2; l <= N; ++l) a[l] = (u * a[l - 1] + (T - 1.0) * a[l - 2]) / l;
+        for (int l = 0; l <= N; ++l) {
+            co[l] = a[l] / isf[l];
+            cu[l] = l >= 1 ? a[l - 1] / isf[l] : 0.0;
+            cT[l] = l >= 2 ? 0.5 * a[l - 2] / isf[l] : 0.0;
+        }
+        return;
+    }
+    const double m = sg == 0 ? u : -u, sgn = sg == 0 ? 1.0 : -1.0;
+    double M[kMaxN + 3];
+    const double g0 = exp(-m * m / (2.0 * T)) / sqrt(2.0 * M_PI * T);
+    M[0] = 0.5 * (1.0 + erf(m / sqrt(2.0 * T)));
+    M[1] = m * M[0] + T * g0;
+    for (int s = 2; s <= N + 2; ++s) M[s] = m * M[s - 1] + (s - 1) * T * M[s - 2];
+    for (int l = 0; l <= N; ++l) {
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int s = 0; s <= l; ++s) {
+            const double dm = (M[s + 1] - m * M[s]) / T;
+            const double dT = (M[s + 2] - 2.0 * m * M[s + 1] + m * m * M[s]) / (2.0 * T * T) - M[s] / (2.0 * T);
+            a += C[l * (N + 1) + s] * M[s];
+            b += C[l * (N + 1) + s] * dm;
+            c += C[l * (N + 1) + s] * dT;
+        }
+        co[l] = a;
+        cu[l] = sgn * b;
+        cT[l] = c;
+    }
+}
+
+// Per-cell data of the linearised stage about a fixed base state (the defect
+// correction's FP64 iterate): from the base state's FP64 moment sums, the cell fields
+// lin_cell[cell] = (n, T, 1/tau, u1, u2) and, per node of both axes, the equilibrium
+// factor g and its derivatives dg/du, dg/dT (scaled bases of the FP32 descriptor:
+// w-free, as the FP32 stage builds them).  One wavefront per work item.
+__global__ __launch_bounds__(256) void couette_lin_prep(const InstDesc* insts32, const WorkItem* work,
+                                                        const double* tab_all, const double* msum, double* lin_cell,
+                                                        float4* lin_node) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const WorkItem* wp = work + (size_t)blockIdx.x * kWavesPerBlock + wave;
+    const int inst = __builtin_amdgcn_readfirstlane(wp->inst);
+    const int dist = __builtin_amdgcn_readfirstlane(wp->dist);
+    const int s0 = __builtin_amdgcn_readfirstlane(wp->s0);
+    const int ncell = __builtin_amdgcn_readfirstlane(wp->ncell);
+    if (ncell <= 0 || dist != 0) return;
+    const InstDesc& I = insts32[inst];
+    const double* tab = tab_all + I.offT;
+    const int Q1 = I.Q1, Q2 = I.Q2, N1 = I.N1, N2 = I.N2, nq = Q1 + Q2;
+    for (int c = 0; c < ncell; ++c) {
+        const int s = s0 + c;
+        const double* ms = msum + (size_t)(I.offC + s) * 5;
+        const double n = ms[0], u1 = ms[1] / n, u2 = ms[2] / n;
+        const double T = (ms[3] + ms[4] - n * (u1 * u1 + u2 * u2)) / (3.0 * n);
+        if (lane == 0) {
+            double* lc = lin_cell + (size_t)(I.offC + s) * kLinCell;
+            lc[0] = n; lc[1] = T; lc[2] = 1.0 / tau_of(I.tau_model, I.Kn, n, T); lc[3] = u1; lc[4] = u2;
+            lc[5] = lc[6] = lc[7] = 0.0;
+        }
+        for (int x = lane; x < nq; x += kWave) {
+            const bool ax1 = x < Q1;
+            const int node = ax1 ? x : x - Q1, kind = ax1 ? I.kind1 : I.kind2, N = ax1 ? N1 : N2;
+            const int Qh = ax1 ? I.Qh1 : I.Qh2;
+            const int sg = (kind == 1 && node >= Qh) ? 1 : 0;
+            double co[kMaxN + 1], cu[kMaxN + 1], cT[kMaxN + 1];
+            axis_coef_deriv(kind, N, ax1 ? u1 : u2, T, tab + (ax1 ? I.tC1 : I.tC2), tab + (ax1 ? I.tisf1 : I.tisf2),
+                            sg, co, cu, cT);
+            const double* B = tab + (ax1 ? I.tB1 : I.tB2) + node * (N + 1);
+            double g = 0.0, gu = 0.0, gT = 0.0;
+            for (int l = 0; l <= N; ++l) { g += B[l] * co[l]; gu += B[l] * cu[l]; gT += B[l] * cT[l]; }
+            lin_node[(size_t)I.offG + (size_t)s * nq + x] = make_float4((float)g, (float)gu, (float)gT, 0.f);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host launchers
-template <typename T>
+template <typename T, bool LIN>
 static hipError_t launch_stage_t(int nblocks, hipStream_t st, const StageArgs& A) {
-    const StageLds<T> lay(A.kmax);
-    hipLaunchKernelGGL(couette_stage<T>, dim3(nblocks), dim3(kStageThreads), lay.total, st, A);
+    const StageLds<T, LIN> lay(A.kmax);
+    hipLaunchKernelGGL((couette_stage<T, LIN>), dim3(nblocks), dim3(kStageThreads), lay.total, st, A);
     return hipGetLastError();
 }
 
-size_t stage_lds(int kmax, int elem) { return elem == 4 ? StageLds<float>(kmax).total : StageLds<double>(kmax).total; }
+size_t stage_lds(int kmax, int elem) {
+    return elem == 4 ? StageLds<float, true>(kmax).total : StageLds<double>(kmax).total;
+}
 
 hipError_t launch_stage(int fp32, int nblocks, hipStream_t st, const StageArgs& A) {
-    return fp32 ? launch_stage_t<float>(nblocks, st, A) : launch_stage_t<double>(nblocks, st, A);
+    if (fp32) return A.lin_cell ? launch_stage_t<float, true>(nblocks, st, A) : launch_stage_t<float, false>(nblocks, st, A);
+    return launch_stage_t<double, false>(nblocks, st, A);
 }
 
 hipError_t launch_moments(int fp32, int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
@@ -691,21 +834,23 @@ hipError_t launch_moments(int fp32, int nblocks, hipStream_t st, const InstDesc*
     return hipGetLastError();
 }
 
-hipError_t launch_convert(int to32, int nblocks, hipStream_t st, const InstDesc* insts32, const WorkItem* work,
-                          const double* tab, double* F64, float* F32) {
-    if (to32)
-        hipLaunchKernelGGL(couette_convert<true>, dim3(nblocks), dim3(kWave * kWavesPerBlock), 0, st, insts32, work,
-                           tab, F64, F32);
-    else
-        hipLaunchKernelGGL(couette_convert<false>, dim3(nblocks), dim3(kWave * kWavesPerBlock), 0, st, insts32, work,
-                           tab, F64, F32);
-    return hipGetLastError();
-}
-
-hipError_t launch_rescale(int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
-                          const double* target, const double* current, double* F) {
-    hipLaunchKernelGGL(couette_rescale, dim3(nblocks), dim3(kWave * kWavesPerBlock), 0, st, insts, work, target,
-                       current, F);
+hipError_t launch_convert(int mode, int nblocks, hipStream_t st, const InstDesc* insts32, const WorkItem* work,
+                          const double* tab, double* F64, float* F32, const double* theta) {
+    const dim3 g(nblocks), b(kWave * kWavesPerBlock);
+    switch (mode) {
+        case kConvTo32:
+            hipLaunchKernelGGL(couette_convert<kConvTo32>, g, b, 0, st, insts32, work, tab, F64, F32, theta);
+            break;
+        case kConvFrom32:
+            hipLaunchKernelGGL(couette_convert<kConvFrom32>, g, b, 0, st, insts32, work, tab, F64, F32, theta);
+            break;
+        case kConvAdd:
+            hipLaunchKernelGGL(couette_convert<kConvAdd>, g, b, 0, st, insts32, work, tab, F64, F32, theta);
+            break;
+        default:
+            hipLaunchKernelGGL(couette_convert<kConvZero32>, g, b, 0, st, insts32, work, tab, F64, F32, theta);
+            break;
+    }
     return hipGetLastError();
 }
 
@@ -730,9 +875,16 @@ hipError_t launch_warm_profile(int ninst, hipStream_t st, const InstDesc* insts,
 }
 
 hipError_t launch_init_profile(int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
-                               const double* tab, const double* prof, double* F) {
+                               const double* tab, const double* prof, const double* par, double* F) {
     hipLaunchKernelGGL(couette_init_profile, dim3(nblocks), dim3(kWave * kWavesPerBlock), 0, st, insts, work, tab,
-                       prof, F);
+                       prof, par, F);
+    return hipGetLastError();
+}
+
+hipError_t launch_lin_prep(int nblocks, hipStream_t st, const InstDesc* insts32, const WorkItem* work,
+                           const double* tab, const double* msum, double* lin_cell, float4* lin_node) {
+    hipLaunchKernelGGL(couette_lin_prep, dim3(nblocks), dim3(kWave * kWavesPerBlock), 0, st, insts32, work, tab, msum,
+                       lin_cell, lin_node);
     return hipGetLastError();
 }
 

@@ -66,19 +66,22 @@ __device__ __forceinline__ double recip<double>(double x) {
 }
 
 // Flux at the face between c and d, upwinded from c (a, b, c, d, e in upwind order).
-template <typename T>
+// GUARD (FP32): stencils whose values span more than the FP32 exponent range (the
+// defect correction's corrections do, populations never) can underflow the weights;
+// there the weights' limit is taken instead (see below).
+template <typename T, bool GUARD = false>
 __device__ __forceinline__ T weno5(T a, T b, T c, T d, T e, T eps);
 
 // Face flux between window cells 2 and 3 of a six-cell window (cells s-2 .. s+3):
 // upwinded from cell 2 when the advection velocity is positive, from cell 3 otherwise
 // (the mirror image of the printed stencil).  The five stencil values are selected
 // first, so a wavefront holding both signs evaluates WENO once.
-template <typename T>
+template <typename T, bool GUARD = false>
 __device__ __forceinline__ T weno_face(bool pos, T w0, T w1, T w2, T w3, T w4, T w5, T eps) {
-    return weno5<T>(pos ? w0 : w5, pos ? w1 : w4, pos ? w2 : w3, pos ? w3 : w2, pos ? w4 : w1, eps);
+    return weno5<T, GUARD>(pos ? w0 : w5, pos ? w1 : w4, pos ? w2 : w3, pos ? w3 : w2, pos ? w4 : w1, eps);
 }
 
-template <typename T>
+template <typename T, bool GUARD>
 __device__ __forceinline__ T weno5(T a, T b, T c, T d, T e, T eps) {
     const T f1 = a * T(1.0 / 3.0) - b * T(7.0 / 6.0) + c * T(11.0 / 6.0);
     const T f2 = -b * T(1.0 / 6.0) + c * T(5.0 / 6.0) + d * T(1.0 / 3.0);
@@ -118,7 +121,15 @@ __device__ __forceinline__ T weno5(T a, T b, T c, T d, T e, T eps) {
     const T w1 = zany ? (z1 ? T(0.1) : T(0)) : T(0.1) * (q23 * q23);
     const T w2 = zany ? (z2 ? T(0.6) : T(0)) : T(0.6) * (q13 * q13);
     const T w3 = zany ? (z3 ? T(0.3) : T(0)) : T(0.3) * (q12 * q12);
-    return (w1 * f1 + w2 * f2 + w3 * f3) * recip<T>(w1 + w2 + w3);
+    const T sw = w1 + w2 + w3;
+    if constexpr (GUARD) {
+        // with two indicators below about 1e-19 of the largest (or the largest itself below
+        // the normal range), the product form underflows; the normalised weights then tend
+        // to 1 on the stencil of the smallest indicator, which is taken
+        if (!zany && !(m >= T(1.17549435e-38f) && sw >= T(1.17549435e-38f)))
+            return (s1 <= s2 && s1 <= s3) ? f1 : (s2 <= s3 ? f2 : f3);
+    }
+    return (w1 * f1 + w2 * f2 + w3 * f3) * recip<T>(sw);
 }
 
 // Expansion coefficients of one axis' equilibrium factor at (u, T) (Sec. IV.D):

@@ -5,6 +5,8 @@
 #include <cstdint>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 namespace vlb {
 
 constexpr int kMaxQ = 200;     // quadrature order per axis (nodes <= 400)
@@ -66,6 +68,7 @@ struct InstDesc {
     int Qh1, Qh2, tau_model, vpt;
     double Kn, dt, T_in, T_out, den_in, den_out, weno_eps;
     long long offF, offC, offT;
+    long long offG;   // node-table offset of the linearised mode (entries of 4 floats, N_R (Q1 + Q2) per instance)
     // table offsets relative to offT
     int tp1, tp2, tK1, tKt2, tB1, tB2, tC1, tC2, tisf1, tisf2;
     int tfin, tfout, tWm, tresW, tRf, tdchi, tGam, pad;
@@ -101,7 +104,16 @@ struct StageArgs {
     int l_only;              // 1: Fout = L[Fin] (dt taken as 1)
     int kmax;                // kernel-table elements reserved in LDS
     const BlockWork* blocks; // stage-kernel block list
+    // linearised mode of the FP32 kernel (defect correction), both null otherwise: the
+    // state is a correction delta about a fixed base state, whose per-cell fields
+    // [cells][kLinCell] (n, T, 1/tau, u1, u2) and per-node equilibrium factors
+    // [offG + cell (Q1 + Q2) + node] = (g, dg/du, dg/dT, 0) lin_prep wrote
+    const double* lin_cell;
+    const float4* lin_node;
 };
+constexpr int kLinCell = 8;
+// modes of the FP64 <-> scaled FP32 conversion kernel
+constexpr int kConvTo32 = 0, kConvFrom32 = 1, kConvAdd = 2, kConvZero32 = 3;
 
 // Arguments of the large-velocity-set stage (one instance per launch sequence): the
 // same stage as StageArgs (FP64 only), plus the instance's scratch blocks: Y [2][NR][NV]

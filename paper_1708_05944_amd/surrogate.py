@@ -38,52 +38,89 @@ def run_to_steady(batch, tol: float, max_steps: int, check_every: int = 500, chu
     return conv, r, bool((conv >= 0).all())
 
 
+def heldout_runs(heldout_descs, mlp, probe: int = 500, max_steps: int = 200_000, chunk: int = 5_000,
+                 check_every: int = 500, stall_window: int = 10_000, log=None, keep_fields: bool = False,
+                 legs=(("cold_fp64", 0, False), ("warm_fp64", 0, True), ("cold_mixed", 1, False),
+                       ("warm_mixed", 1, True))):
+    """The held-out instances run to r < 1e-10 from the cold rest state and from the
+    surrogate's warm start, each in FP64 and in mixed precision (defect correction).
+    Per leg: steps at convergence per instance (-1 if not converged), wall-clock seconds
+    of the whole batch (until every instance converged, or max_steps), the warm starts
+    kept by the acceptance probe and the instances restarted cold by the stall watch."""
+    import torch
+    from .vlb import VLB_MIXED
+    runs = {}
+    for name, prec, warm in legs:
+        b = Batch(heldout_descs, precision=VLB_MIXED if prec else VLB_FP64)
+        b.autotune(3)
+        b.init_equilibrium(-1, 1.0, 0.0, 0.0, 1.0)
+        b.set_stall_window(stall_window)
+        torch.cuda.synchronize()
+        times = np.full(b.B, np.nan)
+        t0 = time.perf_counter()
+        used = b.warm_start(mlp, probe) if warm else np.zeros(b.B, np.int32)
+        t_ws = time.perf_counter() - t0
+        if log:
+            log(f" {name}: {len(heldout_descs)} instances, warm starts kept {int(used.sum())}")
+        steps, r, ok = run_to_steady(b, 1e-10, max_steps, check_every=check_every, chunk=chunk, log=log, times=times)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        on_warm, fell = b.warm_report()
+        runs[name] = dict(steps=steps, times=times + t_ws, seconds=secs, used=used, warm_start_seconds=t_ws,
+                          fp32_steps=b.fp32_steps() if prec else 0, fallback_at=fell, converged=int((steps >= 0).sum()),
+                          probe_steps=2 * probe * int(warm))
+        if keep_fields:
+            runs[name]["fields"] = [b.moments(i) for i in range(b.B)]
+        b.close()
+    return runs
+
+
+def summarise(runs, max_steps: int):
+    """Honest totals of heldout_runs: an instance that did not converge counts max_steps
+    steps (and the batch's whole wall time); speed-ups compare the legs over all
+    instances."""
+    out = {}
+    for name, rr in runs.items():
+        st = np.where(rr["steps"] >= 0, rr["steps"], max_steps)
+        out[name] = dict(converged=rr["converged"], instances=len(st), steps_total=int(st.sum() + rr["probe_steps"]),
+                         seconds=float(rr["seconds"]), warm_used=int(np.sum(rr["used"])),
+                         cold_restarts=int((rr["fallback_at"] >= 0).sum()), fp32_steps=int(rr["fp32_steps"]),
+                         per_instance_steps=[int(x) for x in rr["steps"]])
+    pairs = (("warm_fp64", "cold_fp64"), ("warm_mixed", "cold_mixed"), ("warm_mixed", "cold_fp64"),
+             ("cold_mixed", "cold_fp64"))
+    for w, c in pairs:
+        if w in out and c in out:
+            out[f"speedup_{w}_vs_{c}"] = out[c]["seconds"] / out[w]["seconds"]
+            out[f"step_ratio_{w}_vs_{c}"] = out[c]["steps_total"] / out[w]["steps_total"]
+    return out
+
+
 def warm_start_comparison(train_descs, heldout_descs, epochs: int = 1000, batch: int = 256, lr: float = 1e-3,
                           probe: int = 500, max_steps: int = 200_000, chunk: int = 5_000, log=None,
-                          keep_fields: bool = False):
+                          keep_fields: bool = False, stall_window: int = 10_000, extra=None):
     """The learned warm start end to end: steady states of the training instances ->
-    samples -> trained network -> held-out instances run to r < 1e-10 from the cold rest
-    state in FP64 (the plain solver) and from the warm start in mixed precision.
-    Returns a dict of timings and per-instance step counts; times of a run are taken at
-    the chunk in which its last converging instance converged."""
-    from .vlb import VLB_MIXED
+    samples -> trained network -> held-out instances run to r < 1e-10 cold and warm, in
+    FP64 and mixed precision (heldout_runs, summarise).  extra: {label: descriptors} of
+    further held-out sets run the same way with the same network (out["extra"][label])."""
     X, T, st = steady_samples(train_descs, tol=1e-10, max_steps=max_steps, log=log)
     t0 = time.perf_counter()
     mlp, losses = train(X, T, epochs=epochs, batch=batch, lr=lr)
     t_train = time.perf_counter() - t0
     out = dict(training_solves=st, samples=int(len(X)), train_seconds=t_train, epochs=epochs,
-               final_loss=float(losses[-1]))
-    runs = {}
-    for name, prec, warm in (("cold_fp64", VLB_FP64, False), ("warm_mixed", VLB_MIXED, True)):
-        b = Batch(heldout_descs, precision=prec)
-        b.autotune(3)
-        b.init_equilibrium(-1, 1.0, 0.0, 0.0, 1.0)
-        times = np.full(b.B, np.nan)
-        t0 = time.perf_counter()
-        used = b.warm_start(mlp, probe) if warm else np.zeros(b.B, np.int32)
-        t_ws = time.perf_counter() - t0
-        steps, r, ok = run_to_steady(b, 1e-10, max_steps, chunk=chunk, log=log, times=times)
-        runs[name] = dict(steps=steps, times=times + t_ws, used=used, warm_start_seconds=t_ws,
-                          fp32_steps=b.fp32_steps() if warm else 0)
-        if keep_fields:
-            runs[name]["fields"] = [b.moments(i) for i in range(b.B)]
-        b.close()
-    both = (runs["cold_fp64"]["steps"] >= 0) & (runs["warm_mixed"]["steps"] >= 0)
-    c, w = runs["cold_fp64"], runs["warm_mixed"]
-    out.update(heldout=len(heldout_descs), converged_cold=int((c["steps"] >= 0).sum()),
-               converged_warm=int((w["steps"] >= 0).sum()), converged_both=int(both.sum()),
-               warm_used=int(w["used"].sum()), probe_steps=probe,
-               steps_cold=int(c["steps"][both].sum()), steps_warm=int(w["steps"][both].sum() + 2 * probe * both.sum()),
-               seconds_cold=float(np.nanmax(c["times"][both])) if both.any() else None,
-               seconds_warm=float(np.nanmax(w["times"][both])) if both.any() else None,
-               warm_start_seconds=w["warm_start_seconds"], fp32_steps=int(w["fp32_steps"]),
-               per_instance_steps_cold=[int(x) for x in c["steps"]],
-               per_instance_steps_warm=[int(x) for x in w["steps"]])
-    if out["seconds_cold"] and out["seconds_warm"]:
-        out["speedup"] = out["seconds_cold"] / out["seconds_warm"]
+               final_loss=float(losses[-1]), heldout=len(heldout_descs), probe_steps=probe, max_steps=max_steps,
+               stall_window=stall_window)
+    runs = heldout_runs(heldout_descs, mlp, probe=probe, max_steps=max_steps, chunk=chunk, log=log,
+                        keep_fields=keep_fields, stall_window=stall_window)
+    out.update(summarise(runs, max_steps))
     if keep_fields:
         out["fields"] = {k: v["fields"] for k, v in runs.items()}
-        out["converged_mask"] = both
+        out["steps"] = {k: v["steps"] for k, v in runs.items()}
+    for label, descs in (extra or {}).items():
+        if log:
+            log(f" held-out set {label}")
+        rx = heldout_runs(descs, mlp, probe=probe, max_steps=max_steps, chunk=chunk, log=log,
+                          stall_window=stall_window)
+        out.setdefault("extra", {})[label] = summarise(rx, max_steps)
     mlp.close()
     return out
 

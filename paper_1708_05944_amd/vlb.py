@@ -159,6 +159,8 @@ _SIGS = {
                       ctypes.POINTER(ctypes.c_int), ctypes.c_long, ctypes.c_int, ctypes.c_float, _fp],
     "vlb_batch_surrogate_samples": [ctypes.c_void_p, _fp, _fp, ctypes.c_size_t],
     "vlb_batch_warm_start": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
+    "vlb_batch_set_stall_window": [ctypes.c_void_p, ctypes.c_long],
+    "vlb_batch_warm_report": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_long)],
     "vlb_channel_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(_ChannelDesc), ctypes.c_int,
                            ctypes.c_void_p],
     "vlb_channel_destroy": [ctypes.c_void_p],
@@ -406,6 +408,19 @@ class Batch:
         used = (ctypes.c_int * self.B)()
         _check(load_library().vlb_batch_warm_start(self._h, mlp._h, probe_steps, used), "vlb_batch_warm_start")
         return np.array(list(used), dtype=np.int32)
+
+    def set_stall_window(self, steps: int):
+        """Steps without a new residual low after which run_to_steady restarts a warm-started
+        instance from the cold rest state."""
+        _check(load_library().vlb_batch_set_stall_window(self._h, steps), "vlb_batch_set_stall_window")
+
+    def warm_report(self):
+        """(on_warm, fallback_at) per instance: 1 while still on the warm start; the step of a
+        cold restart (-1 none)."""
+        on = (ctypes.c_int * self.B)()
+        at = (ctypes.c_long * self.B)()
+        _check(load_library().vlb_batch_warm_report(self._h, on, at), "vlb_batch_warm_report")
+        return np.array(list(on), dtype=np.int32), np.array(list(at), dtype=np.int64)
 
 
 def couette_step_noalloc(descs, F, nsteps: int, stream=None) -> np.ndarray:

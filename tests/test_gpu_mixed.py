@@ -1,5 +1,6 @@
 """Reduced-precision (VLB_MIXED) path: FP32 stage kernels on scaled populations, FP64
-moment / wall / residual accumulation, FP64 polish to the steady state.
+moment / wall / residual accumulation, and the defect correction that reaches the FP64
+steady state with FP32 streaming.
 
 Bars: the FP32 operator agrees with the FP64 oracle to FP32 rounding (relative
 max-norm 2e-6, about 30 ulp of float); every steady-state profile (n, u^phi, T,
@@ -51,34 +52,71 @@ def test_fp32_operator_matches_oracle_to_fp32_rounding(case):
     b.close()
 
 
+def _steady(descs, prec, max_steps=80_000):
+    from paper_1708_05944_amd import Batch
+    b = Batch(descs, precision=prec)
+    m0 = b.total_mass()
+    steps, r, ok = b.run_to_steady(1e-10, max_steps, 500)
+    out = dict(ok=ok, steps=steps, r=r, mass=b.total_mass() / m0 - 1, fp32=b.fp32_steps(),
+               fields=[b.moments(i) for i in range(b.B)])
+    b.close()
+    return out
+
+
+def _profile_errors(a, b):
+    return {k: float(np.abs(a[k] - b[k]).max() / np.abs(b[k]).max()) for k in ("n", "u2", "T", "T12")}
+
+
 def test_mixed_steady_state_matches_fp64():
-    """Single-instance workload to r < 1e-10 in FP64 and in mixed precision."""
-    from paper_1708_05944_amd import VLB_MIXED, Batch, CouetteDesc, workloads
+    """Single-instance workload to r < 1e-10 in FP64 and in mixed precision: the defect
+    correction's FP32 steps are at least 80 % of all steps, it converges to the FP64
+    fixed point (every profile, including the shear stress T^{R phi}, within 1e-5 of the
+    FP64 run), and particle number drifts only by FP32 rounding of the corrections
+    (bound 1e-9 relative)."""
+    from paper_1708_05944_amd import VLB_MIXED, workloads
     d = workloads.single_couette()
-    runs = {}
-    for name, prec in (("fp64", 0), ("mixed", VLB_MIXED)):
-        b = Batch([d], precision=prec)
-        m0 = b.total_mass()[0]
-        steps, r, ok = b.run_to_steady(1e-10, 60000, 500)
-        assert ok and r[0] < 1e-10, (name, r)
-        # the FP32 phase's particle-number drift is removed before the FP64 polish; what
-        # remains is FP64 rounding, at most one unit roundoff per step
-        assert abs(b.total_mass()[0] / m0 - 1) < steps[0] * 2.2e-16, name
-        runs[name] = (b.moments(0), steps[0], b.fp32_steps() if prec else 0)
-        b.close()
-    m64, m32 = runs["fp64"][0], runs["mixed"][0]
-    for key in ("n", "u2", "T", "T12"):
-        err = np.abs(m32[key] - m64[key]).max() / np.abs(m64[key]).max()
-        _say(f"{key}: mixed vs fp64 rel err {err:.2e}")
-        assert err <= 1e-5, key
-    _say(f"steps fp64 {runs['fp64'][1]}, mixed {runs['mixed'][1]} ({runs['mixed'][2]} in FP32)")
+    r64 = _steady([d], 0)
+    rmx = _steady([d], VLB_MIXED)
+    assert r64["ok"] and rmx["ok"], (r64["r"], rmx["r"])
+    assert abs(r64["mass"][0]) < r64["steps"][0] * 2.2e-16
+    errs = _profile_errors(rmx["fields"][0], r64["fields"][0])
+    _say(f"steps fp64 {r64['steps'][0]}, mixed {rmx['steps'][0]} ({rmx['fp32']} in FP32); mass drift "
+         f"{rmx['mass'][0]:.1e}; profile errors {errs}")
+    assert rmx["fp32"] >= 0.8 * rmx["steps"][0]
+    assert abs(rmx["mass"][0]) < 1e-9
+    assert max(errs.values()) <= 1e-5
+
+
+def test_mixed_batched_sweep_subset_matches_fp64():
+    """A batch of six instances of the sweep generator (seed 1, Kn <= 0.2, 32 cells,
+    weno_eps = 1e-6) to r < 1e-10 in FP64 and by the mixed defect correction (which may
+    take more steps on instances whose linearised operator overshoots: budget 3x): the
+    same instances converge, and n, u^phi, T and the shear stress T^{R phi} of every
+    instance agree with FP64 to 1e-5 (stated per field)."""
+    from paper_1708_05944_amd import VLB_MIXED, workloads
+    descs = workloads.surrogate_descs(6, workloads.SURROGATE_TRAIN_SEED, N_R=32, Kn_max=0.2)
+    for d in descs:
+        d.weno_eps = 1e-6
+    r64 = _steady(descs, 0, 150_000)
+    rmx = _steady(descs, VLB_MIXED, 450_000)
+    _say(f"steps fp64 {list(r64['steps'])} (r {list(r64['r'])}), mixed {list(rmx['steps'])} (r {list(rmx['r'])})")
+    assert list(r64["steps"] >= 0) == list(rmx["steps"] >= 0)
+    worst = {}
+    for i in np.flatnonzero(r64["steps"] >= 0):
+        e = _profile_errors(rmx["fields"][i], r64["fields"][i])
+        for k, v in e.items():
+            worst[k] = max(worst.get(k, 0.0), v)
+    _say(f"converged {int((r64['steps'] >= 0).sum())}/6; steps fp64 {list(r64['steps'])}, mixed "
+         f"{list(rmx['steps'])}, FP32 steps {rmx['fp32']}; worst profile errors {worst}")
+    assert (r64["steps"] >= 0).sum() >= 5
+    assert max(worst.values()) <= 1e-5
 
 
 def test_fp32_phase_profile_error_is_stated():
-    """The FP32-only state where the residual stops falling, against the FP64 steady
-    state: the profile error there is what the FP64 polish removes (reported, and
-    bounded by 5e-3 so that the polish starts close; measured on MI355X: r floor 3.8e-6,
-    profile errors n 1.9e-4, u^phi 9.0e-4, T 3.0e-6, T^{R phi} 1.1e-3)."""
+    """Plain FP32 steps (vlb_step on a mixed batch) stall where the FP32 rounding floor
+    is reached; the profile error there, against the FP64 steady state, is what the
+    defect correction removes (reported, bounded by 5e-3; measured on MI355X: r floor
+    3.8e-6, profile errors n 1.9e-4, u^phi 9.0e-4, T 3.0e-6, T^{R phi} 1.1e-3)."""
     from paper_1708_05944_amd import VLB_MIXED, Batch, workloads
     d = workloads.single_couette()
     b64 = Batch([d])
