@@ -23,7 +23,7 @@ hipError_t launch_stage(int fp32, int nblocks, hipStream_t st, const StageArgs& 
 hipError_t launch_wide_stage(int NR, int Q1, int Q2, hipStream_t st, const WideArgs& A);
 size_t stage_lds(int kmax, int elem);
 hipError_t launch_moments(int fp32, int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
-                          const double* tab, const void* F, double* msum);
+                          const double* tab, const void* F, double* msum, const int* mask = nullptr, int want = 0);
 hipError_t launch_convert(int mode, int nblocks, hipStream_t st, const InstDesc* insts32, const WorkItem* work,
                           const double* tab, double* F64, float* F32, const double* theta = nullptr);
 hipError_t launch_reduce(int ninst, hipStream_t st, const InstDesc* insts, const double* tab, const double* rpart,
@@ -114,7 +114,7 @@ struct vlb_batch {
     std::vector<double> tab;
     size_t state_n = 0, ncells = 0;
     // workspace layout (byte offsets)
-    size_t off_F[3], off_F32[4], off_M[3], off_rpart, off_lincell, off_linnode, off_theta, off_resid, off_mass, off_tab, off_desc, off_desc32, off_work,
+    size_t off_F[3], off_F32[4], off_M[3], off_rpart, off_lincell, off_linnode, off_theta, off_mask, off_resid, off_mass, off_tab, off_desc, off_desc32, off_work,
         off_diag, off_blocks, off_prof, off_wpar, off_sfeat, off_sy, off_wide, total_bytes;
     size_t wide_n = 0;                  // doubles of the large-velocity-set scratch region
     std::vector<char> active;          // instances the stage kernels advance (run_to_steady retires converged ones)
@@ -137,11 +137,14 @@ struct vlb_batch {
     // three checks in a row without a new residual low, doubled back towards 1 after eight
     // in a row with one), the lowest residual, when it was set and the run of checks
     // without / with a new low, and the switch to FP64 steps for the rest of the run when
-    // some instance sets no new low for kDcWindow steps
+    // an instance sets no new low for kDcWindow steps (dc64: it then takes FP64 steps inside
+    // the correction loop, launched beside the linearised FP32 ones)
     std::vector<double> theta, dc_best;
     std::vector<long> dc_best_at;
     std::vector<int> dc_miss, dc_hit;
-    bool dc_off = false;
+    std::vector<int> dc64;
+    std::vector<BlockWork> blocks_lin, blocks_64;   // the split of `blocks` by dc64
+    int n_dc64 = 0;
     std::vector<InstDesc> desc32;       // FP32 descriptors (rescaled tables)
     char* ws = nullptr;
     bool owns = false;
@@ -168,6 +171,9 @@ struct vlb_batch {
     InstDesc* ddesc() { return (InstDesc*)(ws + off_desc); }
     WorkItem* dwork() { return (WorkItem*)(ws + off_work); }
     BlockWork* dblocks() { return (BlockWork*)(ws + off_blocks); }
+    BlockWork* dblocks_lin() { return dblocks() + max_blocks; }
+    BlockWork* dblocks_64() { return dblocks() + max_blocks + blocks_lin.size(); }
+    int* dmask() { return (int*)(ws + off_mask); }
     double* prof() { return (double*)(ws + off_prof); }
     double* wpar() { return (double*)(ws + off_wpar); }
     float* sfeat() { return (float*)(ws + off_sfeat); }
@@ -309,7 +315,8 @@ void reset_run_state(vlb_batch* b, const int* warm) {
     b->dc_hit.assign(b->B, 0);
     b->dc_best.assign(b->B, INFINITY);
     b->dc_best_at.assign(b->B, 0);
-    b->dc_off = false;
+    b->dc64.assign(b->B, 0);
+    b->n_dc64 = 0;
 }
 
 vlb_status init_from_surrogate(vlb_batch* b, const std::vector<int>& use);
@@ -357,6 +364,8 @@ vlb_status layout_and_alloc(vlb_batch* b, bool alloc, bool ext_state = false) {
     if (b->precision == VLB_MIXED) off = align256(off + b->lin_nodes * sizeof(float4));
     b->off_theta = off;
     off = align256(off + b->B * sizeof(double));
+    b->off_mask = off;
+    off = align256(off + b->B * sizeof(int));
     for (int i = 0; i < 3; ++i) { b->off_M[i] = off; off = align256(off + b->ncells * 5 * sizeof(double)); }
     b->off_rpart = off; off = align256(off + b->ncells * 4 * sizeof(double));
     b->off_diag = off; off = align256(off + b->ncells * 7 * sizeof(double));
@@ -366,7 +375,7 @@ vlb_status layout_and_alloc(vlb_batch* b, bool alloc, bool ext_state = false) {
     b->off_desc = off; off = align256(off + b->desc.size() * sizeof(InstDesc));
     b->off_desc32 = off; off = align256(off + b->desc32.size() * sizeof(InstDesc));
     b->off_work = off; off = align256(off + b->work.size() * sizeof(WorkItem));
-    b->off_blocks = off; off = align256(off + b->max_blocks * sizeof(BlockWork));
+    b->off_blocks = off; off = align256(off + 2 * b->max_blocks * sizeof(BlockWork));
     b->off_prof = off; off = align256(off + b->ncells * 4 * sizeof(double));
     b->off_wpar = off; off = align256(off + b->B * 2 * sizeof(double));
     b->off_sfeat = off; off = align256(off + b->ncells * 4 * sizeof(float));
@@ -403,9 +412,9 @@ vlb_status finish_setup(vlb_batch* b) {
 
 bool check_instance(vlb_batch* b, int inst) { return b && inst >= 0 && inst < b->B; }
 
-// One RK stage (or one operator application) on the current precision's buffers.
-vlb_status run_stage(vlb_batch* b, int stage, bool last, bool l_only) {
-    const bool f32 = b->cur32;
+// Arguments of one RK stage (or one operator application) in FP32 (f32) or FP64, the
+// linearised FP32 stage of the defect correction when lin.
+StageArgs stage_args(vlb_batch* b, int stage, bool last, bool l_only, bool f32, bool lin) {
     auto Fb = [&](int i) -> void* { return f32 ? (void*)b->F32(i) : (void*)b->F(i); };
     StageArgs A;
     A.inst = f32 ? b->ddesc32() : b->ddesc();
@@ -415,7 +424,7 @@ vlb_status run_stage(vlb_batch* b, int stage, bool last, bool l_only) {
     A.C = nullptr;
     A.lin_cell = nullptr;
     A.lin_node = nullptr;
-    if (b->lin && f32) {   // linearised FP32 stage about the defect correction's base state
+    if (lin && f32) {   // linearised FP32 stage about the defect correction's base state
         A.lin_cell = b->lincell();
         A.lin_node = b->linnode();
         A.C = b->F32(3);
@@ -439,6 +448,27 @@ vlb_status run_stage(vlb_batch* b, int stage, bool last, bool l_only) {
         A.ca = 1.0 / 3.0; A.cb = 2.0 / 3.0; A.cc = 2.0 / 3.0;
         if (last && !A.lin_cell) A.rpart = b->rpart();
     }
+    return A;
+}
+
+// One RK stage (or one operator application) on the current precision's buffers.  In the
+// defect correction, instances that fell back to FP64 (dc64) take their FP64 stage in a
+// second launch beside the linearised FP32 one.
+vlb_status run_stage(vlb_batch* b, int stage, bool last, bool l_only) {
+    const bool f32 = b->cur32;
+    if (b->lin && f32 && b->n_dc64 > 0 && !l_only) {
+        const LaunchGroup& g = b->groups[0];
+        StageArgs A = stage_args(b, stage, last, false, true, true);
+        A.blocks = b->dblocks_lin();
+        A.kmax = g.kmax;
+        if (!b->blocks_lin.empty()) HIP_TRY(launch_stage(1, (int)b->blocks_lin.size(), b->stream, A));
+        StageArgs A64 = stage_args(b, stage, last, false, false, false);
+        A64.blocks = b->dblocks_64();
+        A64.kmax = g.kmax;
+        if (!b->blocks_64.empty()) HIP_TRY(launch_stage(0, (int)b->blocks_64.size(), b->stream, A64));
+        return VLB_OK;
+    }
+    const StageArgs A = stage_args(b, stage, last, l_only, f32, b->lin);
     const double values = (l_only || stage == 0) ? 2.0 : 3.0;   // algorithmic HBM values per population
     const double elem = f32 ? sizeof(float) : sizeof(double);
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
@@ -494,7 +524,7 @@ vlb_status run_stage(vlb_batch* b, int stage, bool last, bool l_only) {
 }
 
 constexpr int kGraphSteps = 10;
-constexpr long kDcWindow = 20000;   // steps without a new residual low that end the defect correction
+constexpr long kDcWindow = 20000;   // steps without a new residual low that move an instance to FP64 steps
 
 void drop_graphs(vlb_batch* b) {
     for (hipGraphExec_t& g : b->graph)
@@ -548,11 +578,21 @@ void build_blocks(vlb_batch* b, int tile) {
     });
     for (LaunchGroup& g : b->groups) g.nblocks = (int)b->blocks.size();
     b->tile = tile;
+    b->blocks_lin.clear();
+    b->blocks_64.clear();
+    for (const BlockWork& w : b->blocks)
+        ((b->dc64.size() == (size_t)b->B && b->dc64[w.inst]) ? b->blocks_64 : b->blocks_lin).push_back(w);
 }
 
 vlb_status upload_blocks(vlb_batch* b) {
     HIP_TRY(hipMemcpyAsync(b->dblocks(), b->blocks.data(), b->blocks.size() * sizeof(BlockWork),
                            hipMemcpyHostToDevice, b->stream));
+    if (b->n_dc64 > 0) {   // the linearised / FP64 split of the defect correction
+        HIP_TRY(hipMemcpyAsync(b->dblocks_lin(), b->blocks_lin.data(), b->blocks_lin.size() * sizeof(BlockWork),
+                               hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(hipMemcpyAsync(b->dblocks_64(), b->blocks_64.data(), b->blocks_64.size() * sizeof(BlockWork),
+                               hipMemcpyHostToDevice, b->stream));
+    }
     drop_graphs(b);   // captured launches carry the old grid size
     return VLB_OK;
 }
@@ -609,6 +649,9 @@ vlb_status defect_correction(vlb_batch* b, long m) {
     HIP_TRY(launch_convert(kConvTo32, nblocks, b->stream, b->ddesc32(), b->dwork(), b->dtab(), b->F(1), b->F32(3)));
     HIP_TRY(launch_convert(kConvZero32, nblocks, b->stream, b->ddesc32(), b->dwork(), b->dtab(), b->F(0), b->F32(0)));
     HIP_TRY(launch_moments(1, nblocks, b->stream, b->ddesc32(), b->dwork(), b->dtab(), b->F32(0), b->M(0)));
+    if (b->n_dc64 > 0)   // instances stepping in FP64 keep the moment sums of their FP64 state
+        HIP_TRY(launch_moments(0, nblocks, b->stream, b->ddesc(), b->dwork(), b->dtab(), b->F(0), b->M(0), b->dmask(),
+                               1));
     b->cur32 = true;
     b->lin = true;
     s = step_current(b, m);
@@ -1084,7 +1127,7 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
     while (done < max_steps && remaining > 0) {
         // FP64 steps: the plain solver's residual of the current iterate (mixed batches
         // take one, then check_every - 1 defect-correction steps in FP32)
-        const bool dc = mixed && !b->dc_off;
+        const bool dc = mixed;
         const long n = dc ? 1 : std::min<long>(check_every, max_steps - done);
         s = step_current(b, n);
         if (s != VLB_OK) return s;
@@ -1092,7 +1135,7 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
         b->run_steps += n;
         s = read_residual(b, res.data());
         if (s != VLB_OK) return s;
-        bool retired = false;
+        bool retired = false, dc_split = false;
         std::vector<int> restart(b->B, -1);
         bool any_restart = false;
         for (int i = 0; i < b->B; ++i) {
@@ -1134,9 +1177,9 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
             // relaxation of the defect correction: an instance that sets no new residual low
             // (by 1 %) at three checks in a row has its update halved (a mode the linearised
             // operator overshoots otherwise makes the iteration cycle), one that sets eight
-            // in a row has it doubled back towards the full correction; no new low for
-            // kDcWindow steps on any instance ends the correction for this run: FP64 steps
-            // from then on
+            // in a row has it doubled back towards the full correction; an instance with no
+            // new low for kDcWindow steps takes FP64 steps inside the correction loop from
+            // then on (beside the others' FP32 steps)
             for (int i = 0; i < b->B; ++i) {
                 if (conv[i] >= 0) continue;
                 if (res[i] < 0.99 * b->dc_best[i]) {
@@ -1154,7 +1197,11 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
                     b->theta[i] = std::max(0.125, 0.5 * b->theta[i]);
                     b->dc_miss[i] = 0;
                 }
-                if (b->run_steps - b->dc_best_at[i] >= kDcWindow) b->dc_off = true;
+                if (!b->dc64[i] && b->run_steps - b->dc_best_at[i] >= kDcWindow) {
+                    b->dc64[i] = 1;
+                    ++b->n_dc64;
+                    dc_split = true;
+                }
             }
         }
         if (retired && remaining > 0) {
@@ -1162,7 +1209,14 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
             s = upload_blocks(b);
             if (s != VLB_OK) return s;
         }
-        if (dc && !b->dc_off && remaining > 0 && done < max_steps) {
+        if (dc_split || (retired && b->n_dc64 > 0)) {
+            HIP_TRY(hipMemcpyAsync(b->dmask(), b->dc64.data(), b->B * sizeof(int), hipMemcpyHostToDevice, b->stream));
+            build_blocks(b, b->tile);
+            s = upload_blocks(b);
+            if (s != VLB_OK) return s;
+            guard.dirty = true;
+        }
+        if (dc && remaining > 0 && done < max_steps) {
             const long m = std::min<long>(check_every - 1, max_steps - done);
             if (m > 0) {
                 s = defect_correction(b, m);

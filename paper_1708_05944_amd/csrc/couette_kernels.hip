@@ -30,97 +30,77 @@ namespace vlb {
 
 
 
-// 16 x 16 x 4 matrix-core products (one per wavefront): the A operand of lane l is
-// element (l mod 16, l / 16) of a 16 x 4 block, the B operand element (l / 16, l mod 16)
-// of a 4 x 16 block; register r of lane group g = l / 16 returns row 4 g + r (FP32 form)
-// or g + 4 r (FP64 form) of the 16 x 16 product, column l mod 16.
-typedef float mf_f4 __attribute__((ext_vector_type(4)));
-typedef double mf_d4 __attribute__((ext_vector_type(4)));
+// sum_i a[i] b[i], i < n (n a multiple of 4, both pointers 16-byte aligned LDS), in
+// index order with 16-byte vector reads
 template <typename T>
-struct Mfma;
+__device__ __forceinline__ T dot_lds(const T* a, const T* b, int n);
 template <>
-struct Mfma<float> {
-    typedef mf_f4 V;
-    static __device__ __forceinline__ V op(float a, float b, V c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+__device__ __forceinline__ float dot_lds<float>(const float* a, const float* b, int n) {
+    float acc = 0.f;
+    for (int i = 0; i < n; i += 4) {
+        const float4 x = *reinterpret_cast<const float4*>(a + i), y = *reinterpret_cast<const float4*>(b + i);
+        acc += x.x * y.x;
+        acc += x.y * y.y;
+        acc += x.z * y.z;
+        acc += x.w * y.w;
     }
-    static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
-};
+    return acc;
+}
 template <>
-struct Mfma<double> {
-    typedef mf_d4 V;
-    static __device__ __forceinline__ V op(double a, double b, V c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+__device__ __forceinline__ double dot_lds<double>(const double* a, const double* b, int n) {
+    double acc = 0.0;
+    for (int i = 0; i < n; i += 2) {
+        const double2 x = *reinterpret_cast<const double2*>(a + i), y = *reinterpret_cast<const double2*>(b + i);
+        acc += x.x * y.x;
+        acc += x.y * y.y;
     }
-    static __device__ __forceinline__ int row(int g, int r) { return g + 4 * r; }
-};
-
-// The two momentum-derivative contractions of the force term for one cell of a run,
-// on the matrix cores (Sec. IV.C, Eqs. df_K_hh, dfp_K_H with the kernels of the axes):
-//   r1[i][j] = sum_i' K1[i][i'] F[i'][j]   and   r2[i][j] = sum_j' Kt2[j][j'] F[i][j'],
-// F the cell's populations as a Q1 x Q2 matrix (k = i Q2 + j) in LDS, K1 / Kt2 the kernel
-// rows in LDS with strides P1 / P2, results in LDS in the population order.  The 16 x 16
-// output tiles of both products are jobs, dealt round robin to the run's nw wavefronts
-// (lw = this wavefront's index in the run); the contraction index i' (j') of k-step kk is
-// KS g + kk in lane group g, so each lane group walks its own contiguous quarter of the
-// index range.  Operands outside the matrices are zero.
-template <typename T>
-__device__ __forceinline__ void force_mfma(const T* Fr, const T* K1s, const T* Kt2s, int P1, int P2, int Q1,
-                                           int Q2, int lw, int nw, int lane, T* r1, T* r2) {
-    typedef typename Mfma<T>::V V;
-    const int g = lane >> 4, n = lane & 15;
-    const int MT = (Q1 + 15) >> 4, NT = (Q2 + 15) >> 4;
-    const int KS1 = (Q1 + 3) >> 2, KS2 = (Q2 + 3) >> 2;
-    const int njob = 2 * MT * NT;
-    for (int jb = lw; jb < njob; jb += nw) {
-        const bool first = jb < MT * NT;
-        const int tj = first ? jb : jb - MT * NT;
-        const int Mt = tj / NT, Nt = tj - Mt * NT;
-        const int im = 16 * Mt + n, jn = 16 * Nt + n;
-        V acc = {T(0), T(0), T(0), T(0)};
-        if (first) {
-            // A = K1 rows im, B = F rows i' (columns jn)
-            const int i0 = KS1 * g, nk = min(KS1, Q1 - i0);
-            const T* pa = K1s + im * P1 + i0;
-            const T* pb = Fr + i0 * Q2 + jn;
-            const bool ra = im < Q1, rb = jn < Q2;
-            for (int kk = 0; kk < KS1; ++kk) {
-                T a = T(0), b = T(0);
-                if (kk < nk) {
-                    if (ra) a = pa[kk];
-                    if (rb) b = pb[kk * Q2];
-                }
-                acc = Mfma<T>::op(a, b, acc);
-            }
-        } else {
-            // A = F rows im (columns j'), B = Kt2 rows jn transposed
-            const int j0 = KS2 * g, nk = min(KS2, Q2 - j0);
-            const T* pa = Fr + im * Q2 + j0;
-            const T* pb = Kt2s + jn * P2 + j0;
-            const bool ra = im < Q1, rb = jn < Q2;
-            for (int kk = 0; kk < KS2; ++kk) {
-                T a = T(0), b = T(0);
-                if (kk < nk) {
-                    if (ra) a = pa[kk];
-                    if (rb) b = pb[kk];
-                }
-                acc = Mfma<T>::op(a, b, acc);
-            }
-        }
-        T* out = first ? r1 : r2;
-        if (jn < Q2) {
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int i = 16 * Mt + Mfma<T>::row(g, rr);
-                if (i < Q1) out[i * Q2 + jn] = acc[rr];
-            }
-        }
-    }
+    return acc;
 }
 
-// LDS layout of a stage block (bytes): kernel tables | two buffers of three population
-// rows (one entry per thread: a cell's input, and the two force contractions of it) |
-// two equilibrium-factor buffers | per (run, cell):
+// The two contractions of the force term, sum_i a1[i] b1[i] (i < n1) and sum_i a2[i] b2[i]
+// (i < n2), each in index order exactly as dot_lds; over the common length the reads of
+// both are issued together, so that one LDS round trip serves both (FP32 kernel; the FP64
+// kernel has no registers to spare and calls dot_lds twice).
+__device__ __forceinline__ void dot2_lds(const float* a1, const float* b1, int n1, const float* a2,
+                                         const float* b2, int n2, float& r1, float& r2) {
+    float acc1 = 0.f, acc2 = 0.f;
+    const int nc = n1 < n2 ? n1 : n2;
+    int i = 0;
+#pragma unroll 1
+    for (; i < nc; i += 4) {
+        const float4 x1 = *reinterpret_cast<const float4*>(a1 + i), y1 = *reinterpret_cast<const float4*>(b1 + i);
+        const float4 x2 = *reinterpret_cast<const float4*>(a2 + i), y2 = *reinterpret_cast<const float4*>(b2 + i);
+        acc1 += x1.x * y1.x;
+        acc1 += x1.y * y1.y;
+        acc1 += x1.z * y1.z;
+        acc1 += x1.w * y1.w;
+        acc2 += x2.x * y2.x;
+        acc2 += x2.y * y2.y;
+        acc2 += x2.z * y2.z;
+        acc2 += x2.w * y2.w;
+    }
+#pragma unroll 1
+    for (int j = i; j < n1; j += 4) {
+        const float4 x = *reinterpret_cast<const float4*>(a1 + j), y = *reinterpret_cast<const float4*>(b1 + j);
+        acc1 += x.x * y.x;
+        acc1 += x.y * y.y;
+        acc1 += x.z * y.z;
+        acc1 += x.w * y.w;
+    }
+#pragma unroll 1
+    for (int j = i; j < n2; j += 4) {
+        const float4 x = *reinterpret_cast<const float4*>(a2 + j), y = *reinterpret_cast<const float4*>(b2 + j);
+        acc2 += x.x * y.x;
+        acc2 += x.y * y.y;
+        acc2 += x.z * y.z;
+        acc2 += x.w * y.w;
+    }
+    r1 = acc1;
+    r2 = acc2;
+}
+
+// LDS layout of a stage block (bytes): kernel tables | two cell-row buffers (row-major
+// and transposed copies per run) | two equilibrium-factor buffers | per (run, cell):
 // n, T, 1/tau, equilibrium coefficients and geometry | equilibrium bases | moment and
 // residual partials per wavefront (two buffers) | wall-flux partials per wavefront.
 template <typename T, bool LIN = false>
@@ -130,7 +110,7 @@ struct StageLds {
         auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
         ks = 0;
         rows = al(ks + (size_t)kmax * sizeof(T));
-        gbuf = al(rows + 2 * 3 * (size_t)kStageThreads * sizeof(T));
+        gbuf = al(rows + 2 * (size_t)kRowElems * sizeof(T));
         gbd = al(gbuf + 2 * (size_t)kMaxRuns * kWave * sizeof(T));
         eqc = LIN ? al(gbd + 2 * (size_t)kMaxRuns * kWave * sizeof(T)) : gbd;
         btab = al(eqc + (size_t)kMaxRuns * kTileCells * kEqStride * sizeof(double));
@@ -182,10 +162,13 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     const int vi = kk / Q2, vj = kk - vi * Q2;
     const T p1 = T(tab[I.tp1 + vi]), p2 = T(tab[I.tp2 + vj]);
 
-    // ---- prologue: kernels into LDS (rows of stride P1 / P2, zero beyond Q1 / Q2);
-    // equilibrium coefficients of every (run, cell)
+    // ---- prologue: kernels into LDS (rows of stride P1 / P2, zero beyond Q1 / Q2), both
+    // row buffers cleared (their padding stays zero); equilibrium coefficients of every
+    // (run, cell)
     constexpr int E = sizeof(T);
+    const int L1 = lds_len(Q1, E), L2 = lds_len(Q2, E);        // dot-product lengths
     const int P1 = lds_stride(Q1, E), P2 = lds_stride(Q2, E);  // LDS row strides
+    const int S = row_slot(Q1, Q2, E);
     const int n1 = Q1 * P1, n2 = Q2 * P2;
     for (int x = t; x < n1 + n2; x += kStageThreads) {
         T v = T(0);
@@ -198,6 +181,7 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
         }
         Ks[x] = v;
     }
+    for (int x = t; x < 2 * kRowElems; x += kStageThreads) rows[x] = T(0);
     const int N1 = I.N1, N2 = I.N2;
     for (int x = t; x < R * TC; x += kStageThreads) {
         const int rr = x / TC, cc = x - rr * TC, s = s0 + rr * TC + cc;
@@ -255,13 +239,6 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
         coff = 3 + 2 * (N1 + 1) + ((I.kind2 == 1 && j >= I.Qh2) ? nb : 0);
     }
 
-    // the run's first cell into row buffer 1: its force contractions are the matrix-core
-    // jobs before the sweep (each cell's are computed a cell ahead, into the buffer the
-    // sweep reads in the next cell)
-    const T* Kt = Ks + n1;
-    if (rlen > 0 && k < NV) rows[3 * kStageThreads + t] = (static_cast<const T*>(A.Fin) + I.offF +
-                                                        (size_t)dist * NR * NV + (size_t)rs0 * NV)[k];
-
     // ---- diffuse walls: n_w of Eq. nw, FP64 half-range sums reduced over the run
     const T* Fd = static_cast<const T*>(A.Fin) + I.offF + (size_t)dist * NR * NV;
     const T* Fp = static_cast<const T*>(A.Fin) + I.offF;
@@ -290,11 +267,6 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     }
     __syncthreads();
     const int w0 = r * (nvpad / kWave), nw_waves = nvpad / kWave;
-    if (rlen > 0) {
-        T* rb = rows + 3 * kStageThreads + r * nvpad;
-        force_mfma<T>(rb, Ks, Kt, P1, P2, Q1, Q2, wave - w0, nw_waves, lane, rb + kStageThreads,
-                      rb + 2 * kStageThreads);
-    }
     double nw_in = 0.0, nw_out = 0.0;
     if (rlen > 0) {
         double sin_ = 0.0, sout = 0.0;
@@ -344,6 +316,9 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     const double dt = A.l_only ? 1.0 : I.dt;
     const T cdt = T(A.cc * dt), ca = T(A.ca), cb = T(A.cb);
     const double* resW = tab + I.tresW;
+    const T* Kt = Ks + n1;
+    const T* K1row = Ks + vi * P1;
+    const T* Ktrow = Kt + vj * P2;
     const double pw1 = (double)p1, pw2 = (double)p2;
     const double wmk = Wm[kk], rwk = resW[kk];
 
@@ -373,12 +348,13 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     // issued at its start, and that cell's work is what covers their latency
     const bool need_fn = !A.l_only && ca != T(0);
     constexpr int kAhead = sizeof(T) == 4 ? 4 : 2;
-    T pw[kAhead], fnr[kAhead];
+    T pw[kAhead], fnr[kAhead], cr[LIN ? kAhead : 1];   // (the linearised stage also streams its forcing)
 #pragma unroll
     for (int q = 0; q < kAhead; ++q) {
         const int x = rs0 + 3 + q;
         pw[q] = (act && q < rlen && x < NR) ? (Fd + (size_t)x * NV)[k] : T(0);
         fnr[q] = (act && need_fn && q < rlen) ? (Fnd + (size_t)(rs0 + q) * NV)[k] : T(0);
+        if constexpr (LIN) cr[q] = (act && q < rlen) ? (Cd + (size_t)(rs0 + q) * NV)[k] : T(0);
     }
 
     // the run's first wavefront also finishes the previous cell's sums and its last one
@@ -392,22 +368,29 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     // the ring (a store issued late in the cell would be waited for there)
     T out_prev = T(0);
     T* st_prev = nullptr;
+    // linearised stage: the node factors of the run's first cell (loaded a cell ahead)
+    float4 lin_t4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (LIN && coff >= 0) lin_t4 = A.lin_node[(size_t)I.offG + (size_t)rs0 * (Q1 + Q2) + kg];
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // the ring's first loads
     for (int c = 0; c < TC; ++c) {
         const int buf = c & 1;
         const bool cv = act && c < rlen;
         const int s = rs0 + c;
         const T fn_cur = fnr[0];
+        const T c_cur = cr[0];
         const T lead = pw[0];
+        // this cell's prefetch loads; the ring shifts at the end of the cell, so their first
+        // use (and the wait for them) is at the loop latch
+        T pw_new = T(0), fn_new = T(0), c_new = T(0);
         if (cv) {
-#pragma unroll
-            for (int q = 0; q < kAhead - 1; ++q) { pw[q] = pw[q + 1]; fnr[q] = fnr[q + 1]; }
             const int x = s + 3 + kAhead;
-            pw[kAhead - 1] = (c + kAhead < rlen && x < NR) ? (Fd + (size_t)x * NV)[k] : T(0);
-            fnr[kAhead - 1] = (need_fn && c + kAhead < rlen) ? (Fnd + (size_t)(s + kAhead) * NV)[k] : T(0);
+            if (c + kAhead < rlen && x < NR) pw_new = (Fd + (size_t)x * NV)[k];
+            if (need_fn && c + kAhead < rlen) fn_new = (Fnd + (size_t)(s + kAhead) * NV)[k];
+            if (LIN && c + kAhead < rlen) c_new = (Cd + (size_t)(s + kAhead) * NV)[k];
         }
         if (st_prev) { *st_prev = out_prev; st_prev = nullptr; }
-        T* rowb = rows + (size_t)buf * 3 * kStageThreads;   // cell s+1's row and its contractions (jobs)
-        const T* rowp = rows + (size_t)(buf ^ 1) * 3 * kStageThreads;   // cell s's contractions
+        T* row = rows + (size_t)buf * kRowElems + (size_t)r * 2 * S;
+        T* rowT = row + S;
         T* gb = gbuf + (size_t)buf * kMaxRuns * kWave + (size_t)r * kWave;
         T* gd = gbdb + (size_t)buf * kMaxRuns * kWave + (size_t)r * kWave;
         const double* e = eqc + (size_t)(r * TC + c) * kEqStride;
@@ -415,11 +398,13 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
             w0v = w1v; w1v = w2v; w2v = w3v; w3v = w4v; w4v = w5v;
             // s is wavefront-uniform: interior cells take a plain load
             w5v = s + 3 < NR ? lead : (s + 3 == NR ? gh0 : (s + 3 == NR + 1 ? gh1 : gh2));
-            rowb[t] = w3v;
+            row[vi * P2 + vj] = w2v;
+            rowT[vj * P1 + vi] = w2v;
         }
         if (coff >= 0 && c < rlen) {
             if constexpr (LIN) {
-                const float4 t4 = A.lin_node[(size_t)I.offG + (size_t)s * (Q1 + Q2) + kg];
+                const float4 t4 = lin_t4;
+                if (c + 1 < rlen) lin_t4 = A.lin_node[(size_t)I.offG + (size_t)(s + 1) * (Q1 + Q2) + kg];
                 const double du = kg < Q1 ? e[5] : e[6];
                 gb[kg] = T(t4.x);
                 gd[kg] = T(du * (double)t4.y + e[4] * (double)t4.z);
@@ -431,15 +416,18 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
         }
         __syncthreads();
         if (c > 0) finish(c - 1, buf ^ 1);
-        if (c + 1 < rlen)
-            force_mfma<T>(rowb + r * nvpad, Ks, Kt, P1, P2, Q1, Q2, wave - w0, nw_waves, lane,
-                          rowb + kStageThreads + r * nvpad, rowb + 2 * kStageThreads + r * nvpad);
         double m0 = 0, m1 = 0, m2 = 0, m3 = 0, rd = 0, rn = 0;
         if (cv) {
             const T fr = weno_face<T, LIN>(pos, w0v, w1v, w2v, w3v, w4v, w5v, weps);
             const T Rl = T(e[kEqGeo]), Rr = T(e[kEqGeo + 1]), gam = T(e[kEqGeo + 3]);   // R_{s-+1/2}/dchi_s
             const T adv = p1 * (Rr * fr - Rl * fl);
-            const T kf = rowp[kStageThreads + t], ktf = rowp[2 * kStageThreads + t];
+            T kf = T(0), ktf = T(0);
+            if constexpr (sizeof(T) == 4) {
+                dot2_lds(K1row, rowT + vj * P1, L1, Ktrow, row + vi * P2, L2, kf, ktf);
+            } else {
+                kf = dot_lds<T>(K1row, rowT + vj * P1, L1);
+                ktf = dot_lds<T>(Ktrow, row + vi * P2, L2);
+            }
             const T force = gam * (p2 * p2 * kf - p1 * ktf);
             T fe;
             if constexpr (LIN) {
@@ -452,7 +440,8 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
             }
             const T Fc = w2v;
             T L = -adv - force - (Fc - fe) * T(e[2]);
-            if (Cd) L += Cd[(size_t)s * NV + k];
+            if constexpr (LIN) L += c_cur;
+            else if (Cd) L += Cd[(size_t)s * NV + k];
             T out;
             if (A.l_only) {
                 out = L;
@@ -484,6 +473,21 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
             double* mp = mpart + ((size_t)buf * (kStageThreads / kWave) + wave) * 32 + (lane >> 4);
             mp[0] = m0; mp[4] = m1; mp[8] = m2; mp[12] = m3; mp[16] = rd; mp[20] = rn;
         }
+        // the prefetch loads this cell issued are waited for here, after the cell's work,
+        // where the ring shifts (left to itself, the compiler waits for every outstanding
+        // load at the top of the next cell, right behind the loads issued there)
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+        if (cv) {
+#pragma unroll
+            for (int q = 0; q < kAhead - 1; ++q) { pw[q] = pw[q + 1]; fnr[q] = fnr[q + 1]; }
+            pw[kAhead - 1] = pw_new;
+            fnr[kAhead - 1] = fn_new;
+            if constexpr (LIN) {
+#pragma unroll
+                for (int q = 0; q < kAhead - 1; ++q) cr[q] = cr[q + 1];
+                cr[kAhead - 1] = c_new;
+            }
+        }
     }
     if (st_prev) *st_prev = out_prev;
     __syncthreads();
@@ -491,17 +495,19 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
 }
 
 // Moment sums [n, sum p1 f', sum p2 f', sum |p|^2 f', sum f''] of a state, per cell
-// (FP64 accumulation; populations weighted by Wm, 1 for unscaled FP64 states).
+// (FP64 accumulation; populations weighted by Wm, 1 for unscaled FP64 states); with a
+// mask, only the instances whose mask entry equals want.
 template <typename T>
 __global__ __launch_bounds__(256) void couette_moments(const InstDesc* insts, const WorkItem* work,
-                                                       const double* tab_all, const T* F, double* msum) {
+                                                       const double* tab_all, const T* F, double* msum,
+                                                       const int* mask, int want) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const WorkItem* wp = work + (size_t)blockIdx.x * kWavesPerBlock + wave;
     const int inst = __builtin_amdgcn_readfirstlane(wp->inst);
     const int dist = __builtin_amdgcn_readfirstlane(wp->dist);
     const int s0 = __builtin_amdgcn_readfirstlane(wp->s0);
     const int ncell = __builtin_amdgcn_readfirstlane(wp->ncell);
-    if (ncell <= 0 || dist != 0) return;
+    if (ncell <= 0 || dist != 0 || (mask && mask[inst] != want)) return;
     const InstDesc& I = insts[inst];
     const double* tab = tab_all + I.offT;
     const double* Wm = tab + I.tWm;
@@ -824,13 +830,13 @@ hipError_t launch_stage(int fp32, int nblocks, hipStream_t st, const StageArgs& 
 }
 
 hipError_t launch_moments(int fp32, int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
-                          const double* tab, const void* F, double* msum) {
+                          const double* tab, const void* F, double* msum, const int* mask, int want) {
     if (fp32)
         hipLaunchKernelGGL(couette_moments<float>, dim3(nblocks), dim3(kWave * kWavesPerBlock), 0, st, insts, work,
-                           tab, static_cast<const float*>(F), msum);
+                           tab, static_cast<const float*>(F), msum, mask, want);
     else
         hipLaunchKernelGGL(couette_moments<double>, dim3(nblocks), dim3(kWave * kWavesPerBlock), 0, st, insts, work,
-                           tab, static_cast<const double*>(F), msum);
+                           tab, static_cast<const double*>(F), msum, mask, want);
     return hipGetLastError();
 }
 
