@@ -295,7 +295,7 @@ def main():
         steps, r, ok = b.run_to_steady(1e-10, 100000, 500)
         torch.cuda.synchronize()
         tts[name] = dict(seconds=time.perf_counter() - t0, steps=int(steps[0]), converged=bool(ok),
-                         fp32_steps=b.fp32_steps() if prec else 0, tile=single_tile)
+                         fp32_steps=int(b.mixed_report()[2][0]) if prec else 0, tile=single_tile)
         b.close()
 
     channel = None

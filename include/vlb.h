@@ -198,6 +198,20 @@ vlb_status vlb_total_mass(vlb_batch* b, double* Ntot);
  * start (vlb_batch_warm_report). */
 vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check_every, long* steps, double* r);
 vlb_status vlb_mixed_fp32_steps(const vlb_batch* b, long* n);
+/* State of the defect correction per instance (host arrays of B, any may be NULL, not
+ * all): the relaxation factor theta of its next update F += theta * delta (1: the full
+ * correction; halved to at least 1/8 after three checks in a row without a new residual
+ * low by 1 %, doubled back after eight in a row with one); the step of the current run at
+ * which it left the correction for FP64 steps for good (-1: it has not); the FP32
+ * correction steps it took in the current run.  An instance is put on a trial of FP64
+ * steps (5 checks) when its update was just halved, or when its residual fell by less than
+ * a factor 10 over the last 10 checks, at least 20 checks after its last trial (40, 80, ...
+ * after each lost one); it keeps FP64 steps if their residual decay rate beats the
+ * correction's over the checks before the trial by a factor 1.5 (fp64_from is then the
+ * trial's first step), else it returns to the correction.  An instance that sets no new
+ * low for 20000 steps also keeps FP64 steps.  1 / -1 / 0 for an FP64 batch or before a
+ * run. */
+vlb_status vlb_mixed_report(const vlb_batch* b, double* theta, long* fp64_from, long* fp32_steps);
 
 /* Host-side velocity-set tables of one axis, for checking against independent
  * implementations: nodes p, weights w (nodes entries), d/dp kernel K and d(p .)/dp

@@ -136,13 +136,21 @@ struct vlb_batch {
     // defect correction: per-instance relaxation of the update (halved, down to 1/8, after
     // three checks in a row without a new residual low, doubled back towards 1 after eight
     // in a row with one), the lowest residual, when it was set and the run of checks
-    // without / with a new low, and the switch to FP64 steps for the rest of the run when
-    // an instance sets no new low for kDcWindow steps (dc64: it then takes FP64 steps inside
-    // the correction loop, launched beside the linearised FP32 ones)
+    // without / with a new low; dc64: the instance takes FP64 steps inside the correction
+    // loop, launched beside the linearised FP32 ones, either on trial (after a halving, for
+    // kTrialChecks checks, to compare the FP64 convergence rate with the correction's) or
+    // for the rest of the run (the trial's rate won, or no new low for kDcWindow steps)
     std::vector<double> theta, dc_best;
     std::vector<long> dc_best_at;
     std::vector<int> dc_miss, dc_hit;
     std::vector<int> dc64;
+    std::vector<long> dc64_at;     // run step of the final switch to FP64 steps (-1: none)
+    std::vector<long> fp32_inst;   // FP32 correction steps per instance in the current run
+    std::vector<long> trial_at;    // run step at which the current FP64 trial began (-1: none)
+    std::vector<long> trial_end;   // run step at which the last trial ended (-1: none yet)
+    std::vector<long> trial_gap;   // steps from the end of one trial to the earliest next one
+    std::vector<double> trial_r0, dc_rate;   // residual at the trial's start; the correction's rate before it
+    std::vector<std::vector<std::pair<long, double>>> dc_hist;   // recent (step, residual) checks under the correction
     std::vector<BlockWork> blocks_lin, blocks_64;   // the split of `blocks` by dc64
     int n_dc64 = 0;
     std::vector<InstDesc> desc32;       // FP32 descriptors (rescaled tables)
@@ -316,6 +324,14 @@ void reset_run_state(vlb_batch* b, const int* warm) {
     b->dc_best.assign(b->B, INFINITY);
     b->dc_best_at.assign(b->B, 0);
     b->dc64.assign(b->B, 0);
+    b->dc64_at.assign(b->B, -1);
+    b->fp32_inst.assign(b->B, 0);
+    b->trial_at.assign(b->B, -1);
+    b->trial_end.assign(b->B, -1);
+    b->trial_gap.assign(b->B, 0);
+    b->trial_r0.assign(b->B, 0.0);
+    b->dc_rate.assign(b->B, 0.0);
+    b->dc_hist.assign(b->B, {});
     b->n_dc64 = 0;
 }
 
@@ -525,6 +541,11 @@ vlb_status run_stage(vlb_batch* b, int stage, bool last, bool l_only) {
 
 constexpr int kGraphSteps = 10;
 constexpr long kDcWindow = 20000;   // steps without a new residual low that move an instance to FP64 steps
+constexpr int kTrialChecks = 5;     // checks of an FP64 trial
+constexpr int kRateChecks = 10;     // checks over which the correction's rate is measured
+constexpr int kTrialGap = 4;        // trial lengths between trials of an instance (doubled after each lost one)
+constexpr double kTrialGain = 1.5;  // the FP64 rate must beat the correction's by this factor to be kept
+constexpr double kSlowDecade = 10;  // a correction slower than one decade per kRateChecks checks is put on trial
 
 void drop_graphs(vlb_batch* b) {
     for (hipGraphExec_t& g : b->graph)
@@ -1165,23 +1186,68 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
             s = init_from_surrogate(b, restart);
             if (s != VLB_OK) return s;
             for (int i = 0; i < b->B; ++i)
-                if (restart[i] == 0) {
+                if (restart[i] == 0) {   // the cold start is a new problem for the correction
                     b->theta[i] = 1.0;
                     b->dc_miss[i] = 0;
                     b->dc_hit[i] = 0;
                     b->dc_best[i] = INFINITY;
                     b->dc_best_at[i] = b->run_steps;
+                    b->dc_hist[i].clear();
+                    b->trial_at[i] = b->trial_end[i] = -1;
+                    b->trial_gap[i] = 0;
+                    b->dc64_at[i] = -1;
+                    if (b->dc64[i]) {
+                        b->dc64[i] = 0;
+                        --b->n_dc64;
+                        dc_split = true;
+                    }
                 }
         }
         if (dc) {
             // relaxation of the defect correction: an instance that sets no new residual low
             // (by 1 %) at three checks in a row has its update halved (a mode the linearised
             // operator overshoots otherwise makes the iteration cycle), one that sets eight
-            // in a row has it doubled back towards the full correction; an instance with no
-            // new low for kDcWindow steps takes FP64 steps inside the correction loop from
-            // then on (beside the others' FP32 steps)
+            // in a row has it doubled back towards the full correction.  The linearised
+            // operator can also leave the correction converging far slower than FP64 steps
+            // would: an instance whose update was just halved, or whose residual fell by
+            // less than kSlowDecade over the last kRateChecks checks, is put on an FP64 trial
+            // (kTrialChecks checks of FP64 steps, beside the others' FP32 steps; trials of
+            // an instance kTrialGap trial lengths apart, twice as far after each lost one).
+            // It keeps FP64 steps if their residual decay rate beats the correction's over
+            // the checks before the trial by kTrialGain, else it returns to the correction.
+            // An instance with no new low for kDcWindow steps takes FP64 steps for good.
+            const long trial_len = (long)kTrialChecks * check_every;
+            auto to_fp64 = [&](int i) {
+                b->dc64[i] = 1;
+                ++b->n_dc64;
+                dc_split = true;
+            };
             for (int i = 0; i < b->B; ++i) {
-                if (conv[i] >= 0) continue;
+                if (conv[i] >= 0 || b->dc64_at[i] >= 0) continue;
+                if (b->trial_at[i] >= 0) {   // FP64 trial in progress
+                    const long len = b->run_steps - b->trial_at[i];
+                    if (len < trial_len) continue;
+                    const double rate64 = std::log(b->trial_r0[i] / res[i]) / (double)len;
+                    if (rate64 > kTrialGain * std::max(b->dc_rate[i], 0.0)) {
+                        b->dc64_at[i] = b->trial_at[i];
+                    } else {
+                        b->dc64[i] = 0;
+                        --b->n_dc64;
+                        dc_split = true;
+                        b->dc_hist[i].clear();
+                        b->dc_best[i] = res[i];
+                        b->dc_best_at[i] = b->run_steps;
+                        b->dc_miss[i] = b->dc_hit[i] = 0;
+                        b->trial_gap[i] *= 2;
+                    }
+                    b->trial_at[i] = -1;
+                    b->trial_end[i] = b->run_steps;
+                    continue;
+                }
+                auto& h = b->dc_hist[i];
+                h.emplace_back(b->run_steps, res[i]);
+                if (h.size() > (size_t)kRateChecks + 1) h.erase(h.begin());
+                bool halved = false;
                 if (res[i] < 0.99 * b->dc_best[i]) {
                     b->dc_best[i] = res[i];
                     b->dc_best_at[i] = b->run_steps;
@@ -1190,17 +1256,28 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
                         b->theta[i] = std::min(1.0, 2.0 * b->theta[i]);
                         b->dc_hit[i] = 0;
                     }
+                } else {
+                    b->dc_hit[i] = 0;
+                    if (++b->dc_miss[i] >= 3) {
+                        b->theta[i] = std::max(0.125, 0.5 * b->theta[i]);
+                        b->dc_miss[i] = 0;
+                        halved = true;
+                    }
+                }
+                if (b->trial_gap[i] == 0) b->trial_gap[i] = kTrialGap * trial_len;
+                const bool may_try = b->trial_end[i] < 0 || b->run_steps - b->trial_end[i] >= b->trial_gap[i];
+                const bool slow = h.size() == (size_t)kRateChecks + 1 && h.front().second < kSlowDecade * h.back().second;
+                if (may_try && h.size() > (size_t)kTrialChecks && (halved || slow)) {
+                    b->dc_rate[i] = std::log(h.front().second / h.back().second) /
+                                    (double)(h.back().first - h.front().first);
+                    b->trial_at[i] = b->run_steps;
+                    b->trial_r0[i] = res[i];
+                    to_fp64(i);
                     continue;
                 }
-                b->dc_hit[i] = 0;
-                if (++b->dc_miss[i] >= 3) {
-                    b->theta[i] = std::max(0.125, 0.5 * b->theta[i]);
-                    b->dc_miss[i] = 0;
-                }
-                if (!b->dc64[i] && b->run_steps - b->dc_best_at[i] >= kDcWindow) {
-                    b->dc64[i] = 1;
-                    ++b->n_dc64;
-                    dc_split = true;
+                if (b->run_steps - b->dc_best_at[i] >= kDcWindow) {
+                    b->dc64_at[i] = b->run_steps;
+                    to_fp64(i);
                 }
             }
         }
@@ -1221,6 +1298,8 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
             if (m > 0) {
                 s = defect_correction(b, m);
                 if (s != VLB_OK) return s;
+                for (int i = 0; i < b->B; ++i)
+                    if (conv[i] < 0 && !b->dc64[i]) b->fp32_inst[i] += m;
                 done += m;
                 b->run_steps += m;
                 b->fp32_steps += m;
@@ -1230,6 +1309,17 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
     if (steps) std::copy(conv.begin(), conv.end(), steps);
     if (r) std::copy(res.begin(), res.end(), r);
     return remaining ? fail(VLB_ENOTCONV, "%d instance(s) above tol after %ld steps", remaining, done) : VLB_OK;
+}
+
+vlb_status vlb_mixed_report(const vlb_batch* b, double* theta, long* fp64_from, long* fp32_steps) {
+    if (!b || (!theta && !fp64_from && !fp32_steps)) return fail(VLB_EINVAL, "null argument");
+    const bool have = b->theta.size() == (size_t)b->B;
+    for (int i = 0; i < b->B; ++i) {
+        if (theta) theta[i] = have ? b->theta[i] : 1.0;
+        if (fp64_from) fp64_from[i] = have ? b->dc64_at[i] : -1;
+        if (fp32_steps) fp32_steps[i] = have ? b->fp32_inst[i] : 0;
+    }
+    return VLB_OK;
 }
 
 vlb_status vlb_mixed_fp32_steps(const vlb_batch* b, long* n) {

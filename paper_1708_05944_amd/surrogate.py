@@ -46,7 +46,9 @@ def heldout_runs(heldout_descs, mlp, probe: int = 500, max_steps: int = 200_000,
     surrogate's warm start, each in FP64 and in mixed precision (defect correction).
     Per leg: steps at convergence per instance (-1 if not converged), wall-clock seconds
     of the whole batch (until every instance converged, or max_steps), the warm starts
-    kept by the acceptance probe and the instances restarted cold by the stall watch."""
+    kept by the acceptance probe, the instances restarted cold by the stall watch, and for
+    the mixed legs the FP32 correction steps summed over the instances and the instances
+    that left the correction for FP64 steps for good."""
     import torch
     from .vlb import VLB_MIXED
     runs = {}
@@ -66,9 +68,10 @@ def heldout_runs(heldout_descs, mlp, probe: int = 500, max_steps: int = 200_000,
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         on_warm, fell = b.warm_report()
+        _, fp64_from, n32 = b.mixed_report()
         runs[name] = dict(steps=steps, times=times + t_ws, seconds=secs, used=used, warm_start_seconds=t_ws,
-                          fp32_steps=b.fp32_steps() if prec else 0, fallback_at=fell, converged=int((steps >= 0).sum()),
-                          probe_steps=2 * probe * int(warm))
+                          fp32_steps=int(n32.sum()), fp64_kept=int((fp64_from >= 0).sum()), fallback_at=fell,
+                          converged=int((steps >= 0).sum()), probe_steps=2 * probe * int(warm))
         if keep_fields:
             runs[name]["fields"] = [b.moments(i) for i in range(b.B)]
         b.close()
@@ -78,13 +81,14 @@ def heldout_runs(heldout_descs, mlp, probe: int = 500, max_steps: int = 200_000,
 def summarise(runs, max_steps: int):
     """Honest totals of heldout_runs: an instance that did not converge counts max_steps
     steps (and the batch's whole wall time); speed-ups compare the legs over all
-    instances."""
+    instances; fp32_share = FP32 correction steps / all steps of the instances."""
     out = {}
     for name, rr in runs.items():
         st = np.where(rr["steps"] >= 0, rr["steps"], max_steps)
         out[name] = dict(converged=rr["converged"], instances=len(st), steps_total=int(st.sum() + rr["probe_steps"]),
                          seconds=float(rr["seconds"]), warm_used=int(np.sum(rr["used"])),
                          cold_restarts=int((rr["fallback_at"] >= 0).sum()), fp32_steps=int(rr["fp32_steps"]),
+                         fp32_share=float(rr["fp32_steps"] / st.sum()), fp64_kept=int(rr["fp64_kept"]),
                          per_instance_steps=[int(x) for x in rr["steps"]])
     pairs = (("warm_fp64", "cold_fp64"), ("warm_mixed", "cold_mixed"), ("warm_mixed", "cold_fp64"),
              ("cold_mixed", "cold_fp64"))

@@ -133,6 +133,7 @@ _SIGS = {
     "vlb_step": [ctypes.c_void_p, ctypes.c_long],
     "vlb_step_fp64": [ctypes.c_void_p, ctypes.c_long],
     "vlb_mixed_fp32_steps": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_long)],
+    "vlb_mixed_report": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "vlb_apply_L": [ctypes.c_void_p, _dp, ctypes.c_size_t],
     "vlb_moments": [ctypes.c_void_p, ctypes.c_int] + [_dp] * 7,
     "vlb_residual": [ctypes.c_void_p, _dp],
@@ -317,6 +318,17 @@ class Batch:
         n = ctypes.c_long()
         _check(load_library().vlb_mixed_fp32_steps(self._h, ctypes.byref(n)), "vlb_mixed_fp32_steps")
         return n.value
+
+    def mixed_report(self):
+        """Per instance: (relaxation factor of the defect correction, step at which it left
+        the correction for FP64 steps for good or -1, FP32 correction steps taken)."""
+        theta = np.empty(self.B)
+        at = np.empty(self.B, dtype=np.int64)
+        n32 = np.empty(self.B, dtype=np.int64)
+        vp = ctypes.c_void_p
+        _check(load_library().vlb_mixed_report(self._h, theta.ctypes.data_as(vp), at.ctypes.data_as(vp),
+                                               n32.ctypes.data_as(vp)), "vlb_mixed_report")
+        return theta, at, n32
 
     def apply_L(self) -> np.ndarray:
         out = np.empty(self.state_size)

@@ -57,7 +57,8 @@ def _steady(descs, prec, max_steps=80_000):
     b = Batch(descs, precision=prec)
     m0 = b.total_mass()
     steps, r, ok = b.run_to_steady(1e-10, max_steps, 500)
-    out = dict(ok=ok, steps=steps, r=r, mass=b.total_mass() / m0 - 1, fp32=b.fp32_steps(),
+    _, fp64_from, n32 = b.mixed_report()
+    out = dict(ok=ok, steps=steps, r=r, mass=b.total_mass() / m0 - 1, fp32=n32, fp64_from=fp64_from,
                fields=[b.moments(i) for i in range(b.B)])
     b.close()
     return out
@@ -80,9 +81,10 @@ def test_mixed_steady_state_matches_fp64():
     assert r64["ok"] and rmx["ok"], (r64["r"], rmx["r"])
     assert abs(r64["mass"][0]) < r64["steps"][0] * 2.2e-16
     errs = _profile_errors(rmx["fields"][0], r64["fields"][0])
-    _say(f"steps fp64 {r64['steps'][0]}, mixed {rmx['steps'][0]} ({rmx['fp32']} in FP32); mass drift "
+    _say(f"steps fp64 {r64['steps'][0]}, mixed {rmx['steps'][0]} ({rmx['fp32'][0]} in FP32); mass drift "
          f"{rmx['mass'][0]:.1e}; profile errors {errs}")
-    assert rmx["fp32"] >= 0.8 * rmx["steps"][0]
+    assert rmx["fp32"][0] >= 0.8 * rmx["steps"][0]
+    assert rmx["fp64_from"][0] == -1
     assert abs(rmx["mass"][0]) < 1e-9
     assert max(errs.values()) <= 1e-5
 
@@ -107,7 +109,9 @@ def test_mixed_batched_sweep_subset_matches_fp64():
         for k, v in e.items():
             worst[k] = max(worst.get(k, 0.0), v)
     _say(f"converged {int((r64['steps'] >= 0).sum())}/6; steps fp64 {list(r64['steps'])}, mixed "
-         f"{list(rmx['steps'])}, FP32 steps {rmx['fp32']}; worst profile errors {worst}")
+         f"{list(rmx['steps'])}, FP32 steps {list(rmx['fp32'])} (kept FP64 from {list(rmx['fp64_from'])}); "
+         f"worst profile errors {worst}")
+    assert (rmx["fp32"] <= np.where(rmx["steps"] >= 0, rmx["steps"], 450_000)).all()
     assert (r64["steps"] >= 0).sum() >= 5
     assert max(worst.values()) <= 1e-5
 
