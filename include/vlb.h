@@ -178,7 +178,9 @@ vlb_status vlb_total_mass(vlb_batch* b, double* Ntot);
 
 /* Step every instance until its residual is below tol, checking every check_every
  * steps, at most max_steps steps.  An instance whose residual is below tol at a check
- * retires: the stage kernels stop advancing it while the others run, so its state,
+ * retires: the stage kernels stop advancing it while the others run (on shorter cell runs
+ * than vlb_batch_set_tile / vlb_batch_autotune chose once those left no longer fill the
+ * 256 CUs; the chosen length is restored on return), so its state,
  * moments and residual stay those of the step at which it converged.  steps / r (host
  * arrays of B, may be NULL) receive that step count (or -1) and the last residual.  Returns
  * VLB_ENOTCONV if some instance did not converge.  The residual judged is always the
@@ -206,11 +208,12 @@ vlb_status vlb_mixed_fp32_steps(const vlb_batch* b, long* n);
  * correction steps it took in the current run.  An instance is put on a trial of FP64
  * steps (5 checks) when its update was just halved, or when its residual fell by less than
  * a factor 10 over the last 10 checks, at least 20 checks after its last trial (40, 80, ...
- * after each lost one); it keeps FP64 steps if their residual decay rate beats the
- * correction's over the checks before the trial by a factor 1.5 (fp64_from is then the
- * trial's first step), else it returns to the correction.  An instance that sets no new
- * low for 20000 steps also keeps FP64 steps.  1 / -1 / 0 for an FP64 batch or before a
- * run. */
+ * after each lost one); it keeps FP64 steps if its residual fell by a factor 2 over the
+ * trial and decayed 1.5 times faster than under the correction over the checks before
+ * (fp64_from is then the trial's first step), else it returns to the correction.  On FP64
+ * steps, an instance that sets no new low for 20000 steps (plain stepping can settle
+ * into a cycle that the relaxed correction damps) returns to the correction with theta =
+ * 1/8.  1 / -1 / 0 for an FP64 batch or before a run. */
 vlb_status vlb_mixed_report(const vlb_batch* b, double* theta, long* fp64_from, long* fp32_steps);
 
 /* Host-side velocity-set tables of one axis, for checking against independent

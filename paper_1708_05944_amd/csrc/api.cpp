@@ -110,6 +110,7 @@ struct vlb_batch {
     std::vector<BlockWork> blocks;     // stage-kernel blocks
     size_t max_blocks = 0;             // device capacity of the block list
     int tile = 0;                      // cells per run of the current block list
+    int tile_set = kTileCells;         // cells per run chosen by vlb_batch_set_tile / vlb_batch_autotune
     std::vector<LaunchGroup> groups;
     std::vector<double> tab;
     size_t state_n = 0, ncells = 0;
@@ -137,14 +138,14 @@ struct vlb_batch {
     // three checks in a row without a new residual low, doubled back towards 1 after eight
     // in a row with one), the lowest residual, when it was set and the run of checks
     // without / with a new low; dc64: the instance takes FP64 steps inside the correction
-    // loop, launched beside the linearised FP32 ones, either on trial (after a halving, for
-    // kTrialChecks checks, to compare the FP64 convergence rate with the correction's) or
-    // for the rest of the run (the trial's rate won, or no new low for kDcWindow steps)
+    // loop, launched beside the linearised FP32 ones, either on trial (kTrialChecks checks,
+    // to compare the FP64 convergence rate with the correction's) or after a trial it won
+    // (until it sets no new low for kDcStuck steps: then it returns to the correction)
     std::vector<double> theta, dc_best;
     std::vector<long> dc_best_at;
     std::vector<int> dc_miss, dc_hit;
     std::vector<int> dc64;
-    std::vector<long> dc64_at;     // run step of the final switch to FP64 steps (-1: none)
+    std::vector<long> dc64_at;     // run step of the switch to FP64 steps after a won trial (-1: none)
     std::vector<long> fp32_inst;   // FP32 correction steps per instance in the current run
     std::vector<long> trial_at;    // run step at which the current FP64 trial began (-1: none)
     std::vector<long> trial_end;   // run step at which the last trial ended (-1: none yet)
@@ -540,11 +541,12 @@ vlb_status run_stage(vlb_batch* b, int stage, bool last, bool l_only) {
 }
 
 constexpr int kGraphSteps = 10;
-constexpr long kDcWindow = 20000;   // steps without a new residual low that move an instance to FP64 steps
+constexpr long kDcStuck = 20000;    // steps without a new residual low that return an instance to the correction
 constexpr int kTrialChecks = 5;     // checks of an FP64 trial
 constexpr int kRateChecks = 10;     // checks over which the correction's rate is measured
 constexpr int kTrialGap = 4;        // trial lengths between trials of an instance (doubled after each lost one)
 constexpr double kTrialGain = 1.5;  // the FP64 rate must beat the correction's by this factor to be kept
+constexpr double kTrialDrop = 2;    // ... and the residual fall by at least this factor over the trial
 constexpr double kSlowDecade = 10;  // a correction slower than one decade per kRateChecks checks is put on trial
 
 void drop_graphs(vlb_batch* b) {
@@ -603,6 +605,20 @@ void build_blocks(vlb_batch* b, int tile) {
     b->blocks_64.clear();
     for (const BlockWork& w : b->blocks)
         ((b->dc64.size() == (size_t)b->B && b->dc64[w.inst]) ? b->blocks_64 : b->blocks_lin).push_back(w);
+}
+
+// Cells per run for the instances still active in run_to_steady: the chosen length while
+// its block list fills the CUs (one 1024-thread block each), else the longest shorter one
+// that does (down to kMinTile): a partly filled launch costs the latency of its longest
+// block, which is the cell-run length.  Leaves the block list built for the result.
+int active_tile(vlb_batch* b) {
+    constexpr size_t kFillBlocks = 256;
+    for (int t = b->tile_set; t > kMinTile; --t) {
+        build_blocks(b, t);
+        if (b->blocks.size() >= kFillBlocks) return t;
+    }
+    build_blocks(b, kMinTile);
+    return kMinTile;
 }
 
 vlb_status upload_blocks(vlb_batch* b) {
@@ -1140,7 +1156,7 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
         ~Reinstate() {
             if (!dirty) return;
             b->active.clear();
-            build_blocks(b, b->tile);
+            build_blocks(b, b->tile_set);
             (void)upload_blocks(b);
         }
     } guard{b};
@@ -1213,31 +1229,50 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
             // less than kSlowDecade over the last kRateChecks checks, is put on an FP64 trial
             // (kTrialChecks checks of FP64 steps, beside the others' FP32 steps; trials of
             // an instance kTrialGap trial lengths apart, twice as far after each lost one).
-            // It keeps FP64 steps if their residual decay rate beats the correction's over
-            // the checks before the trial by kTrialGain, else it returns to the correction.
-            // An instance with no new low for kDcWindow steps takes FP64 steps for good.
+            // It keeps FP64 steps if their residual fell by kTrialDrop over the trial and
+            // decayed kTrialGain times faster than the correction's over the checks before,
+            // else it returns to the correction.  On FP64 steps an instance that sets no new
+            // low for kDcStuck steps (plain stepping can settle into a cycle the relaxed
+            // correction damps) returns to the correction at the smallest relaxation.
             const long trial_len = (long)kTrialChecks * check_every;
-            auto to_fp64 = [&](int i) {
-                b->dc64[i] = 1;
-                ++b->n_dc64;
+            auto set_fp64 = [&](int i, int on) {
+                if (b->dc64[i] == on) return;
+                b->dc64[i] = on;
+                b->n_dc64 += on ? 1 : -1;
                 dc_split = true;
             };
+            auto back_to_dc = [&](int i) {
+                set_fp64(i, 0);
+                b->dc_hist[i].clear();
+                b->dc_best[i] = res[i];
+                b->dc_best_at[i] = b->run_steps;
+                b->dc_miss[i] = b->dc_hit[i] = 0;
+            };
             for (int i = 0; i < b->B; ++i) {
-                if (conv[i] >= 0 || b->dc64_at[i] >= 0) continue;
+                if (conv[i] >= 0) continue;
+                if (b->dc64_at[i] >= 0) {   // on FP64 steps after a won trial
+                    if (res[i] < 0.99 * b->dc_best[i]) {
+                        b->dc_best[i] = res[i];
+                        b->dc_best_at[i] = b->run_steps;
+                    } else if (b->run_steps - b->dc_best_at[i] >= kDcStuck) {
+                        back_to_dc(i);
+                        b->dc64_at[i] = -1;
+                        b->theta[i] = 0.125;
+                        b->trial_end[i] = b->run_steps;
+                        b->trial_gap[i] *= 2;
+                    }
+                    continue;
+                }
                 if (b->trial_at[i] >= 0) {   // FP64 trial in progress
                     const long len = b->run_steps - b->trial_at[i];
                     if (len < trial_len) continue;
                     const double rate64 = std::log(b->trial_r0[i] / res[i]) / (double)len;
-                    if (rate64 > kTrialGain * std::max(b->dc_rate[i], 0.0)) {
+                    if (b->trial_r0[i] >= kTrialDrop * res[i] && rate64 > kTrialGain * std::max(b->dc_rate[i], 0.0)) {
                         b->dc64_at[i] = b->trial_at[i];
-                    } else {
-                        b->dc64[i] = 0;
-                        --b->n_dc64;
-                        dc_split = true;
-                        b->dc_hist[i].clear();
                         b->dc_best[i] = res[i];
                         b->dc_best_at[i] = b->run_steps;
-                        b->dc_miss[i] = b->dc_hit[i] = 0;
+                    } else {
+                        back_to_dc(i);
                         b->trial_gap[i] *= 2;
                     }
                     b->trial_at[i] = -1;
@@ -1272,17 +1307,12 @@ vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check
                                     (double)(h.back().first - h.front().first);
                     b->trial_at[i] = b->run_steps;
                     b->trial_r0[i] = res[i];
-                    to_fp64(i);
-                    continue;
-                }
-                if (b->run_steps - b->dc_best_at[i] >= kDcWindow) {
-                    b->dc64_at[i] = b->run_steps;
-                    to_fp64(i);
+                    set_fp64(i, 1);
                 }
             }
         }
         if (retired && remaining > 0) {
-            build_blocks(b, b->tile);
+            active_tile(b);
             s = upload_blocks(b);
             if (s != VLB_OK) return s;
         }
@@ -1333,6 +1363,7 @@ vlb_status vlb_batch_set_tile(vlb_batch* b, int cells_per_run) {
     if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
     HIP_TRY(hipStreamSynchronize(b->stream));
     build_blocks(b, cells_per_run);
+    b->tile_set = cells_per_run;
     return upload_blocks(b);
 }
 
@@ -1382,6 +1413,7 @@ vlb_status vlb_batch_autotune(vlb_batch* b, int steps, int* chosen, double* ms_p
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     build_blocks(b, best);
+    b->tile_set = best;
     vlb_status s2 = upload_blocks(b);
     HIP_TRY(hipMemcpyAsync(cur, keep, bytes, hipMemcpyDeviceToDevice, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
