@@ -238,6 +238,18 @@ vlb_status vlb_batch_autotune(vlb_batch* b, int steps, int* chosen, double* ms_p
  * launches (bitwise the same results). */
 vlb_status vlb_batch_set_graphs(vlb_batch* b, int enable);
 
+/* Multi-step launches (on by default, max_blocks = 64).  While the stage kernel's block
+ * list of the instances being stepped has at most max_blocks blocks (small batches, the
+ * last instances of a run_to_steady) and the device can hold them all resident, a call
+ * of two or more steps runs them in cooperative launches of up to 2000 whole RK3 steps
+ * each, with a grid-wide barrier between stages, instead of three launches (or graph
+ * nodes) per step: a small instance is bound by launch latency otherwise.  Results are
+ * bitwise those of plain launches (the same per-block stage code).  Not used for
+ * instances with large velocity sets, for the defect correction while it splits its
+ * instances between FP64 and linearised FP32 steps, or while per-launch timing is on.
+ * max_blocks = 0 turns it off. */
+vlb_status vlb_batch_set_persistent(vlb_batch* b, int max_blocks);
+
 /* Kernel timing for roofline reports.  When enabled, every launch of the stage kernel
  * is bracketed by HIP events recorded on the batch's stream; launches are grouped by
  * kernel instantiation.  vlb_timing_query synchronises the stream and returns, for up

@@ -20,6 +20,8 @@
 
 namespace vlb {
 hipError_t launch_stage(int fp32, int nblocks, hipStream_t st, const StageArgs& A);
+hipError_t launch_multi(int fp32, int nblocks, hipStream_t st, const MultiArgs& M);
+int multi_capacity(int fp32, int lin, int kmax);
 hipError_t launch_wide_stage(int NR, int Q1, int Q2, hipStream_t st, const WideArgs& A);
 size_t stage_lds(int kmax, int elem);
 hipError_t launch_moments(int fp32, int nblocks, hipStream_t st, const InstDesc* insts, const WorkItem* work,
@@ -161,6 +163,11 @@ struct vlb_batch {
     bool have_resid = false;
     bool timing = false;
     bool use_graphs = true;
+    // multi-step cooperative launches for block lists of at most persist_max blocks (0:
+    // never), and the resident-block capacity of each stage-kernel flavour (FP64, FP32,
+    // linearised FP32; -1 until queried)
+    int persist_max = 64;
+    int multi_cap[3] = {-1, -1, -1};
     hipStream_t cap_stream = nullptr;   // private stream used only to capture step graphs
     hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};   // [FP64, FP32, linearised FP32]: kGraphSteps steps
     std::vector<TimedLaunch> timed;
@@ -634,7 +641,58 @@ vlb_status upload_blocks(vlb_batch* b) {
     return VLB_OK;
 }
 
+constexpr long kMultiChunk = 2000;   // steps per multi-step launch
+
+// The multi-step launch applies: a single block list of at most persist_max blocks that
+// the device can hold resident at once, no large-velocity-set instance running, no
+// FP64 / linearised split of the defect correction, no per-launch timing.
+bool multi_ok(vlb_batch* b) {
+    if (b->persist_max <= 0 || b->timing || b->groups.size() != 1) return false;
+    if (b->lin && b->n_dc64 > 0) return false;
+    const int nb = (int)b->blocks.size();
+    if (nb <= 0 || nb > b->persist_max) return false;
+    for (int i = 0; i < b->B; ++i)
+        if (b->inst[i].wide && (b->active.empty() || b->active[i])) return false;
+    const int key = b->cur32 ? (b->lin ? 2 : 1) : 0;
+    if (b->multi_cap[key] < 0) b->multi_cap[key] = multi_capacity(b->cur32, b->lin, b->groups[0].kmax);
+    return nb <= b->multi_cap[key];
+}
+
+// nsteps RK3 steps in multi-step launches of at most kMultiChunk steps (the residual
+// partials taken in the last step's third stage, as step_current's last plain step does).
+vlb_status step_multi(vlb_batch* b, long nsteps) {
+    MultiArgs M{};
+    for (int q = 0; q < 3; ++q) {
+        const StageArgs S = stage_args(b, q, false, false, b->cur32, b->lin);
+        if (q == 0) M.base = S;
+        M.Fin[q] = S.Fin;
+        M.Fout[q] = S.Fout;
+        M.msum_in[q] = S.msum_in;
+        M.msum_out[q] = S.msum_out;
+        M.ca[q] = S.ca;
+        M.cb[q] = S.cb;
+        M.cc[q] = S.cc;
+    }
+    M.base.blocks = b->dblocks();
+    M.base.kmax = b->groups[0].kmax;
+    const int nb = (int)b->blocks.size();
+    for (long left = nsteps; left > 0;) {
+        const long n = std::min(left, kMultiChunk);
+        M.nsteps = (int)n;
+        M.rpart_last = (n == left && !b->lin) ? b->rpart() : nullptr;
+        HIP_TRY(launch_multi(b->cur32 ? 1 : 0, nb, b->stream, M));
+        left -= n;
+    }
+    if (!b->lin) {
+        HIP_TRY(launch_reduce(b->B, b->stream, b->cur32 ? b->ddesc32() : b->ddesc(), b->dtab(), b->rpart(), b->M(0),
+                              b->resid(), b->massv(), 1));
+        b->have_resid = true;
+    }
+    return VLB_OK;
+}
+
 vlb_status step_current(vlb_batch* b, long nsteps) {
+    if (nsteps >= 2 && multi_ok(b)) return step_multi(b, nsteps);
     // all but the last step: replay captured chunks of kGraphSteps steps
     if (b->use_graphs && !b->timing && nsteps > kGraphSteps) {
         hipGraphExec_t& g = b->graph[b->cur32 ? (b->lin ? 2 : 1) : 0];
@@ -1426,6 +1484,12 @@ vlb_status vlb_batch_autotune(vlb_batch* b, int steps, int* chosen, double* ms_p
     return refresh_moments(b);
 }
 
+vlb_status vlb_batch_set_persistent(vlb_batch* b, int max_blocks) {
+    if (!b || max_blocks < 0) return fail(VLB_EINVAL, "bad arguments");
+    b->persist_max = max_blocks;
+    return VLB_OK;
+}
+
 vlb_status vlb_batch_set_graphs(vlb_batch* b, int enable) {
     if (!b) return fail(VLB_EINVAL, "null batch");
     b->use_graphs = enable != 0;
@@ -1628,6 +1692,7 @@ vlb_status couette_noalloc_plan(int B, const vlb_couette_desc* descs, vlb_batch*
     st = layout_and_alloc(b, false, true);
     if (st != VLB_OK) { vlb_batch_destroy(b); *out = nullptr; return st; }
     b->use_graphs = false;
+    b->persist_max = 0;
     *bytes = b->total_bytes;
     return VLB_OK;
 }

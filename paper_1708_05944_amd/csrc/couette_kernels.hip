@@ -21,6 +21,7 @@
 // Diffuse walls (Sec. III.F, Eqs. weno_flux_eq, weno_populate, extrapol, nw): the
 // runs that reach a wall recompute n_w from the wall-bound WENO flux (a half-range sum
 // reduced across the run) and fill the ghost cells.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include "vlb_device.h"
@@ -128,12 +129,12 @@ struct StageLds {
 // dT follow from delta's moment sums and dg = du g_u + dT g_T from the per-node factors
 // of lin_prep (the variation of tau itself is left to the outer FP64 iteration).
 template <typename T, bool LIN>
-__global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
+__device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
     extern __shared__ double smem_d[];
     char* smem = reinterpret_cast<char*>(smem_d);
     const StageLds<T, LIN> lay(A.kmax);
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-    const BlockWork* bw = A.blocks + blockIdx.x;
+    const BlockWork* bw = A.blocks + blk;
     const int inst = __builtin_amdgcn_readfirstlane(bw->inst);
     const int dist = __builtin_amdgcn_readfirstlane(bw->dist);
     const int s0 = __builtin_amdgcn_readfirstlane(bw->s0);
@@ -494,6 +495,39 @@ __global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
     finish(TC - 1, (TC - 1) & 1);
 }
 
+template <typename T, bool LIN>
+__global__ __launch_bounds__(kStageThreads) void couette_stage(StageArgs A) {
+    stage_block<T, LIN>(A, blockIdx.x);
+}
+
+// nsteps whole RK3 steps in one cooperative launch, for block lists small enough to be
+// resident at once (where a step of three launches is bound by launch latency): every
+// block runs its stage, then the grid synchronises (with the device-scope fence that
+// makes the stage's output and moment sums visible to every XCD) before the next stage
+// reads them.  Each stage is the same per-block code as couette_stage, so the result is
+// bitwise that of 3 nsteps separate launches.  Every block takes the same 3 nsteps - 1
+// grid barriers, and the launch is cooperative: the runtime refuses a grid whose blocks
+// cannot all be resident.
+template <typename T, bool LIN>
+__global__ __launch_bounds__(kStageThreads) void couette_multi(MultiArgs M) {
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    const int n = 3 * M.nsteps;
+    for (int q = 0; q < n; ++q) {
+        const int stg = q % 3;
+        StageArgs A = M.base;
+        A.Fin = stg == 0 ? M.Fin[0] : (stg == 1 ? M.Fin[1] : M.Fin[2]);
+        A.Fout = stg == 0 ? M.Fout[0] : (stg == 1 ? M.Fout[1] : M.Fout[2]);
+        A.msum_in = stg == 0 ? M.msum_in[0] : (stg == 1 ? M.msum_in[1] : M.msum_in[2]);
+        A.msum_out = stg == 0 ? M.msum_out[0] : (stg == 1 ? M.msum_out[1] : M.msum_out[2]);
+        A.ca = stg == 0 ? M.ca[0] : (stg == 1 ? M.ca[1] : M.ca[2]);
+        A.cb = stg == 0 ? M.cb[0] : (stg == 1 ? M.cb[1] : M.cb[2]);
+        A.cc = stg == 0 ? M.cc[0] : (stg == 1 ? M.cc[1] : M.cc[2]);
+        A.rpart = q == n - 1 ? M.rpart_last : nullptr;
+        stage_block<T, LIN>(A, blockIdx.x);
+        if (q + 1 < n) grid.sync();
+    }
+}
+
 // Moment sums [n, sum p1 f', sum p2 f', sum |p|^2 f', sum f''] of a state, per cell
 // (FP64 accumulation; populations weighted by Wm, 1 for unscaled FP64 states); with a
 // mask, only the instances whose mask entry equals want.
@@ -818,6 +852,37 @@ static hipError_t launch_stage_t(int nblocks, hipStream_t st, const StageArgs& A
     const StageLds<T, LIN> lay(A.kmax);
     hipLaunchKernelGGL((couette_stage<T, LIN>), dim3(nblocks), dim3(kStageThreads), lay.total, st, A);
     return hipGetLastError();
+}
+
+template <typename T, bool LIN>
+static hipError_t launch_multi_t(int nblocks, hipStream_t st, const MultiArgs& M) {
+    const StageLds<T, LIN> lay(M.base.kmax);
+    MultiArgs arg = M;
+    void* args[] = {&arg};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&couette_multi<T, LIN>), dim3(nblocks),
+                                      dim3(kStageThreads), args, (unsigned)lay.total, st);
+}
+
+template <typename T, bool LIN>
+static int multi_capacity_t(int kmax) {
+    const StageLds<T, LIN> lay(kmax);
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&couette_multi<T, LIN>),
+                                                     kStageThreads, lay.total) != hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+hipError_t launch_multi(int fp32, int nblocks, hipStream_t st, const MultiArgs& M) {
+    if (fp32) return M.base.lin_cell ? launch_multi_t<float, true>(nblocks, st, M) : launch_multi_t<float, false>(nblocks, st, M);
+    return launch_multi_t<double, false>(nblocks, st, M);
+}
+
+int multi_capacity(int fp32, int lin, int kmax) {
+    if (fp32) return lin ? multi_capacity_t<float, true>(kmax) : multi_capacity_t<float, false>(kmax);
+    return multi_capacity_t<double, false>(kmax);
 }
 
 size_t stage_lds(int kmax, int elem) {

@@ -112,6 +112,21 @@ struct StageArgs {
     const float4* lin_node;
 };
 constexpr int kLinCell = 8;
+
+// Arguments of a multi-step launch: the fields the three stages of a step share, the
+// per-stage buffers and RK coefficients (stage q of a step reads Fin[q], msum_in[q] and
+// writes Fout[q], msum_out[q]; Fn is the step's input), and the residual partials of the
+// last step's third stage (nullable).
+struct MultiArgs {
+    StageArgs base;
+    const void* Fin[3];
+    void* Fout[3];
+    const double* msum_in[3];
+    double* msum_out[3];
+    double ca[3], cb[3], cc[3];
+    double* rpart_last;
+    int nsteps;
+};
 // modes of the FP64 <-> scaled FP32 conversion kernel
 constexpr int kConvTo32 = 0, kConvFrom32 = 1, kConvAdd = 2, kConvZero32 = 3;
 

@@ -143,6 +143,7 @@ _SIGS = {
     "vlb_axis_tables": [_Axis, _dp, _dp, _dp, _dp],
     "vlb_timing_enable": [ctypes.c_void_p, ctypes.c_int],
     "vlb_batch_set_graphs": [ctypes.c_void_p, ctypes.c_int],
+    "vlb_batch_set_persistent": [ctypes.c_void_p, ctypes.c_int],
     "vlb_batch_set_tile": [ctypes.c_void_p, ctypes.c_int],
     "vlb_batch_get_tile": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
     "vlb_batch_autotune": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _dp],
@@ -378,6 +379,10 @@ class Batch:
 
     def set_graphs(self, on: bool = True):
         _check(load_library().vlb_batch_set_graphs(self._h, 1 if on else 0), "vlb_batch_set_graphs")
+
+    def set_persistent(self, max_blocks: int = 64):
+        """Multi-step cooperative launches for block lists of at most max_blocks blocks (0: off)."""
+        _check(load_library().vlb_batch_set_persistent(self._h, max_blocks), "vlb_batch_set_persistent")
 
     def timing_enable(self, on: bool = True):
         _check(load_library().vlb_timing_enable(self._h, 1 if on else 0), "vlb_timing_enable")

@@ -188,6 +188,7 @@ def test_step_graph_replay_is_bitwise_identical():
         runs = []
         for graphs in (True, False):
             b = Batch([_pair(**dict(c))[1] for c in cases], precision=prec)
+            b.set_persistent(0)             # small batch: would take multi-step launches
             b.set_graphs(graphs)
             states = []
             for rep in range(3):
@@ -198,6 +199,72 @@ def test_step_graph_replay_is_bitwise_identical():
         for a, c in zip(runs[0][0], runs[1][0]):
             assert np.array_equal(a, c), prec
         assert np.array_equal(runs[0][1], runs[1][1])
+
+
+def test_multi_step_launch_is_bitwise_identical():
+    """Multi-step cooperative launches (grid barrier between stages) equal plain
+    launches bit for bit: an uneven small batch stepped in both precisions over several
+    calls, and the single-instance workload run to r < 1e-10 in FP64 and by the defect
+    correction (whose linearised FP32 steps also take them): same step counts, residuals
+    and states."""
+    from paper_1708_05944_amd import VLB_MIXED, Batch, workloads
+    cases = [L_CASES[0], L_CASES[5], L_CASES[6]]
+    for prec in (0, VLB_MIXED):
+        runs = []
+        for multi in (True, False):
+            b = Batch([_pair(**dict(c))[1] for c in cases], precision=prec)
+            if not multi:
+                b.set_persistent(0)
+                b.set_graphs(False)
+            states = []
+            for rep in range(3):
+                b.step(25 + rep)
+                states.append(b.get_state())
+            runs.append((states, b.residual()))
+            b.close()
+        for a, c in zip(runs[0][0], runs[1][0]):
+            assert np.array_equal(a, c), prec
+        assert np.array_equal(runs[0][1], runs[1][1])
+    for prec in (0, VLB_MIXED):
+        out = []
+        for multi in (True, False):
+            b = Batch([workloads.single_couette()], precision=prec)
+            if not multi:
+                b.set_persistent(0)
+            steps, r, ok = b.run_to_steady(1e-10, 40_000, 500)
+            out.append((steps, r, b.get_state()))
+            b.close()
+        _say(f"precision {prec}: steps {out[0][0]} / {out[1][0]}, r {out[0][1]} / {out[1][1]}")
+        assert out[0][0][0] > 0 and np.array_equal(out[0][0], out[1][0])
+        assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][2], out[1][2])
+
+
+def test_single_instance_step_time_is_stated():
+    """Time per RK3 step of the single-instance workload (64 cells, 32 velocities, FP64)
+    with multi-step launches against graph-replayed and plain launches (reported; the
+    multi-step launch must not be slower than the graph replay)."""
+    import time
+
+    import torch
+
+    from paper_1708_05944_amd import Batch, workloads
+    res = {}
+    for mode in ("multi", "graphs", "plain"):
+        b = Batch([workloads.single_couette()])
+        b.autotune(20)
+        if mode != "multi":
+            b.set_persistent(0)
+        if mode == "plain":
+            b.set_graphs(False)
+        b.step(200)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(4000)
+        torch.cuda.synchronize()
+        res[mode] = (time.perf_counter() - t0) / 4000 * 1e6
+        b.close()
+    _say("us per step: " + ", ".join(f"{k} {v:.1f}" for k, v in res.items()))
+    assert res["multi"] <= res["graphs"] * 1.05
 
 
 @pytest.mark.parametrize("tile", [2, 5, 32])
