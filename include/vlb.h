@@ -238,7 +238,8 @@ vlb_status vlb_batch_autotune(vlb_batch* b, int steps, int* chosen, double* ms_p
  * launches (bitwise the same results). */
 vlb_status vlb_batch_set_graphs(vlb_batch* b, int enable);
 
-/* Multi-step launches (on by default, max_blocks = 64).  While the stage kernel's block
+/* Multi-step launches (off by default; max_blocks = 64 is the intended setting).  While
+ * the stage kernel's block
  * list of the instances being stepped has at most max_blocks blocks (small batches, the
  * last instances of a run_to_steady) and the device can hold them all resident, a call
  * of two or more steps runs them in cooperative launches of up to 2000 whole RK3 steps
@@ -247,7 +248,10 @@ vlb_status vlb_batch_set_graphs(vlb_batch* b, int enable);
  * bitwise those of plain launches (the same per-block stage code).  Not used for
  * instances with large velocity sets, for the defect correction while it splits its
  * instances between FP64 and linearised FP32 steps, or while per-launch timing is on.
- * max_blocks = 0 turns it off. */
+ * max_blocks = 0 turns it off.  Measured on the single-instance workload (64 cells, 32
+ * velocities) it is no faster than graph replay: a step there is bound by the stage
+ * kernel's own latency (about 16 us per stage, in the per-cell equilibrium set-up and the
+ * cell sweep), not by launches. */
 vlb_status vlb_batch_set_persistent(vlb_batch* b, int max_blocks);
 
 /* Kernel timing for roofline reports.  When enabled, every launch of the stage kernel

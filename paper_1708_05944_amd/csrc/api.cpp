@@ -166,7 +166,7 @@ struct vlb_batch {
     // multi-step cooperative launches for block lists of at most persist_max blocks (0:
     // never), and the resident-block capacity of each stage-kernel flavour (FP64, FP32,
     // linearised FP32; -1 until queried)
-    int persist_max = 64;
+    int persist_max = 0;
     int multi_cap[3] = {-1, -1, -1};
     hipStream_t cap_stream = nullptr;   // private stream used only to capture step graphs
     hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};   // [FP64, FP32, linearised FP32]: kGraphSteps steps

@@ -246,6 +246,11 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
     const T* Fnd = static_cast<const T*>(A.Fn) + I.offF + (size_t)dist * NR * NV;
     T* Fo = static_cast<T*>(A.Fout) + I.offF + (size_t)dist * NR * NV;
     const T* Cd = A.C ? static_cast<const T*>(A.C) + I.offF + (size_t)dist * NR * NV : nullptr;
+    // the cell loop's streams as range-checked buffers over this distribution's block
+    const unsigned dbytes = (unsigned)((size_t)NR * NV * sizeof(T));
+    const __amdgpu_buffer_rsrc_t rF = buf_rsrc(Fd, dbytes), rFn = buf_rsrc(Fnd, dbytes), rO = buf_rsrc(Fo, dbytes),
+                                 rC = buf_rsrc(Cd, Cd ? dbytes : 0u);
+    auto eoff = [&](int c) { return (unsigned)(((size_t)c * NV + k) * sizeof(T)); };   // element (c, k)
     const double* Wm = tab + I.tWm;
     const T weps = T(I.weno_eps);
     const bool near_in = rlen > 0 && rs0 < 3, near_out = rlen > 0 && rs0 + rlen > NR - 3;
@@ -344,18 +349,19 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
         }
     };
 
-    // loads issued kAhead cells before their use (the window's leading cell and F_n); the
-    // ring shifts through registers, so the loop latch waits for the loads each cell
-    // issued at its start, and that cell's work is what covers their latency
+    // loads issued kAhead cells before their use (the window's leading cell and F_n): the
+    // cell loop is unrolled by kAhead, so slot p of the ring is read by the cells
+    // c = p (mod kAhead) and refilled by them for cell c + kAhead with no register moves,
+    // and a cell waits only for the loads issued kAhead cells earlier
     const bool need_fn = !A.l_only && ca != T(0);
     constexpr int kAhead = sizeof(T) == 4 ? 4 : 2;
     T pw[kAhead], fnr[kAhead], cr[LIN ? kAhead : 1];   // (the linearised stage also streams its forcing)
 #pragma unroll
     for (int q = 0; q < kAhead; ++q) {
         const int x = rs0 + 3 + q;
-        pw[q] = (act && q < rlen && x < NR) ? (Fd + (size_t)x * NV)[k] : T(0);
-        fnr[q] = (act && need_fn && q < rlen) ? (Fnd + (size_t)(rs0 + q) * NV)[k] : T(0);
-        if constexpr (LIN) cr[q] = (act && q < rlen) ? (Cd + (size_t)(rs0 + q) * NV)[k] : T(0);
+        pw[q] = buf_load<T>(rF, (act && q < rlen && x < NR) ? eoff(x) : kBufNone);
+        fnr[q] = buf_load<T>(rFn, (act && need_fn && q < rlen) ? eoff(rs0 + q) : kBufNone);
+        if constexpr (LIN) cr[q] = buf_load<T>(rC, (act && q < rlen) ? eoff(rs0 + q) : kBufNone);
     }
 
     // the run's first wavefront also finishes the previous cell's sums and its last one
@@ -368,28 +374,36 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
     // loads: stores count against the same wait as loads, and the loop latch waits for
     // the ring (a store issued late in the cell would be waited for there)
     T out_prev = T(0);
-    T* st_prev = nullptr;
+    unsigned st_off = kBufNone;
     // linearised stage: the node factors of the run's first cell (loaded a cell ahead)
-    float4 lin_t4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (LIN && coff >= 0) lin_t4 = A.lin_node[(size_t)I.offG + (size_t)rs0 * (Q1 + Q2) + kg];
-    __builtin_amdgcn_s_waitcnt(0x0F70);   // the ring's first loads
-    for (int c = 0; c < TC; ++c) {
+    typedef float f3v __attribute__((ext_vector_type(3)));   // (g, dg/du, dg/dT) of a node entry
+    f3v lin_t4 = {0.f, 0.f, 0.f};
+    // (the node-table offset made wavefront-uniform, so the resource stays in scalar registers)
+    const long long offG = ((long long)__builtin_amdgcn_readfirstlane((int)(I.offG >> 32)) << 32) |
+                           (unsigned)__builtin_amdgcn_readfirstlane((int)I.offG);
+    const __amdgpu_buffer_rsrc_t rG =
+        buf_rsrc(LIN ? A.lin_node + offG : nullptr, LIN ? (unsigned)((size_t)NR * (Q1 + Q2) * sizeof(float4)) : 0u);
+    if constexpr (LIN) {
+        const unsigned o = coff >= 0 ? (unsigned)(((size_t)rs0 * (Q1 + Q2) + kg) * sizeof(float4)) : kBufNone;
+        lin_t4 = __builtin_bit_cast(f3v, __builtin_amdgcn_raw_buffer_load_b96(rG, o, 0, 0));
+    }
+#pragma unroll 1
+    for (int c0 = 0; c0 < TC; c0 += kAhead) {
+#pragma unroll
+    for (int p = 0; p < kAhead; ++p) {
+        const int c = c0 + p;
+        if (c >= TC) break;
         const int buf = c & 1;
         const bool cv = act && c < rlen;
         const int s = rs0 + c;
-        const T fn_cur = fnr[0];
-        const T c_cur = cr[0];
-        const T lead = pw[0];
-        // this cell's prefetch loads; the ring shifts at the end of the cell, so their first
-        // use (and the wait for them) is at the loop latch
-        T pw_new = T(0), fn_new = T(0), c_new = T(0);
-        if (cv) {
-            const int x = s + 3 + kAhead;
-            if (c + kAhead < rlen && x < NR) pw_new = (Fd + (size_t)x * NV)[k];
-            if (need_fn && c + kAhead < rlen) fn_new = (Fnd + (size_t)(s + kAhead) * NV)[k];
-            if (LIN && c + kAhead < rlen) c_new = (Cd + (size_t)(s + kAhead) * NV)[k];
-        }
-        if (st_prev) { *st_prev = out_prev; st_prev = nullptr; }
+        const T fn_cur = fnr[p];
+        const T c_cur = cr[LIN ? p : 0];
+        const T lead = pw[p];
+        // this cell's prefetch loads refill the slots it read, each right after the slot's
+        // last use, so the load can take the slot's own register
+        const bool ahead = cv && c + kAhead < rlen;
+        buf_store(rO, st_off, out_prev);
+        st_off = kBufNone;
         T* row = rows + (size_t)buf * kRowElems + (size_t)r * 2 * S;
         T* rowT = row + S;
         T* gb = gbuf + (size_t)buf * kMaxRuns * kWave + (size_t)r * kWave;
@@ -402,10 +416,10 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
             row[vi * P2 + vj] = w2v;
             rowT[vj * P1 + vi] = w2v;
         }
+        pw[p] = buf_load<T>(rF, (ahead && s + 3 + kAhead < NR) ? eoff(s + 3 + kAhead) : kBufNone);
         if (coff >= 0 && c < rlen) {
             if constexpr (LIN) {
-                const float4 t4 = lin_t4;
-                if (c + 1 < rlen) lin_t4 = A.lin_node[(size_t)I.offG + (size_t)(s + 1) * (Q1 + Q2) + kg];
+                const f3v t4 = lin_t4;
                 const double du = kg < Q1 ? e[5] : e[6];
                 gb[kg] = T(t4.x);
                 gd[kg] = T(du * (double)t4.y + e[4] * (double)t4.z);
@@ -414,6 +428,11 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
                 for (int l = 0; l < nb; ++l) g += brow[l] * e[coff + l];
                 gb[kg] = T(g);
             }
+        }
+        if constexpr (LIN) {   // the next cell's node factors (issued by every lane)
+            const unsigned o = (coff >= 0 && c + 1 < rlen)
+                                   ? (unsigned)(((size_t)(s + 1) * (Q1 + Q2) + kg) * sizeof(float4)) : kBufNone;
+            lin_t4 = __builtin_bit_cast(f3v, __builtin_amdgcn_raw_buffer_load_b96(rG, o, 0, 0));
         }
         __syncthreads();
         if (c > 0) finish(c - 1, buf ^ 1);
@@ -442,7 +461,6 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
             const T Fc = w2v;
             T L = -adv - force - (Fc - fe) * T(e[2]);
             if constexpr (LIN) L += c_cur;
-            else if (Cd) L += Cd[(size_t)s * NV + k];
             T out;
             if (A.l_only) {
                 out = L;
@@ -456,7 +474,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
                 }
             }
             out_prev = out;
-            st_prev = Fo + (size_t)s * NV + k;
+            st_off = eoff(s);
             const double wo = wmk * (double)out;
             m0 = wo;
             if (dist == 0) {
@@ -466,6 +484,8 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
             }
             fl = fr;
         }
+        fnr[p] = buf_load<T>(rFn, (ahead && need_fn) ? eoff(s + kAhead) : kBufNone);
+        if constexpr (LIN) cr[p] = buf_load<T>(rC, ahead ? eoff(s + kAhead) : kBufNone);
         // row totals; lanes 0, 16, 32, 48 store them, the finishing lanes add the rows
         m0 = row_sum(m0);
         if (dist == 0) { m1 = row_sum(m1); m2 = row_sum(m2); m3 = row_sum(m3); }
@@ -474,23 +494,9 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
             double* mp = mpart + ((size_t)buf * (kStageThreads / kWave) + wave) * 32 + (lane >> 4);
             mp[0] = m0; mp[4] = m1; mp[8] = m2; mp[12] = m3; mp[16] = rd; mp[20] = rn;
         }
-        // the prefetch loads this cell issued are waited for here, after the cell's work,
-        // where the ring shifts (left to itself, the compiler waits for every outstanding
-        // load at the top of the next cell, right behind the loads issued there)
-        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
-        if (cv) {
-#pragma unroll
-            for (int q = 0; q < kAhead - 1; ++q) { pw[q] = pw[q + 1]; fnr[q] = fnr[q + 1]; }
-            pw[kAhead - 1] = pw_new;
-            fnr[kAhead - 1] = fn_new;
-            if constexpr (LIN) {
-#pragma unroll
-                for (int q = 0; q < kAhead - 1; ++q) cr[q] = cr[q + 1];
-                cr[kAhead - 1] = c_new;
-            }
-        }
     }
-    if (st_prev) *st_prev = out_prev;
+    }
+    buf_store(rO, st_off, out_prev);
     __syncthreads();
     finish(TC - 1, (TC - 1) & 1);
 }

@@ -52,6 +52,33 @@ __device__ __forceinline__ double row_sum(double v) {
 // wider); in FP64 the hardware estimate refined by two Newton steps r <- r + r (1 - x r)
 // (each squares the relative error; the result is within an ulp or so of 1/x, for the
 // normal, positive arguments the WENO weights take; x = 0 gives NaN, like 0 * (1/0)).
+// Raw buffer access (range-checked by the resource): an offset at or beyond the resource's
+// byte count reads 0 and drops the write, so loads and stores of lanes with nothing to
+// move are still issued, and every wavefront issues the same memory instructions in the
+// same order (the compiler then waits for a load by its position in that order, not for
+// every outstanding access).
+constexpr unsigned kBufNone = 0x80000000u;   // an offset outside every resource
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, double v) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, off, 0, 0);
+}
+
 template <typename T>
 __device__ __forceinline__ T recip(T x);
 template <>
