@@ -199,6 +199,9 @@ vlb_status vlb_total_mass(vlb_batch* b, double* Ntot);
  * default 10000 steps) is restarted from the cold rest state and continues as a cold
  * start (vlb_batch_warm_report). */
 vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check_every, long* steps, double* r);
+/* Wall-clock seconds of the last vlb_run_to_steady call on b (host clock around the whole
+ * call, which synchronises at every check, so the device work is inside it); 0 before any. */
+vlb_status vlb_batch_last_run_seconds(const vlb_batch* b, double* seconds);
 vlb_status vlb_mixed_fp32_steps(const vlb_batch* b, long* n);
 /* State of the defect correction per instance (host arrays of B, any may be NULL, not
  * all): the relaxation factor theta of its next update F += theta * delta (1: the full
@@ -419,6 +422,28 @@ typedef struct vlb_channel vlb_channel;
 vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* descs, int precision,
                               void* hip_stream);
 vlb_status vlb_channel_destroy(vlb_channel* c);
+/* Channel batch in caller-supplied device memory: vlb_channel_create_deferred builds the
+ * host side only (no device allocation, no HIP call); vlb_channel_workspace_bytes gives
+ * the bytes it needs; vlb_channel_bind_workspace takes a 256-byte aligned device buffer
+ * of at least that size (e.g. a torch tensor's storage; the caller keeps ownership and
+ * must keep it alive until vlb_channel_destroy), uploads the tables and writes the rest
+ * state (synchronises).  Until a workspace is bound, every call that touches the device
+ * returns VLB_ESTATE.  vlb_channel_create is the same with a library-owned allocation. */
+vlb_status vlb_channel_create_deferred(vlb_channel** out, int B, const vlb_channel_desc* descs, int precision,
+                                       void* hip_stream);
+vlb_status vlb_channel_workspace_bytes(const vlb_channel* c, size_t* bytes);
+vlb_status vlb_channel_bind_workspace(vlb_channel* c, void* dev_ptr, size_t bytes);
+/* Reservoir end of instance inst (ends = 0 only; end 0 = inlet xi_in, 1 = outlet xi_out):
+ * the incoming populations there become the Maxwellian at rest with density n and
+ * temperature T (Sec. VI.C reservoirs; the descriptor's n_in / n_out and T_w at
+ * creation).  Takes effect at the next step.  Errors: VLB_EINVAL (bad arguments or an
+ * instance with flow-rate ends). */
+vlb_status vlb_channel_set_open_bc(vlb_channel* c, int inst, int end, double n, double T);
+/* Total particle number sum dchi dlambda n of every instance (host array of B; the per-cell
+ * contents come from the device, summed on the host in cell order).  Synchronises. */
+vlb_status vlb_channel_total_mass(vlb_channel* c, double* Ntot);
+/* Wall-clock seconds of the last vlb_channel_run_to_steady call. */
+vlb_status vlb_channel_last_run_seconds(const vlb_channel* c, double* seconds);
 vlb_status vlb_channel_info(const vlb_channel* c, int inst, int* N_lambda, int* N_xi, int* NV, double* dt,
                             size_t* state_offset);
 vlb_status vlb_channel_state_size(const vlb_channel* c, size_t* n_doubles);

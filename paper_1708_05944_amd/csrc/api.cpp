@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -167,6 +168,7 @@ struct vlb_batch {
     // never), and the resident-block capacity of each stage-kernel flavour (FP64, FP32,
     // linearised FP32; -1 until queried)
     int persist_max = 0;
+    double run_seconds = 0.0;           // wall clock of the last vlb_run_to_steady
     int multi_cap[3] = {-1, -1, -1};
     hipStream_t cap_stream = nullptr;   // private stream used only to capture step graphs
     hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};   // [FP64, FP32, linearised FP32]: kGraphSteps steps
@@ -1190,7 +1192,24 @@ vlb_status vlb_total_mass(vlb_batch* b, double* Ntot) {
     return VLB_OK;
 }
 
+static vlb_status run_to_steady_impl(vlb_batch* b, double tol, long max_steps, int check_every, long* steps,
+                                     double* r);
+
 vlb_status vlb_run_to_steady(vlb_batch* b, double tol, long max_steps, int check_every, long* steps, double* r) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const vlb_status s = run_to_steady_impl(b, tol, max_steps, check_every, steps, r);
+    if (b) b->run_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return s;
+}
+
+vlb_status vlb_batch_last_run_seconds(const vlb_batch* b, double* seconds) {
+    if (!b || !seconds) return fail(VLB_EINVAL, "null argument");
+    *seconds = b->run_seconds;
+    return VLB_OK;
+}
+
+static vlb_status run_to_steady_impl(vlb_batch* b, double tol, long max_steps, int check_every, long* steps,
+                                     double* r) {
     if (!b || !(tol > 0) || max_steps < 1 || check_every < 1) return fail(VLB_EINVAL, "bad arguments");
     if (!b->ws) return fail(VLB_ESTATE, "no workspace bound");
     std::vector<long> conv(b->B, -1);

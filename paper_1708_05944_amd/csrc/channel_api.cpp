@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <map>
 #include <new>
@@ -51,6 +52,8 @@ struct vlb_channel {
         off_sbase, off_fld, total;
     size_t fld_n = 0;               // doubles of the largest instance's flow diagnostics
     bool have_resid = false;
+    bool owns = false;              // ws allocated by the library (else bound by the caller)
+    double run_seconds = 0.0;       // wall clock of the last vlb_channel_run_to_steady
 
     double* F(int i) { return (double*)(ws + off_F[i]); }
     float* F32(int i) { return (float*)(ws + off_F32[i]); }
@@ -108,8 +111,43 @@ vlb_status channel_precision(vlb_channel* c, bool want32) {
 
 extern "C" {
 
+namespace {
+vlb_status channel_device_setup(vlb_channel* c);
+vlb_status channel_build(vlb_channel** out, int B, const vlb_channel_desc* descs, int precision, void* hip_stream,
+                         bool alloc);
+}  // namespace
+
 vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* descs, int precision,
                               void* hip_stream) {
+    return channel_build(out, B, descs, precision, hip_stream, true);
+}
+
+vlb_status vlb_channel_create_deferred(vlb_channel** out, int B, const vlb_channel_desc* descs, int precision,
+                                       void* hip_stream) {
+    return channel_build(out, B, descs, precision, hip_stream, false);
+}
+
+vlb_status vlb_channel_workspace_bytes(const vlb_channel* c, size_t* bytes) {
+    if (!c || !bytes) return set_error(VLB_EINVAL, "null argument");
+    *bytes = c->total;
+    return VLB_OK;
+}
+
+vlb_status vlb_channel_bind_workspace(vlb_channel* c, void* dev_ptr, size_t bytes) {
+    if (!c || !dev_ptr) return set_error(VLB_EINVAL, "null argument");
+    if (c->ws) return set_error(VLB_ESTATE, "a workspace is already bound");
+    if (bytes < c->total) return set_error(VLB_ENOMEM, "workspace of %zu bytes, need %zu", bytes, c->total);
+    if ((uintptr_t)dev_ptr & 255) return set_error(VLB_EINVAL, "workspace must be 256-byte aligned");
+    c->ws = (char*)dev_ptr;
+    c->owns = false;
+    vlb_status s = channel_device_setup(c);
+    if (s != VLB_OK) c->ws = nullptr;
+    return s;
+}
+
+namespace {
+vlb_status channel_build(vlb_channel** out, int B, const vlb_channel_desc* descs, int precision, void* hip_stream,
+                         bool alloc) {
     if (!out || B < 1 || !descs) return set_error(VLB_EINVAL, "need out, B >= 1 and descriptors");
     *out = nullptr;
     if (precision != VLB_FP64 && precision != VLB_MIXED) return set_error(VLB_EINVAL, "unsupported precision %d", precision);
@@ -465,12 +503,30 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
         c->off_pop_base[fm] = off; off = al256(off + c->pop_base[fm].size() * sizeof(long long));
     }
     c->total = off;
-    void* p = nullptr;
-    if (hipMalloc(&p, c->total) != hipSuccess) {
-        delete c;
-        return set_error(VLB_ENOMEM, "hipMalloc(%zu) failed", c->total);
+    if (alloc) {
+        void* p = nullptr;
+        if (hipMalloc(&p, c->total) != hipSuccess) {
+            delete c;
+            return set_error(VLB_ENOMEM, "hipMalloc(%zu) failed", c->total);
+        }
+        c->ws = (char*)p;
+        c->owns = true;
+        vlb_status s = channel_device_setup(c);
+        if (s != VLB_OK) {
+            (void)hipFree(c->ws);
+            delete c;
+            return s;
+        }
     }
-    c->ws = (char*)p;
+    *out = c;
+    return VLB_OK;
+}
+
+// Tables, descriptors and launch lists into the workspace, and the rest state n = 1,
+// u = 0, T = T_w written on the device.  Synchronises.
+vlb_status channel_device_setup(vlb_channel* c) {
+    const int B = c->B;
+    const int precision = c->precision;
     hipError_t e = hipMemcpyAsync(c->dtab(), c->tab.data(), c->tab.size() * sizeof(double), hipMemcpyHostToDevice,
                                   c->stream);
     if (e == hipSuccess)
@@ -508,14 +564,10 @@ vlb_status vlb_channel_create(vlb_channel** out, int B, const vlb_channel_desc* 
     if (e == hipSuccess)
         e = launch_channel_rest((long long)c->state_n, c->stream, c->ddesc(), c->dsbase(), B, c->dtab(), c->F(0));
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) {
-        (void)hipFree(c->ws);
-        delete c;
-        return set_error(VLB_EDEVICE, "channel set-up failed: %s", hipGetErrorString(e));
-    }
-    *out = c;
+    if (e != hipSuccess) return set_error(VLB_EDEVICE, "channel set-up failed: %s", hipGetErrorString(e));
     return VLB_OK;
 }
+}  // namespace
 
 vlb_status vlb_channel_destroy(vlb_channel* c) {
     if (!c) return VLB_OK;
@@ -523,7 +575,7 @@ vlb_status vlb_channel_destroy(vlb_channel* c) {
     for (hipGraphExec_t& g : c->graph)
         if (g) (void)hipGraphExecDestroy(g);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    if (c->ws) (void)hipFree(c->ws);
+    if (c->ws && c->owns) (void)hipFree(c->ws);
     delete c;
     return VLB_OK;
 }
@@ -553,6 +605,7 @@ vlb_status vlb_channel_state_size(const vlb_channel* c, size_t* n) {
 }
 
 vlb_status vlb_channel_set_state(vlb_channel* c, const double* host, size_t n) {
+    if (c && !c->ws) return set_error(VLB_ESTATE, "no workspace bound");
     if (!c || !host || n != c->state_n) return set_error(VLB_EINVAL, "state size mismatch");
     for (size_t x = 0; x < n; ++x)
         if (!std::isfinite(host[x])) return set_error(VLB_ENONFINITE, "non-finite value at element %zu", x);
@@ -565,6 +618,7 @@ vlb_status vlb_channel_set_state(vlb_channel* c, const double* host, size_t n) {
 }
 
 vlb_status vlb_channel_get_instance_state(vlb_channel* c, int inst, double* host, size_t n) {
+    if (c && !c->ws) return set_error(VLB_ESTATE, "no workspace bound");
     if (!c || inst < 0 || inst >= c->B || !host) return set_error(VLB_EINVAL, "bad instance");
     const ChanDesc& D = c->desc[inst];
     if (n != (size_t)2 * D.NX * D.NL * D.NV) return set_error(VLB_EINVAL, "instance state size mismatch");
@@ -576,6 +630,7 @@ vlb_status vlb_channel_get_instance_state(vlb_channel* c, int inst, double* host
 }
 
 vlb_status vlb_channel_set_instance_state(vlb_channel* c, int inst, const double* host, size_t n) {
+    if (c && !c->ws) return set_error(VLB_ESTATE, "no workspace bound");
     if (!c || inst < 0 || inst >= c->B || !host) return set_error(VLB_EINVAL, "bad instance");
     const ChanDesc& D = c->desc[inst];
     if (n != (size_t)2 * D.NX * D.NL * D.NV) return set_error(VLB_EINVAL, "instance state size mismatch");
@@ -591,6 +646,7 @@ vlb_status vlb_channel_set_instance_state(vlb_channel* c, int inst, const double
 }
 
 vlb_status vlb_channel_get_state(vlb_channel* c, double* host, size_t n) {
+    if (c && !c->ws) return set_error(VLB_ESTATE, "no workspace bound");
     if (!c || !host || n != c->state_n) return set_error(VLB_EINVAL, "state size mismatch");
     vlb_status s = channel_precision(c, false);
     if (s != VLB_OK) return s;
@@ -701,6 +757,7 @@ vlb_status channel_steps(vlb_channel* c, long nsteps) {
 extern "C" {
 
 vlb_status vlb_channel_step(vlb_channel* c, long nsteps) {
+    if (c && !c->ws) return set_error(VLB_ESTATE, "no workspace bound");
     if (!c || nsteps < 0) return set_error(VLB_EINVAL, "bad arguments");
     vlb_status s = channel_precision(c, c->precision == VLB_MIXED);
     if (s != VLB_OK) return s;
@@ -709,6 +766,7 @@ vlb_status vlb_channel_step(vlb_channel* c, long nsteps) {
 }
 
 vlb_status vlb_channel_step_fp64(vlb_channel* c, long nsteps) {
+    if (c && !c->ws) return set_error(VLB_ESTATE, "no workspace bound");
     if (!c || nsteps < 0) return set_error(VLB_EINVAL, "bad arguments");
     vlb_status s = channel_precision(c, false);
     if (s != VLB_OK) return s;
@@ -716,6 +774,7 @@ vlb_status vlb_channel_step_fp64(vlb_channel* c, long nsteps) {
 }
 
 vlb_status vlb_channel_apply_L(vlb_channel* c, double* L, size_t n) {
+    if (c && !c->ws) return set_error(VLB_ESTATE, "no workspace bound");
     if (!c || !L || n != c->state_n) return set_error(VLB_EINVAL, "state size mismatch");
     vlb_status s = channel_stage(c, 0, false, true);
     if (s != VLB_OK) return s;
@@ -734,6 +793,7 @@ vlb_status vlb_channel_fp32_steps(const vlb_channel* c, long* n) {
 }
 
 vlb_status vlb_channel_residual(vlb_channel* c, double* r) {
+    if (c && !c->ws) return set_error(VLB_ESTATE, "no workspace bound");
     if (!c || !r) return set_error(VLB_EINVAL, "null argument");
     if (!c->have_resid) return set_error(VLB_ESTATE, "no step has recorded a residual yet");
     VLB_HIP_TRY(hipMemcpyAsync(r, c->resid(), c->B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -745,6 +805,7 @@ vlb_status vlb_channel_residual(vlb_channel* c, double* r) {
 
 vlb_status vlb_channel_moments(vlb_channel* c, int inst, double* n, double* u1, double* u2, double* T,
                                double* content) {
+    if (c && !c->ws) return set_error(VLB_ESTATE, "no workspace bound");
     if (!c || inst < 0 || inst >= c->B) return set_error(VLB_EINVAL, "bad instance");
     vlb_status s = channel_precision(c, false);
     if (s != VLB_OK) return s;
@@ -765,6 +826,7 @@ vlb_status vlb_channel_moments(vlb_channel* c, int inst, double* n, double* u1, 
 
 vlb_status vlb_channel_flow_fields(vlb_channel* c, int inst, double* ux, double* uy, double* P, double* psi,
                                    double* omega, double* Pw) {
+    if (c && !c->ws) return set_error(VLB_ESTATE, "no workspace bound");
     if (!c || inst < 0 || inst >= c->B) return set_error(VLB_EINVAL, "bad instance");
     vlb_status s = channel_precision(c, false);
     if (s != VLB_OK) return s;
@@ -784,8 +846,85 @@ vlb_status vlb_channel_flow_fields(vlb_channel* c, int inst, double* ux, double*
     return VLB_OK;
 }
 
+vlb_status vlb_channel_set_open_bc(vlb_channel* c, int inst, int end, double n, double T) {
+    if (!c || inst < 0 || inst >= c->B || (end != 0 && end != 1) || !(n > 0) || !(T > 0) || !std::isfinite(n) ||
+        !std::isfinite(T))
+        return set_error(VLB_EINVAL, "bad arguments");
+    vlb_channel_desc& d = c->d[inst];
+    if (d.ends != 0) return set_error(VLB_EINVAL, "instance %d has flow-rate ends, not reservoirs", inst);
+    AxisTables a1, a2;
+    if (!build_axis(d.ax1.kind, d.ax1.Q, d.ax1.N, a1) || !build_axis(d.ax2.kind, d.ax2.Q, d.ax2.N, a2))
+        return set_error(VLB_EINVAL, "axis construction failed");
+    const int n1 = a1.nodes, n2 = a2.nodes, NV = n1 * n2;
+    std::vector<double> g1(n1), g2(n2), f(2 * NV), fs(2 * NV);
+    axis_equilibrium_host(a1, 0.0, T, g1.data());
+    axis_equilibrium_host(a2, 0.0, T, g2.data());
+    for (int a = 0; a < n1; ++a)
+        for (int b = 0; b < n2; ++b) {
+            const int k = a * n2 + b;
+            const double fw = g1[a] * g2[b];   // the same rounding as the tables built at creation
+            f[k] = n * fw;
+            f[NV + k] = n * (T * fw);
+            const double iw = 1.0 / (a1.w[a] * a2.w[b]);
+            fs[k] = f[k] * iw;
+            fs[NV + k] = f[NV + k] * iw;
+        }
+    const ChanDesc& D = c->desc[inst];
+    const size_t at = (size_t)D.offT + (end ? D.tfout : D.tfin);
+    std::copy(f.begin(), f.end(), c->tab.begin() + at);
+    if (c->ws)
+        VLB_HIP_TRY(hipMemcpyAsync(c->dtab() + at, f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice,
+                                   c->stream));
+    if (c->precision == VLB_MIXED) {
+        const ChanDesc& E = c->desc32[inst];
+        const size_t at32 = (size_t)E.offT + (end ? E.tfout : E.tfin);
+        std::copy(fs.begin(), fs.end(), c->tab.begin() + at32);
+        if (c->ws)
+            VLB_HIP_TRY(hipMemcpyAsync(c->dtab() + at32, fs.data(), fs.size() * sizeof(double), hipMemcpyHostToDevice,
+                                       c->stream));
+    }
+    if (c->ws) VLB_HIP_TRY(hipStreamSynchronize(c->stream));
+    (end ? d.n_out : d.n_in) = n;
+    c->have_resid = false;
+    return VLB_OK;
+}
+
+vlb_status vlb_channel_total_mass(vlb_channel* c, double* Ntot) {
+    if (!c || !Ntot) return set_error(VLB_EINVAL, "null argument");
+    if (!c->ws) return set_error(VLB_ESTATE, "no workspace bound");
+    for (int i = 0; i < c->B; ++i) {
+        const ChanDesc& D = c->desc[i];
+        std::vector<double> content((size_t)D.NX * D.NL);
+        vlb_status s = vlb_channel_moments(c, i, nullptr, nullptr, nullptr, nullptr, content.data());
+        if (s != VLB_OK) return s;
+        double acc = 0.0;
+        for (double x : content) acc += x;
+        Ntot[i] = acc;
+    }
+    return VLB_OK;
+}
+
+vlb_status vlb_channel_last_run_seconds(const vlb_channel* c, double* seconds) {
+    if (!c || !seconds) return set_error(VLB_EINVAL, "null argument");
+    *seconds = c->run_seconds;
+    return VLB_OK;
+}
+
+namespace {
+vlb_status channel_run(vlb_channel* c, double tol, long max_steps, int check_every, long* steps, double* r);
+}
+
 vlb_status vlb_channel_run_to_steady(vlb_channel* c, double tol, long max_steps, int check_every, long* steps,
                                      double* r) {
+    if (c && !c->ws) return set_error(VLB_ESTATE, "no workspace bound");
+    const auto t0 = std::chrono::steady_clock::now();
+    const vlb_status s = channel_run(c, tol, max_steps, check_every, steps, r);
+    if (c) c->run_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return s;
+}
+
+namespace {
+vlb_status channel_run(vlb_channel* c, double tol, long max_steps, int check_every, long* steps, double* r) {
     if (!c || !(tol > 0) || max_steps < 1 || check_every < 1) return set_error(VLB_EINVAL, "bad arguments");
     std::vector<long> conv(c->B, -1);
     std::vector<double> res(c->B, INFINITY);
@@ -835,5 +974,6 @@ vlb_status vlb_channel_run_to_steady(vlb_channel* c, double tol, long max_steps,
     if (r) std::copy(res.begin(), res.end(), r);
     return remaining ? set_error(VLB_ENOTCONV, "%d channel(s) above tol after %ld steps", remaining, done) : VLB_OK;
 }
+}  // namespace
 
 }  // extern "C"

@@ -166,6 +166,14 @@ _SIGS = {
     "vlb_channel_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(_ChannelDesc), ctypes.c_int,
                            ctypes.c_void_p],
     "vlb_channel_destroy": [ctypes.c_void_p],
+    "vlb_channel_create_deferred": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(_ChannelDesc),
+                                    ctypes.c_int, ctypes.c_void_p],
+    "vlb_channel_workspace_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "vlb_channel_bind_workspace": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t],
+    "vlb_channel_set_open_bc": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double],
+    "vlb_channel_total_mass": [ctypes.c_void_p, _dp],
+    "vlb_channel_last_run_seconds": [ctypes.c_void_p, _dp],
+    "vlb_batch_last_run_seconds": [ctypes.c_void_p, _dp],
     "vlb_channel_info": [ctypes.c_void_p, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 3
     + [_dp, ctypes.POINTER(ctypes.c_size_t)],
     "vlb_channel_state_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
@@ -319,6 +327,12 @@ class Batch:
         n = ctypes.c_long()
         _check(load_library().vlb_mixed_fp32_steps(self._h, ctypes.byref(n)), "vlb_mixed_fp32_steps")
         return n.value
+
+    def last_run_seconds(self) -> float:
+        """Wall-clock seconds of the last run_to_steady call."""
+        s = ctypes.c_double()
+        _check(load_library().vlb_batch_last_run_seconds(self._h, ctypes.byref(s)), "vlb_batch_last_run_seconds")
+        return s.value
 
     def mixed_report(self):
         """Per instance: (relaxation factor of the defect correction, step at which it left
@@ -566,9 +580,16 @@ class Channel:
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         self.precision = precision
-        _check(load_library().vlb_channel_create(ctypes.byref(h), self.B, arr, precision,
-                                                 ctypes.c_void_p(self.stream.cuda_stream)), "vlb_channel_create")
+        lib = load_library()
+        # device memory from torch's allocator, bound as the batch's workspace
+        _check(lib.vlb_channel_create_deferred(ctypes.byref(h), self.B, arr, precision,
+                                               ctypes.c_void_p(self.stream.cuda_stream)), "vlb_channel_create_deferred")
         self._h = h
+        nbytes = ctypes.c_size_t()
+        _check(lib.vlb_channel_workspace_bytes(h, ctypes.byref(nbytes)), "vlb_channel_workspace_bytes")
+        self._ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self._ws.data_ptr() + 255) & ~255
+        _check(lib.vlb_channel_bind_workspace(h, ctypes.c_void_p(aligned), nbytes.value), "vlb_channel_bind_workspace")
         n = ctypes.c_size_t()
         _check(load_library().vlb_channel_state_size(h, ctypes.byref(n)), "vlb_channel_state_size")
         self.state_size = n.value
@@ -616,6 +637,20 @@ class Channel:
         s = np.ascontiguousarray(F, dtype=np.float64).ravel()
         _check(load_library().vlb_channel_set_instance_state(self._h, b, _ptr(s), s.size),
                "vlb_channel_set_instance_state")
+
+    def set_open_bc(self, b: int, end: int, n: float, T: float):
+        """Reservoir at end 0 (inlet) or 1 (outlet) of instance b: rest Maxwellian (n, T)."""
+        _check(load_library().vlb_channel_set_open_bc(self._h, b, end, n, T), "vlb_channel_set_open_bc")
+
+    def total_mass(self) -> np.ndarray:
+        out = np.empty(self.B)
+        _check(load_library().vlb_channel_total_mass(self._h, _ptr(out)), "vlb_channel_total_mass")
+        return out
+
+    def last_run_seconds(self) -> float:
+        s = ctypes.c_double()
+        _check(load_library().vlb_channel_last_run_seconds(self._h, ctypes.byref(s)), "vlb_channel_last_run_seconds")
+        return s.value
 
     def step(self, nsteps: int = 1):
         _check(load_library().vlb_channel_step(self._h, nsteps), "vlb_channel_step")

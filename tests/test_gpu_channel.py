@@ -158,6 +158,45 @@ def test_channel_moments_and_content():
     c.close()
 
 
+def test_channel_total_mass_open_bc_and_run_seconds():
+    """vlb_channel_total_mass equals the oracle's particle number of the same state;
+    vlb_channel_set_open_bc on an instance created with equal reservoirs gives bitwise the
+    steps of an instance created with the new reservoir density, in both precisions
+    (and, with n = 1 at both ends again, the rest state is stationary again); the run to
+    steady state reports its wall-clock seconds.  The batch runs in a torch-allocated
+    workspace bound through vlb_channel_bind_workspace."""
+    from paper_1708_05944_amd import VLB_MIXED, Channel
+    o, d = _pair(N_lambda=10, N_xi=12, ax1=(1, 4, 3), ax2=(0, 6, 4), Kn=0.1, n_in=1.0, n_out=1.0)
+    for prec in (0, VLB_MIXED):
+        c = Channel([d], precision=prec)
+        F = _perturbed(o, 11)
+        c.set_state(F.ravel())
+        assert c.total_mass()[0] == pytest.approx(o.mass(F), rel=1e-13)
+        c.set_state(o.equilibrium(1.0, 0.0, 0.0, 1.0).ravel())
+        c.set_open_bc(0, 0, 1.15, 1.0)
+        c.set_open_bc(0, 1, 0.9, 1.0)
+        c.step(30)
+        a = c.get_state()
+        _, d2 = _pair(N_lambda=10, N_xi=12, ax1=(1, 4, 3), ax2=(0, 6, 4), Kn=0.1, n_in=1.15, n_out=0.9)
+        c2 = Channel([d2], precision=prec)
+        c2.set_state(o.equilibrium(1.0, 0.0, 0.0, 1.0).ravel())
+        c2.step(30)
+        assert np.array_equal(a, c2.get_state()), prec
+        c2.close()
+        c.set_open_bc(0, 0, 1.0, 1.0)
+        c.set_open_bc(0, 1, 1.0, 1.0)
+        c.set_state(o.equilibrium(1.0, 0.0, 0.0, 1.0).ravel())
+        c.step(5)
+        assert c.residual()[0] < 1e-10
+        c.close()
+    c = Channel([d])
+    c.set_open_bc(0, 0, 1.05, 1.0)
+    steps, r, ok = c.run_to_steady(1e-3, 20_000, 500)
+    _say(f"run to r < 1e-3: {steps[0]} steps in {c.last_run_seconds():.3f} s")
+    assert ok and c.last_run_seconds() > 0
+    c.close()
+
+
 # ---------------------------------------------------------------- mixed precision
 # FP32 stage kernel on populations scaled by 1/(w_i w_j), FP64 moment / wall-flux /
 # residual sums.  Operator bar: relative max-norm 2e-6 (about 30 ulp of float), against

@@ -231,6 +231,7 @@ def test_multi_step_launch_is_bitwise_identical():
             b = Batch([workloads.single_couette()], precision=prec)
             b.set_persistent(64 if multi else 0)
             steps, r, ok = b.run_to_steady(1e-10, 40_000, 500)
+            assert b.last_run_seconds() > 0
             out.append((steps, r, b.get_state()))
             b.close()
         _say(f"precision {prec}: steps {out[0][0]} / {out[1][0]}, r {out[0][1]} / {out[1][1]}")

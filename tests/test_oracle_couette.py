@@ -4,10 +4,13 @@ Each pin is fixed by the paper's analysis or by mathematics, not by the oracle i
 exact particle-number conservation (Sec. III.D), stationarity of the rest state
 (Sec. V.C.2, Eq. f_st), third-order time stepping (Sec. III.A), the rigid-rotation
 solution (Sec. V.C.3, Eqs. rigid_sol and rigid_density), the Navier-Stokes Couette
-profile (Sec. V.D, Eq. NS_U) and the steady-state invariants of Sec. V.B
-(Eqs. TRph and Q_def, and u^R = 0).
+velocity and temperature profiles (Sec. V.D, Eqs. NS_U and NS_T), the steady-state
+invariants of Sec. V.B (Eqs. TRph and Q_def, and u^R = 0), and the Butcher tableau of
+Table rk3 (tests/golden/rk3_butcher.txt) against the oracle's time step.
 """
 import math
+import os
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -89,6 +92,50 @@ def test_rk3_is_third_order_in_time():
     assert 6.0 < e[0] / e[1] < 10.5, e
 
 
+def _butcher(path=os.path.join(os.path.dirname(__file__), "golden", "rk3_butcher.txt")):
+    """(c, A, b) of tests/golden/rk3_butcher.txt (Table rk3), as exact fractions."""
+    rows = [ln.split("|") for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    c, A, b = [], [], None
+    for left, right in rows:
+        vals = [Fraction(x) for x in right.split()]
+        if left.strip() == "b":
+            b = vals
+        else:
+            c.append(Fraction(left.strip()))
+            A.append(vals)
+    return c, A, b
+
+
+def test_rk3_butcher_tableau_golden():
+    """One oracle RK3 step equals the Runge-Kutta step built from the golden Butcher
+    tableau of Table rk3 (stages k_i = L[F + dt sum_j a_ij k_j], F + dt sum b_i k_i) with the
+    oracle's operator L, to rounding; the tableau itself is consistent (rows of A sum to c,
+    b sums to 1, third-order conditions) and a perturbed weight is detected."""
+    c, A, b = _butcher()
+    assert [sum(r) for r in A] == c and sum(b) == 1
+    assert sum(bi * ci for bi, ci in zip(b, c)) == Fraction(1, 2)
+    assert sum(bi * ci * ci for bi, ci in zip(b, c)) == Fraction(1, 3)
+    assert sum(b[i] * A[i][j] * c[j] for i in range(3) for j in range(3)) == Fraction(1, 6)
+    o = CouetteOracle(N_R=12, u_in=0.3, T_in=1.1)
+    rng = np.random.default_rng(5)
+    F = o.equilibrium(1.0, 0.0, 0.05, 1.0) * (1 + 0.05 * rng.standard_normal((2, 12, o.NV)))
+    dt = o.cfl_dt(0.5)
+
+    def tableau_step(bw):
+        ks = []
+        for i in range(3):
+            Fi = F + dt * sum(float(A[i][j]) * ks[j] for j in range(i)) if i else F
+            ks.append(o.L(Fi)[0])
+        return F + dt * sum(float(bi) * k for bi, k in zip(bw, ks))
+
+    got = o.step(F, dt, 1)
+    want = tableau_step(b)
+    scale = np.abs(want - F).max()
+    assert np.abs(got - want).max() <= 1e-12 * scale + 1e-15 * np.abs(F).max()
+    wrong = tableau_step([b[0], b[1] + Fraction(1, 100), b[2] - Fraction(1, 100)])
+    assert np.abs(got - wrong).max() > 1e-6 * scale
+
+
 def _run_to(o, F, dt, tol, chunk=500, max_steps=100000):
     steps = 0
     r = math.inf
@@ -153,6 +200,60 @@ def test_navier_stokes_couette_profile():
         errs.append(np.abs(m["u2"] - u_ns).max() / (Om * Rin))
     assert errs[0] < 5 * 0.01 and errs[1] < 5 * 0.005, errs
     assert 1.6 < errs[0] / errs[1] < 2.6, errs
+
+
+def _ns_limit_runs(Om, Kns, NR=32, tol=1e-8):
+    """Steady states near the hydrodynamic limit (tau = Kn/(nT), Eq. hydro_tau, so mu = Kn
+    and kappa = 5 mu / 2 are constant, as Eqs. NS_U and NS_T assume), started from the
+    Navier-Stokes profiles; returns (R, [moments per Kn])."""
+    Rin, Rout = 1.0, 2.0
+    a = Rin ** -2 - Rout ** -2
+    out = []
+    for Kn in Kns:
+        o = CouetteOracle(N_R=NR, ax1=(0, 5, 4), ax2=(0, 5, 4), Kn=Kn, tau_model=TAU_HYDRO, u_in=Om * Rin)
+        R = o.Rc
+        F = o.equilibrium(1.0, 0.0, _u_ns(R, Om), _T_ns(R, Om))
+        F, steps, r = _run_to(o, F, min(o.cfl_dt(0.5), 2 * Kn), tol, chunk=999)
+        assert r < tol
+        out.append(o.moments(F))
+    return R, out
+
+
+def _u_ns(R, Om, Rin=1.0, Rout=2.0):
+    """Eq. NS_U."""
+    return R ** -1 * Om / (Rin ** -2 - Rout ** -2) - R * Om * Rin ** 2 / (Rout ** 2 - Rin ** 2)
+
+
+def _T_ns(R, Om, Rin=1.0, Rout=2.0, Tw=1.0, mu_over_kappa=0.4):
+    """Eq. NS_T, with mu / kappa = 2/5 (BGK: Prandtl number 1, c_p = 5/2 for m = 1)."""
+    a = Rin ** -2 - Rout ** -2
+    return Tw + mu_over_kappa * Om ** 2 / a * ((Rin ** -2 - R ** -2) / a - np.log(R / Rin) / np.log(Rout / Rin))
+
+
+@pytest.mark.slow
+def test_navier_stokes_temperature_profile():
+    """At Omega_in = 0.5 the viscous heating lifts T by ~2 % in the gap; near the
+    hydrodynamic limit the steady T - T_w approaches Eq. NS_T (constant mu and kappa =
+    5 mu/2), the deviation being the temperature jump and velocity slip at the walls,
+    first order in Kn (measured: 13 Kn of the peak rise at Kn = 0.01 and 0.005).  A dropped
+    energy term (the f'' channel, the heat flux, the viscous heating) would miss the rise
+    entirely.  Richardson extrapolation in Kn (2 X(Kn/2) - X(Kn)) removes the first-order
+    part: the extrapolated u^phi is within 1e-2 Omega_in R_in of Eq. NS_U (measured 8.7e-3:
+    the O(Kn^2) slip and the 32-cell discretisation) and the extrapolated T rise within 2 %
+    of Eq. NS_T's (measured 1.5 %)."""
+    Om = 0.5
+    R, (m1, m2) = _ns_limit_runs(Om, (0.01, 0.005))
+    dTn = _T_ns(R, Om) - 1.0
+    eT = [np.abs((m["T"] - 1.0) - dTn).max() / dTn.max() for m in (m1, m2)]
+    assert abs(dTn.max() - 0.0225) < 5e-4
+    assert eT[0] < 20 * 0.01 and eT[1] < 20 * 0.005, eT
+    assert 1.6 < eT[0] / eT[1] < 2.6, eT
+    u_x = 2 * m2["u2"] - m1["u2"]
+    T_x = 2 * m2["T"] - m1["T"]
+    eu_x = np.abs(u_x - _u_ns(R, Om)).max() / Om
+    eT_x = np.abs((T_x - 1.0) - dTn).max() / dTn.max()
+    assert eu_x < 1e-2, eu_x
+    assert eT_x < 2e-2, eT_x
 
 
 @pytest.mark.slow
