@@ -236,6 +236,7 @@ def main():
     ap.add_argument("--warm-train", type=int, default=4096, help="training instances of the warm-start leg")
     ap.add_argument("--warm-heldout", type=int, default=256, help="held-out instances of the warm-start leg")
     ap.add_argument("--warm-epochs", type=int, default=100, help="training epochs of the warm-start leg")
+    ap.add_argument("--no-channel-warm", action="store_true", help="skip the learned channel warm-start leg")
     ap.add_argument("--no-eps-free", action="store_true", help="skip the epsilon-free held-out runs of the warm leg")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="after the run, one plain device copy of this many MiB (reference kernel for "
@@ -438,6 +439,27 @@ def main():
                             f"epsilon-free WENO weights, warm-started by the same network")
         log("warm start done")
 
+    channel_warm = None
+    if not args.no_channel_warm:
+        # learned warm start of batched expanding channels: a reduced channel family (32 x 8
+        # cells, 64 velocities, Kn 0.04-0.25, r 1.5-3) whose members all reach r < 1e-10;
+        # surrogate trained on 32 channel steady states (seed 11), 16 held-out channels
+        # (seed 12) run cold and warm in FP64
+        from paper_1708_05944_amd import surrogate
+        log = lambda m: print(m, file=sys.stderr, flush=True)
+        tr = workloads.channel_surrogate_descs(32, workloads.CHANNEL_SURROGATE_TRAIN_SEED)
+        ho = workloads.channel_surrogate_descs(16, workloads.CHANNEL_SURROGATE_HELDOUT_SEED)
+        log("channel warm start: 32 training solves")
+        channel_warm = surrogate.channel_warm_comparison(tr, ho, epochs=300, max_steps=200_000, log=log)
+        channel_warm["workload"] = ("learned warm start of expanding channels: 32 training / 16 held-out channels "
+                                    "(seeds 11 / 12), 32 x 8 cells, HH(3;4) x H(4;8), Kn log-uniform 0.04-0.25 "
+                                    "(tau = Kn/(nT)), r uniform 1.5-3 over L = 4, reservoirs 1.1 / 0.9, weno_eps "
+                                    "1e-6; inputs (log Kn, r, xi, lambda); cold = rest state, warm = local "
+                                    "equilibrium of the surrogate's fields (bf16 inference) + stall watch (cold "
+                                    "restart after 40000 steps without a new residual low); FP64 to r < 1e-10; "
+                                    "non-converged instances count the whole 200000-step budget")
+        log("channel warm start done")
+
     out = {
         "metric": "site-velocity updates/s (batched Couette sweep, mixed precision: FP32 streaming)",
         "value": mixed["value"],
@@ -461,6 +483,7 @@ def main():
                  "roofline": roof64},
         "time_to_steady_state_single": tts,
         "time_to_steady_state_warm_start": warm,
+        "time_to_steady_state_channel_warm_start": channel_warm,
         "channel": channel,
         "ballistic": ballistic,
         "vlb_vs_clb": clb,

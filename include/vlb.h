@@ -453,6 +453,14 @@ vlb_status vlb_channel_get_state(vlb_channel* c, double* host, size_t n);
  * batch's FP32 state is converted first).  Synchronise. */
 vlb_status vlb_channel_get_instance_state(vlb_channel* c, int inst, double* host, size_t n);
 vlb_status vlb_channel_set_instance_state(vlb_channel* c, int inst, const double* host, size_t n);
+/* Instance inst set to the local equilibrium of per-cell fields (host arrays [N_xi][N_lambda]:
+ * density n > 0, velocity components u^lambda, u^xi in the cell's orthonormal triad, as
+ * vlb_channel_moments returns them, temperature T > 0): f' = n g1 g2, f'' = T f' with the
+ * equilibrium expansion of the stage kernels (Sec. IV.D, Eqs. feq_red, eq_gak_H,
+ * eq_gak_hh), computed on the device in FP64.  The learned warm start of a channel is
+ * this call on the surrogate's fields.  Vielbein instances only.  Synchronises. */
+vlb_status vlb_channel_init_equilibrium(vlb_channel* c, int inst, const double* n, const double* u1,
+                                        const double* u2, const double* T);
 /* nsteps RK3 steps in the batch's precision (FP32 for VLB_MIXED); the last records the
  * residual (same definition as for Couette, volumes dchi dlambda).  Enqueued on the
  * stream; does not synchronise. */

@@ -645,6 +645,32 @@ vlb_status vlb_channel_set_instance_state(vlb_channel* c, int inst, const double
     return VLB_OK;
 }
 
+vlb_status vlb_channel_init_equilibrium(vlb_channel* c, int inst, const double* n, const double* u1,
+                                        const double* u2, const double* T) {
+    if (c && !c->ws) return set_error(VLB_ESTATE, "no workspace bound");
+    if (!c || inst < 0 || inst >= c->B || !n || !u1 || !u2 || !T) return set_error(VLB_EINVAL, "bad arguments");
+    const ChanDesc& D = c->desc[inst];
+    if (D.cartesian) return set_error(VLB_EINVAL, "instance %d is Cartesian-split", inst);
+    const size_t nc = (size_t)D.NX * D.NL;
+    std::vector<double> prof(4 * nc);
+    const double* src[4] = {n, u1, u2, T};
+    for (int q = 0; q < 4; ++q)
+        for (size_t x = 0; x < nc; ++x) {
+            const double v = src[q][x];
+            if (!std::isfinite(v) || ((q == 0 || q == 3) && !(v > 0)))
+                return set_error(VLB_EINVAL, "field %d at cell %zu: n and T must be positive and finite", q, x);
+            prof[q * nc + x] = v;
+        }
+    vlb_status s = channel_precision(c, false);
+    if (s != VLB_OK) return s;
+    VLB_HIP_TRY(hipMemcpyAsync(c->fld(), prof.data(), prof.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    VLB_HIP_TRY(launch_channel_init_profile((long long)nc, c->stream, c->ddesc() + inst, c->dtab(), c->fld(), c->F(0)));
+    VLB_HIP_TRY(hipStreamSynchronize(c->stream));
+    c->have_resid = false;
+    c->polishing = false;
+    return VLB_OK;
+}
+
 vlb_status vlb_channel_get_state(vlb_channel* c, double* host, size_t n) {
     if (c && !c->ws) return set_error(VLB_ESTATE, "no workspace bound");
     if (!c || !host || n != c->state_n) return set_error(VLB_EINVAL, "state size mismatch");

@@ -60,6 +60,9 @@ hipError_t launch_channel_stage(int fp32, int T1, int T2, int bnd, long long nbl
                                 const ChanArgs& A);
 hipError_t launch_channel_rest(long long nelems, hipStream_t st, const ChanDesc* insts, const long long* sbase, int B,
                                const double* tab, double* F64);
+// local equilibrium of the instance *inst from prof = [4][NX][NL] (n, u^lambda, u^xi, T)
+hipError_t launch_channel_init_profile(long long ncells, hipStream_t st, const ChanDesc* inst, const double* tab,
+                                       const double* prof, double* F64);
 hipError_t launch_channel_convert(int to32, long long nelems, hipStream_t st, const ChanDesc* insts,
                                   const long long* sbase, int B, const double* tab, double* F64, float* F32);
 hipError_t launch_channel_reduce(int ninst, hipStream_t st, const ChanDesc* insts, const double* tab,

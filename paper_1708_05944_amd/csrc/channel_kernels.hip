@@ -969,6 +969,46 @@ static dim3 stride_grid(long long n, long long per_block) {
     return dim3((unsigned)std::max(1LL, std::min(want, 1LL << 20)));
 }
 
+// Local equilibrium of one instance from per-cell fields prof = [4][NX][NL] (n, u^lambda,
+// u^xi, T): f' = n g1(p_i) g2(p_j), f'' = T f' with the equilibrium expansion of the stage
+// kernel (Sec. IV.D, Eqs. feq_red, eq_gak_H, eq_gak_hh).  One wavefront per cell; every
+// lane computes the cell's axis coefficients (no divergence), then the lanes split the
+// velocities.
+__global__ __launch_bounds__(256) void channel_init_profile(const ChanDesc* inst, const double* tab_all,
+                                                            const double* prof, double* F64) {
+    const ChanDesc& I = *inst;
+    const long long nc = (long long)I.NX * I.NL;
+    const long long cell = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (cell >= nc) return;
+    const double* tab = tab_all + I.offT;
+    const int NV = I.NV, Q2 = I.Q2, N1 = I.N1, N2 = I.N2;
+    const double n = prof[cell], u1 = prof[nc + cell], u2 = prof[2 * nc + cell], T_ = prof[3 * nc + cell];
+    double c1[2 * (kMaxN + 1)], c2[2 * (kMaxN + 1)];
+    axis_coef(I.kind1, N1, u1, T_, tab + I.tC1, tab + I.tisf1, c1, c1 + (N1 + 1));
+    axis_coef(I.kind2, N2, u2, T_, tab + I.tC2, tab + I.tisf2, c2, c2 + (N2 + 1));
+    double* out = F64 + (size_t)I.offF + (size_t)cell * NV;
+    const size_t dsz = (size_t)nc * NV;
+    for (int k = lane; k < NV; k += 64) {
+        const int i = k / Q2, j = k - i * Q2;
+        const double* e1 = c1 + ((I.kind1 == 1 && i >= I.Qh1) ? N1 + 1 : 0);
+        const double* e2 = c2 + ((I.kind2 == 1 && j >= I.Qh2) ? N2 + 1 : 0);
+        double g1 = 0.0, g2 = 0.0;
+        for (int l = 0; l <= N1; ++l) g1 += tab[I.tB1 + i * (N1 + 1) + l] * e1[l];
+        for (int l = 0; l <= N2; ++l) g2 += tab[I.tB2 + j * (N2 + 1) + l] * e2[l];
+        const double v = n * g1 * g2;
+        out[k] = v;
+        out[dsz + k] = T_ * v;
+    }
+}
+
+hipError_t launch_channel_init_profile(long long ncells, hipStream_t st, const ChanDesc* inst, const double* tab,
+                                       const double* prof, double* F64) {
+    hipLaunchKernelGGL(channel_init_profile, dim3((unsigned)((ncells + 3) / 4)), dim3(256), 0, st, inst, tab, prof,
+                       F64);
+    return hipGetLastError();
+}
+
 hipError_t launch_channel_rest(long long nelems, hipStream_t st, const ChanDesc* insts, const long long* sbase, int B,
                                const double* tab, double* F64) {
     const dim3 grid = stride_grid(nelems, 256), block(256);

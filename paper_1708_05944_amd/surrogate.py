@@ -153,3 +153,139 @@ def train(X, T, epochs: int = 400, batch: int = 512, lr: float = 1e-3, width: in
     mlp = Mlp(workloads.mlp_init_params(width, depth, init_seed), width, depth)
     losses = [mlp.train(X, T, order, batch, lr) for order in workloads.epoch_orders(len(X), epochs, seed)]
     return mlp, np.array(losses)
+
+
+# ---------------------------------------------------------------- expanding channels
+# The same network (4 -> 128 -> 128 -> 128 -> 4, the library's MLP kernels) maps a channel
+# cell's (log10 Kn, r, xi, lambda), each mapped affinely to [-1, 1], to its steady
+# (n - 1, u^lambda, u^xi, T - 1) times CH_SCALE (outputs of order one).
+CH_SCALE = np.array([10.0, 5.0, 5.0, 50.0])
+
+
+def channel_features(desc, info) -> np.ndarray:
+    """Surrogate inputs of every cell of one channel ([N_xi * N_lambda][4] float32, xi-major
+    like the state): cell centres of the equal xi and lambda cells (full width, A = 0)."""
+    if desc.half or desc.A != 0:
+        raise ValueError("the channel surrogate covers full-width channels on equal cells")
+    NX, NL = info["N_xi"], info["N_lambda"]
+    xi = desc.xi_in + (np.arange(NX) + 0.5) * (desc.xi_out - desc.xi_in) / NX
+    lam = -1.0 + (np.arange(NL) + 0.5) * 2.0 / NL
+    X, L = np.meshgrid(xi, lam, indexing="ij")
+    lo, hi = np.log10(workloads.CHANNEL_SURROGATE_KN[0]), np.log10(workloads.CHANNEL_SURROGATE_KN[1])
+    rlo, rhi = workloads.CHANNEL_SURROGATE_R
+    cols = [np.full(X.shape, (np.log10(desc.Kn) - 0.5 * (lo + hi)) / (0.5 * (hi - lo))),
+            np.full(X.shape, (desc.r - 0.5 * (rlo + rhi)) / (0.5 * (rhi - rlo))),
+            (X - 0.5 * (desc.xi_in + desc.xi_out)) / (0.5 * (desc.xi_out - desc.xi_in)), L]
+    return np.stack([c.ravel() for c in cols], axis=-1).astype(np.float32)
+
+
+def channel_targets(m) -> np.ndarray:
+    return (np.stack([m["n"].ravel() - 1.0, m["u1"].ravel(), m["u2"].ravel(), m["T"].ravel() - 1.0], axis=-1)
+            * CH_SCALE).astype(np.float32)
+
+
+def channel_fields(Y, info):
+    """(n, u^lambda, u^xi, T) per cell ([N_xi][N_lambda] each) from surrogate outputs."""
+    Y = np.asarray(Y, dtype=np.float64) / CH_SCALE
+    shp = (info["N_xi"], info["N_lambda"])
+    return (1.0 + Y[:, 0]).reshape(shp), Y[:, 1].reshape(shp), Y[:, 2].reshape(shp), (1.0 + Y[:, 3]).reshape(shp)
+
+
+def channel_run(c, tol, max_steps, chunk=10_000, check_every=1000, stall_window=None, warm=None, log=None,
+                patience=None):
+    """Run a channel batch (FP64) to r < tol in chunks; returns (steps at convergence per
+    instance or -1, last residuals, cold restarts per instance (step or -1)).  With
+    stall_window, an instance started warm whose residual sets no new low (by 1 %) for
+    stall_window steps is restarted from the rest state (the plain solver's residual is
+    the judge, the cold start the fallback).  With patience, the run also stops once no
+    instance has converged for that many steps (for training solves, where the instances
+    that do converge are what is wanted)."""
+    B = c.B
+    conv = np.full(B, -1, dtype=np.int64)
+    fell = np.full(B, -1, dtype=np.int64)
+    best = np.full(B, np.inf)
+    best_at = np.zeros(B, dtype=np.int64)
+    warm = np.zeros(B, bool) if warm is None else np.asarray(warm, bool).copy()
+    done, r, last_new = 0, None, 0
+    while done < max_steps and (conv < 0).any():
+        n = min(chunk, max_steps - done)
+        steps, r, ok = c.run_to_steady(tol, n, check_every)
+        new = (conv < 0) & (steps >= 0)
+        conv[new] = done + steps[new]
+        done += n
+        if new.any():
+            last_new = done
+        if patience and (conv >= 0).any() and done - last_new >= patience:
+            break
+        for b in np.flatnonzero((conv < 0) & warm):
+            if r[b] < 0.99 * best[b]:
+                best[b], best_at[b] = r[b], done
+            elif stall_window and done - best_at[b] >= stall_window:
+                d = c.descs[b]
+                c.init_equilibrium(b, 1.0, 0.0, 0.0, d.T_w)
+                warm[b] = False
+                fell[b] = done
+        if log:
+            log(f"  {done} steps: {int((conv >= 0).sum())}/{B} below {tol:g}, largest residual {r.max():.2e}")
+    return conv, r, fell
+
+
+def channel_steady_samples(descs, tol=1e-10, max_steps=400_000, log=None):
+    """Steady states of a channel batch (FP64, from rest) and the surrogate samples of the
+    cells of the instances that converged."""
+    from .vlb import Channel
+    c = Channel(descs)
+    t0 = time.perf_counter()
+    conv, r, _ = channel_run(c, tol, max_steps, log=log, patience=30_000)
+    secs = time.perf_counter() - t0
+    X, Y = [], []
+    for b in np.flatnonzero(conv >= 0):
+        X.append(channel_features(descs[b], c.info[b]))
+        Y.append(channel_targets(c.moments(b)))
+    c.close()
+    return (np.concatenate(X), np.concatenate(Y),
+            dict(seconds=secs, converged=int((conv >= 0).sum()), instances=len(descs), max_steps=int(conv.max())))
+
+
+def channel_warm_start(c, mlp, bf16: bool = True):
+    """Set every instance of a channel batch to the local equilibrium of the surrogate's
+    fields (network inference on the device, the state built on the device)."""
+    for b in range(c.B):
+        Y = mlp.forward(channel_features(c.descs[b], c.info[b]), bf16=bf16)
+        c.init_equilibrium(b, *channel_fields(Y, c.info[b]))
+
+
+def channel_warm_comparison(train_descs, heldout_descs, epochs: int = 300, batch: int = 256, lr: float = 1e-3,
+                            max_steps: int = 200_000, stall_window: int = 40_000, log=None):
+    """The learned channel warm start end to end: steady states of the training channels ->
+    samples -> trained network -> held-out channels run to r < 1e-10 from rest and from the
+    surrogate (FP64), with honest totals (an instance that did not converge counts
+    max_steps steps and the leg's whole wall time)."""
+    import torch
+    from .vlb import Channel
+    X, Y, st = channel_steady_samples(train_descs, max_steps=max_steps, log=log)
+    t0 = time.perf_counter()
+    mlp, losses = train(X, Y, epochs=epochs, batch=batch, lr=lr)
+    t_train = time.perf_counter() - t0
+    out = dict(training_solves=st, samples=int(len(X)), train_seconds=t_train, epochs=epochs,
+               final_loss=float(losses[-1]), heldout=len(heldout_descs), max_steps=max_steps,
+               stall_window=stall_window)
+    for name, warm in (("cold_fp64", False), ("warm_fp64", True)):
+        c = Channel(heldout_descs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if warm:
+            channel_warm_start(c, mlp)
+        conv, r, fell = channel_run(c, 1e-10, max_steps, stall_window=stall_window if warm else None,
+                                    warm=np.full(c.B, warm), log=log)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        st_ = np.where(conv >= 0, conv, max_steps)
+        out[name] = dict(converged=int((conv >= 0).sum()), instances=c.B, steps_total=int(st_.sum()),
+                         seconds=secs, cold_restarts=int((fell >= 0).sum()),
+                         per_instance_steps=[int(x) for x in conv])
+        c.close()
+    out["speedup_warm_fp64_vs_cold_fp64"] = out["cold_fp64"]["seconds"] / out["warm_fp64"]["seconds"]
+    out["step_ratio_warm_fp64_vs_cold_fp64"] = out["cold_fp64"]["steps_total"] / out["warm_fp64"]["steps_total"]
+    mlp.close()
+    return out

@@ -171,6 +171,7 @@ _SIGS = {
     "vlb_channel_workspace_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
     "vlb_channel_bind_workspace": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t],
     "vlb_channel_set_open_bc": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double],
+    "vlb_channel_init_equilibrium": [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp, _dp],
     "vlb_channel_total_mass": [ctypes.c_void_p, _dp],
     "vlb_channel_last_run_seconds": [ctypes.c_void_p, _dp],
     "vlb_batch_last_run_seconds": [ctypes.c_void_p, _dp],
@@ -637,6 +638,14 @@ class Channel:
         s = np.ascontiguousarray(F, dtype=np.float64).ravel()
         _check(load_library().vlb_channel_set_instance_state(self._h, b, _ptr(s), s.size),
                "vlb_channel_set_instance_state")
+
+    def init_equilibrium(self, b: int, n, u1, u2, T):
+        """Instance b set to the local equilibrium of per-cell fields ([N_xi][N_lambda] each)."""
+        i = self.info[b]
+        shp = (i["N_xi"], i["N_lambda"])
+        a = [np.ascontiguousarray(np.broadcast_to(np.asarray(x, dtype=np.float64), shp)) for x in (n, u1, u2, T)]
+        _check(load_library().vlb_channel_init_equilibrium(self._h, b, *[_ptr(x) for x in a]),
+               "vlb_channel_init_equilibrium")
 
     def set_open_bc(self, b: int, end: int, n: float, T: float):
         """Reservoir at end 0 (inlet) or 1 (outlet) of instance b: rest Maxwellian (n, T)."""

@@ -129,3 +129,23 @@ def channel_sweep(B: int = 64, seed: int = CHANNEL_SWEEP_SEED):
                                L=4.0, ax1=(1, Ql, 4), ax2=(0, 16, 4), Kn=float(Kn[b]), tau_model=VLB_TAU_HYDRO,
                                n_in=1.1, n_out=0.9, T_w=1.0))
     return out
+
+
+CHANNEL_SURROGATE_TRAIN_SEED, CHANNEL_SURROGATE_HELDOUT_SEED = 11, 12
+CHANNEL_SURROGATE_KN = (0.04, 0.25)
+CHANNEL_SURROGATE_R = (1.5, 3.0)
+
+
+def channel_surrogate_descs(B: int, seed: int, N_xi: int = 32, N_lambda: int = 8):
+    """Reduced channel family of the learned channel warm start: Kn log-uniform in
+    [0.04, 0.25] (tau = Kn/(nT); above Kn ~ 0.3 members of the family settle on a limit
+    cycle at r ~ 1e-5 instead of a steady state), expansion ratio r uniform in [1.5, 3] over L = 4,
+    xi in [-4, 12], HH(3;4) x H(4;8) = 64 velocities, reservoirs n 1.1 / 0.9, T_w = 1,
+    regularised WENO weights (weno_eps = 1e-6), rest initial state."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo, hi = np.log10(CHANNEL_SURROGATE_KN[0]), np.log10(CHANNEL_SURROGATE_KN[1])
+    Kn = 10.0 ** rng.uniform(lo, hi, B)
+    r = rng.uniform(CHANNEL_SURROGATE_R[0], CHANNEL_SURROGATE_R[1], B)
+    return [ChannelDesc(N_lambda=N_lambda, N_xi=N_xi, xi_in=-4.0, xi_out=12.0, r=float(r[b]), L=4.0, ax1=(1, 4, 3),
+                        ax2=(0, 8, 4), Kn=float(Kn[b]), tau_model=VLB_TAU_HYDRO, n_in=1.1, n_out=0.9, T_w=1.0,
+                        weno_eps=1e-6) for b in range(B)]

@@ -197,6 +197,28 @@ def test_channel_total_mass_open_bc_and_run_seconds():
     c.close()
 
 
+def test_channel_init_equilibrium_matches_oracle():
+    """vlb_channel_init_equilibrium builds the local equilibrium of given per-cell fields
+    (n, u^lambda, u^xi, T) as the oracle's equilibrium does (1e-13 relative), for the
+    second instance of an uneven batch in both precisions, leaving the first untouched."""
+    from paper_1708_05944_amd import VLB_MIXED, Channel
+    o0, d0 = _pair(N_lambda=8, N_xi=6, ax1=(1, 4, 3), ax2=(0, 6, 4), Kn=0.1)
+    o, d = _pair(N_lambda=10, N_xi=12, ax1=(1, 8, 4), ax2=(0, 16, 4), Kn=0.05, r=2.5)
+    X, S = np.meshgrid(o.xi_c, o.lam_c, indexing="ij")
+    fields = (1 + 0.1 * np.sin(X) * np.cos(2 * S), 0.05 * np.sin(3 * S), 0.2 * np.cos(S) * (1 - S ** 2),
+              1 + 0.05 * np.cos(X + S))
+    want = o.equilibrium(*fields)
+    for prec in (0, VLB_MIXED):
+        c = Channel([d0, d], precision=prec)
+        before = c.get_instance_state(0)
+        c.init_equilibrium(1, *fields)
+        err = _relerr(c.get_instance_state(1), want)
+        _say(f"precision {prec}: init_equilibrium rel err {err:.2e}")
+        assert err <= 1e-13
+        assert np.array_equal(c.get_instance_state(0), before)
+        c.close()
+
+
 # ---------------------------------------------------------------- mixed precision
 # FP32 stage kernel on populations scaled by 1/(w_i w_j), FP64 moment / wall-flux /
 # residual sums.  Operator bar: relative max-norm 2e-6 (about 30 ulp of float), against
