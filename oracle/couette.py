@@ -62,7 +62,10 @@ class _Params(ctypes.Structure):
                 + [(n, ctypes.POINTER(ctypes.c_double)) for n in
                    ("p1", "w1", "p2", "w2", "B1", "B2", "K1", "Kt2", "Rf", "dchi", "Gam")]
                 + [("Kn", ctypes.c_double), ("tau_model", ctypes.c_int)]
-                + [(n, ctypes.c_double) for n in ("u_in", "T_in", "u_out", "T_out", "weno_eps")])
+                + [(n, ctypes.c_double) for n in ("u_in", "T_in", "u_out", "T_out", "weno_eps")]
+                + [("form", ctypes.c_int)]
+                + [(n, ctypes.POINTER(ctypes.c_double)) for n in ("sqg", "ef")]
+                + [(n, ctypes.c_double) for n in ("deta", "sqg_in", "sqg_out")])
 
 
 def _ptr(a: np.ndarray):
@@ -110,17 +113,40 @@ def couette_faces(R_in: float, R_out: float, N_R: int, A: float = 0.0, delta: fl
     return R
 
 
+def ftilde_metric(R_in: float, R_out: float, N_R: int, A: float = 0.0, delta: float = 0.5):
+    """Metric of the f-tilde formulation on the grid of couette_faces: sqrt(g) = R R'(eta)
+    at the cell centres (eta_s = midpoint of the cell in eta), e_eta^eta = 1/R'(eta) at the
+    faces, the cell width in eta, and sqrt(g) at the two walls (Sec. V.A, Eq.
+    boltz_couette_str_cons with R(eta) of Eq. eta_def).  Equal cells: eta = R, R' = 1."""
+    s = np.arange(N_R + 1, dtype=np.float64)
+    if A == 0.0:
+        Rf = R_in + s / N_R * (R_out - R_in)
+        return 0.5 * (Rf[1:] + Rf[:-1]), np.ones(N_R + 1), (R_out - R_in) / N_R, R_in, R_out
+    A0 = max(delta, 1.0 - delta)
+    eta_l = -math.atanh(A * delta / A0)
+    eta_r = math.atanh(A * (1.0 - delta) / A0)
+    deta = (eta_r - eta_l) / N_R
+    R = lambda eta: R_in + (R_out - R_in) * (delta + A0 / A * np.tanh(eta))
+    dR = lambda eta: (R_out - R_in) * A0 / (A * np.cosh(eta) ** 2)
+    etac = eta_l + (np.arange(N_R) + 0.5) * deta
+    etaf = eta_l + s * deta
+    return R(etac) * dR(etac), 1.0 / dR(etaf), deta, R_in * dR(eta_l), R_out * dR(eta_r)
+
+
 class CouetteOracle:
     """One circular-Couette instance: R_in < R < R_out, inner wall speed u_in, outer u_out.
 
     ax1 / ax2 are (kind, Q, N) for the radial and azimuthal momentum axes
     (kind 0 = full-range H, 1 = half-range HH), e.g. HH(2;4) x H(2;4) is
     ax1=(1, 4, 2), ax2=(0, 4, 2).  weno_eps > 0 selects the regularised WENO weights
-    (an extension for reaching steady states; 0 is the paper's epsilon-free scheme)."""
+    (an extension for reaching steady states; 0 is the paper's epsilon-free scheme).
+    form = 1 selects the f-tilde formulation (the advective flux reconstructed from
+    sqrt(g) f, Sec. III Eq. boltz_cons), kept for the paper's comparison with the chi form
+    (Sec. V.C.2); the state is f in both forms."""
 
     def __init__(self, R_in=1.0, R_out=2.0, N_R=64, ax1=(1, 4, 2), ax2=(0, 4, 2), Kn=0.1,
                  tau_model=TAU_AOKI, u_in=0.1, T_in=1.0, u_out=0.0, T_out=1.0, A=0.0, delta=0.5,
-                 weno_eps=0.0):
+                 weno_eps=0.0, form=0):
         if N_R < 3:
             raise ValueError("need at least 3 cells (wall extrapolation uses 3)")
         self.a1, self.a2 = quad.axis(*ax1), quad.axis(*ax2)
@@ -134,9 +160,11 @@ class CouetteOracle:
         self.Kn, self.tau_model = Kn, tau_model
         self.walls = (u_in, T_in, u_out, T_out)
         self._keep = {}
+        self.form = form
+        self.sqg, self.ef, self.deta, sqg_in, sqg_out = ftilde_metric(R_in, R_out, N_R, A, delta)
         arrays = dict(p1=self.a1.p, w1=self.a1.w, p2=self.a2.p, w2=self.a2.w,
                       B1=self.a1.basis, B2=self.a2.basis, K1=self.a1.K, Kt2=self.a2.Kt,
-                      Rf=self.Rf, dchi=self.dchi, Gam=self.Gam)
+                      Rf=self.Rf, dchi=self.dchi, Gam=self.Gam, sqg=self.sqg, ef=self.ef)
         P = _Params()
         P.NR, P.Q1, P.Q2 = N_R, self.Q1, self.Q2
         P.kind1, P.kind2, P.N1, P.N2 = self.a1.kind, self.a2.kind, self.a1.N, self.a2.N
@@ -148,6 +176,8 @@ class CouetteOracle:
         P.Kn, P.tau_model = Kn, tau_model
         P.u_in, P.T_in, P.u_out, P.T_out = u_in, T_in, u_out, T_out
         P.weno_eps = weno_eps
+        P.form = form
+        P.deta, P.sqg_in, P.sqg_out = self.deta, sqg_in, sqg_out
         self._P = P
         self.W = np.outer(self.a1.w, self.a2.w).ravel()      # quadrature weight per velocity
 

@@ -1,5 +1,6 @@
 /*
- * Plain FP64 CPU oracle of the circular-Couette vielbein LB scheme (chi formulation).
+ * Plain FP64 CPU oracle of the circular-Couette vielbein LB scheme (chi formulation, and
+ * the f-tilde formulation of Sec. III for the comparison of Sec. V.C.2).
  * TEST INFRASTRUCTURE ONLY: nothing in the product library links or includes this
  * file, and this file includes nothing of the product library.
  *
@@ -47,6 +48,15 @@ typedef struct {
     int tau_model;           /* 0: Kn sqrt(pi/8)/n, 1: Kn/(nT), 2: Kn/n */
     double u_in, T_in, u_out, T_out;   /* tangential wall speeds and temperatures */
     double weno_eps;         /* 0: the epsilon-free weights of Table weno; > 0: regularised */
+    /* form 1: the f-tilde formulation (Sec. III, Eqs. boltz_cons and wf_def; Sec. V.A,
+     * Eqs. boltz_couette_cons and boltz_couette_str_cons): the advective flux is
+     * reconstructed from f-tilde = sqrt(g) f.  The state stays f; its time derivative is
+     * the f-tilde equation's divided by sqrt(g) of the cell. */
+    int form;
+    const double *sqg;       /* [NR] sqrt(g) at the cell centres (R R'(eta); R on equal cells) */
+    const double *ef;        /* [NR+1] e_eta^eta = 1 / R'(eta) at the faces (1 on equal cells) */
+    double deta;             /* cell width in eta (delta R on equal cells) */
+    double sqg_in, sqg_out;  /* sqrt(g) at the wall faces */
 } couette_params;
 
 /* ------------------------------------------------------------------ equilibrium */
@@ -228,9 +238,14 @@ void oracle_couette_L(const couette_params* P, const double* F, double* L, doubl
     double* feqw_out = (double*)calloc(NV, sizeof(double));
     double* mom = (double*)calloc((size_t)NR * 4, sizeof(double));
     double* fe = (double*)calloc((size_t)2 * NV, sizeof(double));
+    const int ft = P->form == 1;
     for (int d = 0; d < 2; ++d)
         for (int s = 0; s < NR; ++s)
-            memcpy(E + ((size_t)d * NE + s + 3) * NV, F + d * dsz + (size_t)s * NV, NV * sizeof(double));
+            for (int k = 0; k < NV; ++k) {
+                const double f = F[d * dsz + (size_t)s * NV + k];
+                /* f-tilde formulation: the reconstructed variable is sqrt(g) f */
+                E[((size_t)d * NE + s + 3) * NV + k] = ft ? P->sqg[s] * f : f;
+            }
 #define EX(d, s, k) E[((size_t)(d) * NE + (s) + 3) * NV + (k)]
 
     /* 1. moments and relaxation time per cell */
@@ -271,7 +286,10 @@ void oracle_couette_L(const couette_params* P, const double* F, double* L, doubl
                 num_in += pr * oracle_weno5_eps(EX(0, 2, k), EX(0, 1, k), EX(0, 0, k), EX(0, -1, k), EX(0, -2, k), P->weno_eps);
             }
         }
-    double nw_in = -num_in / den_in, nw_out = -num_out / den_out;
+    /* f-tilde: the emitted ghosts hold sqrt(g_wall) n_w f_eq, whose flux balances the
+     * reconstructed wall-bound flux of f-tilde */
+    const double gin = ft ? P->sqg_in : 1.0, gout = ft ? P->sqg_out : 1.0;
+    double nw_in = -num_in / (gin * den_in), nw_out = -num_out / (gout * den_out);
     if (nw_res) { nw_res[0] = nw_in; nw_res[1] = nw_out; }
     /* emitted populations: ghost cells hold the wall Maxwellian, Eq. weno_populate */
     for (int i = 0; i < Q1; ++i)
@@ -280,13 +298,13 @@ void oracle_couette_L(const couette_params* P, const double* F, double* L, doubl
             double pr = P->p1[i];
             if (pr > 0)
                 for (int g = -3; g <= -1; ++g) {
-                    EX(0, g, k) = nw_in * feqw_in[k];
-                    EX(1, g, k) = P->T_in * nw_in * feqw_in[k];
+                    EX(0, g, k) = gin * (nw_in * feqw_in[k]);
+                    EX(1, g, k) = gin * (P->T_in * nw_in * feqw_in[k]);
                 }
             if (pr < 0)
                 for (int g = NR; g <= NR + 2; ++g) {
-                    EX(0, g, k) = nw_out * feqw_out[k];
-                    EX(1, g, k) = P->T_out * nw_out * feqw_out[k];
+                    EX(0, g, k) = gout * (nw_out * feqw_out[k]);
+                    EX(1, g, k) = gout * (P->T_out * nw_out * feqw_out[k]);
                 }
         }
 
@@ -309,7 +327,10 @@ void oracle_couette_L(const couette_params* P, const double* F, double* L, doubl
                         fl = oracle_weno5_eps(EX(d, s + 2, k), EX(d, s + 1, k), EX(d, s, k), EX(d, s - 1, k), EX(d, s - 2, k), P->weno_eps);
                         fr = oracle_weno5_eps(EX(d, s + 3, k), EX(d, s + 2, k), EX(d, s + 1, k), EX(d, s, k), EX(d, s - 1, k), P->weno_eps);
                     }
-                    double adv = pr * (P->Rf[s + 1] * fr - P->Rf[s] * fl) / P->dchi[s];
+                    /* chi form: Eq. flux_kom_R / flux_kom_eta; f-tilde form: Eq. flux_cons_R /
+                     * flux_cons_eta, divided by sqrt(g) of the cell */
+                    double adv = ft ? pr * (P->ef[s + 1] * fr - P->ef[s] * fl) / (P->deta * P->sqg[s])
+                                    : pr * (P->Rf[s + 1] * fr - P->Rf[s] * fl) / P->dchi[s];
                     double kf = 0.0, ktf = 0.0;
                     for (int ip = 0; ip < Q1; ++ip) kf += P->K1[i * Q1 + ip] * Fc[ip * Q2 + j];
                     for (int jp = 0; jp < Q2; ++jp) ktf += P->Kt2[j * Q2 + jp] * Fc[i * Q2 + jp];
