@@ -101,6 +101,12 @@ typedef struct {
     double dt, cfl;
     double u_in, T_in, u_out, T_out;
     double weno_eps;
+    int form;     /* 0: the chi formulation (Sec. V.A, Eq. boltz_couette_kom), the method; 1: the
+                   * f-tilde formulation (Sec. III, Eq. boltz_cons; Sec. V.A, Eqs. boltz_couette_cons,
+                   * boltz_couette_str_cons), kept for the comparison of Sec. V.C.2: the advective
+                   * flux is reconstructed from sqrt(g) f, sqrt(g) = R R'(eta) at cell centres,
+                   * e_eta = 1/R'(eta) at faces, the emitted wall ghosts holding sqrt(g_wall) n_w
+                   * f_eq; the state is f in both forms.  FP64 only; runs on the four-launch stage. */
 } vlb_couette_desc;
 
 typedef struct vlb_batch vlb_batch;

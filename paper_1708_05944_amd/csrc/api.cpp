@@ -813,7 +813,7 @@ vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_de
         if (!(d.N_R >= 3 && d.R_in > 0 && d.R_out > d.R_in && d.Kn > 0 && d.dt >= 0 && d.A >= 0 && d.A < 1 &&
               d.delta >= 0 && d.delta <= 1 && d.T_in > 0 && d.T_out > 0 && d.tau_model >= 0 && d.tau_model <= 2 &&
               axis_ok(d.ax1) && axis_ok(d.ax2) && (d.dt > 0 || d.cfl > 0) && d.weno_eps >= 0 &&
-              std::isfinite(d.weno_eps))) {
+              std::isfinite(d.weno_eps) && (d.form == 0 || d.form == 1))) {
             delete b;
             return fail(VLB_EINVAL, "invalid descriptor for instance %d", i);
         }
@@ -833,14 +833,14 @@ vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_de
         h.NV = h.a1.nodes * h.a2.nodes;
         // the one-block stage kernel holds a cell's velocities in one block and both kernel
         // tables in LDS; larger sets take the four-launch stage (FP64)
-        h.wide = h.NV > kMaxNV || h.a1.nodes + h.a2.nodes > kWave ||
+        h.wide = d.form == 1 || h.NV > kMaxNV || h.a1.nodes + h.a2.nodes > kWave ||
                  2 * row_slot_any(h.a1.nodes, h.a2.nodes) > kRowElems ||
                  stage_lds(pad4(std::max(ktab_elems(h.a1.nodes, h.a2.nodes, 4), ktab_elems(h.a1.nodes, h.a2.nodes, 8))),
                            sizeof(double)) > 160 * 1024;
         if (h.wide && precision == VLB_MIXED) {
             delete b;
-            return fail(VLB_EINVAL, "instance %d: %d velocities (%d + %d nodes) run in FP64 only", i, h.NV,
-                        h.a1.nodes, h.a2.nodes);
+            return fail(VLB_EINVAL, "instance %d: %d velocities (%d + %d nodes) or the f-tilde form run in FP64 only",
+                        i, h.NV, h.a1.nodes, h.a2.nodes);
         }
         h.Rf = faces(d);
         h.dchi.resize(d.N_R);
@@ -916,6 +916,39 @@ vlb_status vlb_batch_create_couette(vlb_batch** out, int B, const vlb_couette_de
         D.tRf = put(h.Rf);
         D.tdchi = put(h.dchi);
         D.tGam = put(h.Gam);
+        D.form = d.form;
+        if (d.form == 1) {
+            // f-tilde metric: sqrt(g) = R R'(eta) at the cell centres (eta midpoints), e_eta^eta =
+            // 1/R'(eta) at the faces, the cell width in eta and sqrt(g) at the walls; equal
+            // cells take eta = R.  The emitted wall ghosts hold sqrt(g_wall) n_w f_eq, so the
+            // zero-flux density divides by sqrt(g_wall) as well.
+            std::vector<double> sqg(d.N_R), ef(d.N_R + 1);
+            if (d.A == 0.0) {
+                for (int s = 0; s < d.N_R; ++s) sqg[s] = 0.5 * (h.Rf[s] + h.Rf[s + 1]);
+                for (int s = 0; s <= d.N_R; ++s) ef[s] = 1.0;
+                D.deta = (d.R_out - d.R_in) / d.N_R;
+                D.sqg_in = d.R_in;
+                D.sqg_out = d.R_out;
+            } else {
+                const long double A0 = std::max(d.delta, 1.0 - d.delta), AA = d.A, span = d.R_out - d.R_in;
+                const long double el = -std::atanh(AA * d.delta / A0), er = std::atanh(AA * (1.0L - d.delta) / A0);
+                const long double de = (er - el) / d.N_R;
+                auto Rof = [&](long double e) { return (long double)d.R_in + span * ((long double)d.delta + A0 / AA * std::tanh(e)); };
+                auto dRof = [&](long double e) { const long double c = std::cosh(e); return span * A0 / (AA * c * c); };
+                for (int s = 0; s < d.N_R; ++s) {
+                    const long double e = el + (s + 0.5L) * de;
+                    sqg[s] = (double)(Rof(e) * dRof(e));
+                }
+                for (int s = 0; s <= d.N_R; ++s) ef[s] = (double)(1.0L / dRof(el + s * de));
+                D.deta = (double)de;
+                D.sqg_in = (double)((long double)d.R_in * dRof(el));
+                D.sqg_out = (double)((long double)d.R_out * dRof(er));
+            }
+            D.tsqg = put(sqg);
+            D.tef = put(ef);
+            D.den_in *= D.sqg_in;
+            D.den_out *= D.sqg_out;
+        }
         if (precision == VLB_MIXED) {
             // FP32 path: populations scaled by 1/W (f/omega at the nodes, O(1) values); the
             // kernels become diag(1/w) K diag(w), the equilibrium bases lose their w factor
@@ -1067,6 +1100,7 @@ vlb_status vlb_set_wall(vlb_batch* b, int inst, int side, double u, double T) {
     std::vector<double> tbl;
     double den = 0;
     wall_table(h, u, T, side, tbl, den);
+    if (D.form == 1) den *= side == 0 ? D.sqg_in : D.sqg_out;   // f-tilde: ghosts carry sqrt(g_wall)
     const int off = side == 0 ? D.tfin : D.tfout;
     std::copy(tbl.begin(), tbl.end(), b->tab.begin() + D.offT + off);
     if (b->precision == VLB_MIXED) {

@@ -99,13 +99,18 @@ __device__ void wide_prep(const WideArgs& A, int chunk, double* sh) {
     const int k = chunk * kWideThreads + t;
     if (k < NV) {
         const double p1 = tab[I.tp1 + k / Q2];
+        // f-tilde form: the wall-bound flux is reconstructed from sqrt(g) f
+        const double* sg = tab + I.tsqg;
+        const bool ft = I.form == 1;
         if (p1 < 0.0) {
-            const double F1 = Fp[k], F2 = Fp[NV + k], F3 = Fp[2 * NV + k];
+            const double F1 = ft ? sg[0] * Fp[k] : Fp[k], F2 = ft ? sg[1] * Fp[NV + k] : Fp[NV + k],
+                         F3 = ft ? sg[2] * Fp[2 * NV + k] : Fp[2 * NV + k];
             const double g0 = 3.0 * F1 - 3.0 * F2 + F3, gm1 = 6.0 * F1 - 8.0 * F2 + 3.0 * F3;
             ain += p1 * Wm[k] * weno5<double>(F3, F2, F1, g0, gm1, weps);
         } else if (p1 > 0.0) {
-            const double G1 = Fp[(size_t)(NR - 1) * NV + k], G2 = Fp[(size_t)(NR - 2) * NV + k],
-                         G3 = Fp[(size_t)(NR - 3) * NV + k];
+            double G1 = Fp[(size_t)(NR - 1) * NV + k], G2 = Fp[(size_t)(NR - 2) * NV + k],
+                   G3 = Fp[(size_t)(NR - 3) * NV + k];
+            if (ft) { G1 *= sg[NR - 1]; G2 *= sg[NR - 2]; G3 *= sg[NR - 3]; }
             const double g0 = 3.0 * G1 - 3.0 * G2 + G3, gp1 = 6.0 * G1 - 8.0 * G2 + 3.0 * G3;
             aout += p1 * Wm[k] * weno5<double>(G3, G2, G1, g0, gp1, weps);
         }
@@ -237,20 +242,24 @@ __global__ __launch_bounds__(kWideThreads) void wide_update(WideArgs A) {
     const double nwo = dist ? I.T_out * nw_out : nw_out;
     const double* fin = tab + I.tfin;
     const double* fout = tab + I.tfout;
+    // the reconstructed variable: f (chi form) or sqrt(g) f (f-tilde form, whose emitted
+    // ghosts carry sqrt(g) of the wall)
+    const bool ft = I.form == 1;
+    const double* sg = tab + I.tsqg;
+    auto val = [&](int c) -> double { return ft ? sg[c] * Fd[(size_t)c * NV + kk] : Fd[(size_t)c * NV + kk]; };
     // value of cell c for velocity kk: interior, emitted ghost (Eq. weno_populate) or the
     // quadratic extrapolation of the wall-bound populations (Eq. extrapol)
     auto cell = [&](int c) -> double {
-        if (c >= 0 && c < NR) return Fd[(size_t)c * NV + kk];
+        if (c >= 0 && c < NR) return val(c);
         if (c < 0) {
-            if (p1 > 0.0) return nwi * fin[kk];
-            const double F1 = Fd[kk], F2 = Fd[NV + kk], F3 = Fd[2 * NV + kk];
+            if (p1 > 0.0) return ft ? I.sqg_in * (nwi * fin[kk]) : nwi * fin[kk];
+            const double F1 = val(0), F2 = val(1), F3 = val(2);
             if (c == -1) return 3.0 * F1 - 3.0 * F2 + F3;
             if (c == -2) return 6.0 * F1 - 8.0 * F2 + 3.0 * F3;
             return 0.0;
         }
-        if (p1 < 0.0) return nwo * fout[kk];
-        const double G1 = Fd[(size_t)(NR - 1) * NV + kk], G2 = Fd[(size_t)(NR - 2) * NV + kk],
-                     G3 = Fd[(size_t)(NR - 3) * NV + kk];
+        if (p1 < 0.0) return ft ? I.sqg_out * (nwo * fout[kk]) : nwo * fout[kk];
+        const double G1 = val(NR - 1), G2 = val(NR - 2), G3 = val(NR - 3);
         if (c == NR) return 3.0 * G1 - 3.0 * G2 + G3;
         if (c == NR + 1) return 6.0 * G1 - 8.0 * G2 + 3.0 * G3;
         return 0.0;
@@ -263,7 +272,10 @@ __global__ __launch_bounds__(kWideThreads) void wide_update(WideArgs A) {
         const double weps = I.weno_eps;
         const double fl = weno_face<double>(pos, w[0], w[1], w[2], w[3], w[4], w[5], weps);
         const double fr = weno_face<double>(pos, w[1], w[2], w[3], w[4], w[5], w[6], weps);
-        const double adv = p1 * (e[kEqGeo + 1] * fr - e[kEqGeo] * fl);
+        // chi form: Eq. flux_kom_R / flux_kom_eta; f-tilde form: Eq. flux_cons_R / flux_cons_eta
+        // divided by sqrt(g) of the cell
+        const double adv = ft ? p1 * (tab[I.tef + s + 1] * fr - tab[I.tef + s] * fl) / (I.deta * sg[s])
+                              : p1 * (e[kEqGeo + 1] * fr - e[kEqGeo] * fl);
         // force: K1 F from the product launch, F Kt2^T by a short dot product along p^phi
         const double kf = A.Y[(size_t)ds * NV + kk];
         const double* Frow = frow + (vi * Q2 - base);
@@ -280,7 +292,7 @@ __global__ __launch_bounds__(kWideThreads) void wide_update(WideArgs A) {
         for (int l = 0; l <= N2; ++l) g2 += tab[I.tB2 + vj * (N2 + 1) + l] * c2[l];
         double fe = e[0] * g1 * g2;
         if (dist) fe *= e[1];
-        const double Fc = w[3];
+        const double Fc = Fd[(size_t)s * NV + kk];
         double L = -adv - force - (Fc - fe) * e[2];
         if (A.C) L += A.C[I.offF + (size_t)ds * NV + kk];
         double out;

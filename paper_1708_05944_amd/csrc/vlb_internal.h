@@ -67,11 +67,14 @@ struct InstDesc {
     int kind1, kind2, N1, N2;
     int Qh1, Qh2, tau_model, vpt;
     double Kn, dt, T_in, T_out, den_in, den_out, weno_eps;
+    double deta, sqg_in, sqg_out;   // f-tilde form: cell width in eta, sqrt(g) at the walls
     long long offF, offC, offT;
     long long offG;   // node-table offset of the linearised mode (entries of 4 floats, N_R (Q1 + Q2) per instance)
     // table offsets relative to offT
     int tp1, tp2, tK1, tKt2, tB1, tB2, tC1, tC2, tisf1, tisf2;
-    int tfin, tfout, tWm, tresW, tRf, tdchi, tGam, pad;
+    int tfin, tfout, tWm, tresW, tRf, tdchi, tGam;
+    int form;                        // 0: chi formulation, 1: f-tilde (four-launch stage only)
+    int tsqg, tef, pad0, pad1;       // f-tilde form: sqrt(g) at the cells [NR], e_eta at the faces [NR+1]
 };
 
 // One wavefront's work: cells [s0, s0 + ncell) of one distribution of one instance.

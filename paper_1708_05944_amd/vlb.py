@@ -38,7 +38,8 @@ class _CouetteDesc(ctypes.Structure):
                 ("A", ctypes.c_double), ("delta", ctypes.c_double), ("ax1", _Axis), ("ax2", _Axis),
                 ("Kn", ctypes.c_double), ("tau_model", ctypes.c_int), ("dt", ctypes.c_double),
                 ("cfl", ctypes.c_double), ("u_in", ctypes.c_double), ("T_in", ctypes.c_double),
-                ("u_out", ctypes.c_double), ("T_out", ctypes.c_double), ("weno_eps", ctypes.c_double)]
+                ("u_out", ctypes.c_double), ("T_out", ctypes.c_double), ("weno_eps", ctypes.c_double),
+                ("form", ctypes.c_int)]
 
 
 @dataclass
@@ -61,11 +62,12 @@ class CouetteDesc:
     A: float = 0.0
     delta: float = 0.5
     weno_eps: float = 0.0
+    form: int = 0             # 0: chi formulation; 1: f-tilde formulation (comparison only, FP64)
 
     def _c(self) -> _CouetteDesc:
         return _CouetteDesc(self.R_in, self.R_out, self.N_R, self.A, self.delta, _Axis(*self.ax1),
                             _Axis(*self.ax2), self.Kn, self.tau_model, self.dt, self.cfl, self.u_in,
-                            self.T_in, self.u_out, self.T_out, self.weno_eps)
+                            self.T_in, self.u_out, self.T_out, self.weno_eps, self.form)
 
 
 _dp = ctypes.POINTER(ctypes.c_double)

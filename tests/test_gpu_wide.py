@@ -118,3 +118,55 @@ def test_wide_instance_runs_to_steady_state_with_retirement():
     L, _ = o.L(F)
     assert np.abs(L).max() <= 1e-6 * np.abs(F).max()
     b.close()
+
+
+# ---------------------------------------------------------------- f-tilde formulation
+FTILDE_CASES = [
+    # the paper's Fig. komissarov set-up: cylinders at rest, H(4;5)^2, stretched cells
+    dict(N_R=16, ax1=(0, 5, 4), ax2=(0, 5, 4), Kn=1e-3, tau_model=2, u_in=0.0, A=0.95, delta=0.5, form=1),
+    # moving inner wall, half-range radial axis, equal cells, hotter outer wall
+    dict(N_R=12, ax1=(1, 4, 3), ax2=(0, 6, 4), Kn=0.2, u_in=0.3, T_out=1.1, form=1),
+]
+
+
+@pytest.mark.parametrize("case", FTILDE_CASES)
+def test_ftilde_operator_and_steps_match_oracle(case):
+    """The f-tilde formulation (Sec. III, Eq. boltz_cons; the paper's comparison scheme)
+    on the four-launch stage: L and 10 RK3 steps against the oracle's f-tilde operator."""
+    from paper_1708_05944_amd import Batch
+    _say(f"case {case}")
+    o, d = _pair(**dict(case))
+    b = Batch([d])
+    F = _perturbed(o, 5)
+    b.set_state(F.ravel())
+    err = _relerr(b.instance_view(b.apply_L(), 0), o.L(F)[0])
+    _say(f"f-tilde L rel err {err:.2e}")
+    assert err <= TOL
+    b.step(10)
+    err = _relerr(b.instance_view(b.get_state(), 0), o.step(F, b.info[0]["dt"], 10))
+    _say(f"f-tilde 10 steps rel err {err:.2e}")
+    assert err <= TOL
+    b.close()
+
+
+def test_rest_state_ftilde_vs_chi_on_the_gpu():
+    """Sec. V.C.2 (Fig. komissarov): cylinders at rest on stretched cells; from the rest
+    Maxwellian the chi form stays at n = 1 to rounding over 400 steps, the f-tilde form
+    redistributes particles (the same deviation as the oracle's, to 1e-10)."""
+    from paper_1708_05944_amd import Batch
+    dev = {}
+    for form in (0, 1):
+        case = dict(FTILDE_CASES[0], form=form)
+        o, d = _pair(**case)
+        d.dt = 1e-3
+        b = Batch([d])
+        b.init_equilibrium(0, 1.0, 0.0, 0.0, 1.0)
+        b.step(400)
+        n = b.moments(0)["n"]
+        dev[form] = np.abs(n - 1.0).max()
+        if form == 1:
+            want = o.moments(o.step(o.equilibrium(1.0, 0.0, 0.0, 1.0), 1e-3, 400))["n"]
+            assert np.abs(n - want).max() <= 1e-10
+        b.close()
+    _say(f"max |n - 1| after 400 steps: chi {dev[0]:.1e}, f-tilde {dev[1]:.1e}")
+    assert dev[0] <= 1e-12 and dev[1] >= 1e-3
