@@ -277,12 +277,12 @@ def main():
     mixed = measure(VLB_MIXED)
     dom, dom64 = mixed["dom"], fp64["dom"]
     couette_flops_launch = stage_flops(descs)
-    roof = roofline("couette_stage<float>", dom["total_ms"] / dom["launches"], dom["alg_bytes"] / dom["launches"],
-                    couette_flops_launch, VALU_FP32_TFLOPS, measured_traffic("couette_stage<float>"),
+    roof = roofline("couette_stage<float, false>", dom["total_ms"] / dom["launches"], dom["alg_bytes"] / dom["launches"],
+                    couette_flops_launch, VALU_FP32_TFLOPS, measured_traffic("couette_stage<float, false>"),
                     launches=dom["launches"])
-    roof64 = roofline("couette_stage<double>", dom64["total_ms"] / dom64["launches"],
+    roof64 = roofline("couette_stage<double, false>", dom64["total_ms"] / dom64["launches"],
                       dom64["alg_bytes"] / dom64["launches"], couette_flops_launch, VALU_FP64_TFLOPS,
-                      measured_traffic("couette_stage<double>"), launches=dom64["launches"])
+                      measured_traffic("couette_stage<double, false>"), launches=dom64["launches"])
 
     # time to steady state (r < 1e-10) of the single-instance workload, FP64 vs mixed
     tts = {}
