@@ -326,6 +326,11 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
     const T* K1row = Ks + vi * P1;
     const T* Ktrow = Kt + vj * P2;
     const double pw1 = (double)p1, pw2 = (double)p2;
+    // coefficients of the four moment products of the output (1, p1, p2, |p|^2), in the lane
+    // order of row_sum4: this lane's quantity q = lane & 3, then q ^ 2, q ^ 1, q ^ 3
+    auto mcoef = [&](int j) { return j == 0 ? 1.0 : (j == 1 ? pw1 : (j == 2 ? pw2 : pw1 * pw1 + pw2 * pw2)); };
+    const int mq = lane & 3;
+    const double cK1 = mcoef(mq), cK2 = mcoef(mq ^ 2), cS1 = mcoef(mq ^ 1), cS2 = mcoef(mq ^ 3);
     const double wmk = Wm[kk], rwk = resW[kk];
 
     // moments (and residual partials) of cell c of this run, one cell behind the sweep:
@@ -436,7 +441,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
         }
         __syncthreads();
         if (c > 0) finish(c - 1, buf ^ 1);
-        double m0 = 0, m1 = 0, m2 = 0, m3 = 0, rd = 0, rn = 0;
+        double wo = 0, rd = 0, rn = 0;
         if (cv) {
             const T fr = weno_face<T, LIN>(pos, w0v, w1v, w2v, w3v, w4v, w5v, weps);
             const T Rl = T(e[kEqGeo]), Rr = T(e[kEqGeo + 1]), gam = T(e[kEqGeo + 3]);   // R_{s-+1/2}/dchi_s
@@ -475,24 +480,26 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
             }
             out_prev = out;
             st_off = eoff(s);
-            const double wo = wmk * (double)out;
-            m0 = wo;
-            if (dist == 0) {
-                m1 = pw1 * wo;
-                m2 = pw2 * wo;
-                m3 = (pw1 * pw1 + pw2 * pw2) * wo;
-            }
+            wo = wmk * (double)out;
             fl = fr;
         }
         fnr[p] = buf_load<T>(rFn, (ahead && need_fn) ? eoff(s + kAhead) : kBufNone);
         if constexpr (LIN) cr[p] = buf_load<T>(rC, ahead ? eoff(s + kAhead) : kBufNone);
-        // row totals; lanes 0, 16, 32, 48 store them, the finishing lanes add the rows
-        m0 = row_sum(m0);
-        if (dist == 0) { m1 = row_sum(m1); m2 = row_sum(m2); m3 = row_sum(m3); }
-        if (A.rpart) { rd = row_sum(rd); rn = row_sum(rn); }
-        if ((lane & 15) == 0) {
-            double* mp = mpart + ((size_t)buf * (kStageThreads / kWave) + wave) * 32 + (lane >> 4);
-            mp[0] = m0; mp[4] = m1; mp[8] = m2; mp[12] = m3; mp[16] = rd; mp[20] = rn;
+        // row totals of the moment products (f': n, p1, p2, |p|^2 weighted; f'': n only) and
+        // of the residual partials; lanes 4 q + r' hold quantity q's total of row r (the
+        // finishing lanes add the rows), stored at slot 4 q + row
+        double* mp = mpart + ((size_t)buf * (kStageThreads / kWave) + wave) * 32 + (lane >> 4);
+        if (dist == 0) {
+            const double mt = row_sum4(cK1 * wo, cK2 * wo, cS1 * wo, cS2 * wo);
+            if ((lane & 15) < 4) mp[4 * mq] = mt;
+        } else {
+            const double m0 = row_sum(wo);
+            if ((lane & 15) == 0) mp[0] = m0;
+        }
+        if (A.rpart) {
+            rd = row_sum(rd);
+            rn = row_sum(rn);
+            if ((lane & 15) == 0) { mp[16] = rd; mp[20] = rn; }
         }
     }
     }

@@ -48,10 +48,22 @@ __device__ __forceinline__ double row_sum(double v) {
     return v;
 }
 
-// 1/x: the hardware reciprocal in FP32 (about 1 ulp, the FP32 path's tolerance is far
-// wider); in FP64 the hardware estimate refined by two Newton steps r <- r + r (1 - x r)
-// (each squares the relative error; the result is within an ulp or so of 1/x, for the
-// normal, positive arguments the WENO weights take; x = 0 gives NaN, like 0 * (1/0)).
+// Row totals of four quantities at once (a transposed reduction): lane l holds the four
+// products x_q = c_q v, q = 0..3, as k1 = x_{q(l)}, k2 = x_{q(l)^2}, s1 = x_{q(l)^1},
+// s2 = x_{q(l)^3} with q(l) = l & 3.  A quad butterfly (xor 1) leaves each lane the pair
+// sums of its own quantity and of the one its xor-2 partner keeps, a second (xor 2) the
+// quad sum of its own quantity, and row rotations by 4 and 8 (which keep a lane's place in
+// its quad) add the four quads: lane l returns the row total of quantity l & 3, in a fixed
+// order.  Five adds and ten moves, against sixteen and thirty-two for four row_sum calls.
+__device__ __forceinline__ double row_sum4(double k1, double k2, double s1, double s2) {
+    const double a1 = k1 + dpp_mov<0xB1>(s1);   // quad_perm [1,0,3,2]
+    const double a2 = k2 + dpp_mov<0xB1>(s2);
+    double b = a1 + dpp_mov<0x4E>(a2);          // quad_perm [2,3,0,1]
+    b += dpp_mov<0x124>(b);                     // row_ror:4
+    b += dpp_mov<0x128>(b);                     // row_ror:8
+    return b;
+}
+
 // Raw buffer access (range-checked by the resource): an offset at or beyond the resource's
 // byte count reads 0 and drops the write, so loads and stores of lanes with nothing to
 // move are still issued, and every wavefront issues the same memory instructions in the
@@ -79,6 +91,10 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, off, 0, 0);
 }
 
+// 1/x: the hardware reciprocal in FP32 (about 1 ulp, the FP32 path's tolerance is far
+// wider); in FP64 the hardware estimate refined by two Newton steps r <- r + r (1 - x r)
+// (each squares the relative error; the result is within an ulp or so of 1/x, for the
+// normal, positive arguments the WENO weights take; x = 0 gives NaN, like 0 * (1/0)).
 template <typename T>
 __device__ __forceinline__ T recip(T x);
 template <>
