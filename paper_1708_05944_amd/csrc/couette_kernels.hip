@@ -250,7 +250,9 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
     const unsigned dbytes = (unsigned)((size_t)NR * NV * sizeof(T));
     const __amdgpu_buffer_rsrc_t rF = buf_rsrc(Fd, dbytes), rFn = buf_rsrc(Fnd, dbytes), rO = buf_rsrc(Fo, dbytes),
                                  rC = buf_rsrc(Cd, Cd ? dbytes : 0u);
-    auto eoff = [&](int c) { return (unsigned)(((size_t)c * NV + k) * sizeof(T)); };   // element (c, k)
+    // element (c, k) = the lane's velocity offset kE plus the wavefront-uniform cell offset
+    const unsigned kE = (unsigned)(k * sizeof(T));
+    auto cofs = [&](int c) { return (unsigned)((size_t)c * NV * sizeof(T)); };
     const double* Wm = tab + I.tWm;
     const T weps = T(I.weno_eps);
     const bool near_in = rlen > 0 && rs0 < 3, near_out = rlen > 0 && rs0 + rlen > NR - 3;
@@ -364,9 +366,9 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
 #pragma unroll
     for (int q = 0; q < kAhead; ++q) {
         const int x = rs0 + 3 + q;
-        pw[q] = buf_load<T>(rF, (act && q < rlen && x < NR) ? eoff(x) : kBufNone);
-        fnr[q] = buf_load<T>(rFn, (act && need_fn && q < rlen) ? eoff(rs0 + q) : kBufNone);
-        if constexpr (LIN) cr[q] = buf_load<T>(rC, (act && q < rlen) ? eoff(rs0 + q) : kBufNone);
+        pw[q] = buf_load<T>(rF, (act && q < rlen && x < NR) ? kE : kBufNone, cofs(x < NR ? x : 0));
+        fnr[q] = buf_load<T>(rFn, (act && need_fn && q < rlen) ? kE : kBufNone, cofs(rs0 + q));
+        if constexpr (LIN) cr[q] = buf_load<T>(rC, (act && q < rlen) ? kE : kBufNone, cofs(rs0 + q));
     }
 
     // the run's first wavefront also finishes the previous cell's sums and its last one
@@ -379,7 +381,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
     // loads: stores count against the same wait as loads, and the loop latch waits for
     // the ring (a store issued late in the cell would be waited for there)
     T out_prev = T(0);
-    unsigned st_off = kBufNone;
+    unsigned st_v = kBufNone, st_s = 0;
     // linearised stage: the node factors of the run's first cell (loaded a cell ahead)
     typedef float f3v __attribute__((ext_vector_type(3)));   // (g, dg/du, dg/dT) of a node entry
     f3v lin_t4 = {0.f, 0.f, 0.f};
@@ -407,8 +409,8 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
         // this cell's prefetch loads refill the slots it read, each right after the slot's
         // last use, so the load can take the slot's own register
         const bool ahead = cv && c + kAhead < rlen;
-        buf_store(rO, st_off, out_prev);
-        st_off = kBufNone;
+        buf_store(rO, st_v, st_s, out_prev);
+        st_v = kBufNone;
         T* row = rows + (size_t)buf * kRowElems + (size_t)r * 2 * S;
         T* rowT = row + S;
         T* gb = gbuf + (size_t)buf * kMaxRuns * kWave + (size_t)r * kWave;
@@ -421,7 +423,8 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
             row[vi * P2 + vj] = w2v;
             rowT[vj * P1 + vi] = w2v;
         }
-        pw[p] = buf_load<T>(rF, (ahead && s + 3 + kAhead < NR) ? eoff(s + 3 + kAhead) : kBufNone);
+        pw[p] = buf_load<T>(rF, (ahead && s + 3 + kAhead < NR) ? kE : kBufNone,
+                            cofs(s + 3 + kAhead < NR ? s + 3 + kAhead : 0));
         if (coff >= 0 && c < rlen) {
             if constexpr (LIN) {
                 const f3v t4 = lin_t4;
@@ -479,12 +482,13 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
                 }
             }
             out_prev = out;
-            st_off = eoff(s);
             wo = wmk * (double)out;
             fl = fr;
         }
-        fnr[p] = buf_load<T>(rFn, (ahead && need_fn) ? eoff(s + kAhead) : kBufNone);
-        if constexpr (LIN) cr[p] = buf_load<T>(rC, ahead ? eoff(s + kAhead) : kBufNone);
+        st_v = cv ? kE : kBufNone;   // this cell's output, stored at the top of the next cell
+        st_s = cofs(s);
+        fnr[p] = buf_load<T>(rFn, (ahead && need_fn) ? kE : kBufNone, cofs(s + kAhead));
+        if constexpr (LIN) cr[p] = buf_load<T>(rC, ahead ? kE : kBufNone, cofs(s + kAhead));
         // row totals of the moment products (f': n, p1, p2, |p|^2 weighted; f'': n only) and
         // of the residual partials; lanes 4 q + r' hold quantity q's total of row r (the
         // finishing lanes add the rows), stored at slot 4 q + row
@@ -503,7 +507,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, const int blk) {
         }
     }
     }
-    buf_store(rO, st_off, out_prev);
+    buf_store(rO, st_v, st_s, out_prev);
     __syncthreads();
     finish(TC - 1, (TC - 1) & 1);
 }
