@@ -444,6 +444,13 @@ vlb_status channel_build(vlb_channel** out, int B, const vlb_channel_desc* descs
                 c->groups.push_back(vlb_channel::Group{T1, T2, {}, {0}, {0}, 0, 0, 0});
                 it = c->groups.end() - 1;
             }
+            // the stage kernel addresses an interior cell's stencil (seven xi columns) as one
+            // buffer with 32-bit byte offsets
+            if ((unsigned long long)7 * NL * NV * sizeof(double) >= (1ULL << 32)) {
+                delete c;
+                return set_error(VLB_EINVAL, "instance %d: N_lambda x velocities = %lld too large for the stage kernel",
+                                 i, (long long)NL * NV);
+            }
             // interior cells (3 <= s < NL - 3, 3 <= p < NX - 3) in lambda strips of up to
             // kChanStrip cells (a multiple of kChanWaves); edge-band cells in order
             const int NLi = std::max(NL - 6, 0), NXi = std::max(NX - 6, 0);

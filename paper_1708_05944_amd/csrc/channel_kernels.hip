@@ -335,14 +335,20 @@ __global__ __launch_bounds__(kChanWaves * kWave, T1 * T2 == 1 ? (sizeof(T) == 4 
     const T Tcell = T(Tc), itauT = T(itau);
     const double* iW = tab + I.tiW;
     wave_lds_fence();
+    // The FP32 interior variant keeps the cell's F and the equilibrium factors in registers
+    // through the advection loop; the others, at their register limit, read both back from
+    // LDS in the BGK step (held in registers they were spilled to scratch memory).
+    constexpr bool kRegs = F32 && !BND;
     T g1v[T1][4], g2v[T2];
+    if (kRegs) {
 #pragma unroll
-    for (int I_ = 0; I_ < T1; ++I_)
+        for (int I_ = 0; I_ < T1; ++I_)
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            g1v[I_][c] = T(16 * I_ + 4 * c + g < Q1 ? nd * gf[16 * I_ + 4 * c + g] : 0.0);
+            for (int c = 0; c < 4; ++c)
+                g1v[I_][c] = T(16 * I_ + 4 * c + g < Q1 ? nd * gf[16 * I_ + 4 * c + g] : 0.0);
 #pragma unroll
-    for (int J = 0; J < T2; ++J) g2v[J] = T(16 * J + n < Q2 ? gf[Q1 + 16 * J + n] : 0.0);
+        for (int J = 0; J < T2; ++J) g2v[J] = T(16 * J + n < Q2 ? gf[Q1 + 16 * J + n] : 0.0);
+    }
 
 #pragma unroll 1
     for (int d = 0; d < 2; ++d) {
@@ -396,6 +402,13 @@ __global__ __launch_bounds__(kChanWaves * kWave, T1 * T2 == 1 ? (sizeof(T) == 4 
         // and L live in this lane's slots of the LDS rows), one item in registers at a time.
         // Cells whose stencils stay inside the grid (most of them) take a loop without the
         // ghost logic, so its conditions and offsets do not occupy registers there.
+        // Interior cells address their stencil as one buffer over the columns p-3 .. p+3 from
+        // row s: one lane offset and wavefront-uniform offsets per neighbour, so the twelve
+        // loads of an item need no 64-bit lane addresses (the span, 7 NL NV values, is checked
+        // against the 32-bit buffer range at channel creation).
+        const __amdgpu_buffer_rsrc_t rSt = buf_rsrc(BND ? Fd : Fd - 3 * xstride,
+                                                    BND ? 0u : 7u * (unsigned)xstride * (unsigned)sizeof(T));
+        const unsigned xsb = (unsigned)xstride * (unsigned)sizeof(T), nvb = (unsigned)NV * (unsigned)sizeof(T);
         auto advect = [&](auto interior_tag) {
             constexpr bool interior = decltype(interior_tag)::value;
 #pragma unroll 1
@@ -406,7 +419,14 @@ __global__ __launch_bounds__(kChanWaves * kWave, T1 * T2 == 1 ? (sizeof(T) == 4 
                 const T plt = T(tab[I.tp1 + i]), pxt = T(tab[I.tp2 + j]);
                 const T fct = tr[i * RS + j];
                 T lw[7], xw[7];
-                if (interior || lam_interior) {
+                if constexpr (interior) {
+                    const unsigned ko = (unsigned)k * (unsigned)sizeof(T);
+#pragma unroll
+                    for (int q = 0; q < 7; ++q) {   // (q - 3) nvb wraps: the sum is the true offset
+                        lw[q] = q == 3 ? fct : buf_load<T>(rSt, ko, 3u * xsb + (unsigned)(q - 3) * nvb);
+                        xw[q] = q == 3 ? fct : buf_load<T>(rSt, ko, (unsigned)q * xsb);
+                    }
+                } else if (lam_interior) {
 #pragma unroll
                     for (int q = 0; q < 7; ++q) lw[q] = q == 3 ? fct : Fd[(q - 3) * NV + k];
                 } else {
@@ -441,7 +461,8 @@ __global__ __launch_bounds__(kChanWaves * kWave, T1 * T2 == 1 ? (sizeof(T) == 4 
                         lw[q] = v;
                     }
                 }
-                if (interior || xi_interior) {
+                if constexpr (interior) {
+                } else if (xi_interior) {
 #pragma unroll
                     for (int q = 0; q < 7; ++q)
                         xw[q] = q == 3 ? fct : Fd[(ptrdiff_t)(q - 3) * (ptrdiff_t)xstride + k];
@@ -490,29 +511,38 @@ __global__ __launch_bounds__(kChanWaves * kWave, T1 * T2 == 1 ? (sizeof(T) == 4 
         if (!BND) advect(std::true_type{});
         else advect(std::false_type{});
 
-        // BGK, RK combination, store, residual partials (FP64)
-        const T* Fn = A.Fn ? static_cast<const T*>(A.Fn) + I.offF + d * dstride + ((size_t)p * NL + s) * NV
-                           : nullptr;
-        T* Fo = static_cast<T*>(A.Fout) + I.offF + d * dstride + ((size_t)p * NL + s) * NV;
+        // BGK, RK combination, store, residual partials (FP64).  The variants at their
+        // register limit address F_n, the output and the residual weights as buffers of the
+        // cell's populations (a wavefront-uniform base and 32-bit lane offsets), so that no
+        // 64-bit lane addresses stay live across the loop.
+        const size_t cofs = I.offF + d * dstride + ((size_t)p * NL + s) * NV;
+        const T* Fn = A.Fn ? static_cast<const T*>(A.Fn) + cofs : nullptr;
+        T* Fo = static_cast<T*>(A.Fout) + cofs;
+        const __amdgpu_buffer_rsrc_t rFn = buf_rsrc(Fn, Fn ? NV * (unsigned)sizeof(T) : 0u);
+        const __amdgpu_buffer_rsrc_t rFo = buf_rsrc(Fo, NV * (unsigned)sizeof(T));
+        const __amdgpu_buffer_rsrc_t rW = buf_rsrc(iW, NV * (unsigned)sizeof(double));
         double rd = 0.0, rn = 0.0;
 #pragma unroll
         for (int t = 0; t < NI; ++t) {
             if (!item_ok(t)) continue;
             const int k = item_k(t);
-            T fe = g1v[t / (4 * T2)][t & 3] * g2v[(t >> 2) % T2];
+            T fe = kRegs ? g1v[t / (4 * T2)][t & 3] * g2v[(t >> 2) % T2]
+                         : T(nd * gf[item_i(t)]) * T(gf[Q1 + item_j(t)]);
             if (d) fe *= Tcell;
-            const T L = lcb[item_i(t) * RS + item_j(t)] - (fc[t] - fe) * itauT;
+            const T fct = kRegs ? fc[t] : tr[item_i(t) * RS + item_j(t)];
+            const T L = lcb[item_i(t) * RS + item_j(t)] - (fct - fe) * itauT;
             T out;
             if (lonly) {
                 out = L;
             } else {
-                const T fn = ca != T(0) ? Fn[k] : T(0);
-                out = ca * fn + cb * fc[t] + ccdt * L;
-                const double iw = iW[k], dd = (double)out - (double)fn;
+                const T fn = ca == T(0) ? T(0) : kRegs ? Fn[k] : buf_load<T>(rFn, (unsigned)k * (unsigned)sizeof(T));
+                out = ca * fn + cb * fct + ccdt * L;
+                const double iw = kRegs ? iW[k] : buf_load<double>(rW, (unsigned)k * 8u), dd = (double)out - (double)fn;
                 rd += dd * dd * iw;
                 rn += (double)fn * (double)fn * iw;
             }
-            Fo[k] = out;
+            if (kRegs) Fo[k] = out;
+            else buf_store(rFo, (unsigned)k * (unsigned)sizeof(T), 0u, out);
         }
         if (A.rpart) {
             rd = wave_sum(rd);
