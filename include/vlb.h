@@ -230,12 +230,13 @@ vlb_status vlb_mixed_report(const vlb_batch* b, double* theta, long* fp64_from, 
  * kernel Kt (nodes x nodes, row-major; Sec. IV.C).  nodes = Q (kind 0) or 2Q. */
 vlb_status vlb_axis_tables(vlb_axis ax, double* p, double* w, double* K, double* Kt);
 
-/* Cells per run of the stage kernel (2..32; default 16): each block sweeps runs of this
+/* Cells per run of the stage kernel (1..32; default 16): each block sweeps runs of this
  * many consecutive cells, one thread per velocity.  Short runs give small instances more
  * parallel blocks; long runs amortise the 3-cell halo at each run end.
- * vlb_batch_autotune times `steps` steps for each cells-per-run value from 2 to 32 on the
- * batch itself (on a copy of the state, which is restored), keeps the fastest, and returns it with its
- * time per step in ms.  Allocates a temporary device copy of the state. */
+ * vlb_batch_autotune times `steps` steps three times for each cells-per-run value from 1 to
+ * 32 on the batch itself (the state is saved to a device copy and restored), keeps the value
+ * with the fastest of all these timings, and returns it with that time per step in ms.
+ * Allocates a temporary device copy of the state. */
 vlb_status vlb_batch_set_tile(vlb_batch* b, int cells_per_run);
 vlb_status vlb_batch_get_tile(const vlb_batch* b, int* cells_per_run);
 vlb_status vlb_batch_autotune(vlb_batch* b, int steps, int* chosen, double* ms_per_step);

@@ -1504,21 +1504,26 @@ vlb_status vlb_batch_autotune(vlb_batch* b, int steps, int* chosen, double* ms_p
     vlb_status st = VLB_OK;
     // every length: the launch's block count against the 256 CUs (a last, nearly empty
     // round of blocks costs a whole block time), the halo reads and the per-block set-up
-    // all move with it, not monotonically
-    for (int tile = kMinTile; tile <= kMaxTile; ++tile) {
+    // all move with it, not monotonically.  Each length keeps the best of kTuneReps timed
+    // runs: a small instance's few-millisecond timings otherwise pick among neighbouring
+    // lengths by noise.
+    constexpr int kTuneReps = 3;
+    for (int tile = kMinTile; tile <= kMaxTile && st == VLB_OK; ++tile) {
         build_blocks(b, tile);
         st = upload_blocks(b);
         if (st != VLB_OK) break;
         st = step_current(b, 1);   // warm-up (also captures nothing: single plain step)
         if (st != VLB_OK) break;
-        HIP_TRY(hipEventRecord(e0, b->stream));
-        st = step_current(b, steps);
-        if (st != VLB_OK) break;
-        HIP_TRY(hipEventRecord(e1, b->stream));
-        HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) { best_ms = ms; best = tile; }
+        for (int rep = 0; rep < kTuneReps; ++rep) {
+            HIP_TRY(hipEventRecord(e0, b->stream));
+            st = step_current(b, steps);
+            if (st != VLB_OK) break;
+            HIP_TRY(hipEventRecord(e1, b->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) { best_ms = ms; best = tile; }
+        }
     }
     b->timing = timing;
     (void)hipEventDestroy(e0);

@@ -16,7 +16,7 @@ constexpr int kWavesPerBlock = 4;   // blocks of the auxiliary (per-wavefront wo
 constexpr int kStageThreads = 1024; // stage kernel block: one thread per velocity
 constexpr int kMaxNV = kStageThreads;
 constexpr int kTileCells = 16; // default cells per run (auxiliary kernels and stage kernel)
-constexpr int kMinTile = 2, kMaxTile = 32;   // range of the stage kernel's cells per run
+constexpr int kMinTile = 1, kMaxTile = 32;   // range of the stage kernel's cells per run
 constexpr int kMaxRuns = 16;   // cell runs per stage block
 constexpr int kEqStride = 28;  // doubles kept per cell: n, T, 1/tau, coefficients, geometry (last 4)
 constexpr int kEqGeo = kEqStride - 4;   // R_{s-1/2}/dchi_s, R_{s+1/2}/dchi_s, dchi_s, Gamma_s
