@@ -124,8 +124,8 @@ def _cpu_worker(args):
 
 
 def host_cores():
-    """Host threads this process may use (affinity), capped at the GPU machine's CPU share of 16,
-    and the CPU model."""
+    """Host threads this process may use (affinity), capped at 16 (the host CPU share of one
+    GPU on the measurement machines), and the CPU model."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:

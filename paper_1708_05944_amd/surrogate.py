@@ -196,8 +196,8 @@ def channel_run(c, tol, max_steps, chunk=10_000, check_every=1000, stall_window=
     """Run a channel batch (FP64) to r < tol in chunks; returns (steps at convergence per
     instance or -1, last residuals, cold restarts per instance (step or -1)).  With
     stall_window, an instance started warm whose residual sets no new low (by 1 %) for
-    stall_window steps is restarted from the rest state (the plain solver's residual is
-    the judge, the cold start the fallback).  With patience, the run also stops once no
+    stall_window steps is restarted from the rest state (the plain solver's residual
+    decides, the cold start is the fallback).  With patience, the run also stops once no
     instance has converged for that many steps (for training solves, where the instances
     that do converge are what is wanted)."""
     B = c.B
