@@ -232,6 +232,7 @@ def main():
                     help="skip the learned warm-start leg (training solves, training, held-out runs)")
     ap.add_argument("--no-channel", action="store_true", help="skip the expanding-channel leg")
     ap.add_argument("--no-ballistic", action="store_true", help="skip the ballistic (8000-velocity) leg")
+    ap.add_argument("--no-channel-sweep", action="store_true", help="skip the batched 64-channel leg")
     ap.add_argument("--no-clb", action="store_true", help="skip the vielbein vs Cartesian-split channel timing")
     ap.add_argument("--warm-train", type=int, default=4096, help="training instances of the warm-start leg")
     ap.add_argument("--warm-heldout", type=int, default=256, help="held-out instances of the warm-start leg")
@@ -342,6 +343,37 @@ def main():
                                "ratio 2 over 4 widths, reservoirs n 1.1 / 0.9; mixed = FP32 stage kernel on "
                                "weight-scaled populations with FP32 MFMA contractions and FP64 sums",
                    **mixed_ch, "dtype": "f32", "fp64": fp64_ch}
+
+    channel_batch = None
+    if not args.no_channel_sweep:
+        # batched expanding channels: 64 seeded instances (N_lambda 64..256, N_xi = 4 N_lambda,
+        # Kn 0.01..1, expansion ratio 1.5..3, HH(4;Q) x H(4;16) with Q 8..16 by Kn: 256..512
+        # velocities, both velocity-tile classes), advanced together; HIP events around the
+        # timed steps (graph-replayed stages of every instance)
+        from paper_1708_05944_amd import Channel
+        sweep = workloads.channel_sweep()
+        sv_b = sum(d.N_lambda * d.N_xi * 2 * d.ax1[1] * d.ax2[1] for d in sweep)
+
+        def batch_leg(precision):
+            torch.cuda.empty_cache()   # the batch takes 134 GB (FP64) / 201 GB (mixed) of HBM
+            c = Channel(sweep, precision=precision)
+            c.step(1)
+            torch.cuda.synchronize()
+            nst = 3
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            c.step(nst)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / nst
+            c.close()
+            return {"value": sv_b / (ms * 1e-3), "unit": "site-velocity updates/s", "ms_per_step": ms, "steps": nst}
+
+        channel_batch = {"workload": "64 expanding channels (PCG64 seed 3): N_lambda 64-256 x N_xi 4 N_lambda, "
+                                     "Kn 0.01-1, ratio 1.5-3 over 4 widths, HH(4;8..16) x H(4;16) (256-512 "
+                                     "velocities), reservoirs n 1.1 / 0.9, one batch",
+                         "site_velocities_per_step": sv_b, **batch_leg(VLB_MIXED), "dtype": "f32",
+                         "fp64": batch_leg(0)}
 
     ballistic = None
     if not args.no_ballistic:
@@ -485,6 +517,7 @@ def main():
         "time_to_steady_state_warm_start": warm,
         "time_to_steady_state_channel_warm_start": channel_warm,
         "channel": channel,
+        "channel_batch": channel_batch,
         "ballistic": ballistic,
         "vlb_vs_clb": clb,
     }
