@@ -119,7 +119,7 @@ struct Acc4<float> {
 // centreline, ends).  The two launches of a stage write disjoint cells.
 template <typename T, int T1, int T2, bool BND>
 __global__ __launch_bounds__(kChanWaves * kWave, T1 * T2 == 1 ? (sizeof(T) == 4 ? 4 : (BND ? 2 : 3))
-                                                               : (sizeof(T) == 4 && !BND ? 4 : 2)) void channel_stage(ChanArgs A) {
+                                                               : (sizeof(T) == 4 ? (BND ? 3 : 4) : 2)) void channel_stage(ChanArgs A) {
     constexpr bool F32 = sizeof(T) == 4;
     constexpr int NT = T1 * T2, NI = 4 * NT;   // items (tile registers) per lane per distribution
     constexpr int RS = 16 * T2 + 2;           // LDS row stride of the transpose buffer
@@ -340,7 +340,8 @@ __global__ __launch_bounds__(kChanWaves * kWave, T1 * T2 == 1 ? (sizeof(T) == 4 
     // equilibrium factors in registers through the advection loop; the others, at their
     // register limit, read both back from LDS in the BGK step (held in registers they were
     // spilled to scratch memory; the two-tile FP32 interior variant reads them back to run
-    // 4 wavefronts per SIMD instead of 3: 64-channel batch 7.09 -> 7.61 G/s).
+    // 4 wavefronts per SIMD instead of 3: 64-channel batch 7.09 -> 7.61 G/s; its edge-band
+    // variant runs 3 instead of 2, 7.61 -> 7.78 G/s).
     constexpr bool kRegs = F32 && !BND && T1 * T2 == 1;
     T g1v[T1][4], g2v[T2];
     if (kRegs) {
