@@ -396,8 +396,10 @@ vlb_status vlb_couette_step_noalloc(int B, const vlb_couette_desc* descs, double
  * stay FP64), and finishes vlb_channel_run_to_steady in FP64.  The state crosses this
  * interface in FP64 in both forms.  dt = 0 picks cfl / (max advective rate +
  * force-operator bound / sqrt(3)), capped at 2 tau of the rest state.  Errors:
- * VLB_EINVAL (bad descriptor or velocity set too large), VLB_EUNSTABLE (explicit dt
- * above the limit), VLB_ENOMEM, VLB_EDEVICE. */
+ * VLB_EINVAL (bad descriptor, velocity set too large, a tile-kernel instance with
+ * 7 N_lambda x velocities x 8 bytes of 2^32 or more, or a batch whose stage launch would
+ * cover 2^32 work-items), VLB_EUNSTABLE (explicit dt above the limit), VLB_ENOMEM,
+ * VLB_EDEVICE. */
 typedef struct {
     int N_lambda, N_xi;
     double xi_in, xi_out;
