@@ -183,33 +183,60 @@ __device__ __forceinline__ T weno5(T a, T b, T c, T d, T e, T eps) {
 // half range: coefficient of phi_l is sum_s C[l][s] M_s with the half-line moments
 //   M_s = int_0^inf x^s N(x; +-u, T) dx:  M_0 = (1+erf(zeta))/2, M_1 = u M_0 + T g(0),
 //   M_s = u M_{s-1} + (s-1) T M_{s-2}.  Writes plus- and minus-side coefficients.
+// Loops run to the compile-time bound kMaxN with the order N as a guard, so the moments
+// and the table entries live in registers (no per-lane scratch array) and the table loads
+// are independent of one another; the sums keep their order.
+__device__ __forceinline__ void half_line_moments(double uu, double T, double (&M)[kMaxN + 1]) {
+    const double g0 = exp(-uu * uu / (2.0 * T)) / sqrt(2.0 * M_PI * T);
+    M[0] = 0.5 * (1.0 + erf(uu / sqrt(2.0 * T)));
+    M[1] = uu * M[0] + T * g0;
+#pragma unroll
+    for (int s = 2; s <= kMaxN; ++s) M[s] = uu * M[s - 1] + (s - 1) * T * M[s - 2];   // entries past N unused
+}
+// lower triangle of C (rows l <= N), row l at l (l + 1) / 2
+__device__ __forceinline__ void load_half_table(const double* C, int N, double (&Ct)[(kMaxN + 1) * (kMaxN + 2) / 2]) {
+#pragma unroll
+    for (int l = 0; l <= kMaxN; ++l)
+#pragma unroll
+        for (int s = 0; s <= l; ++s) Ct[l * (l + 1) / 2 + s] = l <= N ? C[l * (N + 1) + s] : 0.0;
+}
+__device__ __forceinline__ void half_coef(int N, const double (&Ct)[(kMaxN + 1) * (kMaxN + 2) / 2],
+                                          const double (&M)[kMaxN + 1], double* co) {
+#pragma unroll
+    for (int l = 0; l <= kMaxN; ++l) {
+        if (l > N) break;
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s <= l; ++s) acc += Ct[l * (l + 1) / 2 + s] * M[s];
+        co[l] = acc;
+    }
+}
+__device__ __forceinline__ void full_coef(int N, double u, double T, const double* isf, double* co) {
+    double a0 = 1.0, a1 = u;
+    co[0] = a0 / isf[0];
+    if (N >= 1) co[1] = a1 / isf[1];
+    for (int l = 2; l <= N; ++l) {
+        const double a2 = (u * a1 + (T - 1.0) * a0) / l;
+        co[l] = a2 / isf[l];
+        a0 = a1;
+        a1 = a2;
+    }
+}
+
 static __device__ __noinline__ void axis_coef(int kind, int N, double u, double T, const double* C, const double* isf,
                           double* cp, double* cm) {
     if (kind == 0) {
-        double a0 = 1.0, a1 = u;
-        cp[0] = cm[0] = a0 / isf[0];
-        if (N >= 1) cp[1] = cm[1] = a1 / isf[1];
-        for (int l = 2; l <= N; ++l) {
-            const double a2 = (u * a1 + (T - 1.0) * a0) / l;
-            cp[l] = cm[l] = a2 / isf[l];
-            a0 = a1;
-            a1 = a2;
-        }
+        full_coef(N, u, T, isf, cp);
+        for (int l = 0; l <= N; ++l) cm[l] = cp[l];
         return;
     }
+    double Ct[(kMaxN + 1) * (kMaxN + 2) / 2];
+    load_half_table(C, N, Ct);
+#pragma unroll
     for (int sg = 0; sg < 2; ++sg) {
-        const double uu = sg == 0 ? u : -u;
         double M[kMaxN + 1];
-        const double g0 = exp(-uu * uu / (2.0 * T)) / sqrt(2.0 * M_PI * T);
-        M[0] = 0.5 * (1.0 + erf(uu / sqrt(2.0 * T)));
-        if (N >= 1) M[1] = uu * M[0] + T * g0;
-        for (int s = 2; s <= N; ++s) M[s] = uu * M[s - 1] + (s - 1) * T * M[s - 2];
-        double* co = sg == 0 ? cp : cm;
-        for (int l = 0; l <= N; ++l) {
-            double acc = 0.0;
-            for (int s = 0; s <= l; ++s) acc += C[l * (N + 1) + s] * M[s];
-            co[l] = acc;
-        }
+        half_line_moments(sg == 0 ? u : -u, T, M);
+        half_coef(N, Ct, M, sg == 0 ? cp : cm);
     }
 }
 
@@ -219,28 +246,14 @@ static __device__ __noinline__ void axis_coef(int kind, int N, double u, double 
 static __device__ __noinline__ void axis_coef_side(int kind, int N, double u, double T, const double* C,
                                                    const double* isf, int sg, double* co) {
     if (kind == 0) {
-        double a0 = 1.0, a1 = u;
-        co[0] = a0 / isf[0];
-        if (N >= 1) co[1] = a1 / isf[1];
-        for (int l = 2; l <= N; ++l) {
-            const double a2 = (u * a1 + (T - 1.0) * a0) / l;
-            co[l] = a2 / isf[l];
-            a0 = a1;
-            a1 = a2;
-        }
+        full_coef(N, u, T, isf, co);
         return;
     }
-    const double uu = sg == 0 ? u : -u;
+    double Ct[(kMaxN + 1) * (kMaxN + 2) / 2];
+    load_half_table(C, N, Ct);
     double M[kMaxN + 1];
-    const double g0 = exp(-uu * uu / (2.0 * T)) / sqrt(2.0 * M_PI * T);
-    M[0] = 0.5 * (1.0 + erf(uu / sqrt(2.0 * T)));
-    if (N >= 1) M[1] = uu * M[0] + T * g0;
-    for (int s = 2; s <= N; ++s) M[s] = uu * M[s - 1] + (s - 1) * T * M[s - 2];
-    for (int l = 0; l <= N; ++l) {
-        double acc = 0.0;
-        for (int s = 0; s <= l; ++s) acc += C[l * (N + 1) + s] * M[s];
-        co[l] = acc;
-    }
+    half_line_moments(sg == 0 ? u : -u, T, M);
+    half_coef(N, Ct, M, co);
 }
 
 __device__ __forceinline__ double tau_of(int model, double Kn, double n, double T) {
