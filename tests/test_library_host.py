@@ -80,6 +80,14 @@ def test_channel_create_rejects_invalid_descriptors(kw, needle):
     assert needle in msg, msg
 
 
+def test_channel_create_rejects_stencil_span_beyond_buffer_range():
+    """The tile kernel addresses an interior cell's stencil (seven xi columns of N_lambda
+    cells) as one buffer with 32-bit byte offsets: 7 x 150 000 x 512 velocities x 8 bytes
+    is past 2^32, so creation refuses the instance (before any table or device work)."""
+    st, msg = _channel_create_status(N_lambda=150000, N_xi=8, ax1=(1, 16, 4), ax2=(0, 16, 4))
+    assert st == -1 and "too large for the stage kernel" in msg, (st, msg)
+
+
 def test_channel_create_rejects_unstable_dt():
     st, msg = _channel_create_status(N_lambda=8, N_xi=8, dt=10.0)
     assert st == -7 and "stability limit" in msg, (st, msg)
@@ -143,6 +151,21 @@ def test_large_velocity_sets_are_fp64_only():
     lib.vlb_batch_destroy(h)
     st, msg, _ = _couette_create([small, wide], 1)
     assert st == -1 and "FP64 only" in msg, (st, msg)
+
+
+def test_cells_per_run_range_is_one_to_32():
+    """vlb_batch_set_tile takes 1..32 cells per run: values outside are VLB_EINVAL before
+    anything else; values inside pass that check and then need a bound workspace
+    (VLB_ESTATE on a batch created with deferred allocation, so no GPU is needed)."""
+    from paper_1708_05944_amd import CouetteDesc
+    lib = load_library()
+    st, msg, h = _couette_create([CouetteDesc(N_R=8, ax1=(1, 4, 2), ax2=(0, 4, 2))], 0)
+    assert st == 0, msg
+    try:
+        for tile, want in ((0, -1), (33, -1), (1, -4), (32, -4)):
+            assert lib.vlb_batch_set_tile(h, tile) == want, (tile, lib.vlb_last_error().decode())
+    finally:
+        lib.vlb_batch_destroy(h)
 
 
 def test_noalloc_entry_point_rejects_oversized_and_invalid_calls():
