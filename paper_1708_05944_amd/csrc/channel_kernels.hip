@@ -255,8 +255,14 @@ __global__ __launch_bounds__(kChanWaves * kWave, T1 * T2 == 1 ? (sizeof(T) == 4 
         const double* brow = tab + (ax1 ? I.tB1 : I.tB2) + node * nbas;
         const double* co = ec + (ax1 ? 0 : 2 * (kMaxN + 1)) +
                            (((ax1 ? I.kind1 : I.kind2) == 1 && node >= (ax1 ? I.Qh1 : I.Qh2)) ? nbas : 0);
+        // all entries read at once (indices kept in bounds), the terms past nbas dropped by
+        // a select: five independent loads instead of a chain of dependent ones
         double acc = 0.0;
-        for (int l = 0; l < nbas; ++l) acc += brow[l] * co[l];
+#pragma unroll
+        for (int l = 0; l <= kMaxN; ++l) {
+            const double t = fma(brow[l < nbas ? l : nbas - 1], co[l], acc);
+            acc = l < nbas ? t : acc;
+        }
         gf[lane] = acc;
     }
 
