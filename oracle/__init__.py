@@ -1,8 +1,8 @@
 """CPU oracle for the vielbein lattice-Boltzmann hot path (TEST INFRASTRUCTURE ONLY).
 
 This package is a plain, slow, high-precision / FP64 restatement of the method of
-Busuioc & Ambrus, "Lattice Boltzmann models based on the vielbein formalism for the
-simulation of flows in curvilinear geometries" (arXiv:1708.05944).  It exists only so
+Busuioc & Ambrus (arXiv:1708.05944): vielbein lattice-Boltzmann models for flows in
+curvilinear geometries.  It exists only so
 that tests, the smoke check and the CPU-baseline leg of the benchmark can check the
 HIP library against an independent implementation.
 
